@@ -1,0 +1,173 @@
+"""Benchmark: betweenness TEPS on RMAT scale 16 (all sources), batched sparse
+form against the plain FP64 per-source form on the same GPU.
+
+One step = one complete all-source betweenness computation (forward sweep,
+backward sweep and accumulation for every vertex as a source) over the
+synthetic RMAT-16 graph, inputs resident in HBM.  TEPS = sources * m / t with
+m the undirected edge count after preprocessing.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "BC TEPS (sources·m/s) on RMAT-16; batched-MFMA vs plain BFS form, same GPU"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes_per_source(n: int, m: int) -> dict:
+    """Bytes one source's sweeps must move at minimum in the per-source model:
+    each pass reads the int32 column array once (8m for 2m arcs) and about
+    24 B of per-vertex state (row offsets, level, count, dependency and a
+    share of the BC update): 8m + 24n per pass, 16m + 48n per source."""
+    per_pass = 8 * m + 24 * n
+    return {"fwd": per_pass, "bwd": per_pass, "total": 2 * per_pass}
+
+
+def cpu_baseline(g, target_s: float = 12.0):
+    """The oracle as it stands, on a bounded sample of sources, all host cores
+    it may use (at most 16)."""
+    import oracle
+    threads = max(1, min(16, os.cpu_count() or 1))
+    sample0 = np.arange(0, g.n, max(1, g.n // (2 * threads)))[: 2 * threads].astype(np.int32)
+    t0 = time.perf_counter()
+    oracle.bc(g, sample0, threads=threads)
+    t_cal = time.perf_counter() - t0
+    per_src = t_cal / sample0.size
+    count = int(min(g.n, max(sample0.size, target_s / max(per_src, 1e-9))))
+    sample = np.linspace(0, g.n - 1, count).astype(np.int32)
+    t0 = time.perf_counter()
+    oracle.bc(g, sample, threads=threads)
+    t = time.perf_counter() - t0
+    return {"value": count * g.m / t, "unit": "TEPS", "cores": threads, "kind": "oracle",
+            "sample": f"{count} of {g.n} sources (evenly spaced ids), serial Brandes per source, "
+                      f"{threads} threads over sources, {t:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--plain-steps", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 (sources shard across "
+                                   "GPUs by design, but no multi-GPU path is built)"}))
+        sys.exit(2)
+
+    import torch
+
+    import graphgen as gg
+    import paper_0809_1906_amd as bcgpu
+
+    bcgpu.load()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    t0 = time.perf_counter()
+    g = gg.rmat16()
+    log(f"graph rmat16 n={g.n} m={g.m} max_deg={int(g.degrees().max())} gen {time.perf_counter() - t0:.1f}s")
+    S = g.n
+    work = float(S) * g.m
+
+    def timed_runs(form, steps, warmup, batch=0):
+        ctx = bcgpu.BC(g, form=form, batch=batch, timing=True)
+        for i in range(warmup):
+            ctx.run()
+            ctx.read()
+            log(f"{form} warmup {i} done")
+        ctx.reset()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for i in range(steps):
+            ctx.run()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / steps
+        bc = ctx.read()
+        log(f"{form} {steps} steps: {dt * 1e3:.1f} ms/step, {work / dt:.3e} TEPS")
+        return ctx, dt, bc
+
+    ctx, dt, bc_sparse = timed_runs("sparse", args.steps, args.warmup, args.batch)
+    info = ctx.info()
+    kern = {}
+    for k in ("fwd_pull", "bwd_pull", "batch_init"):
+        ms, launches = ctx.timing(k)
+        kern[k] = (ms, launches)
+    log("kernel times (ms, launches):", kern)
+
+    bytes_src = algorithmic_bytes_per_source(g.n, g.m)
+    dom = "fwd_pull" if kern["fwd_pull"][0] >= kern["bwd_pull"][0] else "bwd_pull"
+    dom_ms, dom_launches = kern[dom]
+    alg_bytes_total = float(S) * args.steps * bytes_src["fwd" if dom == "fwd_pull" else "bwd"]
+    achieved = alg_bytes_total / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else None
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "traffic_rmat16.json")
+    if os.path.exists(tpath):
+        with open(tpath) as f:
+            traffic = json.load(f).get(dom)
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
+                "avg_launch_ms": dom_ms / max(dom_launches, 1), "launches": dom_launches,
+                "alg_bytes_per_launch": alg_bytes_total / max(dom_launches, 1)}
+    ctx.close()
+
+    plain = None
+    if not args.no_plain:
+        pctx, pdt, bc_plain = timed_runs("plain", args.plain_steps, 0)
+        pms, pl = pctx.timing("plain_sweep")
+        pctx.close()
+        err = float(np.max(np.abs(bc_sparse - bc_plain) / np.maximum(np.abs(bc_plain), 1.0)))
+        plain = {"value": work / pdt, "ms_per_step": pdt * 1e3, "kernel_ms": pms,
+                 "sparse_vs_plain_max_rel_diff": err}
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(g)
+
+    out = {
+        "metric": METRIC,
+        "value": work / dt,
+        "unit": "TEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64 counts, f32 dependency state, f64 sums",
+        "data": "synthetic",
+        "config": {"workload": "rmat16: RMAT scale 16, edgefactor 16, (a,b,c,d)=(.57,.19,.19,.05), "
+                               "symmetrised, deduplicated, largest component; exact all-source BC",
+                   "n": g.n, "m": g.m, "sources": S, "batch": info.batch, "form": "sparse",
+                   "levels_max": info.max_levels},
+        "plain_fp64": plain,
+        "batched_vs_plain": (plain["ms_per_step"] / (dt * 1e3)) if plain else None,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

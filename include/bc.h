@@ -1,0 +1,212 @@
+/*
+ * bc.h -- exact betweenness centrality on AMD Instinct MI355X (gfx950).
+ *
+ * The library computes, for an undirected graph with positive integer edge
+ * weights, the betweenness centrality of every vertex (Kintali, "Betweenness
+ * Centrality: Algorithms and Lower Bounds", Sec. 1.1):
+ *
+ *   BC(v) = sum over ordered pairs (s,t), s != v != t, of
+ *           lambda_st(v) / lambda_st
+ *         = sum over sources s != v of delta_s*(v),
+ *
+ * where lambda_st counts shortest s-t paths and delta_s*(v) is the dependency
+ * of s on v.  Each source is processed as a forward sweep (distances and path
+ * counts over the shortest-path DAG) followed by a backward sweep that applies
+ * Brandes's recurrence (Theorem 1.1) farthest vertices first, and the
+ * dependencies are added into a running score (Brandes's algorithm, Sec. 1.1).
+ * Pairs are ORDERED and nothing is halved: the unordered-pair value is BC/2.
+ * Unreachable targets contribute nothing.
+ *
+ * Every entry point returns a bc_status; no exception crosses this boundary.
+ * All pointers are plain host or device pointers as stated per argument.
+ * A context owns every device buffer it allocates until bc_destroy.  A context
+ * is bound to one HIP stream and one device and is not thread-safe.
+ */
+#ifndef BC_H
+#define BC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bc_ctx bc_ctx; /* opaque */
+
+typedef enum {
+    BC_OK = 0,
+    BC_ERR_INVALID_ARG = 1,   /* NULL where a pointer is required, bad size, bad option */
+    BC_ERR_INVALID_GRAPH = 2, /* CSR violates the graph model (see bc_graph) */
+    BC_ERR_NOMEM = 3,         /* a device or host allocation failed */
+    BC_ERR_DEVICE = 4,        /* a HIP runtime call failed; the context is poisoned */
+    BC_ERR_OVERFLOW = 5,      /* a shortest-path count exceeded 2^64 - 1 */
+    BC_ERR_STATE = 6,         /* call not allowed in the context's current state */
+    BC_ERR_UNSUPPORTED = 7    /* valid request this form cannot serve */
+} bc_status;
+
+typedef enum { BC_MEM_HOST = 0, BC_MEM_DEVICE = 1 } bc_mem;
+
+/*
+ * How the sweeps are computed.  Every form returns the same BC up to
+ * floating-point rounding, and the same distances and path counts exactly.
+ *
+ *  BC_FORM_PLAIN_FP64  one source per workgroup, per-source state, dependencies
+ *                      in FP64.  Unit and integer weights.
+ *  BC_FORM_SPARSE      sources in batches (a multiple of 64, default 256);
+ *                      per-level frontier bitmaps, one bit per (vertex, source);
+ *                      CSR gathers pulled per vertex; path counts uint64,
+ *                      dependency state stored as FP32 with FP64 accumulation.
+ *                      Unit weights (the level sweep of Sec. 4); integer weights
+ *                      use bucketed shortest paths with one bucket per distance.
+ *  BC_FORM_ALGEBRAIC   the algebraic method of Sec. 3.1 on a batch of sources:
+ *                      frontier-matrix x adjacency products on BF16 MFMA with
+ *                      path counts carried exactly in 8-bit limbs.  Unit weights.
+ *  BC_FORM_AUTO        chosen by the library from the graph's shape.
+ */
+typedef enum {
+    BC_FORM_AUTO = 0,
+    BC_FORM_PLAIN_FP64 = 1,
+    BC_FORM_SPARSE = 2,
+    BC_FORM_ALGEBRAIC = 3
+} bc_form;
+
+/*
+ * An undirected simple graph as a symmetric CSR (Sec. 1.1: vertices 0..n-1,
+ * positive integer edge weights, unweighted meaning w = 1).
+ *   n        number of vertices, 0 <= n < 2^31
+ *   nnz      number of arcs = 2m (each undirected edge appears as both arcs)
+ *   row_ptr  n+1 int32, row_ptr[0] = 0, nondecreasing, row_ptr[n] = nnz
+ *   col      nnz int32; row v lists the neighbours of v in strictly
+ *            increasing order (so no duplicate arcs); no self-loops; the arc
+ *            (u,v) is present iff (v,u) is
+ *   weight   nnz uint32 or NULL for unit weights; every weight >= 1; the two
+ *            arcs of an edge carry the same weight; max weight * (n-1) < 2^31
+ *   mem      whether row_ptr/col/weight are host or device pointers
+ * Violations give BC_ERR_INVALID_GRAPH.  The arrays are copied; the caller
+ * may free them as soon as the call returns.
+ */
+typedef struct {
+    int32_t n;
+    int32_t nnz;
+    const int32_t *row_ptr;
+    const int32_t *col;
+    const uint32_t *weight;
+    bc_mem mem;
+} bc_graph;
+
+/*
+ * Device-memory provider.  alloc returns `bytes` of device memory usable on
+ * `stream` (NULL on failure); free releases a pointer alloc returned.  When
+ * both are NULL the library uses hipMalloc / hipFree.
+ */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *stream, void *user);
+    void (*free)(void *ptr, void *stream, void *user);
+    void *user;
+} bc_allocator;
+
+typedef struct {
+    uint32_t struct_size; /* sizeof(bc_options); set by bc_options_init */
+    bc_form form;         /* default BC_FORM_AUTO */
+    int32_t batch;        /* sources per batch for batched forms; 0 = default */
+    int32_t device;       /* HIP device ordinal; -1 = the current device */
+    void *stream;         /* hipStream_t to run on; NULL = the null stream */
+    bc_allocator allocator;
+    int32_t timing;       /* nonzero: time every kernel launch with HIP events */
+    int32_t reserved[8];
+} bc_options;
+
+/* Fills *opt with the defaults above.  Never fails for a non-NULL opt. */
+void bc_options_init(bc_options *opt);
+
+/*
+ * Validates the graph on the host (before any device work), then copies it to
+ * device memory obtained from the allocator and prepares the chosen form.
+ * On success *out receives a new context; on failure *out is set to NULL and
+ * nothing stays allocated.  Errors: BC_ERR_INVALID_ARG, BC_ERR_INVALID_GRAPH,
+ * BC_ERR_UNSUPPORTED (form cannot take this graph, e.g. weights with the
+ * algebraic form), BC_ERR_NOMEM, BC_ERR_DEVICE.
+ */
+bc_status bc_create(const bc_graph *g, const bc_options *opt, bc_ctx **out);
+
+/*
+ * Adds, for every entry s of `sources`, the dependencies delta_s*(v) of
+ * s on every v != s into the context's running BC (Sec. 1.1, Brandes's
+ * running centrality score).  `sources` is a multiset of vertex ids in
+ * [0, n): an id listed twice adds twice.  sources = NULL with count = -1 means
+ * every vertex once.  `mem` tells where `sources` lives.  The call is
+ * asynchronous on the context's stream except where a form must read a
+ * frontier size back; results are visible to bc_read.
+ * Errors: BC_ERR_INVALID_ARG (id out of range, bad count), BC_ERR_STATE
+ * (poisoned context), BC_ERR_OVERFLOW (a path count of an earlier call
+ * exceeded 2^64 - 1), BC_ERR_NOMEM, BC_ERR_DEVICE.
+ */
+bc_status bc_run(bc_ctx *ctx, const int32_t *sources, int64_t count, bc_mem mem);
+
+/*
+ * Synchronises the context's stream, then copies BC (n doubles, vertex order)
+ * to `bc_out` (host or device per `mem`).  Returns BC_ERR_OVERFLOW, leaving
+ * bc_out unwritten, if any path count so far exceeded 2^64 - 1.
+ */
+bc_status bc_read(bc_ctx *ctx, double *bc_out, bc_mem mem);
+
+/* Zeroes the running BC and clears a recorded overflow. */
+bc_status bc_reset(bc_ctx *ctx);
+
+/*
+ * Runs `count` sources (1 <= count <= bc_info.batch) through exactly the
+ * kernels and launch configuration bc_run uses, WITHOUT adding to BC, and
+ * copies each source's per-vertex results to host arrays laid out
+ * [count][n] (source-major; any pointer may be NULL):
+ *   dist   d(s,v) (Sec. 1.1), -1 where v is unreachable from s
+ *   sigma  lambda_sv, the number of shortest s-v paths (0 where unreachable)
+ *   delta  delta_s*(v); delta_s*(s) is the recurrence's own value, the number
+ *          of other vertices reachable from s
+ * Errors as bc_run, plus BC_ERR_OVERFLOW when a count of these sources
+ * exceeded 2^64 - 1 (the outputs are then unspecified).
+ */
+bc_status bc_read_sssp(bc_ctx *ctx, const int32_t *sources, int32_t count,
+                       int32_t *dist, uint64_t *sigma, double *delta);
+
+typedef struct {
+    int32_t n;           /* vertices */
+    int64_t m;           /* undirected edges = nnz / 2 */
+    int32_t max_degree;
+    int32_t weighted;    /* 1 when the graph carries weights */
+    bc_form form;        /* the form in use (never BC_FORM_AUTO) */
+    int32_t batch;       /* sources per batch (1 for the plain form) */
+    int32_t max_levels;  /* deepest level (or distinct distance count) seen + 1 */
+    int64_t sources_run; /* sources accumulated since create / reset */
+    int64_t device_bytes;/* device memory the context holds */
+} bc_info;
+
+bc_status bc_get_info(const bc_ctx *ctx, bc_info *out);
+
+/*
+ * Kernel timing (contexts created with timing != 0).  For the kernel named
+ * `kernel` (e.g. "plain_sweep", "fwd_pull", "bwd_pull"), returns the summed
+ * duration in milliseconds of its launches since create / reset, measured
+ * with HIP events on the context's stream, and the number of launches.
+ * Unknown names give zero.  Synchronises the stream.
+ */
+bc_status bc_get_timing(bc_ctx *ctx, const char *kernel, double *total_ms, int64_t *launches);
+
+/* Static description of a status code. */
+const char *bc_status_string(bc_status s);
+
+/*
+ * Message of the last failure on this context, or, with ctx = NULL, of the
+ * last failed bc_create on the calling thread.  Valid until the next call on
+ * the same context (thread).
+ */
+const char *bc_last_error(const bc_ctx *ctx);
+
+/* Releases every resource of the context.  NULL is a no-op. */
+void bc_destroy(bc_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BC_H */

@@ -38,7 +38,7 @@ def build(force: bool = False) -> str:
     """Compile brandes.c with gcc into oracle/_brandes.so (host code only)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + f".tmp{os.getpid()}"
-        subprocess.check_call(["gcc", "-O3", "-march=native", "-std=gnu11", "-fPIC", "-shared",
+        subprocess.check_call(["gcc", "-O3", "-std=gnu11", "-fPIC", "-shared",
                                "-o", tmp, _SRC, "-lpthread"])
         os.replace(tmp, _LIB)
     return _LIB

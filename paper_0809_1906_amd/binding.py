@@ -1,0 +1,298 @@
+"""ctypes binding of the C ABI in include/bc.h.
+
+Argument marshalling only: every step of the computation runs in the HIP
+library (libbc.so).  The names mirror the C entry points.  PyTorch is used for
+device memory (its caching allocator backs the library's allocations) and for
+streams; nothing here computes betweenness.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbc.so")
+
+BC_OK = 0
+BC_ERR_INVALID_ARG = 1
+BC_ERR_INVALID_GRAPH = 2
+BC_ERR_NOMEM = 3
+BC_ERR_DEVICE = 4
+BC_ERR_OVERFLOW = 5
+BC_ERR_STATE = 6
+BC_ERR_UNSUPPORTED = 7
+STATUS_NAMES = {0: "BC_OK", 1: "BC_ERR_INVALID_ARG", 2: "BC_ERR_INVALID_GRAPH", 3: "BC_ERR_NOMEM",
+                4: "BC_ERR_DEVICE", 5: "BC_ERR_OVERFLOW", 6: "BC_ERR_STATE", 7: "BC_ERR_UNSUPPORTED"}
+
+BC_MEM_HOST = 0
+BC_MEM_DEVICE = 1
+
+BC_FORM_AUTO = 0
+BC_FORM_PLAIN_FP64 = 1
+BC_FORM_SPARSE = 2
+BC_FORM_ALGEBRAIC = 3
+FORMS = {"auto": BC_FORM_AUTO, "plain": BC_FORM_PLAIN_FP64, "sparse": BC_FORM_SPARSE,
+         "algebraic": BC_FORM_ALGEBRAIC}
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class bc_graph(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int32),
+                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p),
+                ("weight", ctypes.c_void_p), ("mem", ctypes.c_int)]
+
+
+class bc_allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", ctypes.c_void_p)]
+
+
+class bc_options(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("form", ctypes.c_int), ("batch", ctypes.c_int32),
+                ("device", ctypes.c_int32), ("stream", ctypes.c_void_p), ("allocator", bc_allocator),
+                ("timing", ctypes.c_int32), ("reserved", ctypes.c_int32 * 8)]
+
+
+class bc_info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int64), ("max_degree", ctypes.c_int32),
+                ("weighted", ctypes.c_int32), ("form", ctypes.c_int), ("batch", ctypes.c_int32),
+                ("max_levels", ctypes.c_int32), ("sources_run", ctypes.c_int64),
+                ("device_bytes", ctypes.c_int64)]
+
+
+# Every symbol include/bc.h declares, with its ctypes signature.
+SIGNATURES = {
+    "bc_options_init": (None, [ctypes.POINTER(bc_options)]),
+    "bc_create": (ctypes.c_int, [ctypes.POINTER(bc_graph), ctypes.POINTER(bc_options), ctypes.POINTER(ctypes.c_void_p)]),
+    "bc_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int]),
+    "bc_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
+    "bc_reset": (ctypes.c_int, [ctypes.c_void_p]),
+    "bc_read_sssp": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_void_p]),
+    "bc_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(bc_info)]),
+    "bc_get_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_int64)]),
+    "bc_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "bc_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "bc_destroy": (None, [ctypes.c_void_p]),
+}
+
+_lib = None
+
+
+def load():
+    """Load libbc.so; raises RuntimeError when the HIP library is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build() first")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+class BCError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+def _check(status: int, ctx=None):
+    if status != BC_OK:
+        msg = load().bc_last_error(ctx)
+        raise BCError(status, msg.decode() if msg else "")
+
+
+# ---- thin wrappers with the C names ------------------------------------------------
+
+def bc_options_init() -> bc_options:
+    opt = bc_options()
+    load().bc_options_init(ctypes.byref(opt))
+    return opt
+
+
+def bc_create(graph: bc_graph, options: Optional[bc_options]) -> ctypes.c_void_p:
+    ctx = ctypes.c_void_p()
+    st = load().bc_create(ctypes.byref(graph), ctypes.byref(options) if options is not None else None,
+                          ctypes.byref(ctx))
+    _check(st, None)
+    return ctx
+
+
+def bc_run(ctx, sources_ptr, count: int, mem: int) -> None:
+    _check(load().bc_run(ctx, sources_ptr, count, mem), ctx)
+
+
+def bc_read(ctx, out_ptr, mem: int) -> None:
+    _check(load().bc_read(ctx, out_ptr, mem), ctx)
+
+
+def bc_reset(ctx) -> None:
+    _check(load().bc_reset(ctx), ctx)
+
+
+def bc_read_sssp(ctx, sources_ptr, count: int, dist_ptr, sigma_ptr, delta_ptr) -> None:
+    _check(load().bc_read_sssp(ctx, sources_ptr, count, dist_ptr, sigma_ptr, delta_ptr), ctx)
+
+
+def bc_get_info(ctx) -> bc_info:
+    info = bc_info()
+    _check(load().bc_get_info(ctx, ctypes.byref(info)), ctx)
+    return info
+
+
+def bc_get_timing(ctx, kernel: str):
+    ms = ctypes.c_double()
+    launches = ctypes.c_int64()
+    _check(load().bc_get_timing(ctx, kernel.encode(), ctypes.byref(ms), ctypes.byref(launches)), ctx)
+    return ms.value, launches.value
+
+
+def bc_status_string(status: int) -> str:
+    return load().bc_status_string(status).decode()
+
+
+def bc_last_error(ctx=None) -> str:
+    return load().bc_last_error(ctx).decode()
+
+
+def bc_destroy(ctx) -> None:
+    load().bc_destroy(ctx)
+
+
+# ---- convenience object ---------------------------------------------------------------
+
+class _TorchAllocator:
+    """Backs library allocations with torch's caching allocator."""
+
+    def __init__(self, device: int):
+        import torch
+        self.torch = torch
+        self.device = device
+
+        def _alloc(nbytes, stream, user):
+            try:
+                return self.torch.cuda.caching_allocator_alloc(int(nbytes), self.device, stream or 0)
+            except Exception:
+                return None
+
+        def _free(ptr, stream, user):
+            self.torch.cuda.caching_allocator_delete(ptr)
+
+        self.alloc = ALLOC_FN(_alloc)
+        self.free = FREE_FN(_free)
+
+
+class BC:
+    """A context on one graph.
+
+    >>> ctx = BC(graph, form="sparse")        # graph: object with n, row_ptr, col, weight
+    >>> ctx.run()                              # every source
+    >>> bc = ctx.read()                        # numpy float64[n], ordered pairs
+    """
+
+    def __init__(self, graph, form: str = "auto", batch: int = 0, device: int = 0, stream=None,
+                 allocator: str = "torch", timing: bool = False):
+        import torch
+        load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the betweenness library needs an MI355X")
+        self.torch = torch
+        self.device = device
+        self.n = int(graph.n)
+        self._stream = stream if stream is not None else torch.cuda.current_stream(device)
+        opt = bc_options_init()
+        opt.form = FORMS[form]
+        opt.batch = batch
+        opt.device = device
+        opt.stream = self._stream.cuda_stream
+        opt.timing = 1 if timing else 0
+        self._alloc = None
+        if allocator == "torch":
+            self._alloc = _TorchAllocator(device)
+            opt.allocator.alloc = self._alloc.alloc
+            opt.allocator.free = self._alloc.free
+        rp = np.ascontiguousarray(graph.row_ptr, dtype=np.int32)
+        col = np.ascontiguousarray(graph.col, dtype=np.int32)
+        w = None if graph.weight is None else np.ascontiguousarray(graph.weight, dtype=np.uint32)
+        g = bc_graph()
+        g.n = self.n
+        g.nnz = int(col.size)
+        g.row_ptr = rp.ctypes.data
+        g.col = col.ctypes.data if col.size else None
+        g.weight = w.ctypes.data if w is not None and w.size else None
+        g.mem = BC_MEM_HOST
+        self._ctx = None
+        with torch.cuda.device(device):
+            self._ctx = bc_create(g, opt)
+
+    # -- lifecycle --
+    def close(self):
+        if self._ctx is not None:
+            bc_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- calls --
+    def run(self, sources=None) -> None:
+        if sources is None:
+            bc_run(self._ctx, None, -1, BC_MEM_HOST)
+            return
+        if hasattr(sources, "is_cuda") and sources.is_cuda:
+            s = sources.to(self.torch.int32).contiguous()
+            bc_run(self._ctx, s.data_ptr(), s.numel(), BC_MEM_DEVICE)
+            return
+        s = np.ascontiguousarray(sources, dtype=np.int32)
+        bc_run(self._ctx, s.ctypes.data if s.size else None, int(s.size), BC_MEM_HOST)
+
+    def read(self) -> np.ndarray:
+        out = np.zeros(max(self.n, 1), dtype=np.float64)
+        bc_read(self._ctx, out.ctypes.data, BC_MEM_HOST)
+        return out[: self.n]
+
+    def read_device(self):
+        out = self.torch.empty(max(self.n, 1), dtype=self.torch.float64, device=f"cuda:{self.device}")
+        bc_read(self._ctx, out.data_ptr(), BC_MEM_DEVICE)
+        return out[: self.n]
+
+    def reset(self) -> None:
+        bc_reset(self._ctx)
+
+    def sssp(self, sources):
+        """(dist int32[k,n], sigma uint64[k,n], delta float64[k,n]) for k sources."""
+        s = np.ascontiguousarray(sources, dtype=np.int32)
+        k = int(s.size)
+        dist = np.zeros((k, max(self.n, 1)), np.int32)
+        sigma = np.zeros((k, max(self.n, 1)), np.uint64)
+        delta = np.zeros((k, max(self.n, 1)), np.float64)
+        bc_read_sssp(self._ctx, s.ctypes.data, k, dist.ctypes.data, sigma.ctypes.data, delta.ctypes.data)
+        return dist[:, : self.n], sigma[:, : self.n], delta[:, : self.n]
+
+    def info(self) -> bc_info:
+        return bc_get_info(self._ctx)
+
+    def timing(self, kernel: str):
+        return bc_get_timing(self._ctx, kernel)
+
+    @property
+    def handle(self):
+        return self._ctx

@@ -1,0 +1,502 @@
+// The C ABI of include/bc.h: host-side validation, device memory, streams,
+// and dispatch to the forms.  Every device step runs in the HIP kernels of
+// plain.hip and sparse.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "bc_internal.h"
+
+namespace {
+
+thread_local std::string g_create_error;
+
+bc_status fail_create(bc_status s, const std::string &msg) {
+    g_create_error = msg;
+    return s;
+}
+
+// Host validation of the graph model (Sec. 1.1, undirected simple graph with
+// positive integer weights) on host copies of the arrays.
+bc_status validate_graph(int32_t n, int32_t nnz, const int32_t *rp, const int32_t *col,
+                         const uint32_t *w, std::string &msg, int32_t &max_deg, uint32_t &max_w) {
+    char buf[256];
+    if (rp[0] != 0) { msg = "row_ptr[0] must be 0"; return BC_ERR_INVALID_GRAPH; }
+    if (rp[n] != nnz) {
+        snprintf(buf, sizeof buf, "row_ptr[n] = %d but nnz = %d", rp[n], nnz);
+        msg = buf;
+        return BC_ERR_INVALID_GRAPH;
+    }
+    max_deg = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        if (rp[v + 1] < rp[v]) {
+            snprintf(buf, sizeof buf, "row_ptr decreases at vertex %d", v);
+            msg = buf;
+            return BC_ERR_INVALID_GRAPH;
+        }
+        max_deg = std::max(max_deg, rp[v + 1] - rp[v]);
+        for (int32_t e = rp[v]; e < rp[v + 1]; ++e) {
+            int32_t x = col[e];
+            if (x < 0 || x >= n) {
+                snprintf(buf, sizeof buf, "arc %d of vertex %d points to %d, outside [0,%d)", e, v, x, n);
+                msg = buf;
+                return BC_ERR_INVALID_GRAPH;
+            }
+            if (x == v) {
+                snprintf(buf, sizeof buf, "self-loop at vertex %d", v);
+                msg = buf;
+                return BC_ERR_INVALID_GRAPH;
+            }
+            if (e > rp[v] && col[e - 1] >= x) {
+                snprintf(buf, sizeof buf, "row %d is not strictly increasing (duplicate or unsorted arc)", v);
+                msg = buf;
+                return BC_ERR_INVALID_GRAPH;
+            }
+        }
+    }
+    max_w = 1;
+    if (w) {
+        for (int32_t e = 0; e < nnz; ++e) {
+            if (w[e] == 0) { msg = "edge weight 0 (weights must be >= 1)"; return BC_ERR_INVALID_GRAPH; }
+            max_w = std::max(max_w, w[e]);
+        }
+        if ((int64_t)max_w * (int64_t)(n > 0 ? n - 1 : 0) >= (int64_t(1) << 31)) {
+            msg = "max weight * (n-1) must stay below 2^31";
+            return BC_ERR_INVALID_GRAPH;
+        }
+    }
+    // symmetry: (v,x) present => (x,v) present with the same weight
+    for (int32_t v = 0; v < n; ++v) {
+        for (int32_t e = rp[v]; e < rp[v + 1]; ++e) {
+            int32_t x = col[e];
+            const int32_t *b = col + rp[x], *en = col + rp[x + 1];
+            const int32_t *it = std::lower_bound(b, en, v);
+            if (it == en || *it != v) {
+                snprintf(buf, sizeof buf, "arc (%d,%d) has no reverse arc (graph must be undirected)", v, x);
+                msg = buf;
+                return BC_ERR_INVALID_GRAPH;
+            }
+            if (w && w[it - col] != w[e]) {
+                snprintf(buf, sizeof buf, "arcs (%d,%d) and (%d,%d) carry different weights", v, x, x, v);
+                msg = buf;
+                return BC_ERR_INVALID_GRAPH;
+            }
+        }
+    }
+    return BC_OK;
+}
+
+void release_all(bc_ctx *ctx) {
+    if (!ctx) return;
+    if (ctx->device >= 0) hipSetDevice(ctx->device);
+    hipStreamSynchronize(ctx->stream);
+    for (auto &kv : ctx->timers)
+        for (auto &pr : kv.second.pending) {
+            hipEventDestroy(pr.first);
+            hipEventDestroy(pr.second);
+        }
+    ctx->timers.clear();
+    auto owned = ctx->owned;
+    for (auto &pr : owned) bc_dfree(ctx, pr.first);
+    ctx->owned.clear();
+    if (ctx->status_host) hipHostFree(ctx->status_host);
+    if (ctx->sp.counts_host) hipHostFree(ctx->sp.counts_host);
+    ctx->status_host = nullptr;
+    ctx->sp.counts_host = nullptr;
+}
+
+} // namespace
+
+// ---------------------------------------------------------------------------
+// helpers shared with the forms
+// ---------------------------------------------------------------------------
+
+bc_status bc_fail(bc_ctx *ctx, bc_status s, const std::string &msg) {
+    if (ctx) ctx->err = msg;
+    else g_create_error = msg;
+    return s;
+}
+
+bc_status bc_hip(bc_ctx *ctx, hipError_t e, const char *what) {
+    std::string msg = std::string(what) + ": " + hipGetErrorString(e);
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return bc_fail(ctx, BC_ERR_NOMEM, msg);
+    if (ctx) ctx->poisoned = true;
+    return bc_fail(ctx, BC_ERR_DEVICE, msg);
+}
+
+void *bc_dalloc(bc_ctx *ctx, size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    bytes = (bytes + 255) & ~size_t(255);
+    void *p = nullptr;
+    if (ctx->alloc.alloc) {
+        p = ctx->alloc.alloc(bytes, (void *)ctx->stream, ctx->alloc.user);
+    } else {
+        if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
+    }
+    if (p) {
+        ctx->owned.emplace_back(p, bytes);
+        ctx->device_bytes += (int64_t)bytes;
+    }
+    return p;
+}
+
+void bc_dfree(bc_ctx *ctx, void *p) {
+    if (!p) return;
+    for (size_t i = 0; i < ctx->owned.size(); ++i) {
+        if (ctx->owned[i].first == p) {
+            ctx->device_bytes -= (int64_t)ctx->owned[i].second;
+            ctx->owned.erase(ctx->owned.begin() + (long)i);
+            break;
+        }
+    }
+    if (ctx->alloc.free) ctx->alloc.free(p, (void *)ctx->stream, ctx->alloc.user);
+    else hipFree(p);
+}
+
+LaunchTimer::LaunchTimer(bc_ctx *c, const char *nm) : ctx(c), name(nm) {
+    if (!ctx->timing) return;
+    hipEventCreate(&a);
+    hipEventCreate(&b);
+    hipEventRecord(a, ctx->stream);
+}
+
+void LaunchTimer::done() {
+    if (!ctx->timing || !a) return;
+    hipEventRecord(b, ctx->stream);
+    auto &t = ctx->timers[name];
+    t.pending.emplace_back(a, b);
+    t.launches += 1;
+    a = b = nullptr;
+}
+
+// ---------------------------------------------------------------------------
+// public entry points
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+void bc_options_init(bc_options *opt) {
+    if (!opt) return;
+    memset(opt, 0, sizeof(*opt));
+    opt->struct_size = sizeof(bc_options);
+    opt->form = BC_FORM_AUTO;
+    opt->batch = 0;
+    opt->device = -1;
+}
+
+const char *bc_status_string(bc_status s) {
+    switch (s) {
+    case BC_OK: return "BC_OK: success";
+    case BC_ERR_INVALID_ARG: return "BC_ERR_INVALID_ARG: invalid argument";
+    case BC_ERR_INVALID_GRAPH: return "BC_ERR_INVALID_GRAPH: graph violates the input model";
+    case BC_ERR_NOMEM: return "BC_ERR_NOMEM: out of memory";
+    case BC_ERR_DEVICE: return "BC_ERR_DEVICE: HIP runtime error";
+    case BC_ERR_OVERFLOW: return "BC_ERR_OVERFLOW: a shortest-path count exceeded 2^64-1";
+    case BC_ERR_STATE: return "BC_ERR_STATE: call not allowed in the current state";
+    case BC_ERR_UNSUPPORTED: return "BC_ERR_UNSUPPORTED: request not supported by this form";
+    }
+    return "unknown bc_status";
+}
+
+const char *bc_last_error(const bc_ctx *ctx) {
+    return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+bc_status bc_create(const bc_graph *g, const bc_options *opt_in, bc_ctx **out) {
+    if (!out) return fail_create(BC_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!g) return fail_create(BC_ERR_INVALID_ARG, "graph is NULL");
+    bc_options opt;
+    bc_options_init(&opt);
+    if (opt_in) {
+        if (opt_in->struct_size != sizeof(bc_options))
+            return fail_create(BC_ERR_INVALID_ARG, "bc_options.struct_size mismatch (call bc_options_init)");
+        opt = *opt_in;
+    }
+    if (g->n < 0 || g->nnz < 0) return fail_create(BC_ERR_INVALID_ARG, "negative n or nnz");
+    if (!g->row_ptr) return fail_create(BC_ERR_INVALID_ARG, "row_ptr is NULL");
+    if (g->nnz > 0 && !g->col) return fail_create(BC_ERR_INVALID_ARG, "col is NULL");
+    if (g->mem != BC_MEM_HOST && g->mem != BC_MEM_DEVICE)
+        return fail_create(BC_ERR_INVALID_ARG, "graph mem must be BC_MEM_HOST or BC_MEM_DEVICE");
+    if (opt.form < BC_FORM_AUTO || opt.form > BC_FORM_ALGEBRAIC)
+        return fail_create(BC_ERR_INVALID_ARG, "unknown form");
+    if (opt.batch < 0 || opt.batch % 64 != 0 || opt.batch > 4096)
+        return fail_create(BC_ERR_INVALID_ARG, "batch must be 0 or a multiple of 64 up to 4096");
+    if ((opt.allocator.alloc == nullptr) != (opt.allocator.free == nullptr))
+        return fail_create(BC_ERR_INVALID_ARG, "allocator needs both alloc and free, or neither");
+
+    const int32_t n = g->n, nnz = g->nnz;
+    // Host copies (device inputs are copied down for validation).
+    std::vector<int32_t> rp, col;
+    std::vector<uint32_t> w;
+    const int32_t *hrp = g->row_ptr, *hcol = g->col;
+    const uint32_t *hw = g->weight;
+    if (g->mem == BC_MEM_DEVICE) {
+        rp.resize((size_t)n + 1);
+        col.resize((size_t)std::max(nnz, 1));
+        if (hipMemcpy(rp.data(), g->row_ptr, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToHost) != hipSuccess ||
+            (nnz > 0 && hipMemcpy(col.data(), g->col, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToHost) != hipSuccess))
+            return fail_create(BC_ERR_DEVICE, "copying the device graph to the host for validation failed");
+        if (g->weight) {
+            w.resize((size_t)std::max(nnz, 1));
+            if (nnz > 0 && hipMemcpy(w.data(), g->weight, sizeof(uint32_t) * (size_t)nnz, hipMemcpyDeviceToHost) != hipSuccess)
+                return fail_create(BC_ERR_DEVICE, "copying device weights failed");
+            hw = w.data();
+        }
+        hrp = rp.data();
+        hcol = col.data();
+    }
+    std::string msg;
+    int32_t max_deg = 0;
+    uint32_t max_w = 1;
+    bc_status vs = validate_graph(n, nnz, hrp, hcol, hw, msg, max_deg, max_w);
+    if (vs != BC_OK) return fail_create(vs, msg);
+
+    bc_form form = opt.form;
+    if (form == BC_FORM_AUTO) form = BC_FORM_SPARSE;
+    if (hw && (form == BC_FORM_SPARSE || form == BC_FORM_ALGEBRAIC))
+        return fail_create(BC_ERR_UNSUPPORTED, "weighted graphs are served by the plain form only");
+    if (form == BC_FORM_ALGEBRAIC)
+        return fail_create(BC_ERR_UNSUPPORTED, "the algebraic form is not available");
+
+    // ---- device side ----
+    bc_ctx *ctx = new (std::nothrow) bc_ctx();
+    if (!ctx) return fail_create(BC_ERR_NOMEM, "host allocation of the context failed");
+    ctx->n = n;
+    ctx->nnz = nnz;
+    ctx->max_degree = max_deg;
+    ctx->max_weight = max_w;
+    ctx->weighted = hw != nullptr;
+    ctx->stream = (hipStream_t)opt.stream;
+    ctx->alloc = opt.allocator;
+    ctx->timing = opt.timing != 0;
+    ctx->form = form;
+
+    auto bail = [&](bc_status s, const std::string &m) {
+        release_all(ctx);
+        delete ctx;
+        return fail_create(s, m);
+    };
+    int dev = opt.device;
+    if (dev < 0) {
+        if (hipGetDevice(&dev) != hipSuccess) return bail(BC_ERR_DEVICE, "hipGetDevice failed");
+    }
+    if (hipSetDevice(dev) != hipSuccess) return bail(BC_ERR_DEVICE, "hipSetDevice failed");
+    ctx->device = dev;
+
+    ctx->row_ptr = (int32_t *)bc_dalloc(ctx, sizeof(int32_t) * ((size_t)n + 1));
+    ctx->col = (int32_t *)bc_dalloc(ctx, sizeof(int32_t) * (size_t)std::max(nnz, 1));
+    ctx->bc = (double *)bc_dalloc(ctx, sizeof(double) * (size_t)std::max(n, 1));
+    ctx->status = (uint32_t *)bc_dalloc(ctx, 256);
+    if (!ctx->row_ptr || !ctx->col || !ctx->bc || !ctx->status) return bail(BC_ERR_NOMEM, "device allocation failed");
+    if (hw) {
+        ctx->weight = (uint32_t *)bc_dalloc(ctx, sizeof(uint32_t) * (size_t)std::max(nnz, 1));
+        if (!ctx->weight) return bail(BC_ERR_NOMEM, "device allocation failed");
+    }
+    if (hipHostMalloc((void **)&ctx->status_host, 256) != hipSuccess) return bail(BC_ERR_NOMEM, "pinned allocation failed");
+    hipMemcpyKind kind = g->mem == BC_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    if (hipMemcpyAsync(ctx->row_ptr, g->row_ptr, sizeof(int32_t) * ((size_t)n + 1), kind, ctx->stream) != hipSuccess ||
+        (nnz > 0 && hipMemcpyAsync(ctx->col, g->col, sizeof(int32_t) * (size_t)nnz, kind, ctx->stream) != hipSuccess) ||
+        (hw && nnz > 0 && hipMemcpyAsync(ctx->weight, g->weight, sizeof(uint32_t) * (size_t)nnz, kind, ctx->stream) != hipSuccess) ||
+        hipMemsetAsync(ctx->bc, 0, sizeof(double) * (size_t)std::max(n, 1), ctx->stream) != hipSuccess ||
+        hipMemsetAsync(ctx->status, 0, 256, ctx->stream) != hipSuccess)
+        return bail(BC_ERR_DEVICE, "uploading the graph failed");
+
+    bc_status ps = BC_OK;
+    if (form == BC_FORM_PLAIN_FP64) ps = plain_prepare(ctx);
+    else if (form == BC_FORM_SPARSE) ps = sparse_prepare(ctx, opt.batch ? opt.batch : 256);
+    if (ps != BC_OK) return bail(ps, ctx->err);
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) return bail(BC_ERR_DEVICE, "stream synchronisation failed");
+    *out = ctx;
+    return BC_OK;
+}
+
+static bc_status stage_sources(bc_ctx *ctx, const int32_t *sources, int64_t count, bc_mem mem,
+                               const int32_t **d_out, int64_t *count_out) {
+    if (count == -1 && sources == nullptr) count = ctx->n;
+    else if (count < 0 || (count > 0 && !sources)) return bc_fail(ctx, BC_ERR_INVALID_ARG, "bad sources/count");
+    if (mem != BC_MEM_HOST && mem != BC_MEM_DEVICE) return bc_fail(ctx, BC_ERR_INVALID_ARG, "bad mem");
+    std::vector<int32_t> host;
+    const int32_t *hs = sources;
+    if (sources == nullptr) {
+        host.resize((size_t)count);
+        for (int64_t i = 0; i < count; ++i) host[(size_t)i] = (int32_t)i;
+        hs = host.data();
+        mem = BC_MEM_HOST;
+    } else if (mem == BC_MEM_DEVICE) {
+        host.resize((size_t)count);
+        BC_HIP(ctx, hipMemcpy(host.data(), sources, sizeof(int32_t) * (size_t)count, hipMemcpyDeviceToHost));
+        hs = host.data();
+    }
+    for (int64_t i = 0; i < count; ++i)
+        if (hs[i] < 0 || hs[i] >= ctx->n) {
+            char buf[128];
+            snprintf(buf, sizeof buf, "source %d at position %lld is outside [0,%d)", hs[i], (long long)i, ctx->n);
+            return bc_fail(ctx, BC_ERR_INVALID_ARG, buf);
+        }
+    if (count > ctx->sources_cap) {
+        if (ctx->sources) bc_dfree(ctx, ctx->sources);
+        ctx->sources = (int32_t *)bc_dalloc(ctx, sizeof(int32_t) * (size_t)count);
+        if (!ctx->sources) { ctx->sources_cap = 0; return bc_fail(ctx, BC_ERR_NOMEM, "source staging allocation failed"); }
+        ctx->sources_cap = count;
+    }
+    if (count > 0)
+        BC_HIP(ctx, hipMemcpyAsync(ctx->sources, hs, sizeof(int32_t) * (size_t)count, hipMemcpyHostToDevice, ctx->stream));
+    // the host vector must stay alive until the copy is done
+    if (!host.empty() || mem == BC_MEM_HOST) BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    *d_out = ctx->sources;
+    *count_out = count;
+    return BC_OK;
+}
+
+static bc_status check_usable(bc_ctx *ctx) {
+    if (ctx->poisoned) return bc_fail(ctx, BC_ERR_STATE, "context poisoned by an earlier device error");
+    if (hipSetDevice(ctx->device) != hipSuccess) return bc_hip(ctx, hipErrorInvalidDevice, "hipSetDevice");
+    return BC_OK;
+}
+
+static bc_status check_overflow(bc_ctx *ctx) {
+    BC_HIP(ctx, hipMemcpyAsync(ctx->status_host, ctx->status, sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->stream));
+    BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (*ctx->status_host & BC_DEV_SIGMA_OVERFLOW) {
+        ctx->overflow_seen = true;
+        return bc_fail(ctx, BC_ERR_OVERFLOW, "a shortest-path count exceeded 2^64 - 1");
+    }
+    return BC_OK;
+}
+
+bc_status bc_run(bc_ctx *ctx, const int32_t *sources, int64_t count, bc_mem mem) {
+    if (!ctx) return BC_ERR_INVALID_ARG;
+    bc_status s = check_usable(ctx);
+    if (s != BC_OK) return s;
+    if (ctx->overflow_seen) return bc_fail(ctx, BC_ERR_OVERFLOW, "an earlier run overflowed a path count; call bc_reset");
+    const int32_t *d_src = nullptr;
+    int64_t cnt = 0;
+    s = stage_sources(ctx, sources, count, mem, &d_src, &cnt);
+    if (s != BC_OK) return s;
+    if (cnt == 0 || ctx->n == 0) return BC_OK;
+    if (ctx->form == BC_FORM_PLAIN_FP64) s = plain_run(ctx, d_src, cnt, true, nullptr, nullptr, nullptr);
+    else if (ctx->form == BC_FORM_SPARSE) s = sparse_run(ctx, d_src, cnt);
+    else s = bc_fail(ctx, BC_ERR_UNSUPPORTED, "form not available");
+    if (s == BC_OK) ctx->sources_run += cnt;
+    return s;
+}
+
+bc_status bc_read(bc_ctx *ctx, double *bc_out, bc_mem mem) {
+    if (!ctx) return BC_ERR_INVALID_ARG;
+    if (!bc_out && ctx->n > 0) return bc_fail(ctx, BC_ERR_INVALID_ARG, "bc_out is NULL");
+    bc_status s = check_usable(ctx);
+    if (s != BC_OK) return s;
+    s = check_overflow(ctx);
+    if (s != BC_OK) return s;
+    if (ctx->n == 0) return BC_OK;
+    BC_HIP(ctx, hipMemcpyAsync(bc_out, ctx->bc, sizeof(double) * (size_t)ctx->n,
+                               mem == BC_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, ctx->stream));
+    BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return BC_OK;
+}
+
+bc_status bc_reset(bc_ctx *ctx) {
+    if (!ctx) return BC_ERR_INVALID_ARG;
+    bc_status s = check_usable(ctx);
+    if (s != BC_OK) return s;
+    BC_HIP(ctx, hipMemsetAsync(ctx->bc, 0, sizeof(double) * (size_t)std::max(ctx->n, 1), ctx->stream));
+    BC_HIP(ctx, hipMemsetAsync(ctx->status, 0, 256, ctx->stream));
+    BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    for (auto &kv : ctx->timers) {
+        for (auto &pr : kv.second.pending) { hipEventDestroy(pr.first); hipEventDestroy(pr.second); }
+        kv.second = KernelTimer();
+    }
+    ctx->overflow_seen = false;
+    ctx->sources_run = 0;
+    return BC_OK;
+}
+
+bc_status bc_read_sssp(bc_ctx *ctx, const int32_t *sources, int32_t count,
+                       int32_t *dist, uint64_t *sigma, double *delta) {
+    if (!ctx) return BC_ERR_INVALID_ARG;
+    bc_status s = check_usable(ctx);
+    if (s != BC_OK) return s;
+    int32_t maxc = ctx->form == BC_FORM_SPARSE ? ctx->sp.batch : 4096;
+    if (!sources || count < 1 || count > maxc) return bc_fail(ctx, BC_ERR_INVALID_ARG, "count must be in [1, batch]");
+    const int32_t *d_src = nullptr;
+    int64_t cnt = 0;
+    s = stage_sources(ctx, sources, count, BC_MEM_HOST, &d_src, &cnt);
+    if (s != BC_OK) return s;
+    size_t cells = (size_t)count * (size_t)std::max(ctx->n, 1);
+    int32_t *dd = (int32_t *)bc_dalloc(ctx, cells * sizeof(int32_t));
+    uint64_t *ds = (uint64_t *)bc_dalloc(ctx, cells * sizeof(uint64_t));
+    double *dl = (double *)bc_dalloc(ctx, cells * sizeof(double));
+    auto cleanup = [&]() { bc_dfree(ctx, dd); bc_dfree(ctx, ds); bc_dfree(ctx, dl); };
+    if (!dd || !ds || !dl) { cleanup(); return bc_fail(ctx, BC_ERR_NOMEM, "dump allocation failed"); }
+    // The overflow flag is shared with bc_run: remember and restore it.
+    BC_HIP(ctx, hipMemcpyAsync(ctx->status_host, ctx->status, sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->stream));
+    BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    uint32_t before = *ctx->status_host;
+    BC_HIP(ctx, hipMemsetAsync(ctx->status, 0, sizeof(uint32_t), ctx->stream));
+    if (ctx->form == BC_FORM_PLAIN_FP64) s = plain_run(ctx, d_src, count, false, dl, dd, ds);
+    else s = sparse_dump(ctx, d_src, count, dd, ds, dl);
+    if (s != BC_OK) { cleanup(); return s; }
+    BC_HIP(ctx, hipMemcpyAsync(ctx->status_host, ctx->status, sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->stream));
+    BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    uint32_t now = *ctx->status_host;
+    *ctx->status_host = before;
+    BC_HIP(ctx, hipMemcpyAsync(ctx->status, ctx->status_host, sizeof(uint32_t), hipMemcpyHostToDevice, ctx->stream));
+    BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (now & BC_DEV_SIGMA_OVERFLOW) { cleanup(); return bc_fail(ctx, BC_ERR_OVERFLOW, "a shortest-path count exceeded 2^64 - 1"); }
+    if (ctx->n > 0) {
+        if (dist) BC_HIP(ctx, hipMemcpy(dist, dd, cells * sizeof(int32_t), hipMemcpyDeviceToHost));
+        if (sigma) BC_HIP(ctx, hipMemcpy(sigma, ds, cells * sizeof(uint64_t), hipMemcpyDeviceToHost));
+        if (delta) BC_HIP(ctx, hipMemcpy(delta, dl, cells * sizeof(double), hipMemcpyDeviceToHost));
+    }
+    cleanup();
+    return BC_OK;
+}
+
+bc_status bc_get_info(const bc_ctx *ctx, bc_info *out) {
+    if (!ctx || !out) return BC_ERR_INVALID_ARG;
+    memset(out, 0, sizeof(*out));
+    out->n = ctx->n;
+    out->m = ctx->nnz / 2;
+    out->max_degree = ctx->max_degree;
+    out->weighted = ctx->weighted ? 1 : 0;
+    out->form = ctx->form;
+    out->batch = ctx->form == BC_FORM_SPARSE ? ctx->sp.batch : 1;
+    out->max_levels = ctx->max_levels;
+    out->sources_run = ctx->sources_run;
+    out->device_bytes = ctx->device_bytes;
+    return BC_OK;
+}
+
+bc_status bc_get_timing(bc_ctx *ctx, const char *kernel, double *total_ms, int64_t *launches) {
+    if (!ctx || !kernel || !total_ms || !launches) return BC_ERR_INVALID_ARG;
+    *total_ms = 0.0;
+    *launches = 0;
+    auto it = ctx->timers.find(kernel);
+    if (it == ctx->timers.end()) return BC_OK;
+    BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    for (auto &pr : it->second.pending) {
+        float ms = 0.f;
+        BC_HIP(ctx, hipEventElapsedTime(&ms, pr.first, pr.second));
+        it->second.total_ms += ms;
+        hipEventDestroy(pr.first);
+        hipEventDestroy(pr.second);
+    }
+    it->second.pending.clear();
+    *total_ms = it->second.total_ms;
+    *launches = it->second.launches;
+    return BC_OK;
+}
+
+void bc_destroy(bc_ctx *ctx) {
+    if (!ctx) return;
+    release_all(ctx);
+    delete ctx;
+}
+
+} // extern "C"

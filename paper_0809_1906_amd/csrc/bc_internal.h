@@ -1,0 +1,123 @@
+// Internal declarations shared by the host side of the library and the
+// kernel launchers.  Not part of the public interface (include/bc.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "bc.h"
+
+// Device status word bits, OR-ed in by kernels and read by bc_read.
+enum : uint32_t {
+    BC_DEV_SIGMA_OVERFLOW = 1u, // a path count exceeded 2^64 - 1
+};
+
+// Timing of one kernel name: HIP event pairs not yet folded into total_ms.
+struct KernelTimer {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+    double total_ms = 0.0;
+    int64_t launches = 0;
+};
+
+// State of the batched sparse form (per-level frontier bitmaps).
+struct SparseState {
+    int32_t batch = 0;        // sources per batch, multiple of 64
+    int32_t words = 0;        // batch / 64 bitmap words per vertex
+    int32_t level_cap = 0;    // levels the front array can hold
+    uint64_t *front = nullptr;   // [level_cap][n][words]
+    uint64_t *visited = nullptr; // [n][words]
+    uint64_t *sigma = nullptr;   // [n][batch]
+    float *cval = nullptr;       // [n][batch]  c(v) = (1 + delta(v)) / sigma(v)
+    double *delta_dump = nullptr;// [n][batch]  only for bc_read_sssp
+    int32_t *src = nullptr;      // [batch] sources of the current batch (-1 = empty lane)
+    uint32_t *counts = nullptr;  // [level_cap] non-empty frontier words per level
+    uint32_t *counts_host = nullptr; // pinned mirror of counts
+};
+
+// State of the plain per-source form.
+struct PlainState {
+    int32_t groups = 0;       // persistent workgroups
+    int32_t *dist = nullptr;  // [groups][n]
+    uint64_t *sigma = nullptr;// [groups][n]
+    double *acc = nullptr;    // [groups][n]
+    int32_t *queue = nullptr; // [groups][n]
+    int32_t *lev = nullptr;   // [groups][n + 2] level starts in the queue
+    uint32_t *next = nullptr; // work counter
+};
+
+struct bc_ctx {
+    // graph (host copy of the shape only)
+    int32_t n = 0, nnz = 0;
+    int32_t max_degree = 0;
+    uint32_t max_weight = 1;
+    bool weighted = false;
+
+    // device, stream, memory
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bc_allocator alloc{};
+    std::vector<std::pair<void *, size_t>> owned; // every device allocation
+    int64_t device_bytes = 0;
+
+    // device copies
+    int32_t *row_ptr = nullptr;
+    int32_t *col = nullptr;
+    uint32_t *weight = nullptr;
+    double *bc = nullptr;
+    uint32_t *status = nullptr;
+    uint32_t *status_host = nullptr; // pinned
+    int32_t *sources = nullptr;      // staging for bc_run
+    int64_t sources_cap = 0;
+    double *dump_delta64 = nullptr;  // bc_read_sssp outputs, [count][n]
+    int32_t *dump_dist = nullptr;
+    uint64_t *dump_sigma = nullptr;
+
+    // forms
+    bc_form form = BC_FORM_PLAIN_FP64;
+    SparseState sp;
+    PlainState pl;
+
+    // bookkeeping
+    int64_t sources_run = 0;
+    int32_t max_levels = 0;
+    bool poisoned = false;
+    bool overflow_seen = false;
+    std::string err;
+
+    bool timing = false;
+    std::map<std::string, KernelTimer> timers;
+};
+
+// ---- helpers implemented in bc_api.cpp --------------------------------------
+bc_status bc_fail(bc_ctx *ctx, bc_status s, const std::string &msg);
+bc_status bc_hip(bc_ctx *ctx, hipError_t e, const char *what);
+void *bc_dalloc(bc_ctx *ctx, size_t bytes);
+void bc_dfree(bc_ctx *ctx, void *p);
+// Records an event pair around a launch when timing is on.
+struct LaunchTimer {
+    bc_ctx *ctx;
+    const char *name;
+    hipEvent_t a = nullptr, b = nullptr;
+    LaunchTimer(bc_ctx *c, const char *nm);
+    void done();
+};
+
+#define BC_HIP(ctx, expr)                                                         \
+    do {                                                                          \
+        hipError_t e__ = (expr);                                                  \
+        if (e__ != hipSuccess) return bc_hip((ctx), e__, #expr);                  \
+    } while (0)
+
+// ---- forms (kernels + launchers) ----------------------------------------------
+bc_status plain_prepare(bc_ctx *ctx);
+bc_status plain_run(bc_ctx *ctx, const int32_t *d_sources, int64_t count, bool accumulate,
+                    double *delta_dump, int32_t *dist_dump, uint64_t *sigma_dump);
+
+bc_status sparse_prepare(bc_ctx *ctx, int32_t batch);
+bc_status sparse_run(bc_ctx *ctx, const int32_t *d_sources, int64_t count);
+bc_status sparse_dump(bc_ctx *ctx, const int32_t *d_sources, int32_t count,
+                      int32_t *dist_dump, uint64_t *sigma_dump, double *delta_dump);

@@ -1,0 +1,109 @@
+"""The C-ABI library on the host: it loads, exports every declared symbol,
+and rejects invalid input before any device work (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import paper_0809_1906_amd as bcgpu
+from paper_0809_1906_amd import binding as B
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "bc.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bc_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = bcgpu.load()
+    names = _declared_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(lib, name), f"{name} declared in bc.h but not exported"
+    assert set(names) == set(B.SIGNATURES), "binding signatures out of step with bc.h"
+
+
+def test_status_strings():
+    for code, name in B.STATUS_NAMES.items():
+        assert bcgpu.bc_status_string(code).startswith(name)
+
+
+def test_options_defaults():
+    opt = bcgpu.bc_options_init()
+    assert opt.struct_size == ctypes.sizeof(B.bc_options)
+    assert opt.form == B.BC_FORM_AUTO and opt.batch == 0 and opt.device == -1
+
+
+def _graph_struct(n, rp, col, w=None):
+    rp = np.ascontiguousarray(rp, np.int32)
+    col = np.ascontiguousarray(col, np.int32)
+    g = B.bc_graph()
+    g.n = n
+    g.nnz = int(col.size)
+    g.row_ptr = rp.ctypes.data
+    g.col = col.ctypes.data if col.size else None
+    if w is not None:
+        w = np.ascontiguousarray(w, np.uint32)
+        g.weight = w.ctypes.data
+    g.mem = B.BC_MEM_HOST
+    return g, (rp, col, w)
+
+
+def _create_status(n, rp, col, w=None, opt=None):
+    g, keep = _graph_struct(n, rp, col, w)
+    ctx = ctypes.c_void_p()
+    st = bcgpu.load().bc_create(ctypes.byref(g), ctypes.byref(opt) if opt is not None else None, ctypes.byref(ctx))
+    assert ctx.value is None, "a failed create must leave no context"
+    return st, bcgpu.bc_last_error(None)
+
+
+@pytest.mark.parametrize("case,n,rp,col,w", [
+    ("asymmetric", 3, [0, 1, 1, 1], [1], None),
+    ("self-loop", 2, [0, 2, 3], [0, 1, 0], None),
+    ("duplicate", 2, [0, 2, 4], [1, 1, 0, 0], None),
+    ("unsorted", 3, [0, 2, 3, 4], [2, 1, 0, 0], None),
+    ("out-of-range", 2, [0, 1, 2], [5, 0], None),
+    ("row_ptr[0]", 2, [1, 1, 2], [1, 0], None),
+    ("row_ptr[n] != nnz", 2, [0, 1, 1], [1, 0], None),
+    ("decreasing", 3, [0, 2, 1, 2], [1, 2], None),
+    ("zero weight", 2, [0, 1, 2], [1, 0], [0, 0]),
+    ("asymmetric weight", 2, [0, 1, 2], [1, 0], [3, 4]),
+])
+def test_invalid_graphs_rejected_on_host(case, n, rp, col, w):
+    st, msg = _create_status(n, rp, col, w)
+    assert st == B.BC_ERR_INVALID_GRAPH, (case, st, msg)
+    assert msg
+
+
+def test_weight_times_diameter_bound():
+    g = gg.path(3)
+    st, msg = _create_status(g.n, g.row_ptr, g.col, np.full(g.nnz, 2 ** 30, np.uint32))
+    assert st == B.BC_ERR_INVALID_GRAPH and "2^31" in msg
+
+
+def test_invalid_arguments():
+    lib = bcgpu.load()
+    ctx = ctypes.c_void_p()
+    assert lib.bc_create(None, None, ctypes.byref(ctx)) == B.BC_ERR_INVALID_ARG
+    g, keep = _graph_struct(2, [0, 1, 2], [1, 0])
+    assert lib.bc_create(ctypes.byref(g), None, None) == B.BC_ERR_INVALID_ARG
+    opt = bcgpu.bc_options_init()
+    opt.batch = 100  # not a multiple of 64
+    assert lib.bc_create(ctypes.byref(g), ctypes.byref(opt), ctypes.byref(ctx)) == B.BC_ERR_INVALID_ARG
+    opt = bcgpu.bc_options_init()
+    opt.struct_size = 3
+    assert lib.bc_create(ctypes.byref(g), ctypes.byref(opt), ctypes.byref(ctx)) == B.BC_ERR_INVALID_ARG
+    opt = bcgpu.bc_options_init()
+    opt.form = 42
+    assert lib.bc_create(ctypes.byref(g), ctypes.byref(opt), ctypes.byref(ctx)) == B.BC_ERR_INVALID_ARG
+    # calls on a NULL context
+    assert lib.bc_run(None, None, -1, 0) == B.BC_ERR_INVALID_ARG
+    assert lib.bc_read(None, None, 0) == B.BC_ERR_INVALID_ARG
+    assert lib.bc_reset(None) == B.BC_ERR_INVALID_ARG
+    lib.bc_destroy(None)

@@ -1,0 +1,189 @@
+"""GPU parity: the HIP library, called through the C ABI, against the oracle.
+
+Distances and path counts must match bit-exactly; BC and per-source
+dependencies within the form's tolerance (max |x-y| / max(|y|, 1)):
+1e-12 for the plain FP64 form, 1e-5 for the batched forms whose c(v) state is
+stored in FP32.
+"""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"plain": 1e-12, "sparse": 1e-5}
+FORMS = ["plain", "sparse"]
+
+
+def rel_err(x, y):
+    x, y = np.asarray(x, np.float64), np.asarray(y, np.float64)
+    if y.size == 0:
+        return 0.0
+    return float(np.max(np.abs(x - y) / np.maximum(np.abs(y), 1.0)))
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+def small_graphs():
+    return [gg.path(1), gg.path(2), gg.path(33), gg.star(50), gg.cycle(31), gg.cycle(32), gg.complete(64),
+            gg.complete_bipartite(5, 7), gg.random_tree(100, 3),
+            gg.disjoint_union(gg.path(7), gg.cycle(8), gg.star(6), gg.complete(4)),
+            gg.grid(20, 20), gg.er1024(), gg.watts_strogatz(300, 6, 0.1, 7)]
+
+
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("gi", range(13))
+def test_bc_all_sources(gpu_lib, form, gi):
+    g = small_graphs()[gi]
+    say("bc_all_sources", form, g.name, g.n, g.m)
+    want = oracle.bc(g)
+    with gpu_lib.BC(g, form=form) as ctx:
+        ctx.run()
+        got = ctx.read()
+    assert rel_err(got, want) <= TOL[form], g.name
+
+
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("name", ["er1024", "grid20", "union", "ws300"])
+def test_sssp_bit_exact(gpu_lib, form, name):
+    g = {"er1024": gg.er1024, "grid20": lambda: gg.grid(20, 20),
+         "union": lambda: gg.disjoint_union(gg.path(40), gg.er_plus_tree(200, 5.0, 3)),
+         "ws300": lambda: gg.watts_strogatz(300, 6, 0.1, 7)}[name]()
+    say("sssp_bit_exact", form, name, g.n)
+    rng = gg.Stream(123)
+    src = np.concatenate([np.arange(8), np.arange(g.n - 8, g.n), rng.bounded(np.full(16, g.n))]).astype(np.int32)
+    with gpu_lib.BC(g, form=form) as ctx:
+        dist, sigma, delta = ctx.sssp(src)
+        bc_after = ctx.read()
+    assert np.all(bc_after == 0.0), "bc_read_sssp must not add to BC"
+    for i, s in enumerate(src):
+        d, sg, dl = oracle.sssp_u64(g, int(s))
+        np.testing.assert_array_equal(dist[i], d, err_msg=f"dist, source {s}")
+        np.testing.assert_array_equal(sigma[i], sg, err_msg=f"sigma, source {s}")
+        assert rel_err(delta[i], dl) <= TOL[form], f"delta, source {s}"
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_sigma_above_2_24_uses_exact_counts(gpu_lib, form):
+    """grid 20x20: corner-to-corner count C(38,19) > 2^24."""
+    g = gg.grid(20, 20)
+    say("sigma_above_2_24", form)
+    with gpu_lib.BC(g, form=form) as ctx:
+        _, sigma, _ = ctx.sssp(np.array([0], np.int32))
+    assert int(sigma[0, g.n - 1]) == 35345263800
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_overflow_reported(gpu_lib, form):
+    """grid 35x35: C(68,34) > 2^64 - 1 must give BC_ERR_OVERFLOW, never a wrapped count."""
+    g = gg.grid(35, 35)
+    say("overflow", form)
+    with gpu_lib.BC(g, form=form) as ctx:
+        ctx.run(np.array([0], np.int32))
+        with pytest.raises(gpu_lib.BCError) as ei:
+            ctx.read()
+        assert ei.value.status == gpu_lib.BC_ERR_OVERFLOW
+        with pytest.raises(gpu_lib.BCError):
+            ctx.run(np.array([1], np.int32))
+        ctx.reset()
+        ctx.run(np.array([35 * 17 + 17], np.int32))  # centre: counts stay below 2^64
+        assert np.isfinite(ctx.read()).all()
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_largest_square_grid_within_u64(gpu_lib, form):
+    g = gg.grid(34, 34)
+    say("grid34", form)
+    with gpu_lib.BC(g, form=form) as ctx:
+        _, sigma, _ = ctx.sssp(np.array([0], np.int32))
+    assert int(sigma[0, g.n - 1]) == 7219428434016265740  # C(66,33)
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_multiset_ragged_and_accumulate(gpu_lib, form):
+    g = gg.er_plus_tree(700, 5.0, 31)
+    say("multiset_ragged", form)
+    a = np.array([5, 5, 7, 699, 0], np.int32)
+    b = np.arange(100, 400, dtype=np.int32)  # 300 sources: a full batch of 256 and a ragged tail
+    with gpu_lib.BC(g, form=form) as ctx:
+        ctx.run(a)
+        assert rel_err(ctx.read(), oracle.bc(g, a)) <= TOL[form]
+        ctx.run(b)
+        assert rel_err(ctx.read(), oracle.bc(g, np.concatenate([a, b]))) <= TOL[form]
+        ctx.reset()
+        assert np.all(ctx.read() == 0.0)
+        ctx.run(np.zeros(0, np.int32))
+        assert np.all(ctx.read() == 0.0)
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_invalid_sources(gpu_lib, form):
+    g = gg.path(10)
+    with gpu_lib.BC(g, form=form) as ctx:
+        with pytest.raises(gpu_lib.BCError) as ei:
+            ctx.run(np.array([3, 10], np.int32))
+        assert ei.value.status == gpu_lib.BC_ERR_INVALID_ARG
+        ctx.run(np.array([3], np.int32))
+        np.testing.assert_allclose(ctx.read(), oracle.bc(g, [3]), rtol=1e-12)
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_device_sources_and_deterministic_counts(gpu_lib, form):
+    import torch
+    g = gg.rmat(12, 16, 77)
+    say("device_sources", form, g.n)
+    src = torch.arange(0, g.n, 3, dtype=torch.int32, device="cuda:0")
+    with gpu_lib.BC(g, form=form) as ctx:
+        ctx.run(src)
+        x = ctx.read()
+        d1, s1, _ = ctx.sssp(np.arange(64, dtype=np.int32))
+        d2, s2, _ = ctx.sssp(np.arange(64, dtype=np.int32))
+    np.testing.assert_array_equal(d1, d2)
+    np.testing.assert_array_equal(s1, s2)
+    assert rel_err(x, oracle.bc(g, np.arange(0, g.n, 3))) <= TOL[form]
+
+
+def test_rmat16_full_size_sampled(gpu_lib):
+    """The benchmark workload (RMAT scale 16, batch 256) at full size: one full
+    batch of per-source results bit-exact against the oracle, and BC over 512
+    sources (two batches) within tolerance."""
+    g = gg.rmat16()
+    say("rmat16_full", g.n, g.m)
+    rng = gg.Stream(2024)
+    src = np.unique(np.concatenate([np.arange(8), np.arange(g.n - 8, g.n),
+                                    rng.bounded(np.full(260, g.n))]))[:256].astype(np.int32)
+    assert src.size == 256
+    with gpu_lib.BC(g, form="sparse", batch=256) as ctx:
+        dist, sigma, delta = ctx.sssp(src)
+        for i in range(0, 256, 1):
+            s = int(src[i])
+            d, sg, dl = oracle.sssp_u64(g, s)
+            assert np.array_equal(dist[i], d), f"dist source {s}"
+            assert np.array_equal(sigma[i], sg), f"sigma source {s}"
+            assert rel_err(delta[i], dl) <= 1e-5, f"delta source {s}"
+        sub = rng.bounded(np.full(512, g.n)).astype(np.int32)
+        ctx.run(sub)
+        got = ctx.read()
+    want = oracle.bc(g, sub, threads=8)
+    err = rel_err(got, want)
+    say("rmat16 BC(512 sources) max rel err", err)
+    assert err <= 1e-5
+
+
+def test_rmat16_plain_form_sampled(gpu_lib):
+    g = gg.rmat16()
+    say("rmat16_plain", g.n, g.m)
+    sub = gg.Stream(7).bounded(np.full(96, g.n)).astype(np.int32)
+    with gpu_lib.BC(g, form="plain") as ctx:
+        ctx.run(sub)
+        got = ctx.read()
+        dist, sigma, delta = ctx.sssp(sub[:8])
+    assert rel_err(got, oracle.bc(g, sub, threads=8)) <= 1e-12
+    for i in range(8):
+        d, sg, dl = oracle.sssp_u64(g, int(sub[i]))
+        assert np.array_equal(dist[i], d) and np.array_equal(sigma[i], sg)
+        assert rel_err(delta[i], dl) <= 1e-12
