@@ -114,7 +114,9 @@ typedef struct {
     void *stream;         /* hipStream_t to run on; NULL = the null stream */
     bc_allocator allocator;
     int32_t timing;       /* nonzero: time every kernel launch with HIP events */
-    int32_t reserved[8];
+    int32_t split_degree; /* batched forms: rows longer than this are split into
+                             segments of this many arcs; 0 = default (256) */
+    int32_t reserved[7];
 } bc_options;
 
 /* Fills *opt with the defaults above.  Never fails for a non-NULL opt. */

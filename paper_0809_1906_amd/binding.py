@@ -54,7 +54,8 @@ class bc_allocator(ctypes.Structure):
 class bc_options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("form", ctypes.c_int), ("batch", ctypes.c_int32),
                 ("device", ctypes.c_int32), ("stream", ctypes.c_void_p), ("allocator", bc_allocator),
-                ("timing", ctypes.c_int32), ("reserved", ctypes.c_int32 * 8)]
+                ("timing", ctypes.c_int32), ("split_degree", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 7)]
 
 
 class bc_info(ctypes.Structure):
@@ -200,7 +201,7 @@ class BC:
     """
 
     def __init__(self, graph, form: str = "auto", batch: int = 0, device: int = 0, stream=None,
-                 allocator: str = "torch", timing: bool = False):
+                 allocator: str = "torch", timing: bool = False, split_degree: int = 0):
         import torch
         load()
         if not torch.cuda.is_available():
@@ -215,6 +216,7 @@ class BC:
         opt.device = device
         opt.stream = self._stream.cuda_stream
         opt.timing = 1 if timing else 0
+        opt.split_degree = split_degree
         self._alloc = None
         if allocator == "torch":
             self._alloc = _TorchAllocator(device)

@@ -227,6 +227,8 @@ bc_status bc_create(const bc_graph *g, const bc_options *opt_in, bc_ctx **out) {
         return fail_create(BC_ERR_INVALID_ARG, "unknown form");
     if (opt.batch < 0 || opt.batch % 64 != 0 || opt.batch > 4096)
         return fail_create(BC_ERR_INVALID_ARG, "batch must be 0 or a multiple of 64 up to 4096");
+    if (opt.split_degree != 0 && opt.split_degree < 64)
+        return fail_create(BC_ERR_INVALID_ARG, "split_degree must be 0 (default) or at least 64");
     if ((opt.allocator.alloc == nullptr) != (opt.allocator.free == nullptr))
         return fail_create(BC_ERR_INVALID_ARG, "allocator needs both alloc and free, or neither");
 
@@ -276,6 +278,7 @@ bc_status bc_create(const bc_graph *g, const bc_options *opt_in, bc_ctx **out) {
     ctx->alloc = opt.allocator;
     ctx->timing = opt.timing != 0;
     ctx->form = form;
+    ctx->h_row_ptr.assign(hrp, hrp + (size_t)n + 1);
 
     auto bail = [&](bc_status s, const std::string &m) {
         release_all(ctx);
@@ -309,7 +312,7 @@ bc_status bc_create(const bc_graph *g, const bc_options *opt_in, bc_ctx **out) {
 
     bc_status ps = BC_OK;
     if (form == BC_FORM_PLAIN_FP64) ps = plain_prepare(ctx);
-    else if (form == BC_FORM_SPARSE) ps = sparse_prepare(ctx, opt.batch ? opt.batch : 256);
+    else if (form == BC_FORM_SPARSE) ps = sparse_prepare(ctx, opt.batch ? opt.batch : 256, opt.split_degree);
     if (ps != BC_OK) return bail(ps, ctx->err);
     if (hipStreamSynchronize(ctx->stream) != hipSuccess) return bail(BC_ERR_DEVICE, "stream synchronisation failed");
     *out = ctx;

@@ -28,7 +28,9 @@ struct SparseState {
     int32_t batch = 0;        // sources per batch, multiple of 64
     int32_t words = 0;        // batch / 64 bitmap words per vertex
     int32_t level_cap = 0;    // levels the front array can hold
+    int32_t split = 256;      // rows longer than this are split into segments
     uint64_t *front = nullptr;   // [level_cap][n][words]
+    uint32_t *any = nullptr;     // [level_cap][(n+31)/32] OR over sources, per vertex
     uint64_t *visited = nullptr; // [n][words]
     uint64_t *sigma = nullptr;   // [n][batch]
     float *cval = nullptr;       // [n][batch]  c(v) = (1 + delta(v)) / sigma(v)
@@ -36,6 +38,14 @@ struct SparseState {
     int32_t *src = nullptr;      // [batch] sources of the current batch (-1 = empty lane)
     uint32_t *counts = nullptr;  // [level_cap] non-empty frontier words per level
     uint32_t *counts_host = nullptr; // pinned mirror of counts
+    int32_t *heavy_id = nullptr; // [n] index among heavy rows or -1
+    int32_t *heavy_v = nullptr;  // [nheavy]
+    int32_t *heavy_nseg = nullptr; // [nheavy] segments per heavy row
+    uint32_t *arrive = nullptr;  // [nheavy][words] segment arrival counters
+    int32_t depth_guess = 8;     // forward levels launched before the first check
+    int32_t *seg_v = nullptr, *seg_beg = nullptr, *seg_end = nullptr; // [nseg]
+    int32_t nheavy = 0, nseg = 0;
+    double *hacc = nullptr;      // [nheavy][batch] partial sums of split rows (u64 or f64)
 };
 
 // State of the plain per-source form.
@@ -53,6 +63,7 @@ struct bc_ctx {
     // graph (host copy of the shape only)
     int32_t n = 0, nnz = 0;
     int32_t max_degree = 0;
+    std::vector<int32_t> h_row_ptr; // host copy of the CSR offsets
     uint32_t max_weight = 1;
     bool weighted = false;
 
@@ -117,7 +128,7 @@ bc_status plain_prepare(bc_ctx *ctx);
 bc_status plain_run(bc_ctx *ctx, const int32_t *d_sources, int64_t count, bool accumulate,
                     double *delta_dump, int32_t *dist_dump, uint64_t *sigma_dump);
 
-bc_status sparse_prepare(bc_ctx *ctx, int32_t batch);
+bc_status sparse_prepare(bc_ctx *ctx, int32_t batch, int32_t split_degree);
 bc_status sparse_run(bc_ctx *ctx, const int32_t *d_sources, int64_t count);
 bc_status sparse_dump(bc_ctx *ctx, const int32_t *d_sources, int32_t count,
                       int32_t *dist_dump, uint64_t *sigma_dump, double *delta_dump);

@@ -187,3 +187,24 @@ def test_rmat16_plain_form_sampled(gpu_lib):
         d, sg, dl = oracle.sssp_u64(g, int(sub[i]))
         assert np.array_equal(dist[i], d) and np.array_equal(sigma[i], sg)
         assert rel_err(delta[i], dl) <= 1e-12
+
+
+@pytest.mark.parametrize("split", [64, 100, 256])
+@pytest.mark.parametrize("name", ["star4096", "rmat12", "kab"])
+def test_split_rows_parity(gpu_lib, split, name):
+    """Rows longer than split_degree are cut into segments whose partial sums
+    meet through atomics; results must not depend on the cut."""
+    g = {"star4096": lambda: gg.star(4096), "rmat12": lambda: gg.rmat(12, 16, 5),
+         "kab": lambda: gg.complete_bipartite(3, 700)}[name]()
+    say("split_rows", name, split, g.n, int(g.degrees().max()))
+    want = oracle.bc(g)
+    with gpu_lib.BC(g, form="sparse", split_degree=split) as ctx:
+        ctx.run()
+        got = ctx.read()
+        src = np.array([0, 1, g.n - 1, g.n // 2], np.int32)
+        dist, sigma, delta = ctx.sssp(src)
+    assert rel_err(got, want) <= 1e-5
+    for i, s in enumerate(src):
+        d, sg, dl = oracle.sssp_u64(g, int(s))
+        assert np.array_equal(dist[i], d) and np.array_equal(sigma[i], sg)
+        assert rel_err(delta[i], dl) <= 1e-5
