@@ -8,7 +8,9 @@ m the undirected edge count after preprocessing.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 
-Prints one JSON line.
+Prints one JSON line.  Profiling runs use --sources N (a bounded prefix of the
+sources) and --calibrate-copy (a 1 GiB device-to-device copy at the end, the
+reference against which rocprofv3 FETCH_SIZE / WRITE_SIZE are scaled).
 """
 from __future__ import annotations
 
@@ -22,10 +24,40 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+import hashlib  # noqa: E402
+
 import numpy as np  # noqa: E402
 
 METRIC = "BC TEPS (sources·m/s) on RMAT-16; batched-MFMA vs plain BFS form, same GPU"
 HBM_PEAK_GBS = 8000.0
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sparse_rmat16_traffic.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_0809_1906_amd", "csrc", "sparse.hip")
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when the summary is missing or the kernel source changed
+    since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    fields = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#") and "=" in line:
+                k, v = line.split("=", 1)
+                fields[k.strip()] = v.strip()
+    if fields.get("source_sha256_16") != kernel_source_hash():
+        return None
+    v = fields.get(f"{kernel}.bytes_per_launch")
+    return float(v) if v else None
 
 
 def log(*a):
@@ -70,6 +102,8 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--sources", type=int, default=0, help="run only the first N sources (profiling)")
+    ap.add_argument("--calibrate-copy", action="store_true", help="end with a 1 GiB device copy")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 (sources shard across "
@@ -89,20 +123,21 @@ def main():
     t0 = time.perf_counter()
     g = gg.rmat16()
     log(f"graph rmat16 n={g.n} m={g.m} max_deg={int(g.degrees().max())} gen {time.perf_counter() - t0:.1f}s")
-    S = g.n
+    S = g.n if args.sources <= 0 else min(args.sources, g.n)
+    src = None if S == g.n else np.arange(S, dtype=np.int32)
     work = float(S) * g.m
 
     def timed_runs(form, steps, warmup, batch=0):
         ctx = bcgpu.BC(g, form=form, batch=batch, timing=True)
         for i in range(warmup):
-            ctx.run()
+            ctx.run(src)
             ctx.read()
             log(f"{form} warmup {i} done")
         ctx.reset()
         torch.cuda.synchronize()
         t = time.perf_counter()
         for i in range(steps):
-            ctx.run()
+            ctx.run(src)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t) / steps
         bc = ctx.read()
@@ -122,11 +157,7 @@ def main():
     dom_ms, dom_launches = kern[dom]
     alg_bytes_total = float(S) * args.steps * bytes_src["fwd" if dom == "fwd_pull" else "bwd"]
     achieved = alg_bytes_total / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else None
-    traffic = None
-    tpath = os.path.join(ROOT, "profiles", "traffic_rmat16.json")
-    if os.path.exists(tpath):
-        with open(tpath) as f:
-            traffic = json.load(f).get(dom)
+    traffic = measured_traffic(dom)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
                 "avg_launch_ms": dom_ms / max(dom_launches, 1), "launches": dom_launches,
@@ -143,6 +174,14 @@ def main():
                  "sparse_vs_plain_max_rel_diff": err}
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(g)
+
+    if args.calibrate_copy:
+        x = torch.empty(256 << 20, dtype=torch.float32, device=dev)  # 1 GiB
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        log("calibration copy: 1 GiB read, 1 GiB written")
 
     out = {
         "metric": METRIC,

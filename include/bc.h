@@ -115,9 +115,18 @@ typedef struct {
     bc_allocator allocator;
     int32_t timing;       /* nonzero: time every kernel launch with HIP events */
     int32_t split_degree; /* batched forms: rows longer than this are split into
-                             segments of this many arcs; 0 = default (256) */
-    int32_t reserved[7];
+                             segments of this many arcs; 0 = default (128) */
+    int32_t vertex_order; /* internal vertex numbering (a device layout choice that
+                             results never show): BC_ORDER_DEGREE (default) or
+                             BC_ORDER_INPUT */
+    int32_t reserved[6];
 } bc_options;
+
+/* Internal vertex numbering.  BC_ORDER_DEGREE renumbers vertices by
+ * nonincreasing degree so that the rows of high-degree vertices, which most
+ * arcs point to, share a small region of memory; every input and output of the
+ * interface stays in the caller's numbering. */
+enum { BC_ORDER_DEGREE = 0, BC_ORDER_INPUT = 1 };
 
 /* Fills *opt with the defaults above.  Never fails for a non-NULL opt. */
 void bc_options_init(bc_options *opt);

@@ -55,7 +55,7 @@ class bc_options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("form", ctypes.c_int), ("batch", ctypes.c_int32),
                 ("device", ctypes.c_int32), ("stream", ctypes.c_void_p), ("allocator", bc_allocator),
                 ("timing", ctypes.c_int32), ("split_degree", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 7)]
+                ("vertex_order", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
 
 
 class bc_info(ctypes.Structure):
@@ -201,7 +201,8 @@ class BC:
     """
 
     def __init__(self, graph, form: str = "auto", batch: int = 0, device: int = 0, stream=None,
-                 allocator: str = "torch", timing: bool = False, split_degree: int = 0):
+                 allocator: str = "torch", timing: bool = False, split_degree: int = 0,
+                 vertex_order: str = "degree"):
         import torch
         load()
         if not torch.cuda.is_available():
@@ -217,6 +218,7 @@ class BC:
         opt.stream = self._stream.cuda_stream
         opt.timing = 1 if timing else 0
         opt.split_degree = split_degree
+        opt.vertex_order = {"degree": 0, "input": 1}[vertex_order]
         self._alloc = None
         if allocator == "torch":
             self._alloc = _TorchAllocator(device)

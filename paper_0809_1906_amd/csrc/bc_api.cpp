@@ -105,9 +105,9 @@ void release_all(bc_ctx *ctx) {
     for (auto &pr : owned) bc_dfree(ctx, pr.first);
     ctx->owned.clear();
     if (ctx->status_host) hipHostFree(ctx->status_host);
-    if (ctx->sp.counts_host) hipHostFree(ctx->sp.counts_host);
+    if (ctx->sp.any_host) hipHostFree(ctx->sp.any_host);
     ctx->status_host = nullptr;
-    ctx->sp.counts_host = nullptr;
+    ctx->sp.any_host = nullptr;
 }
 
 } // namespace
@@ -227,6 +227,8 @@ bc_status bc_create(const bc_graph *g, const bc_options *opt_in, bc_ctx **out) {
         return fail_create(BC_ERR_INVALID_ARG, "unknown form");
     if (opt.batch < 0 || opt.batch % 64 != 0 || opt.batch > 4096)
         return fail_create(BC_ERR_INVALID_ARG, "batch must be 0 or a multiple of 64 up to 4096");
+    if (opt.vertex_order != BC_ORDER_DEGREE && opt.vertex_order != BC_ORDER_INPUT)
+        return fail_create(BC_ERR_INVALID_ARG, "unknown vertex_order");
     if (opt.split_degree != 0 && opt.split_degree < 64)
         return fail_create(BC_ERR_INVALID_ARG, "split_degree must be 0 (default) or at least 64");
     if ((opt.allocator.alloc == nullptr) != (opt.allocator.free == nullptr))
@@ -278,7 +280,6 @@ bc_status bc_create(const bc_graph *g, const bc_options *opt_in, bc_ctx **out) {
     ctx->alloc = opt.allocator;
     ctx->timing = opt.timing != 0;
     ctx->form = form;
-    ctx->h_row_ptr.assign(hrp, hrp + (size_t)n + 1);
 
     auto bail = [&](bc_status s, const std::string &m) {
         release_all(ctx);
@@ -292,20 +293,67 @@ bc_status bc_create(const bc_graph *g, const bc_options *opt_in, bc_ctx **out) {
     if (hipSetDevice(dev) != hipSuccess) return bail(BC_ERR_DEVICE, "hipSetDevice failed");
     ctx->device = dev;
 
+    // Internal numbering: vertices by nonincreasing degree (stable), or as given.
+    const bool relabel = opt.vertex_order == BC_ORDER_DEGREE && n > 1;
+    std::vector<int32_t> new_of_old, irp, icol;
+    std::vector<uint32_t> iw;
+    const int32_t *urp = hrp, *ucol = hcol;
+    const uint32_t *uw = hw;
+    if (relabel) {
+        std::vector<int32_t> old_of_new((size_t)n);
+        for (int32_t v = 0; v < n; ++v) old_of_new[(size_t)v] = v;
+        std::stable_sort(old_of_new.begin(), old_of_new.end(), [&](int32_t a, int32_t b) {
+            return hrp[a + 1] - hrp[a] > hrp[b + 1] - hrp[b];
+        });
+        new_of_old.resize((size_t)n);
+        for (int32_t u = 0; u < n; ++u) new_of_old[(size_t)old_of_new[(size_t)u]] = u;
+        irp.resize((size_t)n + 1);
+        icol.resize((size_t)std::max(nnz, 1));
+        if (hw) iw.resize((size_t)std::max(nnz, 1));
+        irp[0] = 0;
+        std::vector<std::pair<int32_t, uint32_t>> row;
+        for (int32_t u = 0; u < n; ++u) {
+            const int32_t o = old_of_new[(size_t)u];
+            const int32_t b = hrp[o], e = hrp[o + 1];
+            irp[(size_t)u + 1] = irp[(size_t)u] + (e - b);
+            row.clear();
+            for (int32_t k = b; k < e; ++k) row.emplace_back(new_of_old[(size_t)hcol[k]], hw ? hw[k] : 1u);
+            std::sort(row.begin(), row.end());
+            for (size_t k = 0; k < row.size(); ++k) {
+                icol[(size_t)irp[(size_t)u] + k] = row[k].first;
+                if (hw) iw[(size_t)irp[(size_t)u] + k] = row[k].second;
+            }
+        }
+        urp = irp.data();
+        ucol = icol.data();
+        uw = hw ? iw.data() : nullptr;
+    }
+    ctx->h_row_ptr.assign(urp, urp + (size_t)n + 1);
+
     ctx->row_ptr = (int32_t *)bc_dalloc(ctx, sizeof(int32_t) * ((size_t)n + 1));
     ctx->col = (int32_t *)bc_dalloc(ctx, sizeof(int32_t) * (size_t)std::max(nnz, 1));
     ctx->bc = (double *)bc_dalloc(ctx, sizeof(double) * (size_t)std::max(n, 1));
+    ctx->bc_scratch = (double *)bc_dalloc(ctx, sizeof(double) * (size_t)std::max(n, 1));
     ctx->status = (uint32_t *)bc_dalloc(ctx, 256);
-    if (!ctx->row_ptr || !ctx->col || !ctx->bc || !ctx->status) return bail(BC_ERR_NOMEM, "device allocation failed");
+    if (!ctx->row_ptr || !ctx->col || !ctx->bc || !ctx->bc_scratch || !ctx->status)
+        return bail(BC_ERR_NOMEM, "device allocation failed");
     if (hw) {
         ctx->weight = (uint32_t *)bc_dalloc(ctx, sizeof(uint32_t) * (size_t)std::max(nnz, 1));
         if (!ctx->weight) return bail(BC_ERR_NOMEM, "device allocation failed");
     }
+    if (relabel) {
+        ctx->new_of_old = (int32_t *)bc_dalloc(ctx, sizeof(int32_t) * (size_t)n);
+        if (!ctx->new_of_old) return bail(BC_ERR_NOMEM, "device allocation failed");
+    }
     if (hipHostMalloc((void **)&ctx->status_host, 256) != hipSuccess) return bail(BC_ERR_NOMEM, "pinned allocation failed");
-    hipMemcpyKind kind = g->mem == BC_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-    if (hipMemcpyAsync(ctx->row_ptr, g->row_ptr, sizeof(int32_t) * ((size_t)n + 1), kind, ctx->stream) != hipSuccess ||
-        (nnz > 0 && hipMemcpyAsync(ctx->col, g->col, sizeof(int32_t) * (size_t)nnz, kind, ctx->stream) != hipSuccess) ||
-        (hw && nnz > 0 && hipMemcpyAsync(ctx->weight, g->weight, sizeof(uint32_t) * (size_t)nnz, kind, ctx->stream) != hipSuccess) ||
+    // Host arrays (the caller's or the relabelled copies) go up synchronously.
+    const bool direct_device = !relabel && g->mem == BC_MEM_DEVICE;
+    hipMemcpyKind kind = direct_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    if (hipMemcpy(ctx->row_ptr, urp, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyHostToDevice) != hipSuccess ||
+        (nnz > 0 && hipMemcpy(ctx->col, direct_device ? g->col : ucol, sizeof(int32_t) * (size_t)nnz, kind) != hipSuccess) ||
+        (hw && nnz > 0 &&
+         hipMemcpy(ctx->weight, direct_device ? g->weight : uw, sizeof(uint32_t) * (size_t)nnz, kind) != hipSuccess) ||
+        (relabel && hipMemcpy(ctx->new_of_old, new_of_old.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice) != hipSuccess) ||
         hipMemsetAsync(ctx->bc, 0, sizeof(double) * (size_t)std::max(n, 1), ctx->stream) != hipSuccess ||
         hipMemsetAsync(ctx->status, 0, 256, ctx->stream) != hipSuccess)
         return bail(BC_ERR_DEVICE, "uploading the graph failed");
@@ -352,6 +400,11 @@ static bc_status stage_sources(bc_ctx *ctx, const int32_t *sources, int64_t coun
         BC_HIP(ctx, hipMemcpyAsync(ctx->sources, hs, sizeof(int32_t) * (size_t)count, hipMemcpyHostToDevice, ctx->stream));
     // the host vector must stay alive until the copy is done
     if (!host.empty() || mem == BC_MEM_HOST) BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    // Explicit sources are caller ids; "every vertex" is generated in internal ids.
+    if (sources != nullptr) {
+        bc_status ms = map_ids_to_internal(ctx, ctx->sources, count);
+        if (ms != BC_OK) return ms;
+    }
     *d_out = ctx->sources;
     *count_out = count;
     return BC_OK;
@@ -398,7 +451,9 @@ bc_status bc_read(bc_ctx *ctx, double *bc_out, bc_mem mem) {
     s = check_overflow(ctx);
     if (s != BC_OK) return s;
     if (ctx->n == 0) return BC_OK;
-    BC_HIP(ctx, hipMemcpyAsync(bc_out, ctx->bc, sizeof(double) * (size_t)ctx->n,
+    s = rows_to_caller_order_f64(ctx, ctx->bc_scratch, ctx->bc, 1);
+    if (s != BC_OK) return s;
+    BC_HIP(ctx, hipMemcpyAsync(bc_out, ctx->bc_scratch, sizeof(double) * (size_t)ctx->n,
                                mem == BC_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, ctx->stream));
     BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
     return BC_OK;
@@ -435,8 +490,14 @@ bc_status bc_read_sssp(bc_ctx *ctx, const int32_t *sources, int32_t count,
     int32_t *dd = (int32_t *)bc_dalloc(ctx, cells * sizeof(int32_t));
     uint64_t *ds = (uint64_t *)bc_dalloc(ctx, cells * sizeof(uint64_t));
     double *dl = (double *)bc_dalloc(ctx, cells * sizeof(double));
-    auto cleanup = [&]() { bc_dfree(ctx, dd); bc_dfree(ctx, ds); bc_dfree(ctx, dl); };
-    if (!dd || !ds || !dl) { cleanup(); return bc_fail(ctx, BC_ERR_NOMEM, "dump allocation failed"); }
+    int32_t *od = (int32_t *)bc_dalloc(ctx, cells * sizeof(int32_t));
+    uint64_t *os = (uint64_t *)bc_dalloc(ctx, cells * sizeof(uint64_t));
+    double *ol = (double *)bc_dalloc(ctx, cells * sizeof(double));
+    auto cleanup = [&]() {
+        bc_dfree(ctx, dd); bc_dfree(ctx, ds); bc_dfree(ctx, dl);
+        bc_dfree(ctx, od); bc_dfree(ctx, os); bc_dfree(ctx, ol);
+    };
+    if (!dd || !ds || !dl || !od || !os || !ol) { cleanup(); return bc_fail(ctx, BC_ERR_NOMEM, "dump allocation failed"); }
     // The overflow flag is shared with bc_run: remember and restore it.
     BC_HIP(ctx, hipMemcpyAsync(ctx->status_host, ctx->status, sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->stream));
     BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -453,9 +514,13 @@ bc_status bc_read_sssp(bc_ctx *ctx, const int32_t *sources, int32_t count,
     BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
     if (now & BC_DEV_SIGMA_OVERFLOW) { cleanup(); return bc_fail(ctx, BC_ERR_OVERFLOW, "a shortest-path count exceeded 2^64 - 1"); }
     if (ctx->n > 0) {
-        if (dist) BC_HIP(ctx, hipMemcpy(dist, dd, cells * sizeof(int32_t), hipMemcpyDeviceToHost));
-        if (sigma) BC_HIP(ctx, hipMemcpy(sigma, ds, cells * sizeof(uint64_t), hipMemcpyDeviceToHost));
-        if (delta) BC_HIP(ctx, hipMemcpy(delta, dl, cells * sizeof(double), hipMemcpyDeviceToHost));
+        if ((s = rows_to_caller_order_i32(ctx, od, dd, count)) != BC_OK ||
+            (s = rows_to_caller_order_u64(ctx, os, ds, count)) != BC_OK ||
+            (s = rows_to_caller_order_f64(ctx, ol, dl, count)) != BC_OK) { cleanup(); return s; }
+        BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        if (dist) BC_HIP(ctx, hipMemcpy(dist, od, cells * sizeof(int32_t), hipMemcpyDeviceToHost));
+        if (sigma) BC_HIP(ctx, hipMemcpy(sigma, os, cells * sizeof(uint64_t), hipMemcpyDeviceToHost));
+        if (delta) BC_HIP(ctx, hipMemcpy(delta, ol, cells * sizeof(double), hipMemcpyDeviceToHost));
     }
     cleanup();
     return BC_OK;

@@ -25,24 +25,25 @@ struct KernelTimer {
 
 // State of the batched sparse form (per-level frontier bitmaps).
 struct SparseState {
-    int32_t batch = 0;        // sources per batch, multiple of 64
+    int32_t batch = 0;        // sources per batch: 64, 128, 256 or 512
     int32_t words = 0;        // batch / 64 bitmap words per vertex
     int32_t level_cap = 0;    // levels the front array can hold
     int32_t split = 256;      // rows longer than this are split into segments
     uint64_t *front = nullptr;   // [level_cap][n][words]
     uint32_t *any = nullptr;     // [level_cap][(n+31)/32] OR over sources, per vertex
     uint64_t *visited = nullptr; // [n][words]
-    uint64_t *sigma = nullptr;   // [n][batch]
+    uint64_t *sigma = nullptr;   // [n][batch] as uint64, or uint32 in its first half
     float *cval = nullptr;       // [n][batch]  c(v) = (1 + delta(v)) / sigma(v)
     double *delta_dump = nullptr;// [n][batch]  only for bc_read_sssp
     int32_t *src = nullptr;      // [batch] sources of the current batch (-1 = empty lane)
-    uint32_t *counts = nullptr;  // [level_cap] non-empty frontier words per level
-    uint32_t *counts_host = nullptr; // pinned mirror of counts
+    uint32_t *any_host = nullptr; // pinned mirror of any, read once per batch
     int32_t *heavy_id = nullptr; // [n] index among heavy rows or -1
-    int32_t *heavy_v = nullptr;  // [nheavy]
     int32_t *heavy_nseg = nullptr; // [nheavy] segments per heavy row
-    uint32_t *arrive = nullptr;  // [nheavy][words] segment arrival counters
+    uint32_t *arrive = nullptr;  // [nheavy] segment arrival counters (per row)
+    uint32_t *arrive_w = nullptr;// [nheavy][words] segment arrival counters (per row and word)
+    bool bwd_per_word = true;    // backward: one wave per (row, word) instead of per row
     int32_t depth_guess = 8;     // forward levels launched before the first check
+    bool wide = false;           // counts need uint64 storage (else uint32)
     int32_t *seg_v = nullptr, *seg_beg = nullptr, *seg_end = nullptr; // [nseg]
     int32_t nheavy = 0, nseg = 0;
     double *hacc = nullptr;      // [nheavy][batch] partial sums of split rows (u64 or f64)
@@ -74,18 +75,19 @@ struct bc_ctx {
     std::vector<std::pair<void *, size_t>> owned; // every device allocation
     int64_t device_bytes = 0;
 
-    // device copies
+    // internal numbering (null when it equals the caller's)
+    int32_t *new_of_old = nullptr; // [n] internal id of caller vertex v
+    double *bc_scratch = nullptr;  // [n] BC in the caller's order, for bc_read
+
+    // device copies (internal numbering)
     int32_t *row_ptr = nullptr;
     int32_t *col = nullptr;
     uint32_t *weight = nullptr;
     double *bc = nullptr;
-    uint32_t *status = nullptr;
+    uint32_t *status = nullptr;      // [0]: BC_DEV_* bits; [1]: a batch needs uint64 counts
     uint32_t *status_host = nullptr; // pinned
     int32_t *sources = nullptr;      // staging for bc_run
     int64_t sources_cap = 0;
-    double *dump_delta64 = nullptr;  // bc_read_sssp outputs, [count][n]
-    int32_t *dump_dist = nullptr;
-    uint64_t *dump_sigma = nullptr;
 
     // forms
     bc_form form = BC_FORM_PLAIN_FP64;
@@ -122,6 +124,12 @@ struct LaunchTimer {
         hipError_t e__ = (expr);                                                  \
         if (e__ != hipSuccess) return bc_hip((ctx), e__, #expr);                  \
     } while (0)
+
+// ---- numbering (common.hip) ------------------------------------------------------
+bc_status map_ids_to_internal(bc_ctx *ctx, int32_t *ids, int64_t count);
+bc_status rows_to_caller_order_f64(bc_ctx *ctx, double *out, const double *in, int64_t rows);
+bc_status rows_to_caller_order_i32(bc_ctx *ctx, int32_t *out, const int32_t *in, int64_t rows);
+bc_status rows_to_caller_order_u64(bc_ctx *ctx, uint64_t *out, const uint64_t *in, int64_t rows);
 
 // ---- forms (kernels + launchers) ----------------------------------------------
 bc_status plain_prepare(bc_ctx *ctx);

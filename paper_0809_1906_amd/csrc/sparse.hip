@@ -1,26 +1,29 @@
-// Batched sparse form: B sources at once (B a multiple of 64), unit weights.
+// Batched sparse form: B sources at once (B = 64 NW, NW in {1, 2, 4, 8}),
+// unit weights.
 //
 // State is batch-minor.  For level l the frontier is a bitmap
 // front[l][v][q] (uint64): bit b of word q is set iff d(s_{64q+b}, v) = l,
 // and any[l] holds one bit per vertex: the OR of its B frontier bits.
-// Path counts sigma[v][64q+b] are uint64 and c(v) = (1 + delta(v)) / sigma(v)
-// is stored as FP32 in cval[v][64q+b]; all sums are formed in FP64 registers.
+// Path counts sigma[v][64q+b] are exact integers, stored as uint32 while every
+// count fits and as uint64 otherwise; c(v) = (1 + delta(v)) / sigma(v) is
+// stored as FP32 in cval[v][64q+b]; all sums are formed in 64-bit registers.
 //
-// One wave handles one (row segment, word) pair; lane b is source 64q+b, so
-// every gather of a neighbour's sigma or c row is one coalesced 512 B (256 B)
-// read.  The wave loads 64 neighbour ids at once, drops those whose any[] bit
-// is clear, gathers the frontier words of the rest, keeps the neighbours whose
-// word intersects its own mask (ballot) and gathers rows for those only, four
-// at a time.  Rows longer than split_degree arcs (hubs) are cut into segments
-// that run on separate waves; their partial sums meet in a small per-hub
-// scratch array through atomics, and the last segment wave to finish completes
-// the hub.
+// One wave handles one row (or one segment of a long row) for all NW words;
+// lane b of word q is source 64q+b, so every gather of a neighbour's sigma or
+// c row is a coalesced 256 B / 512 B read.  The wave loads 64 neighbour ids at
+// once, drops those whose any[] bit is clear, loads the NW frontier words of
+// the rest, keeps the neighbours whose words meet its own masks (ballot) and
+// gathers rows for those only, several in flight at a time.  Rows longer than
+// split_degree arcs (hubs) are cut into segments that run on separate waves;
+// their partial sums meet in a small per-hub scratch array through atomics,
+// and the last segment wave to finish completes the hub.
 //
 //   forward level l -> l+1 (pull):  for w with unvisited sources U,
 //       sigma(w,b) = sum over neighbours v with bit b of front[l][v] & U of
 //       sigma(v,b);  front[l+1][w] = bits where that sum is non-zero.
 //       This is the level-synchronous search of Sec. 4 with the counting rule
-//       lambda_sw = sum of lambda_sv over v in P_s(w) (Sec. 1.1).
+//       lambda_sw = sum of lambda_sv over v in P_s(w) (Sec. 1.1).  Level 0 -> 1
+//       is pushed from the sources instead (lambda = 1 at distance 1).
 //   backward level l (pull):  for v with bits F = front[l][v],
 //       delta(v,b) = sigma(v,b) * sum over neighbours w with bit b of
 //       front[l+1][w] & F of c(w,b)      (Theorem 1.1; ParallelCompute of
@@ -35,8 +38,7 @@ namespace {
 
 constexpr int SB = 256;      // threads per block = 4 waves
 constexpr int WPB = SB / 64; // waves per block
-constexpr int CSLOTS = 64;   // frontier counters per level, one per 128 B line
-constexpr int CSTRIDE = 32;  // uint32 per counter slot
+constexpr int GDEPTH = 8;    // row gathers issued back to back per wave
 
 __device__ __forceinline__ int32_t rl32(int32_t x, int j) { return __builtin_amdgcn_readlane(x, j); }
 __device__ __forceinline__ uint64_t rl64(uint64_t x, int j) {
@@ -52,135 +54,199 @@ __device__ __forceinline__ int pop_lowest(uint64_t &m) {
 
 // Graph-side description shared by the level kernels.
 struct Topo {
-    int32_t n, NW, B;
+    int32_t n, B;
     const int32_t *rp, *col;
-    const int32_t *heavy_id;                 // [n]: index among heavy rows, -1 for light rows
+    const int32_t *heavy_id;                  // [n]: index among heavy rows, -1 for light rows
     const int32_t *seg_v, *seg_beg, *seg_end; // [nseg]: segments of heavy rows
     int32_t nseg;
-    const int32_t *heavy_v;                  // [nheavy]
-    const int32_t *heavy_nseg;               // [nheavy]: segments per heavy row
-    int32_t nheavy;
+    const int32_t *heavy_nseg;                // [nheavy]: segments per heavy row
 };
 
-// Sum over arcs [beg, end) of row w of sigma(v, 64q+lane) for neighbours v
-// whose frontier word intersects U at this lane.  Returns the sum; ovf is set
-// when a uint64 addition wrapped.
-__device__ __forceinline__ uint64_t fwd_scan(const Topo &t, int32_t beg, int32_t end, int q, uint64_t U,
-                                             const uint32_t *__restrict__ any_cur,
-                                             const uint64_t *__restrict__ fcur,
-                                             const uint64_t *__restrict__ sigma, int lane, bool &ovf) {
-    const uint64_t *sig_q = sigma + (size_t)q * 64 + lane;
-    uint64_t acc = 0;
+// Which row (or row segment) wave `wid` serves.  Returns false when the wave
+// has nothing to do (a heavy row in the light range, or past the end).
+struct Item {
+    int32_t v, beg, end, h;
+    bool first; // the segment that starts the row (or a light row)
+};
+__device__ __forceinline__ bool item_of(const Topo &t, int64_t wid, Item &it) {
+    if (wid < t.n) {
+        it.v = (int32_t)wid;
+        if (t.heavy_id[it.v] >= 0) return false;
+        it.beg = t.rp[it.v];
+        it.end = t.rp[it.v + 1];
+        it.h = -1;
+        it.first = true;
+        return true;
+    }
+    const int64_t k = wid - t.n;
+    if (k >= t.nseg) return false;
+    it.v = t.seg_v[k];
+    it.beg = t.seg_beg[k];
+    it.end = t.seg_end[k];
+    it.h = t.heavy_id[it.v];
+    it.first = it.beg == t.rp[it.v];
+    return true;
+}
+
+// Lane-distributed load of the NW words of a bitmap row, then broadcast.
+template <int NW>
+__device__ __forceinline__ void load_words(const uint64_t *__restrict__ row, int lane, uint64_t (&w)[NW]) {
+    const uint64_t mine = lane < NW ? row[lane] : 0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) w[q] = rl64(mine, q);
+}
+
+// Path counts are stored as uint32 while they fit (half the gather bytes); a
+// count of 2^32 or more raises the need-wide flag and the batch is re-run with
+// uint64 storage.
+__device__ __forceinline__ void store_count(uint64_t *p, uint64_t x, bool &wide) { *p = x; }
+__device__ __forceinline__ void store_count(uint32_t *p, uint64_t x, bool &wide) {
+    wide |= x > 0xFFFFFFFFull;
+    *p = (uint32_t)x;
+}
+
+// Last-arriver protocol for split rows: every segment wave of heavy row h adds
+// its partial sums into hacc with device-scope atomics, waits until they have
+// completed, then counts itself in arrive[h]; the wave that brings the count to
+// the row's segment total resets the counter and completes the row, reading
+// hacc with device-scope atomic loads.  hacc and arrive are touched only by
+// device-scope atomics, so completion order is all the protocol needs: no
+// cache write-back fence.
+__device__ __forceinline__ void wait_memory() { __asm__ __volatile__("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+__device__ __forceinline__ bool last_arriver(uint32_t *arrive, int32_t total, int lane) {
+    wait_memory();
+    uint32_t old = 0;
+    if (lane == 0) old = atomicAdd(arrive, 1u);
+    old = (uint32_t)__builtin_amdgcn_readfirstlane((int)old);
+    if (old + 1 != (uint32_t)total) return false;
+    if (lane == 0) __hip_atomic_store(arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return true;
+}
+
+// acc[q] += sum over arcs [beg, end) of sigma(v, 64q+lane) for neighbours v
+// whose word q of the level-l frontier meets U[q] at this lane.
+template <int NW, typename S>
+__device__ __forceinline__ void fwd_scan(const Topo &t, int32_t beg, int32_t end, const uint64_t (&U)[NW],
+                                         const uint32_t *__restrict__ any_cur, const uint64_t *__restrict__ fcur,
+                                         const S *__restrict__ sigma, int lane, uint64_t (&acc)[NW], bool &ovf) {
+    constexpr int ARCS = NW >= GDEPTH ? 1 : GDEPTH / NW; // arcs per round, ARCS * NW gathers in flight
+    const S *sig = sigma + lane;
     for (int32_t base = beg; base < end; base += 64) {
         const int32_t e = base + lane;
         int32_t v = 0;
-        uint64_t f = 0;
+        uint64_t f[NW];
+#pragma unroll
+        for (int q = 0; q < NW; ++q) f[q] = 0;
         if (e < end) {
             v = t.col[e];
-            if ((any_cur[v >> 5] >> (v & 31)) & 1) f = fcur[(size_t)v * t.NW + q] & U;
+            if ((any_cur[v >> 5] >> (v & 31)) & 1) {
+#pragma unroll
+                for (int q = 0; q < NW; ++q) f[q] = fcur[(size_t)v * NW + q] & U[q];
+            }
         }
-        uint64_t act = __ballot(f != 0);
+        uint64_t nz = 0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) nz |= f[q];
+        uint64_t act = __ballot(nz != 0);
         while (act) {
-            const int j0 = pop_lowest(act);
-            const int j1 = act ? pop_lowest(act) : -1;
-            const int j2 = act ? pop_lowest(act) : -1;
-            const int j3 = act ? pop_lowest(act) : -1;
-            uint64_t x0 = 0, x1 = 0, x2 = 0, x3 = 0;
-            {
-                const uint64_t fj = rl64(f, j0);
-                if ((fj >> lane) & 1) x0 = sig_q[(size_t)rl32(v, j0) * t.B];
+            uint64_t x[ARCS][NW];
+#pragma unroll
+            for (int a = 0; a < ARCS; ++a) {
+#pragma unroll
+                for (int q = 0; q < NW; ++q) x[a][q] = 0;
+                if (act) {
+                    const int j = pop_lowest(act);
+                    const size_t row = (size_t)rl32(v, j) * t.B;
+#pragma unroll
+                    for (int q = 0; q < NW; ++q) {
+                        const uint64_t fj = rl64(f[q], j);
+                        if (fj != 0 && ((fj >> lane) & 1)) x[a][q] = (uint64_t)sig[row + (size_t)q * 64];
+                    }
+                }
             }
-            if (j1 >= 0) {
-                const uint64_t fj = rl64(f, j1);
-                if ((fj >> lane) & 1) x1 = sig_q[(size_t)rl32(v, j1) * t.B];
+#pragma unroll
+            for (int a = 0; a < ARCS; ++a) {
+#pragma unroll
+                for (int q = 0; q < NW; ++q) {
+                    const uint64_t s = acc[q] + x[a][q];
+                    ovf |= s < acc[q];
+                    acc[q] = s;
+                }
             }
-            if (j2 >= 0) {
-                const uint64_t fj = rl64(f, j2);
-                if ((fj >> lane) & 1) x2 = sig_q[(size_t)rl32(v, j2) * t.B];
-            }
-            if (j3 >= 0) {
-                const uint64_t fj = rl64(f, j3);
-                if ((fj >> lane) & 1) x3 = sig_q[(size_t)rl32(v, j3) * t.B];
-            }
-            uint64_t s = acc + x0;
-            ovf |= s < acc;
-            acc = s;
-            s = acc + x1;
-            ovf |= s < acc;
-            acc = s;
-            s = acc + x2;
-            ovf |= s < acc;
-            acc = s;
-            s = acc + x3;
-            ovf |= s < acc;
-            acc = s;
         }
     }
-    return acc;
 }
 
-// Sum over arcs [beg, end) of row v of c(w, 64q+lane) for neighbours w whose
-// next-level word intersects F at this lane.
-__device__ __forceinline__ double bwd_scan(const Topo &t, int32_t beg, int32_t end, int q, uint64_t F,
-                                           const uint32_t *__restrict__ any_next,
-                                           const uint64_t *__restrict__ fnext,
-                                           const float *__restrict__ cval, int lane) {
-    const float *c_q = cval + (size_t)q * 64 + lane;
-    double acc = 0.0;
+// acc[q] += sum over arcs [beg, end) of c(w, 64q+lane) for neighbours w whose
+// word q of the level-(l+1) frontier meets F[q] at this lane.
+template <int NW>
+__device__ __forceinline__ void bwd_scan(const Topo &t, int32_t beg, int32_t end, const uint64_t (&F)[NW],
+                                         const uint32_t *__restrict__ any_next, const uint64_t *__restrict__ fnext,
+                                         const float *__restrict__ cval, int lane, double (&acc)[NW]) {
+    constexpr int ARCS = NW >= GDEPTH ? 1 : GDEPTH / NW;
+    const float *c = cval + lane;
     for (int32_t base = beg; base < end; base += 64) {
         const int32_t e = base + lane;
         int32_t w = 0;
-        uint64_t g = 0;
+        uint64_t g[NW];
+#pragma unroll
+        for (int q = 0; q < NW; ++q) g[q] = 0;
         if (e < end) {
             w = t.col[e];
-            if ((any_next[w >> 5] >> (w & 31)) & 1) g = fnext[(size_t)w * t.NW + q] & F;
+            if ((any_next[w >> 5] >> (w & 31)) & 1) {
+#pragma unroll
+                for (int q = 0; q < NW; ++q) g[q] = fnext[(size_t)w * NW + q] & F[q];
+            }
         }
-        uint64_t act = __ballot(g != 0);
+        uint64_t nz = 0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) nz |= g[q];
+        uint64_t act = __ballot(nz != 0);
         while (act) {
-            const int j0 = pop_lowest(act);
-            const int j1 = act ? pop_lowest(act) : -1;
-            const int j2 = act ? pop_lowest(act) : -1;
-            const int j3 = act ? pop_lowest(act) : -1;
-            float x0 = 0.f, x1 = 0.f, x2 = 0.f, x3 = 0.f;
-            {
-                const uint64_t gj = rl64(g, j0);
-                if ((gj >> lane) & 1) x0 = c_q[(size_t)rl32(w, j0) * t.B];
+            float x[ARCS][NW];
+#pragma unroll
+            for (int a = 0; a < ARCS; ++a) {
+#pragma unroll
+                for (int q = 0; q < NW; ++q) x[a][q] = 0.f;
+                if (act) {
+                    const int j = pop_lowest(act);
+                    const size_t row = (size_t)rl32(w, j) * t.B;
+#pragma unroll
+                    for (int q = 0; q < NW; ++q) {
+                        const uint64_t gj = rl64(g[q], j);
+                        if (gj != 0 && ((gj >> lane) & 1)) x[a][q] = c[row + (size_t)q * 64];
+                    }
+                }
             }
-            if (j1 >= 0) {
-                const uint64_t gj = rl64(g, j1);
-                if ((gj >> lane) & 1) x1 = c_q[(size_t)rl32(w, j1) * t.B];
+#pragma unroll
+            for (int a = 0; a < ARCS; ++a) {
+#pragma unroll
+                for (int q = 0; q < NW; ++q) acc[q] += (double)x[a][q];
             }
-            if (j2 >= 0) {
-                const uint64_t gj = rl64(g, j2);
-                if ((gj >> lane) & 1) x2 = c_q[(size_t)rl32(w, j2) * t.B];
-            }
-            if (j3 >= 0) {
-                const uint64_t gj = rl64(g, j3);
-                if ((gj >> lane) & 1) x3 = c_q[(size_t)rl32(w, j3) * t.B];
-            }
-            acc += (double)x0;
-            acc += (double)x1;
-            acc += (double)x2;
-            acc += (double)x3;
         }
     }
-    return acc;
 }
 
-// delta(v,b) = sigma(v,b) * acc; c(v,b) = (1 + delta) / sigma; BC(v) += sum of delta
-// over this wave's lanes whose source is not v.
-__device__ __forceinline__ void bwd_finalize(int32_t v, int q, uint64_t F, double acc, int lane, int B,
-                                             const uint64_t *__restrict__ sigma, float *__restrict__ cval,
+// For every word with sources at this level: delta(v,b) = sigma(v,b) * acc,
+// c(v,b) = (1 + delta) / sigma; BC(v) += sum of delta over lanes whose source
+// is not v (one atomic per vertex).
+template <int NW, typename S>
+__device__ __forceinline__ void bwd_finalize(int32_t v, const uint64_t (&F)[NW], const double (&acc)[NW], int lane,
+                                             int B, const S *__restrict__ sigma, float *__restrict__ cval,
                                              const int32_t *__restrict__ src_lane, double *__restrict__ bc,
                                              double *__restrict__ delta_dump, int accumulate) {
     double contrib = 0.0;
-    if ((F >> lane) & 1) {
-        const size_t idx = (size_t)v * B + (size_t)q * 64 + lane;
-        const double sv = (double)sigma[idx];
-        const double dl = sv * acc;
-        cval[idx] = (float)((1.0 + dl) / sv);
-        if (delta_dump) delta_dump[idx] = dl;
-        if (src_lane[q * 64 + lane] != v) contrib = dl;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+        if ((F[q] >> lane) & 1) {
+            const size_t idx = (size_t)v * B + (size_t)q * 64 + lane;
+            const double sv = (double)sigma[idx];
+            const double dl = sv * acc[q];
+            cval[idx] = (float)((1.0 + dl) / sv);
+            if (delta_dump) delta_dump[idx] = dl;
+            if (src_lane[q * 64 + lane] != v) contrib += dl;
+        }
     }
     if (accumulate) {
 #pragma unroll
@@ -189,21 +255,23 @@ __device__ __forceinline__ void bwd_finalize(int32_t v, int q, uint64_t F, doubl
     }
 }
 
+// Clears front levels 0 and 1 (a: 2 * words entries), visited (b) and every
+// level's vertex filter.
 __global__ __launch_bounds__(SB) void k_sp_clear(uint64_t *__restrict__ a, uint64_t *__restrict__ b, size_t words,
-                                                 uint32_t *__restrict__ any_all, size_t any_total,
-                                                 uint32_t *__restrict__ counts, int32_t count_words) {
+                                                 uint32_t *__restrict__ any_all, size_t any_total) {
     const size_t tid = (size_t)blockIdx.x * SB + threadIdx.x, stride = (size_t)gridDim.x * SB;
     for (size_t i = tid; i < words; i += stride) {
         a[i] = 0;
+        a[words + i] = 0;
         b[i] = 0;
     }
     for (size_t i = tid; i < any_total; i += stride) any_all[i] = 0;
-    for (size_t i = tid; i < (size_t)count_words; i += stride) counts[i] = 0;
 }
 
+template <typename S>
 __global__ __launch_bounds__(SB) void k_sp_seed(const int32_t *__restrict__ src, int32_t count, int32_t B, int32_t NW,
-                                                uint64_t *front0, uint64_t *visited, uint64_t *sigma,
-                                                int32_t *src_lane, uint32_t *any0) {
+                                                uint64_t *front0, uint64_t *visited, S *sigma, int32_t *src_lane,
+                                                uint32_t *any0) {
     const int32_t b = blockIdx.x * SB + threadIdx.x;
     if (b >= B) return;
     const int32_t s = b < count ? src[b] : -1;
@@ -217,170 +285,233 @@ __global__ __launch_bounds__(SB) void k_sp_seed(const int32_t *__restrict__ src,
     }
 }
 
-// Whether level l (l >= 1) has any vertex: any of the CSLOTS counters of the
-// kernel that produced it is non-zero.  Read by one wave, shared through LDS.
-__device__ __forceinline__ bool level_nonempty(const uint32_t *__restrict__ cnt_in, uint32_t *s_flag) {
-    if (cnt_in == nullptr) return true;
-    if (threadIdx.x < 64) {
-        const uint32_t x = threadIdx.x < CSLOTS ? cnt_in[threadIdx.x * CSTRIDE] : 0u;
-        const uint64_t nz = __ballot(x != 0);
-        if (threadIdx.x == 0) *s_flag = nz != 0;
+// Forward level 0 -> 1, pushed from the sources: every neighbour w of s_b
+// is at distance 1 with exactly one shortest path (lambda = 1).  One block per
+// batch lane; the block's threads take the source's arcs.
+template <typename S>
+__global__ __launch_bounds__(SB) void k_fwd_push0(Topo t, int32_t NW, const int32_t *__restrict__ src_lane,
+                                                  uint64_t *__restrict__ fnext, uint64_t *__restrict__ visited,
+                                                  S *__restrict__ sigma, uint32_t *__restrict__ any_next) {
+    const int32_t b = blockIdx.x;
+    const int32_t s = src_lane[b];
+    if (s < 0) return;
+    const unsigned long long bit = 1ull << (b & 63);
+    const int q = b >> 6;
+    for (int32_t e = t.rp[s] + threadIdx.x; e < t.rp[s + 1]; e += SB) {
+        const int32_t w = t.col[e];
+        atomicOr((unsigned long long *)&fnext[(size_t)w * NW + q], bit);
+        atomicOr((unsigned long long *)&visited[(size_t)w * NW + q], bit);
+        atomicOr(&any_next[w >> 5], 1u << (w & 31));
+        sigma[(size_t)w * t.B + b] = 1;
     }
-    __syncthreads();
-    return *s_flag != 0;
 }
 
-// Last-arriver protocol for split rows: every segment wave of (heavy row h,
-// word q) adds its partial sums into hacc with device-scope atomics, waits
-// until they have completed, then counts itself in arrive[h][q]; the wave
-// that brings the count to the row's segment total resets the counter and
-// completes the row, reading hacc with device-scope atomic loads.  hacc and
-// arrive are touched only by device-scope atomics, so completion order is all
-// the protocol needs: no cache write-back fence.
-__device__ __forceinline__ void wait_memory() { __asm__ __volatile__("s_waitcnt vmcnt(0)" ::: "memory"); }
-
-__device__ __forceinline__ bool last_arriver(uint32_t *arrive, int32_t total, int lane) {
-    wait_memory();
-    uint32_t old = 0;
-    if (lane == 0) old = atomicAdd(arrive, 1u);
-    old = (uint32_t)__builtin_amdgcn_readfirstlane((int)old);
-    if (old + 1 != (uint32_t)total) return false;
-    if (lane == 0) __hip_atomic_store(arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return true;
+// Writes the level-(l+1) words of vertex w (lanes 0..NW-1) and marks any_next.
+template <int NW>
+__device__ __forceinline__ void fwd_commit(int32_t w, const uint64_t (&vis)[NW], const uint64_t (&out)[NW], int lane,
+                                           uint64_t *__restrict__ fnext, uint64_t *__restrict__ visited,
+                                           uint32_t *__restrict__ any_next) {
+    uint64_t mine_out = 0, mine_vis = 0, all = 0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+        if (lane == q) {
+            mine_out = out[q];
+            mine_vis = vis[q] | out[q];
+        }
+        all |= out[q];
+    }
+    if (lane < NW) {
+        fnext[(size_t)w * NW + lane] = mine_out;
+        if (mine_out) visited[(size_t)w * NW + lane] = mine_vis;
+    }
+    if (lane == 0 && all) atomicOr(&any_next[w >> 5], 1u << (w & 31));
 }
 
-// Forward level l -> l+1.  Light rows complete in their wave; split rows
-// complete in the last segment wave to arrive.  Marks any_next and the level
-// counters; exits at once when level l is empty (speculative launch).
-__global__ __launch_bounds__(SB) void k_fwd_pull(Topo t, const uint32_t *__restrict__ cnt_in,
-                                                 const uint32_t *__restrict__ any_cur,
+// Forward level l -> l+1 for l >= 1.  Light rows complete in their wave; split
+// rows complete in the last segment wave to arrive.  After the last real level
+// every vertex is visited for every source it can reach, so speculative
+// launches past the depth exit after one load per wave.
+template <int NW, typename S>
+__global__ __launch_bounds__(SB) void k_fwd_pull(Topo t, const uint32_t *__restrict__ any_cur,
                                                  const uint64_t *__restrict__ fcur, uint64_t *__restrict__ fnext,
-                                                 uint64_t *__restrict__ visited, uint64_t *__restrict__ sigma,
+                                                 uint64_t *__restrict__ visited, S *__restrict__ sigma,
                                                  unsigned long long *__restrict__ hacc, uint32_t *__restrict__ arrive,
-                                                 uint32_t *__restrict__ any_next, uint32_t *__restrict__ cnt_out,
-                                                 uint32_t *__restrict__ status) {
-    __shared__ uint32_t s_flag;
-    __shared__ uint32_t s_any[2];
-    __shared__ uint32_t s_cnt;
-    if (!level_nonempty(cnt_in, &s_flag)) return;
-    if (threadIdx.x == 0) {
-        s_any[0] = s_any[1] = 0;
-        s_cnt = 0;
-    }
-    __syncthreads();
+                                                 uint32_t *__restrict__ any_next, uint32_t *__restrict__ status) {
     const int lane = threadIdx.x & 63;
-    const int64_t wid0 = (int64_t)blockIdx.x * WPB;
-    const int64_t wid = wid0 + (threadIdx.x >> 6);
-    const int64_t nlight = (int64_t)t.n * t.NW;
-    const int32_t wbase = (int32_t)(min(wid0, nlight - 1) / t.NW) >> 5; // any word of the block's first vertex
-    bool ovf = false;
-    if (wid < nlight) {
-        const int32_t w = (int32_t)(wid / t.NW), q = (int32_t)(wid - (int64_t)w * t.NW);
-        if (t.heavy_id[w] < 0) {
-            const uint64_t vis = visited[wid];
-            const uint64_t U = ~vis;
-            uint64_t out = 0;
-            if (U != 0) {
-                const uint64_t acc = fwd_scan(t, t.rp[w], t.rp[w + 1], q, U, any_cur, fcur, sigma, lane, ovf);
-                out = __ballot(acc != 0);
-                if (acc != 0) sigma[(size_t)w * t.B + (size_t)q * 64 + lane] = acc;
-            }
-            if (lane == 0) {
-                fnext[wid] = out;
-                if (out) {
-                    visited[wid] = vis | out;
-                    atomicOr(&s_any[(w >> 5) - wbase], 1u << (w & 31));
-                    atomicAdd(&s_cnt, 1u);
-                }
+    const int64_t wid = (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6);
+    Item it;
+    if (!item_of(t, wid, it)) return;
+    const int32_t w = it.v;
+    uint64_t vis[NW], U[NW];
+    load_words<NW>(visited + (size_t)w * NW, lane, vis);
+    uint64_t anyU = 0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+        U[q] = ~vis[q];
+        anyU |= U[q];
+    }
+    if (anyU == 0) {
+        if (it.first && lane < NW) fnext[(size_t)w * NW + lane] = 0;
+        return;
+    }
+    uint64_t acc[NW];
+#pragma unroll
+    for (int q = 0; q < NW; ++q) acc[q] = 0;
+    bool ovf = false, wide = false;
+    fwd_scan<NW, S>(t, it.beg, it.end, U, any_cur, fcur, sigma, lane, acc, ovf);
+    uint64_t out[NW];
+    if (it.h < 0) {
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+            out[q] = __ballot(acc[q] != 0);
+            if (acc[q] != 0) store_count(&sigma[(size_t)w * t.B + (size_t)q * 64 + lane], acc[q], wide);
+        }
+        fwd_commit<NW>(w, vis, out, lane, fnext, visited, any_next);
+    } else {
+        unsigned long long *hrow = hacc + (size_t)it.h * t.B + lane;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+            if (acc[q] != 0) {
+                const unsigned long long old = atomicAdd(&hrow[q * 64], (unsigned long long)acc[q]);
+                ovf |= old + acc[q] < old;
             }
         }
-    } else if (wid < nlight + (int64_t)t.nseg * t.NW) {
-        const int64_t k = (wid - nlight) / t.NW;
-        const int32_t q = (int32_t)(wid - nlight - k * t.NW);
-        const int32_t w = t.seg_v[k];
-        const int32_t h = t.heavy_id[w];
-        const size_t vw = (size_t)w * t.NW + q;
-        const uint64_t vis = visited[vw];
-        const uint64_t U = ~vis;
-        if (U == 0) {
-            if (lane == 0 && t.seg_beg[k] == t.rp[w]) fnext[vw] = 0;
-        } else {
-            const size_t hi = (size_t)h * t.B + (size_t)q * 64 + lane;
-            const uint64_t acc = fwd_scan(t, t.seg_beg[k], t.seg_end[k], q, U, any_cur, fcur, sigma, lane, ovf);
-            if (acc != 0) {
-                const unsigned long long old = atomicAdd(&hacc[hi], (unsigned long long)acc);
-                ovf |= old + acc < old;
-            }
-            if (last_arriver(&arrive[(size_t)h * t.NW + q], t.heavy_nseg[h], lane)) {
-                const uint64_t x = __hip_atomic_load(&hacc[hi], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (last_arriver(&arrive[it.h], t.heavy_nseg[it.h], lane)) {
+#pragma unroll
+            for (int q = 0; q < NW; ++q) {
+                const uint64_t x = __hip_atomic_load(&hrow[q * 64], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if (x != 0) {
-                    __hip_atomic_store(&hacc[hi], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    sigma[(size_t)w * t.B + (size_t)q * 64 + lane] = x;
+                    __hip_atomic_store(&hrow[q * 64], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    store_count(&sigma[(size_t)w * t.B + (size_t)q * 64 + lane], x, wide);
                 }
-                const uint64_t out = __ballot(x != 0);
-                if (lane == 0) {
-                    fnext[vw] = out;
-                    if (out) {
-                        visited[vw] = vis | out;
-                        atomicOr(&any_next[w >> 5], 1u << (w & 31));
-                        atomicAdd(&s_cnt, 1u);
-                    }
-                }
+                out[q] = __ballot(x != 0);
             }
+            fwd_commit<NW>(w, vis, out, lane, fnext, visited, any_next);
         }
     }
-    if (__any(ovf) && lane == 0) atomicOr(status, (uint32_t)BC_DEV_SIGMA_OVERFLOW);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        if (s_any[0]) atomicOr(&any_next[wbase], s_any[0]);
-        if (s_any[1]) atomicOr(&any_next[wbase + 1], s_any[1]);
-        if (s_cnt) atomicAdd(&cnt_out[(blockIdx.x % CSLOTS) * CSTRIDE], s_cnt);
-    }
+    if (__any(ovf) && lane == 0) atomicOr(&status[0], (uint32_t)BC_DEV_SIGMA_OVERFLOW);
+    if (__any(wide) && lane == 0) atomicOr(&status[1], 1u);
 }
 
 // Backward level l.  Light rows complete in their wave; split rows in the last
 // segment wave to arrive.  fnext = nullptr at the deepest level.
+template <int NW, typename S>
 __global__ __launch_bounds__(SB) void k_bwd_pull(Topo t, const uint64_t *__restrict__ fcur,
                                                  const uint32_t *__restrict__ any_next,
-                                                 const uint64_t *__restrict__ fnext,
-                                                 const uint64_t *__restrict__ sigma, float *__restrict__ cval,
-                                                 const int32_t *__restrict__ src_lane, double *__restrict__ bc,
-                                                 double *__restrict__ hacc, uint32_t *__restrict__ arrive,
-                                                 double *__restrict__ delta_dump, int accumulate) {
+                                                 const uint64_t *__restrict__ fnext, const S *__restrict__ sigma,
+                                                 float *__restrict__ cval, const int32_t *__restrict__ src_lane,
+                                                 double *__restrict__ bc, double *__restrict__ hacc,
+                                                 uint32_t *__restrict__ arrive, double *__restrict__ delta_dump,
+                                                 int accumulate) {
     const int lane = threadIdx.x & 63;
     const int64_t wid = (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6);
-    const int64_t nlight = (int64_t)t.n * t.NW;
-    if (wid < nlight) {
-        const uint64_t F = fcur[wid];
-        if (F == 0) return;
-        const int32_t v = (int32_t)(wid / t.NW), q = (int32_t)(wid - (int64_t)v * t.NW);
-        if (t.heavy_id[v] >= 0) return;
-        const double acc = fnext ? bwd_scan(t, t.rp[v], t.rp[v + 1], q, F, any_next, fnext, cval, lane) : 0.0;
-        bwd_finalize(v, q, F, acc, lane, t.B, sigma, cval, src_lane, bc, delta_dump, accumulate);
-    } else if (wid < nlight + (int64_t)t.nseg * t.NW) {
-        const int64_t k = (wid - nlight) / t.NW;
-        const int32_t q = (int32_t)(wid - nlight - k * t.NW);
-        const int32_t v = t.seg_v[k];
-        const uint64_t F = fcur[(size_t)v * t.NW + q];
-        if (F == 0) return;
-        const int32_t h = t.heavy_id[v];
-        const size_t hi = (size_t)h * t.B + (size_t)q * 64 + lane;
-        const double acc = fnext ? bwd_scan(t, t.seg_beg[k], t.seg_end[k], q, F, any_next, fnext, cval, lane) : 0.0;
-        if (acc != 0.0) unsafeAtomicAdd(&hacc[hi], acc);
-        if (last_arriver(&arrive[(size_t)h * t.NW + q], t.heavy_nseg[h], lane)) {
-            double x = 0.0;
-            if ((F >> lane) & 1) {
-                x = __hip_atomic_load(&hacc[hi], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (x != 0.0) __hip_atomic_store(&hacc[hi], 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    Item it;
+    if (!item_of(t, wid, it)) return;
+    const int32_t v = it.v;
+    uint64_t F[NW];
+    load_words<NW>(fcur + (size_t)v * NW, lane, F);
+    uint64_t anyF = 0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) anyF |= F[q];
+    if (anyF == 0) return;
+    double acc[NW];
+#pragma unroll
+    for (int q = 0; q < NW; ++q) acc[q] = 0.0;
+    if (fnext) bwd_scan<NW>(t, it.beg, it.end, F, any_next, fnext, cval, lane, acc);
+    if (it.h < 0) {
+        bwd_finalize<NW, S>(v, F, acc, lane, t.B, sigma, cval, src_lane, bc, delta_dump, accumulate);
+        return;
+    }
+    double *hrow = hacc + (size_t)it.h * t.B + lane;
+#pragma unroll
+    for (int q = 0; q < NW; ++q)
+        if (acc[q] != 0.0) unsafeAtomicAdd(&hrow[q * 64], acc[q]);
+    if (last_arriver(&arrive[it.h], t.heavy_nseg[it.h], lane)) {
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+            acc[q] = 0.0;
+            if ((F[q] >> lane) & 1) {
+                acc[q] = __hip_atomic_load(&hrow[q * 64], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (acc[q] != 0.0) __hip_atomic_store(&hrow[q * 64], 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            bwd_finalize(v, q, F, x, lane, t.B, sigma, cval, src_lane, bc, delta_dump, accumulate);
         }
+        bwd_finalize<NW, S>(v, F, acc, lane, t.B, sigma, cval, src_lane, bc, delta_dump, accumulate);
+    }
+}
+
+// Backward level l, one wave per (row or row segment, word q): at the fat
+// levels this keeps NW times more waves in flight than a wave per row, and a
+// word with no sources at this level costs its wave a single load.
+template <int NW, typename S>
+__global__ __launch_bounds__(SB) void k_bwd_pull_w(Topo t, const uint64_t *__restrict__ fcur,
+                                                   const uint32_t *__restrict__ any_next,
+                                                   const uint64_t *__restrict__ fnext, const S *__restrict__ sigma,
+                                                   float *__restrict__ cval, const int32_t *__restrict__ src_lane,
+                                                   double *__restrict__ bc, double *__restrict__ hacc,
+                                                   uint32_t *__restrict__ arrive, double *__restrict__ delta_dump,
+                                                   int accumulate) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6);
+    const int q = (int)(wid % NW);
+    Item it;
+    if (!item_of(t, wid / NW, it)) return;
+    const int32_t v = it.v;
+    const uint64_t F = fcur[(size_t)v * NW + q];
+    if (F == 0) return;
+    const uint64_t F1[1] = {F};
+    double acc[1] = {0.0};
+    if (fnext) {
+        // the single-word scan over word q: shift the row base by q words
+        const float *c = cval + (size_t)q * 64 + lane;
+        for (int32_t base = it.beg; base < it.end; base += 64) {
+            const int32_t e = base + lane;
+            int32_t w = 0;
+            uint64_t g = 0;
+            if (e < it.end) {
+                w = t.col[e];
+                if ((any_next[w >> 5] >> (w & 31)) & 1) g = fnext[(size_t)w * NW + q] & F;
+            }
+            uint64_t act = __ballot(g != 0);
+            while (act) {
+                float x[GDEPTH];
+#pragma unroll
+                for (int u = 0; u < GDEPTH; ++u) {
+                    x[u] = 0.f;
+                    if (act) {
+                        const int j = pop_lowest(act);
+                        if ((rl64(g, j) >> lane) & 1) x[u] = c[(size_t)rl32(w, j) * t.B];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < GDEPTH; ++u) acc[0] += (double)x[u];
+            }
+        }
+    }
+    const S *sig_q = sigma + (size_t)q * 64;
+    float *cval_q = cval + (size_t)q * 64;
+    const int32_t *src_q = src_lane + q * 64;
+    if (it.h < 0) {
+        bwd_finalize<1, S>(v, F1, acc, lane, t.B, sig_q, cval_q, src_q, bc,
+                           delta_dump ? delta_dump + (size_t)q * 64 : nullptr, accumulate);
+        return;
+    }
+    double *hp = hacc + (size_t)it.h * t.B + (size_t)q * 64 + lane;
+    if (acc[0] != 0.0) unsafeAtomicAdd(hp, acc[0]);
+    if (last_arriver(&arrive[(size_t)it.h * NW + q], t.heavy_nseg[it.h], lane)) {
+        acc[0] = 0.0;
+        if ((F >> lane) & 1) {
+            acc[0] = __hip_atomic_load(hp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (acc[0] != 0.0) __hip_atomic_store(hp, 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        bwd_finalize<1, S>(v, F1, acc, lane, t.B, sig_q, cval_q, src_q, bc,
+                           delta_dump ? delta_dump + (size_t)q * 64 : nullptr, accumulate);
     }
 }
 
 // Per-source readout for bc_read_sssp: out[b][v] in source-major layout.
+template <typename S>
 __global__ __launch_bounds__(SB) void k_sp_dump(int32_t n, int32_t NW, int32_t B, int32_t count, int32_t nlev,
-                                                const uint64_t *__restrict__ front, const uint64_t *__restrict__ sigma,
+                                                const uint64_t *__restrict__ front, const S *__restrict__ sigma,
                                                 const double *__restrict__ dstate, int32_t *__restrict__ dist_out,
                                                 uint64_t *__restrict__ sigma_out, double *__restrict__ delta_out) {
     const int64_t i = (int64_t)blockIdx.x * SB + threadIdx.x;
@@ -392,7 +523,7 @@ __global__ __launch_bounds__(SB) void k_sp_dump(int32_t n, int32_t NW, int32_t B
         if ((front[((size_t)l * n + v) * NW + q] >> bit) & 1) d = l;
     const size_t idx = (size_t)v * B + b;
     dist_out[i] = d;
-    sigma_out[i] = d >= 0 ? sigma[idx] : 0;
+    sigma_out[i] = d >= 0 ? (uint64_t)sigma[idx] : 0;
     delta_out[i] = d >= 0 ? dstate[idx] : 0.0;
 }
 
@@ -400,7 +531,6 @@ Topo topo(bc_ctx *ctx) {
     const SparseState &s = ctx->sp;
     Topo t;
     t.n = ctx->n;
-    t.NW = s.words;
     t.B = s.batch;
     t.rp = ctx->row_ptr;
     t.col = ctx->col;
@@ -409,9 +539,7 @@ Topo topo(bc_ctx *ctx) {
     t.seg_beg = s.seg_beg;
     t.seg_end = s.seg_end;
     t.nseg = s.nseg;
-    t.heavy_v = s.heavy_v;
     t.heavy_nseg = s.heavy_nseg;
-    t.nheavy = s.nheavy;
     return t;
 }
 
@@ -422,8 +550,8 @@ bc_status ensure_levels(bc_ctx *ctx, int32_t need) {
     if (need <= s.level_cap) return BC_OK;
     int32_t cap = std::max(s.level_cap * 2, need);
     const size_t aw = (size_t)any_words(ctx);
-    const size_t cw = (size_t)CSLOTS * CSTRIDE;
-    const size_t per_level = (size_t)ctx->n * s.words * sizeof(uint64_t) + aw * sizeof(uint32_t);
+    const size_t lvl_words = (size_t)ctx->n * s.words;
+    const size_t per_level = lvl_words * sizeof(uint64_t) + aw * sizeof(uint32_t);
     const size_t budget = size_t(32) << 30;
     if ((size_t)cap * per_level > budget) {
         cap = need;
@@ -431,15 +559,12 @@ bc_status ensure_levels(bc_ctx *ctx, int32_t need) {
             return bc_fail(ctx, BC_ERR_UNSUPPORTED,
                            "sparse form: the graph is too deep for per-level frontier bitmaps; use the plain form");
     }
-    const size_t lvl_words = (size_t)ctx->n * s.words;
     uint64_t *nf = (uint64_t *)bc_dalloc(ctx, (size_t)cap * lvl_words * sizeof(uint64_t));
     uint32_t *na = (uint32_t *)bc_dalloc(ctx, (size_t)cap * aw * sizeof(uint32_t));
-    uint32_t *nc = (uint32_t *)bc_dalloc(ctx, (size_t)cap * cw * sizeof(uint32_t));
     uint32_t *nh = nullptr;
-    if (!nf || !na || !nc || hipHostMalloc((void **)&nh, (size_t)cap * cw * sizeof(uint32_t)) != hipSuccess) {
+    if (!nf || !na || hipHostMalloc((void **)&nh, (size_t)cap * aw * sizeof(uint32_t)) != hipSuccess) {
         bc_dfree(ctx, nf);
         bc_dfree(ctx, na);
-        bc_dfree(ctx, nc);
         return bc_fail(ctx, BC_ERR_NOMEM, "sparse form: frontier allocation failed");
     }
     const int32_t old = s.level_cap;
@@ -447,38 +572,39 @@ bc_status ensure_levels(bc_ctx *ctx, int32_t need) {
         BC_HIP(ctx, hipMemcpyAsync(nf, s.front, (size_t)old * lvl_words * sizeof(uint64_t), hipMemcpyDeviceToDevice,
                                    ctx->stream));
         BC_HIP(ctx, hipMemcpyAsync(na, s.any, (size_t)old * aw * sizeof(uint32_t), hipMemcpyDeviceToDevice, ctx->stream));
-        BC_HIP(ctx, hipMemcpyAsync(nc, s.counts, (size_t)old * cw * sizeof(uint32_t), hipMemcpyDeviceToDevice, ctx->stream));
     }
     BC_HIP(ctx, hipMemsetAsync(na + (size_t)old * aw, 0, (size_t)(cap - old) * aw * sizeof(uint32_t), ctx->stream));
-    BC_HIP(ctx, hipMemsetAsync(nc + (size_t)old * cw, 0, (size_t)(cap - old) * cw * sizeof(uint32_t), ctx->stream));
     BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
     if (s.front) {
         bc_dfree(ctx, s.front);
         bc_dfree(ctx, s.any);
-        bc_dfree(ctx, s.counts);
-        hipHostFree(s.counts_host);
+        hipHostFree(s.any_host);
     }
     s.front = nf;
     s.any = na;
-    s.counts = nc;
-    s.counts_host = nh;
+    s.any_host = nh;
     s.level_cap = cap;
     return BC_OK;
 }
 
-// One batch of up to B sources; *nlev_out receives the number of non-empty
-// levels.  Forward levels are launched ahead of the host knowing whether they
-// are needed (as many as the previous batch used); a kernel whose input level
-// is empty exits at once, and the host reads all level counters with one
-// synchronisation per batch.
-bc_status run_batch(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool accumulate, int32_t *nlev_out) {
+// One batch of up to B sources with counts stored as S; *nlev_out receives
+// the number of non-empty levels.  Forward levels are launched ahead of the
+// host knowing whether they are needed (as many as the previous batch used);
+// the host then reads the per-level vertex filters back with one
+// synchronisation and finds the first empty level.  With S = uint32_t,
+// *need_wide reports a count of 2^32 or more, before anything was added to BC.
+template <int NW, typename S>
+bc_status run_batch_t(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool accumulate, int32_t *nlev_out,
+                      bool *need_wide) {
     SparseState &s = ctx->sp;
-    const int32_t n = ctx->n, NW = s.words, B = s.batch;
+    const int32_t n = ctx->n, B = s.batch;
     const size_t words = (size_t)n * NW;
     const int32_t aw = any_words(ctx);
-    const size_t cw = (size_t)CSLOTS * CSTRIDE;
-    const int pull_blocks = (int)(((int64_t)(n + s.nseg) * NW + WPB - 1) / WPB);
+    const int pull_blocks = (int)(((int64_t)n + s.nseg + WPB - 1) / WPB);
+    const int word_blocks = (int)((((int64_t)n + s.nseg) * NW + WPB - 1) / WPB);
     const int32_t guess = std::max(s.depth_guess, 2);
+    S *sigma = reinterpret_cast<S *>(s.sigma);
+    *need_wide = false;
     bc_status st = ensure_levels(ctx, guess + 1);
     if (st != BC_OK) return st;
     const Topo t = topo(ctx);
@@ -486,34 +612,48 @@ bc_status run_batch(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool accum
         LaunchTimer tm(ctx, "batch_init");
         const int blocks = (int)std::min<size_t>((words + SB - 1) / SB, 8192);
         hipLaunchKernelGGL(k_sp_clear, dim3(std::max(blocks, 1)), dim3(SB), 0, ctx->stream, s.front, s.visited, words,
-                           s.any, (size_t)s.level_cap * aw, s.counts, (int32_t)((size_t)s.level_cap * cw));
-        hipLaunchKernelGGL(k_sp_seed, dim3((B + SB - 1) / SB), dim3(SB), 0, ctx->stream, d_src, count, B, NW, s.front,
-                           s.visited, s.sigma, s.src, s.any);
+                           s.any, (size_t)s.level_cap * aw);
+        hipLaunchKernelGGL(k_sp_seed<S>, dim3((B + SB - 1) / SB), dim3(SB), 0, ctx->stream, d_src, count, B, NW,
+                           s.front, s.visited, sigma, s.src, s.any);
         tm.done();
         BC_HIP(ctx, hipGetLastError());
     }
     int32_t launched = 0, nlev = -1;
     while (nlev < 0) {
-        const int32_t target = launched == 0 ? guess : launched + 4;
+        const int32_t target = launched == 0 ? guess : launched + 2;
         st = ensure_levels(ctx, target + 1);
         if (st != BC_OK) return st;
         for (int32_t l = launched; l < target; ++l) {
+            if (l == 0) {
+                LaunchTimer tm(ctx, "fwd_push0");
+                hipLaunchKernelGGL(k_fwd_push0<S>, dim3(B), dim3(SB), 0, ctx->stream, t, NW, (const int32_t *)s.src,
+                                   s.front + words, s.visited, sigma, s.any + aw);
+                tm.done();
+                continue;
+            }
             LaunchTimer tm(ctx, "fwd_pull");
-            hipLaunchKernelGGL(k_fwd_pull, dim3(pull_blocks), dim3(SB), 0, ctx->stream, t,
-                               l == 0 ? (const uint32_t *)nullptr : s.counts + (size_t)l * cw, s.any + (size_t)l * aw,
-                               s.front + (size_t)l * words, s.front + (size_t)(l + 1) * words, s.visited, s.sigma,
-                               (unsigned long long *)s.hacc, s.arrive, s.any + (size_t)(l + 1) * aw,
-                               s.counts + (size_t)(l + 1) * cw, ctx->status);
+            hipLaunchKernelGGL((k_fwd_pull<NW, S>), dim3(pull_blocks), dim3(SB), 0, ctx->stream, t,
+                               s.any + (size_t)l * aw, s.front + (size_t)l * words, s.front + (size_t)(l + 1) * words,
+                               s.visited, sigma, (unsigned long long *)s.hacc, s.arrive, s.any + (size_t)(l + 1) * aw,
+                               ctx->status);
             tm.done();
         }
         BC_HIP(ctx, hipGetLastError());
-        BC_HIP(ctx, hipMemcpyAsync(s.counts_host + cw, s.counts + cw, (size_t)target * cw * sizeof(uint32_t),
+        BC_HIP(ctx, hipMemcpyAsync(s.any_host + aw, s.any + aw, (size_t)target * aw * sizeof(uint32_t),
                                    hipMemcpyDeviceToHost, ctx->stream));
+        BC_HIP(ctx, hipMemcpyAsync(ctx->status_host + 1, ctx->status + 1, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                                   ctx->stream));
         BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        if (ctx->status_host[1] != 0) {
+            BC_HIP(ctx, hipMemsetAsync(ctx->status + 1, 0, sizeof(uint32_t), ctx->stream));
+            *need_wide = true;
+            return BC_OK;
+        }
         for (int32_t l = 1; l <= target && nlev < 0; ++l) {
-            uint64_t total = 0;
-            for (int i = 0; i < CSLOTS; ++i) total += s.counts_host[(size_t)l * cw + (size_t)i * CSTRIDE];
-            if (total == 0) nlev = l;
+            const uint32_t *a = s.any_host + (size_t)l * aw;
+            bool empty = true;
+            for (int32_t i = 0; i < aw && empty; ++i) empty = a[i] == 0;
+            if (empty) nlev = l;
         }
         launched = target;
     }
@@ -526,8 +666,13 @@ bc_status run_batch(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool accum
         const uint64_t *fnext = deeper ? s.front + (size_t)(lv + 1) * words : nullptr;
         const uint32_t *anext = deeper ? s.any + (size_t)(lv + 1) * aw : nullptr;
         LaunchTimer tm(ctx, "bwd_pull");
-        hipLaunchKernelGGL(k_bwd_pull, dim3(pull_blocks), dim3(SB), 0, ctx->stream, t, fcur, anext, fnext, s.sigma,
-                           s.cval, s.src, ctx->bc, s.hacc, s.arrive, ddump, accumulate ? 1 : 0);
+        if (s.bwd_per_word)
+            hipLaunchKernelGGL((k_bwd_pull_w<NW, S>), dim3(word_blocks), dim3(SB), 0, ctx->stream, t, fcur, anext,
+                               fnext, (const S *)sigma, s.cval, s.src, ctx->bc, s.hacc, s.arrive_w, ddump,
+                               accumulate ? 1 : 0);
+        else
+            hipLaunchKernelGGL((k_bwd_pull<NW, S>), dim3(pull_blocks), dim3(SB), 0, ctx->stream, t, fcur, anext, fnext,
+                               (const S *)sigma, s.cval, s.src, ctx->bc, s.hacc, s.arrive, ddump, accumulate ? 1 : 0);
         tm.done();
     }
     BC_HIP(ctx, hipGetLastError());
@@ -536,23 +681,50 @@ bc_status run_batch(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool accum
     return BC_OK;
 }
 
+template <int NW>
+bc_status run_batch_nw(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool accumulate, int32_t *nlev_out) {
+    SparseState &s = ctx->sp;
+    if (!s.wide) {
+        bool need_wide = false;
+        bc_status st = run_batch_t<NW, uint32_t>(ctx, d_src, count, accumulate, nlev_out, &need_wide);
+        if (st != BC_OK || !need_wide) return st;
+        s.wide = true;
+    }
+    bool unused = false;
+    return run_batch_t<NW, uint64_t>(ctx, d_src, count, accumulate, nlev_out, &unused);
+}
+
+// Counts start as uint32; the first batch that needs more switches the context
+// to uint64 storage for good and is re-run.
+bc_status run_batch(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool accumulate, int32_t *nlev_out) {
+    switch (ctx->sp.words) {
+    case 1: return run_batch_nw<1>(ctx, d_src, count, accumulate, nlev_out);
+    case 2: return run_batch_nw<2>(ctx, d_src, count, accumulate, nlev_out);
+    case 4: return run_batch_nw<4>(ctx, d_src, count, accumulate, nlev_out);
+    case 8: return run_batch_nw<8>(ctx, d_src, count, accumulate, nlev_out);
+    }
+    return bc_fail(ctx, BC_ERR_INVALID_ARG, "sparse form: batch must be 64, 128, 256 or 512");
+}
+
 } // namespace
 
 bc_status sparse_prepare(bc_ctx *ctx, int32_t batch, int32_t split_degree) {
     SparseState &s = ctx->sp;
+    if (batch != 64 && batch != 128 && batch != 256 && batch != 512)
+        return bc_fail(ctx, BC_ERR_INVALID_ARG, "sparse form: batch must be 64, 128, 256 or 512");
     s.batch = batch;
     s.words = batch / 64;
-    s.split = split_degree > 0 ? split_degree : 256;
+    s.split = split_degree > 0 ? split_degree : 128;
     const int32_t n = ctx->n;
     const size_t nn = (size_t)std::max(n, 1);
     // Heavy rows and their segments, from the host copy of row_ptr.
     const std::vector<int32_t> &rp = ctx->h_row_ptr;
-    std::vector<int32_t> heavy_id((size_t)n, -1), heavy_v, heavy_nseg, seg_v, seg_beg, seg_end;
+    std::vector<int32_t> heavy_id((size_t)n, -1), heavy_nseg, seg_v, seg_beg, seg_end;
+    int32_t nheavy = 0;
     for (int32_t v = 0; v < n; ++v) {
         const int32_t deg = rp[v + 1] - rp[v];
         if (deg <= s.split) continue;
-        heavy_id[v] = (int32_t)heavy_v.size();
-        heavy_v.push_back(v);
+        heavy_id[v] = nheavy++;
         heavy_nseg.push_back((deg + s.split - 1) / s.split);
         for (int32_t b = rp[v]; b < rp[v + 1]; b += s.split) {
             seg_v.push_back(v);
@@ -560,33 +732,36 @@ bc_status sparse_prepare(bc_ctx *ctx, int32_t batch, int32_t split_degree) {
             seg_end.push_back(std::min(b + s.split, rp[v + 1]));
         }
     }
-    s.nheavy = (int32_t)heavy_v.size();
+    s.nheavy = nheavy;
     s.nseg = (int32_t)seg_v.size();
+    const size_t nh = std::max<size_t>((size_t)nheavy, 1), ns = std::max<size_t>(seg_v.size(), 1);
     s.heavy_id = (int32_t *)bc_dalloc(ctx, nn * sizeof(int32_t));
-    s.heavy_v = (int32_t *)bc_dalloc(ctx, std::max<size_t>(heavy_v.size(), 1) * sizeof(int32_t));
-    s.heavy_nseg = (int32_t *)bc_dalloc(ctx, std::max<size_t>(heavy_v.size(), 1) * sizeof(int32_t));
-    s.arrive = (uint32_t *)bc_dalloc(ctx, std::max<size_t>(heavy_v.size(), 1) * s.words * sizeof(uint32_t));
-    s.seg_v = (int32_t *)bc_dalloc(ctx, std::max<size_t>(seg_v.size(), 1) * sizeof(int32_t));
-    s.seg_beg = (int32_t *)bc_dalloc(ctx, std::max<size_t>(seg_v.size(), 1) * sizeof(int32_t));
-    s.seg_end = (int32_t *)bc_dalloc(ctx, std::max<size_t>(seg_v.size(), 1) * sizeof(int32_t));
-    s.hacc = (double *)bc_dalloc(ctx, std::max<size_t>(heavy_v.size(), 1) * batch * sizeof(double));
+    s.heavy_nseg = (int32_t *)bc_dalloc(ctx, nh * sizeof(int32_t));
+    s.arrive = (uint32_t *)bc_dalloc(ctx, nh * sizeof(uint32_t));
+    s.arrive_w = (uint32_t *)bc_dalloc(ctx, nh * s.words * sizeof(uint32_t));
+    s.seg_v = (int32_t *)bc_dalloc(ctx, ns * sizeof(int32_t));
+    s.seg_beg = (int32_t *)bc_dalloc(ctx, ns * sizeof(int32_t));
+    s.seg_end = (int32_t *)bc_dalloc(ctx, ns * sizeof(int32_t));
+    s.hacc = (double *)bc_dalloc(ctx, nh * batch * sizeof(double));
     s.visited = (uint64_t *)bc_dalloc(ctx, nn * s.words * sizeof(uint64_t));
     s.sigma = (uint64_t *)bc_dalloc(ctx, nn * batch * sizeof(uint64_t));
     s.cval = (float *)bc_dalloc(ctx, nn * batch * sizeof(float));
     s.src = (int32_t *)bc_dalloc(ctx, batch * sizeof(int32_t));
-    if (!s.heavy_id || !s.heavy_v || !s.heavy_nseg || !s.arrive || !s.seg_v || !s.seg_beg || !s.seg_end || !s.hacc || !s.visited || !s.sigma ||
-        !s.cval || !s.src)
+    if (!s.heavy_id || !s.heavy_nseg || !s.arrive || !s.arrive_w || !s.seg_v || !s.seg_beg || !s.seg_end || !s.hacc || !s.visited ||
+        !s.sigma || !s.cval || !s.src)
         return bc_fail(ctx, BC_ERR_NOMEM, "sparse form: state allocation failed");
-    if (n > 0) BC_HIP(ctx, hipMemcpyAsync(s.heavy_id, heavy_id.data(), nn * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
-    if (s.nheavy) {
-        BC_HIP(ctx, hipMemcpyAsync(s.heavy_v, heavy_v.data(), heavy_v.size() * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
-        BC_HIP(ctx, hipMemcpyAsync(s.heavy_nseg, heavy_nseg.data(), heavy_v.size() * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+    if (n > 0)
+        BC_HIP(ctx, hipMemcpyAsync(s.heavy_id, heavy_id.data(), nn * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+    if (nheavy) {
+        BC_HIP(ctx, hipMemcpyAsync(s.heavy_nseg, heavy_nseg.data(), (size_t)nheavy * sizeof(int32_t),
+                                   hipMemcpyHostToDevice, ctx->stream));
         BC_HIP(ctx, hipMemcpyAsync(s.seg_v, seg_v.data(), seg_v.size() * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
         BC_HIP(ctx, hipMemcpyAsync(s.seg_beg, seg_beg.data(), seg_v.size() * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
         BC_HIP(ctx, hipMemcpyAsync(s.seg_end, seg_end.data(), seg_v.size() * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
     }
-    BC_HIP(ctx, hipMemsetAsync(s.arrive, 0, std::max<size_t>(heavy_v.size(), 1) * s.words * sizeof(uint32_t), ctx->stream));
-    BC_HIP(ctx, hipMemsetAsync(s.hacc, 0, std::max<size_t>(heavy_v.size(), 1) * batch * sizeof(double), ctx->stream));
+    BC_HIP(ctx, hipMemsetAsync(s.arrive, 0, nh * sizeof(uint32_t), ctx->stream));
+    BC_HIP(ctx, hipMemsetAsync(s.arrive_w, 0, nh * s.words * sizeof(uint32_t), ctx->stream));
+    BC_HIP(ctx, hipMemsetAsync(s.hacc, 0, nh * batch * sizeof(double), ctx->stream));
     BC_HIP(ctx, hipStreamSynchronize(ctx->stream)); // host vectors above go out of scope
     return ensure_levels(ctx, 16);
 }
@@ -612,8 +787,13 @@ bc_status sparse_dump(bc_ctx *ctx, const int32_t *d_src, int32_t count,
     bc_status st = run_batch(ctx, d_src, count, false, &nlev);
     if (st != BC_OK) return st;
     const int64_t cells = (int64_t)ctx->n * count;
-    hipLaunchKernelGGL(k_sp_dump, dim3((unsigned)((cells + SB - 1) / SB)), dim3(SB), 0, ctx->stream, ctx->n, s.words,
-                       s.batch, count, nlev, s.front, s.sigma, s.delta_dump, dist_dump, sigma_dump, delta_dump);
+    const unsigned blocks = (unsigned)((cells + SB - 1) / SB);
+    if (s.wide)
+        hipLaunchKernelGGL(k_sp_dump<uint64_t>, dim3(blocks), dim3(SB), 0, ctx->stream, ctx->n, s.words, s.batch, count,
+                           nlev, s.front, (const uint64_t *)s.sigma, s.delta_dump, dist_dump, sigma_dump, delta_dump);
+    else
+        hipLaunchKernelGGL(k_sp_dump<uint32_t>, dim3(blocks), dim3(SB), 0, ctx->stream, ctx->n, s.words, s.batch, count,
+                           nlev, s.front, (const uint32_t *)s.sigma, s.delta_dump, dist_dump, sigma_dump, delta_dump);
     BC_HIP(ctx, hipGetLastError());
     return BC_OK;
 }

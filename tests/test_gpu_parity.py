@@ -208,3 +208,23 @@ def test_split_rows_parity(gpu_lib, split, name):
         d, sg, dl = oracle.sssp_u64(g, int(s))
         assert np.array_equal(dist[i], d) and np.array_equal(sigma[i], sg)
         assert rel_err(delta[i], dl) <= 1e-5
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_vertex_order_is_invisible(gpu_lib, form):
+    """The internal numbering (degree order or input order) never shows in results."""
+    g = gg.rmat(11, 16, 13)
+    say("vertex_order", form, g.n)
+    src = np.array([3, 17, 17, g.n - 1, 100], np.int32)
+    out = {}
+    for order in ("degree", "input"):
+        with gpu_lib.BC(g, form=form, vertex_order=order) as ctx:
+            ctx.run(src)
+            out[order] = (ctx.read(),) + ctx.sssp(src[:3])
+    want = oracle.bc(g, src)
+    for order, (bc, dist, sigma, delta) in out.items():
+        assert rel_err(bc, want) <= TOL[form], order
+        for i, s in enumerate(src[:3]):
+            d, sg, dl = oracle.sssp_u64(g, int(s))
+            assert np.array_equal(dist[i], d) and np.array_equal(sigma[i], sg), order
+            assert rel_err(delta[i], dl) <= TOL[form], order
