@@ -1,0 +1,502 @@
+// Algebraic form (Sec. 3.1): a batch of B sources is a frontier matrix and each
+// level is a product with the 0/1 adjacency matrix A on BF16 MFMA.
+//
+// Forward (Compute Path Count, first-hit reading): with F_l[v][b] = lambda(s_b, v)
+// where d(s_b, v) = l and 0 elsewhere,
+//     F_{l+1} = Mask_unvisited(A . F_l),
+// i.e. for every w not yet reached from s_b, lambda(s_b, w) = sum over
+// neighbours v at level l of lambda(s_b, v).  Counts are carried exactly:
+// F_l is split into 8-bit limbs F^(k) (each exact in BF16), every product
+// A . F^(k) is accumulated in FP32 -- exact, because each output is an integer
+// of at most 255 * deg(w) < 2^24 (deg <= 65792 is checked at create) -- and the
+// limbs are recombined as sum_k 2^(8k) P^(k) in 64-bit integers.
+//
+// Backward (Compute Dependency): with C_{l+1}[w][b] = (1 + delta(w,b)) /
+// lambda(s_b, w) for w at level l+1 (the "(D_l + Delta_l) div Lambda" matrix of
+// the paper, one level deeper), Delta_l = Mask_l(A . C_{l+1}) mult Lambda.
+// C is FP32; it is split exactly into three BF16 planes hi + mid + lo
+// (3 x 8 significand bits cover FP32's 24) and the three products are summed
+// in the same FP32 accumulators, which gives FP32-GEMM accuracy against a 0/1
+// matrix.  The dependencies are added into BC in the epilogue (column sums of
+// Delta without the diagonal: level 0 is never accumulated).
+//
+// Data layout: A is a dense row-major BF16 [npad][npad] matrix (npad = n
+// rounded up to 64).  Planes are k-packed: plane[v / 8][b][v % 8], so each
+// MFMA B-operand lane reads 16 contiguous bytes.  Every product is
+// C[w][b] = sum_v A[w][v] X[v][b] with rows = vertices and columns = sources;
+// in the 32x32 MFMA output the 32 lanes of each half-wave hold 32 consecutive
+// sources of one vertex, so two ballots give a 64-bit frontier word.
+// The frontier bitmaps, visited words, counts and c values are the batched
+// sparse form's state (sparse.hip): levels can switch between the two forms.
+#include "bc_internal.h"
+
+#include <algorithm>
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int GM = 64;   // rows (vertices) per block
+constexpr int GN = 256;  // columns (sources) per block: 4 waves x 64
+constexpr int GK = 32;   // k (vertices) per pipeline stage
+constexpr int GT = 256;  // threads per block
+constexpr int SA = GK + 8; // LDS row stride of the adjacency tile, in BF16 (padding against bank conflicts)
+constexpr int PB = 256;  // threads per block of the element-wise kernels
+
+enum { EPI_ONLY = 0, EPI_FIRST = 1, EPI_MID = 2, EPI_LAST = 3, EPI_BWD = 4 };
+
+struct GemmArgs {
+    const __bf16 *adj;     // [npad][npad]
+    const __bf16 *planes;  // NP planes of [npad/8][B][8]
+    const uint32_t *kflags;// [npad/GK][B/GN]: some plane entry of this k-tile is non-zero
+    int32_t npad, n, B, NW;
+    size_t plane_elems;    // npad * B
+};
+
+struct EpiArgs {
+    int shift;             // 8 * limb index
+    uint64_t *part;        // [npad][B] partial limb sums (FIRST/MID/LAST)
+    const uint64_t *fcur;  // backward: front[l]
+    uint64_t *fnext;       // forward: front[l+1]
+    uint64_t *visited;
+    void *sigma;           // uint32_t or uint64_t [n][B]
+    float *cval;           // [n][B]
+    const int32_t *src_lane;
+    double *bc, *delta_dump;
+    uint32_t *any_next, *status;
+    unsigned long long *level_max; // forward: max count of the new level
+    int accumulate;
+};
+
+__device__ __forceinline__ void store_count(uint64_t *p, uint64_t x, bool &) { *p = x; }
+__device__ __forceinline__ void store_count(uint32_t *p, uint64_t x, bool &wide) {
+    wide |= x > 0xFFFFFFFFull;
+    *p = (uint32_t)x;
+}
+
+// ---- the product -------------------------------------------------------------------
+
+// One pipeline stage held in registers between its global loads and its LDS
+// stores: 16 B of the adjacency tile and 4 x 16 B of each plane tile per thread.
+template <int NP>
+struct Stage {
+    u32x4 a;
+    u32x4 x[NP * 4];
+};
+
+template <int NP>
+__device__ __forceinline__ void load_stage(const GemmArgs &g, int kt, int w0, int b0, int tid, Stage<NP> &st) {
+    const int row = tid >> 2, kq = tid & 3;
+    st.a = *reinterpret_cast<const u32x4 *>(g.adj + (size_t)(w0 + row) * g.npad + (size_t)kt * GK + kq * 8);
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            st.x[p * 4 + i] = *reinterpret_cast<const u32x4 *>(
+                g.planes + (size_t)p * g.plane_elems + (((size_t)kt * (GK / 8) + i) * g.B + b0 + tid) * 8);
+}
+
+template <int NP>
+__device__ __forceinline__ void store_stage(__bf16 *sA, __bf16 *sX, int tid, const Stage<NP> &st) {
+    const int row = tid >> 2, kq = tid & 3;
+    *reinterpret_cast<u32x4 *>(sA + row * SA + kq * 8) = st.a;
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            *reinterpret_cast<u32x4 *>(sX + (((size_t)p * 4 + i) * GN + tid) * 8) = st.x[p * 4 + i];
+}
+
+template <int NP>
+__device__ __forceinline__ void mma_stage(const __bf16 *sA, const __bf16 *sX, int lane, int wv, f32x16 (&acc)[2][2]) {
+#pragma unroll
+    for (int kh = 0; kh < 2; ++kh) {
+        bf16x8 a[2];
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+            a[rt] = *reinterpret_cast<const bf16x8 *>(sA + (rt * 32 + (lane & 31)) * SA + kh * 16 + (lane >> 5) * 8);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct) {
+                const bf16x8 b = *reinterpret_cast<const bf16x8 *>(
+                    sX + (((size_t)p * 4 + kh * 2 + (lane >> 5)) * GN + wv * 64 + ct * 32 + (lane & 31)) * 8);
+#pragma unroll
+                for (int rt = 0; rt < 2; ++rt)
+                    acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[rt], b, acc[rt][ct], 0, 0, 0);
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ int next_tile(const uint32_t *flags, int ntn, int kt, int nkt) {
+    while (kt < nkt && flags[(size_t)kt * ntn] == 0) ++kt;
+    return kt;
+}
+
+// C[w][b] = sum over k-tiles with a non-zero flag of A[w][k] X[k][b], then the
+// epilogue.  Grid: (npad / GM, B / GN); 4 waves, wave wv owns sources
+// [b0 + 64 wv, b0 + 64 wv + 64) = one bitmap word, for all 64 rows of the block.
+template <int NP, int MODE, typename S>
+__global__ __launch_bounds__(GT) void k_mfma(GemmArgs g, EpiArgs e) {
+    __shared__ __align__(16) __bf16 sA[2][GM * SA];
+    __shared__ __align__(16) __bf16 sX[2][NP * 4 * GN * 8];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int w0 = blockIdx.x * GM, b0 = blockIdx.y * GN;
+    const int nkt = g.npad / GK, ntn = g.B / GN;
+    const uint32_t *flags = g.kflags + blockIdx.y;
+
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[rt][ct][r] = 0.f;
+
+    int kt = next_tile(flags, ntn, 0, nkt);
+    int buf = 0;
+    Stage<NP> st;
+    if (kt < nkt) {
+        load_stage<NP>(g, kt, w0, b0, tid, st);
+        store_stage<NP>(sA[0], sX[0], tid, st);
+    }
+    __syncthreads();
+    while (kt < nkt) {
+        const int kn = next_tile(flags, ntn, kt + 1, nkt);
+        if (kn < nkt) load_stage<NP>(g, kn, w0, b0, tid, st); // in flight during the products
+        mma_stage<NP>(sA[buf], sX[buf], lane, wv, acc);
+        if (kn < nkt) store_stage<NP>(sA[buf ^ 1], sX[buf ^ 1], tid, st);
+        __syncthreads();
+        buf ^= 1;
+        kt = kn;
+    }
+
+    // ---- epilogue ----
+    const int q = (b0 >> 6) + wv;           // bitmap word of this wave's sources
+    const int half = lane >> 5, col = lane & 31;
+    if constexpr (MODE == EPI_BWD) {
+        S *sigma = reinterpret_cast<S *>(e.sigma);
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int v = w0 + rt * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                const uint64_t F = v < g.n ? e.fcur[(size_t)v * g.NW + q] : 0;
+                double contrib = 0.0;
+#pragma unroll
+                for (int ct = 0; ct < 2; ++ct) {
+                    const int bit = ct * 32 + col;
+                    if ((F >> bit) & 1) {
+                        const size_t idx = (size_t)v * g.B + (size_t)q * 64 + bit;
+                        const double sv = (double)sigma[idx];
+                        const double dl = sv * (double)acc[rt][ct][r];
+                        e.cval[idx] = (float)((1.0 + dl) / sv);
+                        if (e.delta_dump) e.delta_dump[idx] = dl;
+                        if (e.src_lane[q * 64 + bit] != v) contrib += dl;
+                    }
+                }
+                if (e.accumulate) {
+#pragma unroll
+                    for (int off = 16; off > 0; off >>= 1) contrib += __shfl_xor(contrib, off, 64);
+                    if (col == 0 && contrib != 0.0) unsafeAtomicAdd(&e.bc[v], contrib);
+                }
+            }
+        }
+    } else {
+        S *sigma = reinterpret_cast<S *>(e.sigma);
+        bool wide = false;
+        uint64_t mx = 0;
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int w = w0 + rt * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                const bool valid = w < g.n;
+                uint64_t vis = ~0ull;
+                if (MODE == EPI_ONLY || MODE == EPI_LAST) vis = valid ? e.visited[(size_t)w * g.NW + q] : ~0ull;
+                uint64_t m[2];
+#pragma unroll
+                for (int ct = 0; ct < 2; ++ct) {
+                    const int bit = ct * 32 + col;
+                    const uint64_t P = (uint64_t)acc[rt][ct][r]; // exact integer < 2^24
+                    bool fresh = false;
+                    if (MODE == EPI_FIRST) {
+                        if (valid) e.part[(size_t)w * g.B + (size_t)q * 64 + bit] = P;
+                    } else if (MODE == EPI_MID) {
+                        if (valid) e.part[(size_t)w * g.B + (size_t)q * 64 + bit] += P << e.shift;
+                    } else {
+                        uint64_t tot = P << e.shift;
+                        if (MODE == EPI_LAST && valid) tot += e.part[(size_t)w * g.B + (size_t)q * 64 + bit];
+                        fresh = valid && !((vis >> bit) & 1) && tot != 0;
+                        if (fresh) {
+                            store_count(&sigma[(size_t)w * g.B + (size_t)q * 64 + bit], tot, wide);
+                            mx = tot > mx ? tot : mx;
+                        }
+                    }
+                    m[ct] = __ballot(fresh);
+                }
+                if (MODE == EPI_ONLY || MODE == EPI_LAST) {
+                    // lanes 0..31 hold vertex w of half 0, lanes 32..63 vertex w + 4
+                    const uint64_t word = half == 0 ? ((m[0] & 0xFFFFFFFFull) | (m[1] << 32))
+                                                    : ((m[0] >> 32) | (m[1] & 0xFFFFFFFF00000000ull));
+                    if (col == 0 && valid) {
+                        e.fnext[(size_t)w * g.NW + q] = word;
+                        if (word) {
+                            e.visited[(size_t)w * g.NW + q] = vis | word;
+                            atomicOr(&e.any_next[w >> 5], 1u << (w & 31));
+                        }
+                    }
+                }
+            }
+        }
+        if (MODE == EPI_ONLY || MODE == EPI_LAST) {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                const uint64_t o = __shfl_xor(mx, off, 64);
+                mx = o > mx ? o : mx;
+            }
+            if (lane == 0 && mx) atomicMax(e.level_max, (unsigned long long)mx);
+            if (__any(wide) && lane == 0) atomicOr(&e.status[1], 1u);
+        }
+    }
+}
+
+// ---- element-wise kernels -------------------------------------------------------
+
+__global__ __launch_bounds__(PB) void k_build_adj(int32_t n, int32_t npad, const int32_t *__restrict__ rp,
+                                                  const int32_t *__restrict__ col, __bf16 *__restrict__ adj) {
+    const int32_t v = blockIdx.x;
+    if (v >= n) return;
+    const __bf16 one = (__bf16)1.0f;
+    for (int32_t e = rp[v] + threadIdx.x; e < rp[v + 1]; e += PB) adj[(size_t)v * npad + col[e]] = one;
+}
+
+// Largest count at level l (for the number of 8-bit limbs).
+template <typename S>
+__global__ __launch_bounds__(PB) void k_level_max(int32_t n, int32_t B, int32_t NW, const uint64_t *__restrict__ fl,
+                                                  const S *__restrict__ sigma, unsigned long long *out) {
+    uint64_t mx = 0;
+    const size_t total = (size_t)n * B;
+    for (size_t i = (size_t)blockIdx.x * PB + threadIdx.x; i < total; i += (size_t)gridDim.x * PB) {
+        const size_t v = i / B;
+        const int b = (int)(i - v * B);
+        if ((fl[v * NW + (b >> 6)] >> (b & 63)) & 1) {
+            const uint64_t s = (uint64_t)sigma[i];
+            mx = s > mx ? s : mx;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint64_t o = __shfl_xor(mx, off, 64);
+        mx = o > mx ? o : mx;
+    }
+    if ((threadIdx.x & 63) == 0 && mx) atomicMax(out, (unsigned long long)mx);
+}
+
+// planes[k][v/8][b][v%8] = limb k of lambda(s_b, v) for v at level l, else 0;
+// kflags[v / GK][b / GN] |= (some limb non-zero).  Thread (vg, b) covers 8 rows.
+template <typename S>
+__global__ __launch_bounds__(PB) void k_limb_split(int32_t n, int32_t npad, int32_t B, int32_t NW, int32_t L,
+                                                   const uint64_t *__restrict__ fl, const S *__restrict__ sigma,
+                                                   __bf16 *__restrict__ planes, size_t plane_elems,
+                                                   uint32_t *__restrict__ kflags) {
+    const size_t id = (size_t)blockIdx.x * PB + threadIdx.x;
+    if (id >= (size_t)(npad / 8) * B) return;
+    const int32_t vg = (int32_t)(id / B), b = (int32_t)(id - (size_t)vg * B);
+    uint64_t s[8];
+    bool nz = false;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int32_t v = vg * 8 + j;
+        s[j] = 0;
+        if (v < n && ((fl[(size_t)v * NW + (b >> 6)] >> (b & 63)) & 1)) s[j] = (uint64_t)sigma[(size_t)v * B + b];
+        nz |= s[j] != 0;
+    }
+    for (int k = 0; k < L; ++k) {
+        bf16x8 o;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) o[j] = (__bf16)(float)((s[j] >> (8 * k)) & 0xFF);
+        *reinterpret_cast<bf16x8 *>(planes + (size_t)k * plane_elems + id * 8) = o;
+    }
+    if (__ballot(nz) && (threadIdx.x & 63) == 0) atomicOr(&kflags[(size_t)(vg * 8 / GK) * (B / GN) + b / GN], 1u);
+}
+
+// planes[0..2][v/8][b][v%8] = hi, mid, lo BF16 parts of c(v, b) for v at level l.
+__global__ __launch_bounds__(PB) void k_coef_split(int32_t n, int32_t npad, int32_t B, int32_t NW,
+                                                   const uint64_t *__restrict__ fl, const float *__restrict__ cval,
+                                                   __bf16 *__restrict__ planes, size_t plane_elems,
+                                                   uint32_t *__restrict__ kflags) {
+    const size_t id = (size_t)blockIdx.x * PB + threadIdx.x;
+    if (id >= (size_t)(npad / 8) * B) return;
+    const int32_t vg = (int32_t)(id / B), b = (int32_t)(id - (size_t)vg * B);
+    bf16x8 hi, mid, lo;
+    bool nz = false;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int32_t v = vg * 8 + j;
+        float c = 0.f;
+        if (v < n && ((fl[(size_t)v * NW + (b >> 6)] >> (b & 63)) & 1)) c = cval[(size_t)v * B + b];
+        const __bf16 h = (__bf16)c;
+        const float r1 = c - (float)h;
+        const __bf16 m = (__bf16)r1;
+        const float r2 = r1 - (float)m;
+        hi[j] = h;
+        mid[j] = m;
+        lo[j] = (__bf16)r2;
+        nz |= c != 0.f;
+    }
+    *reinterpret_cast<bf16x8 *>(planes + id * 8) = hi;
+    *reinterpret_cast<bf16x8 *>(planes + plane_elems + id * 8) = mid;
+    *reinterpret_cast<bf16x8 *>(planes + 2 * plane_elems + id * 8) = lo;
+    if (__ballot(nz) && (threadIdx.x & 63) == 0) atomicOr(&kflags[(size_t)(vg * 8 / GK) * (B / GN) + b / GN], 1u);
+}
+
+inline unsigned blocks_for(size_t count, int per) { return (unsigned)((count + per - 1) / per); }
+
+GemmArgs gemm_args(bc_ctx *ctx, const __bf16 *planes) {
+    AlgebraicState &a = ctx->al;
+    GemmArgs g;
+    g.adj = a.adj;
+    g.planes = planes;
+    g.kflags = a.kflags;
+    g.npad = a.npad;
+    g.n = ctx->n;
+    g.B = ctx->sp.batch;
+    g.NW = ctx->sp.words;
+    g.plane_elems = (size_t)a.npad * ctx->sp.batch;
+    return g;
+}
+
+} // namespace
+
+bc_status algebraic_prepare(bc_ctx *ctx) {
+    AlgebraicState &a = ctx->al;
+    const int32_t B = ctx->sp.batch;
+    if (ctx->weighted) return bc_fail(ctx, BC_ERR_UNSUPPORTED, "algebraic form: unit weights only");
+    if (B % GN != 0) return bc_fail(ctx, BC_ERR_UNSUPPORTED, "algebraic form: batch must be 256 or 512");
+    if (ctx->max_degree > 65792)
+        return bc_fail(ctx, BC_ERR_UNSUPPORTED,
+                       "algebraic form: a degree above 65792 breaks exact FP32 accumulation of 8-bit limbs");
+    a.npad = std::max(64, (ctx->n + 63) / 64 * 64);
+    const size_t adj_bytes = (size_t)a.npad * a.npad * sizeof(__bf16);
+    if (adj_bytes > (size_t(96) << 30))
+        return bc_fail(ctx, BC_ERR_UNSUPPORTED, "algebraic form: the dense adjacency would exceed 96 GiB");
+    const size_t plane_elems = (size_t)a.npad * B;
+    a.adj = (__bf16 *)bc_dalloc(ctx, adj_bytes);
+    a.planes = (__bf16 *)bc_dalloc(ctx, 8 * plane_elems * sizeof(__bf16)); // up to 8 limbs, or 3 coefficient planes
+    a.part = (uint64_t *)bc_dalloc(ctx, plane_elems * sizeof(uint64_t));
+    a.kflags = (uint32_t *)bc_dalloc(ctx, (size_t)(a.npad / GK) * (B / GN) * sizeof(uint32_t));
+    a.level_max = (unsigned long long *)bc_dalloc(ctx, 256);
+    a.host = nullptr;
+    if (!a.adj || !a.planes || !a.part || !a.kflags || !a.level_max ||
+        hipHostMalloc((void **)&a.host, 256) != hipSuccess)
+        return bc_fail(ctx, BC_ERR_NOMEM, "algebraic form: allocation failed");
+    BC_HIP(ctx, hipMemsetAsync(a.adj, 0, adj_bytes, ctx->stream));
+    if (ctx->n > 0)
+        hipLaunchKernelGGL(k_build_adj, dim3(ctx->n), dim3(PB), 0, ctx->stream, ctx->n, a.npad, ctx->row_ptr,
+                           ctx->col, a.adj);
+    BC_HIP(ctx, hipGetLastError());
+    return BC_OK;
+}
+
+// Largest count among level-l entries of the batch (synchronises).
+template <typename S>
+static bc_status level_max(bc_ctx *ctx, const uint64_t *fl, uint64_t *out) {
+    AlgebraicState &a = ctx->al;
+    const SparseState &s = ctx->sp;
+    BC_HIP(ctx, hipMemsetAsync(a.level_max, 0, sizeof(unsigned long long), ctx->stream));
+    const size_t total = (size_t)ctx->n * s.batch;
+    hipLaunchKernelGGL(k_level_max<S>, dim3(std::min<unsigned>(blocks_for(total, PB), 4096)), dim3(PB), 0,
+                       ctx->stream, ctx->n, s.batch, s.words, fl, (const S *)s.sigma, a.level_max);
+    BC_HIP(ctx, hipGetLastError());
+    BC_HIP(ctx, hipMemcpyAsync(a.host, a.level_max, sizeof(unsigned long long), hipMemcpyDeviceToHost, ctx->stream));
+    BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    *out = *a.host;
+    return BC_OK;
+}
+
+// Forward level l -> l+1 as products with A.  Writes front[l+1], visited,
+// counts and any[l+1] exactly as the pull kernel does.
+template <typename S>
+bc_status algebraic_forward_level_t(bc_ctx *ctx, const uint64_t *fcur, uint64_t *fnext, uint32_t *any_next) {
+    AlgebraicState &a = ctx->al;
+    SparseState &s = ctx->sp;
+    uint64_t mx = 0;
+    bc_status st = level_max<S>(ctx, fcur, &mx);
+    if (st != BC_OK) return st;
+    int L = 1;
+    while (L < 8 && (mx >> (8 * L)) != 0) ++L;
+    const size_t plane_elems = (size_t)a.npad * s.batch;
+    BC_HIP(ctx, hipMemsetAsync(a.kflags, 0, (size_t)(a.npad / GK) * (s.batch / GN) * sizeof(uint32_t), ctx->stream));
+    {
+        LaunchTimer tm(ctx, "limb_split");
+        hipLaunchKernelGGL(k_limb_split<S>, dim3(blocks_for(plane_elems / 8, PB)), dim3(PB), 0, ctx->stream, ctx->n,
+                           a.npad, s.batch, s.words, L, fcur, (const S *)s.sigma, a.planes, plane_elems, a.kflags);
+        tm.done();
+    }
+    EpiArgs e{};
+    e.part = a.part;
+    e.fnext = fnext;
+    e.visited = s.visited;
+    e.sigma = s.sigma;
+    e.any_next = any_next;
+    e.status = ctx->status;
+    e.level_max = a.level_max;
+    const dim3 grid(a.npad / GM, s.batch / GN);
+    for (int k = 0; k < L; ++k) {
+        const GemmArgs g = gemm_args(ctx, a.planes + (size_t)k * plane_elems);
+        e.shift = 8 * k;
+        LaunchTimer tm(ctx, "mfma_fwd");
+        if (L == 1) hipLaunchKernelGGL((k_mfma<1, EPI_ONLY, S>), grid, dim3(GT), 0, ctx->stream, g, e);
+        else if (k == 0) hipLaunchKernelGGL((k_mfma<1, EPI_FIRST, S>), grid, dim3(GT), 0, ctx->stream, g, e);
+        else if (k + 1 < L) hipLaunchKernelGGL((k_mfma<1, EPI_MID, S>), grid, dim3(GT), 0, ctx->stream, g, e);
+        else hipLaunchKernelGGL((k_mfma<1, EPI_LAST, S>), grid, dim3(GT), 0, ctx->stream, g, e);
+        tm.done();
+    }
+    BC_HIP(ctx, hipGetLastError());
+    return BC_OK;
+}
+
+// Backward level l as a product with A: acc = A . C_{l+1}, masked to level l.
+template <typename S>
+bc_status algebraic_backward_level_t(bc_ctx *ctx, const uint64_t *fcur, const uint64_t *fnext, double *delta_dump,
+                                     bool accumulate) {
+    AlgebraicState &a = ctx->al;
+    SparseState &s = ctx->sp;
+    const size_t plane_elems = (size_t)a.npad * s.batch;
+    BC_HIP(ctx, hipMemsetAsync(a.kflags, 0, (size_t)(a.npad / GK) * (s.batch / GN) * sizeof(uint32_t), ctx->stream));
+    {
+        LaunchTimer tm(ctx, "coef_split");
+        hipLaunchKernelGGL(k_coef_split, dim3(blocks_for(plane_elems / 8, PB)), dim3(PB), 0, ctx->stream, ctx->n,
+                           a.npad, s.batch, s.words, fnext, s.cval, a.planes, plane_elems, a.kflags);
+        tm.done();
+    }
+    EpiArgs e{};
+    e.fcur = fcur;
+    e.sigma = s.sigma;
+    e.cval = s.cval;
+    e.src_lane = s.src;
+    e.bc = ctx->bc;
+    e.delta_dump = delta_dump;
+    e.accumulate = accumulate ? 1 : 0;
+    const GemmArgs g = gemm_args(ctx, a.planes);
+    LaunchTimer tm(ctx, "mfma_bwd");
+    hipLaunchKernelGGL((k_mfma<3, EPI_BWD, S>), dim3(a.npad / GM, s.batch / GN), dim3(GT), 0, ctx->stream, g, e);
+    tm.done();
+    BC_HIP(ctx, hipGetLastError());
+    return BC_OK;
+}
+
+bc_status algebraic_forward_level(bc_ctx *ctx, bool wide, const uint64_t *fcur, uint64_t *fnext, uint32_t *any_next) {
+    return wide ? algebraic_forward_level_t<uint64_t>(ctx, fcur, fnext, any_next)
+                : algebraic_forward_level_t<uint32_t>(ctx, fcur, fnext, any_next);
+}
+
+bc_status algebraic_backward_level(bc_ctx *ctx, bool wide, const uint64_t *fcur, const uint64_t *fnext,
+                                   double *delta_dump, bool accumulate) {
+    return wide ? algebraic_backward_level_t<uint64_t>(ctx, fcur, fnext, delta_dump, accumulate)
+                : algebraic_backward_level_t<uint32_t>(ctx, fcur, fnext, delta_dump, accumulate);
+}

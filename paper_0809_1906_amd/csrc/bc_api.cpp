@@ -106,6 +106,8 @@ void release_all(bc_ctx *ctx) {
     ctx->owned.clear();
     if (ctx->status_host) hipHostFree(ctx->status_host);
     if (ctx->sp.any_host) hipHostFree(ctx->sp.any_host);
+    if (ctx->al.host) hipHostFree(ctx->al.host);
+    ctx->al.host = nullptr;
     ctx->status_host = nullptr;
     ctx->sp.any_host = nullptr;
 }
@@ -265,8 +267,6 @@ bc_status bc_create(const bc_graph *g, const bc_options *opt_in, bc_ctx **out) {
     if (form == BC_FORM_AUTO) form = BC_FORM_SPARSE;
     if (hw && (form == BC_FORM_SPARSE || form == BC_FORM_ALGEBRAIC))
         return fail_create(BC_ERR_UNSUPPORTED, "weighted graphs are served by the plain form only");
-    if (form == BC_FORM_ALGEBRAIC)
-        return fail_create(BC_ERR_UNSUPPORTED, "the algebraic form is not available");
 
     // ---- device side ----
     bc_ctx *ctx = new (std::nothrow) bc_ctx();
@@ -361,6 +361,12 @@ bc_status bc_create(const bc_graph *g, const bc_options *opt_in, bc_ctx **out) {
     bc_status ps = BC_OK;
     if (form == BC_FORM_PLAIN_FP64) ps = plain_prepare(ctx);
     else if (form == BC_FORM_SPARSE) ps = sparse_prepare(ctx, opt.batch ? opt.batch : 256, opt.split_degree);
+    else if (form == BC_FORM_ALGEBRAIC) {
+        ps = sparse_prepare(ctx, opt.batch ? opt.batch : 256, opt.split_degree);
+        if (ps == BC_OK) ps = algebraic_prepare(ctx);
+        ctx->al.fwd_levels = ~1u; // every level l >= 1 as a product with A
+        ctx->al.bwd_levels = ~1u;
+    }
     if (ps != BC_OK) return bail(ps, ctx->err);
     if (hipStreamSynchronize(ctx->stream) != hipSuccess) return bail(BC_ERR_DEVICE, "stream synchronisation failed");
     *out = ctx;
@@ -437,7 +443,7 @@ bc_status bc_run(bc_ctx *ctx, const int32_t *sources, int64_t count, bc_mem mem)
     if (s != BC_OK) return s;
     if (cnt == 0 || ctx->n == 0) return BC_OK;
     if (ctx->form == BC_FORM_PLAIN_FP64) s = plain_run(ctx, d_src, cnt, true, nullptr, nullptr, nullptr);
-    else if (ctx->form == BC_FORM_SPARSE) s = sparse_run(ctx, d_src, cnt);
+    else if (ctx->form == BC_FORM_SPARSE || ctx->form == BC_FORM_ALGEBRAIC) s = sparse_run(ctx, d_src, cnt);
     else s = bc_fail(ctx, BC_ERR_UNSUPPORTED, "form not available");
     if (s == BC_OK) ctx->sources_run += cnt;
     return s;
@@ -480,7 +486,7 @@ bc_status bc_read_sssp(bc_ctx *ctx, const int32_t *sources, int32_t count,
     if (!ctx) return BC_ERR_INVALID_ARG;
     bc_status s = check_usable(ctx);
     if (s != BC_OK) return s;
-    int32_t maxc = ctx->form == BC_FORM_SPARSE ? ctx->sp.batch : 4096;
+    int32_t maxc = ctx->form == BC_FORM_PLAIN_FP64 ? 4096 : ctx->sp.batch;
     if (!sources || count < 1 || count > maxc) return bc_fail(ctx, BC_ERR_INVALID_ARG, "count must be in [1, batch]");
     const int32_t *d_src = nullptr;
     int64_t cnt = 0;
@@ -534,7 +540,7 @@ bc_status bc_get_info(const bc_ctx *ctx, bc_info *out) {
     out->max_degree = ctx->max_degree;
     out->weighted = ctx->weighted ? 1 : 0;
     out->form = ctx->form;
-    out->batch = ctx->form == BC_FORM_SPARSE ? ctx->sp.batch : 1;
+    out->batch = ctx->form == BC_FORM_PLAIN_FP64 ? 1 : ctx->sp.batch;
     out->max_levels = ctx->max_levels;
     out->sources_run = ctx->sources_run;
     out->device_bytes = ctx->device_bytes;

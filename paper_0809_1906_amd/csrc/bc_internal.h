@@ -49,6 +49,19 @@ struct SparseState {
     double *hacc = nullptr;      // [nheavy][batch] partial sums of split rows (u64 or f64)
 };
 
+// State of the algebraic form (dense adjacency products on MFMA).
+struct AlgebraicState {
+    int32_t npad = 0;                  // n rounded up to 64
+    __bf16 *adj = nullptr;             // [npad][npad] 0/1
+    __bf16 *planes = nullptr;          // up to 8 planes of [npad/8][batch][8]
+    uint64_t *part = nullptr;          // [npad][batch] partial limb sums
+    uint32_t *kflags = nullptr;        // [npad/32][batch/256] non-empty k-tiles
+    unsigned long long *level_max = nullptr;
+    unsigned long long *host = nullptr; // pinned
+    uint32_t fwd_levels = 0;           // bit l: forward level l -> l+1 by products (l >= 1)
+    uint32_t bwd_levels = 0;           // bit l: backward level l by products (l >= 1)
+};
+
 // State of the plain per-source form.
 struct PlainState {
     int32_t groups = 0;       // persistent workgroups
@@ -92,6 +105,7 @@ struct bc_ctx {
     // forms
     bc_form form = BC_FORM_PLAIN_FP64;
     SparseState sp;
+    AlgebraicState al;
     PlainState pl;
 
     // bookkeeping
@@ -137,6 +151,10 @@ bc_status plain_run(bc_ctx *ctx, const int32_t *d_sources, int64_t count, bool a
                     double *delta_dump, int32_t *dist_dump, uint64_t *sigma_dump);
 
 bc_status sparse_prepare(bc_ctx *ctx, int32_t batch, int32_t split_degree);
+bc_status algebraic_prepare(bc_ctx *ctx);
+bc_status algebraic_forward_level(bc_ctx *ctx, bool wide, const uint64_t *fcur, uint64_t *fnext, uint32_t *any_next);
+bc_status algebraic_backward_level(bc_ctx *ctx, bool wide, const uint64_t *fcur, const uint64_t *fnext,
+                                   double *delta_dump, bool accumulate);
 bc_status sparse_run(bc_ctx *ctx, const int32_t *d_sources, int64_t count);
 bc_status sparse_dump(bc_ctx *ctx, const int32_t *d_sources, int32_t count,
                       int32_t *dist_dump, uint64_t *sigma_dump, double *delta_dump);

@@ -619,8 +619,12 @@ bc_status run_batch_t(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool acc
         BC_HIP(ctx, hipGetLastError());
     }
     int32_t launched = 0, nlev = -1;
+    const uint32_t mfma_fwd = ctx->al.fwd_levels;
+    const bool wide_now = sizeof(S) == 8;
     while (nlev < 0) {
-        const int32_t target = launched == 0 ? guess : launched + 2;
+        // With products at some forward level the host needs each level's
+        // largest count first, so levels go one at a time.
+        const int32_t target = mfma_fwd ? launched + 1 : (launched == 0 ? guess : launched + 2);
         st = ensure_levels(ctx, target + 1);
         if (st != BC_OK) return st;
         for (int32_t l = launched; l < target; ++l) {
@@ -631,6 +635,12 @@ bc_status run_batch_t(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool acc
                 tm.done();
                 continue;
             }
+            if (l < 32 && ((mfma_fwd >> l) & 1)) {
+                st = algebraic_forward_level(ctx, wide_now, s.front + (size_t)l * words,
+                                             s.front + (size_t)(l + 1) * words, s.any + (size_t)(l + 1) * aw);
+                if (st != BC_OK) return st;
+                continue;
+            }
             LaunchTimer tm(ctx, "fwd_pull");
             hipLaunchKernelGGL((k_fwd_pull<NW, S>), dim3(pull_blocks), dim3(SB), 0, ctx->stream, t,
                                s.any + (size_t)l * aw, s.front + (size_t)l * words, s.front + (size_t)(l + 1) * words,
@@ -639,8 +649,10 @@ bc_status run_batch_t(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool acc
             tm.done();
         }
         BC_HIP(ctx, hipGetLastError());
-        BC_HIP(ctx, hipMemcpyAsync(s.any_host + aw, s.any + aw, (size_t)target * aw * sizeof(uint32_t),
-                                   hipMemcpyDeviceToHost, ctx->stream));
+        const int32_t first = mfma_fwd ? target : 1; // levels whose filter is read back
+        BC_HIP(ctx, hipMemcpyAsync(s.any_host + (size_t)first * aw, s.any + (size_t)first * aw,
+                                   (size_t)(target - first + 1) * aw * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                                   ctx->stream));
         BC_HIP(ctx, hipMemcpyAsync(ctx->status_host + 1, ctx->status + 1, sizeof(uint32_t), hipMemcpyDeviceToHost,
                                    ctx->stream));
         BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -649,7 +661,7 @@ bc_status run_batch_t(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool acc
             *need_wide = true;
             return BC_OK;
         }
-        for (int32_t l = 1; l <= target && nlev < 0; ++l) {
+        for (int32_t l = first; l <= target && nlev < 0; ++l) {
             const uint32_t *a = s.any_host + (size_t)l * aw;
             bool empty = true;
             for (int32_t i = 0; i < aw && empty; ++i) empty = a[i] == 0;
@@ -665,6 +677,11 @@ bc_status run_batch_t(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool acc
         const bool deeper = lv + 1 < nlev;
         const uint64_t *fnext = deeper ? s.front + (size_t)(lv + 1) * words : nullptr;
         const uint32_t *anext = deeper ? s.any + (size_t)(lv + 1) * aw : nullptr;
+        if (deeper && lv < 32 && ((ctx->al.bwd_levels >> lv) & 1)) {
+            st = algebraic_backward_level(ctx, sizeof(S) == 8, fcur, fnext, ddump, accumulate);
+            if (st != BC_OK) return st;
+            continue;
+        }
         LaunchTimer tm(ctx, "bwd_pull");
         if (s.bwd_per_word)
             hipLaunchKernelGGL((k_bwd_pull_w<NW, S>), dim3(word_blocks), dim3(SB), 0, ctx->stream, t, fcur, anext,

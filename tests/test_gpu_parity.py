@@ -13,8 +13,8 @@ import oracle
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"plain": 1e-12, "sparse": 1e-5}
-FORMS = ["plain", "sparse"]
+TOL = {"plain": 1e-12, "sparse": 1e-5, "algebraic": 1e-5}
+FORMS = ["plain", "sparse", "algebraic"]
 
 
 def rel_err(x, y):
@@ -172,6 +172,43 @@ def test_rmat16_full_size_sampled(gpu_lib):
     err = rel_err(got, want)
     say("rmat16 BC(512 sources) max rel err", err)
     assert err <= 1e-5
+
+
+def test_rmat16_algebraic_form_sampled(gpu_lib):
+    """The algebraic form (products with the dense adjacency on MFMA) at the
+    benchmark's full size: one batch of per-source results, and BC over a
+    ragged two-batch source list."""
+    g = gg.rmat16()
+    say("rmat16_algebraic", g.n, g.m)
+    src = gg.Stream(99).bounded(np.full(256, g.n)).astype(np.int32)
+    with gpu_lib.BC(g, form="algebraic", batch=256) as ctx:
+        dist, sigma, delta = ctx.sssp(src)
+        sub = src[:300 - 44]
+        ctx.run(np.concatenate([sub, src[:44]]))
+        got = ctx.read()
+    for i in range(0, 256, 8):
+        d, sg, dl = oracle.sssp_u64(g, int(src[i]))
+        assert np.array_equal(dist[i], d) and np.array_equal(sigma[i], sg), f"source {src[i]}"
+        assert rel_err(delta[i], dl) <= 1e-5
+    want = oracle.bc(g, np.concatenate([sub, src[:44]]), threads=8)
+    assert rel_err(got, want) <= 1e-5
+
+
+def test_algebraic_limbs_and_wide_counts(gpu_lib):
+    """Counts of several 8-bit limbs (grid 20x20: up to C(38,19) > 2^32, so
+    five limbs and uint64 storage) stay exact through the BF16 products."""
+    g = gg.grid(20, 20)
+    say("algebraic_limbs")
+    src = np.array([0, 19, 210, 399], np.int32)
+    with gpu_lib.BC(g, form="algebraic") as ctx:
+        dist, sigma, delta = ctx.sssp(src)
+        ctx.run(src)
+        got = ctx.read()
+    for i, s in enumerate(src):
+        d, sg, dl = oracle.sssp_u64(g, int(s))
+        assert np.array_equal(dist[i], d) and np.array_equal(sigma[i], sg)
+        assert rel_err(delta[i], dl) <= 1e-5
+    assert rel_err(got, oracle.bc(g, src)) <= 1e-5
 
 
 def test_rmat16_plain_form_sampled(gpu_lib):
