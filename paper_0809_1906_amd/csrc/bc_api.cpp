@@ -264,9 +264,10 @@ bc_status bc_create(const bc_graph *g, const bc_options *opt_in, bc_ctx **out) {
     if (vs != BC_OK) return fail_create(vs, msg);
 
     bc_form form = opt.form;
-    if (form == BC_FORM_AUTO) form = BC_FORM_SPARSE;
+    if (form == BC_FORM_AUTO) form = hw ? BC_FORM_PLAIN_FP64 : BC_FORM_SPARSE;
     if (hw && (form == BC_FORM_SPARSE || form == BC_FORM_ALGEBRAIC))
-        return fail_create(BC_ERR_UNSUPPORTED, "weighted graphs are served by the plain form only");
+        return fail_create(BC_ERR_UNSUPPORTED,
+                           "weighted graphs are served by the per-source form (BC_FORM_PLAIN_FP64) only");
 
     // ---- device side ----
     bc_ctx *ctx = new (std::nothrow) bc_ctx();

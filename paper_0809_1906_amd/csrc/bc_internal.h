@@ -62,6 +62,17 @@ struct AlgebraicState {
     uint32_t bwd_levels = 0;           // bit l: backward level l by products (l >= 1)
 };
 
+// State of the weighted per-source form (bucketed shortest paths).
+struct WeightedState {
+    int32_t groups = 0;
+    int64_t cap = 0;              // arena entries per workgroup
+    int32_t *dist = nullptr, *order = nullptr, *gstart = nullptr, *gdist = nullptr, *arena = nullptr;
+    int32_t *bstart = nullptr, *bcount = nullptr;
+    uint64_t *sigma = nullptr;
+    double *acc = nullptr;
+    uint32_t *next = nullptr;
+};
+
 // State of the plain per-source form.
 struct PlainState {
     int32_t groups = 0;       // persistent workgroups
@@ -107,6 +118,7 @@ struct bc_ctx {
     SparseState sp;
     AlgebraicState al;
     PlainState pl;
+    WeightedState wt;
 
     // bookkeeping
     int64_t sources_run = 0;
@@ -149,6 +161,10 @@ bc_status rows_to_caller_order_u64(bc_ctx *ctx, uint64_t *out, const uint64_t *i
 bc_status plain_prepare(bc_ctx *ctx);
 bc_status plain_run(bc_ctx *ctx, const int32_t *d_sources, int64_t count, bool accumulate,
                     double *delta_dump, int32_t *dist_dump, uint64_t *sigma_dump);
+
+bc_status weighted_prepare(bc_ctx *ctx);
+bc_status weighted_run(bc_ctx *ctx, const int32_t *d_sources, int64_t count, bool accumulate,
+                       double *delta_dump, int32_t *dist_dump, uint64_t *sigma_dump);
 
 bc_status sparse_prepare(bc_ctx *ctx, int32_t batch, int32_t split_degree);
 bc_status algebraic_prepare(bc_ctx *ctx);

@@ -221,6 +221,7 @@ __global__ __launch_bounds__(PB) void k_plain_sweep(
 } // namespace
 
 bc_status plain_prepare(bc_ctx *ctx) {
+    if (ctx->weighted) return weighted_prepare(ctx);
     PlainState &p = ctx->pl;
     const size_t n = (size_t)std::max(ctx->n, 1);
     const size_t per_group = n * (4 + 8 + 8 + 4) + (n + 2) * 4;
@@ -241,7 +242,7 @@ bc_status plain_prepare(bc_ctx *ctx) {
 
 bc_status plain_run(bc_ctx *ctx, const int32_t *d_sources, int64_t count, bool accumulate,
                     double *delta_dump, int32_t *dist_dump, uint64_t *sigma_dump) {
-    if (ctx->weighted) return bc_fail(ctx, BC_ERR_UNSUPPORTED, "plain form: weighted sweep not available");
+    if (ctx->weighted) return weighted_run(ctx, d_sources, count, accumulate, delta_dump, dist_dump, sigma_dump);
     PlainState &p = ctx->pl;
     BC_HIP(ctx, hipMemsetAsync(p.next, 0, sizeof(unsigned long long), ctx->stream));
     const int grid = (int)std::min<int64_t>(count, p.groups);

@@ -19,5 +19,6 @@ def gpu_lib():
     if not torch.cuda.is_available():
         pytest.fail("GPU test run without a visible GPU")
     import paper_0809_1906_amd as bcgpu
+    import paper_0809_1906_amd.binding  # noqa: F401
     bcgpu.load()  # raises if the shared library is missing
     return bcgpu

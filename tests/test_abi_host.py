@@ -107,3 +107,12 @@ def test_invalid_arguments():
     assert lib.bc_read(None, None, 0) == B.BC_ERR_INVALID_ARG
     assert lib.bc_reset(None) == B.BC_ERR_INVALID_ARG
     lib.bc_destroy(None)
+
+
+def test_batched_forms_refuse_weights_before_device_work():
+    g = gg.with_uniform_weights(gg.path(5), 1, 1, 9)
+    for form in (B.BC_FORM_SPARSE, B.BC_FORM_ALGEBRAIC):
+        opt = bcgpu.bc_options_init()
+        opt.form = form
+        st, msg = _create_status(g.n, g.row_ptr, g.col, g.weight, opt)
+        assert st == B.BC_ERR_UNSUPPORTED and "weighted" in msg

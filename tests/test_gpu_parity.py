@@ -265,3 +265,57 @@ def test_vertex_order_is_invisible(gpu_lib, form):
             d, sg, dl = oracle.sssp_u64(g, int(s))
             assert np.array_equal(dist[i], d) and np.array_equal(sigma[i], sg), order
             assert rel_err(delta[i], dl) <= TOL[form], order
+
+
+def weighted_graphs():
+    return [gg.random_graph(40, 0.15, 5, weights=9), gg.kkp_undirected(6),
+            gg.with_uniform_weights(gg.er_plus_tree(500, 6.0, 8), 8, 1, 255),
+            gg.with_constant_weight(gg.grid(15, 17), 3),
+            gg.disjoint_union(gg.with_uniform_weights(gg.path(30), 2, 1, 4), gg.random_graph(50, 0.1, 9, weights=7)),
+            gg.with_uniform_weights(gg.rmat(11, 16, 4), 4, 1, 255)]
+
+
+@pytest.mark.parametrize("gi", range(6))
+def test_weighted_bc_and_sssp(gpu_lib, gi):
+    """Positive integer weights: bucketed shortest paths, one bucket per distance."""
+    g = weighted_graphs()[gi]
+    say("weighted", g.name, g.n, g.m)
+    want = oracle.bc(g)
+    src = np.unique(np.array([0, 1, g.n // 3, g.n - 1], np.int32))
+    with gpu_lib.BC(g) as ctx:  # the automatic choice for weighted graphs
+        assert ctx.info().form == gpu_lib.binding.BC_FORM_PLAIN_FP64
+        ctx.run()
+        got = ctx.read()
+        dist, sigma, delta = ctx.sssp(src)
+    assert rel_err(got, want) <= 1e-12
+    for i, s in enumerate(src):
+        d, sg, dl = oracle.sssp_u64(g, int(s))
+        assert np.array_equal(dist[i], d), f"dist source {s}"
+        assert np.array_equal(sigma[i], sg), f"sigma source {s}"
+        assert rel_err(delta[i], dl) <= 1e-12
+
+
+def test_weighted_overflow_reported(gpu_lib):
+    g = gg.with_constant_weight(gg.grid(35, 35), 2)
+    say("weighted_overflow")
+    with gpu_lib.BC(g) as ctx:
+        ctx.run(np.array([0], np.int32))
+        with pytest.raises(gpu_lib.BCError) as ei:
+            ctx.read()
+        assert ei.value.status == gpu_lib.BC_ERR_OVERFLOW
+
+
+def test_weighted_rmat16_sampled(gpu_lib):
+    """RMAT-16 with weights U{1..255}: a seeded source sample against the oracle."""
+    g = gg.with_uniform_weights(gg.rmat16(), 77, 1, 255)
+    say("weighted_rmat16", g.n, g.m)
+    src = gg.sample_sources(g.n, 96, 77)
+    with gpu_lib.BC(g) as ctx:
+        ctx.run(src)
+        got = ctx.read()
+        dist, sigma, delta = ctx.sssp(src[:6])
+    assert rel_err(got, oracle.bc(g, src, threads=8)) <= 1e-12
+    for i in range(6):
+        d, sg, dl = oracle.sssp_u64(g, int(src[i]))
+        assert np.array_equal(dist[i], d) and np.array_equal(sigma[i], sg)
+        assert rel_err(delta[i], dl) <= 1e-12
