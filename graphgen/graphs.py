@@ -80,8 +80,7 @@ def from_edges(n: int, u, v, weight=None, name: str = "", meta=None) -> Graph:
     order = np.lexsort((cols, rows))
     rows, cols = rows[order], cols[order]
     row_ptr = np.zeros(n + 1, dtype=np.int64)
-    np.add.at(row_ptr, rows + 1, 1)
-    row_ptr = np.cumsum(row_ptr)
+    row_ptr[1:] = np.cumsum(np.bincount(rows, minlength=n))
     if row_ptr[-1] >= 2 ** 31:
         raise ValueError("too many arcs for an int32 CSR")
     wa = None

@@ -119,7 +119,11 @@ typedef struct {
     int32_t vertex_order; /* internal vertex numbering (a device layout choice that
                              results never show): BC_ORDER_DEGREE (default) or
                              BC_ORDER_INPUT */
-    int32_t reserved[6];
+    int32_t arena_log2;   /* weighted graphs: each workgroup files relaxed vertices in
+                             a ring of 2^arena_log2 entries (0 = default, max(4n, 2^16)
+                             rounded up); a source that outgrows it is re-run with a
+                             ring of nnz entries, so results never depend on it */
+    int32_t reserved[5];
 } bc_options;
 
 /* Internal vertex numbering.  BC_ORDER_DEGREE renumbers vertices by

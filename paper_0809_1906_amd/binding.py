@@ -55,7 +55,8 @@ class bc_options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("form", ctypes.c_int), ("batch", ctypes.c_int32),
                 ("device", ctypes.c_int32), ("stream", ctypes.c_void_p), ("allocator", bc_allocator),
                 ("timing", ctypes.c_int32), ("split_degree", ctypes.c_int32),
-                ("vertex_order", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+                ("vertex_order", ctypes.c_int32), ("arena_log2", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
 
 
 class bc_info(ctypes.Structure):
@@ -186,7 +187,10 @@ class _TorchAllocator:
                 return None
 
         def _free(ptr, stream, user):
-            self.torch.cuda.caching_allocator_delete(ptr)
+            try:
+                self.torch.cuda.caching_allocator_delete(ptr)
+            except Exception:  # interpreter shutdown: torch is already gone
+                pass
 
         self.alloc = ALLOC_FN(_alloc)
         self.free = FREE_FN(_free)
@@ -202,7 +206,7 @@ class BC:
 
     def __init__(self, graph, form: str = "auto", batch: int = 0, device: int = 0, stream=None,
                  allocator: str = "torch", timing: bool = False, split_degree: int = 0,
-                 vertex_order: str = "degree"):
+                 vertex_order: str = "degree", arena_log2: int = 0):
         import torch
         load()
         if not torch.cuda.is_available():
@@ -219,6 +223,7 @@ class BC:
         opt.timing = 1 if timing else 0
         opt.split_degree = split_degree
         opt.vertex_order = {"degree": 0, "input": 1}[vertex_order]
+        opt.arena_log2 = arena_log2
         self._alloc = None
         if allocator == "torch":
             self._alloc = _TorchAllocator(device)

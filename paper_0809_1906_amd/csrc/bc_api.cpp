@@ -107,6 +107,8 @@ void release_all(bc_ctx *ctx) {
     if (ctx->status_host) hipHostFree(ctx->status_host);
     if (ctx->sp.any_host) hipHostFree(ctx->sp.any_host);
     if (ctx->al.host) hipHostFree(ctx->al.host);
+    if (ctx->wt.host) hipHostFree(ctx->wt.host);
+    ctx->wt.host = nullptr;
     ctx->al.host = nullptr;
     ctx->status_host = nullptr;
     ctx->sp.any_host = nullptr;
@@ -231,6 +233,8 @@ bc_status bc_create(const bc_graph *g, const bc_options *opt_in, bc_ctx **out) {
         return fail_create(BC_ERR_INVALID_ARG, "batch must be 0 or a multiple of 64 up to 4096");
     if (opt.vertex_order != BC_ORDER_DEGREE && opt.vertex_order != BC_ORDER_INPUT)
         return fail_create(BC_ERR_INVALID_ARG, "unknown vertex_order");
+    if (opt.arena_log2 < 0 || opt.arena_log2 > 30)
+        return fail_create(BC_ERR_INVALID_ARG, "arena_log2 must be in [0, 30]");
     if (opt.split_degree != 0 && opt.split_degree < 64)
         return fail_create(BC_ERR_INVALID_ARG, "split_degree must be 0 (default) or at least 64");
     if ((opt.allocator.alloc == nullptr) != (opt.allocator.free == nullptr))
@@ -330,6 +334,7 @@ bc_status bc_create(const bc_graph *g, const bc_options *opt_in, bc_ctx **out) {
         uw = hw ? iw.data() : nullptr;
     }
     ctx->h_row_ptr.assign(urp, urp + (size_t)n + 1);
+    ctx->wt.arena_log2 = opt.arena_log2;
 
     ctx->row_ptr = (int32_t *)bc_dalloc(ctx, sizeof(int32_t) * ((size_t)n + 1));
     ctx->col = (int32_t *)bc_dalloc(ctx, sizeof(int32_t) * (size_t)std::max(nnz, 1));

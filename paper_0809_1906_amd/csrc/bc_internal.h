@@ -63,14 +63,24 @@ struct AlgebraicState {
 };
 
 // State of the weighted per-source form (bucketed shortest paths).
-struct WeightedState {
-    int32_t groups = 0;
-    int64_t cap = 0;              // arena entries per workgroup
+struct WeightedBuffers {
+    int groups = 0;
+    int64_t cap = 0;              // arena ring entries per workgroup (power of two)
     int32_t *dist = nullptr, *order = nullptr, *gstart = nullptr, *gdist = nullptr, *arena = nullptr;
-    int32_t *bstart = nullptr, *bcount = nullptr;
+    int32_t *bstart = nullptr, *bcount = nullptr, *pstart = nullptr;
     uint64_t *sigma = nullptr;
     double *acc = nullptr;
+};
+struct WeightedState {
+    WeightedBuffers main;         // many workgroups, arena of max(4n, 2^16)
+    WeightedBuffers big;          // few workgroups, arena of nnz (allocated on first need)
     uint32_t *next = nullptr;
+    int32_t *retry = nullptr;     // rows whose live bins outgrew the main arena
+    uint32_t *retry_count = nullptr;
+    uint32_t *host = nullptr;     // pinned
+    int64_t retry_cap = 0;
+    int64_t retried = 0;
+    int32_t arena_log2 = 0;       // requested main arena size (0 = default)
 };
 
 // State of the plain per-source form.

@@ -38,16 +38,20 @@ struct WeightedWork {
     int32_t *order;  // [groups][n]   settled vertices, nondecreasing distance
     int32_t *gstart; // [groups][n+1] distance groups in order[]
     int32_t *gdist;  // [groups][n]
-    int32_t *arena;  // [groups][cap] relaxed vertices, binned per (phase, weight)
-    int32_t *bstart; // [groups][RING][RING]
+    int32_t *arena;  // [groups][cap] ring of relaxed vertices, binned per (phase, weight)
+    int32_t *bstart; // [groups][RING][RING] unwrapped arena position of each bin
     int32_t *bcount; // [groups][RING][RING]
-    int64_t cap;
+    int32_t *pstart; // [groups][RING] unwrapped arena position of each phase's bins
+    int64_t cap;     // arena entries per workgroup, a power of two
+    int32_t *retry;  // sources (positions in the source list) whose live bins outgrew the arena
+    uint32_t *retry_count;
 };
 
 __global__ __launch_bounds__(PB) void k_weighted_sweep(
     int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col, const uint32_t *__restrict__ wt,
-    const int32_t *__restrict__ sources, int64_t count, unsigned long long *next_counter, WeightedWork W,
-    double *bc, uint32_t *status, int accumulate, double *delta_dump, int32_t *dist_dump, uint64_t *sigma_dump) {
+    const int32_t *__restrict__ sources, const int32_t *__restrict__ slot_of, int64_t count,
+    unsigned long long *next_counter, WeightedWork W, double *bc, uint32_t *status, int accumulate,
+    double *delta_dump, int32_t *dist_dump, uint64_t *sigma_dump) {
     __shared__ wg::Chunk ch;
     __shared__ int32_t s_len[PB + 1];
     __shared__ int32_t s_st[PB];
@@ -55,8 +59,8 @@ __global__ __launch_bounds__(PB) void k_weighted_sweep(
     __shared__ int32_t s_cur[RING];
     __shared__ long long s_idx;
     __shared__ int32_t s_nset, s_maxt;
-    __shared__ uint32_t s_ovf;
-    __shared__ long long s_top;
+    __shared__ uint32_t s_ovf, s_abort;
+    __shared__ int32_t s_top;
 
     const int tid = threadIdx.x;
     const size_t g = blockIdx.x;
@@ -69,6 +73,8 @@ __global__ __launch_bounds__(PB) void k_weighted_sweep(
     int32_t *arena = W.arena + g * (size_t)W.cap;
     int32_t *bstart = W.bstart + g * (size_t)RING * RING;
     int32_t *bcount = W.bcount + g * (size_t)RING * RING;
+    int32_t *pstart = W.pstart + g * (size_t)RING;
+    const int32_t cmask = (int32_t)(W.cap - 1);
     auto none = [](int, int32_t) {};
 
     for (;;) {
@@ -77,6 +83,7 @@ __global__ __launch_bounds__(PB) void k_weighted_sweep(
         const long long idx = s_idx;
         if (idx >= count) break;
         const int32_t s = sources[idx];
+        const size_t out = slot_of ? (size_t)slot_of[idx] : (size_t)idx; // row of the per-source outputs
         for (int32_t v = tid; v < n; v += PB) {
             dist[v] = INF;
             sigma[v] = 0;
@@ -88,6 +95,7 @@ __global__ __launch_bounds__(PB) void k_weighted_sweep(
             sigma[s] = 1;
             s_maxt = 0;
             s_ovf = 0;
+            s_abort = 0;
             s_top = 0;
         }
         wg::bar();
@@ -118,7 +126,7 @@ __global__ __launch_bounds__(PB) void k_weighted_sweep(
             } else {
                 for (int i = tid; i < tot; i += PB) {
                     const int k = wg::owner(s_len, i);
-                    const int32_t w = arena[s_st[k] + (i - s_len[k])];
+                    const int32_t w = arena[(s_st[k] + (i - s_len[k])) & cmask];
                     if (dist[w] == d) order[nsettled + atomicAdd(&s_nset, 1)] = w;
                 }
             }
@@ -126,6 +134,7 @@ __global__ __launch_bounds__(PB) void k_weighted_sweep(
             const int32_t cnt = s_nset;
             if (cnt == 0) {
                 if (tid < RING) bcount[slot * RING + tid] = 0;
+                if (tid == 0) pstart[slot] = s_top;
                 wg::bar();
                 continue;
             }
@@ -136,38 +145,43 @@ __global__ __launch_bounds__(PB) void k_weighted_sweep(
             }
             nsettled = le;
             ++ngroups;
-            // (2) counts: pull over predecessors (all settled at smaller distances)
-            if (d > 0) {
-                wg::for_arcs(order, lb, le, rp, ch, none, [&](int, int32_t w, int32_t a) {
-                    const int32_t v = col[a];
-                    const int32_t dv = dist[v];
-                    if (dv != INF && dv + (int32_t)wt[a] == d) {
-                        const uint64_t x = sigma[v];
-                        const uint64_t old = atomicAdd((unsigned long long *)&sigma[w], (unsigned long long)x);
-                        if (old + x < old) s_ovf = 1;
-                    }
-                });
-            }
-            // (3) relax: count improvements per weight, allocate bins, file them
+            // (2) one pass over the settled vertices' arcs: pull counts from
+            // predecessors (all settled at smaller distances) and count, per
+            // weight, the relaxations that would improve a neighbour
             if (tid < RING) s_hist[tid] = 0;
             wg::bar();
-            wg::for_arcs(order, lb, le, rp, ch, none, [&](int, int32_t, int32_t a) {
-                const int32_t x = col[a];
+            wg::for_arcs(order, lb, le, rp, ch, none, [&](int, int32_t w, int32_t a) {
+                const int32_t v = col[a];
                 const int32_t c = (int32_t)wt[a];
-                if (d + c < dist[x]) atomicAdd(&s_hist[c], 1);
+                const int32_t dv = dist[v];
+                if (d > 0 && dv != INF && dv + c == d) {
+                    const uint64_t x = sigma[v];
+                    const uint64_t old = atomicAdd((unsigned long long *)&sigma[w], (unsigned long long)x);
+                    if (old + x < old) s_ovf = 1;
+                }
+                if (d + c < dv) atomicAdd(&s_hist[c], 1);
             });
+            // (3) allocate this phase's bins in the arena ring; the live window
+            // (phases d-255 .. d) must fit, else the source is retried later
             {
                 const int32_t h = tid < RING ? s_hist[tid] : 0;
                 int total;
                 const int pre = wg::block_excl_scan(h, ch.wsum, &total);
-                if (tid < RING) {
-                    bstart[slot * RING + tid] = (int32_t)s_top + pre;
+                const int32_t oldest = d >= RING - 1 ? pstart[(d - (RING - 1)) & (RING - 1)] : 0;
+                if ((int64_t)s_top + total - oldest > W.cap) {
+                    if (tid == 0) s_abort = 1;
+                } else if (tid < RING) {
+                    bstart[slot * RING + tid] = s_top + pre;
                     s_cur[tid] = 0;
                 }
                 __syncthreads();
-                if (tid == 0) s_top += total;
+                if (tid == 0 && !s_abort) {
+                    pstart[slot] = s_top;
+                    s_top += total;
+                }
             }
             wg::bar();
+            if (s_abort) break;
             wg::for_arcs(order, lb, le, rp, ch, none, [&](int, int32_t, int32_t a) {
                 const int32_t x = col[a];
                 const int32_t c = (int32_t)wt[a];
@@ -176,13 +190,18 @@ __global__ __launch_bounds__(PB) void k_weighted_sweep(
                     const int32_t old = atomicMin(&dist[x], nd);
                     if (nd < old) {
                         const int k = atomicAdd(&s_cur[c], 1);
-                        arena[bstart[slot * RING + c] + k] = x;
+                        arena[(bstart[slot * RING + c] + k) & cmask] = x;
                         atomicMax(&s_maxt, nd);
                     }
                 }
             });
             if (tid < RING) bcount[slot * RING + tid] = s_cur[tid];
             wg::bar();
+        }
+        if (s_abort) {
+            if (tid == 0) W.retry[atomicAdd(W.retry_count, 1u)] = (int32_t)out;
+            wg::bar();
+            continue;
         }
         if (tid == 0) gstart[ngroups] = nsettled;
         wg::bar();
@@ -202,7 +221,7 @@ __global__ __launch_bounds__(PB) void k_weighted_sweep(
                 const double sv = (double)sigma[v];
                 const double dl = sv * acc[v];
                 if (accumulate && v != s) unsafeAtomicAdd(&bc[v], dl);
-                if (delta_dump) delta_dump[(size_t)idx * n + v] = dl;
+                if (delta_dump) delta_dump[out * n + v] = dl;
                 acc[v] = (1.0 + dl) / sv;
             }
             wg::bar();
@@ -210,9 +229,9 @@ __global__ __launch_bounds__(PB) void k_weighted_sweep(
         if (dist_dump) {
             for (int32_t v = tid; v < n; v += PB) {
                 const int32_t dv = dist[v];
-                dist_dump[(size_t)idx * n + v] = dv == INF ? -1 : dv;
-                sigma_dump[(size_t)idx * n + v] = dv == INF ? 0 : sigma[v];
-                if (dv == INF) delta_dump[(size_t)idx * n + v] = 0.0;
+                dist_dump[out * n + v] = dv == INF ? -1 : dv;
+                sigma_dump[out * n + v] = dv == INF ? 0 : sigma[v];
+                if (dv == INF) delta_dump[out * n + v] = 0.0;
             }
         }
         if (tid == 0 && s_ovf) atomicOr(status, (uint32_t)BC_DEV_SIGMA_OVERFLOW);
@@ -220,51 +239,127 @@ __global__ __launch_bounds__(PB) void k_weighted_sweep(
     }
 }
 
-WeightedWork work_of(bc_ctx *ctx) {
+bc_status alloc_work(bc_ctx *ctx, WeightedBuffers &b, int64_t cap, int groups) {
+    const size_t n = (size_t)std::max(ctx->n, 1);
+    const size_t G = (size_t)groups;
+    b.groups = groups;
+    b.cap = cap;
+    b.dist = (int32_t *)bc_dalloc(ctx, G * n * 4);
+    b.sigma = (uint64_t *)bc_dalloc(ctx, G * n * 8);
+    b.acc = (double *)bc_dalloc(ctx, G * n * 8);
+    b.order = (int32_t *)bc_dalloc(ctx, G * n * 4);
+    b.gstart = (int32_t *)bc_dalloc(ctx, G * (n + 1) * 4);
+    b.gdist = (int32_t *)bc_dalloc(ctx, G * n * 4);
+    b.arena = (int32_t *)bc_dalloc(ctx, G * (size_t)cap * 4);
+    b.bstart = (int32_t *)bc_dalloc(ctx, G * RING * RING * 4);
+    b.bcount = (int32_t *)bc_dalloc(ctx, G * RING * RING * 4);
+    b.pstart = (int32_t *)bc_dalloc(ctx, G * RING * 4);
+    if (!b.dist || !b.sigma || !b.acc || !b.order || !b.gstart || !b.gdist || !b.arena || !b.bstart || !b.bcount ||
+        !b.pstart)
+        return bc_fail(ctx, BC_ERR_NOMEM, "weighted form: workspace allocation failed");
+    return BC_OK;
+}
+
+size_t per_group_bytes(bc_ctx *ctx, int64_t cap) {
+    const size_t n = (size_t)std::max(ctx->n, 1);
+    return n * (4 + 8 + 8 + 4 + 4 + 4) + 4 + (size_t)cap * 4 + (2 * (size_t)RING + 1) * RING * 4;
+}
+
+int64_t pow2_at_least(int64_t x) {
+    int64_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+WeightedWork work_of(bc_ctx *ctx, const WeightedBuffers &b) {
     WeightedState &w = ctx->wt;
-    return WeightedWork{w.dist, w.sigma, w.acc, w.order, w.gstart, w.gdist, w.arena, w.bstart, w.bcount, w.cap};
+    return WeightedWork{b.dist, b.sigma, b.acc, b.order, b.gstart, b.gdist, b.arena, b.bstart, b.bcount,
+                        b.pstart, b.cap, w.retry, w.retry_count};
 }
 
 } // namespace
 
+// Workgroups get an arena ring of max(4n, 2^16) entries (rounded up to a power
+// of two); a source whose live bins outgrow it is re-run with an arena of nnz
+// entries, which always suffices (a vertex settles once, so at most one entry
+// per arc is ever filed).
 bc_status weighted_prepare(bc_ctx *ctx) {
     WeightedState &w = ctx->wt;
     if (ctx->max_weight > 255)
         return bc_fail(ctx, BC_ERR_UNSUPPORTED, "weighted form: weights above 255 are not supported");
-    const size_t n = (size_t)std::max(ctx->n, 1);
-    w.cap = (int64_t)std::max(ctx->nnz, 1) + 1;
-    const size_t per_group = n * (4 + 8 + 8 + 4 + 4 + 4) + 4 + (size_t)w.cap * 4 + 2 * (size_t)RING * RING * 4;
+    const int64_t cap = w.arena_log2 > 0 ? (int64_t(1) << w.arena_log2)
+                                         : pow2_at_least(std::max<int64_t>(4 * (int64_t)std::max(ctx->n, 1), 1 << 16));
     const size_t budget = size_t(48) << 30;
     int groups = 1024;
-    while (groups > 1 && per_group * (size_t)groups > budget) groups /= 2;
-    w.groups = groups;
-    const size_t G = (size_t)groups;
-    w.dist = (int32_t *)bc_dalloc(ctx, G * n * 4);
-    w.sigma = (uint64_t *)bc_dalloc(ctx, G * n * 8);
-    w.acc = (double *)bc_dalloc(ctx, G * n * 8);
-    w.order = (int32_t *)bc_dalloc(ctx, G * n * 4);
-    w.gstart = (int32_t *)bc_dalloc(ctx, G * (n + 1) * 4);
-    w.gdist = (int32_t *)bc_dalloc(ctx, G * n * 4);
-    w.arena = (int32_t *)bc_dalloc(ctx, G * (size_t)w.cap * 4);
-    w.bstart = (int32_t *)bc_dalloc(ctx, G * RING * RING * 4);
-    w.bcount = (int32_t *)bc_dalloc(ctx, G * RING * RING * 4);
+    while (groups > 1 && per_group_bytes(ctx, cap) * (size_t)groups > budget) groups /= 2;
+    bc_status st = alloc_work(ctx, w.main, cap, groups);
+    if (st != BC_OK) return st;
     w.next = (uint32_t *)bc_dalloc(ctx, 256);
-    if (!w.dist || !w.sigma || !w.acc || !w.order || !w.gstart || !w.gdist || !w.arena || !w.bstart || !w.bcount ||
-        !w.next)
-        return bc_fail(ctx, BC_ERR_NOMEM, "weighted form: workspace allocation failed");
+    w.retry_count = (uint32_t *)bc_dalloc(ctx, 256);
+    w.retry = (int32_t *)bc_dalloc(ctx, (size_t)4096 * 4);
+    w.retry_cap = 4096;
+    if (!w.next || !w.retry_count || !w.retry || hipHostMalloc((void **)&w.host, 256) != hipSuccess)
+        return bc_fail(ctx, BC_ERR_NOMEM, "weighted form: allocation failed");
+    return BC_OK;
+}
+
+static bc_status launch(bc_ctx *ctx, const WeightedBuffers &b, const int32_t *d_sources, const int32_t *slot_of,
+                        int64_t count, bool accumulate, double *delta_dump, int32_t *dist_dump, uint64_t *sigma_dump) {
+    WeightedState &w = ctx->wt;
+    BC_HIP(ctx, hipMemsetAsync(w.next, 0, sizeof(unsigned long long), ctx->stream));
+    const int grid = (int)std::min<int64_t>(count, b.groups);
+    LaunchTimer t(ctx, "weighted_sweep");
+    hipLaunchKernelGGL(k_weighted_sweep, dim3(grid), dim3(PB), 0, ctx->stream, ctx->n, ctx->row_ptr, ctx->col,
+                       ctx->weight, d_sources, slot_of, count, (unsigned long long *)w.next, work_of(ctx, b),
+                       ctx->bc, ctx->status, accumulate ? 1 : 0, delta_dump, dist_dump, sigma_dump);
+    t.done();
+    BC_HIP(ctx, hipGetLastError());
     return BC_OK;
 }
 
 bc_status weighted_run(bc_ctx *ctx, const int32_t *d_sources, int64_t count, bool accumulate,
                        double *delta_dump, int32_t *dist_dump, uint64_t *sigma_dump) {
     WeightedState &w = ctx->wt;
-    BC_HIP(ctx, hipMemsetAsync(w.next, 0, sizeof(unsigned long long), ctx->stream));
-    const int grid = (int)std::min<int64_t>(count, w.groups);
-    LaunchTimer t(ctx, "weighted_sweep");
-    hipLaunchKernelGGL(k_weighted_sweep, dim3(grid), dim3(PB), 0, ctx->stream, ctx->n, ctx->row_ptr, ctx->col,
-                       ctx->weight, d_sources, count, (unsigned long long *)w.next, work_of(ctx), ctx->bc, ctx->status,
-                       accumulate ? 1 : 0, delta_dump, dist_dump, sigma_dump);
-    t.done();
-    BC_HIP(ctx, hipGetLastError());
+    // the retry list holds at most one entry per source in flight: run in chunks
+    for (int64_t c0 = 0; c0 < count; c0 += w.retry_cap) {
+        const int64_t cnt = std::min<int64_t>(w.retry_cap, count - c0);
+        BC_HIP(ctx, hipMemsetAsync(w.retry_count, 0, sizeof(uint32_t), ctx->stream));
+        // per-source output rows are positions in the whole list
+        bc_status st = launch(ctx, w.main, d_sources + c0, nullptr, cnt, accumulate,
+                              delta_dump ? delta_dump + (size_t)c0 * ctx->n : nullptr,
+                              dist_dump ? dist_dump + (size_t)c0 * ctx->n : nullptr,
+                              sigma_dump ? sigma_dump + (size_t)c0 * ctx->n : nullptr);
+        if (st != BC_OK) return st;
+        BC_HIP(ctx, hipMemcpyAsync(w.host, w.retry_count, sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->stream));
+        BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        const uint32_t nretry = *w.host;
+        if (nretry == 0) continue;
+        if (!w.big.dist) {
+            const int64_t cap = pow2_at_least((int64_t)std::max(ctx->nnz, 1) + 1);
+            int groups = 64;
+            while (groups > 1 && per_group_bytes(ctx, cap) * (size_t)groups > (size_t(16) << 30)) groups /= 2;
+            st = alloc_work(ctx, w.big, cap, groups);
+            if (st != BC_OK) return st;
+        }
+        // sources of the retried rows, gathered on the host
+        std::vector<int32_t> rows(nretry), srcs(nretry);
+        BC_HIP(ctx, hipMemcpy(rows.data(), w.retry, nretry * sizeof(int32_t), hipMemcpyDeviceToHost));
+        std::vector<int32_t> all((size_t)cnt);
+        BC_HIP(ctx, hipMemcpy(all.data(), d_sources + c0, (size_t)cnt * sizeof(int32_t), hipMemcpyDeviceToHost));
+        for (uint32_t i = 0; i < nretry; ++i) srcs[i] = all[(size_t)rows[i]];
+        int32_t *dev = (int32_t *)bc_dalloc(ctx, 2 * (size_t)nretry * sizeof(int32_t));
+        if (!dev) return bc_fail(ctx, BC_ERR_NOMEM, "weighted form: retry allocation failed");
+        BC_HIP(ctx, hipMemcpy(dev, srcs.data(), nretry * sizeof(int32_t), hipMemcpyHostToDevice));
+        BC_HIP(ctx, hipMemcpy(dev + nretry, rows.data(), nretry * sizeof(int32_t), hipMemcpyHostToDevice));
+        BC_HIP(ctx, hipMemsetAsync(w.retry_count, 0, sizeof(uint32_t), ctx->stream));
+        st = launch(ctx, w.big, dev, dev + nretry, nretry, accumulate,
+                    delta_dump ? delta_dump + (size_t)c0 * ctx->n : nullptr,
+                    dist_dump ? dist_dump + (size_t)c0 * ctx->n : nullptr,
+                    sigma_dump ? sigma_dump + (size_t)c0 * ctx->n : nullptr);
+        BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        bc_dfree(ctx, dev);
+        if (st != BC_OK) return st;
+        ctx->wt.retried += nretry;
+    }
     return BC_OK;
 }

@@ -319,3 +319,21 @@ def test_weighted_rmat16_sampled(gpu_lib):
         d, sg, dl = oracle.sssp_u64(g, int(src[i]))
         assert np.array_equal(dist[i], d) and np.array_equal(sigma[i], sg)
         assert rel_err(delta[i], dl) <= 1e-12
+
+
+@pytest.mark.parametrize("log2", [6, 9])
+def test_weighted_arena_retry(gpu_lib, log2):
+    """A tiny relaxation ring forces sources onto the full-size re-run path;
+    results must not change."""
+    g = gg.with_uniform_weights(gg.er_plus_tree(800, 8.0, 21), 21, 1, 255)
+    say("weighted_retry", log2)
+    src = np.arange(0, g.n, 3, dtype=np.int32)
+    with gpu_lib.BC(g, arena_log2=log2) as ctx:
+        ctx.run(src)
+        got = ctx.read()
+        dist, sigma, delta = ctx.sssp(src[:5])
+    assert rel_err(got, oracle.bc(g, src)) <= 1e-12
+    for i in range(5):
+        d, sg, dl = oracle.sssp_u64(g, int(src[i]))
+        assert np.array_equal(dist[i], d) and np.array_equal(sigma[i], sg)
+        assert rel_err(delta[i], dl) <= 1e-12
