@@ -235,38 +235,35 @@ def watts_strogatz(n: int, k: int, p: float, seed: int, name: str = "") -> Graph
     i-major for j = 1..k/2, is rewired with probability p to (i, x) where x is
     uniform over vertices that are neither i nor already adjacent to i."""
     half = k // 2
-    adj = [set() for _ in range(n)]
-    for i in range(n):
-        for j in range(1, half + 1):
-            t = (i + j) % n
-            adj[i].add(t)
-            adj[t].add(i)
+    i = np.repeat(np.arange(n, dtype=np.int64), half)
+    t = (i + np.tile(np.arange(1, half + 1, dtype=np.int64), n)) % n
+    lo, hi = np.minimum(i, t), np.maximum(i, t)
+    edges = set((lo * n + hi).tolist())
+    deg = np.bincount(np.concatenate([lo, hi]), minlength=n) if n else np.zeros(0, np.int64)
+    deg = deg.tolist()
     s = Stream(substream(seed, 0x3A))
-    coins = s.doubles(n * half) < p
-    order = [(i, j) for i in range(n) for j in range(1, half + 1)]
-    for idx in np.flatnonzero(coins):
-        i, j = order[idx]
-        t = (i + j) % n
-        if t not in adj[i]:
-            continue  # this lattice edge was already rewired away from i's side
-        if len(adj[i]) >= n - 1:
+    coins = np.flatnonzero(s.doubles(n * half) < p)
+    cand = s.bounded(np.full(max(4 * coins.size, 16), max(n, 1))).tolist()
+    ci = 0
+    for idx in coins.tolist():
+        a, b = int(i[idx]), int(t[idx])
+        key = min(a, b) * n + max(a, b)
+        if key not in edges or deg[a] >= n - 1:
             continue
         while True:
-            x = int(s.bounded([n])[0])
-            if x != i and x not in adj[i]:
+            if ci == len(cand):
+                cand = s.bounded(np.full(len(cand), n)).tolist()
+                ci = 0
+            x = cand[ci]
+            ci += 1
+            if x != a and (min(a, x) * n + max(a, x)) not in edges:
                 break
-        adj[i].discard(t)
-        adj[t].discard(i)
-        adj[i].add(x)
-        adj[x].add(i)
-    us, vs = [], []
-    for i in range(n):
-        for t in adj[i]:
-            if i < t:
-                us.append(i)
-                vs.append(t)
-    return from_edges(n, np.array(us, dtype=np.int64), np.array(vs, dtype=np.int64),
-                      name=name or f"ws{n}-k{k}-p{p:g}")
+        edges.discard(key)
+        deg[b] -= 1
+        edges.add(min(a, x) * n + max(a, x))
+        deg[x] += 1
+    keys = np.fromiter(edges, dtype=np.int64, count=len(edges))
+    return from_edges(n, keys // max(n, 1), keys % max(n, 1), name=name or f"ws{n}-k{k}-p{p:g}")
 
 
 def sample_sources(n: int, count: int, seed: int) -> np.ndarray:

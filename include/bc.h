@@ -68,7 +68,8 @@ typedef enum {
     BC_FORM_AUTO = 0,
     BC_FORM_PLAIN_FP64 = 1,
     BC_FORM_SPARSE = 2,
-    BC_FORM_ALGEBRAIC = 3
+    BC_FORM_ALGEBRAIC = 3,
+    BC_FORM_MANY = 5 /* reported by bc_get_info for bc_create_many contexts */
 } bc_form;
 
 /*
@@ -144,6 +145,22 @@ void bc_options_init(bc_options *opt);
  * algebraic form), BC_ERR_NOMEM, BC_ERR_DEVICE.
  */
 bc_status bc_create(const bc_graph *g, const bc_options *opt, bc_ctx **out);
+
+/*
+ * Many small graphs in one context, for all-source BC of every graph.
+ *   gs[0..count)  unweighted graphs in host memory (mem = BC_MEM_HOST), each
+ *                 satisfying the bc_graph model with at most 4096 vertices
+ * The graphs are concatenated: vertex v of graph g has id
+ * (n_0 + ... + n_{g-1}) + v, and bc_read returns BC in that numbering
+ * (sum of n_g doubles).  opt->batch, when nonzero, is the number of sources
+ * one work unit takes (default 64).  bc_run accepts only "every vertex"
+ * (NULL, -1): it runs one persistent launch over a work queue of
+ * (graph, source range) units, largest graphs first, recorded once into a HIP
+ * graph and replayed.  bc_read_sssp takes ids in the concatenated numbering.
+ * Errors: as bc_create; BC_ERR_UNSUPPORTED for weights or a graph above 4096
+ * vertices.
+ */
+bc_status bc_create_many(const bc_graph *gs, int32_t count, const bc_options *opt, bc_ctx **out);
 
 /*
  * Adds, for every entry s of `sources`, the dependencies delta_s*(v) of

@@ -4,7 +4,7 @@ The computation lives in the HIP library libbc.so behind the C ABI of
 include/bc.h; this package only binds it.  Importing never falls back to a
 CPU path: without the built library, :func:`load` raises.
 """
-from .binding import (BC, BCError, FORMS, bc_create, bc_destroy, bc_get_info, bc_get_timing,  # noqa: F401
+from .binding import (BC, BCError, FORMS, bc_create, bc_create_many, bc_destroy, bc_get_info, bc_get_timing,  # noqa: F401
                       bc_last_error, bc_options_init, bc_read, bc_read_sssp, bc_reset, bc_run,
                       bc_status_string, load, LIB_PATH, SIGNATURES)
 from .binding import (BC_OK, BC_ERR_INVALID_ARG, BC_ERR_INVALID_GRAPH, BC_ERR_NOMEM,  # noqa: F401

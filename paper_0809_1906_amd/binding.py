@@ -34,6 +34,7 @@ BC_FORM_AUTO = 0
 BC_FORM_PLAIN_FP64 = 1
 BC_FORM_SPARSE = 2
 BC_FORM_ALGEBRAIC = 3
+BC_FORM_MANY = 5
 FORMS = {"auto": BC_FORM_AUTO, "plain": BC_FORM_PLAIN_FP64, "sparse": BC_FORM_SPARSE,
          "algebraic": BC_FORM_ALGEBRAIC}
 
@@ -70,6 +71,8 @@ class bc_info(ctypes.Structure):
 SIGNATURES = {
     "bc_options_init": (None, [ctypes.POINTER(bc_options)]),
     "bc_create": (ctypes.c_int, [ctypes.POINTER(bc_graph), ctypes.POINTER(bc_options), ctypes.POINTER(ctypes.c_void_p)]),
+    "bc_create_many": (ctypes.c_int, [ctypes.POINTER(bc_graph), ctypes.c_int32, ctypes.POINTER(bc_options),
+                                      ctypes.POINTER(ctypes.c_void_p)]),
     "bc_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int]),
     "bc_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
     "bc_reset": (ctypes.c_int, [ctypes.c_void_p]),
@@ -125,6 +128,14 @@ def bc_create(graph: bc_graph, options: Optional[bc_options]) -> ctypes.c_void_p
     ctx = ctypes.c_void_p()
     st = load().bc_create(ctypes.byref(graph), ctypes.byref(options) if options is not None else None,
                           ctypes.byref(ctx))
+    _check(st, None)
+    return ctx
+
+
+def bc_create_many(graphs, count: int, options: Optional[bc_options]) -> ctypes.c_void_p:
+    ctx = ctypes.c_void_p()
+    st = load().bc_create_many(graphs, count, ctypes.byref(options) if options is not None else None,
+                               ctypes.byref(ctx))
     _check(st, None)
     return ctx
 
@@ -200,6 +211,7 @@ class BC:
     """A context on one graph.
 
     >>> ctx = BC(graph, form="sparse")        # graph: object with n, row_ptr, col, weight
+    >>> many = BC([g0, g1, g2])               # a list: one context over many small graphs
     >>> ctx.run()                              # every source
     >>> bc = ctx.read()                        # numpy float64[n], ordered pairs
     """
@@ -213,7 +225,7 @@ class BC:
             raise RuntimeError("no GPU visible: the betweenness library needs an MI355X")
         self.torch = torch
         self.device = device
-        self.n = int(graph.n)
+        self.n = int(sum(g.n for g in graph)) if isinstance(graph, (list, tuple)) else int(graph.n)
         self._stream = stream if stream is not None else torch.cuda.current_stream(device)
         opt = bc_options_init()
         opt.form = FORMS[form]
@@ -229,19 +241,26 @@ class BC:
             self._alloc = _TorchAllocator(device)
             opt.allocator.alloc = self._alloc.alloc
             opt.allocator.free = self._alloc.free
-        rp = np.ascontiguousarray(graph.row_ptr, dtype=np.int32)
-        col = np.ascontiguousarray(graph.col, dtype=np.int32)
-        w = None if graph.weight is None else np.ascontiguousarray(graph.weight, dtype=np.uint32)
-        g = bc_graph()
-        g.n = self.n
-        g.nnz = int(col.size)
-        g.row_ptr = rp.ctypes.data
-        g.col = col.ctypes.data if col.size else None
-        g.weight = w.ctypes.data if w is not None and w.size else None
-        g.mem = BC_MEM_HOST
         self._ctx = None
+        graphs = graph if isinstance(graph, (list, tuple)) else [graph]
+        keep = []
+        arr = (bc_graph * max(len(graphs), 1))()
+        for i, gr in enumerate(graphs):
+            rp = np.ascontiguousarray(gr.row_ptr, dtype=np.int32)
+            col = np.ascontiguousarray(gr.col, dtype=np.int32)
+            w = None if gr.weight is None else np.ascontiguousarray(gr.weight, dtype=np.uint32)
+            keep.append((rp, col, w))
+            arr[i].n = int(gr.n)
+            arr[i].nnz = int(col.size)
+            arr[i].row_ptr = rp.ctypes.data
+            arr[i].col = col.ctypes.data if col.size else None
+            arr[i].weight = w.ctypes.data if w is not None and w.size else None
+            arr[i].mem = BC_MEM_HOST
         with torch.cuda.device(device):
-            self._ctx = bc_create(g, opt)
+            if isinstance(graph, (list, tuple)):
+                self._ctx = bc_create_many(arr, len(graphs), opt)
+            else:
+                self._ctx = bc_create(arr[0], opt)
 
     # -- lifecycle --
     def close(self):

@@ -95,6 +95,13 @@ void release_all(bc_ctx *ctx) {
     if (!ctx) return;
     if (ctx->device >= 0) hipSetDevice(ctx->device);
     hipStreamSynchronize(ctx->stream);
+    if (ctx->mg.stream) hipStreamSynchronize(ctx->mg.stream);
+    if (ctx->mg.exec) hipGraphExecDestroy(ctx->mg.exec);
+    if (ctx->mg.ev) hipEventDestroy(ctx->mg.ev);
+    if (ctx->mg.stream) hipStreamDestroy(ctx->mg.stream);
+    ctx->mg.exec = nullptr;
+    ctx->mg.ev = nullptr;
+    ctx->mg.stream = nullptr;
     for (auto &kv : ctx->timers)
         for (auto &pr : kv.second.pending) {
             hipEventDestroy(pr.first);
@@ -379,6 +386,98 @@ bc_status bc_create(const bc_graph *g, const bc_options *opt_in, bc_ctx **out) {
     return BC_OK;
 }
 
+
+bc_status bc_create_many(const bc_graph *gs, int32_t count, const bc_options *opt_in, bc_ctx **out) {
+    if (!out) return fail_create(BC_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (count < 0 || (count > 0 && !gs)) return fail_create(BC_ERR_INVALID_ARG, "bad graph list");
+    bc_options opt;
+    bc_options_init(&opt);
+    if (opt_in) {
+        if (opt_in->struct_size != sizeof(bc_options))
+            return fail_create(BC_ERR_INVALID_ARG, "bc_options.struct_size mismatch (call bc_options_init)");
+        opt = *opt_in;
+    }
+    if (opt.batch < 0) return fail_create(BC_ERR_INVALID_ARG, "batch must be >= 0");
+    if ((opt.allocator.alloc == nullptr) != (opt.allocator.free == nullptr))
+        return fail_create(BC_ERR_INVALID_ARG, "allocator needs both alloc and free, or neither");
+    // host validation of every graph, then the concatenated layout
+    std::vector<int32_t> voff(1, 0), rpoff, rp, col;
+    int64_t total_n = 0, total_arcs = 0;
+    int32_t max_deg = 0;
+    for (int32_t g = 0; g < count; ++g) {
+        const bc_graph &G = gs[g];
+        char buf[160];
+        if (G.mem != BC_MEM_HOST) return fail_create(BC_ERR_INVALID_ARG, "bc_create_many takes host graphs");
+        if (G.n < 0 || G.nnz < 0 || !G.row_ptr || (G.nnz > 0 && !G.col)) {
+            snprintf(buf, sizeof buf, "graph %d: bad arrays", g);
+            return fail_create(BC_ERR_INVALID_ARG, buf);
+        }
+        if (G.weight) return fail_create(BC_ERR_UNSUPPORTED, "bc_create_many takes unweighted graphs");
+        if (G.n > MG_MAX_N) {
+            snprintf(buf, sizeof buf, "graph %d has %d vertices; at most %d are supported", g, G.n, MG_MAX_N);
+            return fail_create(BC_ERR_UNSUPPORTED, buf);
+        }
+        std::string msg;
+        int32_t md = 0;
+        uint32_t mw = 1;
+        bc_status vs = validate_graph(G.n, G.nnz, G.row_ptr, G.col, nullptr, msg, md, mw);
+        if (vs != BC_OK) {
+            snprintf(buf, sizeof buf, "graph %d: ", g);
+            return fail_create(vs, buf + msg);
+        }
+        max_deg = std::max(max_deg, md);
+        if (total_n + G.n >= (int64_t(1) << 31) || total_arcs + G.nnz >= (int64_t(1) << 31))
+            return fail_create(BC_ERR_INVALID_GRAPH, "the graphs together exceed 2^31 vertices or arcs");
+        rpoff.push_back((int32_t)rp.size());
+        for (int32_t v = 0; v <= G.n; ++v) rp.push_back((int32_t)total_arcs + G.row_ptr[v]);
+        col.insert(col.end(), G.col, G.col + G.nnz);
+        total_n += G.n;
+        total_arcs += G.nnz;
+        voff.push_back((int32_t)total_n);
+    }
+    bc_ctx *ctx = new (std::nothrow) bc_ctx();
+    if (!ctx) return fail_create(BC_ERR_NOMEM, "host allocation of the context failed");
+    ctx->n = (int32_t)total_n;
+    ctx->nnz = (int32_t)total_arcs;
+    ctx->max_degree = max_deg;
+    ctx->stream = (hipStream_t)opt.stream;
+    ctx->alloc = opt.allocator;
+    ctx->timing = opt.timing != 0;
+    ctx->form = BC_FORM_MANY;
+    ctx->many = true;
+    auto bail = [&](bc_status s, const std::string &m) {
+        release_all(ctx);
+        delete ctx;
+        return fail_create(s, m);
+    };
+    int dev = opt.device;
+    if (dev < 0 && hipGetDevice(&dev) != hipSuccess) return bail(BC_ERR_DEVICE, "hipGetDevice failed");
+    if (hipSetDevice(dev) != hipSuccess) return bail(BC_ERR_DEVICE, "hipSetDevice failed");
+    ctx->device = dev;
+    if (hipStreamCreateWithFlags(&ctx->mg.stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->mg.ev, hipEventDisableTiming) != hipSuccess)
+        return bail(BC_ERR_DEVICE, "stream creation failed");
+    const size_t nn = (size_t)std::max<int64_t>(total_n, 1);
+    ctx->col = (int32_t *)bc_dalloc(ctx, sizeof(int32_t) * (size_t)std::max<int64_t>(total_arcs, 1));
+    ctx->bc = (double *)bc_dalloc(ctx, sizeof(double) * nn);
+    ctx->bc_scratch = (double *)bc_dalloc(ctx, sizeof(double) * nn);
+    ctx->status = (uint32_t *)bc_dalloc(ctx, 256);
+    if (!ctx->col || !ctx->bc || !ctx->bc_scratch || !ctx->status ||
+        hipHostMalloc((void **)&ctx->status_host, 256) != hipSuccess)
+        return bail(BC_ERR_NOMEM, "device allocation failed");
+    if ((total_arcs > 0 &&
+         hipMemcpy(ctx->col, col.data(), sizeof(int32_t) * (size_t)total_arcs, hipMemcpyHostToDevice) != hipSuccess) ||
+        hipMemsetAsync(ctx->bc, 0, sizeof(double) * nn, ctx->stream) != hipSuccess ||
+        hipMemsetAsync(ctx->status, 0, 256, ctx->stream) != hipSuccess)
+        return bail(BC_ERR_DEVICE, "uploading the graphs failed");
+    bc_status ps = multigraph_prepare(ctx, voff, rpoff, rp, opt.batch);
+    if (ps != BC_OK) return bail(ps, ctx->err);
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) return bail(BC_ERR_DEVICE, "stream synchronisation failed");
+    *out = ctx;
+    return BC_OK;
+}
+
 static bc_status stage_sources(bc_ctx *ctx, const int32_t *sources, int64_t count, bc_mem mem,
                                const int32_t **d_out, int64_t *count_out) {
     if (count == -1 && sources == nullptr) count = ctx->n;
@@ -443,6 +542,13 @@ bc_status bc_run(bc_ctx *ctx, const int32_t *sources, int64_t count, bc_mem mem)
     bc_status s = check_usable(ctx);
     if (s != BC_OK) return s;
     if (ctx->overflow_seen) return bc_fail(ctx, BC_ERR_OVERFLOW, "an earlier run overflowed a path count; call bc_reset");
+    if (ctx->many) {
+        if (sources != nullptr || count != -1)
+            return bc_fail(ctx, BC_ERR_UNSUPPORTED, "a many-graph context runs every source: pass NULL, -1");
+        s = multigraph_run(ctx);
+        if (s == BC_OK) ctx->sources_run += ctx->n;
+        return s;
+    }
     const int32_t *d_src = nullptr;
     int64_t cnt = 0;
     s = stage_sources(ctx, sources, count, mem, &d_src, &cnt);
@@ -492,7 +598,7 @@ bc_status bc_read_sssp(bc_ctx *ctx, const int32_t *sources, int32_t count,
     if (!ctx) return BC_ERR_INVALID_ARG;
     bc_status s = check_usable(ctx);
     if (s != BC_OK) return s;
-    int32_t maxc = ctx->form == BC_FORM_PLAIN_FP64 ? 4096 : ctx->sp.batch;
+    int32_t maxc = ctx->many ? 64 : ctx->form == BC_FORM_PLAIN_FP64 ? 4096 : ctx->sp.batch;
     if (!sources || count < 1 || count > maxc) return bc_fail(ctx, BC_ERR_INVALID_ARG, "count must be in [1, batch]");
     const int32_t *d_src = nullptr;
     int64_t cnt = 0;
@@ -515,7 +621,8 @@ bc_status bc_read_sssp(bc_ctx *ctx, const int32_t *sources, int32_t count,
     BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
     uint32_t before = *ctx->status_host;
     BC_HIP(ctx, hipMemsetAsync(ctx->status, 0, sizeof(uint32_t), ctx->stream));
-    if (ctx->form == BC_FORM_PLAIN_FP64) s = plain_run(ctx, d_src, count, false, dl, dd, ds);
+    if (ctx->many) s = multigraph_dump(ctx, sources, count, dd, ds, dl);
+    else if (ctx->form == BC_FORM_PLAIN_FP64) s = plain_run(ctx, d_src, count, false, dl, dd, ds);
     else s = sparse_dump(ctx, d_src, count, dd, ds, dl);
     if (s != BC_OK) { cleanup(); return s; }
     BC_HIP(ctx, hipMemcpyAsync(ctx->status_host, ctx->status, sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->stream));
@@ -546,7 +653,7 @@ bc_status bc_get_info(const bc_ctx *ctx, bc_info *out) {
     out->max_degree = ctx->max_degree;
     out->weighted = ctx->weighted ? 1 : 0;
     out->form = ctx->form;
-    out->batch = ctx->form == BC_FORM_PLAIN_FP64 ? 1 : ctx->sp.batch;
+    out->batch = ctx->many ? ctx->mg.chunk : ctx->form == BC_FORM_PLAIN_FP64 ? 1 : ctx->sp.batch;
     out->max_levels = ctx->max_levels;
     out->sources_run = ctx->sources_run;
     out->device_bytes = ctx->device_bytes;

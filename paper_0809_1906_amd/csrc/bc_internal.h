@@ -83,6 +83,18 @@ struct WeightedState {
     int32_t arena_log2 = 0;       // requested main arena size (0 = default)
 };
 
+// State of a many-graph context (bc_create_many).
+constexpr int MG_MAX_N = 4096; // largest graph a many-graph context takes
+struct MultiState {
+    int32_t ngraphs = 0, nunits = 0, chunk = 64, grid = 0;
+    int32_t *voff = nullptr, *rpoff = nullptr, *rp = nullptr, *units = nullptr;
+    unsigned int *next = nullptr;
+    std::vector<int32_t> h_voff;
+    hipStream_t stream = nullptr;     // private stream the launch is captured on
+    hipEvent_t ev = nullptr;
+    hipGraphExec_t exec = nullptr;    // captured reset + persistent sweep
+};
+
 // State of the plain per-source form.
 struct PlainState {
     int32_t groups = 0;       // persistent workgroups
@@ -129,6 +141,8 @@ struct bc_ctx {
     AlgebraicState al;
     PlainState pl;
     WeightedState wt;
+    MultiState mg;
+    bool many = false;
 
     // bookkeeping
     int64_t sources_run = 0;
@@ -175,6 +189,12 @@ bc_status plain_run(bc_ctx *ctx, const int32_t *d_sources, int64_t count, bool a
 bc_status weighted_prepare(bc_ctx *ctx);
 bc_status weighted_run(bc_ctx *ctx, const int32_t *d_sources, int64_t count, bool accumulate,
                        double *delta_dump, int32_t *dist_dump, uint64_t *sigma_dump);
+
+bc_status multigraph_prepare(bc_ctx *ctx, const std::vector<int32_t> &voff, const std::vector<int32_t> &rpoff,
+                             const std::vector<int32_t> &rp, int32_t chunk);
+bc_status multigraph_run(bc_ctx *ctx);
+bc_status multigraph_dump(bc_ctx *ctx, const int32_t *h_sources, int32_t count, int32_t *dist_dump,
+                          uint64_t *sigma_dump, double *delta_dump);
 
 bc_status sparse_prepare(bc_ctx *ctx, int32_t batch, int32_t split_degree);
 bc_status algebraic_prepare(bc_ctx *ctx);

@@ -1,0 +1,300 @@
+// Many small graphs in one persistent launch.
+//
+// A context built by bc_create_many holds up to millions of small unweighted
+// graphs (each with at most MG_MAX_N vertices) concatenated: vertex v of graph
+// g has global id voff[g] + v, and BC is returned in that numbering.  bc_run
+// computes all-source BC of every graph (Brandes's algorithm, Sec. 1.1, per
+// graph).
+//
+// The work is a device queue of units (graph, [s0, s1) of its sources) sorted
+// by n_g^2 descending, largest first (longest-processing-time order).  A grid
+// of persistent 512-thread workgroups pulls units with an atomic counter and
+// exits when the queue is drained.  For each source the workgroup runs the
+// level-synchronous forward sweep (distance, exact uint64 counts) and the
+// backward sweep (c(v) = (1 + delta(v)) / lambda(v) in FP32, sums in FP64)
+// entirely in LDS; each unit's dependencies are summed in an FP64 LDS vector
+// and added to BC once per unit.  The launch (a queue-counter reset kernel and
+// the persistent kernel) is captured once into a HIP graph and replayed.
+#include "bc_internal.h"
+
+#include <algorithm>
+
+namespace {
+
+constexpr int MT = 512;          // threads per workgroup
+constexpr int32_t MG_INF = 0x7FFFFFFF;
+constexpr int ABURST = 8;        // column reads issued together per vertex
+
+struct MultiArgs {
+    const int32_t *voff;   // [ngraphs+1] first global vertex of each graph
+    const int32_t *rpoff;  // [ngraphs] where graph g's row offsets start in rp
+    const int32_t *rp;     // concatenated per-graph row offsets (global arc indices)
+    const int32_t *col;    // concatenated arcs, local vertex ids
+    const int32_t *units;  // [nunits][3] = (graph, s0, s1), local source ids
+    int32_t nunits;
+    unsigned int *next;    // queue counter
+    double *bc;            // [sum n]
+    uint32_t *status;
+    // per-source readout (bc_read_sssp): unit u covers one source, row u
+    int32_t dump_n;        // sum n (row length); 0 = no readout
+    int32_t *dist_dump;
+    uint64_t *sigma_dump;
+    double *delta_dump;
+};
+
+__global__ void k_mg_reset(unsigned int *next) { *next = 0; }
+
+__global__ __launch_bounds__(MT) void k_mg_sweep(MultiArgs a) {
+    __shared__ int32_t s_dist[MG_MAX_N];
+    __shared__ unsigned long long s_sig[MG_MAX_N];
+    __shared__ float s_c[MG_MAX_N];
+    __shared__ int32_t s_queue[MG_MAX_N];
+    __shared__ int32_t s_lev[MG_MAX_N + 2];
+    __shared__ double s_bc[MG_MAX_N];
+    __shared__ int32_t s_rp[MG_MAX_N + 1]; // the unit's graph: row offsets relative to its first arc
+    __shared__ int32_t s_unit, s_cnt[3];
+    __shared__ uint32_t s_ovf;
+
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) s_unit = (int32_t)atomicAdd(a.next, 1u);
+        __syncthreads();
+        const int32_t u = s_unit;
+        if (u >= a.nunits) break;
+        const int32_t g = a.units[3 * u], s0 = a.units[3 * u + 1], s1 = a.units[3 * u + 2];
+        const int32_t vo = a.voff[g], n = a.voff[g + 1] - vo;
+        const int32_t *grp = a.rp + a.rpoff[g];
+        const int32_t *col = a.col + grp[0];
+        for (int32_t v = tid; v <= n; v += MT) s_rp[v] = grp[v] - grp[0];
+        for (int32_t v = tid; v < n; v += MT) s_bc[v] = 0.0;
+        if (tid == 0) s_ovf = 0;
+        __syncthreads();
+        for (int32_t s = s0; s < s1; ++s) {
+            for (int32_t v = tid; v < n; v += MT) {
+                s_dist[v] = v == s ? 0 : MG_INF;
+                s_sig[v] = v == s ? 1ull : 0ull;
+            }
+            if (tid == 0) {
+                s_queue[0] = s;
+                s_lev[0] = 0;
+                s_lev[1] = 1;
+                s_cnt[0] = 0;
+                s_cnt[1] = 0;
+                s_cnt[2] = 0;
+            }
+            __syncthreads();
+            // forward: level L spans queue[qb, qe); appends of level L go to
+            // queue[qe + s_cnt[L % 3]].  Three counters let one barrier per
+            // level suffice: while level L appends to s_cnt[L % 3], thread 0
+            // clears s_cnt[(L + 1) % 3], last read before the previous barrier.
+            int32_t qb = 0, qe = 1, L = 0;
+            while (qb < qe) {
+                const int cur = L % 3;
+                if (tid == 0) s_cnt[(L + 1) % 3] = 0;
+                for (int32_t i = qb + tid; i < qe; i += MT) {
+                    const int32_t v = s_queue[i];
+                    const unsigned long long sv = s_sig[v];
+                    const int32_t rb = s_rp[v], re = s_rp[v + 1];
+                    for (int32_t e0 = rb; e0 < re; e0 += ABURST) {
+                        int32_t ws[ABURST]; // one burst of column reads in flight
+#pragma unroll
+                        for (int j = 0; j < ABURST; ++j) ws[j] = e0 + j < re ? col[e0 + j] : -1;
+#pragma unroll
+                        for (int j = 0; j < ABURST; ++j) {
+                            const int32_t w = ws[j];
+                            if (w < 0) continue;
+                            int32_t dw = s_dist[w];
+                            if (dw == MG_INF) {
+                                const int32_t old = atomicCAS(&s_dist[w], MG_INF, L + 1);
+                                if (old == MG_INF) {
+                                    s_queue[qe + atomicAdd(&s_cnt[cur], 1)] = w;
+                                    dw = L + 1;
+                                } else {
+                                    dw = old;
+                                }
+                            }
+                            if (dw == L + 1) { // v in P_s(w)
+                                const unsigned long long old = atomicAdd(&s_sig[w], sv);
+                                if (old + sv < old) s_ovf = 1;
+                            }
+                        }
+                    }
+                }
+                __syncthreads();
+                qb = qe;
+                qe += s_cnt[cur];
+                ++L;
+                if (tid == 0) s_lev[L + 1] = qe;
+            }
+            __syncthreads();
+            const int32_t nlev = L;
+            // backward: deepest level first; one thread per vertex, no atomics
+            const int32_t lowest = a.dump_n ? 0 : 1;
+            for (int32_t l = nlev - 1; l >= lowest; --l) {
+                for (int32_t i = s_lev[l] + tid; i < s_lev[l + 1]; i += MT) {
+                    const int32_t v = s_queue[i];
+                    double acc = 0.0;
+                    if (l + 1 < nlev) {
+                        const int32_t rb = s_rp[v], re = s_rp[v + 1];
+                        for (int32_t e0 = rb; e0 < re; e0 += ABURST) {
+                            int32_t ws[ABURST];
+#pragma unroll
+                            for (int j = 0; j < ABURST; ++j) ws[j] = e0 + j < re ? col[e0 + j] : -1;
+#pragma unroll
+                            for (int j = 0; j < ABURST; ++j)
+                                if (ws[j] >= 0 && s_dist[ws[j]] == l + 1) acc += (double)s_c[ws[j]];
+                        }
+                    }
+                    const double sv = (double)s_sig[v];
+                    const double dl = sv * acc;
+                    s_c[v] = (float)((1.0 + dl) / sv);
+                    if (v != s) s_bc[v] += dl;
+                    if (a.dump_n) a.delta_dump[(size_t)u * a.dump_n + vo + v] = dl;
+                }
+                __syncthreads();
+            }
+            if (a.dump_n) {
+                for (int32_t v = tid; v < n; v += MT) {
+                    const int32_t d = s_dist[v];
+                    a.dist_dump[(size_t)u * a.dump_n + vo + v] = d == MG_INF ? -1 : d;
+                    a.sigma_dump[(size_t)u * a.dump_n + vo + v] = d == MG_INF ? 0 : s_sig[v];
+                    if (d == MG_INF) a.delta_dump[(size_t)u * a.dump_n + vo + v] = 0.0;
+                }
+            }
+            __syncthreads();
+        }
+        if (!a.dump_n)
+            for (int32_t v = tid; v < n; v += MT)
+                if (s_bc[v] != 0.0) unsafeAtomicAdd(&a.bc[vo + v], s_bc[v]);
+        if (tid == 0 && s_ovf) atomicOr(a.status, (uint32_t)BC_DEV_SIGMA_OVERFLOW);
+        __syncthreads();
+    }
+}
+
+// Fill for the per-source readout rows: vertices of other graphs are
+// unreachable (-1, 0, 0).
+__global__ __launch_bounds__(256) void k_mg_fill(int64_t cells, int32_t *dist, uint64_t *sigma, double *delta) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= cells) return;
+    dist[i] = -1;
+    sigma[i] = 0;
+    delta[i] = 0.0;
+}
+
+MultiArgs args_of(bc_ctx *ctx, const int32_t *units, int32_t nunits) {
+    MultiState &m = ctx->mg;
+    MultiArgs a{};
+    a.voff = m.voff;
+    a.rpoff = m.rpoff;
+    a.rp = m.rp;
+    a.col = ctx->col;
+    a.units = units;
+    a.nunits = nunits;
+    a.next = m.next;
+    a.bc = ctx->bc;
+    a.status = ctx->status;
+    return a;
+}
+
+} // namespace
+
+// Host side of bc_create_many: concatenated arrays and the LPT-ordered queue.
+bc_status multigraph_prepare(bc_ctx *ctx, const std::vector<int32_t> &voff, const std::vector<int32_t> &rpoff,
+                             const std::vector<int32_t> &rp, int32_t chunk) {
+    MultiState &m = ctx->mg;
+    const int32_t ng = (int32_t)voff.size() - 1;
+    m.ngraphs = ng;
+    m.chunk = chunk > 0 ? chunk : 64;
+    m.h_voff = voff;
+    // units sorted by n_g^2 descending (stable: ties keep graph order)
+    std::vector<int32_t> order((size_t)ng);
+    for (int32_t g = 0; g < ng; ++g) order[(size_t)g] = g;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+        return voff[x + 1] - voff[x] > voff[y + 1] - voff[y];
+    });
+    std::vector<int32_t> units;
+    for (int32_t g : order) {
+        const int32_t n = voff[g + 1] - voff[g];
+        for (int32_t s0 = 0; s0 < n; s0 += m.chunk) {
+            units.push_back(g);
+            units.push_back(s0);
+            units.push_back(std::min(n, s0 + m.chunk));
+        }
+    }
+    m.nunits = (int32_t)(units.size() / 3);
+    m.voff = (int32_t *)bc_dalloc(ctx, voff.size() * sizeof(int32_t));
+    m.rpoff = (int32_t *)bc_dalloc(ctx, std::max<size_t>(rpoff.size(), 1) * sizeof(int32_t));
+    m.rp = (int32_t *)bc_dalloc(ctx, std::max<size_t>(rp.size(), 1) * sizeof(int32_t));
+    m.units = (int32_t *)bc_dalloc(ctx, std::max<size_t>(units.size(), 3) * sizeof(int32_t));
+    m.next = (unsigned int *)bc_dalloc(ctx, 256);
+    if (!m.voff || !m.rpoff || !m.rp || !m.units || !m.next)
+        return bc_fail(ctx, BC_ERR_NOMEM, "many graphs: allocation failed");
+    BC_HIP(ctx, hipMemcpy(m.voff, voff.data(), voff.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    if (!rpoff.empty())
+        BC_HIP(ctx, hipMemcpy(m.rpoff, rpoff.data(), rpoff.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    if (!rp.empty()) BC_HIP(ctx, hipMemcpy(m.rp, rp.data(), rp.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    if (!units.empty())
+        BC_HIP(ctx, hipMemcpy(m.units, units.data(), units.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    int cus = 0;
+    BC_HIP(ctx, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
+    m.grid = std::max(1, std::min(m.nunits, cus > 0 ? cus : 256));
+    return BC_OK;
+}
+
+// All sources of every graph.  The first call records the launch into a HIP
+// graph on the context's stream; later calls replay it.
+bc_status multigraph_run(bc_ctx *ctx) {
+    MultiState &m = ctx->mg;
+    if (m.nunits == 0) return BC_OK;
+    const MultiArgs a = args_of(ctx, m.units, m.nunits);
+    if (!m.exec) {
+        hipGraph_t graph = nullptr;
+        BC_HIP(ctx, hipStreamBeginCapture(m.stream, hipStreamCaptureModeThreadLocal));
+        hipLaunchKernelGGL(k_mg_reset, dim3(1), dim3(1), 0, m.stream, m.next);
+        hipLaunchKernelGGL(k_mg_sweep, dim3(m.grid), dim3(MT), 0, m.stream, a);
+        BC_HIP(ctx, hipStreamEndCapture(m.stream, &graph));
+        const hipError_t e = hipGraphInstantiate(&m.exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (e != hipSuccess) return bc_hip(ctx, e, "hipGraphInstantiate");
+    }
+    // order the private capture stream after prior work on the context stream
+    BC_HIP(ctx, hipEventRecord(m.ev, ctx->stream));
+    BC_HIP(ctx, hipStreamWaitEvent(m.stream, m.ev, 0));
+    LaunchTimer t(ctx, "multigraph_sweep");
+    BC_HIP(ctx, hipGraphLaunch(m.exec, m.stream));
+    BC_HIP(ctx, hipEventRecord(m.ev, m.stream));
+    BC_HIP(ctx, hipStreamWaitEvent(ctx->stream, m.ev, 0));
+    t.done();
+    return BC_OK;
+}
+
+// Per-source readout: global vertex ids of the concatenated numbering.
+bc_status multigraph_dump(bc_ctx *ctx, const int32_t *h_sources, int32_t count, int32_t *dist_dump,
+                          uint64_t *sigma_dump, double *delta_dump) {
+    MultiState &m = ctx->mg;
+    std::vector<int32_t> units((size_t)3 * count);
+    for (int32_t i = 0; i < count; ++i) {
+        const int32_t s = h_sources[i];
+        const int32_t g = (int32_t)(std::upper_bound(m.h_voff.begin(), m.h_voff.end(), s) - m.h_voff.begin()) - 1;
+        units[(size_t)3 * i] = g;
+        units[(size_t)3 * i + 1] = s - m.h_voff[(size_t)g];
+        units[(size_t)3 * i + 2] = s - m.h_voff[(size_t)g] + 1;
+    }
+    int32_t *du = (int32_t *)bc_dalloc(ctx, units.size() * sizeof(int32_t));
+    if (!du) return bc_fail(ctx, BC_ERR_NOMEM, "many graphs: readout allocation failed");
+    BC_HIP(ctx, hipMemcpy(du, units.data(), units.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    const int64_t cells = (int64_t)count * ctx->n;
+    hipLaunchKernelGGL(k_mg_fill, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, ctx->stream, cells, dist_dump,
+                       sigma_dump, delta_dump);
+    MultiArgs a = args_of(ctx, du, count);
+    a.dump_n = ctx->n;
+    a.dist_dump = dist_dump;
+    a.sigma_dump = sigma_dump;
+    a.delta_dump = delta_dump;
+    hipLaunchKernelGGL(k_mg_reset, dim3(1), dim3(1), 0, ctx->stream, m.next);
+    hipLaunchKernelGGL(k_mg_sweep, dim3(std::min(count, m.grid)), dim3(MT), 0, ctx->stream, a);
+    BC_HIP(ctx, hipGetLastError());
+    BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    bc_dfree(ctx, du);
+    return BC_OK;
+}

@@ -116,3 +116,28 @@ def test_batched_forms_refuse_weights_before_device_work():
         opt.form = form
         st, msg = _create_status(g.n, g.row_ptr, g.col, g.weight, opt)
         assert st == B.BC_ERR_UNSUPPORTED and "weighted" in msg
+
+
+def test_many_graphs_host_checks():
+    lib = bcgpu.load()
+    big = gg.path(5000)
+    small = gg.path(10)
+    weighted = gg.with_uniform_weights(gg.path(6), 3, 1, 5)
+    for graphs, want in (([small, big], B.BC_ERR_UNSUPPORTED), ([small, weighted], B.BC_ERR_UNSUPPORTED)):
+        arr = (B.bc_graph * len(graphs))()
+        keep = []
+        for i, gr in enumerate(graphs):
+            g, k = _graph_struct(gr.n, gr.row_ptr, gr.col, gr.weight)
+            keep.append(k)
+            arr[i] = g
+        ctx = ctypes.c_void_p()
+        st = lib.bc_create_many(arr, len(graphs), None, ctypes.byref(ctx))
+        assert st == want and ctx.value is None
+    # an invalid member graph is reported with its index
+    arr = (B.bc_graph * 2)()
+    g0, k0 = _graph_struct(small.n, small.row_ptr, small.col)
+    g1, k1 = _graph_struct(3, [0, 1, 1, 1], [1])
+    arr[0], arr[1] = g0, g1
+    ctx = ctypes.c_void_p()
+    assert lib.bc_create_many(arr, 2, None, ctypes.byref(ctx)) == B.BC_ERR_INVALID_GRAPH
+    assert "graph 1" in bcgpu.bc_last_error(None)

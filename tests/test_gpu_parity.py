@@ -337,3 +337,57 @@ def test_weighted_arena_retry(gpu_lib, log2):
         d, sg, dl = oracle.sssp_u64(g, int(src[i]))
         assert np.array_equal(dist[i], d) and np.array_equal(sigma[i], sg)
         assert rel_err(delta[i], dl) <= 1e-12
+
+
+def many_graphs():
+    gs = [gg.path(1), gg.path(2), gg.path(40), gg.cycle(31), gg.star(300), gg.complete(50), gg.grid(12, 13),
+          gg.random_tree(500, 4), gg.complete_bipartite(4, 9), gg.er_plus_tree(700, 5.0, 6),
+          gg.disjoint_union(gg.path(9), gg.cycle(12))]
+    sizes = gg.Stream(31).bounded(np.full(40, 4096 - 64 + 1)) + 64
+    gs += [gg.watts_strogatz(int(n), 6, 0.1, 1000 + i) for i, n in enumerate(sizes)]
+    gs.append(gg.watts_strogatz(4096, 6, 0.1, 7))
+    return gs
+
+
+def test_many_graphs_one_launch(gpu_lib):
+    """Many graphs in one persistent, graph-captured launch: each graph's BC
+    equals its own oracle BC; replays accumulate; readouts use the
+    concatenated numbering."""
+    gs = many_graphs()
+    say("many_graphs", len(gs), sum(g.n for g in gs))
+    want = np.concatenate([oracle.bc(g, threads=8) for g in gs])
+    with gpu_lib.BC(gs) as ctx:
+        assert ctx.info().form == gpu_lib.binding.BC_FORM_MANY
+        ctx.run()
+        first = ctx.read()
+        assert rel_err(first, want) <= 1e-5
+        ctx.run()  # replay of the recorded launch
+        ctx.run()
+        assert rel_err(ctx.read(), 3 * want) <= 1e-5
+        ctx.reset()
+        assert np.all(ctx.read() == 0.0)
+        ctx.run()
+        assert rel_err(ctx.read(), want) <= 1e-5
+        with pytest.raises(gpu_lib.BCError) as ei:
+            ctx.run(np.array([0], np.int32))
+        assert ei.value.status == gpu_lib.BC_ERR_UNSUPPORTED
+        offs = np.concatenate([[0], np.cumsum([g.n for g in gs])])
+        picks = [(9, 3), (10, 0), (len(gs) - 1, 100)]
+        src = np.array([offs[g] + v for g, v in picks], np.int32)
+        dist, sigma, delta = ctx.sssp(src)
+    for i, (g, v) in enumerate(picks):
+        d, sg, dl = oracle.sssp_u64(gs[g], v)
+        lo, hi = offs[g], offs[g + 1]
+        assert np.array_equal(dist[i][lo:hi], d) and np.array_equal(sigma[i][lo:hi], sg)
+        assert np.all(dist[i][:lo] == -1) and np.all(dist[i][hi:] == -1)
+        assert rel_err(delta[i][lo:hi], dl) <= 1e-5
+
+
+def test_many_graphs_overflow(gpu_lib):
+    gs = [gg.path(5), gg.grid(35, 35)]  # C(68,34) > 2^64 - 1 in the second graph
+    say("many_overflow")
+    with gpu_lib.BC(gs) as ctx:
+        ctx.run()
+        with pytest.raises(gpu_lib.BCError) as ei:
+            ctx.read()
+        assert ei.value.status == gpu_lib.BC_ERR_OVERFLOW
