@@ -1,5 +1,7 @@
-"""Benchmark: betweenness TEPS on RMAT scale 16 (all sources), batched sparse
-form against the plain FP64 per-source form on the same GPU.
+"""Benchmark: betweenness TEPS on RMAT scale 16 (all sources), the batched
+mixed-precision form (hybrid: sparse pulls or MFMA products per level, as the
+tuner chose before timing) against the plain FP64 per-source form on the same
+GPU.
 
 One step = one complete all-source betweenness computation (forward sweep,
 backward sweep and accumulation for every vertex as a source) over the
@@ -30,6 +32,7 @@ import numpy as np  # noqa: E402
 
 METRIC = "BC TEPS (sources·m/s) on RMAT-16; batched-MFMA vs plain BFS form, same GPU"
 HBM_PEAK_GBS = 8000.0
+MFMA_BF16_PEAK_TFS = 2500.0
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sparse_rmat16_traffic.txt")
@@ -99,6 +102,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--form", default="hybrid", choices=["hybrid", "sparse", "algebraic"])
+    ap.add_argument("--no-free-batch", action="store_true", help="skip the extra run at the tuned batch width")
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -127,8 +132,13 @@ def main():
     src = None if S == g.n else np.arange(S, dtype=np.int32)
     work = float(S) * g.m
 
-    def timed_runs(form, steps, warmup, batch=0):
-        ctx = bcgpu.BC(g, form=form, batch=batch, timing=True)
+    def timed_runs(form, steps, warmup, batch=0, timing=True):
+        t = time.perf_counter()
+        ctx = bcgpu.BC(g, form=form, batch=batch, timing=timing)
+        info = ctx.info()
+        log(f"{form} create (upload, dense adjacency, tuning) {time.perf_counter() - t:.2f}s: batch {info.batch}, "
+            f"products when density >= ({info.mfma_density_fwd:.3f} fwd, {info.mfma_density_bwd:.3f} bwd), "
+            f"tuning source {info.tune_source}")
         for i in range(warmup):
             ctx.run(src)
             ctx.read()
@@ -144,25 +154,45 @@ def main():
         log(f"{form} {steps} steps: {dt * 1e3:.1f} ms/step, {work / dt:.3e} TEPS")
         return ctx, dt, bc
 
-    ctx, dt, bc_sparse = timed_runs("sparse", args.steps, args.warmup, args.batch)
+    ctx, dt, bc_sparse = timed_runs(args.form, args.steps, args.warmup, args.batch)
     info = ctx.info()
     kern = {}
-    for k in ("fwd_pull", "bwd_pull", "fwd_push0", "batch_init"):
+    for k in ("fwd_pull", "bwd_pull", "fwd_push0", "batch_init", "limb_split", "mfma_fwd", "coef_split", "mfma_bwd"):
         ms, launches = ctx.timing(k)
-        kern[k] = (ms, launches)
+        if launches:
+            kern[k] = (ms, launches)
     log("kernel times (ms, launches):", kern)
 
     bytes_src = algorithmic_bytes_per_source(g.n, g.m)
-    dom = "fwd_pull" if kern["fwd_pull"][0] >= kern["bwd_pull"][0] else "bwd_pull"
+    dom = max(kern, key=lambda k: kern[k][0])
     dom_ms, dom_launches = kern[dom]
-    alg_bytes_total = float(S) * args.steps * bytes_src["fwd" if dom == "fwd_pull" else "bwd"]
-    achieved = alg_bytes_total / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else None
-    traffic = measured_traffic(dom)
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
-                "avg_launch_ms": dom_ms / max(dom_launches, 1), "launches": dom_launches,
-                "alg_bytes_per_launch": alg_bytes_total / max(dom_launches, 1)}
+    if dom in ("fwd_pull", "bwd_pull"):
+        alg_total = float(S) * args.steps * bytes_src["fwd" if dom == "fwd_pull" else "bwd"]
+        achieved = alg_total / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else None
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": measured_traffic(dom),
+                    "avg_launch_ms": dom_ms / max(dom_launches, 1), "launches": dom_launches,
+                    "alg_bytes_per_launch": alg_total / max(dom_launches, 1)}
+    else:
+        # products: issued MFMA work is 2 * batch * npad * npad per limb or
+        # coefficient plane; launches already count one plane each for the
+        # forward, three planes per launch for the backward
+        npad = (g.n + 63) // 64 * 64
+        planes = dom_launches * (3 if dom == "mfma_bwd" else 1)
+        flops = 2.0 * info.batch * npad * npad * planes
+        achieved = flops / (dom_ms * 1e-3) / 1e12 if dom_ms > 0 else None
+        roofline = {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": MFMA_BF16_PEAK_TFS,
+                    "unit": "TFLOP/s", "frac": (achieved / MFMA_BF16_PEAK_TFS) if achieved else None,
+                    "traffic": None, "avg_launch_ms": dom_ms / max(dom_launches, 1), "launches": dom_launches}
     ctx.close()
+
+    free = None
+    if not args.no_free_batch and args.batch != 0:
+        fctx, fdt, _ = timed_runs(args.form, 1, 1, 0, timing=False)
+        finfo = fctx.info()
+        fctx.close()
+        free = {"batch": finfo.batch, "value": work / fdt, "ms_per_step": fdt * 1e3,
+                "mfma_density": [finfo.mfma_density_fwd, finfo.mfma_density_bwd]}
 
     plain = None
     if not args.no_plain:
@@ -200,8 +230,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": "rmat16: RMAT scale 16, edgefactor 16, (a,b,c,d)=(.57,.19,.19,.05), "
                                "symmetrised, deduplicated, largest component; exact all-source BC",
-                   "n": g.n, "m": g.m, "sources": S, "batch": info.batch, "form": "sparse",
+                   "n": g.n, "m": g.m, "sources": S, "batch": info.batch, "form": args.form,
+                   "mfma_density_thresholds": [info.mfma_density_fwd, info.mfma_density_bwd],
+                   "tune_source": ["default", "measured", "cached"][info.tune_source],
                    "levels_max": info.max_levels},
+        "tuned_batch_width": free,
         "plain_fp64": plain,
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kern.items()},
         "batched_vs_plain": (plain["ms_per_step"] / (dt * 1e3)) if plain else None,

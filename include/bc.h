@@ -52,16 +52,26 @@ typedef enum { BC_MEM_HOST = 0, BC_MEM_DEVICE = 1 } bc_mem;
  * floating-point rounding, and the same distances and path counts exactly.
  *
  *  BC_FORM_PLAIN_FP64  one source per workgroup, per-source state, dependencies
- *                      in FP64.  Unit and integer weights.
- *  BC_FORM_SPARSE      sources in batches (a multiple of 64, default 256);
+ *                      in FP64.  Unit weights by the level sweep of Sec. 4;
+ *                      integer weights by bucketed shortest paths with one
+ *                      bucket per distance value.
+ *  BC_FORM_SPARSE      sources in batches (64, 128, 256 or 512; 0 = tuned);
  *                      per-level frontier bitmaps, one bit per (vertex, source);
  *                      CSR gathers pulled per vertex; path counts uint64,
  *                      dependency state stored as FP32 with FP64 accumulation.
- *                      Unit weights (the level sweep of Sec. 4); integer weights
- *                      use bucketed shortest paths with one bucket per distance.
+ *                      Unit weights.
  *  BC_FORM_ALGEBRAIC   the algebraic method of Sec. 3.1 on a batch of sources:
  *                      frontier-matrix x adjacency products on BF16 MFMA with
  *                      path counts carried exactly in 8-bit limbs.  Unit weights.
+ *  BC_FORM_HYBRID      the sparse form's batches, where each level l >= 1 goes
+ *                      either by CSR pulls or by the algebraic form's products,
+ *                      chosen per batch from the level's union-frontier density
+ *                      (the fraction of vertices at level l for at least one
+ *                      source of the batch) against two thresholds (forward,
+ *                      backward) fixed at create time by timed calibration
+ *                      batches or a tuning cache.  Unit weights.  Graphs whose
+ *                      dense adjacency would exceed 16 GiB, or with a degree
+ *                      above 65792, run every level by pulls.
  *  BC_FORM_AUTO        chosen by the library from the graph's shape.
  */
 typedef enum {
@@ -69,6 +79,7 @@ typedef enum {
     BC_FORM_PLAIN_FP64 = 1,
     BC_FORM_SPARSE = 2,
     BC_FORM_ALGEBRAIC = 3,
+    BC_FORM_HYBRID = 4,
     BC_FORM_MANY = 5 /* reported by bc_get_info for bc_create_many contexts */
 } bc_form;
 
@@ -110,7 +121,11 @@ typedef struct {
 typedef struct {
     uint32_t struct_size; /* sizeof(bc_options); set by bc_options_init */
     bc_form form;         /* default BC_FORM_AUTO */
-    int32_t batch;        /* sources per batch for batched forms; 0 = default */
+    int32_t batch;        /* sources per batch for batched forms.  0 = tuned for
+                             the sparse and hybrid forms (timed calibration
+                             batches choose among 128, 256, 512, or 256 and 512
+                             when products are possible; graphs under 2048
+                             vertices take 256), 256 for the algebraic form */
     int32_t device;       /* HIP device ordinal; -1 = the current device */
     void *stream;         /* hipStream_t to run on; NULL = the null stream */
     bc_allocator allocator;
@@ -124,8 +139,16 @@ typedef struct {
                              a ring of 2^arena_log2 entries (0 = default, max(4n, 2^16)
                              rounded up); a source that outgrows it is re-run with a
                              ring of nnz entries, so results never depend on it */
-    int32_t reserved[5];
+    const char *tune_cache; /* sparse and hybrid forms: path of a text file of
+                             tuning results keyed by the graph's shape (n, m,
+                             degree histogram), the form, the requested batch and
+                             the device; a hit skips calibration, a miss appends
+                             the measured result.  NULL = this process only. */
+    int32_t reserved[3];
 } bc_options;
+
+/* Where the batch width and hybrid thresholds of a context came from. */
+enum { BC_TUNE_DEFAULT = 0, BC_TUNE_MEASURED = 1, BC_TUNE_CACHED = 2 };
 
 /* Internal vertex numbering.  BC_ORDER_DEGREE renumbers vertices by
  * nonincreasing degree so that the rows of high-degree vertices, which most
@@ -211,6 +234,11 @@ typedef struct {
     int32_t max_levels;  /* deepest level (or distinct distance count) seen + 1 */
     int64_t sources_run; /* sources accumulated since create / reset */
     int64_t device_bytes;/* device memory the context holds */
+    double mfma_density_fwd; /* hybrid form: forward level l -> l+1 by products when
+                                density(l) >= this (above 1: never) */
+    double mfma_density_bwd; /* hybrid form: backward level l by products when
+                                density(l) >= this (above 1: never) */
+    int32_t tune_source;     /* BC_TUNE_* for the batch width and thresholds */
 } bc_info;
 
 bc_status bc_get_info(const bc_ctx *ctx, bc_info *out);

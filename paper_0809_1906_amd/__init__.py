@@ -9,3 +9,5 @@ from .binding import (BC, BCError, FORMS, bc_create, bc_create_many, bc_destroy,
                       bc_status_string, load, LIB_PATH, SIGNATURES)
 from .binding import (BC_OK, BC_ERR_INVALID_ARG, BC_ERR_INVALID_GRAPH, BC_ERR_NOMEM,  # noqa: F401
                       BC_ERR_DEVICE, BC_ERR_OVERFLOW, BC_ERR_STATE, BC_ERR_UNSUPPORTED)
+from .binding import (BC_FORM_AUTO, BC_FORM_PLAIN_FP64, BC_FORM_SPARSE, BC_FORM_ALGEBRAIC,  # noqa: F401
+                      BC_FORM_HYBRID, BC_FORM_MANY, BC_TUNE_DEFAULT, BC_TUNE_MEASURED, BC_TUNE_CACHED)

@@ -34,9 +34,14 @@ BC_FORM_AUTO = 0
 BC_FORM_PLAIN_FP64 = 1
 BC_FORM_SPARSE = 2
 BC_FORM_ALGEBRAIC = 3
+BC_FORM_HYBRID = 4
 BC_FORM_MANY = 5
 FORMS = {"auto": BC_FORM_AUTO, "plain": BC_FORM_PLAIN_FP64, "sparse": BC_FORM_SPARSE,
-         "algebraic": BC_FORM_ALGEBRAIC}
+         "algebraic": BC_FORM_ALGEBRAIC, "hybrid": BC_FORM_HYBRID}
+
+BC_TUNE_DEFAULT = 0
+BC_TUNE_MEASURED = 1
+BC_TUNE_CACHED = 2
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
@@ -57,14 +62,15 @@ class bc_options(ctypes.Structure):
                 ("device", ctypes.c_int32), ("stream", ctypes.c_void_p), ("allocator", bc_allocator),
                 ("timing", ctypes.c_int32), ("split_degree", ctypes.c_int32),
                 ("vertex_order", ctypes.c_int32), ("arena_log2", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("tune_cache", ctypes.c_char_p), ("reserved", ctypes.c_int32 * 3)]
 
 
 class bc_info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int64), ("max_degree", ctypes.c_int32),
                 ("weighted", ctypes.c_int32), ("form", ctypes.c_int), ("batch", ctypes.c_int32),
                 ("max_levels", ctypes.c_int32), ("sources_run", ctypes.c_int64),
-                ("device_bytes", ctypes.c_int64)]
+                ("device_bytes", ctypes.c_int64), ("mfma_density_fwd", ctypes.c_double),
+                ("mfma_density_bwd", ctypes.c_double), ("tune_source", ctypes.c_int32)]
 
 
 # Every symbol include/bc.h declares, with its ctypes signature.
@@ -218,7 +224,7 @@ class BC:
 
     def __init__(self, graph, form: str = "auto", batch: int = 0, device: int = 0, stream=None,
                  allocator: str = "torch", timing: bool = False, split_degree: int = 0,
-                 vertex_order: str = "degree", arena_log2: int = 0):
+                 vertex_order: str = "degree", arena_log2: int = 0, tune_cache: Optional[str] = None):
         import torch
         load()
         if not torch.cuda.is_available():
@@ -236,6 +242,8 @@ class BC:
         opt.split_degree = split_degree
         opt.vertex_order = {"degree": 0, "input": 1}[vertex_order]
         opt.arena_log2 = arena_log2
+        self._tune_cache = None if tune_cache is None else os.fsencode(tune_cache)
+        opt.tune_cache = self._tune_cache
         self._alloc = None
         if allocator == "torch":
             self._alloc = _TorchAllocator(device)

@@ -207,7 +207,7 @@ __global__ __launch_bounds__(GT) void k_mfma(GemmArgs g, EpiArgs e) {
         }
     } else {
         S *sigma = reinterpret_cast<S *>(e.sigma);
-        bool wide = false;
+        bool wide = false, ovf = false;
         uint64_t mx = 0;
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt) {
@@ -216,21 +216,34 @@ __global__ __launch_bounds__(GT) void k_mfma(GemmArgs g, EpiArgs e) {
                 const int w = w0 + rt * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
                 const bool valid = w < g.n;
                 uint64_t vis = ~0ull;
-                if (MODE == EPI_ONLY || MODE == EPI_LAST) vis = valid ? e.visited[(size_t)w * g.NW + q] : ~0ull;
+                if (MODE != EPI_FIRST) vis = valid ? e.visited[(size_t)w * g.NW + q] : ~0ull;
                 uint64_t m[2];
 #pragma unroll
                 for (int ct = 0; ct < 2; ++ct) {
                     const int bit = ct * 32 + col;
                     const uint64_t P = (uint64_t)acc[rt][ct][r]; // exact integer < 2^24
                     bool fresh = false;
+                    // A limb sum that carries out of 64 bits is a count above
+                    // 2^64 - 1 when w is unvisited (a level-(l+1) vertex);
+                    // visited vertices' sums are discarded.
+                    const bool open = valid && !((vis >> bit) & 1);
                     if (MODE == EPI_FIRST) {
                         if (valid) e.part[(size_t)w * g.B + (size_t)q * 64 + bit] = P;
                     } else if (MODE == EPI_MID) {
-                        if (valid) e.part[(size_t)w * g.B + (size_t)q * 64 + bit] += P << e.shift;
+                        if (valid) {
+                            uint64_t &pt = e.part[(size_t)w * g.B + (size_t)q * 64 + bit];
+                            const uint64_t add = P << e.shift, sum = pt + add;
+                            if (open && ((P >> (64 - e.shift)) != 0 || sum < add)) ovf = true;
+                            pt = sum;
+                        }
                     } else {
                         uint64_t tot = P << e.shift;
-                        if (MODE == EPI_LAST && valid) tot += e.part[(size_t)w * g.B + (size_t)q * 64 + bit];
-                        fresh = valid && !((vis >> bit) & 1) && tot != 0;
+                        if (MODE == EPI_LAST && valid) {
+                            const uint64_t add = tot;
+                            tot += e.part[(size_t)w * g.B + (size_t)q * 64 + bit];
+                            if (open && ((P >> (64 - e.shift)) != 0 || tot < add)) ovf = true;
+                        }
+                        fresh = open && tot != 0;
                         if (fresh) {
                             store_count(&sigma[(size_t)w * g.B + (size_t)q * 64 + bit], tot, wide);
                             mx = tot > mx ? tot : mx;
@@ -261,6 +274,7 @@ __global__ __launch_bounds__(GT) void k_mfma(GemmArgs g, EpiArgs e) {
             if (lane == 0 && mx) atomicMax(e.level_max, (unsigned long long)mx);
             if (__any(wide) && lane == 0) atomicOr(&e.status[1], 1u);
         }
+        if (MODE != EPI_FIRST && __any(ovf) && lane == 0) atomicOr(&e.status[0], (uint32_t)BC_DEV_SIGMA_OVERFLOW);
     }
 }
 
@@ -399,6 +413,18 @@ bc_status algebraic_prepare(bc_ctx *ctx) {
         hipLaunchKernelGGL(k_build_adj, dim3(ctx->n), dim3(PB), 0, ctx->stream, ctx->n, a.npad, ctx->row_ptr,
                            ctx->col, a.adj);
     BC_HIP(ctx, hipGetLastError());
+    return BC_OK;
+}
+
+bc_status algebraic_release(bc_ctx *ctx) {
+    AlgebraicState &a = ctx->al;
+    BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    for (void *p : {(void *)a.adj, (void *)a.planes, (void *)a.part, (void *)a.kflags, (void *)a.level_max})
+        if (p) bc_dfree(ctx, p);
+    if (a.host) hipHostFree(a.host);
+    const bool every = a.every_level;
+    a = AlgebraicState{};
+    a.every_level = every;
     return BC_OK;
 }
 

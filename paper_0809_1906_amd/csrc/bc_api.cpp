@@ -102,12 +102,9 @@ void release_all(bc_ctx *ctx) {
     ctx->mg.exec = nullptr;
     ctx->mg.ev = nullptr;
     ctx->mg.stream = nullptr;
-    for (auto &kv : ctx->timers)
-        for (auto &pr : kv.second.pending) {
-            hipEventDestroy(pr.first);
-            hipEventDestroy(pr.second);
-        }
-    ctx->timers.clear();
+    bc_timers_clear(ctx);
+    for (hipEvent_t e : ctx->event_pool) hipEventDestroy(e);
+    ctx->event_pool.clear();
     auto owned = ctx->owned;
     for (auto &pr : owned) bc_dfree(ctx, pr.first);
     ctx->owned.clear();
@@ -169,11 +166,41 @@ void bc_dfree(bc_ctx *ctx, void *p) {
     else hipFree(p);
 }
 
+hipEvent_t bc_event_get(bc_ctx *ctx) {
+    if (!ctx->event_pool.empty()) {
+        hipEvent_t e = ctx->event_pool.back();
+        ctx->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
+    return e;
+}
+
+void bc_event_put(bc_ctx *ctx, hipEvent_t e) {
+    if (e) ctx->event_pool.push_back(e);
+}
+
+void bc_timers_clear(bc_ctx *ctx) {
+    for (auto &kv : ctx->timers)
+        for (auto &pr : kv.second.pending) {
+            bc_event_put(ctx, pr.first);
+            bc_event_put(ctx, pr.second);
+        }
+    ctx->timers.clear();
+}
+
 LaunchTimer::LaunchTimer(bc_ctx *c, const char *nm) : ctx(c), name(nm) {
     if (!ctx->timing) return;
-    hipEventCreate(&a);
-    hipEventCreate(&b);
-    hipEventRecord(a, ctx->stream);
+    a = bc_event_get(ctx);
+    b = bc_event_get(ctx);
+    if (a && b) {
+        hipEventRecord(a, ctx->stream);
+    } else {
+        bc_event_put(ctx, a);
+        bc_event_put(ctx, b);
+        a = b = nullptr;
+    }
 }
 
 void LaunchTimer::done() {
@@ -234,7 +261,7 @@ bc_status bc_create(const bc_graph *g, const bc_options *opt_in, bc_ctx **out) {
     if (g->nnz > 0 && !g->col) return fail_create(BC_ERR_INVALID_ARG, "col is NULL");
     if (g->mem != BC_MEM_HOST && g->mem != BC_MEM_DEVICE)
         return fail_create(BC_ERR_INVALID_ARG, "graph mem must be BC_MEM_HOST or BC_MEM_DEVICE");
-    if (opt.form < BC_FORM_AUTO || opt.form > BC_FORM_ALGEBRAIC)
+    if (opt.form < BC_FORM_AUTO || opt.form > BC_FORM_HYBRID)
         return fail_create(BC_ERR_INVALID_ARG, "unknown form");
     if (opt.batch < 0 || opt.batch % 64 != 0 || opt.batch > 4096)
         return fail_create(BC_ERR_INVALID_ARG, "batch must be 0 or a multiple of 64 up to 4096");
@@ -276,7 +303,7 @@ bc_status bc_create(const bc_graph *g, const bc_options *opt_in, bc_ctx **out) {
 
     bc_form form = opt.form;
     if (form == BC_FORM_AUTO) form = hw ? BC_FORM_PLAIN_FP64 : BC_FORM_SPARSE;
-    if (hw && (form == BC_FORM_SPARSE || form == BC_FORM_ALGEBRAIC))
+    if (hw && (form == BC_FORM_SPARSE || form == BC_FORM_ALGEBRAIC || form == BC_FORM_HYBRID))
         return fail_create(BC_ERR_UNSUPPORTED,
                            "weighted graphs are served by the per-source form (BC_FORM_PLAIN_FP64) only");
 
@@ -373,12 +400,11 @@ bc_status bc_create(const bc_graph *g, const bc_options *opt_in, bc_ctx **out) {
 
     bc_status ps = BC_OK;
     if (form == BC_FORM_PLAIN_FP64) ps = plain_prepare(ctx);
-    else if (form == BC_FORM_SPARSE) ps = sparse_prepare(ctx, opt.batch ? opt.batch : 256, opt.split_degree);
+    else if (form == BC_FORM_SPARSE || form == BC_FORM_HYBRID) ps = tune_prepare(ctx, opt, form);
     else if (form == BC_FORM_ALGEBRAIC) {
         ps = sparse_prepare(ctx, opt.batch ? opt.batch : 256, opt.split_degree);
         if (ps == BC_OK) ps = algebraic_prepare(ctx);
-        ctx->al.fwd_levels = ~1u; // every level l >= 1 as a product with A
-        ctx->al.bwd_levels = ~1u;
+        ctx->al.every_level = true;
     }
     if (ps != BC_OK) return bail(ps, ctx->err);
     if (hipStreamSynchronize(ctx->stream) != hipSuccess) return bail(BC_ERR_DEVICE, "stream synchronisation failed");
@@ -555,7 +581,8 @@ bc_status bc_run(bc_ctx *ctx, const int32_t *sources, int64_t count, bc_mem mem)
     if (s != BC_OK) return s;
     if (cnt == 0 || ctx->n == 0) return BC_OK;
     if (ctx->form == BC_FORM_PLAIN_FP64) s = plain_run(ctx, d_src, cnt, true, nullptr, nullptr, nullptr);
-    else if (ctx->form == BC_FORM_SPARSE || ctx->form == BC_FORM_ALGEBRAIC) s = sparse_run(ctx, d_src, cnt);
+    else if (ctx->form == BC_FORM_SPARSE || ctx->form == BC_FORM_ALGEBRAIC || ctx->form == BC_FORM_HYBRID)
+        s = sparse_run(ctx, d_src, cnt);
     else s = bc_fail(ctx, BC_ERR_UNSUPPORTED, "form not available");
     if (s == BC_OK) ctx->sources_run += cnt;
     return s;
@@ -584,10 +611,7 @@ bc_status bc_reset(bc_ctx *ctx) {
     BC_HIP(ctx, hipMemsetAsync(ctx->bc, 0, sizeof(double) * (size_t)std::max(ctx->n, 1), ctx->stream));
     BC_HIP(ctx, hipMemsetAsync(ctx->status, 0, 256, ctx->stream));
     BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    for (auto &kv : ctx->timers) {
-        for (auto &pr : kv.second.pending) { hipEventDestroy(pr.first); hipEventDestroy(pr.second); }
-        kv.second = KernelTimer();
-    }
+    bc_timers_clear(ctx);
     ctx->overflow_seen = false;
     ctx->sources_run = 0;
     return BC_OK;
@@ -657,6 +681,11 @@ bc_status bc_get_info(const bc_ctx *ctx, bc_info *out) {
     out->max_levels = ctx->max_levels;
     out->sources_run = ctx->sources_run;
     out->device_bytes = ctx->device_bytes;
+    const bool every = ctx->form == BC_FORM_ALGEBRAIC;
+    const bool hybrid = ctx->form == BC_FORM_HYBRID && ctx->hy.products;
+    out->mfma_density_fwd = every ? 0.0 : hybrid ? ctx->hy.theta_fwd : 2.0;
+    out->mfma_density_bwd = every ? 0.0 : hybrid ? ctx->hy.theta_bwd : 2.0;
+    out->tune_source = ctx->hy.tune_source;
     return BC_OK;
 }
 
@@ -671,8 +700,8 @@ bc_status bc_get_timing(bc_ctx *ctx, const char *kernel, double *total_ms, int64
         float ms = 0.f;
         BC_HIP(ctx, hipEventElapsedTime(&ms, pr.first, pr.second));
         it->second.total_ms += ms;
-        hipEventDestroy(pr.first);
-        hipEventDestroy(pr.second);
+        bc_event_put(ctx, pr.first);
+        bc_event_put(ctx, pr.second);
     }
     it->second.pending.clear();
     *total_ms = it->second.total_ms;

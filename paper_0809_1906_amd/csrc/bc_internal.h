@@ -58,8 +58,33 @@ struct AlgebraicState {
     uint32_t *kflags = nullptr;        // [npad/32][batch/256] non-empty k-tiles
     unsigned long long *level_max = nullptr;
     unsigned long long *host = nullptr; // pinned
-    uint32_t fwd_levels = 0;           // bit l: forward level l -> l+1 by products (l >= 1)
-    uint32_t bwd_levels = 0;           // bit l: backward level l by products (l >= 1)
+    bool every_level = false;          // the algebraic form: every level l >= 1 by products
+};
+
+// Per-level record of batches run while a probe is attached: the GPU time of
+// each level's work and the level's union-frontier density.
+struct LevelProbe {
+    int mode = 0; // 0: follow the thresholds; 1: every level by CSR pulls;
+                  // 2: every level >= 1 by products with A
+    struct Rec {
+        bool forward;
+        int32_t level;
+        double density;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs; // whoever attached the probe returns the events to the pool
+};
+
+// Hybrid form: each level l >= 1 goes by CSR pulls or by products with the
+// dense adjacency, chosen per batch from the union-frontier density of the
+// level (the fraction of vertices at level l for at least one source of the
+// batch) against thresholds fixed at create time.
+struct HybridState {
+    bool products = false;   // the dense adjacency exists and levels may use it
+    double theta_fwd = 2.0;  // forward l -> l+1 by products when density(l) >= theta_fwd
+    double theta_bwd = 2.0;  // backward l by products when density(l) >= theta_bwd
+    int32_t tune_source = 0; // BC_TUNE_DEFAULT / BC_TUNE_MEASURED / BC_TUNE_CACHED
+    LevelProbe *probe = nullptr;
 };
 
 // State of the weighted per-source form (bucketed shortest paths).
@@ -142,6 +167,7 @@ struct bc_ctx {
     PlainState pl;
     WeightedState wt;
     MultiState mg;
+    HybridState hy;
     bool many = false;
 
     // bookkeeping
@@ -153,6 +179,7 @@ struct bc_ctx {
 
     bool timing = false;
     std::map<std::string, KernelTimer> timers;
+    std::vector<hipEvent_t> event_pool; // timing events ready for reuse
 };
 
 // ---- helpers implemented in bc_api.cpp --------------------------------------
@@ -160,6 +187,12 @@ bc_status bc_fail(bc_ctx *ctx, bc_status s, const std::string &msg);
 bc_status bc_hip(bc_ctx *ctx, hipError_t e, const char *what);
 void *bc_dalloc(bc_ctx *ctx, size_t bytes);
 void bc_dfree(bc_ctx *ctx, void *p);
+// Timing events from the context's pool (created without the system-scope
+// fence: they only time work on the stream); nullptr if creation fails.
+hipEvent_t bc_event_get(bc_ctx *ctx);
+void bc_event_put(bc_ctx *ctx, hipEvent_t e);
+// Returns every pending kernel-timer event to the pool and zeroes the timers.
+void bc_timers_clear(bc_ctx *ctx);
 // Records an event pair around a launch when timing is on.
 struct LaunchTimer {
     bc_ctx *ctx;
@@ -201,6 +234,16 @@ bc_status algebraic_prepare(bc_ctx *ctx);
 bc_status algebraic_forward_level(bc_ctx *ctx, bool wide, const uint64_t *fcur, uint64_t *fnext, uint32_t *any_next);
 bc_status algebraic_backward_level(bc_ctx *ctx, bool wide, const uint64_t *fcur, const uint64_t *fnext,
                                    double *delta_dump, bool accumulate);
+bc_status sparse_release(bc_ctx *ctx);
+bc_status algebraic_release(bc_ctx *ctx);
+// One batch of at most sp.batch internal source ids (device memory) through
+// the batched forms; accumulate = false leaves BC untouched.
+bc_status sparse_batch(bc_ctx *ctx, const int32_t *d_sources, int32_t count, bool accumulate);
 bc_status sparse_run(bc_ctx *ctx, const int32_t *d_sources, int64_t count);
 bc_status sparse_dump(bc_ctx *ctx, const int32_t *d_sources, int32_t count,
                       int32_t *dist_dump, uint64_t *sigma_dump, double *delta_dump);
+
+// ---- tuning (tune.cpp) ----------------------------------------------------------
+// Prepares the sparse or hybrid form: batch width and hybrid thresholds come
+// from opt, from the tuning cache, or from timed calibration batches.
+bc_status tune_prepare(bc_ctx *ctx, const bc_options &opt, bc_form form);

@@ -545,6 +545,59 @@ Topo topo(bc_ctx *ctx) {
 
 inline int32_t any_words(const bc_ctx *ctx) { return (ctx->n + 31) >> 5; }
 
+// Union-frontier density of level l, from the host mirror of any[l].
+double level_density(const bc_ctx *ctx, int32_t l) {
+    const int32_t aw = any_words(ctx);
+    const uint32_t *a = ctx->sp.any_host + (size_t)l * aw;
+    int64_t c = 0;
+    for (int32_t i = 0; i < aw; ++i) c += __builtin_popcount(a[i]);
+    return ctx->n > 0 ? (double)c / ctx->n : 0.0;
+}
+
+int probe_mode(const bc_ctx *ctx) { return ctx->hy.probe ? ctx->hy.probe->mode : 0; }
+
+// Does level l (>= 1) go by products with A?  The algebraic form takes them at
+// every level; the hybrid form compares the level's density with a threshold.
+bool by_products(const bc_ctx *ctx, int32_t l, bool forward) {
+    if (l < 1) return false;
+    if (ctx->al.every_level) return true;
+    if (!ctx->hy.products) return false;
+    const int mode = probe_mode(ctx);
+    if (mode != 0) return mode == 2;
+    return level_density(ctx, l) >= (forward ? ctx->hy.theta_fwd : ctx->hy.theta_bwd);
+}
+
+// The forward goes one level at a time (reading each level back) when some
+// level may need products: the decision needs the level's density, and the
+// products need its largest count.
+bool stepwise_forward(const bc_ctx *ctx) {
+    if (ctx->al.every_level) return true;
+    if (!ctx->hy.products) return false;
+    const int mode = probe_mode(ctx);
+    return mode == 2 || (mode == 0 && ctx->hy.theta_fwd <= 1.0);
+}
+
+// Event pair around one level's work while a probe is attached.
+struct ProbeScope {
+    bc_ctx *ctx;
+    hipEvent_t a = nullptr;
+    ProbeScope(bc_ctx *c) : ctx(c) {
+        if (ctx->hy.probe && (a = bc_event_get(ctx)) != nullptr) hipEventRecord(a, ctx->stream);
+    }
+    void done(bool forward, int32_t level) {
+        if (!a) return;
+        hipEvent_t b = bc_event_get(ctx);
+        if (!b) {
+            bc_event_put(ctx, a);
+            a = nullptr;
+            return;
+        }
+        hipEventRecord(b, ctx->stream);
+        ctx->hy.probe->recs.push_back({forward, level, 0.0, a, b});
+        a = nullptr;
+    }
+};
+
 bc_status ensure_levels(bc_ctx *ctx, int32_t need) {
     SparseState &s = ctx->sp;
     if (need <= s.level_cap) return BC_OK;
@@ -619,12 +672,11 @@ bc_status run_batch_t(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool acc
         BC_HIP(ctx, hipGetLastError());
     }
     int32_t launched = 0, nlev = -1;
-    const uint32_t mfma_fwd = ctx->al.fwd_levels;
+    const bool stepwise = stepwise_forward(ctx);
     const bool wide_now = sizeof(S) == 8;
+    const size_t rec0 = ctx->hy.probe ? ctx->hy.probe->recs.size() : 0;
     while (nlev < 0) {
-        // With products at some forward level the host needs each level's
-        // largest count first, so levels go one at a time.
-        const int32_t target = mfma_fwd ? launched + 1 : (launched == 0 ? guess : launched + 2);
+        const int32_t target = stepwise ? launched + 1 : (launched == 0 ? guess : launched + 2);
         st = ensure_levels(ctx, target + 1);
         if (st != BC_OK) return st;
         for (int32_t l = launched; l < target; ++l) {
@@ -635,10 +687,12 @@ bc_status run_batch_t(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool acc
                 tm.done();
                 continue;
             }
-            if (l < 32 && ((mfma_fwd >> l) & 1)) {
+            ProbeScope ps(ctx);
+            if (stepwise && by_products(ctx, l, true)) {
                 st = algebraic_forward_level(ctx, wide_now, s.front + (size_t)l * words,
                                              s.front + (size_t)(l + 1) * words, s.any + (size_t)(l + 1) * aw);
                 if (st != BC_OK) return st;
+                ps.done(true, l);
                 continue;
             }
             LaunchTimer tm(ctx, "fwd_pull");
@@ -647,9 +701,10 @@ bc_status run_batch_t(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool acc
                                s.visited, sigma, (unsigned long long *)s.hacc, s.arrive, s.any + (size_t)(l + 1) * aw,
                                ctx->status);
             tm.done();
+            ps.done(true, l);
         }
         BC_HIP(ctx, hipGetLastError());
-        const int32_t first = mfma_fwd ? target : 1; // levels whose filter is read back
+        const int32_t first = stepwise ? target : 1; // levels whose filter is read back
         BC_HIP(ctx, hipMemcpyAsync(s.any_host + (size_t)first * aw, s.any + (size_t)first * aw,
                                    (size_t)(target - first + 1) * aw * sizeof(uint32_t), hipMemcpyDeviceToHost,
                                    ctx->stream));
@@ -677,9 +732,11 @@ bc_status run_batch_t(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool acc
         const bool deeper = lv + 1 < nlev;
         const uint64_t *fnext = deeper ? s.front + (size_t)(lv + 1) * words : nullptr;
         const uint32_t *anext = deeper ? s.any + (size_t)(lv + 1) * aw : nullptr;
-        if (deeper && lv < 32 && ((ctx->al.bwd_levels >> lv) & 1)) {
+        ProbeScope ps(ctx);
+        if (deeper && by_products(ctx, lv, false)) {
             st = algebraic_backward_level(ctx, sizeof(S) == 8, fcur, fnext, ddump, accumulate);
             if (st != BC_OK) return st;
+            ps.done(false, lv);
             continue;
         }
         LaunchTimer tm(ctx, "bwd_pull");
@@ -691,8 +748,25 @@ bc_status run_batch_t(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool acc
             hipLaunchKernelGGL((k_bwd_pull<NW, S>), dim3(pull_blocks), dim3(SB), 0, ctx->stream, t, fcur, anext, fnext,
                                (const S *)sigma, s.cval, s.src, ctx->bc, s.hacc, s.arrive, ddump, accumulate ? 1 : 0);
         tm.done();
+        ps.done(false, lv);
     }
     BC_HIP(ctx, hipGetLastError());
+    if (LevelProbe *p = ctx->hy.probe) {
+        // Levels past the deepest were launched speculatively and did nothing;
+        // level 0 of the backward is not a level the hybrid choice covers.
+        size_t keep = rec0;
+        for (size_t i = rec0; i < p->recs.size(); ++i) {
+            LevelProbe::Rec r = p->recs[i];
+            if (r.level < 1 || r.level >= nlev) {
+                bc_event_put(ctx, r.a);
+                bc_event_put(ctx, r.b);
+                continue;
+            }
+            r.density = level_density(ctx, r.level);
+            p->recs[keep++] = r;
+        }
+        p->recs.resize(keep);
+    }
     ctx->max_levels = std::max(ctx->max_levels, nlev);
     *nlev_out = nlev;
     return BC_OK;
@@ -781,6 +855,23 @@ bc_status sparse_prepare(bc_ctx *ctx, int32_t batch, int32_t split_degree) {
     BC_HIP(ctx, hipMemsetAsync(s.hacc, 0, nh * batch * sizeof(double), ctx->stream));
     BC_HIP(ctx, hipStreamSynchronize(ctx->stream)); // host vectors above go out of scope
     return ensure_levels(ctx, 16);
+}
+
+bc_status sparse_batch(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool accumulate) {
+    int32_t nlev = 0;
+    return run_batch(ctx, d_src, count, accumulate, &nlev);
+}
+
+bc_status sparse_release(bc_ctx *ctx) {
+    SparseState &s = ctx->sp;
+    BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    for (void *p : {(void *)s.front, (void *)s.any, (void *)s.visited, (void *)s.sigma, (void *)s.cval,
+                    (void *)s.delta_dump, (void *)s.src, (void *)s.heavy_id, (void *)s.heavy_nseg, (void *)s.arrive,
+                    (void *)s.arrive_w, (void *)s.seg_v, (void *)s.seg_beg, (void *)s.seg_end, (void *)s.hacc})
+        if (p) bc_dfree(ctx, p);
+    if (s.any_host) hipHostFree(s.any_host);
+    s = SparseState{};
+    return BC_OK;
 }
 
 bc_status sparse_run(bc_ctx *ctx, const int32_t *d_src, int64_t count) {

@@ -1,0 +1,357 @@
+// Autotuning of the batched forms.
+//
+// The paper analyses one method at a time; choosing between them per level is
+// this library's own addition.  Before any timed work, the tuner fixes
+//   * the batch width B of the sparse and hybrid forms, and
+//   * the hybrid form's two density thresholds: forward level l -> l+1 (and
+//     backward level l) is computed by products with the dense adjacency
+//     (Sec. 3.1) when the level's union-frontier density reaches the
+//     threshold, and by CSR pulls (the level sweep of Sec. 4) otherwise.
+// It measures calibration batches of sources drawn from the graph itself,
+// each width once with every level by pulls and once with every level >= 1 by
+// products, records every level's GPU time and density, and picks for each
+// direction the threshold that minimises the summed time of the recorded
+// levels.  Results are cached per process and, optionally, in a text file.
+#include "bc_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+namespace {
+
+constexpr int32_t kTinyN = 2048;                    // smaller graphs take the defaults
+constexpr size_t kStateBudget = size_t(24) << 30;   // batch state allowed for a candidate width
+constexpr size_t kHybridAdjBudget = size_t(16) << 30; // dense adjacency allowed for the hybrid form
+constexpr int kReps = 2;                            // timed calibration batches per width and mode
+constexpr double kSyncMs = 0.02;                    // host round trip per level of a stepwise forward
+constexpr double kNever = 2.0;                      // a threshold no density reaches
+constexpr double kAccept = 0.97;                    // a mix must beat pulls by 3% to be kept
+constexpr int kConfirm = 3;                         // alternating whole-batch comparisons of a mix
+
+struct TuneResult {
+    int32_t batch;
+    double theta_fwd, theta_bwd;
+};
+
+std::mutex g_mu;
+std::map<std::string, TuneResult> g_cache;
+
+uint64_t fnv1a(const void *p, size_t n, uint64_t h = 1469598103934665603ull) {
+    const unsigned char *b = (const unsigned char *)p;
+    for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+    return h;
+}
+
+// Graph shape key: n, m, the degree histogram in log2 buckets quantised to
+// 1/64 of the vertices, the form, the requested width, the row split and the
+// device.
+std::string make_key(const bc_ctx *ctx, bc_form form, int32_t req_batch, int32_t split) {
+    int64_t hist[33] = {0};
+    const std::vector<int32_t> &rp = ctx->h_row_ptr;
+    for (int32_t v = 0; v < ctx->n; ++v) {
+        const uint32_t d = (uint32_t)(rp[(size_t)v + 1] - rp[(size_t)v]) + 1u;
+        ++hist[31 - __builtin_clz(d)];
+    }
+    uint8_t q[33];
+    for (int k = 0; k < 33; ++k) q[k] = (uint8_t)std::lround(64.0 * (double)hist[k] / std::max(ctx->n, 1));
+    hipDeviceProp_t prop{};
+    if (hipGetDeviceProperties(&prop, ctx->device) != hipSuccess) std::strcpy(prop.gcnArchName, "unknown");
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "n=%d m=%lld dh=%016llx form=%d batch=%d split=%d arch=%s cu=%d", ctx->n,
+                  (long long)ctx->nnz / 2, (unsigned long long)fnv1a(q, sizeof q), (int)form, req_batch, split,
+                  prop.gcnArchName, prop.multiProcessorCount);
+    for (char *c = buf; *c; ++c)
+        if (*c == '\t' || *c == '\n') *c = ' ';
+    return buf;
+}
+
+// File format: one entry per line, "<key>\t<batch> <theta_fwd> <theta_bwd>";
+// the last entry for a key wins; lines starting with '#' are ignored.
+bool file_lookup(const char *path, const std::string &key, TuneResult &out) {
+    std::ifstream f(path);
+    if (!f) return false;
+    bool found = false;
+    std::string line;
+    while (std::getline(f, line)) {
+        if (line.empty() || line[0] == '#') continue;
+        const size_t tab = line.find('\t');
+        if (tab == std::string::npos || line.compare(0, tab, key) != 0 || tab != key.size()) continue;
+        std::istringstream v(line.substr(tab + 1));
+        TuneResult r{};
+        if (v >> r.batch >> r.theta_fwd >> r.theta_bwd) {
+            out = r;
+            found = true;
+        }
+    }
+    return found;
+}
+
+void file_store(const char *path, const std::string &key, const TuneResult &r) {
+    FILE *f = std::fopen(path, "a");
+    if (!f) return; // an unwritable cache only costs a later calibration
+    std::fprintf(f, "%s\t%d %.17g %.17g\n", key.c_str(), r.batch, r.theta_fwd, r.theta_bwd);
+    std::fclose(f);
+}
+
+uint64_t fmix64(uint64_t x) {
+    x ^= x >> 33;
+    x *= 0xff51afd7ed558ccdull;
+    x ^= x >> 33;
+    x *= 0xc4ceb9fe1a85ec53ull;
+    return x ^ (x >> 33);
+}
+
+size_t state_bytes(int32_t n, int32_t batch) {
+    // counts (8 B) and coefficients (4 B) per (vertex, source), plus 16
+    // levels of frontier bits
+    return (size_t)n * batch * 12 + (size_t)16 * n * (batch / 8);
+}
+
+bool products_possible(const bc_ctx *ctx) {
+    if (ctx->weighted || ctx->max_degree > 65792) return false;
+    const size_t npad = (size_t)std::max(64, (ctx->n + 63) / 64 * 64);
+    return npad * npad * 2 <= kHybridAdjBudget;
+}
+
+bc_status prepare_width(bc_ctx *ctx, int32_t batch, int32_t split, bool products) {
+    bc_status st = sparse_prepare(ctx, batch, split);
+    if (st == BC_OK && products) st = algebraic_prepare(ctx);
+    return st;
+}
+
+bc_status release_width(bc_ctx *ctx, bool products) {
+    bc_status st = sparse_release(ctx);
+    if (st == BC_OK && products) st = algebraic_release(ctx);
+    return st;
+}
+
+struct Sample {
+    double density = 0.0, t_pull = 0.0, t_prod = 0.0;
+    bool has_pull = false, has_prod = false;
+};
+using SampleKey = std::pair<int, std::pair<int, int>>; // (batch index, (forward, level))
+
+struct Calibration {
+    std::map<SampleKey, Sample> samples;
+};
+
+// Modes of a calibration run: per-level probes with every level by pulls or
+// by products, or whole batches without probes, with the current thresholds
+// or with pulls only.
+enum { kProbePulls = 1, kProbeProducts = 2, kPlainMixed = 3, kPlainPulls = 4 };
+
+// Runs batches [0, kReps] (batch 0 warms up) of the calibration sources;
+// per-level times go into cal.samples and the device time per source of the
+// timed batches into *ms_per_source.
+bc_status run_mode(bc_ctx *ctx, const int32_t *d_src, int32_t B, int mode, Calibration &cal,
+                   double *ms_per_source) {
+    LevelProbe probe;
+    probe.mode = mode == kProbeProducts ? 2 : 1;
+    const bool products = ctx->hy.products;
+    if (mode == kProbePulls || mode == kProbeProducts) ctx->hy.probe = &probe;
+    if (mode == kPlainPulls) ctx->hy.products = false;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    bc_status st = BC_OK;
+    std::vector<size_t> batch_end;
+    if (!(t0 = bc_event_get(ctx)) || !(t1 = bc_event_get(ctx))) st = bc_fail(ctx, BC_ERR_DEVICE, "hipEventCreate failed");
+    for (int j = 0; j <= kReps && st == BC_OK; ++j) {
+        if (j == 1 && hipEventRecord(t0, ctx->stream) != hipSuccess) st = bc_fail(ctx, BC_ERR_DEVICE, "hipEventRecord failed");
+        if (st == BC_OK) st = sparse_batch(ctx, d_src + (size_t)j * B, B, true);
+        batch_end.push_back(probe.recs.size());
+    }
+    if (st == BC_OK && hipEventRecord(t1, ctx->stream) != hipSuccess) st = bc_fail(ctx, BC_ERR_DEVICE, "hipEventRecord failed");
+    if (st == BC_OK && hipEventSynchronize(t1) != hipSuccess) st = bc_fail(ctx, BC_ERR_DEVICE, "calibration failed");
+    if (st == BC_OK) {
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, t0, t1);
+        *ms_per_source = (double)ms / ((double)kReps * B);
+    }
+    size_t j = 0;
+    for (size_t i = 0; i < probe.recs.size(); ++i) {
+        while (j < batch_end.size() && i >= batch_end[j]) ++j;
+        const LevelProbe::Rec &r = probe.recs[i];
+        if (st == BC_OK && j >= 1) { // batch 0 warms up
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, r.a, r.b);
+            Sample &smp = cal.samples[{(int)j, {r.forward ? 1 : 0, r.level}}];
+            smp.density = r.density;
+            if (mode == kProbePulls) {
+                smp.t_pull = ms;
+                smp.has_pull = true;
+            } else {
+                smp.t_prod = ms;
+                smp.has_prod = true;
+            }
+        }
+        bc_event_put(ctx, r.a);
+        bc_event_put(ctx, r.b);
+    }
+    bc_event_put(ctx, t0);
+    bc_event_put(ctx, t1);
+    ctx->hy.probe = nullptr;
+    ctx->hy.products = products;
+    return st;
+}
+
+// Threshold for one direction minimising the summed level time of the
+// samples; *saved_ms is the time it saves over all-pulls.  Ties keep pulls.
+double fit_threshold(const Calibration &cal, bool forward, double *saved_ms) {
+    std::vector<const Sample *> v;
+    for (const auto &kv : cal.samples)
+        if ((kv.first.second.first == 1) == forward && kv.second.has_pull && kv.second.has_prod) v.push_back(&kv.second);
+    double all_pull = 0.0;
+    for (const Sample *s : v) all_pull += s->t_pull;
+    double best_theta = kNever, best = all_pull;
+    for (const Sample *c : v) {
+        const double theta = c->density;
+        double cost = forward ? kSyncMs * (double)v.size() : 0.0;
+        for (const Sample *s : v) cost += s->density >= theta ? s->t_prod : s->t_pull;
+        if (cost < best || (cost == best && theta > best_theta && best_theta <= 1.0)) {
+            best = cost;
+            best_theta = theta;
+        }
+    }
+    *saved_ms = all_pull - best;
+    return best_theta;
+}
+
+void clear_after_calibration(bc_ctx *ctx) {
+    bc_timers_clear(ctx);
+    ctx->max_levels = 0;
+}
+
+} // namespace
+
+bc_status tune_prepare(bc_ctx *ctx, const bc_options &opt, bc_form form) {
+    const bool hybrid = form == BC_FORM_HYBRID;
+    const int32_t split = opt.split_degree;
+    if (hybrid && opt.batch != 0 && opt.batch != 256 && opt.batch != 512)
+        return bc_fail(ctx, BC_ERR_INVALID_ARG, "hybrid form: batch must be 0 (tuned), 256 or 512");
+    const bool products = hybrid && products_possible(ctx);
+    ctx->hy = HybridState{};
+    ctx->hy.products = products;
+    if (!hybrid && opt.batch != 0) return sparse_prepare(ctx, opt.batch, split); // nothing to tune
+
+    const std::string key = make_key(ctx, form, opt.batch, split);
+    // The caller's file comes first, then what this process measured before.
+    TuneResult r{};
+    bool hit = opt.tune_cache && file_lookup(opt.tune_cache, key, r);
+    if (!hit) {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_cache.find(key);
+        if (it != g_cache.end()) {
+            r = it->second;
+            hit = true;
+        }
+    }
+    if (hit) {
+        const bool ok_width = r.batch == 128 || r.batch == 256 || r.batch == 512 || (!hybrid && r.batch == 64);
+        if (!ok_width || (hybrid && r.batch % 256 != 0) || (opt.batch != 0 && r.batch != opt.batch))
+            return bc_fail(ctx, BC_ERR_INVALID_ARG, "tuning cache: entry for this graph names an unusable batch width");
+        bc_status st = prepare_width(ctx, r.batch, split, products);
+        if (st != BC_OK) return st;
+        ctx->hy.theta_fwd = products ? r.theta_fwd : kNever;
+        ctx->hy.theta_bwd = products ? r.theta_bwd : kNever;
+        ctx->hy.tune_source = BC_TUNE_CACHED;
+        return BC_OK;
+    }
+    if (ctx->n < kTinyN) { // calibration would time launch latency only
+        const int32_t w = opt.batch ? opt.batch : 256;
+        bc_status st = prepare_width(ctx, w, split, products);
+        ctx->hy.tune_source = BC_TUNE_DEFAULT;
+        if (st == BC_OK && opt.tune_cache) file_store(opt.tune_cache, key, TuneResult{w, kNever, kNever});
+        return st;
+    }
+
+    std::vector<int32_t> widths;
+    if (opt.batch) widths.push_back(opt.batch);
+    else if (hybrid) widths = {256, 512};
+    else widths = {128, 256, 512};
+    while (widths.size() > 1 && state_bytes(ctx->n, widths.back()) > kStateBudget) widths.pop_back();
+
+    const int32_t maxw = widths.back();
+    const size_t nsrc = (size_t)(kReps + 1) * maxw;
+    std::vector<int32_t> h_src(nsrc);
+    for (size_t i = 0; i < nsrc; ++i) h_src[i] = (int32_t)(fmix64(0x0809190600ull + i) % (uint64_t)ctx->n);
+    int32_t *d_src = (int32_t *)bc_dalloc(ctx, nsrc * sizeof(int32_t));
+    if (!d_src) return bc_fail(ctx, BC_ERR_NOMEM, "tuning: source buffer allocation failed");
+    BC_HIP(ctx, hipMemcpy(d_src, h_src.data(), nsrc * sizeof(int32_t), hipMemcpyHostToDevice));
+
+    double best_ms = 0.0;
+    int32_t best_w = 0, prepared = 0;
+    double best_tf = kNever, best_tb = kNever;
+    bc_status st = BC_OK;
+    for (int32_t w : widths) {
+        if (prepared) st = release_width(ctx, products);
+        if (st == BC_OK) st = prepare_width(ctx, w, split, products);
+        if (st != BC_OK) break;
+        prepared = w;
+        Calibration cal;
+        double ms = 0.0, unused = 0.0;
+        st = run_mode(ctx, d_src, w, kPlainPulls, cal, &ms);
+        if (st == BC_OK && products) st = run_mode(ctx, d_src, w, kProbePulls, cal, &unused);
+        if (st == BC_OK && products) st = run_mode(ctx, d_src, w, kProbeProducts, cal, &unused);
+        if (st != BC_OK) break;
+        double tf = kNever, tb = kNever, saved = 0.0;
+        if (products) {
+            tf = fit_threshold(cal, true, &saved);
+            tb = fit_threshold(cal, false, &saved);
+        }
+        if (tf <= 1.0 || tb <= 1.0) {
+            // The per-level fit leaves out host round trips and launch gaps:
+            // keep the mix only if whole batches with it beat pulls, timed
+            // alternately so that both see the same cache and clock state.
+            ctx->hy.theta_fwd = tf;
+            ctx->hy.theta_bwd = tb;
+            double mixed = 0.0, pulls = 0.0;
+            for (int rep = 0; rep < kConfirm && st == BC_OK; ++rep) {
+                double a = 0.0, b = 0.0;
+                st = run_mode(ctx, d_src, w, kPlainMixed, cal, &a);
+                if (st == BC_OK) st = run_mode(ctx, d_src, w, kPlainPulls, cal, &b);
+                mixed += a;
+                pulls += b;
+            }
+            if (st != BC_OK) break;
+            if (mixed < kAccept * pulls) ms = mixed / kConfirm;
+            else {
+                tf = tb = kNever;
+                ms = pulls / kConfirm;
+            }
+        }
+        if (best_w == 0 || ms < best_ms) {
+            best_ms = ms;
+            best_w = w;
+            best_tf = tf;
+            best_tb = tb;
+        }
+    }
+    bc_dfree(ctx, d_src);
+    if (st == BC_OK && prepared != best_w) {
+        st = release_width(ctx, products);
+        if (st == BC_OK) st = prepare_width(ctx, best_w, split, products);
+    }
+    if (st != BC_OK) return st;
+    // Calibration added to BC and may have flagged an overflow: start clean.
+    BC_HIP(ctx, hipMemsetAsync(ctx->bc, 0, sizeof(double) * (size_t)std::max(ctx->n, 1), ctx->stream));
+    BC_HIP(ctx, hipMemsetAsync(ctx->status, 0, 256, ctx->stream));
+    BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    clear_after_calibration(ctx);
+    ctx->hy.theta_fwd = best_tf;
+    ctx->hy.theta_bwd = best_tb;
+    ctx->hy.tune_source = BC_TUNE_MEASURED;
+    r = TuneResult{best_w, best_tf, best_tb};
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_cache[key] = r;
+    }
+    if (opt.tune_cache) file_store(opt.tune_cache, key, r);
+    return BC_OK;
+}

@@ -3,6 +3,7 @@ and rejects invalid input before any device work (no GPU needed)."""
 import ctypes
 import os
 import re
+import subprocess
 
 import numpy as np
 import pytest
@@ -38,6 +39,30 @@ def test_options_defaults():
     opt = bcgpu.bc_options_init()
     assert opt.struct_size == ctypes.sizeof(B.bc_options)
     assert opt.form == B.BC_FORM_AUTO and opt.batch == 0 and opt.device == -1
+    assert opt.tune_cache is None
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """sizeof and every field offset of the C structs, from a C program
+    compiled against bc.h, equal the ctypes mirrors."""
+    structs = {"bc_options": B.bc_options, "bc_info": B.bc_info, "bc_graph": B.bc_graph,
+               "bc_allocator": B.bc_allocator}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "bc.h"', 'int main(void) {']
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for field, _ in cls._fields_:
+            lines.append(f'printf("{name} {field} %zu\\n", offsetof({name}, {field}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    for line in filter(None, out):
+        name, field, value = line.split()
+        cls = structs[name]
+        want = ctypes.sizeof(cls) if field == "size" else getattr(cls, field).offset
+        assert int(value) == want, f"{name}.{field}: C {value}, ctypes {want}"
 
 
 def _graph_struct(n, rp, col, w=None):
@@ -111,7 +136,7 @@ def test_invalid_arguments():
 
 def test_batched_forms_refuse_weights_before_device_work():
     g = gg.with_uniform_weights(gg.path(5), 1, 1, 9)
-    for form in (B.BC_FORM_SPARSE, B.BC_FORM_ALGEBRAIC):
+    for form in (B.BC_FORM_SPARSE, B.BC_FORM_ALGEBRAIC, B.BC_FORM_HYBRID):
         opt = bcgpu.bc_options_init()
         opt.form = form
         st, msg = _create_status(g.n, g.row_ptr, g.col, g.weight, opt)
