@@ -1,14 +1,24 @@
-"""Benchmark: betweenness TEPS on RMAT scale 16 (all sources), the batched
-mixed-precision form (hybrid: sparse pulls or MFMA products per level, as the
-tuner chose before timing) against the plain FP64 per-source form on the same
-GPU.
+"""Benchmark: betweenness TEPS on MI355X, with the oracle timed beside it.
 
-One step = one complete all-source betweenness computation (forward sweep,
-backward sweep and accumulation for every vertex as a source) over the
-synthetic RMAT-16 graph, inputs resident in HBM.  TEPS = sources * m / t with
-m the undirected edge count after preprocessing.
+Default workload (the headline): RMAT scale 16, all sources, the batched
+mixed-precision form (hybrid: each level by sparse pulls or by MFMA products,
+as the tuner chose before timing; batches of 256 sources) against the plain
+FP64 per-source form on the same GPU.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+One step = one complete betweenness computation over the workload (forward
+sweep, backward sweep and accumulation for every source), inputs resident in
+HBM.  TEPS = sources * m / t, m = undirected edges after preprocessing (for
+the many-graph workload, the sum over graphs of n_g * m_g).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+                    [--form F] [--batch B] [--no-cpu-baseline] [--no-compare]
+
+Other workloads (same JSON schema; used for profiles and design figures):
+  er16384  ER n=16384, degree 256, all sources: algebraic form, batch 512,
+           against the sparse and hybrid forms
+  ws4096   4096 Watts-Strogatz graphs, all sources: one persistent launch
+  rmat20w  RMAT-20 with weights U{1..255}, 4096 sampled sources: bucketed
+           shortest paths per source
 
 Prints one JSON line.  Profiling runs use --sources N (a bounded prefix of the
 sources) and --calibrate-copy (a 1 GiB device-to-device copy at the end, the
@@ -17,6 +27,7 @@ reference against which rocprofv3 FETCH_SIZE / WRITE_SIZE are scaled).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,17 +37,38 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-import hashlib  # noqa: E402
-
 import numpy as np  # noqa: E402
 
 METRIC = "BC TEPS (sources·m/s) on RMAT-16; batched-MFMA vs plain BFS form, same GPU"
 HBM_PEAK_GBS = 8000.0
 MFMA_BF16_PEAK_TFS = 2500.0
 
-
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sparse_rmat16_traffic.txt")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_0809_1906_amd", "csrc", "sparse.hip")
+
+WORKLOADS = {
+    "rmat16": {"form": "hybrid", "batch": 256, "compare": [("plain", 0)],
+               "desc": "rmat16: RMAT scale 16, edgefactor 16, (a,b,c,d)=(.57,.19,.19,.05), symmetrised, "
+                       "deduplicated, largest component; exact all-source BC"},
+    "er16384": {"form": "algebraic", "batch": 512, "compare": [("sparse", 512), ("hybrid", 512)],
+                "desc": "er16384: Erdos-Renyi n=16384, average degree 256, largest component; exact "
+                        "all-source BC"},
+    "ws4096": {"form": "many", "batch": 0, "compare": [],
+               "desc": "ws4096: 4096 Watts-Strogatz graphs, n ~ U{64..4096}, k=6, p=0.1, seeded per graph; "
+                       "exact all-source BC of every graph in one persistent launch"},
+    "rmat20w": {"form": "plain", "batch": 0, "compare": [],
+                "desc": "rmat20w: RMAT scale 20, edgefactor 16, largest component, weights U{1..255}; BC "
+                        "over 4096 sources sampled without replacement"},
+}
+
+DTYPES = {
+    "plain": "u64 counts, f64 dependency state and sums",
+    "sparse": "u64 counts, f32 dependency state, f64 sums",
+    "hybrid": "u64 counts, f32 dependency state, f64 sums; bf16 MFMA products (8-bit limbs) where chosen",
+    "algebraic": "bf16 MFMA products of 8-bit count limbs with f32 accumulate, u64 counts, f32 dependency "
+                 "state, f64 sums",
+    "many": "u64 counts, f32 dependency state, f64 sums",
+}
 
 
 def kernel_source_hash() -> str:
@@ -44,11 +76,11 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, workload: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, or None when the summary is missing or the kernel source changed
-    since the counters were taken."""
-    if not os.path.exists(TRAFFIC_FILE):
+    summary, or None when the summary is missing, covers another workload, or
+    the kernel source changed since the counters were taken."""
+    if workload != "rmat16" or not os.path.exists(TRAFFIC_FILE):
         return None
     fields = {}
     with open(TRAFFIC_FILE) as f:
@@ -67,33 +99,111 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes_per_source(n: int, m: int) -> dict:
-    """Bytes one source's sweeps must move at minimum in the per-source model:
-    each pass reads the int32 column array once (8m for 2m arcs) and about
-    24 B of per-vertex state (row offsets, level, count, dependency and a
-    share of the BC update): 8m + 24n per pass, 16m + 48n per source."""
-    per_pass = 8 * m + 24 * n
-    return {"fwd": per_pass, "bwd": per_pass, "total": 2 * per_pass}
+def pass_bytes(n: int, m: int) -> int:
+    """Bytes one source's sweep must move at minimum per pass in the
+    per-source model: the int32 column array once (8m for 2m arcs) and about
+    24 B of per-vertex state (row offsets, level, count, dependency and a share
+    of the BC update): 8m + 24n per pass, 16m + 48n per source."""
+    return 8 * m + 24 * n
 
 
-def cpu_baseline(g, target_s: float = 12.0):
-    """The oracle as it stands, on a bounded sample of sources, all host cores
-    it may use (at most 16)."""
+def weighted_bytes(n: int, m: int) -> int:
+    """Per source, weighted: the forward reads every arc's column (4 B) and
+    weight (1 B, the values fit a byte), the backward only the DAG arcs (a few
+    percent), plus about 50 B of per-vertex state: 10m + 50n."""
+    return 10 * m + 50 * n
+
+
+def load_workload(name, sources):
+    import graphgen as gg
+    t0 = time.perf_counter()
+    if name == "ws4096":
+        gs = gg.ws_batch(4096)
+        n = sum(g.n for g in gs)
+        m = sum(g.m for g in gs)
+        log(f"graphs ws4096: {len(gs)} graphs, sum n={n}, sum m={m}, gen {time.perf_counter() - t0:.1f}s")
+        return {"graph": gs, "n": n, "m": m, "src": None, "S": n,
+                "work": float(sum(g.n * g.m for g in gs))}
+    if name == "rmat20w":
+        g, src = gg.rmat20w()
+    else:
+        g = getattr(gg, name)()
+        src = None
+    log(f"graph {name} n={g.n} m={g.m} max_deg={int(g.degrees().max())} gen {time.perf_counter() - t0:.1f}s")
+    if sources > 0:
+        src = (np.arange(min(sources, g.n), dtype=np.int32) if src is None else src[:sources])
+    S = g.n if src is None else int(src.size)
+    return {"graph": g, "n": g.n, "m": g.m, "src": src, "S": S, "work": float(S) * g.m}
+
+
+def cpu_baseline(name, wl, target_s: float = 12.0):
+    """The oracle as it stands, on a bounded sample of the workload, all host
+    cores it may use (at most 16)."""
     import oracle
     threads = max(1, min(16, os.cpu_count() or 1))
-    sample0 = np.arange(0, g.n, max(1, g.n // (2 * threads)))[: 2 * threads].astype(np.int32)
+    if name == "ws4096":
+        gs = wl["graph"]
+        order = list(range(0, len(gs), 97))
+        t0 = time.perf_counter()
+        done, work = 0, 0.0
+        for i in order:
+            oracle.bc(gs[i], threads=threads)
+            done += 1
+            work += gs[i].n * gs[i].m
+            if time.perf_counter() - t0 > target_s:
+                break
+        t = time.perf_counter() - t0
+        return {"value": work / t, "unit": "TEPS", "cores": threads, "kind": "oracle",
+                "sample": f"{done} of {len(gs)} graphs (every 97th), all sources each, {threads} threads "
+                          f"over sources, {t:.1f} s"}
+    g = wl["graph"]
+    pool = wl["src"] if wl["src"] is not None else np.arange(g.n, dtype=np.int32)
+    probe = pool[np.linspace(0, pool.size - 1, min(pool.size, threads)).astype(np.int64)]
     t0 = time.perf_counter()
-    oracle.bc(g, sample0, threads=threads)
-    t_cal = time.perf_counter() - t0
-    per_src = t_cal / sample0.size
-    count = int(min(g.n, max(sample0.size, target_s / max(per_src, 1e-9))))
-    sample = np.linspace(0, g.n - 1, count).astype(np.int32)
+    oracle.bc(g, probe, threads=threads)
+    per_src = (time.perf_counter() - t0) / probe.size
+    count = int(min(pool.size, max(probe.size, target_s / max(per_src, 1e-9))))
+    sample = pool[np.linspace(0, pool.size - 1, count).astype(np.int64)]
     t0 = time.perf_counter()
     oracle.bc(g, sample, threads=threads)
     t = time.perf_counter() - t0
     return {"value": count * g.m / t, "unit": "TEPS", "cores": threads, "kind": "oracle",
-            "sample": f"{count} of {g.n} sources (evenly spaced ids), serial Brandes per source, "
+            "sample": f"{count} of {pool.size} sources (evenly spaced), serial Brandes per source, "
                       f"{threads} threads over sources, {t:.1f} s"}
+
+
+KERNELS = ("fwd_pull", "bwd_pull", "fwd_push0", "batch_init", "limb_split", "mfma_fwd", "coef_split", "mfma_bwd",
+           "plain_sweep", "weighted_sweep", "multigraph_sweep")
+
+
+def roofline(name, wl, kern, info, steps):
+    """Roofline of the dominant kernel: algorithmic bytes (or flops) per
+    launch over its average launch time from HIP events in the timed region."""
+    dom = max(kern, key=lambda k: kern[k][0])
+    ms, launches = kern[dom]
+    n, m, S = wl["n"], wl["m"], wl["S"]
+    base = {"kernel": dom, "avg_launch_ms": ms / max(launches, 1), "launches": launches}
+    if dom in ("mfma_fwd", "mfma_bwd"):
+        npad = (n + 63) // 64 * 64
+        planes = launches * (3 if dom == "mfma_bwd" else 1)
+        flops = 2.0 * info.batch * npad * npad * planes
+        ach = flops / (ms * 1e-3) / 1e12
+        return dict(base, bound="mfma", achieved=ach, peak=MFMA_BF16_PEAK_TFS, unit="TFLOP/s",
+                    frac=ach / MFMA_BF16_PEAK_TFS, traffic=None,
+                    alg_flops_per_launch=flops / max(launches, 1),
+                    note="issued dense products: 2 * batch * npad^2 per limb or coefficient plane")
+    if dom == "weighted_sweep":
+        total = float(S) * steps * weighted_bytes(n, m)
+    elif dom == "multigraph_sweep":
+        total = float(steps) * sum(g.n * (2 * pass_bytes(g.n, g.m)) for g in wl["graph"])
+        base["note"] = "per-source state is LDS-resident; HBM model only"
+    elif dom == "plain_sweep":
+        total = float(S) * steps * 2 * pass_bytes(n, m)
+    else:
+        total = float(S) * steps * pass_bytes(n, m)
+    ach = total / (ms * 1e-3) / 1e9
+    return dict(base, bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
+                traffic=measured_traffic(dom, name), alg_bytes_per_launch=total / max(launches, 1))
 
 
 def main():
@@ -101,12 +211,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--batch", type=int, default=256)
-    ap.add_argument("--form", default="hybrid", choices=["hybrid", "sparse", "algebraic"])
+    ap.add_argument("--workload", default="rmat16", choices=sorted(WORKLOADS))
+    ap.add_argument("--form", default=None, help="form of the measured line (default: the workload's)")
+    ap.add_argument("--batch", type=int, default=None, help="batch width (default: the workload's; 0 = tuned)")
+    ap.add_argument("--no-compare", "--no-plain", dest="no_compare", action="store_true",
+                    help="skip the comparison forms")
+    ap.add_argument("--compare-steps", "--plain-steps", dest="compare_steps", type=int, default=1)
     ap.add_argument("--no-free-batch", action="store_true", help="skip the extra run at the tuned batch width")
-    ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--sources", type=int, default=0, help="run only the first N sources (profiling)")
     ap.add_argument("--calibrate-copy", action="store_true", help="end with a 1 GiB device copy")
     args = ap.parse_args()
@@ -117,7 +229,6 @@ def main():
 
     import torch
 
-    import graphgen as gg
     import paper_0809_1906_amd as bcgpu
 
     bcgpu.load()
@@ -125,16 +236,15 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 
-    t0 = time.perf_counter()
-    g = gg.rmat16()
-    log(f"graph rmat16 n={g.n} m={g.m} max_deg={int(g.degrees().max())} gen {time.perf_counter() - t0:.1f}s")
-    S = g.n if args.sources <= 0 else min(args.sources, g.n)
-    src = None if S == g.n else np.arange(S, dtype=np.int32)
-    work = float(S) * g.m
+    spec = WORKLOADS[args.workload]
+    form = args.form or spec["form"]
+    batch = spec["batch"] if args.batch is None else args.batch
+    wl = load_workload(args.workload, args.sources)
+    src, work = wl["src"], wl["work"]
 
     def timed_runs(form, steps, warmup, batch=0, timing=True):
         t = time.perf_counter()
-        ctx = bcgpu.BC(g, form=form, batch=batch, timing=timing)
+        ctx = bcgpu.BC(wl["graph"], form="auto" if form == "many" else form, batch=batch, timing=timing)
         info = ctx.info()
         log(f"{form} create (upload, dense adjacency, tuning) {time.perf_counter() - t:.2f}s: batch {info.batch}, "
             f"products when density >= ({info.mfma_density_fwd:.3f} fwd, {info.mfma_density_bwd:.3f} bwd), "
@@ -148,64 +258,46 @@ def main():
         t = time.perf_counter()
         for i in range(steps):
             ctx.run(src)
-        torch.cuda.synchronize()
+            torch.cuda.synchronize()
+            log(f"{form} step {i} done")
         dt = (time.perf_counter() - t) / steps
         bc = ctx.read()
         log(f"{form} {steps} steps: {dt * 1e3:.1f} ms/step, {work / dt:.3e} TEPS")
         return ctx, dt, bc
 
-    ctx, dt, bc_sparse = timed_runs(args.form, args.steps, args.warmup, args.batch)
+    ctx, dt, bc_main = timed_runs(form, args.steps, args.warmup, batch)
     info = ctx.info()
     kern = {}
-    for k in ("fwd_pull", "bwd_pull", "fwd_push0", "batch_init", "limb_split", "mfma_fwd", "coef_split", "mfma_bwd"):
+    for k in KERNELS:
         ms, launches = ctx.timing(k)
         if launches:
             kern[k] = (ms, launches)
     log("kernel times (ms, launches):", kern)
-
-    bytes_src = algorithmic_bytes_per_source(g.n, g.m)
-    dom = max(kern, key=lambda k: kern[k][0])
-    dom_ms, dom_launches = kern[dom]
-    if dom in ("fwd_pull", "bwd_pull"):
-        alg_total = float(S) * args.steps * bytes_src["fwd" if dom == "fwd_pull" else "bwd"]
-        achieved = alg_total / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else None
-        roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": measured_traffic(dom),
-                    "avg_launch_ms": dom_ms / max(dom_launches, 1), "launches": dom_launches,
-                    "alg_bytes_per_launch": alg_total / max(dom_launches, 1)}
-    else:
-        # products: issued MFMA work is 2 * batch * npad * npad per limb or
-        # coefficient plane; launches already count one plane each for the
-        # forward, three planes per launch for the backward
-        npad = (g.n + 63) // 64 * 64
-        planes = dom_launches * (3 if dom == "mfma_bwd" else 1)
-        flops = 2.0 * info.batch * npad * npad * planes
-        achieved = flops / (dom_ms * 1e-3) / 1e12 if dom_ms > 0 else None
-        roofline = {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": MFMA_BF16_PEAK_TFS,
-                    "unit": "TFLOP/s", "frac": (achieved / MFMA_BF16_PEAK_TFS) if achieved else None,
-                    "traffic": None, "avg_launch_ms": dom_ms / max(dom_launches, 1), "launches": dom_launches}
+    roof = roofline(args.workload, wl, kern, info, args.steps)
     ctx.close()
 
     free = None
-    if not args.no_free_batch and args.batch != 0:
-        fctx, fdt, _ = timed_runs(args.form, 1, 1, 0, timing=False)
+    if form in ("hybrid", "sparse") and batch != 0 and not args.no_free_batch:
+        fctx, fdt, _ = timed_runs(form, 1, 1, 0, timing=False)
         finfo = fctx.info()
         fctx.close()
         free = {"batch": finfo.batch, "value": work / fdt, "ms_per_step": fdt * 1e3,
                 "mfma_density": [finfo.mfma_density_fwd, finfo.mfma_density_bwd]}
 
-    plain = None
-    if not args.no_plain:
-        pctx, pdt, bc_plain = timed_runs("plain", args.plain_steps, 0)
-        pms, pl = pctx.timing("plain_sweep")
-        pctx.close()
-        # each context accumulated its own number of steps
-        per_sparse, per_plain = bc_sparse / args.steps, bc_plain / args.plain_steps
-        err = float(np.max(np.abs(per_sparse - per_plain) / np.maximum(np.abs(per_plain), 1.0)))
-        plain = {"value": work / pdt, "ms_per_step": pdt * 1e3, "kernel_ms": pms,
-                 "sparse_vs_plain_max_rel_diff": err}
+    compare = {}
+    if not args.no_compare:
+        for cform, cbatch in spec["compare"]:
+            cctx, cdt, bc_c = timed_runs(cform, args.compare_steps, 0, cbatch)
+            cinfo = cctx.info()
+            ckern = {k: cctx.timing(k)[0] for k in KERNELS if cctx.timing(k)[1]}
+            cctx.close()
+            # each context accumulated its own number of steps
+            per_main, per_c = bc_main / args.steps, bc_c / args.compare_steps
+            err = float(np.max(np.abs(per_main - per_c) / np.maximum(np.abs(per_c), 1.0)))
+            compare[cform] = {"value": work / cdt, "ms_per_step": cdt * 1e3, "batch": cinfo.batch,
+                              "kernel_ms": ckern, "max_rel_diff_vs_measured": err}
 
-    cpu = None if args.no_cpu_baseline else cpu_baseline(g)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args.workload, wl)
 
     if args.calibrate_copy:
         x = torch.empty(256 << 20, dtype=torch.float32, device=dev)  # 1 GiB
@@ -215,8 +307,13 @@ def main():
         torch.cuda.synchronize()
         log("calibration copy: 1 GiB read, 1 GiB written")
 
+    config = {"workload": spec["desc"], "n": wl["n"], "m": wl["m"], "sources": wl["S"], "batch": info.batch,
+              "form": form, "levels_max": info.max_levels}
+    if form in ("hybrid", "sparse", "algebraic"):
+        config["mfma_density_thresholds"] = [info.mfma_density_fwd, info.mfma_density_bwd]
+        config["tune_source"] = ["default", "measured", "cached"][info.tune_source]
     out = {
-        "metric": METRIC,
+        "metric": METRIC if args.workload == "rmat16" else f"BC TEPS (sources·m/s) on {args.workload}",
         "value": work / dt,
         "unit": "TEPS",
         "n_gpus": 1,
@@ -226,21 +323,19 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u64 counts, f32 dependency state, f64 sums",
+        "dtype": DTYPES[form],
         "data": "synthetic",
-        "config": {"workload": "rmat16: RMAT scale 16, edgefactor 16, (a,b,c,d)=(.57,.19,.19,.05), "
-                               "symmetrised, deduplicated, largest component; exact all-source BC",
-                   "n": g.n, "m": g.m, "sources": S, "batch": info.batch, "form": args.form,
-                   "mfma_density_thresholds": [info.mfma_density_fwd, info.mfma_density_bwd],
-                   "tune_source": ["default", "measured", "cached"][info.tune_source],
-                   "levels_max": info.max_levels},
+        "config": config,
         "tuned_batch_width": free,
-        "plain_fp64": plain,
+        "compare": compare,
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kern.items()},
-        "batched_vs_plain": (plain["ms_per_step"] / (dt * 1e3)) if plain else None,
-        "roofline": roofline,
+        "roofline": roof,
         "cpu_baseline": cpu,
     }
+    if args.workload == "rmat16" and "plain" in compare:
+        # the headline ratio: batched mixed-precision form over the plain FP64 form
+        out["plain_fp64"] = compare["plain"]
+        out["batched_vs_plain"] = compare["plain"]["ms_per_step"] / (dt * 1e3)
     print(json.dumps(out), flush=True)
 
 

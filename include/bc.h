@@ -239,8 +239,15 @@ typedef struct {
     double mfma_density_bwd; /* hybrid form: backward level l by products when
                                 density(l) >= this (above 1: never) */
     int32_t tune_source;     /* BC_TUNE_* for the batch width and thresholds */
+    int64_t mfma_planes;     /* products with the adjacency issued since create /
+                                reset: one per 8-bit limb of a forward level, three
+                                per backward level; each is batch * npad^2
+                                multiply-adds, 2 * batch * npad^2 flops (npad = n
+                                rounded up to 64) */
 } bc_info;
 
+/* Fills *out; synchronises the context's stream (mfma_planes is read from the
+ * device). */
 bc_status bc_get_info(const bc_ctx *ctx, bc_info *out);
 
 /*

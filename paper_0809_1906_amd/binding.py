@@ -70,7 +70,8 @@ class bc_info(ctypes.Structure):
                 ("weighted", ctypes.c_int32), ("form", ctypes.c_int), ("batch", ctypes.c_int32),
                 ("max_levels", ctypes.c_int32), ("sources_run", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("mfma_density_fwd", ctypes.c_double),
-                ("mfma_density_bwd", ctypes.c_double), ("tune_source", ctypes.c_int32)]
+                ("mfma_density_bwd", ctypes.c_double), ("tune_source", ctypes.c_int32),
+                ("mfma_planes", ctypes.c_int64)]
 
 
 # Every symbol include/bc.h declares, with its ctypes signature.

@@ -9,7 +9,10 @@
 // F_l is split into 8-bit limbs F^(k) (each exact in BF16), every product
 // A . F^(k) is accumulated in FP32 -- exact, because each output is an integer
 // of at most 255 * deg(w) < 2^24 (deg <= 65792 is checked at create) -- and the
-// limbs are recombined as sum_k 2^(8k) P^(k) in 64-bit integers.
+// limbs are recombined as sum_k 2^(8k) P^(k) in 64-bit integers, with a carry
+// out of 64 bits reported as an overflowing count.  The number of limbs comes
+// from the largest count of level l, which the kernel that wrote level l
+// recorded on the device, so no host round trip precedes the products.
 //
 // Backward (Compute Dependency): with C_{l+1}[w][b] = (1 + delta(w,b)) /
 // lambda(s_b, w) for w at level l+1 (the "(D_l + Delta_l) div Lambda" matrix of
@@ -45,19 +48,18 @@ constexpr int GT = 256;  // threads per block
 constexpr int SA = GK + 8; // LDS row stride of the adjacency tile, in BF16 (padding against bank conflicts)
 constexpr int PB = 256;  // threads per block of the element-wise kernels
 
-enum { EPI_ONLY = 0, EPI_FIRST = 1, EPI_MID = 2, EPI_LAST = 3, EPI_BWD = 4 };
+enum { EPI_ONLY = 0, EPI_FIRST = 1, EPI_MID = 2, EPI_LAST = 3 };
 
 struct GemmArgs {
     const __bf16 *adj;     // [npad][npad]
-    const __bf16 *planes;  // NP planes of [npad/8][B][8]
+    const __bf16 *planes;  // planes of [npad/8][B][8]
     const uint32_t *kflags;// [npad/GK][B/GN]: some plane entry of this k-tile is non-zero
     int32_t npad, n, B, NW;
     size_t plane_elems;    // npad * B
 };
 
 struct EpiArgs {
-    int shift;             // 8 * limb index
-    uint64_t *part;        // [npad][B] partial limb sums (FIRST/MID/LAST)
+    uint64_t *part;        // [npad][B] partial limb sums
     const uint64_t *fcur;  // backward: front[l]
     uint64_t *fnext;       // forward: front[l+1]
     uint64_t *visited;
@@ -66,7 +68,9 @@ struct EpiArgs {
     const int32_t *src_lane;
     double *bc, *delta_dump;
     uint32_t *any_next, *status;
-    unsigned long long *level_max; // forward: max count of the new level
+    const unsigned long long *lvmax_cur; // forward: largest count of level l
+    unsigned long long *lvmax_next;      // forward: largest count of level l+1
+    unsigned long long *planes_issued;   // products issued (limb or coefficient planes)
     int accumulate;
 };
 
@@ -74,6 +78,13 @@ __device__ __forceinline__ void store_count(uint64_t *p, uint64_t x, bool &) { *
 __device__ __forceinline__ void store_count(uint32_t *p, uint64_t x, bool &wide) {
     wide |= x > 0xFFFFFFFFull;
     *p = (uint32_t)x;
+}
+
+// 8-bit limbs needed for a count (at least one).
+__device__ __forceinline__ int limbs_of(uint64_t mx) {
+    int L = 1;
+    while (L < 8 && (mx >> (8 * L)) != 0) ++L;
+    return L;
 }
 
 // ---- the product -------------------------------------------------------------------
@@ -87,7 +98,8 @@ struct Stage {
 };
 
 template <int NP>
-__device__ __forceinline__ void load_stage(const GemmArgs &g, int kt, int w0, int b0, int tid, Stage<NP> &st) {
+__device__ __forceinline__ void load_stage(const GemmArgs &g, const __bf16 *planes, int kt, int w0, int b0, int tid,
+                                           Stage<NP> &st) {
     const int row = tid >> 2, kq = tid & 3;
     st.a = *reinterpret_cast<const u32x4 *>(g.adj + (size_t)(w0 + row) * g.npad + (size_t)kt * GK + kq * 8);
 #pragma unroll
@@ -95,7 +107,7 @@ __device__ __forceinline__ void load_stage(const GemmArgs &g, int kt, int w0, in
 #pragma unroll
         for (int i = 0; i < 4; ++i)
             st.x[p * 4 + i] = *reinterpret_cast<const u32x4 *>(
-                g.planes + (size_t)p * g.plane_elems + (((size_t)kt * (GK / 8) + i) * g.B + b0 + tid) * 8);
+                planes + (size_t)p * g.plane_elems + (((size_t)kt * (GK / 8) + i) * g.B + b0 + tid) * 8);
 }
 
 template <int NP>
@@ -136,19 +148,15 @@ __device__ __forceinline__ int next_tile(const uint32_t *flags, int ntn, int kt,
     return kt;
 }
 
-// C[w][b] = sum over k-tiles with a non-zero flag of A[w][k] X[k][b], then the
-// epilogue.  Grid: (npad / GM, B / GN); 4 waves, wave wv owns sources
-// [b0 + 64 wv, b0 + 64 wv + 64) = one bitmap word, for all 64 rows of the block.
-template <int NP, int MODE, typename S>
-__global__ __launch_bounds__(GT) void k_mfma(GemmArgs g, EpiArgs e) {
-    __shared__ __align__(16) __bf16 sA[2][GM * SA];
-    __shared__ __align__(16) __bf16 sX[2][NP * 4 * GN * 8];
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int w0 = blockIdx.x * GM, b0 = blockIdx.y * GN;
+// acc[w][b] = sum over k-tiles with a non-zero flag of A[w][k] X_p[k][b],
+// summed over the NP planes starting at `planes`, for the block's 64 rows
+// and its 256 sources (wave wv: sources [b0 + 64 wv, b0 + 64 wv + 64)).
+template <int NP>
+__device__ __forceinline__ void gemm_tile(const GemmArgs &g, const __bf16 *planes, int w0, int b0, int tid,
+                                          __bf16 (*sA)[GM * SA], __bf16 (*sX)[NP * 4 * GN * 8], f32x16 (&acc)[2][2]) {
+    const int lane = tid & 63, wv = tid >> 6;
     const int nkt = g.npad / GK, ntn = g.B / GN;
     const uint32_t *flags = g.kflags + blockIdx.y;
-
-    f32x16 acc[2][2];
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
@@ -160,121 +168,165 @@ __global__ __launch_bounds__(GT) void k_mfma(GemmArgs g, EpiArgs e) {
     int buf = 0;
     Stage<NP> st;
     if (kt < nkt) {
-        load_stage<NP>(g, kt, w0, b0, tid, st);
+        load_stage<NP>(g, planes, kt, w0, b0, tid, st);
         store_stage<NP>(sA[0], sX[0], tid, st);
     }
     __syncthreads();
     while (kt < nkt) {
         const int kn = next_tile(flags, ntn, kt + 1, nkt);
-        if (kn < nkt) load_stage<NP>(g, kn, w0, b0, tid, st); // in flight during the products
+        if (kn < nkt) load_stage<NP>(g, planes, kn, w0, b0, tid, st); // in flight during the products
         mma_stage<NP>(sA[buf], sX[buf], lane, wv, acc);
         if (kn < nkt) store_stage<NP>(sA[buf ^ 1], sX[buf ^ 1], tid, st);
         __syncthreads();
         buf ^= 1;
         kt = kn;
     }
+}
 
-    // ---- epilogue ----
-    const int q = (b0 >> 6) + wv;           // bitmap word of this wave's sources
+// Forward epilogue for limb `shift / 8`; `mode` (uniform over the launch) says
+// whether it is the only limb, the first, a middle one or the last.  Lane
+// layout of the 32x32 output: lane l, register r holds row 8(r/4) + 4(l/32) +
+// r%4 and column l%32.
+template <typename S>
+__device__ __forceinline__ void epi_fwd(const GemmArgs &g, const EpiArgs &e, int mode, int shift,
+                                        const f32x16 (&acc)[2][2], int w0, int q, int lane) {
     const int half = lane >> 5, col = lane & 31;
-    if constexpr (MODE == EPI_BWD) {
-        S *sigma = reinterpret_cast<S *>(e.sigma);
+    const bool first = mode == EPI_FIRST, mid = mode == EPI_MID, last = mode == EPI_LAST;
+    const bool final_limb = mode == EPI_ONLY || last;
+    S *sigma = reinterpret_cast<S *>(e.sigma);
+    bool wide = false, ovf = false;
+    uint64_t mx = 0;
 #pragma unroll
-        for (int rt = 0; rt < 2; ++rt) {
+    for (int rt = 0; rt < 2; ++rt) {
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int v = w0 + rt * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
-                const uint64_t F = v < g.n ? e.fcur[(size_t)v * g.NW + q] : 0;
-                double contrib = 0.0;
+        for (int r = 0; r < 16; ++r) {
+            const int w = w0 + rt * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+            const bool valid = w < g.n;
+            const uint64_t vis = (!first && valid) ? e.visited[(size_t)w * g.NW + q] : ~0ull;
+            uint64_t m[2];
 #pragma unroll
-                for (int ct = 0; ct < 2; ++ct) {
-                    const int bit = ct * 32 + col;
-                    if ((F >> bit) & 1) {
-                        const size_t idx = (size_t)v * g.B + (size_t)q * 64 + bit;
-                        const double sv = (double)sigma[idx];
-                        const double dl = sv * (double)acc[rt][ct][r];
-                        e.cval[idx] = (float)((1.0 + dl) / sv);
-                        if (e.delta_dump) e.delta_dump[idx] = dl;
-                        if (e.src_lane[q * 64 + bit] != v) contrib += dl;
-                    }
-                }
-                if (e.accumulate) {
-#pragma unroll
-                    for (int off = 16; off > 0; off >>= 1) contrib += __shfl_xor(contrib, off, 64);
-                    if (col == 0 && contrib != 0.0) unsafeAtomicAdd(&e.bc[v], contrib);
-                }
-            }
-        }
-    } else {
-        S *sigma = reinterpret_cast<S *>(e.sigma);
-        bool wide = false, ovf = false;
-        uint64_t mx = 0;
-#pragma unroll
-        for (int rt = 0; rt < 2; ++rt) {
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int w = w0 + rt * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
-                const bool valid = w < g.n;
-                uint64_t vis = ~0ull;
-                if (MODE != EPI_FIRST) vis = valid ? e.visited[(size_t)w * g.NW + q] : ~0ull;
-                uint64_t m[2];
-#pragma unroll
-                for (int ct = 0; ct < 2; ++ct) {
-                    const int bit = ct * 32 + col;
-                    const uint64_t P = (uint64_t)acc[rt][ct][r]; // exact integer < 2^24
-                    bool fresh = false;
-                    // A limb sum that carries out of 64 bits is a count above
-                    // 2^64 - 1 when w is unvisited (a level-(l+1) vertex);
-                    // visited vertices' sums are discarded.
-                    const bool open = valid && !((vis >> bit) & 1);
-                    if (MODE == EPI_FIRST) {
-                        if (valid) e.part[(size_t)w * g.B + (size_t)q * 64 + bit] = P;
-                    } else if (MODE == EPI_MID) {
-                        if (valid) {
-                            uint64_t &pt = e.part[(size_t)w * g.B + (size_t)q * 64 + bit];
-                            const uint64_t add = P << e.shift, sum = pt + add;
-                            if (open && ((P >> (64 - e.shift)) != 0 || sum < add)) ovf = true;
-                            pt = sum;
-                        }
+            for (int ct = 0; ct < 2; ++ct) {
+                const int bit = ct * 32 + col;
+                const uint64_t P = (uint64_t)acc[rt][ct][r]; // exact integer < 2^24
+                const size_t idx = (size_t)w * g.B + (size_t)q * 64 + bit;
+                // A limb sum that carries out of 64 bits is a count above
+                // 2^64 - 1 when w is unvisited (a level-(l+1) vertex);
+                // visited vertices' sums are discarded.
+                const bool open = valid && !((vis >> bit) & 1);
+                bool fresh = false;
+                if (first) {
+                    if (valid) e.part[idx] = P;
+                } else {
+                    const uint64_t add = P << shift;
+                    uint64_t tot = add;
+                    if (valid && (mid || last)) tot += e.part[idx];
+                    if (open && shift > 0 && ((P >> (64 - shift)) != 0 || tot < add)) ovf = true;
+                    if (mid) {
+                        if (valid) e.part[idx] = tot;
                     } else {
-                        uint64_t tot = P << e.shift;
-                        if (MODE == EPI_LAST && valid) {
-                            const uint64_t add = tot;
-                            tot += e.part[(size_t)w * g.B + (size_t)q * 64 + bit];
-                            if (open && ((P >> (64 - e.shift)) != 0 || tot < add)) ovf = true;
-                        }
                         fresh = open && tot != 0;
                         if (fresh) {
-                            store_count(&sigma[(size_t)w * g.B + (size_t)q * 64 + bit], tot, wide);
+                            store_count(&sigma[idx], tot, wide);
                             mx = tot > mx ? tot : mx;
                         }
                     }
-                    m[ct] = __ballot(fresh);
                 }
-                if (MODE == EPI_ONLY || MODE == EPI_LAST) {
-                    // lanes 0..31 hold vertex w of half 0, lanes 32..63 vertex w + 4
-                    const uint64_t word = half == 0 ? ((m[0] & 0xFFFFFFFFull) | (m[1] << 32))
-                                                    : ((m[0] >> 32) | (m[1] & 0xFFFFFFFF00000000ull));
-                    if (col == 0 && valid) {
-                        e.fnext[(size_t)w * g.NW + q] = word;
-                        if (word) {
-                            e.visited[(size_t)w * g.NW + q] = vis | word;
-                            atomicOr(&e.any_next[w >> 5], 1u << (w & 31));
-                        }
+                m[ct] = __ballot(fresh);
+            }
+            if (final_limb) {
+                // lanes 0..31 hold vertex w of half 0, lanes 32..63 vertex w + 4
+                const uint64_t word = half == 0 ? ((m[0] & 0xFFFFFFFFull) | (m[1] << 32))
+                                                : ((m[0] >> 32) | (m[1] & 0xFFFFFFFF00000000ull));
+                if (col == 0 && valid) {
+                    e.fnext[(size_t)w * g.NW + q] = word;
+                    if (word) {
+                        e.visited[(size_t)w * g.NW + q] = vis | word;
+                        atomicOr(&e.any_next[w >> 5], 1u << (w & 31));
                     }
                 }
             }
         }
-        if (MODE == EPI_ONLY || MODE == EPI_LAST) {
+    }
+    if (final_limb) {
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                const uint64_t o = __shfl_xor(mx, off, 64);
-                mx = o > mx ? o : mx;
-            }
-            if (lane == 0 && mx) atomicMax(e.level_max, (unsigned long long)mx);
-            if (__any(wide) && lane == 0) atomicOr(&e.status[1], 1u);
+        for (int off = 32; off > 0; off >>= 1) {
+            const uint64_t o = __shfl_xor(mx, off, 64);
+            mx = o > mx ? o : mx;
         }
-        if (MODE != EPI_FIRST && __any(ovf) && lane == 0) atomicOr(&e.status[0], (uint32_t)BC_DEV_SIGMA_OVERFLOW);
+        if (lane == 0 && mx > __hip_atomic_load(e.lvmax_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax(e.lvmax_next, (unsigned long long)mx);
+        if (__any(wide) && lane == 0) atomicOr(&e.status[1], 1u);
+    }
+    if (__any(ovf) && lane == 0) atomicOr(&e.status[0], (uint32_t)BC_DEV_SIGMA_OVERFLOW);
+}
+
+// Forward level l -> l+1: one pass per 8-bit limb of level l's largest count,
+// each followed by its epilogue.  Grid: (npad / GM, B / GN).
+template <typename S>
+__global__ __launch_bounds__(GT) void k_mfma_fwd(GemmArgs g, EpiArgs e) {
+    __shared__ __align__(16) __bf16 sA[2][GM * SA];
+    __shared__ __align__(16) __bf16 sX[2][4 * GN * 8];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int w0 = blockIdx.x * GM, b0 = blockIdx.y * GN;
+    const int q = (b0 >> 6) + wv; // bitmap word of this wave's sources
+    const int L = limbs_of(*e.lvmax_cur);
+    if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) atomicAdd(e.planes_issued, (unsigned long long)L);
+    f32x16 acc[2][2];
+#pragma nounroll
+    for (int k = 0; k < L; ++k) {
+        gemm_tile<1>(g, g.planes + (size_t)k * g.plane_elems, w0, b0, tid, sA, sX, acc);
+        const int mode = L == 1 ? EPI_ONLY : k == 0 ? EPI_FIRST : k + 1 < L ? EPI_MID : EPI_LAST;
+        // The epilogue's row addresses do not depend on k; an opaque copy of
+        // the block's first row keeps the compiler from computing all of them
+        // once before the loop and holding them through the products.
+        int w0k = w0;
+        __asm__ volatile("" : "+s"(w0k));
+        epi_fwd<S>(g, e, mode, 8 * k, acc, w0k, q, lane);
+        __syncthreads(); // the next limb's pipeline reuses the LDS tiles
+    }
+}
+
+// Backward level l: acc = A . (hi + mid + lo planes of C_{l+1}), then
+// delta(v,b) = lambda(v,b) * acc for v at level l, c(v,b) = (1 + delta) / lambda,
+// and BC(v) += delta summed over the block's sources (v != s_b).
+template <typename S>
+__global__ __launch_bounds__(GT) void k_mfma_bwd(GemmArgs g, EpiArgs e) {
+    __shared__ __align__(16) __bf16 sA[2][GM * SA];
+    __shared__ __align__(16) __bf16 sX[2][3 * 4 * GN * 8];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int w0 = blockIdx.x * GM, b0 = blockIdx.y * GN;
+    if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) atomicAdd(e.planes_issued, 3ull);
+    f32x16 acc[2][2];
+    gemm_tile<3>(g, g.planes, w0, b0, tid, sA, sX, acc);
+
+    const int q = (b0 >> 6) + wv;
+    const int half = lane >> 5, col = lane & 31;
+    S *sigma = reinterpret_cast<S *>(e.sigma);
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int v = w0 + rt * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+            const uint64_t F = v < g.n ? e.fcur[(size_t)v * g.NW + q] : 0;
+            double contrib = 0.0;
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct) {
+                const int bit = ct * 32 + col;
+                if ((F >> bit) & 1) {
+                    const size_t idx = (size_t)v * g.B + (size_t)q * 64 + bit;
+                    const double sv = (double)sigma[idx];
+                    const double dl = sv * (double)acc[rt][ct][r];
+                    e.cval[idx] = (float)((1.0 + dl) / sv);
+                    if (e.delta_dump) e.delta_dump[idx] = dl;
+                    if (e.src_lane[q * 64 + bit] != v) contrib += dl;
+                }
+            }
+            if (e.accumulate) {
+#pragma unroll
+                for (int off = 16; off > 0; off >>= 1) contrib += __shfl_xor(contrib, off, 64);
+                if (col == 0 && contrib != 0.0) unsafeAtomicAdd(&e.bc[v], contrib);
+            }
+        }
     }
 }
 
@@ -288,37 +340,18 @@ __global__ __launch_bounds__(PB) void k_build_adj(int32_t n, int32_t npad, const
     for (int32_t e = rp[v] + threadIdx.x; e < rp[v + 1]; e += PB) adj[(size_t)v * npad + col[e]] = one;
 }
 
-// Largest count at level l (for the number of 8-bit limbs).
+// planes[k][v/8][b][v%8] = limb k of lambda(s_b, v) for v at level l, else 0,
+// for the limbs of level l's largest count; kflags[v / GK][b / GN] |= (some
+// limb non-zero).  Thread (vg, b) covers 8 rows.
 template <typename S>
-__global__ __launch_bounds__(PB) void k_level_max(int32_t n, int32_t B, int32_t NW, const uint64_t *__restrict__ fl,
-                                                  const S *__restrict__ sigma, unsigned long long *out) {
-    uint64_t mx = 0;
-    const size_t total = (size_t)n * B;
-    for (size_t i = (size_t)blockIdx.x * PB + threadIdx.x; i < total; i += (size_t)gridDim.x * PB) {
-        const size_t v = i / B;
-        const int b = (int)(i - v * B);
-        if ((fl[v * NW + (b >> 6)] >> (b & 63)) & 1) {
-            const uint64_t s = (uint64_t)sigma[i];
-            mx = s > mx ? s : mx;
-        }
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const uint64_t o = __shfl_xor(mx, off, 64);
-        mx = o > mx ? o : mx;
-    }
-    if ((threadIdx.x & 63) == 0 && mx) atomicMax(out, (unsigned long long)mx);
-}
-
-// planes[k][v/8][b][v%8] = limb k of lambda(s_b, v) for v at level l, else 0;
-// kflags[v / GK][b / GN] |= (some limb non-zero).  Thread (vg, b) covers 8 rows.
-template <typename S>
-__global__ __launch_bounds__(PB) void k_limb_split(int32_t n, int32_t npad, int32_t B, int32_t NW, int32_t L,
+__global__ __launch_bounds__(PB) void k_limb_split(int32_t n, int32_t npad, int32_t B, int32_t NW,
+                                                   const unsigned long long *__restrict__ lvmax_cur,
                                                    const uint64_t *__restrict__ fl, const S *__restrict__ sigma,
                                                    __bf16 *__restrict__ planes, size_t plane_elems,
                                                    uint32_t *__restrict__ kflags) {
     const size_t id = (size_t)blockIdx.x * PB + threadIdx.x;
     if (id >= (size_t)(npad / 8) * B) return;
+    const int L = limbs_of(*lvmax_cur);
     const int32_t vg = (int32_t)(id / B), b = (int32_t)(id - (size_t)vg * B);
     uint64_t s[8];
     bool nz = false;
@@ -403,12 +436,11 @@ bc_status algebraic_prepare(bc_ctx *ctx) {
     a.planes = (__bf16 *)bc_dalloc(ctx, 8 * plane_elems * sizeof(__bf16)); // up to 8 limbs, or 3 coefficient planes
     a.part = (uint64_t *)bc_dalloc(ctx, plane_elems * sizeof(uint64_t));
     a.kflags = (uint32_t *)bc_dalloc(ctx, (size_t)(a.npad / GK) * (B / GN) * sizeof(uint32_t));
-    a.level_max = (unsigned long long *)bc_dalloc(ctx, 256);
-    a.host = nullptr;
-    if (!a.adj || !a.planes || !a.part || !a.kflags || !a.level_max ||
-        hipHostMalloc((void **)&a.host, 256) != hipSuccess)
+    a.planes_issued = (unsigned long long *)bc_dalloc(ctx, 256);
+    if (!a.adj || !a.planes || !a.part || !a.kflags || !a.planes_issued)
         return bc_fail(ctx, BC_ERR_NOMEM, "algebraic form: allocation failed");
     BC_HIP(ctx, hipMemsetAsync(a.adj, 0, adj_bytes, ctx->stream));
+    BC_HIP(ctx, hipMemsetAsync(a.planes_issued, 0, sizeof(unsigned long long), ctx->stream));
     if (ctx->n > 0)
         hipLaunchKernelGGL(k_build_adj, dim3(ctx->n), dim3(PB), 0, ctx->stream, ctx->n, a.npad, ctx->row_ptr,
                            ctx->col, a.adj);
@@ -419,69 +451,47 @@ bc_status algebraic_prepare(bc_ctx *ctx) {
 bc_status algebraic_release(bc_ctx *ctx) {
     AlgebraicState &a = ctx->al;
     BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    for (void *p : {(void *)a.adj, (void *)a.planes, (void *)a.part, (void *)a.kflags, (void *)a.level_max})
+    for (void *p : {(void *)a.adj, (void *)a.planes, (void *)a.part, (void *)a.kflags, (void *)a.planes_issued})
         if (p) bc_dfree(ctx, p);
-    if (a.host) hipHostFree(a.host);
     const bool every = a.every_level;
     a = AlgebraicState{};
     a.every_level = every;
     return BC_OK;
 }
 
-// Largest count among level-l entries of the batch (synchronises).
-template <typename S>
-static bc_status level_max(bc_ctx *ctx, const uint64_t *fl, uint64_t *out) {
-    AlgebraicState &a = ctx->al;
-    const SparseState &s = ctx->sp;
-    BC_HIP(ctx, hipMemsetAsync(a.level_max, 0, sizeof(unsigned long long), ctx->stream));
-    const size_t total = (size_t)ctx->n * s.batch;
-    hipLaunchKernelGGL(k_level_max<S>, dim3(std::min<unsigned>(blocks_for(total, PB), 4096)), dim3(PB), 0,
-                       ctx->stream, ctx->n, s.batch, s.words, fl, (const S *)s.sigma, a.level_max);
-    BC_HIP(ctx, hipGetLastError());
-    BC_HIP(ctx, hipMemcpyAsync(a.host, a.level_max, sizeof(unsigned long long), hipMemcpyDeviceToHost, ctx->stream));
-    BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    *out = *a.host;
-    return BC_OK;
-}
-
 // Forward level l -> l+1 as products with A.  Writes front[l+1], visited,
-// counts and any[l+1] exactly as the pull kernel does.
+// counts, any[l+1] and the largest count of level l+1 exactly as the pull
+// kernel does; reads the largest count of level l on the device.
 template <typename S>
-bc_status algebraic_forward_level_t(bc_ctx *ctx, const uint64_t *fcur, uint64_t *fnext, uint32_t *any_next) {
+bc_status algebraic_forward_level_t(bc_ctx *ctx, int32_t l) {
     AlgebraicState &a = ctx->al;
     SparseState &s = ctx->sp;
-    uint64_t mx = 0;
-    bc_status st = level_max<S>(ctx, fcur, &mx);
-    if (st != BC_OK) return st;
-    int L = 1;
-    while (L < 8 && (mx >> (8 * L)) != 0) ++L;
+    const size_t words = (size_t)ctx->n * s.words;
+    const size_t aw = (size_t)(ctx->n + 31) / 32;
+    const uint64_t *fcur = s.front + (size_t)l * words;
     const size_t plane_elems = (size_t)a.npad * s.batch;
     BC_HIP(ctx, hipMemsetAsync(a.kflags, 0, (size_t)(a.npad / GK) * (s.batch / GN) * sizeof(uint32_t), ctx->stream));
     {
         LaunchTimer tm(ctx, "limb_split");
         hipLaunchKernelGGL(k_limb_split<S>, dim3(blocks_for(plane_elems / 8, PB)), dim3(PB), 0, ctx->stream, ctx->n,
-                           a.npad, s.batch, s.words, L, fcur, (const S *)s.sigma, a.planes, plane_elems, a.kflags);
+                           a.npad, s.batch, s.words, s.lvmax + l, fcur, (const S *)s.sigma, a.planes, plane_elems,
+                           a.kflags);
         tm.done();
     }
     EpiArgs e{};
     e.part = a.part;
-    e.fnext = fnext;
+    e.fnext = s.front + (size_t)(l + 1) * words;
     e.visited = s.visited;
     e.sigma = s.sigma;
-    e.any_next = any_next;
+    e.any_next = s.any + (size_t)(l + 1) * aw;
     e.status = ctx->status;
-    e.level_max = a.level_max;
-    const dim3 grid(a.npad / GM, s.batch / GN);
-    for (int k = 0; k < L; ++k) {
-        const GemmArgs g = gemm_args(ctx, a.planes + (size_t)k * plane_elems);
-        e.shift = 8 * k;
-        LaunchTimer tm(ctx, "mfma_fwd");
-        if (L == 1) hipLaunchKernelGGL((k_mfma<1, EPI_ONLY, S>), grid, dim3(GT), 0, ctx->stream, g, e);
-        else if (k == 0) hipLaunchKernelGGL((k_mfma<1, EPI_FIRST, S>), grid, dim3(GT), 0, ctx->stream, g, e);
-        else if (k + 1 < L) hipLaunchKernelGGL((k_mfma<1, EPI_MID, S>), grid, dim3(GT), 0, ctx->stream, g, e);
-        else hipLaunchKernelGGL((k_mfma<1, EPI_LAST, S>), grid, dim3(GT), 0, ctx->stream, g, e);
-        tm.done();
-    }
+    e.lvmax_cur = s.lvmax + l;
+    e.lvmax_next = s.lvmax + l + 1;
+    e.planes_issued = a.planes_issued;
+    const GemmArgs g = gemm_args(ctx, a.planes);
+    LaunchTimer tm(ctx, "mfma_fwd");
+    hipLaunchKernelGGL(k_mfma_fwd<S>, dim3(a.npad / GM, s.batch / GN), dim3(GT), 0, ctx->stream, g, e);
+    tm.done();
     BC_HIP(ctx, hipGetLastError());
     return BC_OK;
 }
@@ -508,21 +518,35 @@ bc_status algebraic_backward_level_t(bc_ctx *ctx, const uint64_t *fcur, const ui
     e.bc = ctx->bc;
     e.delta_dump = delta_dump;
     e.accumulate = accumulate ? 1 : 0;
+    e.planes_issued = a.planes_issued;
     const GemmArgs g = gemm_args(ctx, a.planes);
     LaunchTimer tm(ctx, "mfma_bwd");
-    hipLaunchKernelGGL((k_mfma<3, EPI_BWD, S>), dim3(a.npad / GM, s.batch / GN), dim3(GT), 0, ctx->stream, g, e);
+    hipLaunchKernelGGL(k_mfma_bwd<S>, dim3(a.npad / GM, s.batch / GN), dim3(GT), 0, ctx->stream, g, e);
     tm.done();
     BC_HIP(ctx, hipGetLastError());
     return BC_OK;
 }
 
-bc_status algebraic_forward_level(bc_ctx *ctx, bool wide, const uint64_t *fcur, uint64_t *fnext, uint32_t *any_next) {
-    return wide ? algebraic_forward_level_t<uint64_t>(ctx, fcur, fnext, any_next)
-                : algebraic_forward_level_t<uint32_t>(ctx, fcur, fnext, any_next);
+bc_status algebraic_forward_level(bc_ctx *ctx, bool wide, int32_t l) {
+    return wide ? algebraic_forward_level_t<uint64_t>(ctx, l) : algebraic_forward_level_t<uint32_t>(ctx, l);
 }
 
 bc_status algebraic_backward_level(bc_ctx *ctx, bool wide, const uint64_t *fcur, const uint64_t *fnext,
                                    double *delta_dump, bool accumulate) {
     return wide ? algebraic_backward_level_t<uint64_t>(ctx, fcur, fnext, delta_dump, accumulate)
                 : algebraic_backward_level_t<uint32_t>(ctx, fcur, fnext, delta_dump, accumulate);
+}
+
+int64_t algebraic_planes_issued(bc_ctx *ctx) {
+    AlgebraicState &a = ctx->al;
+    if (!a.planes_issued) return 0;
+    unsigned long long v = 0;
+    if (hipMemcpyAsync(&v, a.planes_issued, sizeof v, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess)
+        return -1;
+    return (int64_t)v;
+}
+
+void algebraic_reset_counters(bc_ctx *ctx) {
+    if (ctx->al.planes_issued) hipMemsetAsync(ctx->al.planes_issued, 0, sizeof(unsigned long long), ctx->stream);
 }

@@ -110,10 +110,8 @@ void release_all(bc_ctx *ctx) {
     ctx->owned.clear();
     if (ctx->status_host) hipHostFree(ctx->status_host);
     if (ctx->sp.any_host) hipHostFree(ctx->sp.any_host);
-    if (ctx->al.host) hipHostFree(ctx->al.host);
     if (ctx->wt.host) hipHostFree(ctx->wt.host);
     ctx->wt.host = nullptr;
-    ctx->al.host = nullptr;
     ctx->status_host = nullptr;
     ctx->sp.any_host = nullptr;
 }
@@ -612,6 +610,7 @@ bc_status bc_reset(bc_ctx *ctx) {
     BC_HIP(ctx, hipMemsetAsync(ctx->status, 0, 256, ctx->stream));
     BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
     bc_timers_clear(ctx);
+    algebraic_reset_counters(ctx);
     ctx->overflow_seen = false;
     ctx->sources_run = 0;
     return BC_OK;
@@ -686,6 +685,7 @@ bc_status bc_get_info(const bc_ctx *ctx, bc_info *out) {
     out->mfma_density_fwd = every ? 0.0 : hybrid ? ctx->hy.theta_fwd : 2.0;
     out->mfma_density_bwd = every ? 0.0 : hybrid ? ctx->hy.theta_bwd : 2.0;
     out->tune_source = ctx->hy.tune_source;
+    out->mfma_planes = ctx->poisoned ? 0 : algebraic_planes_issued(const_cast<bc_ctx *>(ctx));
     return BC_OK;
 }
 

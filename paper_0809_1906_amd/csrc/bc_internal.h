@@ -31,6 +31,7 @@ struct SparseState {
     int32_t split = 256;      // rows longer than this are split into segments
     uint64_t *front = nullptr;   // [level_cap][n][words]
     uint32_t *any = nullptr;     // [level_cap][(n+31)/32] OR over sources, per vertex
+    unsigned long long *lvmax = nullptr; // [level_cap] largest count at each level (for limb counts)
     uint64_t *visited = nullptr; // [n][words]
     uint64_t *sigma = nullptr;   // [n][batch] as uint64, or uint32 in its first half
     float *cval = nullptr;       // [n][batch]  c(v) = (1 + delta(v)) / sigma(v)
@@ -56,8 +57,7 @@ struct AlgebraicState {
     __bf16 *planes = nullptr;          // up to 8 planes of [npad/8][batch][8]
     uint64_t *part = nullptr;          // [npad][batch] partial limb sums
     uint32_t *kflags = nullptr;        // [npad/32][batch/256] non-empty k-tiles
-    unsigned long long *level_max = nullptr;
-    unsigned long long *host = nullptr; // pinned
+    unsigned long long *planes_issued = nullptr; // products issued (limb or coefficient planes)
     bool every_level = false;          // the algebraic form: every level l >= 1 by products
 };
 
@@ -83,6 +83,8 @@ struct HybridState {
     bool products = false;   // the dense adjacency exists and levels may use it
     double theta_fwd = 2.0;  // forward l -> l+1 by products when density(l) >= theta_fwd
     double theta_bwd = 2.0;  // backward l by products when density(l) >= theta_bwd
+    std::vector<double> prev_density; // level densities of the last batch: the forward
+                                      // decides level l from them, so it need not wait
     int32_t tune_source = 0; // BC_TUNE_DEFAULT / BC_TUNE_MEASURED / BC_TUNE_CACHED
     LevelProbe *probe = nullptr;
 };
@@ -231,9 +233,12 @@ bc_status multigraph_dump(bc_ctx *ctx, const int32_t *h_sources, int32_t count, 
 
 bc_status sparse_prepare(bc_ctx *ctx, int32_t batch, int32_t split_degree);
 bc_status algebraic_prepare(bc_ctx *ctx);
-bc_status algebraic_forward_level(bc_ctx *ctx, bool wide, const uint64_t *fcur, uint64_t *fnext, uint32_t *any_next);
+// Forward level l -> l+1 by products (front, counts, any and lvmax of level l+1).
+bc_status algebraic_forward_level(bc_ctx *ctx, bool wide, int32_t l);
 bc_status algebraic_backward_level(bc_ctx *ctx, bool wide, const uint64_t *fcur, const uint64_t *fnext,
                                    double *delta_dump, bool accumulate);
+int64_t algebraic_planes_issued(bc_ctx *ctx); // synchronises; -1 on a device error
+void algebraic_reset_counters(bc_ctx *ctx);
 bc_status sparse_release(bc_ctx *ctx);
 bc_status algebraic_release(bc_ctx *ctx);
 // One batch of at most sp.batch internal source ids (device memory) through

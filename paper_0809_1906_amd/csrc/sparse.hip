@@ -258,7 +258,8 @@ __device__ __forceinline__ void bwd_finalize(int32_t v, const uint64_t (&F)[NW],
 // Clears front levels 0 and 1 (a: 2 * words entries), visited (b) and every
 // level's vertex filter.
 __global__ __launch_bounds__(SB) void k_sp_clear(uint64_t *__restrict__ a, uint64_t *__restrict__ b, size_t words,
-                                                 uint32_t *__restrict__ any_all, size_t any_total) {
+                                                 uint32_t *__restrict__ any_all, size_t any_total,
+                                                 unsigned long long *__restrict__ lvmax, int32_t levels) {
     const size_t tid = (size_t)blockIdx.x * SB + threadIdx.x, stride = (size_t)gridDim.x * SB;
     for (size_t i = tid; i < words; i += stride) {
         a[i] = 0;
@@ -266,6 +267,8 @@ __global__ __launch_bounds__(SB) void k_sp_clear(uint64_t *__restrict__ a, uint6
         b[i] = 0;
     }
     for (size_t i = tid; i < any_total; i += stride) any_all[i] = 0;
+    // every count of level 1 is 1 (the pushed first level)
+    for (size_t i = tid; i < (size_t)levels; i += stride) lvmax[i] = i <= 1 ? 1ull : 0ull;
 }
 
 template <typename S>
@@ -306,6 +309,18 @@ __global__ __launch_bounds__(SB) void k_fwd_push0(Topo t, int32_t NW, const int3
     }
 }
 
+// Largest x over the wave into *dst (every lane of the wave calls).  The
+// maximum settles after a few waves; later waves read it and skip the atomic.
+__device__ __forceinline__ void wave_max_to(unsigned long long *dst, uint64_t x) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint64_t o = __shfl_xor(x, off, 64);
+        x = o > x ? o : x;
+    }
+    if ((threadIdx.x & 63) == 0 && x > __hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        atomicMax(dst, (unsigned long long)x);
+}
+
 // Writes the level-(l+1) words of vertex w (lanes 0..NW-1) and marks any_next.
 template <int NW>
 __device__ __forceinline__ void fwd_commit(int32_t w, const uint64_t (&vis)[NW], const uint64_t (&out)[NW], int lane,
@@ -336,7 +351,8 @@ __global__ __launch_bounds__(SB) void k_fwd_pull(Topo t, const uint32_t *__restr
                                                  const uint64_t *__restrict__ fcur, uint64_t *__restrict__ fnext,
                                                  uint64_t *__restrict__ visited, S *__restrict__ sigma,
                                                  unsigned long long *__restrict__ hacc, uint32_t *__restrict__ arrive,
-                                                 uint32_t *__restrict__ any_next, uint32_t *__restrict__ status) {
+                                                 uint32_t *__restrict__ any_next, uint32_t *__restrict__ status,
+                                                 unsigned long long *__restrict__ lvmax_next) {
     const int lane = threadIdx.x & 63;
     const int64_t wid = (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6);
     Item it;
@@ -361,12 +377,15 @@ __global__ __launch_bounds__(SB) void k_fwd_pull(Topo t, const uint32_t *__restr
     fwd_scan<NW, S>(t, it.beg, it.end, U, any_cur, fcur, sigma, lane, acc, ovf);
     uint64_t out[NW];
     if (it.h < 0) {
+        uint64_t mx = 0;
 #pragma unroll
         for (int q = 0; q < NW; ++q) {
             out[q] = __ballot(acc[q] != 0);
             if (acc[q] != 0) store_count(&sigma[(size_t)w * t.B + (size_t)q * 64 + lane], acc[q], wide);
+            mx = acc[q] > mx ? acc[q] : mx;
         }
         fwd_commit<NW>(w, vis, out, lane, fnext, visited, any_next);
+        if (lvmax_next) wave_max_to(lvmax_next, mx);
     } else {
         unsigned long long *hrow = hacc + (size_t)it.h * t.B + lane;
 #pragma unroll
@@ -377,6 +396,7 @@ __global__ __launch_bounds__(SB) void k_fwd_pull(Topo t, const uint32_t *__restr
             }
         }
         if (last_arriver(&arrive[it.h], t.heavy_nseg[it.h], lane)) {
+            uint64_t mx = 0;
 #pragma unroll
             for (int q = 0; q < NW; ++q) {
                 const uint64_t x = __hip_atomic_load(&hrow[q * 64], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -385,8 +405,10 @@ __global__ __launch_bounds__(SB) void k_fwd_pull(Topo t, const uint32_t *__restr
                     store_count(&sigma[(size_t)w * t.B + (size_t)q * 64 + lane], x, wide);
                 }
                 out[q] = __ballot(x != 0);
+                mx = x > mx ? x : mx;
             }
             fwd_commit<NW>(w, vis, out, lane, fnext, visited, any_next);
+            if (lvmax_next) wave_max_to(lvmax_next, mx);
         }
     }
     if (__any(ovf) && lane == 0) atomicOr(&status[0], (uint32_t)BC_DEV_SIGMA_OVERFLOW);
@@ -558,23 +580,19 @@ int probe_mode(const bc_ctx *ctx) { return ctx->hy.probe ? ctx->hy.probe->mode :
 
 // Does level l (>= 1) go by products with A?  The algebraic form takes them at
 // every level; the hybrid form compares the level's density with a threshold.
+// The backward knows the batch's own densities.  The forward is launched ahead
+// of the host (levels are read back once per several levels), so it decides
+// level l from the density level l had in the previous batch of this context;
+// a level no earlier batch reached goes by pulls.
 bool by_products(const bc_ctx *ctx, int32_t l, bool forward) {
     if (l < 1) return false;
     if (ctx->al.every_level) return true;
     if (!ctx->hy.products) return false;
     const int mode = probe_mode(ctx);
     if (mode != 0) return mode == 2;
-    return level_density(ctx, l) >= (forward ? ctx->hy.theta_fwd : ctx->hy.theta_bwd);
-}
-
-// The forward goes one level at a time (reading each level back) when some
-// level may need products: the decision needs the level's density, and the
-// products need its largest count.
-bool stepwise_forward(const bc_ctx *ctx) {
-    if (ctx->al.every_level) return true;
-    if (!ctx->hy.products) return false;
-    const int mode = probe_mode(ctx);
-    return mode == 2 || (mode == 0 && ctx->hy.theta_fwd <= 1.0);
+    if (!forward) return level_density(ctx, l) >= ctx->hy.theta_bwd;
+    const std::vector<double> &pd = ctx->hy.prev_density;
+    return (size_t)l < pd.size() && pd[(size_t)l] >= ctx->hy.theta_fwd;
 }
 
 // Event pair around one level's work while a probe is attached.
@@ -614,10 +632,12 @@ bc_status ensure_levels(bc_ctx *ctx, int32_t need) {
     }
     uint64_t *nf = (uint64_t *)bc_dalloc(ctx, (size_t)cap * lvl_words * sizeof(uint64_t));
     uint32_t *na = (uint32_t *)bc_dalloc(ctx, (size_t)cap * aw * sizeof(uint32_t));
+    unsigned long long *nm = (unsigned long long *)bc_dalloc(ctx, (size_t)cap * sizeof(unsigned long long));
     uint32_t *nh = nullptr;
-    if (!nf || !na || hipHostMalloc((void **)&nh, (size_t)cap * aw * sizeof(uint32_t)) != hipSuccess) {
+    if (!nf || !na || !nm || hipHostMalloc((void **)&nh, (size_t)cap * aw * sizeof(uint32_t)) != hipSuccess) {
         bc_dfree(ctx, nf);
         bc_dfree(ctx, na);
+        bc_dfree(ctx, nm);
         return bc_fail(ctx, BC_ERR_NOMEM, "sparse form: frontier allocation failed");
     }
     const int32_t old = s.level_cap;
@@ -625,16 +645,21 @@ bc_status ensure_levels(bc_ctx *ctx, int32_t need) {
         BC_HIP(ctx, hipMemcpyAsync(nf, s.front, (size_t)old * lvl_words * sizeof(uint64_t), hipMemcpyDeviceToDevice,
                                    ctx->stream));
         BC_HIP(ctx, hipMemcpyAsync(na, s.any, (size_t)old * aw * sizeof(uint32_t), hipMemcpyDeviceToDevice, ctx->stream));
+        BC_HIP(ctx, hipMemcpyAsync(nm, s.lvmax, (size_t)old * sizeof(unsigned long long), hipMemcpyDeviceToDevice,
+                                   ctx->stream));
     }
     BC_HIP(ctx, hipMemsetAsync(na + (size_t)old * aw, 0, (size_t)(cap - old) * aw * sizeof(uint32_t), ctx->stream));
+    BC_HIP(ctx, hipMemsetAsync(nm + old, 0, (size_t)(cap - old) * sizeof(unsigned long long), ctx->stream));
     BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
     if (s.front) {
         bc_dfree(ctx, s.front);
         bc_dfree(ctx, s.any);
+        bc_dfree(ctx, s.lvmax);
         hipHostFree(s.any_host);
     }
     s.front = nf;
     s.any = na;
+    s.lvmax = nm;
     s.any_host = nh;
     s.level_cap = cap;
     return BC_OK;
@@ -665,18 +690,18 @@ bc_status run_batch_t(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool acc
         LaunchTimer tm(ctx, "batch_init");
         const int blocks = (int)std::min<size_t>((words + SB - 1) / SB, 8192);
         hipLaunchKernelGGL(k_sp_clear, dim3(std::max(blocks, 1)), dim3(SB), 0, ctx->stream, s.front, s.visited, words,
-                           s.any, (size_t)s.level_cap * aw);
+                           s.any, (size_t)s.level_cap * aw, s.lvmax, s.level_cap);
         hipLaunchKernelGGL(k_sp_seed<S>, dim3((B + SB - 1) / SB), dim3(SB), 0, ctx->stream, d_src, count, B, NW,
                            s.front, s.visited, sigma, s.src, s.any);
         tm.done();
         BC_HIP(ctx, hipGetLastError());
     }
     int32_t launched = 0, nlev = -1;
-    const bool stepwise = stepwise_forward(ctx);
     const bool wide_now = sizeof(S) == 8;
+
     const size_t rec0 = ctx->hy.probe ? ctx->hy.probe->recs.size() : 0;
     while (nlev < 0) {
-        const int32_t target = stepwise ? launched + 1 : (launched == 0 ? guess : launched + 2);
+        const int32_t target = launched == 0 ? guess : launched + 2;
         st = ensure_levels(ctx, target + 1);
         if (st != BC_OK) return st;
         for (int32_t l = launched; l < target; ++l) {
@@ -688,9 +713,8 @@ bc_status run_batch_t(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool acc
                 continue;
             }
             ProbeScope ps(ctx);
-            if (stepwise && by_products(ctx, l, true)) {
-                st = algebraic_forward_level(ctx, wide_now, s.front + (size_t)l * words,
-                                             s.front + (size_t)(l + 1) * words, s.any + (size_t)(l + 1) * aw);
+            if (by_products(ctx, l, true)) {
+                st = algebraic_forward_level(ctx, wide_now, l);
                 if (st != BC_OK) return st;
                 ps.done(true, l);
                 continue;
@@ -699,12 +723,12 @@ bc_status run_batch_t(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool acc
             hipLaunchKernelGGL((k_fwd_pull<NW, S>), dim3(pull_blocks), dim3(SB), 0, ctx->stream, t,
                                s.any + (size_t)l * aw, s.front + (size_t)l * words, s.front + (size_t)(l + 1) * words,
                                s.visited, sigma, (unsigned long long *)s.hacc, s.arrive, s.any + (size_t)(l + 1) * aw,
-                               ctx->status);
+                               ctx->status, by_products(ctx, l + 1, true) ? s.lvmax + l + 1 : nullptr);
             tm.done();
             ps.done(true, l);
         }
         BC_HIP(ctx, hipGetLastError());
-        const int32_t first = stepwise ? target : 1; // levels whose filter is read back
+        const int32_t first = 1; // levels whose filter is read back
         BC_HIP(ctx, hipMemcpyAsync(s.any_host + (size_t)first * aw, s.any + (size_t)first * aw,
                                    (size_t)(target - first + 1) * aw * sizeof(uint32_t), hipMemcpyDeviceToHost,
                                    ctx->stream));
@@ -751,6 +775,11 @@ bc_status run_batch_t(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool acc
         ps.done(false, lv);
     }
     BC_HIP(ctx, hipGetLastError());
+    if (ctx->hy.products) {
+        std::vector<double> &pd = ctx->hy.prev_density;
+        pd.assign((size_t)nlev, 0.0);
+        for (int32_t l = 1; l < nlev; ++l) pd[(size_t)l] = level_density(ctx, l);
+    }
     if (LevelProbe *p = ctx->hy.probe) {
         // Levels past the deepest were launched speculatively and did nothing;
         // level 0 of the backward is not a level the hybrid choice covers.
@@ -865,7 +894,7 @@ bc_status sparse_batch(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool ac
 bc_status sparse_release(bc_ctx *ctx) {
     SparseState &s = ctx->sp;
     BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    for (void *p : {(void *)s.front, (void *)s.any, (void *)s.visited, (void *)s.sigma, (void *)s.cval,
+    for (void *p : {(void *)s.front, (void *)s.any, (void *)s.lvmax, (void *)s.visited, (void *)s.sigma, (void *)s.cval,
                     (void *)s.delta_dump, (void *)s.src, (void *)s.heavy_id, (void *)s.heavy_nseg, (void *)s.arrive,
                     (void *)s.arrive_w, (void *)s.seg_v, (void *)s.seg_beg, (void *)s.seg_end, (void *)s.hacc})
         if (p) bc_dfree(ctx, p);

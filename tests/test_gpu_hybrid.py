@@ -66,7 +66,15 @@ def test_hybrid_forced_mix_bc(gpu_lib, tmp_path, name, mix):
         assert info.mfma_density_fwd == tf and info.mfma_density_bwd == tb
         ctx.run()
         got = ctx.read()
+        planes = ctx.info().mfma_planes
     assert rel_err(got, want) <= TOL
+    # the backward decides from the batch's own densities, so products appear
+    # in the first batch already (wherever a level has a deeper one: not in
+    # K_64, of diameter 1); the forward follows the previous batch
+    if (tf, tb) == (0.0, 0.0) and name != "complete64":
+        assert planes > 0
+    if (tf, tb) == (2.0, 2.0):
+        assert planes == 0
 
 
 @pytest.mark.parametrize("mix", range(len(MIXES)))
