@@ -184,14 +184,17 @@ def roofline(name, wl, kern, info, steps):
     n, m, S = wl["n"], wl["m"], wl["S"]
     base = {"kernel": dom, "avg_launch_ms": ms / max(launches, 1), "launches": launches}
     if dom in ("mfma_fwd", "mfma_bwd"):
-        npad = (n + 63) // 64 * 64
-        planes = launches * (3 if dom == "mfma_bwd" else 1)
+        npad = (n + 255) // 256 * 256
+        # a backward launch is three coefficient planes; a forward launch loops
+        # over its level's 8-bit limbs, counted by the library (mfma_planes)
+        bwd_launches = kern.get("mfma_bwd", (0.0, 0))[1]
+        planes = 3 * launches if dom == "mfma_bwd" else max(info.mfma_planes - 3 * bwd_launches, launches)
         flops = 2.0 * info.batch * npad * npad * planes
         ach = flops / (ms * 1e-3) / 1e12
         return dict(base, bound="mfma", achieved=ach, peak=MFMA_BF16_PEAK_TFS, unit="TFLOP/s",
                     frac=ach / MFMA_BF16_PEAK_TFS, traffic=None,
                     alg_flops_per_launch=flops / max(launches, 1),
-                    note="issued dense products: 2 * batch * npad^2 per limb or coefficient plane")
+                    planes=planes, note="issued dense products: 2 * batch * npad^2 per limb or coefficient plane")
     if dom == "weighted_sweep":
         total = float(S) * steps * weighted_bytes(n, m)
     elif dom == "multigraph_sweep":

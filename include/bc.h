@@ -243,7 +243,7 @@ typedef struct {
                                 reset: one per 8-bit limb of a forward level, three
                                 per backward level; each is batch * npad^2
                                 multiply-adds, 2 * batch * npad^2 flops (npad = n
-                                rounded up to 64) */
+                                rounded up to 256) */
 } bc_info;
 
 /* Fills *out; synchronises the context's stream (mfma_planes is read from the

@@ -24,7 +24,7 @@
 // Delta without the diagonal: level 0 is never accumulated).
 //
 // Data layout: A is a dense row-major BF16 [npad][npad] matrix (npad = n
-// rounded up to 64).  Planes are k-packed: plane[v / 8][b][v % 8], so each
+// rounded up to 256, the block's row count).  Planes are k-packed: plane[v / 8][b][v % 8], so each
 // MFMA B-operand lane reads 16 contiguous bytes.  Every product is
 // C[w][b] = sum_v A[w][v] X[v][b] with rows = vertices and columns = sources;
 // in the 32x32 MFMA output the 32 lanes of each half-wave hold 32 consecutive
@@ -41,10 +41,12 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int GM = 64;   // rows (vertices) per block
-constexpr int GN = 256;  // columns (sources) per block: 4 waves x 64
+constexpr int GM = 256;  // rows (vertices) per block: 2 wave rows x 128
+constexpr int GN = 128;  // columns (sources) per block: 2 wave columns x 64 (one bitmap word)
 constexpr int GK = 32;   // k (vertices) per pipeline stage
-constexpr int GT = 256;  // threads per block
+constexpr int GT = 256;  // threads per block (4 waves, 2 x 2)
+constexpr int WM = 128;  // rows per wave: 4 MFMA row tiles of 32
+constexpr int RT = WM / 32;
 constexpr int SA = GK + 8; // LDS row stride of the adjacency tile, in BF16 (padding against bank conflicts)
 constexpr int PB = 256;  // threads per block of the element-wise kernels
 
@@ -90,53 +92,64 @@ __device__ __forceinline__ int limbs_of(uint64_t mx) {
 // ---- the product -------------------------------------------------------------------
 
 // One pipeline stage held in registers between its global loads and its LDS
-// stores: 16 B of the adjacency tile and 4 x 16 B of each plane tile per thread.
+// stores: per thread 4 x 16 B of the adjacency tile (GM x GK) and 2 x 16 B of
+// each plane tile (GK x GN).
 template <int NP>
 struct Stage {
-    u32x4 a;
-    u32x4 x[NP * 4];
+    u32x4 a[4];
+    u32x4 x[NP * 2];
 };
 
 template <int NP>
 __device__ __forceinline__ void load_stage(const GemmArgs &g, const __bf16 *planes, int kt, int w0, int b0, int tid,
                                            Stage<NP> &st) {
-    const int row = tid >> 2, kq = tid & 3;
-    st.a = *reinterpret_cast<const u32x4 *>(g.adj + (size_t)(w0 + row) * g.npad + (size_t)kt * GK + kq * 8);
+    const int row = tid >> 2, kq = tid & 3; // four threads read one row's 64 B
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        st.a[i] = *reinterpret_cast<const u32x4 *>(g.adj + (size_t)(w0 + row + 64 * i) * g.npad + (size_t)kt * GK +
+                                                   kq * 8);
+    const int c = tid & (GN - 1), i0 = tid / GN; // k-group i0 and i0 + 2, column c
 #pragma unroll
     for (int p = 0; p < NP; ++p)
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            st.x[p * 4 + i] = *reinterpret_cast<const u32x4 *>(
-                planes + (size_t)p * g.plane_elems + (((size_t)kt * (GK / 8) + i) * g.B + b0 + tid) * 8);
+        for (int j = 0; j < 2; ++j)
+            st.x[p * 2 + j] = *reinterpret_cast<const u32x4 *>(
+                planes + (size_t)p * g.plane_elems + (((size_t)kt * (GK / 8) + i0 + 2 * j) * g.B + b0 + c) * 8);
 }
 
 template <int NP>
 __device__ __forceinline__ void store_stage(__bf16 *sA, __bf16 *sX, int tid, const Stage<NP> &st) {
     const int row = tid >> 2, kq = tid & 3;
-    *reinterpret_cast<u32x4 *>(sA + row * SA + kq * 8) = st.a;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) *reinterpret_cast<u32x4 *>(sA + (row + 64 * i) * SA + kq * 8) = st.a[i];
+    const int c = tid & (GN - 1), i0 = tid / GN;
 #pragma unroll
     for (int p = 0; p < NP; ++p)
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            *reinterpret_cast<u32x4 *>(sX + (((size_t)p * 4 + i) * GN + tid) * 8) = st.x[p * 4 + i];
+        for (int j = 0; j < 2; ++j)
+            *reinterpret_cast<u32x4 *>(sX + (((size_t)p * 4 + i0 + 2 * j) * GN + c) * 8) = st.x[p * 2 + j];
 }
 
+// Wave (wr, wc) multiplies rows [128 wr, 128 wr + 128) of the A tile by
+// columns [64 wc, 64 wc + 64) of each plane tile.
 template <int NP>
-__device__ __forceinline__ void mma_stage(const __bf16 *sA, const __bf16 *sX, int lane, int wv, f32x16 (&acc)[2][2]) {
+__device__ __forceinline__ void mma_stage(const __bf16 *sA, const __bf16 *sX, int lane, int wr, int wc,
+                                          f32x16 (&acc)[RT][2]) {
 #pragma unroll
     for (int kh = 0; kh < 2; ++kh) {
-        bf16x8 a[2];
+        bf16x8 a[RT];
 #pragma unroll
-        for (int rt = 0; rt < 2; ++rt)
-            a[rt] = *reinterpret_cast<const bf16x8 *>(sA + (rt * 32 + (lane & 31)) * SA + kh * 16 + (lane >> 5) * 8);
+        for (int rt = 0; rt < RT; ++rt)
+            a[rt] = *reinterpret_cast<const bf16x8 *>(sA + (wr * WM + rt * 32 + (lane & 31)) * SA + kh * 16 +
+                                                      (lane >> 5) * 8);
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
 #pragma unroll
             for (int ct = 0; ct < 2; ++ct) {
                 const bf16x8 b = *reinterpret_cast<const bf16x8 *>(
-                    sX + (((size_t)p * 4 + kh * 2 + (lane >> 5)) * GN + wv * 64 + ct * 32 + (lane & 31)) * 8);
+                    sX + (((size_t)p * 4 + kh * 2 + (lane >> 5)) * GN + wc * 64 + ct * 32 + (lane & 31)) * 8);
 #pragma unroll
-                for (int rt = 0; rt < 2; ++rt)
+                for (int rt = 0; rt < RT; ++rt)
                     acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[rt], b, acc[rt][ct], 0, 0, 0);
             }
         }
@@ -148,17 +161,26 @@ __device__ __forceinline__ int next_tile(const uint32_t *flags, int ntn, int kt,
     return kt;
 }
 
+// LDS stages of the pipeline: two for one plane; one for three planes, whose
+// stage is three times larger, so that two blocks fit a compute unit.
+template <int NP>
+constexpr int stages() { return NP == 1 ? 2 : 1; }
+
 // acc[w][b] = sum over k-tiles with a non-zero flag of A[w][k] X_p[k][b],
-// summed over the NP planes starting at `planes`, for the block's 64 rows
-// and its 256 sources (wave wv: sources [b0 + 64 wv, b0 + 64 wv + 64)).
+// summed over the NP planes starting at `planes`, for the block's 256 rows and
+// 128 sources; wave (wr, wc) holds rows w0 + 128 wr + [0, 128) and sources
+// b0 + 64 wc + [0, 64).  The next stage's global loads are in flight (in
+// registers) during the current stage's products.  (Two register stages in
+// flight measured slower: the extra registers pushed the forward kernel into
+// AGPR spills.)
 template <int NP>
 __device__ __forceinline__ void gemm_tile(const GemmArgs &g, const __bf16 *planes, int w0, int b0, int tid,
-                                          __bf16 (*sA)[GM * SA], __bf16 (*sX)[NP * 4 * GN * 8], f32x16 (&acc)[2][2]) {
-    const int lane = tid & 63, wv = tid >> 6;
+                                          __bf16 (*sA)[GM * SA], __bf16 (*sX)[NP * 4 * GN * 8], f32x16 (&acc)[RT][2]) {
+    const int lane = tid & 63, wv = tid >> 6, wr = wv >> 1, wc = wv & 1;
     const int nkt = g.npad / GK, ntn = g.B / GN;
     const uint32_t *flags = g.kflags + blockIdx.y;
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
+    for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
@@ -174,11 +196,17 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, const __bf16 *plane
     __syncthreads();
     while (kt < nkt) {
         const int kn = next_tile(flags, ntn, kt + 1, nkt);
-        if (kn < nkt) load_stage<NP>(g, planes, kn, w0, b0, tid, st); // in flight during the products
-        mma_stage<NP>(sA[buf], sX[buf], lane, wv, acc);
-        if (kn < nkt) store_stage<NP>(sA[buf ^ 1], sX[buf ^ 1], tid, st);
-        __syncthreads();
-        buf ^= 1;
+        if (kn < nkt) load_stage<NP>(g, planes, kn, w0, b0, tid, st);
+        mma_stage<NP>(sA[buf], sX[buf], lane, wr, wc, acc);
+        if constexpr (stages<NP>() == 2) {
+            if (kn < nkt) store_stage<NP>(sA[buf ^ 1], sX[buf ^ 1], tid, st);
+            __syncthreads();
+            buf ^= 1;
+        } else {
+            __syncthreads(); // every wave is done with the stage
+            if (kn < nkt) store_stage<NP>(sA[0], sX[0], tid, st);
+            __syncthreads();
+        }
         kt = kn;
     }
 }
@@ -189,7 +217,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, const __bf16 *plane
 // r%4 and column l%32.
 template <typename S>
 __device__ __forceinline__ void epi_fwd(const GemmArgs &g, const EpiArgs &e, int mode, int shift,
-                                        const f32x16 (&acc)[2][2], int w0, int q, int lane) {
+                                        const f32x16 (&acc)[RT][2], int w0, int q, int lane) {
     const int half = lane >> 5, col = lane & 31;
     const bool first = mode == EPI_FIRST, mid = mode == EPI_MID, last = mode == EPI_LAST;
     const bool final_limb = mode == EPI_ONLY || last;
@@ -197,7 +225,7 @@ __device__ __forceinline__ void epi_fwd(const GemmArgs &g, const EpiArgs &e, int
     bool wide = false, ovf = false;
     uint64_t mx = 0;
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt) {
+    for (int rt = 0; rt < RT; ++rt) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int w = w0 + rt * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
@@ -263,18 +291,18 @@ __device__ __forceinline__ void epi_fwd(const GemmArgs &g, const EpiArgs &e, int
 // Forward level l -> l+1: one pass per 8-bit limb of level l's largest count,
 // each followed by its epilogue.  Grid: (npad / GM, B / GN).
 template <typename S>
-__global__ __launch_bounds__(GT) void k_mfma_fwd(GemmArgs g, EpiArgs e) {
+__global__ __launch_bounds__(GT, 2) void k_mfma_fwd(GemmArgs g, EpiArgs e) {
     __shared__ __align__(16) __bf16 sA[2][GM * SA];
     __shared__ __align__(16) __bf16 sX[2][4 * GN * 8];
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int w0 = blockIdx.x * GM, b0 = blockIdx.y * GN;
-    const int q = (b0 >> 6) + wv; // bitmap word of this wave's sources
+    const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int w0 = blockIdx.x * GM + (wv >> 1) * WM, b0 = blockIdx.y * GN;
+    const int q = (b0 >> 6) + (wv & 1); // bitmap word of this wave's sources
     const int L = limbs_of(*e.lvmax_cur);
     if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) atomicAdd(e.planes_issued, (unsigned long long)L);
-    f32x16 acc[2][2];
+    f32x16 acc[RT][2];
 #pragma nounroll
     for (int k = 0; k < L; ++k) {
-        gemm_tile<1>(g, g.planes + (size_t)k * g.plane_elems, w0, b0, tid, sA, sX, acc);
+        gemm_tile<1>(g, g.planes + (size_t)k * g.plane_elems, blockIdx.x * GM, b0, tid, sA, sX, acc);
         const int mode = L == 1 ? EPI_ONLY : k == 0 ? EPI_FIRST : k + 1 < L ? EPI_MID : EPI_LAST;
         // The epilogue's row addresses do not depend on k; an opaque copy of
         // the block's first row keeps the compiler from computing all of them
@@ -290,20 +318,21 @@ __global__ __launch_bounds__(GT) void k_mfma_fwd(GemmArgs g, EpiArgs e) {
 // delta(v,b) = lambda(v,b) * acc for v at level l, c(v,b) = (1 + delta) / lambda,
 // and BC(v) += delta summed over the block's sources (v != s_b).
 template <typename S>
-__global__ __launch_bounds__(GT) void k_mfma_bwd(GemmArgs g, EpiArgs e) {
-    __shared__ __align__(16) __bf16 sA[2][GM * SA];
-    __shared__ __align__(16) __bf16 sX[2][3 * 4 * GN * 8];
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int w0 = blockIdx.x * GM, b0 = blockIdx.y * GN;
+__global__ __launch_bounds__(GT, 2) void k_mfma_bwd(GemmArgs g, EpiArgs e) {
+    __shared__ __align__(16) __bf16 sA[stages<3>()][GM * SA];
+    __shared__ __align__(16) __bf16 sX[stages<3>()][3 * 4 * GN * 8];
+    const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int b0 = blockIdx.y * GN;
     if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) atomicAdd(e.planes_issued, 3ull);
-    f32x16 acc[2][2];
-    gemm_tile<3>(g, g.planes, w0, b0, tid, sA, sX, acc);
+    f32x16 acc[RT][2];
+    gemm_tile<3>(g, g.planes, blockIdx.x * GM, b0, tid, sA, sX, acc);
 
-    const int q = (b0 >> 6) + wv;
+    const int w0 = blockIdx.x * GM + (wv >> 1) * WM;
+    const int q = (b0 >> 6) + (wv & 1);
     const int half = lane >> 5, col = lane & 31;
     S *sigma = reinterpret_cast<S *>(e.sigma);
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt) {
+    for (int rt = 0; rt < RT; ++rt) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int v = w0 + rt * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
@@ -427,7 +456,7 @@ bc_status algebraic_prepare(bc_ctx *ctx) {
     if (ctx->max_degree > 65792)
         return bc_fail(ctx, BC_ERR_UNSUPPORTED,
                        "algebraic form: a degree above 65792 breaks exact FP32 accumulation of 8-bit limbs");
-    a.npad = std::max(64, (ctx->n + 63) / 64 * 64);
+    a.npad = std::max(GM, (ctx->n + GM - 1) / GM * GM);
     const size_t adj_bytes = (size_t)a.npad * a.npad * sizeof(__bf16);
     if (adj_bytes > (size_t(96) << 30))
         return bc_fail(ctx, BC_ERR_UNSUPPORTED, "algebraic form: the dense adjacency would exceed 96 GiB");

@@ -52,7 +52,7 @@ struct SparseState {
 
 // State of the algebraic form (dense adjacency products on MFMA).
 struct AlgebraicState {
-    int32_t npad = 0;                  // n rounded up to 64
+    int32_t npad = 0;                  // n rounded up to 256 (the product's row block)
     __bf16 *adj = nullptr;             // [npad][npad] 0/1
     __bf16 *planes = nullptr;          // up to 8 planes of [npad/8][batch][8]
     uint64_t *part = nullptr;          // [npad][batch] partial limb sums

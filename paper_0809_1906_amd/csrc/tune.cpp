@@ -117,7 +117,7 @@ size_t state_bytes(int32_t n, int32_t batch) {
 
 bool products_possible(const bc_ctx *ctx) {
     if (ctx->weighted || ctx->max_degree > 65792) return false;
-    const size_t npad = (size_t)std::max(64, (ctx->n + 63) / 64 * 64);
+    const size_t npad = (size_t)std::max(256, (ctx->n + 255) / 256 * 256);
     return npad * npad * 2 <= kHybridAdjBudget;
 }
 
