@@ -507,14 +507,23 @@ static bc_status stage_sources(bc_ctx *ctx, const int32_t *sources, int64_t coun
     if (count == -1 && sources == nullptr) count = ctx->n;
     else if (count < 0 || (count > 0 && !sources)) return bc_fail(ctx, BC_ERR_INVALID_ARG, "bad sources/count");
     if (mem != BC_MEM_HOST && mem != BC_MEM_DEVICE) return bc_fail(ctx, BC_ERR_INVALID_ARG, "bad mem");
+    if (count > ctx->sources_cap) {
+        if (ctx->sources) bc_dfree(ctx, ctx->sources);
+        ctx->sources = (int32_t *)bc_dalloc(ctx, sizeof(int32_t) * (size_t)count);
+        if (!ctx->sources) { ctx->sources_cap = 0; return bc_fail(ctx, BC_ERR_NOMEM, "source staging allocation failed"); }
+        ctx->sources_cap = count;
+    }
+    if (sources == nullptr) { // "every vertex", generated on the device in internal ids
+        bc_status fs = fill_all_sources(ctx, ctx->sources, count);
+        if (fs != BC_OK) return fs;
+        *d_out = ctx->sources;
+        *count_out = count;
+        return BC_OK;
+    }
+    // Explicit sources: validated on the host (a device list is read back first).
     std::vector<int32_t> host;
     const int32_t *hs = sources;
-    if (sources == nullptr) {
-        host.resize((size_t)count);
-        for (int64_t i = 0; i < count; ++i) host[(size_t)i] = (int32_t)i;
-        hs = host.data();
-        mem = BC_MEM_HOST;
-    } else if (mem == BC_MEM_DEVICE) {
+    if (mem == BC_MEM_DEVICE) {
         host.resize((size_t)count);
         BC_HIP(ctx, hipMemcpy(host.data(), sources, sizeof(int32_t) * (size_t)count, hipMemcpyDeviceToHost));
         hs = host.data();
@@ -525,21 +534,12 @@ static bc_status stage_sources(bc_ctx *ctx, const int32_t *sources, int64_t coun
             snprintf(buf, sizeof buf, "source %d at position %lld is outside [0,%d)", hs[i], (long long)i, ctx->n);
             return bc_fail(ctx, BC_ERR_INVALID_ARG, buf);
         }
-    if (count > ctx->sources_cap) {
-        if (ctx->sources) bc_dfree(ctx, ctx->sources);
-        ctx->sources = (int32_t *)bc_dalloc(ctx, sizeof(int32_t) * (size_t)count);
-        if (!ctx->sources) { ctx->sources_cap = 0; return bc_fail(ctx, BC_ERR_NOMEM, "source staging allocation failed"); }
-        ctx->sources_cap = count;
-    }
     if (count > 0)
         BC_HIP(ctx, hipMemcpyAsync(ctx->sources, hs, sizeof(int32_t) * (size_t)count, hipMemcpyHostToDevice, ctx->stream));
-    // the host vector must stay alive until the copy is done
-    if (!host.empty() || mem == BC_MEM_HOST) BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    // Explicit sources are caller ids; "every vertex" is generated in internal ids.
-    if (sources != nullptr) {
-        bc_status ms = map_ids_to_internal(ctx, ctx->sources, count);
-        if (ms != BC_OK) return ms;
-    }
+    // the caller's (or our) host array must stay alive until the copy is done
+    BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    bc_status ms = map_ids_to_internal(ctx, ctx->sources, count);
+    if (ms != BC_OK) return ms;
     *d_out = ctx->sources;
     *count_out = count;
     return BC_OK;

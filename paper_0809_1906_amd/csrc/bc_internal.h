@@ -212,6 +212,7 @@ struct LaunchTimer {
 
 // ---- numbering (common.hip) ------------------------------------------------------
 bc_status map_ids_to_internal(bc_ctx *ctx, int32_t *ids, int64_t count);
+bc_status fill_all_sources(bc_ctx *ctx, int32_t *ids, int64_t count); // ids[i] = i on the device
 bc_status rows_to_caller_order_f64(bc_ctx *ctx, double *out, const double *in, int64_t rows);
 bc_status rows_to_caller_order_i32(bc_ctx *ctx, int32_t *out, const int32_t *in, int64_t rows);
 bc_status rows_to_caller_order_u64(bc_ctx *ctx, uint64_t *out, const uint64_t *in, int64_t rows);

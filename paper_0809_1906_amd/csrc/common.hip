@@ -12,6 +12,11 @@ __global__ __launch_bounds__(CB) void k_map_ids(int32_t *__restrict__ ids, int64
     if (i < count) ids[i] = table[ids[i]];
 }
 
+__global__ __launch_bounds__(CB) void k_iota(int32_t *__restrict__ ids, int64_t count) {
+    const int64_t i = (int64_t)blockIdx.x * CB + threadIdx.x;
+    if (i < count) ids[i] = (int32_t)i;
+}
+
 // out[r][v] = in[r][table[v]] for rows r < rows, v < n.
 template <typename T>
 __global__ __launch_bounds__(CB) void k_gather_rows(T *__restrict__ out, const T *__restrict__ in, int64_t rows,
@@ -26,6 +31,13 @@ __global__ __launch_bounds__(CB) void k_gather_rows(T *__restrict__ out, const T
 inline unsigned blocks_for(int64_t count) { return (unsigned)((count + CB - 1) / CB); }
 
 } // namespace
+
+bc_status fill_all_sources(bc_ctx *ctx, int32_t *ids, int64_t count) {
+    if (count <= 0) return BC_OK;
+    hipLaunchKernelGGL(k_iota, dim3(blocks_for(count)), dim3(CB), 0, ctx->stream, ids, count);
+    BC_HIP(ctx, hipGetLastError());
+    return BC_OK;
+}
 
 bc_status map_ids_to_internal(bc_ctx *ctx, int32_t *ids, int64_t count) {
     if (count <= 0 || !ctx->new_of_old) return BC_OK;
