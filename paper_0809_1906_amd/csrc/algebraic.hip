@@ -156,6 +156,24 @@ __device__ __forceinline__ void mma_stage(const __bf16 *sA, const __bf16 *sX, in
     }
 }
 
+// Block -> (row block, column block), XCD-aware.  Consecutive blocks go to
+// consecutive XCDs (each with its own L2), so block L runs on XCD L % 8; the
+// blocks of one XCD take (row block, column block) pairs with the column
+// fastest, so all column blocks of a row block run on the same XCD at about
+// the same time and share its adjacency rows in that L2.  Row blocks past the
+// matrix (padding to a multiple of 8) return at once.
+struct Tile {
+    int row, col;
+};
+__device__ __forceinline__ Tile tile_of(int npad, int B) {
+    const int R = npad / GM, C = B / GN;
+    const int L = blockIdx.x, x = L & 7, t = L >> 3;
+    (void)R;
+    // uniform over the block: keep it in scalar registers
+    return Tile{__builtin_amdgcn_readfirstlane((t / C) * 8 + x), __builtin_amdgcn_readfirstlane(t % C)};
+}
+inline unsigned grid_blocks(int npad, int B) { return (unsigned)(((npad / GM + 7) / 8) * 8 * (B / GN)); }
+
 __device__ __forceinline__ int next_tile(const uint32_t *flags, int ntn, int kt, int nkt) {
     while (kt < nkt && flags[(size_t)kt * ntn] == 0) ++kt;
     return kt;
@@ -178,7 +196,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, const __bf16 *plane
                                           __bf16 (*sA)[GM * SA], __bf16 (*sX)[NP * 4 * GN * 8], f32x16 (&acc)[RT][2]) {
     const int lane = tid & 63, wv = tid >> 6, wr = wv >> 1, wc = wv & 1;
     const int nkt = g.npad / GK, ntn = g.B / GN;
-    const uint32_t *flags = g.kflags + blockIdx.y;
+    const uint32_t *flags = g.kflags + b0 / GN;
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -289,20 +307,22 @@ __device__ __forceinline__ void epi_fwd(const GemmArgs &g, const EpiArgs &e, int
 }
 
 // Forward level l -> l+1: one pass per 8-bit limb of level l's largest count,
-// each followed by its epilogue.  Grid: (npad / GM, B / GN).
+// each followed by its epilogue.  Grid: grid_blocks(npad, B), tiles by tile_of.
 template <typename S>
 __global__ __launch_bounds__(GT, 2) void k_mfma_fwd(GemmArgs g, EpiArgs e) {
     __shared__ __align__(16) __bf16 sA[2][GM * SA];
     __shared__ __align__(16) __bf16 sX[2][4 * GN * 8];
+    const Tile tl = tile_of(g.npad, g.B);
+    if (tl.row >= g.npad / GM) return;
     const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int w0 = blockIdx.x * GM + (wv >> 1) * WM, b0 = blockIdx.y * GN;
+    const int w0 = tl.row * GM + (wv >> 1) * WM, b0 = tl.col * GN;
     const int q = (b0 >> 6) + (wv & 1); // bitmap word of this wave's sources
     const int L = limbs_of(*e.lvmax_cur);
-    if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) atomicAdd(e.planes_issued, (unsigned long long)L);
+    if (blockIdx.x == 0 && tid == 0) atomicAdd(e.planes_issued, (unsigned long long)L);
     f32x16 acc[RT][2];
 #pragma nounroll
     for (int k = 0; k < L; ++k) {
-        gemm_tile<1>(g, g.planes + (size_t)k * g.plane_elems, blockIdx.x * GM, b0, tid, sA, sX, acc);
+        gemm_tile<1>(g, g.planes + (size_t)k * g.plane_elems, tl.row * GM, b0, tid, sA, sX, acc);
         const int mode = L == 1 ? EPI_ONLY : k == 0 ? EPI_FIRST : k + 1 < L ? EPI_MID : EPI_LAST;
         // The epilogue's row addresses do not depend on k; an opaque copy of
         // the block's first row keeps the compiler from computing all of them
@@ -321,13 +341,15 @@ template <typename S>
 __global__ __launch_bounds__(GT, 2) void k_mfma_bwd(GemmArgs g, EpiArgs e) {
     __shared__ __align__(16) __bf16 sA[stages<3>()][GM * SA];
     __shared__ __align__(16) __bf16 sX[stages<3>()][3 * 4 * GN * 8];
+    const Tile tl = tile_of(g.npad, g.B);
+    if (tl.row >= g.npad / GM) return;
     const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int b0 = blockIdx.y * GN;
-    if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) atomicAdd(e.planes_issued, 3ull);
+    const int b0 = tl.col * GN;
+    if (blockIdx.x == 0 && tid == 0) atomicAdd(e.planes_issued, 3ull);
     f32x16 acc[RT][2];
-    gemm_tile<3>(g, g.planes, blockIdx.x * GM, b0, tid, sA, sX, acc);
+    gemm_tile<3>(g, g.planes, tl.row * GM, b0, tid, sA, sX, acc);
 
-    const int w0 = blockIdx.x * GM + (wv >> 1) * WM;
+    const int w0 = tl.row * GM + (wv >> 1) * WM;
     const int q = (b0 >> 6) + (wv & 1);
     const int half = lane >> 5, col = lane & 31;
     S *sigma = reinterpret_cast<S *>(e.sigma);
@@ -519,7 +541,7 @@ bc_status algebraic_forward_level_t(bc_ctx *ctx, int32_t l) {
     e.planes_issued = a.planes_issued;
     const GemmArgs g = gemm_args(ctx, a.planes);
     LaunchTimer tm(ctx, "mfma_fwd");
-    hipLaunchKernelGGL(k_mfma_fwd<S>, dim3(a.npad / GM, s.batch / GN), dim3(GT), 0, ctx->stream, g, e);
+    hipLaunchKernelGGL(k_mfma_fwd<S>, dim3(grid_blocks(a.npad, s.batch)), dim3(GT), 0, ctx->stream, g, e);
     tm.done();
     BC_HIP(ctx, hipGetLastError());
     return BC_OK;
@@ -550,7 +572,7 @@ bc_status algebraic_backward_level_t(bc_ctx *ctx, const uint64_t *fcur, const ui
     e.planes_issued = a.planes_issued;
     const GemmArgs g = gemm_args(ctx, a.planes);
     LaunchTimer tm(ctx, "mfma_bwd");
-    hipLaunchKernelGGL(k_mfma_bwd<S>, dim3(a.npad / GM, s.batch / GN), dim3(GT), 0, ctx->stream, g, e);
+    hipLaunchKernelGGL(k_mfma_bwd<S>, dim3(grid_blocks(a.npad, s.batch)), dim3(GT), 0, ctx->stream, g, e);
     tm.done();
     BC_HIP(ctx, hipGetLastError());
     return BC_OK;
@@ -577,5 +599,6 @@ int64_t algebraic_planes_issued(bc_ctx *ctx) {
 }
 
 void algebraic_reset_counters(bc_ctx *ctx) {
-    if (ctx->al.planes_issued) hipMemsetAsync(ctx->al.planes_issued, 0, sizeof(unsigned long long), ctx->stream);
+    if (ctx->al.planes_issued)
+        (void)hipMemsetAsync(ctx->al.planes_issued, 0, sizeof(unsigned long long), ctx->stream);
 }
