@@ -144,7 +144,13 @@ typedef struct {
                              degree histogram), the form, the requested batch and
                              the device; a hit skips calibration, a miss appends
                              the measured result.  NULL = this process only. */
-    int32_t reserved[3];
+    int32_t grid;         /* plain form (unit and integer weights): persistent
+                             workgroups, each running one source at a time;
+                             0 = default (the most that fit a workspace budget,
+                             at most 2048 unweighted, 1024 weighted; the budget
+                             is 16 GB unweighted, 96 GB weighted, 192 GB weighted
+                             with an explicit grid) */
+    int32_t reserved[2];
 } bc_options;
 
 /* Where the batch width and hybrid thresholds of a context came from. */

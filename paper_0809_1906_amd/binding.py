@@ -62,7 +62,7 @@ class bc_options(ctypes.Structure):
                 ("device", ctypes.c_int32), ("stream", ctypes.c_void_p), ("allocator", bc_allocator),
                 ("timing", ctypes.c_int32), ("split_degree", ctypes.c_int32),
                 ("vertex_order", ctypes.c_int32), ("arena_log2", ctypes.c_int32),
-                ("tune_cache", ctypes.c_char_p), ("reserved", ctypes.c_int32 * 3)]
+                ("tune_cache", ctypes.c_char_p), ("grid", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class bc_info(ctypes.Structure):
@@ -225,7 +225,8 @@ class BC:
 
     def __init__(self, graph, form: str = "auto", batch: int = 0, device: int = 0, stream=None,
                  allocator: str = "torch", timing: bool = False, split_degree: int = 0,
-                 vertex_order: str = "degree", arena_log2: int = 0, tune_cache: Optional[str] = None):
+                 vertex_order: str = "degree", arena_log2: int = 0, tune_cache: Optional[str] = None,
+                 grid: int = 0):
         import torch
         load()
         if not torch.cuda.is_available():
@@ -245,6 +246,7 @@ class BC:
         opt.arena_log2 = arena_log2
         self._tune_cache = None if tune_cache is None else os.fsencode(tune_cache)
         opt.tune_cache = self._tune_cache
+        opt.grid = grid
         self._alloc = None
         if allocator == "torch":
             self._alloc = _TorchAllocator(device)

@@ -267,6 +267,8 @@ bc_status bc_create(const bc_graph *g, const bc_options *opt_in, bc_ctx **out) {
         return fail_create(BC_ERR_INVALID_ARG, "unknown vertex_order");
     if (opt.arena_log2 < 0 || opt.arena_log2 > 30)
         return fail_create(BC_ERR_INVALID_ARG, "arena_log2 must be in [0, 30]");
+    if (opt.grid < 0 || opt.grid > 65536)
+        return fail_create(BC_ERR_INVALID_ARG, "grid must be in [0, 65536]");
     if (opt.split_degree != 0 && opt.split_degree < 64)
         return fail_create(BC_ERR_INVALID_ARG, "split_degree must be 0 (default) or at least 64");
     if ((opt.allocator.alloc == nullptr) != (opt.allocator.free == nullptr))
@@ -367,6 +369,8 @@ bc_status bc_create(const bc_graph *g, const bc_options *opt_in, bc_ctx **out) {
     }
     ctx->h_row_ptr.assign(urp, urp + (size_t)n + 1);
     ctx->wt.arena_log2 = opt.arena_log2;
+    ctx->wt.grid = opt.grid;
+    ctx->pl.grid = opt.grid;
 
     ctx->row_ptr = (int32_t *)bc_dalloc(ctx, sizeof(int32_t) * ((size_t)n + 1));
     ctx->col = (int32_t *)bc_dalloc(ctx, sizeof(int32_t) * (size_t)std::max(nnz, 1));
@@ -375,8 +379,13 @@ bc_status bc_create(const bc_graph *g, const bc_options *opt_in, bc_ctx **out) {
     ctx->status = (uint32_t *)bc_dalloc(ctx, 256);
     if (!ctx->row_ptr || !ctx->col || !ctx->bc || !ctx->bc_scratch || !ctx->status)
         return bail(BC_ERR_NOMEM, "device allocation failed");
-    if (hw) {
-        ctx->weight = (uint32_t *)bc_dalloc(ctx, sizeof(uint32_t) * (size_t)std::max(nnz, 1));
+    // Weights go to the device as bytes (the weighted sweep takes weights up
+    // to 255 and refuses larger ones when it is prepared).
+    std::vector<uint8_t> w8;
+    if (hw && max_w <= 255) {
+        w8.resize((size_t)std::max(nnz, 1));
+        for (int32_t e = 0; e < nnz; ++e) w8[(size_t)e] = (uint8_t)uw[e];
+        ctx->weight = (uint8_t *)bc_dalloc(ctx, (size_t)std::max(nnz, 1));
         if (!ctx->weight) return bail(BC_ERR_NOMEM, "device allocation failed");
     }
     if (relabel) {
@@ -389,8 +398,7 @@ bc_status bc_create(const bc_graph *g, const bc_options *opt_in, bc_ctx **out) {
     hipMemcpyKind kind = direct_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     if (hipMemcpy(ctx->row_ptr, urp, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyHostToDevice) != hipSuccess ||
         (nnz > 0 && hipMemcpy(ctx->col, direct_device ? g->col : ucol, sizeof(int32_t) * (size_t)nnz, kind) != hipSuccess) ||
-        (hw && nnz > 0 &&
-         hipMemcpy(ctx->weight, direct_device ? g->weight : uw, sizeof(uint32_t) * (size_t)nnz, kind) != hipSuccess) ||
+        (ctx->weight && nnz > 0 && hipMemcpy(ctx->weight, w8.data(), (size_t)nnz, hipMemcpyHostToDevice) != hipSuccess) ||
         (relabel && hipMemcpy(ctx->new_of_old, new_of_old.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice) != hipSuccess) ||
         hipMemsetAsync(ctx->bc, 0, sizeof(double) * (size_t)std::max(n, 1), ctx->stream) != hipSuccess ||
         hipMemsetAsync(ctx->status, 0, 256, ctx->stream) != hipSuccess)

@@ -95,6 +95,10 @@ struct WeightedBuffers {
     int64_t cap = 0;              // arena ring entries per workgroup (power of two)
     int32_t *dist = nullptr, *order = nullptr, *gstart = nullptr, *gdist = nullptr, *arena = nullptr;
     int32_t *bstart = nullptr, *bcount = nullptr, *pstart = nullptr;
+    int32_t *imp_x = nullptr;     // improvement list of the current phase
+    uint8_t *imp_c = nullptr;
+    int32_t *dag_p = nullptr, *dag_s = nullptr, *gdag = nullptr; // DAG arcs by phase
+    int64_t icap = 0, dcap = 0;
     uint64_t *sigma = nullptr;
     double *acc = nullptr;
 };
@@ -108,6 +112,7 @@ struct WeightedState {
     int64_t retry_cap = 0;
     int64_t retried = 0;
     int32_t arena_log2 = 0;       // requested main arena size (0 = default)
+    int32_t grid = 0;             // requested workgroups (0 = default)
 };
 
 // State of a many-graph context (bc_create_many).
@@ -124,6 +129,7 @@ struct MultiState {
 
 // State of the plain per-source form.
 struct PlainState {
+    int32_t grid = 0;         // requested workgroups (0 = default)
     int32_t groups = 0;       // persistent workgroups
     int32_t *dist = nullptr;  // [groups][n]
     uint64_t *sigma = nullptr;// [groups][n]
@@ -155,7 +161,7 @@ struct bc_ctx {
     // device copies (internal numbering)
     int32_t *row_ptr = nullptr;
     int32_t *col = nullptr;
-    uint32_t *weight = nullptr;
+    uint8_t *weight = nullptr;       // weights as bytes (weighted graphs with max weight <= 255)
     double *bc = nullptr;
     uint32_t *status = nullptr;      // [0]: BC_DEV_* bits; [1]: a batch needs uint64 counts
     uint32_t *status_host = nullptr; // pinned

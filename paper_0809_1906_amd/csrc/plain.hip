@@ -226,7 +226,7 @@ bc_status plain_prepare(bc_ctx *ctx) {
     const size_t n = (size_t)std::max(ctx->n, 1);
     const size_t per_group = n * (4 + 8 + 8 + 4) + (n + 2) * 4;
     const size_t budget = size_t(16) << 30;
-    int groups = 2048;
+    int groups = p.grid > 0 ? p.grid : 2048;
     while (groups > 1 && per_group * (size_t)groups > budget) groups /= 2;
     p.groups = groups;
     p.dist = (int32_t *)bc_dalloc(ctx, n * groups * sizeof(int32_t));

@@ -5,17 +5,23 @@
 // forward of Sec. 3.2.1 read as path counts summed over P_s in nondecreasing
 // distance):
 //   forward   phase d = 0, 1, 2, ...: the vertices whose tentative distance is
-//             d are final (every weight is >= 1).  They are settled, their
-//             count is pulled over predecessors,
+//             d are final (every weight is >= 1).  They are settled, and one
+//             pass over their arcs both pulls their counts over predecessors,
 //                 lambda_sw = sum of lambda_sv over v with d(s,v) + w(v,w) = d,
-//             and their arcs are relaxed.  A relaxation that improves x to
-//             d + c is filed in bin c of phase d's slot in a ring of 256
-//             slots (max weight <= 255), so phase d + c finds it again by
-//             looking back at most 255 phases: no priority queue.
+//             and relaxes the arcs, from a single read of each neighbour's
+//             distance.  A relaxation that improves x to d + c is listed, then
+//             filed in bin c of phase d's slot in a ring of 256 slots (max
+//             weight <= 255), so phase d + c finds it again by looking back
+//             at most 255 phases: no priority queue.  Each thread keeps eight
+//             arcs' loads in flight.
 //   backward  distance groups from the farthest down to 1:
 //             delta(v) = lambda_sv * sum over successors w
 //             (d(s,w) = d(s,v) + w(v,w)) of c(w), c(w) = (1 + delta(w)) / lambda_sw,
-//             and BC(v) += delta(v) for v != s (Theorem 1.1, FP64).
+//             and BC(v) += delta(v) for v != s (Theorem 1.1, FP64).  The
+//             forward's count pull lists every DAG arc (predecessor,
+//             successor) by phase, so the backward touches only those arcs (a
+//             few percent of all arcs): once a group's c(w) are final, each is
+//             added into its predecessors' sums.
 //
 // Weights above 255 are handled by the same ring with a wider window: the
 // ring has W = 256 slots when max weight <= 255 and is refused otherwise
@@ -30,6 +36,7 @@ namespace {
 using wg::PB;
 constexpr int RING = 256;        // phases kept in the ring (max weight + 1)
 constexpr int32_t INF = 0x7FFFFFFF;
+constexpr int U = 8;             // arcs per thread with loads in flight together
 
 struct WeightedWork {
     int32_t *dist;   // [groups][n]
@@ -42,13 +49,20 @@ struct WeightedWork {
     int32_t *bstart; // [groups][RING][RING] unwrapped arena position of each bin
     int32_t *bcount; // [groups][RING][RING]
     int32_t *pstart; // [groups][RING] unwrapped arena position of each phase's bins
+    int32_t *imp_x;  // [groups][icap] vertices improved in the current phase
+    uint8_t *imp_c;  // [groups][icap] the weight of the improving arc
+    int32_t *dag_p;  // [groups][dcap] DAG arcs in phase order: predecessor
+    int32_t *dag_s;  // [groups][dcap]                         and successor
+    int32_t *gdag;   // [groups][n+1] first DAG arc of each distance group
     int64_t cap;     // arena entries per workgroup, a power of two
+    int64_t icap;    // improvement-list entries per workgroup
+    int64_t dcap;    // DAG-arc entries per workgroup
     int32_t *retry;  // sources (positions in the source list) whose live bins outgrew the arena
     uint32_t *retry_count;
 };
 
 __global__ __launch_bounds__(PB) void k_weighted_sweep(
-    int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col, const uint32_t *__restrict__ wt,
+    int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col, const uint8_t *__restrict__ wt,
     const int32_t *__restrict__ sources, const int32_t *__restrict__ slot_of, int64_t count,
     unsigned long long *next_counter, WeightedWork W, double *bc, uint32_t *status, int accumulate,
     double *delta_dump, int32_t *dist_dump, uint64_t *sigma_dump) {
@@ -58,7 +72,7 @@ __global__ __launch_bounds__(PB) void k_weighted_sweep(
     __shared__ int32_t s_hist[RING];
     __shared__ int32_t s_cur[RING];
     __shared__ long long s_idx;
-    __shared__ int32_t s_nset, s_maxt;
+    __shared__ int32_t s_nset, s_maxt, s_nimp, s_ndag;
     __shared__ uint32_t s_ovf, s_abort;
     __shared__ int32_t s_top;
 
@@ -74,8 +88,12 @@ __global__ __launch_bounds__(PB) void k_weighted_sweep(
     int32_t *bstart = W.bstart + g * (size_t)RING * RING;
     int32_t *bcount = W.bcount + g * (size_t)RING * RING;
     int32_t *pstart = W.pstart + g * (size_t)RING;
+    int32_t *imp_x = W.imp_x + g * (size_t)W.icap;
+    uint8_t *imp_c = W.imp_c + g * (size_t)W.icap;
+    int32_t *dag_p = W.dag_p + g * (size_t)W.dcap;
+    int32_t *dag_s = W.dag_s + g * (size_t)W.dcap;
+    int32_t *gdag = W.gdag + g * ((size_t)n + 1);
     const int32_t cmask = (int32_t)(W.cap - 1);
-    auto none = [](int, int32_t) {};
 
     for (;;) {
         if (tid == 0) s_idx = (long long)atomicAdd(next_counter, 1ull);
@@ -97,6 +115,7 @@ __global__ __launch_bounds__(PB) void k_weighted_sweep(
             s_ovf = 0;
             s_abort = 0;
             s_top = 0;
+            s_ndag = 0;
         }
         wg::bar();
 
@@ -142,25 +161,66 @@ __global__ __launch_bounds__(PB) void k_weighted_sweep(
             if (tid == 0) {
                 gstart[ngroups] = lb;
                 gdist[ngroups] = d;
+                gdag[ngroups] = s_ndag;
             }
             nsettled = le;
             ++ngroups;
-            // (2) one pass over the settled vertices' arcs: pull counts from
-            // predecessors (all settled at smaller distances) and count, per
-            // weight, the relaxations that would improve a neighbour
+            // (2) one pass over the settled vertices' arcs: pull each count
+            // from its predecessors (all settled at smaller distances) and
+            // relax, listing the improvements
             if (tid < RING) s_hist[tid] = 0;
-            wg::bar();
-            wg::for_arcs(order, lb, le, rp, ch, none, [&](int, int32_t w, int32_t a) {
-                const int32_t v = col[a];
-                const int32_t c = (int32_t)wt[a];
-                const int32_t dv = dist[v];
-                if (d > 0 && dv != INF && dv + c == d) {
-                    const uint64_t x = sigma[v];
-                    const uint64_t old = atomicAdd((unsigned long long *)&sigma[w], (unsigned long long)x);
-                    if (old + x < old) s_ovf = 1;
+            if (tid == 0) s_nimp = 0;
+            __syncthreads();
+            for (int32_t cb = lb; cb < le; cb += PB) {
+                const int tot = wg::stage_chunk(order, cb, le, rp, ch);
+                for (int e0 = tid; e0 < tot; e0 += PB * U) {
+                    int k[U];
+                    int32_t a[U], x[U], c[U], dx[U];
+                    wg::arc_burst<U>(ch, e0, tot, k, a);
+#pragma unroll
+                    for (int j = 0; j < U; ++j) {
+                        x[j] = a[j] >= 0 ? col[a[j]] : 0;
+                        c[j] = a[j] >= 0 ? (int32_t)wt[a[j]] : 0;
+                    }
+#pragma unroll
+                    for (int j = 0; j < U; ++j) dx[j] = a[j] >= 0 ? dist[x[j]] : INF;
+#pragma unroll
+                    for (int j = 0; j < U; ++j) {
+                        if (a[j] < 0) continue;
+                        if (d > 0 && dx[j] != INF && dx[j] + c[j] == d) { // x in P_s(w)
+                            const int32_t w = ch.v[k[j]];
+                            const uint64_t sx = sigma[x[j]];
+                            const uint64_t old = atomicAdd((unsigned long long *)&sigma[w], (unsigned long long)sx);
+                            if (old + sx < old) s_ovf = 1;
+                            const int32_t pos = atomicAdd(&s_ndag, 1);
+                            if (pos < W.dcap) {
+                                dag_p[pos] = x[j];
+                                dag_s[pos] = w;
+                            } else {
+                                s_abort = 1;
+                            }
+                        }
+                        const int32_t nd = d + c[j];
+                        if (nd < dx[j]) {
+                            const int32_t old = atomicMin(&dist[x[j]], nd);
+                            if (nd < old) {
+                                const int32_t pos = atomicAdd(&s_nimp, 1);
+                                if (pos < W.icap) {
+                                    imp_x[pos] = x[j];
+                                    imp_c[pos] = (uint8_t)c[j];
+                                    atomicAdd(&s_hist[c[j]], 1);
+                                    atomicMax(&s_maxt, nd);
+                                } else {
+                                    s_abort = 1;
+                                }
+                            }
+                        }
+                    }
                 }
-                if (d + c < dv) atomicAdd(&s_hist[c], 1);
-            });
+                __syncthreads(); // the chunk's LDS is restaged
+            }
+            wg::bar();
+            if (s_abort) break;
             // (3) allocate this phase's bins in the arena ring; the live window
             // (phases d-255 .. d) must fit, else the source is retried later
             {
@@ -182,19 +242,14 @@ __global__ __launch_bounds__(PB) void k_weighted_sweep(
             }
             wg::bar();
             if (s_abort) break;
-            wg::for_arcs(order, lb, le, rp, ch, none, [&](int, int32_t, int32_t a) {
-                const int32_t x = col[a];
-                const int32_t c = (int32_t)wt[a];
-                const int32_t nd = d + c;
-                if (nd < dist[x]) {
-                    const int32_t old = atomicMin(&dist[x], nd);
-                    if (nd < old) {
-                        const int k = atomicAdd(&s_cur[c], 1);
-                        arena[(bstart[slot * RING + c] + k) & cmask] = x;
-                        atomicMax(&s_maxt, nd);
-                    }
-                }
-            });
+            // (4) file the listed improvements in their bins
+            const int32_t nimp = s_nimp;
+            for (int32_t i = tid; i < nimp; i += PB) {
+                const int32_t x = imp_x[i], c = imp_c[i];
+                const int kk = atomicAdd(&s_cur[c], 1);
+                arena[(bstart[slot * RING + c] + kk) & cmask] = x;
+            }
+            __syncthreads();
             if (tid < RING) bcount[slot * RING + tid] = s_cur[tid];
             wg::bar();
         }
@@ -203,19 +258,18 @@ __global__ __launch_bounds__(PB) void k_weighted_sweep(
             wg::bar();
             continue;
         }
-        if (tid == 0) gstart[ngroups] = nsettled;
+        if (tid == 0) {
+            gstart[ngroups] = nsettled;
+            gdag[ngroups] = s_ndag;
+        }
         wg::bar();
 
         // ---- backward: distance groups from the farthest down ----
         const int32_t lowest = accumulate ? 1 : 0;
         for (int32_t gi = ngroups - 1; gi >= lowest; --gi) {
-            const int32_t lb = gstart[gi], le = gstart[gi + 1], d = gdist[gi];
-            if (gi < ngroups - 1) {
-                wg::for_arcs(order, lb, le, rp, ch, none, [&](int, int32_t v, int32_t a) {
-                    const int32_t w = col[a];
-                    if (dist[w] != INF && dist[w] == d + (int32_t)wt[a]) unsafeAtomicAdd(&acc[v], acc[w]);
-                });
-            }
+            const int32_t lb = gstart[gi], le = gstart[gi + 1];
+            // acc[v] holds the sum of c over v's successors, pushed by the
+            // deeper groups
             for (int32_t i = lb + tid; i < le; i += PB) {
                 const int32_t v = order[i];
                 const double sv = (double)sigma[v];
@@ -223,6 +277,22 @@ __global__ __launch_bounds__(PB) void k_weighted_sweep(
                 if (accumulate && v != s) unsafeAtomicAdd(&bc[v], dl);
                 if (delta_dump) delta_dump[out * n + v] = dl;
                 acc[v] = (1.0 + dl) / sv;
+            }
+            wg::bar();
+            // c(w) of this group into each predecessor's sum
+            const int32_t db = gdag[gi], de = gdag[gi + 1];
+            for (int32_t i0 = db + tid; i0 < de; i0 += PB * U) {
+                int32_t p[U];
+                double cw[U];
+#pragma unroll
+                for (int j = 0; j < U; ++j) {
+                    const int32_t i = i0 + j * PB;
+                    p[j] = i < de ? dag_p[i] : -1;
+                    cw[j] = i < de ? acc[dag_s[i]] : 0.0;
+                }
+#pragma unroll
+                for (int j = 0; j < U; ++j)
+                    if (p[j] >= 0) unsafeAtomicAdd(&acc[p[j]], cw[j]);
             }
             wg::bar();
         }
@@ -239,11 +309,20 @@ __global__ __launch_bounds__(PB) void k_weighted_sweep(
     }
 }
 
-bc_status alloc_work(bc_ctx *ctx, WeightedBuffers &b, int64_t cap, int groups) {
+// Main workspaces list a quarter of the ring's size in improvements per phase
+// and half of it in DAG arcs, and send a source that needs more to the retry
+// workspace; the retry workspace (ring of nnz + 1 entries or more) holds every
+// improvement of a phase and every DAG arc, so it never needs a retry itself.
+int64_t imp_cap(int64_t cap, bool retry_ws) { return retry_ws ? cap : std::max<int64_t>(cap / 4, 1); }
+int64_t dag_cap(int64_t cap) { return std::max<int64_t>(cap / 2, 1); }
+
+bc_status alloc_work(bc_ctx *ctx, WeightedBuffers &b, int64_t cap, int groups, bool retry_ws) {
     const size_t n = (size_t)std::max(ctx->n, 1);
     const size_t G = (size_t)groups;
     b.groups = groups;
     b.cap = cap;
+    b.icap = imp_cap(cap, retry_ws);
+    b.dcap = dag_cap(cap);
     b.dist = (int32_t *)bc_dalloc(ctx, G * n * 4);
     b.sigma = (uint64_t *)bc_dalloc(ctx, G * n * 8);
     b.acc = (double *)bc_dalloc(ctx, G * n * 8);
@@ -254,15 +333,23 @@ bc_status alloc_work(bc_ctx *ctx, WeightedBuffers &b, int64_t cap, int groups) {
     b.bstart = (int32_t *)bc_dalloc(ctx, G * RING * RING * 4);
     b.bcount = (int32_t *)bc_dalloc(ctx, G * RING * RING * 4);
     b.pstart = (int32_t *)bc_dalloc(ctx, G * RING * 4);
+    b.imp_x = (int32_t *)bc_dalloc(ctx, G * (size_t)b.icap * 4);
+    b.imp_c = (uint8_t *)bc_dalloc(ctx, G * (size_t)b.icap);
+    b.dag_p = (int32_t *)bc_dalloc(ctx, G * (size_t)b.dcap * 4);
+    b.dag_s = (int32_t *)bc_dalloc(ctx, G * (size_t)b.dcap * 4);
+    b.gdag = (int32_t *)bc_dalloc(ctx, G * (n + 1) * 4);
     if (!b.dist || !b.sigma || !b.acc || !b.order || !b.gstart || !b.gdist || !b.arena || !b.bstart || !b.bcount ||
-        !b.pstart)
+        !b.pstart || !b.imp_x || !b.imp_c || !b.dag_p || !b.dag_s || !b.gdag)
         return bc_fail(ctx, BC_ERR_NOMEM, "weighted form: workspace allocation failed");
     return BC_OK;
 }
 
-size_t per_group_bytes(bc_ctx *ctx, int64_t cap) {
+size_t per_group_bytes(bc_ctx *ctx, int64_t cap, bool retry_ws) {
     const size_t n = (size_t)std::max(ctx->n, 1);
-    return n * (4 + 8 + 8 + 4 + 4 + 4) + 4 + (size_t)cap * 4 + (2 * (size_t)RING + 1) * RING * 4;
+    // per vertex: dist, sigma, acc, order, gstart, gdist, gdag; the arena; the
+    // improvement list (5 B per entry); the DAG list (8 B per arc); the bins
+    return n * (4 + 8 + 8 + 4 + 4 + 4 + 4) + 8 + (size_t)cap * 4 + (size_t)imp_cap(cap, retry_ws) * 5 +
+           (size_t)dag_cap(cap) * 8 + (2 * (size_t)RING + 1) * RING * 4;
 }
 
 int64_t pow2_at_least(int64_t x) {
@@ -274,7 +361,8 @@ int64_t pow2_at_least(int64_t x) {
 WeightedWork work_of(bc_ctx *ctx, const WeightedBuffers &b) {
     WeightedState &w = ctx->wt;
     return WeightedWork{b.dist, b.sigma, b.acc, b.order, b.gstart, b.gdist, b.arena, b.bstart, b.bcount,
-                        b.pstart, b.cap, w.retry, w.retry_count};
+                        b.pstart, b.imp_x, b.imp_c, b.dag_p, b.dag_s, b.gdag, b.cap, b.icap, b.dcap, w.retry,
+                        w.retry_count};
 }
 
 } // namespace
@@ -289,10 +377,11 @@ bc_status weighted_prepare(bc_ctx *ctx) {
         return bc_fail(ctx, BC_ERR_UNSUPPORTED, "weighted form: weights above 255 are not supported");
     const int64_t cap = w.arena_log2 > 0 ? (int64_t(1) << w.arena_log2)
                                          : pow2_at_least(std::max<int64_t>(4 * (int64_t)std::max(ctx->n, 1), 1 << 16));
-    const size_t budget = size_t(48) << 30;
-    int groups = 1024;
-    while (groups > 1 && per_group_bytes(ctx, cap) * (size_t)groups > budget) groups /= 2;
-    bc_status st = alloc_work(ctx, w.main, cap, groups);
+    // workspace budget: 96 GB by default, 192 GB for an explicitly requested grid
+    const size_t budget = size_t(w.grid > 0 ? 192 : 96) << 30;
+    int groups = w.grid > 0 ? w.grid : 1024;
+    while (groups > 1 && per_group_bytes(ctx, cap, false) * (size_t)groups > budget) groups /= 2;
+    bc_status st = alloc_work(ctx, w.main, cap, groups, false);
     if (st != BC_OK) return st;
     w.next = (uint32_t *)bc_dalloc(ctx, 256);
     w.retry_count = (uint32_t *)bc_dalloc(ctx, 256);
@@ -337,8 +426,8 @@ bc_status weighted_run(bc_ctx *ctx, const int32_t *d_sources, int64_t count, boo
         if (!w.big.dist) {
             const int64_t cap = pow2_at_least((int64_t)std::max(ctx->nnz, 1) + 1);
             int groups = 64;
-            while (groups > 1 && per_group_bytes(ctx, cap) * (size_t)groups > (size_t(16) << 30)) groups /= 2;
-            st = alloc_work(ctx, w.big, cap, groups);
+            while (groups > 1 && per_group_bytes(ctx, cap, true) * (size_t)groups > (size_t(16) << 30)) groups /= 2;
+            st = alloc_work(ctx, w.big, cap, groups, true);
             if (st != BC_OK) return st;
         }
         // sources of the retried rows, gathered on the host
@@ -356,9 +445,12 @@ bc_status weighted_run(bc_ctx *ctx, const int32_t *d_sources, int64_t count, boo
                     delta_dump ? delta_dump + (size_t)c0 * ctx->n : nullptr,
                     dist_dump ? dist_dump + (size_t)c0 * ctx->n : nullptr,
                     sigma_dump ? sigma_dump + (size_t)c0 * ctx->n : nullptr);
+        BC_HIP(ctx, hipMemcpyAsync(w.host, w.retry_count, sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->stream));
         BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
         bc_dfree(ctx, dev);
         if (st != BC_OK) return st;
+        if (*w.host != 0) // cannot happen: the retry workspace holds any source's lists
+            return bc_fail(ctx, BC_ERR_DEVICE, "weighted form: a source outgrew the retry workspace");
         ctx->wt.retried += nretry;
     }
     return BC_OK;

@@ -99,4 +99,44 @@ __device__ __forceinline__ void for_arcs(const int32_t *list, int32_t lb, int32_
     }
 }
 
+// Stages the vertices list[cb .. min(cb + PB, le)) in c (vertex, row offset,
+// exclusive degree prefix; c.off[PB] = total) and returns their total degree.
+// Every thread of the workgroup calls; ends with __syncthreads().
+__device__ __forceinline__ int stage_chunk(const int32_t *list, int32_t cb, int32_t le,
+                                           const int32_t *__restrict__ rp, Chunk &c) {
+    const int tid = threadIdx.x;
+    const int32_t i = cb + tid;
+    int32_t v = -1, r = 0, d = 0;
+    if (i < le) {
+        v = list[i];
+        r = rp[v];
+        d = rp[v + 1] - r;
+    }
+    int tot;
+    const int off = block_excl_scan(d, c.wsum, &tot);
+    c.v[tid] = v;
+    c.rp[tid] = r;
+    c.off[tid] = off;
+    if (tid == 0) c.off[PB] = tot;
+    __syncthreads();
+    return tot;
+}
+
+// Arc positions e0 + j * PB (j < U) of a staged chunk with `tot` arcs: slot
+// k[j] of the owning vertex and arc index a[j] (-1 past the end).  The U
+// owner searches are independent, so they overlap.
+template <int U>
+__device__ __forceinline__ void arc_burst(const Chunk &c, int e0, int tot, int (&k)[U], int32_t (&a)[U]) {
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+        const int e = e0 + j * PB;
+        k[j] = 0;
+        a[j] = -1;
+        if (e < tot) {
+            k[j] = owner(c.off, e);
+            a[j] = c.rp[k[j]] + (e - c.off[k[j]]);
+        }
+    }
+}
+
 } // namespace wg
