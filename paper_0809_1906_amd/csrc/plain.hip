@@ -13,61 +13,16 @@
 //   score     BC(v) += delta_s*(v) for v != s.
 //
 // Each level's frontier is expanded in chunks of 256 vertices whose degree
-// prefix sums are staged in LDS, so a thread takes one arc, not one vertex:
-// hub vertices are spread over the whole workgroup.
+// prefix sums are staged in LDS, so a thread takes arcs, not vertices: hub
+// vertices are spread over the whole workgroup.  Each thread keeps eight
+// arcs' loads in flight.
 #include "bc_internal.h"
+#include "wg_utils.h"
 
 namespace {
 
-constexpr int PB = 256; // threads per workgroup
-
-// Workgroup barrier with device-scope ordering: the per-source arrays are
-// updated by device atomics (performed in L2), so every phase change must
-// make them visible across the workgroup's waves.
-__device__ __forceinline__ void bar() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-}
-
-__device__ __forceinline__ int wave_incl_scan(int x) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        int y = __shfl_up(x, d, 64);
-        if (lane >= d) x += y;
-    }
-    return x;
-}
-
-// Exclusive prefix sum over the workgroup; *total receives the sum.
-__device__ __forceinline__ int block_excl_scan(int x, int *wsum, int *total) {
-    const int incl = wave_incl_scan(x);
-    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (lane == 63) wsum[wid] = incl;
-    __syncthreads();
-    int off = 0, tot = 0;
-#pragma unroll
-    for (int i = 0; i < PB / 64; ++i) {
-        int s = wsum[i];
-        if (i < wid) off += s;
-        tot += s;
-    }
-    __syncthreads();
-    *total = tot;
-    return off + incl - x;
-}
-
-// Largest k in [0, PB) with off[k] <= e, given off[0] = 0 <= e < off[PB].
-__device__ __forceinline__ int owner(const int *off, int e) {
-    int lo = 0, hi = PB;
-    while (hi - lo > 1) {
-        int mid = (lo + hi) >> 1;
-        if (off[mid] <= e) lo = mid;
-        else hi = mid;
-    }
-    return lo;
-}
+using wg::PB;
+constexpr int U = 8; // arcs per thread with loads in flight together
 
 __global__ __launch_bounds__(PB) void k_plain_sweep(
     int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
@@ -75,11 +30,7 @@ __global__ __launch_bounds__(PB) void k_plain_sweep(
     int32_t *dist_all, uint64_t *sigma_all, double *acc_all, int32_t *queue_all, int32_t *lev_all,
     double *bc, uint32_t *status, int accumulate,
     double *delta_dump, int32_t *dist_dump, uint64_t *sigma_dump) {
-    __shared__ int32_t s_v[PB];
-    __shared__ int32_t s_rp[PB];
-    __shared__ int32_t s_off[PB + 1];
-    __shared__ uint64_t s_sig[PB];
-    __shared__ int32_t s_wsum[PB / 64];
+    __shared__ wg::Chunk ch;
     __shared__ int32_t s_tail;
     __shared__ long long s_idx;
     __shared__ uint32_t s_ovf;
@@ -104,7 +55,7 @@ __global__ __launch_bounds__(PB) void k_plain_sweep(
             sigma[v] = 0;
             acc[v] = 0.0;
         }
-        bar();
+        wg::bar();
         if (tid == 0) {
             dist[s] = 0;
             sigma[s] = 1;
@@ -114,56 +65,49 @@ __global__ __launch_bounds__(PB) void k_plain_sweep(
             s_tail = 1;
             s_ovf = 0;
         }
-        bar();
+        wg::bar();
 
         // ---- forward: level L spans queue[qb, qe) ----
         int32_t qb = 0, qe = 1, L = 0;
         while (qb < qe) {
             for (int32_t cb = qb; cb < qe; cb += PB) {
-                const int32_t i = cb + tid;
-                int32_t v = -1, r = 0, d = 0;
-                uint64_t sg = 0;
-                if (i < qe) {
-                    v = queue[i];
-                    r = rp[v];
-                    d = rp[v + 1] - r;
-                    sg = sigma[v];
-                }
-                int tot;
-                const int off = block_excl_scan(d, s_wsum, &tot);
-                s_v[tid] = v;
-                s_rp[tid] = r;
-                s_off[tid] = off;
-                s_sig[tid] = sg;
-                if (tid == 0) s_off[PB] = tot;
-                __syncthreads();
-                for (int e = tid; e < tot; e += PB) {
-                    const int k = owner(s_off, e);
-                    const int32_t w = col[s_rp[k] + (e - s_off[k])];
-                    int32_t dw = dist[w];
-                    if (dw < 0) {
-                        const int32_t old = atomicCAS(&dist[w], -1, L + 1);
-                        if (old == -1) {
-                            const int pos = atomicAdd(&s_tail, 1);
-                            queue[pos] = w;
-                            dw = L + 1;
-                        } else {
-                            dw = old;
+                const int tot = wg::stage_chunk(queue, cb, qe, rp, ch);
+                for (int e0 = tid; e0 < tot; e0 += PB * U) {
+                    int k[U];
+                    int32_t a[U], w[U], dw[U];
+                    wg::arc_burst<U>(ch, e0, tot, k, a);
+#pragma unroll
+                    for (int j = 0; j < U; ++j) w[j] = a[j] >= 0 ? col[a[j]] : 0;
+#pragma unroll
+                    for (int j = 0; j < U; ++j) dw[j] = a[j] >= 0 ? dist[w[j]] : 0;
+#pragma unroll
+                    for (int j = 0; j < U; ++j) {
+                        if (a[j] < 0) continue;
+                        int32_t d = dw[j];
+                        if (d < 0) {
+                            const int32_t old = atomicCAS(&dist[w[j]], -1, L + 1);
+                            if (old == -1) {
+                                queue[atomicAdd(&s_tail, 1)] = w[j];
+                                d = L + 1;
+                            } else {
+                                d = old;
+                            }
+                        }
+                        if (d == L + 1) { // v in P_s(w)
+                            const uint64_t x = sigma[ch.v[k[j]]];
+                            const uint64_t old = atomicAdd((unsigned long long *)&sigma[w[j]], (unsigned long long)x);
+                            if (old + x < old) s_ovf = 1;
                         }
                     }
-                    if (dw == L + 1) { // v in P_s(w)
-                        const uint64_t x = s_sig[k];
-                        const uint64_t old = atomicAdd((unsigned long long *)&sigma[w], (unsigned long long)x);
-                        if (old + x < old) s_ovf = 1;
-                    }
                 }
-                bar();
+                __syncthreads(); // the chunk's LDS is restaged
             }
+            wg::bar();
             qb = qe;
             qe = s_tail;
             ++L;
             if (tid == 0) lev[L + 1] = qe;
-            bar();
+            wg::bar();
         }
         const int32_t nlev = L; // non-empty levels 0..nlev-1
 
@@ -172,28 +116,24 @@ __global__ __launch_bounds__(PB) void k_plain_sweep(
         for (int32_t l = nlev - 1; l >= lowest; --l) {
             const int32_t lb = lev[l], le = lev[l + 1];
             if (l < nlev - 1) {
+                // acc[v] = sum of c(w) = acc[w] over successors w (level l + 1)
                 for (int32_t cb = lb; cb < le; cb += PB) {
-                    const int32_t i = cb + tid;
-                    int32_t v = -1, r = 0, d = 0;
-                    if (i < le) {
-                        v = queue[i];
-                        r = rp[v];
-                        d = rp[v + 1] - r;
+                    const int tot = wg::stage_chunk(queue, cb, le, rp, ch);
+                    for (int e0 = tid; e0 < tot; e0 += PB * U) {
+                        int k[U];
+                        int32_t a[U], w[U], dw[U];
+                        wg::arc_burst<U>(ch, e0, tot, k, a);
+#pragma unroll
+                        for (int j = 0; j < U; ++j) w[j] = a[j] >= 0 ? col[a[j]] : 0;
+#pragma unroll
+                        for (int j = 0; j < U; ++j) dw[j] = a[j] >= 0 ? dist[w[j]] : -1;
+#pragma unroll
+                        for (int j = 0; j < U; ++j)
+                            if (a[j] >= 0 && dw[j] == l + 1) unsafeAtomicAdd(&acc[ch.v[k[j]]], acc[w[j]]);
                     }
-                    int tot;
-                    const int off = block_excl_scan(d, s_wsum, &tot);
-                    s_v[tid] = v;
-                    s_rp[tid] = r;
-                    s_off[tid] = off;
-                    if (tid == 0) s_off[PB] = tot;
                     __syncthreads();
-                    for (int e = tid; e < tot; e += PB) {
-                        const int k = owner(s_off, e);
-                        const int32_t w = col[s_rp[k] + (e - s_off[k])];
-                        if (dist[w] == l + 1) unsafeAtomicAdd(&acc[s_v[k]], acc[w]); // acc[w] holds c(w)
-                    }
-                    bar();
                 }
+                wg::bar();
             }
             for (int32_t i = lb + tid; i < le; i += PB) {
                 const int32_t v = queue[i];
@@ -203,7 +143,7 @@ __global__ __launch_bounds__(PB) void k_plain_sweep(
                 if (delta_dump) delta_dump[(size_t)idx * n + v] = dl;
                 acc[v] = (1.0 + dl) / sv;
             }
-            bar();
+            wg::bar();
         }
         if (dist_dump) {
             for (int32_t v = tid; v < n; v += PB) {
@@ -214,7 +154,7 @@ __global__ __launch_bounds__(PB) void k_plain_sweep(
             }
         }
         if (tid == 0 && s_ovf) atomicOr(status, (uint32_t)BC_DEV_SIGMA_OVERFLOW);
-        bar();
+        wg::bar();
     }
 }
 
