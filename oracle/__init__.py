@@ -7,7 +7,8 @@ library never does, and the two share no code.
 Contents
   brandes.c  serial Brandes (Sec. 1.1, Theorem 1.1): BFS for unit weights,
              Dijkstra for positive integer weights; exact 128-bit path counts,
-             IEEE double dependencies and BC.  Loaded here through ctypes.
+             IEEE double dependencies, BC and (optionally) edge betweenness.
+             Loaded here through ctypes.
   cross.py   independent cross-oracles used to pin brandes.c:
              brute-force path enumeration from the definitions (Sec. 1.1),
              all-pairs counts + Algorithm 2 (Sec. 4.2.1), and the corrected
@@ -58,6 +59,10 @@ def _load():
             lib.oracle_bc.argtypes = [ctypes.c_int32, i32p, i32p, u32p, i32p, ctypes.c_int64,
                                       ctypes.c_int32, ctypes.POINTER(ctypes.c_double), i32p]
             lib.oracle_bc.restype = ctypes.c_int
+            lib.oracle_edge_bc.argtypes = [ctypes.c_int32, i32p, i32p, u32p, i32p, ctypes.c_int64,
+                                           ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_double), i32p]
+            lib.oracle_edge_bc.restype = ctypes.c_int
             lib.oracle_sssp.argtypes = [ctypes.c_int32, i32p, i32p, u32p, ctypes.c_int32,
                                         ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_uint64),
                                         ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double)]
@@ -101,6 +106,26 @@ def bc(g, sources=None, threads: int = 1, return_flags: bool = False):
         raise OracleError(f"oracle_bc failed with code {rc}")
     out = out[: g.n]
     return (out, bool(flag[0])) if return_flags else out
+
+
+def edge_bc(g, sources=None, threads: int = 1):
+    """(BC, EB): vertex betweenness as :func:`bc` and, per arc of g's CSR, the
+    edge betweenness of its edge -- the sum over ordered pairs (s,t), s in the
+    sources, of the fraction of shortest s-t paths through the edge.  Both arcs
+    of an edge carry the same value.  Rows of g must be sorted."""
+    lib = _load()
+    rp, col, w = _graph_arrays(g)
+    src = np.arange(g.n, dtype=np.int32) if sources is None else np.ascontiguousarray(sources, dtype=np.int32)
+    out = np.zeros(max(g.n, 1), dtype=np.float64)
+    eb = np.zeros(max(col.size, 1), dtype=np.float64)
+    flag = np.zeros(1, dtype=np.int32)
+    src_arg = src if src.size else np.zeros(1, np.int32)
+    rc = lib.oracle_edge_bc(g.n, _ptr(rp, ctypes.c_int32), _ptr(col, ctypes.c_int32), _ptr(w, ctypes.c_uint32),
+                            _ptr(src_arg, ctypes.c_int32), int(src.size), int(threads),
+                            _ptr(out, ctypes.c_double), _ptr(eb, ctypes.c_double), _ptr(flag, ctypes.c_int32))
+    if rc != OK:
+        raise OracleError(f"oracle_edge_bc failed with code {rc}")
+    return out[: g.n], eb[: int(np.asarray(g.col).size)]
 
 
 def sssp(g, s: int):

@@ -15,7 +15,12 @@
  *                     (lambda_sv / lambda_sw) * (1 + delta_s*(w)),
  *     where P_s(w) = { u : (u,w) in E, d(s,w) = d(s,u) + w(u,w) };
  *   - BC(v) = sum over sources s != v of delta_s*(v): the running score of
- *     Brandes's algorithm, over ordered pairs, with no halving.
+ *     Brandes's algorithm, over ordered pairs, with no halving;
+ *   - optionally the edge betweenness of every edge {v,x}: the sum over
+ *     ordered pairs (s,t) of the fraction of shortest s-t paths that use the
+ *     edge.  For a source s each shortest-path DAG arc v -> x (v in P_s(x))
+ *     carries (lambda_sv / lambda_sx) * (1 + delta_s*(x)) of them -- the same
+ *     per-arc term whose sum over x is delta_s*(v) in Theorem 1.1.
  *
  * Unit weights use a FIFO breadth-first search; positive integer weights use
  * Dijkstra's algorithm with a binary heap, then visit the reached vertices in
@@ -181,7 +186,8 @@ static int forward_dijkstra(const graph_t *g, int32_t s, work_t *w) {
 }
 
 /* ---- backward sweep: Theorem 1.1, farthest vertices first ---- */
-static void backward(const graph_t *g, work_t *w) {
+/* eb (may be NULL): per-arc edge betweenness, each DAG arc's term added to it */
+static void backward(const graph_t *g, work_t *w, double *eb) {
     for (int32_t v = 0; v < g->n; ++v) w->delta[v] = 0.0;
     for (int32_t i = w->reached - 1; i >= 0; --i) {
         int32_t v = w->order[i];
@@ -191,17 +197,19 @@ static void backward(const graph_t *g, work_t *w) {
             int64_t wt = g->weight ? (int64_t)g->weight[e] : 1;
             if (w->dist[x] >= 0 && w->dist[x] == w->dist[v] + wt) { /* v in P_s(x) */
                 double ratio = (double)w->sigma[v] / (double)w->sigma[x];
-                acc += ratio * (1.0 + w->delta[x]);
+                double term = ratio * (1.0 + w->delta[x]);
+                acc += term;
+                if (eb) eb[e] += term;
             }
         }
         w->delta[v] = acc;
     }
 }
 
-static int single_source(const graph_t *g, int32_t s, work_t *w) {
+static int single_source(const graph_t *g, int32_t s, work_t *w, double *eb) {
     int rc = g->weight ? forward_dijkstra(g, s, w) : forward_bfs(g, s, w);
     if (rc) return rc;
-    backward(g, w);
+    backward(g, w, eb);
     return ORACLE_OK;
 }
 
@@ -212,6 +220,7 @@ typedef struct {
     const int32_t *sources;
     int64_t begin, end;
     double *bc;  /* this thread's partial sum, n entries */
+    double *eb;  /* this thread's per-arc partial sum, nnz entries, or NULL */
     int rc;
     int above_u64;
 } job_t;
@@ -222,7 +231,7 @@ static void *run_job(void *arg) {
     if (work_alloc(&w, j->g->n, j->g->row_ptr[j->g->n])) { work_free(&w); j->rc = ORACLE_ERR_NOMEM; return NULL; }
     for (int64_t i = j->begin; i < j->end && !j->rc; ++i) {
         int32_t s = j->sources[i];
-        j->rc = single_source(j->g, s, &w);
+        j->rc = single_source(j->g, s, &w, j->eb);
         if (j->rc) break;
         for (int32_t v = 0; v < j->g->n; ++v)
             if (v != s) j->bc[v] += w.delta[v];
@@ -245,14 +254,17 @@ static int check_graph(int32_t n, const int32_t *row_ptr, const int32_t *col) {
 
 /*
  * BC over the given sources (a multiset of vertex ids; each entry adds its
- * dependencies).  bc_out: n doubles, overwritten.  Sources are split into
- * nthreads contiguous chunks; per-thread partial sums are added in thread
- * order, so the result is deterministic for a fixed nthreads.
+ * dependencies).  bc_out: n doubles, overwritten.  eb_out (may be NULL): nnz
+ * doubles, overwritten with the edge betweenness of each arc's edge (both
+ * arcs of an edge carry the same value: the sum of the terms of its two
+ * directions).  Rows must be sorted when eb_out is requested.  Sources are
+ * split into nthreads contiguous chunks; per-thread partial sums are added in
+ * thread order, so the result is deterministic for a fixed nthreads.
  * above_u64_out (may be NULL): set to 1 when some path count exceeded 2^64-1.
  */
-int oracle_bc(int32_t n, const int32_t *row_ptr, const int32_t *col, const uint32_t *weight,
-              const int32_t *sources, int64_t nsources, int32_t nthreads,
-              double *bc_out, int32_t *above_u64_out) {
+int oracle_edge_bc(int32_t n, const int32_t *row_ptr, const int32_t *col, const uint32_t *weight,
+                   const int32_t *sources, int64_t nsources, int32_t nthreads,
+                   double *bc_out, double *eb_out, int32_t *above_u64_out) {
     if (check_graph(n, row_ptr, col) || !bc_out || nsources < 0 || (nsources > 0 && !sources))
         return ORACLE_ERR_ARG;
     for (int64_t i = 0; i < nsources; ++i)
@@ -260,6 +272,7 @@ int oracle_bc(int32_t n, const int32_t *row_ptr, const int32_t *col, const uint3
     if (weight)
         for (int32_t e = 0; e < row_ptr[n]; ++e)
             if (weight[e] == 0) return ORACLE_ERR_ARG;
+    const int64_t nnz = row_ptr[n];
     graph_t g = { n, row_ptr, col, weight };
     if (nthreads < 1) nthreads = 1;
     if (nthreads > nsources && nsources > 0) nthreads = (int32_t)nsources;
@@ -275,6 +288,10 @@ int oracle_bc(int32_t n, const int32_t *row_ptr, const int32_t *col, const uint3
         jobs[t].end = nsources * (t + 1) / nthreads;
         jobs[t].bc = calloc(n > 0 ? (size_t)n : 1, sizeof(double));
         if (!jobs[t].bc) rc = ORACLE_ERR_NOMEM;
+        if (eb_out) {
+            jobs[t].eb = calloc(nnz > 0 ? (size_t)nnz : 1, sizeof(double));
+            if (!jobs[t].eb) rc = ORACLE_ERR_NOMEM;
+        }
     }
     if (rc == ORACLE_OK) {
         if (nthreads == 1) {
@@ -290,11 +307,38 @@ int oracle_bc(int32_t n, const int32_t *row_ptr, const int32_t *col, const uint3
             above |= jobs[t].above_u64;
             for (int32_t v = 0; v < n; ++v) bc_out[v] += jobs[t].bc[v];
         }
+        if (eb_out) {
+            double *arc = calloc(nnz > 0 ? (size_t)nnz : 1, sizeof(double));
+            if (!arc) rc = rc ? rc : ORACLE_ERR_NOMEM;
+            else {
+                for (int32_t t = 0; t < nthreads; ++t)
+                    for (int64_t e = 0; e < nnz; ++e) arc[e] += jobs[t].eb[e];
+                /* an edge's value: the terms of both of its arcs */
+                for (int32_t v = 0; v < n; ++v)
+                    for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+                        int32_t x = col[e], lo = row_ptr[x], hi = row_ptr[x + 1];
+                        while (lo < hi) { /* the reverse arc x -> v in x's sorted row */
+                            int32_t mid = lo + (hi - lo) / 2;
+                            if (col[mid] < v) lo = mid + 1;
+                            else hi = mid;
+                        }
+                        eb_out[e] = arc[e] + (lo < row_ptr[x + 1] && col[lo] == v ? arc[lo] : 0.0);
+                    }
+                free(arc);
+            }
+        }
         if (above_u64_out) *above_u64_out = above;
     }
-    for (int32_t t = 0; t < nthreads; ++t) free(jobs[t].bc);
+    for (int32_t t = 0; t < nthreads; ++t) { free(jobs[t].bc); free(jobs[t].eb); }
     free(jobs); free(th);
     return rc;
+}
+
+/* BC only: oracle_edge_bc without the edge output. */
+int oracle_bc(int32_t n, const int32_t *row_ptr, const int32_t *col, const uint32_t *weight,
+              const int32_t *sources, int64_t nsources, int32_t nthreads,
+              double *bc_out, int32_t *above_u64_out) {
+    return oracle_edge_bc(n, row_ptr, col, weight, sources, nsources, nthreads, bc_out, NULL, above_u64_out);
 }
 
 /*
@@ -309,7 +353,7 @@ int oracle_sssp(int32_t n, const int32_t *row_ptr, const int32_t *col, const uin
     graph_t g = { n, row_ptr, col, weight };
     work_t w;
     if (work_alloc(&w, n, row_ptr[n])) { work_free(&w); return ORACLE_ERR_NOMEM; }
-    int rc = single_source(&g, s, &w);
+    int rc = single_source(&g, s, &w, NULL);
     if (rc == ORACLE_OK) {
         for (int32_t v = 0; v < n; ++v) {
             if (dist) dist[v] = w.dist[v];

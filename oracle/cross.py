@@ -82,6 +82,39 @@ def brute_force(g):
     return dist, count, bc
 
 
+def brute_force_edges(g):
+    """Edge betweenness from the definition: for every ordered pair (s,t) the
+    fraction of shortest s-t paths (all simple paths enumerated) that use each
+    edge, summed.  Returns {(min(u,x), max(u,x)): Fraction}."""
+    n = g.n
+    adj = _adjacency(g)
+    eb = {}
+    for s in range(n):
+        best = [None] * n
+        cnt = [0] * n
+        thr = [dict() for _ in range(n)]  # thr[t][edge] = shortest s-t paths through edge
+        stack = [(s, 1 << s, 0, ())]
+        while stack:
+            v, seen, length, edges = stack.pop()
+            if best[v] is None or length < best[v]:
+                best[v] = length
+                cnt[v] = 1
+                thr[v] = {e: 1 for e in edges}
+            elif length == best[v]:
+                cnt[v] += 1
+                for e in edges:
+                    thr[v][e] = thr[v].get(e, 0) + 1
+            for x, w in adj[v]:
+                if not (seen >> x) & 1:
+                    stack.append((x, seen | (1 << x), length + w, edges + ((min(v, x), max(v, x)),)))
+        for t in range(n):
+            if t == s or cnt[t] == 0:
+                continue
+            for e, c in thr[t].items():
+                eb[e] = eb.get(e, Fraction(0)) + Fraction(c, cnt[t])
+    return eb
+
+
 INF = np.int64(1) << np.int64(50)
 
 
