@@ -221,6 +221,7 @@ def main():
                     help="skip the comparison forms")
     ap.add_argument("--compare-steps", "--plain-steps", dest="compare_steps", type=int, default=1)
     ap.add_argument("--no-free-batch", action="store_true", help="skip the extra run at the tuned batch width")
+    ap.add_argument("--edges", action="store_true", help="also accumulate edge betweenness in the measured form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sources", type=int, default=0, help="run only the first N sources (profiling)")
     ap.add_argument("--calibrate-copy", action="store_true", help="end with a 1 GiB device copy")
@@ -245,9 +246,10 @@ def main():
     wl = load_workload(args.workload, args.sources)
     src, work = wl["src"], wl["work"]
 
-    def timed_runs(form, steps, warmup, batch=0, timing=True):
+    def timed_runs(form, steps, warmup, batch=0, timing=True, edges=False):
         t = time.perf_counter()
-        ctx = bcgpu.BC(wl["graph"], form="auto" if form == "many" else form, batch=batch, timing=timing)
+        ctx = bcgpu.BC(wl["graph"], form="auto" if form == "many" else form, batch=batch, timing=timing,
+                       edges=edges)
         info = ctx.info()
         log(f"{form} create (upload, dense adjacency, tuning) {time.perf_counter() - t:.2f}s: batch {info.batch}, "
             f"products when density >= ({info.mfma_density_fwd:.3f} fwd, {info.mfma_density_bwd:.3f} bwd), "
@@ -268,7 +270,7 @@ def main():
         log(f"{form} {steps} steps: {dt * 1e3:.1f} ms/step, {work / dt:.3e} TEPS")
         return ctx, dt, bc
 
-    ctx, dt, bc_main = timed_runs(form, args.steps, args.warmup, batch)
+    ctx, dt, bc_main = timed_runs(form, args.steps, args.warmup, batch, edges=args.edges)
     info = ctx.info()
     kern = {}
     for k in KERNELS:
@@ -311,7 +313,7 @@ def main():
         log("calibration copy: 1 GiB read, 1 GiB written")
 
     config = {"workload": spec["desc"], "n": wl["n"], "m": wl["m"], "sources": wl["S"], "batch": info.batch,
-              "form": form, "levels_max": info.max_levels}
+              "form": form, "levels_max": info.max_levels, "edge_betweenness": bool(args.edges)}
     if form in ("hybrid", "sparse", "algebraic"):
         config["mfma_density_thresholds"] = [info.mfma_density_fwd, info.mfma_density_bwd]
         config["tune_source"] = ["default", "measured", "cached"][info.tune_source]

@@ -150,7 +150,12 @@ typedef struct {
                              at most 2048 unweighted, 1024 weighted; the budget
                              is 16 GB unweighted, 96 GB weighted, 192 GB weighted
                              with an explicit grid) */
-    int32_t reserved[2];
+    int32_t edges;        /* nonzero: also accumulate edge betweenness (read with
+                             bc_read_edges).  Plain, sparse and hybrid forms
+                             (the hybrid form then takes every backward level
+                             by pulls); BC_ERR_UNSUPPORTED for the algebraic
+                             form and bc_create_many. */
+    int32_t reserved[1];
 } bc_options;
 
 /* Where the batch width and hybrid thresholds of a context came from. */
@@ -212,7 +217,20 @@ bc_status bc_run(bc_ctx *ctx, const int32_t *sources, int64_t count, bc_mem mem)
  */
 bc_status bc_read(bc_ctx *ctx, double *bc_out, bc_mem mem);
 
-/* Zeroes the running BC and clears a recorded overflow. */
+/*
+ * Edge betweenness (contexts created with edges != 0): for every arc e of the
+ * caller's CSR, the betweenness of its undirected edge {u, col[e]} -- the sum,
+ * over the sources run and every target t, of the fraction of shortest s-t
+ * paths that use the edge (ordered pairs, no halving, as BC; both arcs of an
+ * edge carry the same value).  For a source s each shortest-path DAG arc
+ * v -> w contributes lambda_sv * (1 + delta_s*(w)) / lambda_sw, the per-arc
+ * term of Theorem 1.1.  eb_out: nnz doubles (host or device per mem);
+ * synchronises.  Errors: BC_ERR_UNSUPPORTED (context without edges),
+ * BC_ERR_OVERFLOW as bc_read.
+ */
+bc_status bc_read_edges(bc_ctx *ctx, double *eb_out, bc_mem mem);
+
+/* Zeroes the running BC (and edge betweenness) and clears a recorded overflow. */
 bc_status bc_reset(bc_ctx *ctx);
 
 /*

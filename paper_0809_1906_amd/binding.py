@@ -62,7 +62,8 @@ class bc_options(ctypes.Structure):
                 ("device", ctypes.c_int32), ("stream", ctypes.c_void_p), ("allocator", bc_allocator),
                 ("timing", ctypes.c_int32), ("split_degree", ctypes.c_int32),
                 ("vertex_order", ctypes.c_int32), ("arena_log2", ctypes.c_int32),
-                ("tune_cache", ctypes.c_char_p), ("grid", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("tune_cache", ctypes.c_char_p), ("grid", ctypes.c_int32), ("edges", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 1)]
 
 
 class bc_info(ctypes.Structure):
@@ -83,6 +84,7 @@ SIGNATURES = {
     "bc_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int]),
     "bc_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
     "bc_reset": (ctypes.c_int, [ctypes.c_void_p]),
+    "bc_read_edges": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
     "bc_read_sssp": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_void_p]),
     "bc_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(bc_info)]),
@@ -159,6 +161,10 @@ def bc_reset(ctx) -> None:
     _check(load().bc_reset(ctx), ctx)
 
 
+def bc_read_edges(ctx, out_ptr, mem: int) -> None:
+    _check(load().bc_read_edges(ctx, out_ptr, mem), ctx)
+
+
 def bc_read_sssp(ctx, sources_ptr, count: int, dist_ptr, sigma_ptr, delta_ptr) -> None:
     _check(load().bc_read_sssp(ctx, sources_ptr, count, dist_ptr, sigma_ptr, delta_ptr), ctx)
 
@@ -226,7 +232,7 @@ class BC:
     def __init__(self, graph, form: str = "auto", batch: int = 0, device: int = 0, stream=None,
                  allocator: str = "torch", timing: bool = False, split_degree: int = 0,
                  vertex_order: str = "degree", arena_log2: int = 0, tune_cache: Optional[str] = None,
-                 grid: int = 0):
+                 grid: int = 0, edges: bool = False):
         import torch
         load()
         if not torch.cuda.is_available():
@@ -234,6 +240,8 @@ class BC:
         self.torch = torch
         self.device = device
         self.n = int(sum(g.n for g in graph)) if isinstance(graph, (list, tuple)) else int(graph.n)
+        self.nnz = (int(sum(np.asarray(g.col).size for g in graph)) if isinstance(graph, (list, tuple))
+                    else int(np.asarray(graph.col).size))
         self._stream = stream if stream is not None else torch.cuda.current_stream(device)
         opt = bc_options_init()
         opt.form = FORMS[form]
@@ -247,6 +255,7 @@ class BC:
         self._tune_cache = None if tune_cache is None else os.fsencode(tune_cache)
         opt.tune_cache = self._tune_cache
         opt.grid = grid
+        opt.edges = 1 if edges else 0
         self._alloc = None
         if allocator == "torch":
             self._alloc = _TorchAllocator(device)
@@ -307,6 +316,12 @@ class BC:
         out = np.zeros(max(self.n, 1), dtype=np.float64)
         bc_read(self._ctx, out.ctypes.data, BC_MEM_HOST)
         return out[: self.n]
+
+    def read_edges(self) -> np.ndarray:
+        """Edge betweenness per arc of the graph's CSR (contexts made with edges=True)."""
+        out = np.zeros(max(self.nnz, 1), dtype=np.float64)
+        bc_read_edges(self._ctx, out.ctypes.data, BC_MEM_HOST)
+        return out[: self.nnz]
 
     def read_device(self):
         out = self.torch.empty(max(self.n, 1), dtype=self.torch.float64, device=f"cuda:{self.device}")

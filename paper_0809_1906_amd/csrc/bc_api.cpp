@@ -303,6 +303,9 @@ bc_status bc_create(const bc_graph *g, const bc_options *opt_in, bc_ctx **out) {
 
     bc_form form = opt.form;
     if (form == BC_FORM_AUTO) form = hw ? BC_FORM_PLAIN_FP64 : BC_FORM_SPARSE;
+    if (opt.edges && form == BC_FORM_ALGEBRAIC)
+        return fail_create(BC_ERR_UNSUPPORTED,
+                           "edge betweenness needs per-arc terms; the algebraic form's products give row sums only");
     if (hw && (form == BC_FORM_SPARSE || form == BC_FORM_ALGEBRAIC || form == BC_FORM_HYBRID))
         return fail_create(BC_ERR_UNSUPPORTED,
                            "weighted graphs are served by the per-source form (BC_FORM_PLAIN_FP64) only");
@@ -404,6 +407,34 @@ bc_status bc_create(const bc_graph *g, const bc_options *opt_in, bc_ctx **out) {
         hipMemsetAsync(ctx->status, 0, 256, ctx->stream) != hipSuccess)
         return bail(BC_ERR_DEVICE, "uploading the graph failed");
 
+    if (opt.edges) {
+        // caller arc e = (u, x) -> internal arcs (u', x') and (x', u'), found
+        // in the sorted internal rows
+        ctx->edges = true;
+        std::vector<int32_t> fwd((size_t)std::max(nnz, 1)), rev((size_t)std::max(nnz, 1));
+        auto find = [&](int32_t row, int32_t x) {
+            const int32_t *b = ucol + urp[row], *e = ucol + urp[row + 1];
+            return (int32_t)(std::lower_bound(b, e, x) - ucol);
+        };
+        for (int32_t u = 0; u < n; ++u)
+            for (int32_t e = hrp[u]; e < hrp[u + 1]; ++e) {
+                const int32_t x = hcol[e];
+                const int32_t iu = relabel ? new_of_old[(size_t)u] : u, ix = relabel ? new_of_old[(size_t)x] : x;
+                fwd[(size_t)e] = find(iu, ix);
+                rev[(size_t)e] = find(ix, iu);
+            }
+        ctx->eb = (double *)bc_dalloc(ctx, sizeof(double) * (size_t)std::max(nnz, 1));
+        ctx->eb_scratch = (double *)bc_dalloc(ctx, sizeof(double) * (size_t)std::max(nnz, 1));
+        ctx->arc_fwd = (int32_t *)bc_dalloc(ctx, sizeof(int32_t) * (size_t)std::max(nnz, 1));
+        ctx->arc_rev = (int32_t *)bc_dalloc(ctx, sizeof(int32_t) * (size_t)std::max(nnz, 1));
+        if (!ctx->eb || !ctx->eb_scratch || !ctx->arc_fwd || !ctx->arc_rev)
+            return bail(BC_ERR_NOMEM, "device allocation failed");
+        if (hipMemsetAsync(ctx->eb, 0, sizeof(double) * (size_t)std::max(nnz, 1), ctx->stream) != hipSuccess ||
+            (nnz > 0 && (hipMemcpy(ctx->arc_fwd, fwd.data(), sizeof(int32_t) * (size_t)nnz, hipMemcpyHostToDevice) != hipSuccess ||
+                         hipMemcpy(ctx->arc_rev, rev.data(), sizeof(int32_t) * (size_t)nnz, hipMemcpyHostToDevice) != hipSuccess)))
+            return bail(BC_ERR_DEVICE, "uploading the arc maps failed");
+    }
+
     bc_status ps = BC_OK;
     if (form == BC_FORM_PLAIN_FP64) ps = plain_prepare(ctx);
     else if (form == BC_FORM_SPARSE || form == BC_FORM_HYBRID) ps = tune_prepare(ctx, opt, form);
@@ -431,6 +462,7 @@ bc_status bc_create_many(const bc_graph *gs, int32_t count, const bc_options *op
         opt = *opt_in;
     }
     if (opt.batch < 0) return fail_create(BC_ERR_INVALID_ARG, "batch must be >= 0");
+    if (opt.edges) return fail_create(BC_ERR_UNSUPPORTED, "bc_create_many computes vertex betweenness only");
     if ((opt.allocator.alloc == nullptr) != (opt.allocator.free == nullptr))
         return fail_create(BC_ERR_INVALID_ARG, "allocator needs both alloc and free, or neither");
     // host validation of every graph, then the concatenated layout
@@ -610,11 +642,29 @@ bc_status bc_read(bc_ctx *ctx, double *bc_out, bc_mem mem) {
     return BC_OK;
 }
 
+bc_status bc_read_edges(bc_ctx *ctx, double *eb_out, bc_mem mem) {
+    if (!ctx) return BC_ERR_INVALID_ARG;
+    if (!ctx->edges) return bc_fail(ctx, BC_ERR_UNSUPPORTED, "the context was created without edges");
+    if (!eb_out && ctx->nnz > 0) return bc_fail(ctx, BC_ERR_INVALID_ARG, "eb_out is NULL");
+    bc_status s = check_usable(ctx);
+    if (s != BC_OK) return s;
+    s = check_overflow(ctx);
+    if (s != BC_OK) return s;
+    if (ctx->nnz == 0) return BC_OK;
+    s = edges_to_caller_order(ctx, ctx->eb_scratch);
+    if (s != BC_OK) return s;
+    BC_HIP(ctx, hipMemcpyAsync(eb_out, ctx->eb_scratch, sizeof(double) * (size_t)ctx->nnz,
+                               mem == BC_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, ctx->stream));
+    BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return BC_OK;
+}
+
 bc_status bc_reset(bc_ctx *ctx) {
     if (!ctx) return BC_ERR_INVALID_ARG;
     bc_status s = check_usable(ctx);
     if (s != BC_OK) return s;
     BC_HIP(ctx, hipMemsetAsync(ctx->bc, 0, sizeof(double) * (size_t)std::max(ctx->n, 1), ctx->stream));
+    if (ctx->eb) BC_HIP(ctx, hipMemsetAsync(ctx->eb, 0, sizeof(double) * (size_t)std::max(ctx->nnz, 1), ctx->stream));
     BC_HIP(ctx, hipMemsetAsync(ctx->status, 0, 256, ctx->stream));
     BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
     bc_timers_clear(ctx);

@@ -97,7 +97,7 @@ struct WeightedBuffers {
     int32_t *bstart = nullptr, *bcount = nullptr, *pstart = nullptr;
     int32_t *imp_x = nullptr;     // improvement list of the current phase
     uint8_t *imp_c = nullptr;
-    int32_t *dag_p = nullptr, *dag_s = nullptr, *gdag = nullptr; // DAG arcs by phase
+    int32_t *dag_p = nullptr, *dag_s = nullptr, *dag_a = nullptr, *gdag = nullptr; // DAG arcs by phase
     int64_t icap = 0, dcap = 0;
     uint64_t *sigma = nullptr;
     double *acc = nullptr;
@@ -163,6 +163,11 @@ struct bc_ctx {
     int32_t *col = nullptr;
     uint8_t *weight = nullptr;       // weights as bytes (weighted graphs with max weight <= 255)
     double *bc = nullptr;
+    double *eb = nullptr;            // [nnz] edge betweenness terms per internal arc (edges on)
+    double *eb_scratch = nullptr;    // [nnz] caller-order staging for bc_read_edges
+    int32_t *arc_fwd = nullptr;      // [nnz] internal arc of caller arc e = (u, x)
+    int32_t *arc_rev = nullptr;      // [nnz] internal arc of (x, u)
+    bool edges = false;
     uint32_t *status = nullptr;      // [0]: BC_DEV_* bits; [1]: a batch needs uint64 counts
     uint32_t *status_host = nullptr; // pinned
     int32_t *sources = nullptr;      // staging for bc_run
@@ -222,6 +227,8 @@ bc_status fill_all_sources(bc_ctx *ctx, int32_t *ids, int64_t count); // ids[i] 
 bc_status rows_to_caller_order_f64(bc_ctx *ctx, double *out, const double *in, int64_t rows);
 bc_status rows_to_caller_order_i32(bc_ctx *ctx, int32_t *out, const int32_t *in, int64_t rows);
 bc_status rows_to_caller_order_u64(bc_ctx *ctx, uint64_t *out, const uint64_t *in, int64_t rows);
+// out[e] = eb[arc_fwd[e]] + eb[arc_rev[e]] for the caller's arcs
+bc_status edges_to_caller_order(bc_ctx *ctx, double *out);
 
 // ---- forms (kernels + launchers) ----------------------------------------------
 bc_status plain_prepare(bc_ctx *ctx);

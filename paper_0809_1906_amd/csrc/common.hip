@@ -32,6 +32,21 @@ inline unsigned blocks_for(int64_t count) { return (unsigned)((count + CB - 1) /
 
 } // namespace
 
+__global__ __launch_bounds__(CB) void k_edge_gather(double *__restrict__ out, const double *__restrict__ eb,
+                                                    const int32_t *__restrict__ fwd, const int32_t *__restrict__ rev,
+                                                    int64_t nnz) {
+    const int64_t e = (int64_t)blockIdx.x * CB + threadIdx.x;
+    if (e < nnz) out[e] = eb[fwd[e]] + eb[rev[e]];
+}
+
+bc_status edges_to_caller_order(bc_ctx *ctx, double *out) {
+    if (ctx->nnz <= 0) return BC_OK;
+    hipLaunchKernelGGL(k_edge_gather, dim3(blocks_for(ctx->nnz)), dim3(CB), 0, ctx->stream, out, ctx->eb,
+                       ctx->arc_fwd, ctx->arc_rev, (int64_t)ctx->nnz);
+    BC_HIP(ctx, hipGetLastError());
+    return BC_OK;
+}
+
 bc_status fill_all_sources(bc_ctx *ctx, int32_t *ids, int64_t count) {
     if (count <= 0) return BC_OK;
     hipLaunchKernelGGL(k_iota, dim3(blocks_for(count)), dim3(CB), 0, ctx->stream, ids, count);

@@ -254,7 +254,7 @@ bc_status multigraph_run(bc_ctx *ctx) {
         hipLaunchKernelGGL(k_mg_sweep, dim3(m.grid), dim3(MT), 0, m.stream, a);
         BC_HIP(ctx, hipStreamEndCapture(m.stream, &graph));
         const hipError_t e = hipGraphInstantiate(&m.exec, graph, nullptr, nullptr, 0);
-        hipGraphDestroy(graph);
+        (void)hipGraphDestroy(graph);
         if (e != hipSuccess) return bc_hip(ctx, e, "hipGraphInstantiate");
     }
     // order the private capture stream after prior work on the context stream

@@ -29,7 +29,7 @@ __global__ __launch_bounds__(PB) void k_plain_sweep(
     const int32_t *__restrict__ sources, int64_t count, unsigned long long *next_counter,
     int32_t *dist_all, uint64_t *sigma_all, double *acc_all, int32_t *queue_all, int32_t *lev_all,
     double *bc, uint32_t *status, int accumulate,
-    double *delta_dump, int32_t *dist_dump, uint64_t *sigma_dump) {
+    double *delta_dump, int32_t *dist_dump, uint64_t *sigma_dump, double *eb) {
     __shared__ wg::Chunk ch;
     __shared__ int32_t s_tail;
     __shared__ long long s_idx;
@@ -112,7 +112,8 @@ __global__ __launch_bounds__(PB) void k_plain_sweep(
         const int32_t nlev = L; // non-empty levels 0..nlev-1
 
         // ---- backward: deepest level first ----
-        const int32_t lowest = accumulate ? 1 : 0;
+        // (level 0 adds nothing to BC, but its arcs carry edge terms)
+        const int32_t lowest = accumulate && !eb ? 1 : 0;
         for (int32_t l = nlev - 1; l >= lowest; --l) {
             const int32_t lb = lev[l], le = lev[l + 1];
             if (l < nlev - 1) {
@@ -129,7 +130,13 @@ __global__ __launch_bounds__(PB) void k_plain_sweep(
                         for (int j = 0; j < U; ++j) dw[j] = a[j] >= 0 ? dist[w[j]] : -1;
 #pragma unroll
                         for (int j = 0; j < U; ++j)
-                            if (a[j] >= 0 && dw[j] == l + 1) unsafeAtomicAdd(&acc[ch.v[k[j]]], acc[w[j]]);
+                            if (a[j] >= 0 && dw[j] == l + 1) {
+                                const int32_t v = ch.v[k[j]];
+                                const double cw = acc[w[j]];
+                                unsafeAtomicAdd(&acc[v], cw);
+                                // edge term of arc v -> w: lambda(v) c(w)
+                                if (eb) unsafeAtomicAdd(&eb[a[j]], (double)sigma[v] * cw);
+                            }
                     }
                     __syncthreads();
                 }
@@ -189,7 +196,8 @@ bc_status plain_run(bc_ctx *ctx, const int32_t *d_sources, int64_t count, bool a
     LaunchTimer t(ctx, "plain_sweep");
     hipLaunchKernelGGL(k_plain_sweep, dim3(grid), dim3(PB), 0, ctx->stream, ctx->n, ctx->row_ptr, ctx->col,
                        d_sources, count, (unsigned long long *)p.next, p.dist, p.sigma, p.acc, p.queue, p.lev,
-                       ctx->bc, ctx->status, accumulate ? 1 : 0, delta_dump, dist_dump, sigma_dump);
+                       ctx->bc, ctx->status, accumulate ? 1 : 0, delta_dump, dist_dump, sigma_dump,
+                       accumulate && ctx->edges ? ctx->eb : nullptr);
     t.done();
     BC_HIP(ctx, hipGetLastError());
     return BC_OK;

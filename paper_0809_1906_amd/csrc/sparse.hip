@@ -471,7 +471,7 @@ __global__ __launch_bounds__(SB) void k_bwd_pull_w(Topo t, const uint64_t *__res
                                                    float *__restrict__ cval, const int32_t *__restrict__ src_lane,
                                                    double *__restrict__ bc, double *__restrict__ hacc,
                                                    uint32_t *__restrict__ arrive, double *__restrict__ delta_dump,
-                                                   int accumulate) {
+                                                   int accumulate, double *__restrict__ eb) {
     const int lane = threadIdx.x & 63;
     const int64_t wid = (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6);
     const int q = (int)(wid % NW);
@@ -485,6 +485,9 @@ __global__ __launch_bounds__(SB) void k_bwd_pull_w(Topo t, const uint64_t *__res
     if (fnext) {
         // the single-word scan over word q: shift the row base by q words
         const float *c = cval + (size_t)q * 64 + lane;
+        // edge betweenness: arc v -> w carries sum over this word's sources of
+        // lambda(v) c(w) (the per-arc term of Theorem 1.1)
+        const double sv = eb && ((F >> lane) & 1) ? (double)sigma[(size_t)v * t.B + (size_t)q * 64 + lane] : 0.0;
         for (int32_t base = it.beg; base < it.end; base += 64) {
             const int32_t e = base + lane;
             int32_t w = 0;
@@ -496,16 +499,29 @@ __global__ __launch_bounds__(SB) void k_bwd_pull_w(Topo t, const uint64_t *__res
             uint64_t act = __ballot(g != 0);
             while (act) {
                 float x[GDEPTH];
+                int jj[GDEPTH];
 #pragma unroll
                 for (int u = 0; u < GDEPTH; ++u) {
                     x[u] = 0.f;
+                    jj[u] = -1;
                     if (act) {
                         const int j = pop_lowest(act);
+                        jj[u] = j;
                         if ((rl64(g, j) >> lane) & 1) x[u] = c[(size_t)rl32(w, j) * t.B];
                     }
                 }
 #pragma unroll
                 for (int u = 0; u < GDEPTH; ++u) acc[0] += (double)x[u];
+                if (eb) {
+#pragma unroll
+                    for (int u = 0; u < GDEPTH; ++u) {
+                        if (jj[u] < 0) continue;
+                        double p = sv * (double)x[u];
+#pragma unroll
+                        for (int off = 32; off > 0; off >>= 1) p += __shfl_xor(p, off, 64);
+                        if (lane == 0 && p != 0.0) unsafeAtomicAdd(&eb[base + jj[u]], p);
+                    }
+                }
             }
         }
     }
@@ -588,6 +604,7 @@ bool by_products(const bc_ctx *ctx, int32_t l, bool forward) {
     if (l < 1) return false;
     if (ctx->al.every_level) return true;
     if (!ctx->hy.products) return false;
+    if (!forward && ctx->edges) return false; // edge terms need the per-arc pulls
     const int mode = probe_mode(ctx);
     if (mode != 0) return mode == 2;
     if (!forward) return level_density(ctx, l) >= ctx->hy.theta_bwd;
@@ -749,7 +766,9 @@ bc_status run_batch_t(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool acc
         launched = target;
     }
     s.depth_guess = nlev;
-    const int32_t lowest = accumulate ? 1 : 0;
+    // Level 0 adds nothing to BC (v is the source), but with edges on its
+    // arcs out of the source carry edge terms.
+    const int32_t lowest = accumulate && !ctx->edges ? 1 : 0;
     double *ddump = accumulate ? nullptr : s.delta_dump;
     for (int32_t lv = nlev - 1; lv >= lowest; --lv) {
         const uint64_t *fcur = s.front + (size_t)lv * words;
@@ -764,10 +783,10 @@ bc_status run_batch_t(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool acc
             continue;
         }
         LaunchTimer tm(ctx, "bwd_pull");
-        if (s.bwd_per_word)
+        if (s.bwd_per_word || ctx->edges) // edge terms come from the per-word pull
             hipLaunchKernelGGL((k_bwd_pull_w<NW, S>), dim3(word_blocks), dim3(SB), 0, ctx->stream, t, fcur, anext,
                                fnext, (const S *)sigma, s.cval, s.src, ctx->bc, s.hacc, s.arrive_w, ddump,
-                               accumulate ? 1 : 0);
+                               accumulate ? 1 : 0, accumulate && ctx->edges ? ctx->eb : nullptr);
         else
             hipLaunchKernelGGL((k_bwd_pull<NW, S>), dim3(pull_blocks), dim3(SB), 0, ctx->stream, t, fcur, anext, fnext,
                                (const S *)sigma, s.cval, s.src, ctx->bc, s.hacc, s.arrive, ddump, accumulate ? 1 : 0);

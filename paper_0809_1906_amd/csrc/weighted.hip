@@ -51,8 +51,9 @@ struct WeightedWork {
     int32_t *pstart; // [groups][RING] unwrapped arena position of each phase's bins
     int32_t *imp_x;  // [groups][icap] vertices improved in the current phase
     uint8_t *imp_c;  // [groups][icap] the weight of the improving arc
-    int32_t *dag_p;  // [groups][dcap] DAG arcs in phase order: predecessor
-    int32_t *dag_s;  // [groups][dcap]                         and successor
+    int32_t *dag_p;  // [groups][dcap] DAG arcs in phase order: predecessor,
+    int32_t *dag_s;  // [groups][dcap]                         successor
+    int32_t *dag_a;  // [groups][dcap]                         and arc index
     int32_t *gdag;   // [groups][n+1] first DAG arc of each distance group
     int64_t cap;     // arena entries per workgroup, a power of two
     int64_t icap;    // improvement-list entries per workgroup
@@ -65,7 +66,7 @@ __global__ __launch_bounds__(PB) void k_weighted_sweep(
     int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col, const uint8_t *__restrict__ wt,
     const int32_t *__restrict__ sources, const int32_t *__restrict__ slot_of, int64_t count,
     unsigned long long *next_counter, WeightedWork W, double *bc, uint32_t *status, int accumulate,
-    double *delta_dump, int32_t *dist_dump, uint64_t *sigma_dump) {
+    double *delta_dump, int32_t *dist_dump, uint64_t *sigma_dump, double *eb) {
     __shared__ wg::Chunk ch;
     __shared__ int32_t s_len[PB + 1];
     __shared__ int32_t s_st[PB];
@@ -92,6 +93,7 @@ __global__ __launch_bounds__(PB) void k_weighted_sweep(
     uint8_t *imp_c = W.imp_c + g * (size_t)W.icap;
     int32_t *dag_p = W.dag_p + g * (size_t)W.dcap;
     int32_t *dag_s = W.dag_s + g * (size_t)W.dcap;
+    int32_t *dag_a = W.dag_a + g * (size_t)W.dcap;
     int32_t *gdag = W.gdag + g * ((size_t)n + 1);
     const int32_t cmask = (int32_t)(W.cap - 1);
 
@@ -196,6 +198,7 @@ __global__ __launch_bounds__(PB) void k_weighted_sweep(
                             if (pos < W.dcap) {
                                 dag_p[pos] = x[j];
                                 dag_s[pos] = w;
+                                dag_a[pos] = a[j];
                             } else {
                                 s_abort = 1;
                             }
@@ -292,7 +295,11 @@ __global__ __launch_bounds__(PB) void k_weighted_sweep(
                 }
 #pragma unroll
                 for (int j = 0; j < U; ++j)
-                    if (p[j] >= 0) unsafeAtomicAdd(&acc[p[j]], cw[j]);
+                    if (p[j] >= 0) {
+                        unsafeAtomicAdd(&acc[p[j]], cw[j]);
+                        // edge term of the DAG arc p -> w: lambda(p) c(w)
+                        if (eb) unsafeAtomicAdd(&eb[dag_a[i0 + j * PB]], (double)sigma[p[j]] * cw[j]);
+                    }
             }
             wg::bar();
         }
@@ -337,9 +344,10 @@ bc_status alloc_work(bc_ctx *ctx, WeightedBuffers &b, int64_t cap, int groups, b
     b.imp_c = (uint8_t *)bc_dalloc(ctx, G * (size_t)b.icap);
     b.dag_p = (int32_t *)bc_dalloc(ctx, G * (size_t)b.dcap * 4);
     b.dag_s = (int32_t *)bc_dalloc(ctx, G * (size_t)b.dcap * 4);
+    b.dag_a = (int32_t *)bc_dalloc(ctx, G * (size_t)b.dcap * 4);
     b.gdag = (int32_t *)bc_dalloc(ctx, G * (n + 1) * 4);
     if (!b.dist || !b.sigma || !b.acc || !b.order || !b.gstart || !b.gdist || !b.arena || !b.bstart || !b.bcount ||
-        !b.pstart || !b.imp_x || !b.imp_c || !b.dag_p || !b.dag_s || !b.gdag)
+        !b.pstart || !b.imp_x || !b.imp_c || !b.dag_p || !b.dag_s || !b.dag_a || !b.gdag)
         return bc_fail(ctx, BC_ERR_NOMEM, "weighted form: workspace allocation failed");
     return BC_OK;
 }
@@ -347,9 +355,9 @@ bc_status alloc_work(bc_ctx *ctx, WeightedBuffers &b, int64_t cap, int groups, b
 size_t per_group_bytes(bc_ctx *ctx, int64_t cap, bool retry_ws) {
     const size_t n = (size_t)std::max(ctx->n, 1);
     // per vertex: dist, sigma, acc, order, gstart, gdist, gdag; the arena; the
-    // improvement list (5 B per entry); the DAG list (8 B per arc); the bins
+    // improvement list (5 B per entry); the DAG list (12 B per arc); the bins
     return n * (4 + 8 + 8 + 4 + 4 + 4 + 4) + 8 + (size_t)cap * 4 + (size_t)imp_cap(cap, retry_ws) * 5 +
-           (size_t)dag_cap(cap) * 8 + (2 * (size_t)RING + 1) * RING * 4;
+           (size_t)dag_cap(cap) * 12 + (2 * (size_t)RING + 1) * RING * 4;
 }
 
 int64_t pow2_at_least(int64_t x) {
@@ -361,7 +369,7 @@ int64_t pow2_at_least(int64_t x) {
 WeightedWork work_of(bc_ctx *ctx, const WeightedBuffers &b) {
     WeightedState &w = ctx->wt;
     return WeightedWork{b.dist, b.sigma, b.acc, b.order, b.gstart, b.gdist, b.arena, b.bstart, b.bcount,
-                        b.pstart, b.imp_x, b.imp_c, b.dag_p, b.dag_s, b.gdag, b.cap, b.icap, b.dcap, w.retry,
+                        b.pstart, b.imp_x, b.imp_c, b.dag_p, b.dag_s, b.dag_a, b.gdag, b.cap, b.icap, b.dcap, w.retry,
                         w.retry_count};
 }
 
@@ -400,7 +408,8 @@ static bc_status launch(bc_ctx *ctx, const WeightedBuffers &b, const int32_t *d_
     LaunchTimer t(ctx, "weighted_sweep");
     hipLaunchKernelGGL(k_weighted_sweep, dim3(grid), dim3(PB), 0, ctx->stream, ctx->n, ctx->row_ptr, ctx->col,
                        ctx->weight, d_sources, slot_of, count, (unsigned long long *)w.next, work_of(ctx, b),
-                       ctx->bc, ctx->status, accumulate ? 1 : 0, delta_dump, dist_dump, sigma_dump);
+                       ctx->bc, ctx->status, accumulate ? 1 : 0, delta_dump, dist_dump, sigma_dump,
+                       accumulate && ctx->edges ? ctx->eb : nullptr);
     t.done();
     BC_HIP(ctx, hipGetLastError());
     return BC_OK;

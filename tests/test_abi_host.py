@@ -143,6 +143,25 @@ def test_batched_forms_refuse_weights_before_device_work():
         assert st == B.BC_ERR_UNSUPPORTED and "weighted" in msg
 
 
+def test_edges_refused_where_not_computed():
+    """Edge betweenness needs per-arc terms: the algebraic form (row sums
+    only) and many-graph contexts refuse it before any device work."""
+    lib = bcgpu.load()
+    g = gg.path(5)
+    opt = bcgpu.bc_options_init()
+    opt.form = B.BC_FORM_ALGEBRAIC
+    opt.edges = 1
+    st, msg = _create_status(g.n, g.row_ptr, g.col, None, opt)
+    assert st == B.BC_ERR_UNSUPPORTED and "edge" in msg
+    arr = (B.bc_graph * 1)()
+    gs, keep = _graph_struct(g.n, g.row_ptr, g.col)
+    arr[0] = gs
+    opt = bcgpu.bc_options_init()
+    opt.edges = 1
+    ctx = ctypes.c_void_p()
+    assert lib.bc_create_many(arr, 1, ctypes.byref(opt), ctypes.byref(ctx)) == B.BC_ERR_UNSUPPORTED
+
+
 def test_many_graphs_host_checks():
     lib = bcgpu.load()
     big = gg.path(5000)
