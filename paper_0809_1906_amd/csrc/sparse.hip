@@ -105,6 +105,30 @@ __device__ __forceinline__ void store_count(uint32_t *p, uint64_t x, bool &wide)
     *p = (uint32_t)x;
 }
 
+// Sums of eight per-lane values over the wave by reduce-scatter: lanes trade
+// halves of their values with the lanes 32, 16 and 8 apart (4 + 2 + 1
+// shuffles), then finish the one value they keep over the lanes 4, 2 and 1
+// apart.  Lane l ends with the wave sum of p[(l >> 3) & 7].
+__device__ __forceinline__ double wave_sum8(const double (&p)[8], int lane) {
+    double a[4], b[2];
+    const bool h5 = lane & 32, h4 = lane & 16, h3 = lane & 8;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const double keep = h5 ? p[i + 4] : p[i], send = h5 ? p[i] : p[i + 4];
+        a[i] = keep + __shfl_xor(send, 32, 64);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const double keep = h4 ? a[i + 2] : a[i], send = h4 ? a[i] : a[i + 2];
+        b[i] = keep + __shfl_xor(send, 16, 64);
+    }
+    double y = (h3 ? b[1] : b[0]) + __shfl_xor(h3 ? b[0] : b[1], 8, 64);
+    y += __shfl_xor(y, 4, 64);
+    y += __shfl_xor(y, 2, 64);
+    y += __shfl_xor(y, 1, 64);
+    return y;
+}
+
 // Last-arriver protocol for split rows: every segment wave of heavy row h adds
 // its partial sums into hacc with device-scope atomics, waits until they have
 // completed, then counts itself in arrive[h]; the wave that brings the count to
@@ -513,14 +537,16 @@ __global__ __launch_bounds__(SB) void k_bwd_pull_w(Topo t, const uint64_t *__res
 #pragma unroll
                 for (int u = 0; u < GDEPTH; ++u) acc[0] += (double)x[u];
                 if (eb) {
+                    static_assert(GDEPTH == 8, "wave_sum8 reduces eight arcs");
+                    double p[8];
 #pragma unroll
-                    for (int u = 0; u < GDEPTH; ++u) {
-                        if (jj[u] < 0) continue;
-                        double p = sv * (double)x[u];
+                    for (int u = 0; u < 8; ++u) p[u] = sv * (double)x[u];
+                    const double tot = wave_sum8(p, lane);
+                    int mine = -1; // the arc whose sum this lane holds
 #pragma unroll
-                        for (int off = 32; off > 0; off >>= 1) p += __shfl_xor(p, off, 64);
-                        if (lane == 0 && p != 0.0) unsafeAtomicAdd(&eb[base + jj[u]], p);
-                    }
+                    for (int u = 0; u < 8; ++u)
+                        if (((lane >> 3) & 7) == u) mine = jj[u];
+                    if ((lane & 7) == 0 && mine >= 0 && tot != 0.0) unsafeAtomicAdd(&eb[base + mine], tot);
                 }
             }
         }
