@@ -248,6 +248,25 @@ bc_status bc_reset(bc_ctx *ctx);
 bc_status bc_read_sssp(bc_ctx *ctx, const int32_t *sources, int32_t count,
                        int32_t *dist, uint64_t *sigma, double *delta);
 
+/*
+ * Betweenness over every ordered pair by Algorithm 2 (Sec. 4.2.1).  Fills the
+ * all-pairs distance matrix D and path-count matrix Lambda with the context's
+ * own forward kernels (every vertex a source), then sums on the device, for
+ * each vertex v, lambda_sv * lambda_vt / lambda_st over the ordered pairs
+ * (s, t) with s != v != t and d(s,t) = d(s,v) + d(v,t): no dependencies and no
+ * backward pass.  The result equals all-source BC (bc_run over every vertex)
+ * and serves as an independent check of it and of the forward outputs.
+ * Writes n doubles in the caller's vertex order to bc_out (host or device per
+ * mem), computed in FP64; the running BC is left untouched.  Holds 12 n^2
+ * bytes of device memory during the call (n <= BC_ALL_PAIRS_MAX_N: 12.9 GB).
+ * Synchronises.
+ * Errors: BC_ERR_UNSUPPORTED (context of many graphs, n above the limit),
+ * BC_ERR_OVERFLOW (a path count exceeded 2^64 - 1; the running BC's own
+ * overflow state is unchanged), BC_ERR_NOMEM, BC_ERR_DEVICE, BC_ERR_STATE.
+ */
+#define BC_ALL_PAIRS_MAX_N 32768
+bc_status bc_all_pairs(bc_ctx *ctx, double *bc_out, bc_mem mem);
+
 typedef struct {
     int32_t n;           /* vertices */
     int64_t m;           /* undirected edges = nnz / 2 */

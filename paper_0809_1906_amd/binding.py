@@ -39,6 +39,7 @@ BC_FORM_MANY = 5
 FORMS = {"auto": BC_FORM_AUTO, "plain": BC_FORM_PLAIN_FP64, "sparse": BC_FORM_SPARSE,
          "algebraic": BC_FORM_ALGEBRAIC, "hybrid": BC_FORM_HYBRID}
 
+BC_ALL_PAIRS_MAX_N = 32768
 BC_TUNE_DEFAULT = 0
 BC_TUNE_MEASURED = 1
 BC_TUNE_CACHED = 2
@@ -85,6 +86,7 @@ SIGNATURES = {
     "bc_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
     "bc_reset": (ctypes.c_int, [ctypes.c_void_p]),
     "bc_read_edges": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
+    "bc_all_pairs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
     "bc_read_sssp": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_void_p]),
     "bc_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(bc_info)]),
@@ -163,6 +165,10 @@ def bc_reset(ctx) -> None:
 
 def bc_read_edges(ctx, out_ptr, mem: int) -> None:
     _check(load().bc_read_edges(ctx, out_ptr, mem), ctx)
+
+
+def bc_all_pairs(ctx, out_ptr, mem: int) -> None:
+    _check(load().bc_all_pairs(ctx, out_ptr, mem), ctx)
 
 
 def bc_read_sssp(ctx, sources_ptr, count: int, dist_ptr, sigma_ptr, delta_ptr) -> None:
@@ -322,6 +328,13 @@ class BC:
         out = np.zeros(max(self.nnz, 1), dtype=np.float64)
         bc_read_edges(self._ctx, out.ctypes.data, BC_MEM_HOST)
         return out[: self.nnz]
+
+    def all_pairs(self) -> np.ndarray:
+        """BC over every ordered pair by Algorithm 2 (Sec. 4.2.1) from all-pairs
+        distances and path counts; the running BC is not touched."""
+        out = np.zeros(max(self.n, 1), dtype=np.float64)
+        bc_all_pairs(self._ctx, out.ctypes.data, BC_MEM_HOST)
+        return out[: self.n]
 
     def read_device(self):
         out = self.torch.empty(max(self.n, 1), dtype=self.torch.float64, device=f"cuda:{self.device}")

@@ -1,0 +1,234 @@
+// All-pairs betweenness by Algorithm 2 (Sec. 4.2.1, the backward pass from
+// all-pairs distances): with the distance matrix D and the path-count matrix
+// Lambda of every pair, each vertex v sums, over ordered pairs (s,t) with
+// s != v != t and d(s,t) = d(s,v) + d(v,t),
+//     BC(v) += lambda_sv * lambda_vt / lambda_st,
+// with no dependencies at all.  The context's forward kernels (those bc_run
+// uses; the batched forms run their forward only) fill D and Lambda row by
+// row, so the triple sum is an independent check of the forward outputs and of
+// the Brandes backward.
+//
+// The context's forward kernels write D (int32, -1 = unreachable) and Lambda
+// (uint64) [n][n], row = source, internal numbering.  A preparation pass turns
+// them into
+//   Dp  uint32 [n][ld], ld = n rounded up to 64: d(s,t) where 0 < d, else FAR
+//       (t = s, t unreachable, and the padding columns)
+//   R   double [n][n]: 1 / lambda_st where 0 < d(s,t), else 0
+// The graph is undirected, so every matrix is symmetric: d(v,t) is row t of Dp
+// and lambda_vt is row v of Lambda.
+//
+// The mask d(s,v) + d(v,t) = d(s,t) holds for a small share of triples (about
+// (L - 1) / n of them for mean distance L), so the sum is organised around
+// testing it cheaply.  A block takes VT vertices v and SC sources s; each
+// thread owns targets t and keeps d(v,t) for its VT vertices in registers; per
+// source the VT distances d(s,v) are uniform across the wave and come in by
+// scalar loads.  A triple costs one three-operand add, x = d(s,v) + d(v,t) -
+// d(s,t) (mod 2^32), and half a three-operand minimum; a group of 8 vertices is
+// tested once, by a ballot on its minimum.  Groups with a hit (x = 0) are
+// queued and their terms added into the block's LDS accumulators later.  FAR = 2^31 makes
+// the one compare exact: real distances are below 2^31, so a sum of two stays
+// below 2^32, FAR plus a real distance lies in (2^31, 2^32), FAR + FAR wraps to
+// 0, and no Dp entry is 0; x = 0 is the same test.  A sum of two real distances
+// equal to 2^31 could meet dst = FAR; R is 0 there, so such a term adds nothing.
+#include "bc_internal.h"
+
+namespace {
+
+constexpr int AT = 256;               // threads per block
+constexpr int VT = 64;                // vertices v per block
+constexpr int SC = 256;               // sources s per block
+constexpr uint32_t FAR = 0x80000000u; // t = s, no path, or padding
+
+__global__ __launch_bounds__(256) void k_alg2_prep(int32_t n, int32_t ld, const int32_t *__restrict__ D,
+                                                   const uint64_t *__restrict__ Lam, uint32_t *__restrict__ Dp,
+                                                   double *__restrict__ R) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (size_t)n * ld) return;
+    const int32_t s = (int32_t)(i / ld), c = (int32_t)(i % ld);
+    if (c < n) {
+        const size_t k = (size_t)s * n + c;
+        const int32_t d = D[k];
+        Dp[i] = d > 0 ? (uint32_t)d : FAR;
+        R[k] = d > 0 ? 1.0 / (double)Lam[k] : 0.0;
+    } else {
+        Dp[i] = FAR;
+    }
+}
+
+// Deferred hits: a lane whose group of 8 vertices has a hit appends the code
+// (source slot << 3 | group) to its own queue in LDS; the queue is drained
+// after the source loop, or when some lane of the wave could overflow it.  The
+// drain recomputes the 8 tests of each queued group and, for every hit, loads
+// lambda_sv, lambda_vt and 1/lambda_st; its loads are independent across lanes
+// and records, so their latency overlaps instead of stalling the test loop.
+constexpr int QK = 24; // queue entries per thread
+
+__global__ __launch_bounds__(AT) void k_alg2(int32_t n, int32_t ld, const uint32_t *__restrict__ Dp,
+                                             const double *__restrict__ R, const uint64_t *__restrict__ Lam,
+                                             double *__restrict__ bc) {
+    __shared__ double s_acc[VT];
+    __shared__ uint16_t s_q[QK][AT];
+    const int tid = threadIdx.x;
+    if (tid < VT) s_acc[tid] = 0.0;
+    __syncthreads();
+    const int32_t v0 = blockIdx.x * VT, sa = blockIdx.y * SC;
+    const int32_t ns = min(SC, n - sa);
+    // the queued groups of target t: recompute their 8 tests, add the hits
+    auto drain = [&](int32_t t, int32_t cnt) {
+        const uint32_t *trow = Dp + (size_t)t * ld + v0;
+        for (int32_t i = 0; i < cnt; ++i) {
+            const uint32_t code = s_q[i][tid];
+            const int32_t s = sa + (int32_t)(code >> 3), g = (int32_t)(code & 7);
+            const uint32_t *srow = Dp + (size_t)s * ld;
+            const uint32_t ndst = 0u - srow[t];
+            const uint4 p0 = *reinterpret_cast<const uint4 *>(srow + v0 + 8 * g);
+            const uint4 p1 = *reinterpret_cast<const uint4 *>(srow + v0 + 8 * g + 4);
+            const uint4 q0 = *reinterpret_cast<const uint4 *>(trow + 8 * g);
+            const uint4 q1 = *reinterpret_cast<const uint4 *>(trow + 8 * g + 4);
+            const uint32_t x[8] = {p0.x + q0.x + ndst, p0.y + q0.y + ndst, p0.z + q0.z + ndst, p0.w + q0.w + ndst,
+                                   p1.x + q1.x + ndst, p1.y + q1.y + ndst, p1.z + q1.z + ndst, p1.w + q1.w + ndst};
+            const double r = R[(size_t)s * n + t];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                if (x[k] == 0) {
+                    // a hit has d(s,v) < FAR, so v < n
+                    const int32_t v = v0 + 8 * g + k;
+                    const double term = (double)Lam[(size_t)s * n + v] * (double)Lam[(size_t)t * n + v] * r;
+                    unsafeAtomicAdd(&s_acc[8 * g + k], term);
+                }
+            }
+        }
+    };
+    for (int32_t t = tid; t < n; t += AT) {
+        uint32_t dvt[VT];
+        const uint4 *row = reinterpret_cast<const uint4 *>(Dp + (size_t)t * ld + v0);
+#pragma unroll
+        for (int q = 0; q < VT / 4; ++q) {
+            const uint4 x = row[q];
+            dvt[4 * q] = x.x;
+            dvt[4 * q + 1] = x.y;
+            dvt[4 * q + 2] = x.z;
+            dvt[4 * q + 3] = x.w;
+        }
+        int32_t cnt = 0;
+        uint32_t dnext = Dp[(size_t)sa * ld + t];
+        for (int32_t sl = 0; sl < ns; ++sl) {
+            const int32_t s = sa + sl;
+            const uint32_t *srow = Dp + (size_t)s * ld; // uniform
+            // -d(s,t), opaque so that x below stays one three-operand add
+            uint32_t ndst = 0u - dnext;
+            __asm__ volatile("" : "+v"(ndst));
+            if (sl + 1 < ns) dnext = srow[(size_t)ld + t];
+#pragma unroll
+            for (int h = 0; h < VT / 32; ++h) {
+                // d(s,v) for 32 vertices: uniform, loaded before any test
+                const uint4 *sq = reinterpret_cast<const uint4 *>(srow + v0 + 32 * h);
+                uint32_t dsv[32];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const uint4 x = sq[q];
+                    dsv[4 * q] = x.x;
+                    dsv[4 * q + 1] = x.y;
+                    dsv[4 * q + 2] = x.z;
+                    dsv[4 * q + 3] = x.w;
+                }
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    // x = d(s,v) + d(v,t) - d(s,t) (mod 2^32) for 8 vertices;
+                    // the group is tested once, by the minimum
+                    uint32_t mn = 0xffffffffu;
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) mn = min(mn, dsv[8 * g + k] + dvt[32 * h + 8 * g + k] + ndst);
+                    // hits are rare: keep the no-hit path a fall-through
+                    if (__builtin_expect(__builtin_amdgcn_ballot_w64(mn == 0) != 0, 0)) {
+                        if (__builtin_expect(__builtin_amdgcn_ballot_w64(cnt == QK) != 0, 0)) {
+                            drain(t, cnt);
+                            cnt = 0;
+                        }
+                        if (mn == 0) s_q[cnt++][tid] = (uint16_t)((sl << 3) | (4 * h + g));
+                    }
+                }
+            }
+        }
+        drain(t, cnt);
+    }
+    __syncthreads();
+    if (tid < VT && v0 + tid < n && s_acc[tid] != 0.0) unsafeAtomicAdd(&bc[v0 + tid], s_acc[tid]);
+}
+
+__global__ __launch_bounds__(256) void k_iota_from(int32_t *__restrict__ ids, int32_t first, int32_t count) {
+    const int32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i < count) ids[i] = first + i;
+}
+
+__global__ __launch_bounds__(256) void k_zero_f64(double *__restrict__ x, int32_t count) {
+    const int32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i < count) x[i] = 0.0;
+}
+
+} // namespace
+
+bc_status allpairs_bc(bc_ctx *ctx, double *bc_internal) {
+    const int32_t n = ctx->n;
+    if (n == 0) return BC_OK;
+    const int32_t ld = (n + VT - 1) / VT * VT;
+    const size_t nn = (size_t)n * n;
+    const bool plain = ctx->form == BC_FORM_PLAIN_FP64;
+    const int32_t chunk = plain ? std::min(n, 4096) : std::min(n, ctx->sp.batch);
+    int32_t *D = (int32_t *)bc_dalloc(ctx, nn * sizeof(int32_t));
+    uint64_t *Lam = (uint64_t *)bc_dalloc(ctx, nn * sizeof(uint64_t));
+    // the plain sweep dumps dependencies too; the batched forms run the
+    // forward only
+    double *dtmp = plain ? (double *)bc_dalloc(ctx, (size_t)chunk * n * sizeof(double)) : nullptr;
+    int32_t *src = (int32_t *)bc_dalloc(ctx, (size_t)chunk * sizeof(int32_t));
+    uint32_t *Dp = nullptr;
+    double *R = nullptr;
+    auto cleanup = [&]() {
+        bc_dfree(ctx, D);
+        bc_dfree(ctx, Lam);
+        bc_dfree(ctx, dtmp);
+        bc_dfree(ctx, src);
+        bc_dfree(ctx, Dp);
+        bc_dfree(ctx, R);
+    };
+    if (!D || !Lam || (plain && !dtmp) || !src) {
+        cleanup();
+        return bc_fail(ctx, BC_ERR_NOMEM, "all pairs: allocation of D and Lambda failed");
+    }
+    // rows of D and Lambda: every source in internal order, one batch at a time
+    for (int32_t s0 = 0; s0 < n; s0 += chunk) {
+        const int32_t cnt = std::min(chunk, n - s0);
+        hipLaunchKernelGGL(k_iota_from, dim3((cnt + 255) / 256), dim3(256), 0, ctx->stream, src, s0, cnt);
+        const size_t row = (size_t)s0 * n;
+        bc_status st = plain ? plain_run(ctx, src, cnt, false, dtmp, D + row, Lam + row)
+                             : sparse_dump(ctx, src, cnt, D + row, Lam + row, nullptr);
+        if (st != BC_OK) {
+            cleanup();
+            return st;
+        }
+    }
+    bc_dfree(ctx, dtmp);
+    dtmp = nullptr;
+    Dp = (uint32_t *)bc_dalloc(ctx, (size_t)n * ld * sizeof(uint32_t));
+    R = (double *)bc_dalloc(ctx, nn * sizeof(double));
+    if (!Dp || !R) {
+        cleanup();
+        return bc_fail(ctx, BC_ERR_NOMEM, "all pairs: allocation of the prepared matrices failed");
+    }
+    const size_t cells = (size_t)n * ld;
+    hipLaunchKernelGGL(k_alg2_prep, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, ctx->stream, n, ld, D, Lam,
+                       Dp, R);
+    hipLaunchKernelGGL(k_zero_f64, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, bc_internal, n);
+    const dim3 grid(ld / VT, (n + SC - 1) / SC);
+    {
+        LaunchTimer tm(ctx, "all_pairs");
+        hipLaunchKernelGGL(k_alg2, grid, dim3(AT), 0, ctx->stream, n, ld, Dp, R, Lam, bc_internal);
+        tm.done();
+    }
+    const hipError_t e = hipGetLastError();
+    const hipError_t sy = hipStreamSynchronize(ctx->stream);
+    cleanup();
+    if (e != hipSuccess) return bc_hip(ctx, e, "k_alg2");
+    if (sy != hipSuccess) return bc_hip(ctx, sy, "all pairs");
+    return BC_OK;
+}

@@ -674,6 +674,27 @@ bc_status bc_reset(bc_ctx *ctx) {
     return BC_OK;
 }
 
+// Calls that run sources without adding to BC (per-source dumps, all pairs)
+// share the device overflow flag with bc_run: they save it and clear it first,
+// then read what they raised and put the saved value back.
+static bc_status status_save(bc_ctx *ctx, uint32_t *before) {
+    BC_HIP(ctx, hipMemcpyAsync(ctx->status_host, ctx->status, sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->stream));
+    BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    *before = *ctx->status_host;
+    BC_HIP(ctx, hipMemsetAsync(ctx->status, 0, sizeof(uint32_t), ctx->stream));
+    return BC_OK;
+}
+
+static bc_status status_restore(bc_ctx *ctx, uint32_t before, uint32_t *now) {
+    BC_HIP(ctx, hipMemcpyAsync(ctx->status_host, ctx->status, sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->stream));
+    BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    *now = *ctx->status_host;
+    *ctx->status_host = before;
+    BC_HIP(ctx, hipMemcpyAsync(ctx->status, ctx->status_host, sizeof(uint32_t), hipMemcpyHostToDevice, ctx->stream));
+    BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return BC_OK;
+}
+
 bc_status bc_read_sssp(bc_ctx *ctx, const int32_t *sources, int32_t count,
                        int32_t *dist, uint64_t *sigma, double *delta) {
     if (!ctx) return BC_ERR_INVALID_ARG;
@@ -697,21 +718,14 @@ bc_status bc_read_sssp(bc_ctx *ctx, const int32_t *sources, int32_t count,
         bc_dfree(ctx, od); bc_dfree(ctx, os); bc_dfree(ctx, ol);
     };
     if (!dd || !ds || !dl || !od || !os || !ol) { cleanup(); return bc_fail(ctx, BC_ERR_NOMEM, "dump allocation failed"); }
-    // The overflow flag is shared with bc_run: remember and restore it.
-    BC_HIP(ctx, hipMemcpyAsync(ctx->status_host, ctx->status, sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->stream));
-    BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    uint32_t before = *ctx->status_host;
-    BC_HIP(ctx, hipMemsetAsync(ctx->status, 0, sizeof(uint32_t), ctx->stream));
-    if (ctx->many) s = multigraph_dump(ctx, sources, count, dd, ds, dl);
-    else if (ctx->form == BC_FORM_PLAIN_FP64) s = plain_run(ctx, d_src, count, false, dl, dd, ds);
-    else s = sparse_dump(ctx, d_src, count, dd, ds, dl);
-    if (s != BC_OK) { cleanup(); return s; }
-    BC_HIP(ctx, hipMemcpyAsync(ctx->status_host, ctx->status, sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->stream));
-    BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    uint32_t now = *ctx->status_host;
-    *ctx->status_host = before;
-    BC_HIP(ctx, hipMemcpyAsync(ctx->status, ctx->status_host, sizeof(uint32_t), hipMemcpyHostToDevice, ctx->stream));
-    BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    uint32_t before = 0, now = 0;
+    if ((s = status_save(ctx, &before)) != BC_OK) { cleanup(); return s; }
+    bc_status run;
+    if (ctx->many) run = multigraph_dump(ctx, sources, count, dd, ds, dl);
+    else if (ctx->form == BC_FORM_PLAIN_FP64) run = plain_run(ctx, d_src, count, false, dl, dd, ds);
+    else run = sparse_dump(ctx, d_src, count, dd, ds, dl);
+    if (run != BC_ERR_DEVICE) s = status_restore(ctx, before, &now);
+    if (run != BC_OK || s != BC_OK) { cleanup(); return run != BC_OK ? run : s; }
     if (now & BC_DEV_SIGMA_OVERFLOW) { cleanup(); return bc_fail(ctx, BC_ERR_OVERFLOW, "a shortest-path count exceeded 2^64 - 1"); }
     if (ctx->n > 0) {
         if ((s = rows_to_caller_order_i32(ctx, od, dd, count)) != BC_OK ||
@@ -724,6 +738,44 @@ bc_status bc_read_sssp(bc_ctx *ctx, const int32_t *sources, int32_t count,
     }
     cleanup();
     return BC_OK;
+}
+
+bc_status bc_all_pairs(bc_ctx *ctx, double *bc_out, bc_mem mem) {
+    if (!ctx) return BC_ERR_INVALID_ARG;
+    if (!bc_out && ctx->n > 0) return bc_fail(ctx, BC_ERR_INVALID_ARG, "bc_out is NULL");
+    bc_status s = check_usable(ctx);
+    if (s != BC_OK) return s;
+    if (ctx->many) return bc_fail(ctx, BC_ERR_UNSUPPORTED, "all pairs: not for a context of many graphs");
+    if (ctx->n > BC_ALL_PAIRS_MAX_N)
+        return bc_fail(ctx, BC_ERR_UNSUPPORTED, "all pairs: n above BC_ALL_PAIRS_MAX_N");
+    if (ctx->n == 0) return BC_OK;
+    double *res = (double *)bc_dalloc(ctx, sizeof(double) * (size_t)ctx->n);
+    if (!res) return bc_fail(ctx, BC_ERR_NOMEM, "all pairs: result allocation failed");
+    uint32_t before = 0, now = 0;
+    if ((s = status_save(ctx, &before)) != BC_OK) {
+        bc_dfree(ctx, res);
+        return s;
+    }
+    const bc_status run = allpairs_bc(ctx, res);
+    if (run != BC_ERR_DEVICE) s = status_restore(ctx, before, &now);
+    if (run != BC_OK || s != BC_OK) {
+        bc_dfree(ctx, res);
+        return run != BC_OK ? run : s;
+    }
+    if (now & BC_DEV_SIGMA_OVERFLOW) {
+        bc_dfree(ctx, res);
+        return bc_fail(ctx, BC_ERR_OVERFLOW, "a shortest-path count exceeded 2^64 - 1");
+    }
+    s = rows_to_caller_order_f64(ctx, ctx->bc_scratch, res, 1);
+    if (s == BC_OK) {
+        hipError_t e = hipMemcpyAsync(bc_out, ctx->bc_scratch, sizeof(double) * (size_t)ctx->n,
+                                      mem == BC_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                                      ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) s = bc_hip(ctx, e, "all pairs: copy out");
+    }
+    bc_dfree(ctx, res);
+    return s;
 }
 
 bc_status bc_get_info(const bc_ctx *ctx, bc_info *out) {

@@ -259,8 +259,14 @@ bc_status algebraic_release(bc_ctx *ctx);
 // the batched forms; accumulate = false leaves BC untouched.
 bc_status sparse_batch(bc_ctx *ctx, const int32_t *d_sources, int32_t count, bool accumulate);
 bc_status sparse_run(bc_ctx *ctx, const int32_t *d_sources, int64_t count);
+// delta_dump = nullptr runs the forward only (distances and counts).
 bc_status sparse_dump(bc_ctx *ctx, const int32_t *d_sources, int32_t count,
                       int32_t *dist_dump, uint64_t *sigma_dump, double *delta_dump);
+
+// ---- all pairs (allpairs.hip) ---------------------------------------------------
+// BC of every vertex (internal order) by Algorithm 2 from all-pairs D and
+// Lambda, which the form's own forward kernels fill; bc_internal: n doubles.
+bc_status allpairs_bc(bc_ctx *ctx, double *bc_internal);
 
 // ---- tuning (tune.cpp) ----------------------------------------------------------
 // Prepares the sparse or hybrid form: batch width and hybrid thresholds come

@@ -588,7 +588,7 @@ __global__ __launch_bounds__(SB) void k_sp_dump(int32_t n, int32_t NW, int32_t B
     const size_t idx = (size_t)v * B + b;
     dist_out[i] = d;
     sigma_out[i] = d >= 0 ? (uint64_t)sigma[idx] : 0;
-    delta_out[i] = d >= 0 ? dstate[idx] : 0.0;
+    if (delta_out) delta_out[i] = d >= 0 ? dstate[idx] : 0.0;
 }
 
 Topo topo(bc_ctx *ctx) {
@@ -716,7 +716,7 @@ bc_status ensure_levels(bc_ctx *ctx, int32_t need) {
 // *need_wide reports a count of 2^32 or more, before anything was added to BC.
 template <int NW, typename S>
 bc_status run_batch_t(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool accumulate, int32_t *nlev_out,
-                      bool *need_wide) {
+                      bool *need_wide, bool backward) {
     SparseState &s = ctx->sp;
     const int32_t n = ctx->n, B = s.batch;
     const size_t words = (size_t)n * NW;
@@ -794,7 +794,8 @@ bc_status run_batch_t(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool acc
     s.depth_guess = nlev;
     // Level 0 adds nothing to BC (v is the source), but with edges on its
     // arcs out of the source carry edge terms.
-    const int32_t lowest = accumulate && !ctx->edges ? 1 : 0;
+    // A forward-only batch (all-pairs distances and counts) runs no level.
+    const int32_t lowest = !backward ? nlev : accumulate && !ctx->edges ? 1 : 0;
     double *ddump = accumulate ? nullptr : s.delta_dump;
     for (int32_t lv = nlev - 1; lv >= lowest; --lv) {
         const uint64_t *fcur = s.front + (size_t)lv * words;
@@ -847,26 +848,28 @@ bc_status run_batch_t(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool acc
 }
 
 template <int NW>
-bc_status run_batch_nw(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool accumulate, int32_t *nlev_out) {
+bc_status run_batch_nw(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool accumulate, int32_t *nlev_out,
+                       bool backward) {
     SparseState &s = ctx->sp;
     if (!s.wide) {
         bool need_wide = false;
-        bc_status st = run_batch_t<NW, uint32_t>(ctx, d_src, count, accumulate, nlev_out, &need_wide);
+        bc_status st = run_batch_t<NW, uint32_t>(ctx, d_src, count, accumulate, nlev_out, &need_wide, backward);
         if (st != BC_OK || !need_wide) return st;
         s.wide = true;
     }
     bool unused = false;
-    return run_batch_t<NW, uint64_t>(ctx, d_src, count, accumulate, nlev_out, &unused);
+    return run_batch_t<NW, uint64_t>(ctx, d_src, count, accumulate, nlev_out, &unused, backward);
 }
 
 // Counts start as uint32; the first batch that needs more switches the context
 // to uint64 storage for good and is re-run.
-bc_status run_batch(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool accumulate, int32_t *nlev_out) {
+bc_status run_batch(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool accumulate, int32_t *nlev_out,
+                    bool backward = true) {
     switch (ctx->sp.words) {
-    case 1: return run_batch_nw<1>(ctx, d_src, count, accumulate, nlev_out);
-    case 2: return run_batch_nw<2>(ctx, d_src, count, accumulate, nlev_out);
-    case 4: return run_batch_nw<4>(ctx, d_src, count, accumulate, nlev_out);
-    case 8: return run_batch_nw<8>(ctx, d_src, count, accumulate, nlev_out);
+    case 1: return run_batch_nw<1>(ctx, d_src, count, accumulate, nlev_out, backward);
+    case 2: return run_batch_nw<2>(ctx, d_src, count, accumulate, nlev_out, backward);
+    case 4: return run_batch_nw<4>(ctx, d_src, count, accumulate, nlev_out, backward);
+    case 8: return run_batch_nw<8>(ctx, d_src, count, accumulate, nlev_out, backward);
     }
     return bc_fail(ctx, BC_ERR_INVALID_ARG, "sparse form: batch must be 64, 128, 256 or 512");
 }
@@ -961,12 +964,12 @@ bc_status sparse_run(bc_ctx *ctx, const int32_t *d_src, int64_t count) {
 bc_status sparse_dump(bc_ctx *ctx, const int32_t *d_src, int32_t count,
                       int32_t *dist_dump, uint64_t *sigma_dump, double *delta_dump) {
     SparseState &s = ctx->sp;
-    if (!s.delta_dump) {
+    if (delta_dump && !s.delta_dump) {
         s.delta_dump = (double *)bc_dalloc(ctx, (size_t)std::max(ctx->n, 1) * s.batch * sizeof(double));
         if (!s.delta_dump) return bc_fail(ctx, BC_ERR_NOMEM, "sparse form: dump allocation failed");
     }
     int32_t nlev = 0;
-    bc_status st = run_batch(ctx, d_src, count, false, &nlev);
+    bc_status st = run_batch(ctx, d_src, count, false, &nlev, delta_dump != nullptr);
     if (st != BC_OK) return st;
     const int64_t cells = (int64_t)ctx->n * count;
     const unsigned blocks = (unsigned)((cells + SB - 1) / SB);
