@@ -32,6 +32,8 @@
 // equal to 2^31 could meet dst = FAR; R is 0 there, so such a term adds nothing.
 #include "bc_internal.h"
 
+#include <type_traits>
+
 namespace {
 
 constexpr int AT = 256;               // threads per block
@@ -56,45 +58,70 @@ __global__ __launch_bounds__(256) void k_alg2_prep(int32_t n, int32_t ld, const 
 }
 
 // Deferred hits: a lane whose group of 8 vertices has a hit appends the code
-// (source slot << 3 | group) to its own queue in LDS; the queue is drained
-// after the source loop, or when some lane of the wave could overflow it.  The
-// drain recomputes the 8 tests of each queued group and, for every hit, loads
-// lambda_sv, lambda_vt and 1/lambda_st; its loads are independent across lanes
-// and records, so their latency overlaps instead of stalling the test loop.
+// (source slot << 3 | group) and -d(s,t) to its own queue in LDS; the queue is
+// drained after the source loop, or when some lane of the wave could overflow
+// it.  The drain recomputes the 8 tests of each queued group from rows s and t
+// (cached) and, for every hit, loads 1/lambda_st, lambda_sv and lambda_vt (a
+// count at distance 1 is 1 and is not loaded); its loads are independent
+// across lanes and records, so their latency overlaps instead of stalling the
+// test loop.
 constexpr int QK = 24; // queue entries per thread
 
 __global__ __launch_bounds__(AT) void k_alg2(int32_t n, int32_t ld, const uint32_t *__restrict__ Dp,
                                              const double *__restrict__ R, const uint64_t *__restrict__ Lam,
                                              double *__restrict__ bc) {
     __shared__ double s_acc[VT];
-    __shared__ uint16_t s_q[QK][AT];
+    __shared__ uint16_t s_q[QK][AT];  // source slot << 3 | group
+    __shared__ uint32_t s_nd[QK][AT]; // -d(s,t)
     const int tid = threadIdx.x;
     if (tid < VT) s_acc[tid] = 0.0;
     __syncthreads();
     const int32_t v0 = blockIdx.x * VT, sa = blockIdx.y * SC;
     const int32_t ns = min(SC, n - sa);
-    // the queued groups of target t: recompute their 8 tests, add the hits
-    auto drain = [&](int32_t t, int32_t cnt) {
+    // the queued groups of target t: recompute their 8 tests from the record's
+    // -d(s,t) and the cached rows s and t, then add the hits.  After the source
+    // loop, where d(v,t) no longer occupies registers, several records go per
+    // step, so that their loads are in flight together; inside it, one.
+    auto drain = [&](int32_t t, int32_t cnt, auto unroll) {
+        constexpr int U = decltype(unroll)::value;
         const uint32_t *trow = Dp + (size_t)t * ld + v0;
-        for (int32_t i = 0; i < cnt; ++i) {
-            const uint32_t code = s_q[i][tid];
-            const int32_t s = sa + (int32_t)(code >> 3), g = (int32_t)(code & 7);
-            const uint32_t *srow = Dp + (size_t)s * ld;
-            const uint32_t ndst = 0u - srow[t];
-            const uint4 p0 = *reinterpret_cast<const uint4 *>(srow + v0 + 8 * g);
-            const uint4 p1 = *reinterpret_cast<const uint4 *>(srow + v0 + 8 * g + 4);
-            const uint4 q0 = *reinterpret_cast<const uint4 *>(trow + 8 * g);
-            const uint4 q1 = *reinterpret_cast<const uint4 *>(trow + 8 * g + 4);
-            const uint32_t x[8] = {p0.x + q0.x + ndst, p0.y + q0.y + ndst, p0.z + q0.z + ndst, p0.w + q0.w + ndst,
-                                   p1.x + q1.x + ndst, p1.y + q1.y + ndst, p1.z + q1.z + ndst, p1.w + q1.w + ndst};
-            const double r = R[(size_t)s * n + t];
+        const uint64_t *ltrow = Lam + (size_t)t * n + v0;
+        for (int32_t i = 0; i < cnt; i += U) {
+            int32_t sv[U], gv[U];
+            uint32_t ndv[U];
+            uint4 p0[U], p1[U], q0[U], q1[U];
+            double rv[U];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                if (x[k] == 0) {
-                    // a hit has d(s,v) < FAR, so v < n
-                    const int32_t v = v0 + 8 * g + k;
-                    const double term = (double)Lam[(size_t)s * n + v] * (double)Lam[(size_t)t * n + v] * r;
-                    unsafeAtomicAdd(&s_acc[8 * g + k], term);
+            for (int u = 0; u < U; ++u) {
+                const int32_t e = i + u < cnt ? i + u : i; // a repeat is loaded, not added
+                const uint32_t code = s_q[e][tid];
+                sv[u] = sa + (int32_t)(code >> 3);
+                gv[u] = (int32_t)(code & 7);
+                ndv[u] = s_nd[e][tid];
+                const uint4 *sp = reinterpret_cast<const uint4 *>(Dp + (size_t)sv[u] * ld + v0 + 8 * gv[u]);
+                const uint4 *tp = reinterpret_cast<const uint4 *>(trow + 8 * gv[u]);
+                p0[u] = sp[0];
+                p1[u] = sp[1];
+                q0[u] = tp[0];
+                q1[u] = tp[1];
+                rv[u] = R[(size_t)sv[u] * n + t];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (i + u >= cnt) break;
+                const uint32_t ds[8] = {p0[u].x, p0[u].y, p0[u].z, p0[u].w, p1[u].x, p1[u].y, p1[u].z, p1[u].w};
+                const uint32_t dt[8] = {q0[u].x, q0[u].y, q0[u].z, q0[u].w, q1[u].x, q1[u].y, q1[u].z, q1[u].w};
+                const uint64_t *lsrow = Lam + (size_t)sv[u] * n + v0;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    if (ds[k] + dt[k] + ndv[u] == 0) {
+                        // a hit has d(s,v) < FAR, so v < n; a count at
+                        // distance 1 is 1 and is not loaded
+                        const int32_t j = 8 * gv[u] + k;
+                        const double ls = ds[k] == 1 ? 1.0 : (double)lsrow[j];
+                        const double lt = dt[k] == 1 ? 1.0 : (double)ltrow[j];
+                        unsafeAtomicAdd(&s_acc[j], ls * lt * rv[u]);
+                    }
                 }
             }
         }
@@ -111,7 +138,7 @@ __global__ __launch_bounds__(AT) void k_alg2(int32_t n, int32_t ld, const uint32
             dvt[4 * q + 3] = x.w;
         }
         int32_t cnt = 0;
-        uint32_t dnext = Dp[(size_t)sa * ld + t];
+        uint32_t dnext = Dp[(size_t)sa * ld + t]; // d(s,t), one source ahead
         for (int32_t sl = 0; sl < ns; ++sl) {
             const int32_t s = sa + sl;
             const uint32_t *srow = Dp + (size_t)s * ld; // uniform
@@ -142,15 +169,19 @@ __global__ __launch_bounds__(AT) void k_alg2(int32_t n, int32_t ld, const uint32
                     // hits are rare: keep the no-hit path a fall-through
                     if (__builtin_expect(__builtin_amdgcn_ballot_w64(mn == 0) != 0, 0)) {
                         if (__builtin_expect(__builtin_amdgcn_ballot_w64(cnt == QK) != 0, 0)) {
-                            drain(t, cnt);
+                            drain(t, cnt, std::integral_constant<int, 1>());
                             cnt = 0;
                         }
-                        if (mn == 0) s_q[cnt++][tid] = (uint16_t)((sl << 3) | (4 * h + g));
+                        if (mn == 0) {
+                            s_q[cnt][tid] = (uint16_t)((sl << 3) | (4 * h + g));
+                            s_nd[cnt][tid] = ndst;
+                            ++cnt;
+                        }
                     }
                 }
             }
         }
-        drain(t, cnt);
+        drain(t, cnt, std::integral_constant<int, 4>());
     }
     __syncthreads();
     if (tid < VT && v0 + tid < n && s_acc[tid] != 0.0) unsafeAtomicAdd(&bc[v0 + tid], s_acc[tid]);
