@@ -19,6 +19,11 @@ Other workloads (same JSON schema; used for profiles and design figures):
   ws4096   4096 Watts-Strogatz graphs, all sources: one persistent launch
   rmat20w  RMAT-20 with weights U{1..255}, 4096 sampled sources: bucketed
            shortest paths per source
+  allpairs16384
+           ER n=16384, degree 256: BC over every pair by Algorithm 2 (the
+           algebraic form's forward fills all-pairs distances and counts, one
+           kernel sums the masked triple terms), against Brandes in the same
+           context
 
 Prints one JSON line.  Profiling runs use --sources N (a bounded prefix of the
 sources) and --calibrate-copy (a 1 GiB device-to-device copy at the end, the
@@ -42,6 +47,8 @@ import numpy as np  # noqa: E402
 METRIC = "BC TEPS (sources·m/s) on RMAT-16; batched-MFMA vs plain BFS form, same GPU"
 HBM_PEAK_GBS = 8000.0
 MFMA_BF16_PEAK_TFS = 2500.0
+# 32-bit integer vector operations: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz
+VALU_INT32_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sparse_rmat16_traffic.txt")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_0809_1906_amd", "csrc", "sparse.hip")
@@ -59,6 +66,9 @@ WORKLOADS = {
     "rmat20w": {"form": "plain", "batch": 0, "compare": [],
                 "desc": "rmat20w: RMAT scale 20, edgefactor 16, largest component, weights U{1..255}; BC "
                         "over 4096 sources sampled without replacement"},
+    "allpairs16384": {"form": "algebraic", "batch": 512, "compare": [],
+                      "desc": "allpairs16384: Erdos-Renyi n=16384, average degree 256, largest component; BC "
+                              "over every ordered pair by Algorithm 2 from all-pairs distances and counts"},
 }
 
 DTYPES = {
@@ -68,6 +78,8 @@ DTYPES = {
     "algebraic": "bf16 MFMA products of 8-bit count limbs with f32 accumulate, u64 counts, f32 dependency "
                  "state, f64 sums",
     "many": "u64 counts, f32 dependency state, f64 sums",
+    "allpairs": "u64 counts and int32 distances (forward by bf16 MFMA products of 8-bit limbs), u32 mask "
+                "arithmetic, f64 terms and sums",
 }
 
 
@@ -126,6 +138,8 @@ def load_workload(name, sources):
                 "work": float(sum(g.n * g.m for g in gs))}
     if name == "rmat20w":
         g, src = gg.rmat20w()
+    elif name == "allpairs16384":
+        g, src = gg.er16384(), None
     else:
         g = getattr(gg, name)()
         src = None
@@ -209,6 +223,70 @@ def roofline(name, wl, kern, info, steps):
                 traffic=measured_traffic(dom, name), alg_bytes_per_launch=total / max(launches, 1))
 
 
+def run_allpairs(args, spec, wl, bcgpu, torch):
+    """One step = one bc_all_pairs call: the forward fills all-pairs D and
+    Lambda, then one kernel sums lambda_sv * lambda_vt / lambda_st over the
+    triples with d(s,t) = d(s,v) + d(v,t) (Algorithm 2, Sec. 4.2.1)."""
+    g, n, m = wl["graph"], wl["n"], wl["m"]
+    form = args.form or spec["form"]
+    batch = spec["batch"] if args.batch is None else args.batch
+    ctx = bcgpu.BC(g, form=form, batch=batch, timing=True)
+    info = ctx.info()
+    for i in range(args.warmup):
+        ctx.all_pairs()
+        log(f"all pairs warmup {i} done")
+    ctx.reset()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for i in range(args.steps):
+        got = ctx.all_pairs()
+        log(f"all pairs step {i} done")
+    dt = (time.perf_counter() - t) / args.steps
+    kern = {k: ctx.timing(k) for k in KERNELS + ("all_pairs",) if ctx.timing(k)[1]}
+    log("kernel times (ms, launches):", kern)
+    ms, launches = kern["all_pairs"]
+    avg = ms / launches
+    ops = 2.0 * float(n) ** 3  # one add and one compare per tested triple
+    ach = ops / (avg * 1e-3) / 1e12
+    roof = {"kernel": "all_pairs", "avg_launch_ms": avg, "launches": launches, "bound": "alu", "achieved": ach,
+            "peak": VALU_INT32_PEAK_TOPS, "unit": "Top/s", "frac": ach / VALU_INT32_PEAK_TOPS, "traffic": None,
+            "alg_ops_per_launch": ops,
+            "note": "n^3 tested triples x 2 int32 ops (add, compare) per launch; peak = 256 CUs x 64 lanes x 2.4 GHz"}
+    compare = {}
+    if not args.no_compare:
+        ctx.reset()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        ctx.run()
+        brandes = ctx.read()
+        bdt = time.perf_counter() - t
+        err = float(np.max(np.abs(got - brandes) / np.maximum(np.abs(brandes), 1.0)))
+        compare["brandes_same_context"] = {"value": n * m / bdt, "ms_per_step": bdt * 1e3,
+                                           "max_rel_diff_vs_all_pairs": err}
+        log(f"brandes {bdt * 1e3:.1f} ms, max rel diff {err:.2e}")
+    ctx.close()
+    cpu = None if args.no_cpu_baseline else cpu_baseline("er16384", wl)
+    return {
+        "metric": "all-pairs BC by Algorithm 2 on ER-16384, TEPS (n·m/s)",
+        "value": n * m / dt,
+        "unit": "TEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPES["allpairs"],
+        "data": "synthetic",
+        "config": {"workload": spec["desc"], "n": n, "m": m, "form_filling_D_Lambda": form, "batch": info.batch},
+        "compare": compare,
+        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kern.items()},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -244,6 +322,9 @@ def main():
     form = args.form or spec["form"]
     batch = spec["batch"] if args.batch is None else args.batch
     wl = load_workload(args.workload, args.sources)
+    if args.workload == "allpairs16384":
+        print(json.dumps(run_allpairs(args, spec, wl, bcgpu, torch)), flush=True)
+        return
     src, work = wl["src"], wl["work"]
 
     def timed_runs(form, steps, warmup, batch=0, timing=True, edges=False):
