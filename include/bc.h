@@ -62,7 +62,11 @@ typedef enum { BC_MEM_HOST = 0, BC_MEM_DEVICE = 1 } bc_mem;
  *                      Unit weights.
  *  BC_FORM_ALGEBRAIC   the algebraic method of Sec. 3.1 on a batch of sources:
  *                      frontier-matrix x adjacency products on BF16 MFMA with
- *                      path counts carried exactly in 8-bit limbs.  Unit weights.
+ *                      path counts carried exactly in 8-bit limbs.  Unit
+ *                      weights, or integer weights up to
+ *                      BC_ALGEBRAIC_MAX_WEIGHT (Sec. 3.2): one 0/1 matrix per
+ *                      weight c, levels are distances, and level L is the
+ *                      sum over c of the class-c matrix times level L - c.
  *  BC_FORM_HYBRID      the sparse form's batches, where each level l >= 1 goes
  *                      either by CSR pulls or by the algebraic form's products,
  *                      chosen per batch from the level's union-frontier density
@@ -74,6 +78,9 @@ typedef enum { BC_MEM_HOST = 0, BC_MEM_DEVICE = 1 } bc_mem;
  *                      above 65792, run every level by pulls.
  *  BC_FORM_AUTO        chosen by the library from the graph's shape.
  */
+/* Largest integer weight the algebraic form takes (one product class each). */
+#define BC_ALGEBRAIC_MAX_WEIGHT 8
+
 typedef enum {
     BC_FORM_AUTO = 0,
     BC_FORM_PLAIN_FP64 = 1,

@@ -23,6 +23,16 @@ reaches BC by a route that shares nothing with brandes.c:
                     Delta_{l-1} = Mask(((D_l + Delta_l) div Lambda) . A, l-1)
                     mult Lambda, and BC as column sums of Delta without the
                     diagonal.  Unit weights only.
+  algebraic_weighted
+                    the algebraic method for integer weights 1..M (Sec. 3.2),
+                    read as per-weight-class products: with A_c the 0/1 matrix
+                    of the edges of weight c and levels taken as distances,
+                    F_L = Mask_unreached(sum_c F_{L-c} . A_c) gives d and
+                    lambda; the backward takes, for j at distance L from i,
+                    Delta[i][j] = Lambda[i][j] * sum_c (X_{L+c} . A_c)[i][j]
+                    with X_L = (1 + Delta) div Lambda on level L: a weighted
+                    edge (j, k) of weight c leads to a successor exactly when
+                    d(i,k) = d(i,j) + c.  Exact integers and rationals.
 """
 from __future__ import annotations
 
@@ -221,5 +231,66 @@ def algebraic(g):
             nxt[i, j] = Y[i, j] * int(Lam[i, j])
         Delta = Delta + nxt
         Delta_l = nxt
+    bc = [sum((Delta[i, j] for i in range(n) if i != j), Fraction(0)) for j in range(n)]
+    return D, Lam, Delta, bc
+
+
+def algebraic_weighted(g):
+    """(D, Lambda, Delta, bc) by per-weight-class products (Sec. 3.2, as read
+    in the module docstring), in exact arithmetic.  Integer weights >= 1;
+    unit weights give the method of Sec. 3.1 with M = 1."""
+    n = g.n
+    w = np.ones(g.col.size, dtype=np.int64) if g.weight is None else np.asarray(g.weight, dtype=np.int64)
+    M = int(w.max()) if w.size else 1
+    rows = np.repeat(np.arange(n), np.diff(g.row_ptr))
+    A = []
+    for c in range(1, M + 1):
+        Ac = np.zeros((n, n), dtype=object)
+        Ac[:, :] = 0
+        for r, col, wc in zip(rows, g.col, w):
+            if wc == c:
+                Ac[r, col] = 1
+        A.append(Ac)
+    zero = np.zeros((n, n), dtype=object)
+    zero[:, :] = 0
+    # Forward: levels are distances.  F[L][i][j] = lambda_ij where d(i,j) = L.
+    D = np.full((n, n), -1, dtype=np.int64)
+    Lam = zero.copy()
+    F = [zero.copy()]
+    for i in range(n):
+        D[i, i] = 0
+        Lam[i, i] = 1
+        F[0][i, i] = 1
+    L, empty_run = 0, 0
+    while empty_run < M:
+        L += 1
+        P = zero.copy()
+        for c in range(1, M + 1):
+            if L - c >= 0:
+                P = P + F[L - c].dot(A[c - 1])
+        first = (D < 0) & (P != 0)
+        Fl = zero.copy()
+        Fl[first] = P[first]
+        D[first] = L
+        Lam[first] = P[first]
+        F.append(Fl)
+        empty_run = 0 if first.any() else empty_run + 1
+    top = int(D.max()) if n else 0
+    # Backward, from the deepest level down to 0 (level 0 gives the diagonal).
+    X = {}
+    Delta = zero.copy()
+    Delta[:, :] = Fraction(0)
+    for l in range(top, -1, -1):
+        Y = zero.copy()
+        Y[:, :] = Fraction(0)
+        for c in range(1, M + 1):
+            if l + c in X:
+                Y = Y + X[l + c].dot(A[c - 1])
+        Xl = zero.copy()
+        Xl[:, :] = Fraction(0)
+        for i, j in zip(*np.nonzero(D == l)):
+            Delta[i, j] = Y[i, j] * int(Lam[i, j])
+            Xl[i, j] = (1 + Delta[i, j]) / Fraction(int(Lam[i, j]))
+        X[l] = Xl
     bc = [sum((Delta[i, j] for i in range(n) if i != j), Fraction(0)) for j in range(n)]
     return D, Lam, Delta, bc

@@ -40,6 +40,7 @@ FORMS = {"auto": BC_FORM_AUTO, "plain": BC_FORM_PLAIN_FP64, "sparse": BC_FORM_SP
          "algebraic": BC_FORM_ALGEBRAIC, "hybrid": BC_FORM_HYBRID}
 
 BC_ALL_PAIRS_MAX_N = 32768
+BC_ALGEBRAIC_MAX_WEIGHT = 8
 BC_TUNE_DEFAULT = 0
 BC_TUNE_MEASURED = 1
 BC_TUNE_CACHED = 2

@@ -23,7 +23,20 @@
 // matrix.  The dependencies are added into BC in the epilogue (column sums of
 // Delta without the diagonal: level 0 is never accumulated).
 //
-// Data layout: A is a dense row-major BF16 [npad][npad] matrix (npad = n
+// Integer weights 1..M (Sec. 3.2): levels are distances, A_c is the 0/1
+// matrix of the edges of weight c, and
+//     F_L = Mask_unvisited(sum_{c=1..M} A_c . F_{L-c}),
+// a vertex's first non-empty level being its distance (every weight is at
+// least 1, so levels L-M .. L-1 are complete when level L is formed).  The
+// backward takes, for v at level L, delta(v) = lambda(v) * sum_c (A_c .
+// C_{L+c})[v]: the w with d(w) = d(v) + c over an edge of weight c are exactly
+// v's successors in the shortest-path DAG.  Both sums are one product with
+// the class matrices side by side, [A_1 | ... | A_M] (rows = vertices, K =
+// M * npad), against the stacked planes [X_1; ...; X_M] of the levels involved;
+// unit weights are M = 1.  The exactness bound is unchanged: an output sums at
+// most deg(w) non-zero terms of at most 255.
+//
+// Data layout: A is a dense row-major BF16 [npad][M * npad] matrix (npad = n
 // rounded up to 256, the block's row count).  Planes are k-packed: plane[v / 8][b][v % 8], so each
 // MFMA B-operand lane reads 16 contiguous bytes.  Every product is
 // C[w][b] = sum_v A[w][v] X[v][b] with rows = vertices and columns = sources;
@@ -53,11 +66,12 @@ constexpr int PB = 256;  // threads per block of the element-wise kernels
 enum { EPI_ONLY = 0, EPI_FIRST = 1, EPI_MID = 2, EPI_LAST = 3 };
 
 struct GemmArgs {
-    const __bf16 *adj;     // [npad][npad]
-    const __bf16 *planes;  // planes of [npad/8][B][8]
-    const uint32_t *kflags;// [npad/GK][B/GN]: some plane entry of this k-tile is non-zero
+    const __bf16 *adj;     // [npad][K]
+    const __bf16 *planes;  // planes of [K/8][B][8]
+    const uint32_t *kflags;// [K/GK][B/GN]: some plane entry of this k-tile is non-zero
     int32_t npad, n, B, NW;
-    size_t plane_elems;    // npad * B
+    int32_t K;             // M * npad: the class matrices side by side
+    size_t plane_elems;    // K * B
 };
 
 struct EpiArgs {
@@ -70,8 +84,9 @@ struct EpiArgs {
     const int32_t *src_lane;
     double *bc, *delta_dump;
     uint32_t *any_next, *status;
-    const unsigned long long *lvmax_cur; // forward: largest count of level l
+    const unsigned long long *lvmax_cur; // forward: largest count of level l (then l-1, ...)
     unsigned long long *lvmax_next;      // forward: largest count of level l+1
+    int32_t classes, level;              // forward: M, and l (levels l+1-M .. l feed level l+1)
     unsigned long long *planes_issued;   // products issued (limb or coefficient planes)
     int accumulate;
 };
@@ -87,6 +102,14 @@ __device__ __forceinline__ int limbs_of(uint64_t mx) {
     int L = 1;
     while (L < 8 && (mx >> (8 * L)) != 0) ++L;
     return L;
+}
+
+// Limbs for the product forming level l+1: the largest count of the levels
+// l+1-M .. l that feed it (levels below 0 do not exist).
+__device__ __forceinline__ int limbs_feeding(const unsigned long long *lvmax_l, int32_t l, int32_t M) {
+    unsigned long long mx = 0;
+    for (int32_t c = 0; c < M && c <= l; ++c) mx = max(mx, lvmax_l[-c]);
+    return limbs_of(mx);
 }
 
 // ---- the product -------------------------------------------------------------------
@@ -106,7 +129,7 @@ __device__ __forceinline__ void load_stage(const GemmArgs &g, const __bf16 *plan
     const int row = tid >> 2, kq = tid & 3; // four threads read one row's 64 B
 #pragma unroll
     for (int i = 0; i < 4; ++i)
-        st.a[i] = *reinterpret_cast<const u32x4 *>(g.adj + (size_t)(w0 + row + 64 * i) * g.npad + (size_t)kt * GK +
+        st.a[i] = *reinterpret_cast<const u32x4 *>(g.adj + (size_t)(w0 + row + 64 * i) * g.K + (size_t)kt * GK +
                                                    kq * 8);
     const int c = tid & (GN - 1), i0 = tid / GN; // k-group i0 and i0 + 2, column c
 #pragma unroll
@@ -195,7 +218,7 @@ template <int NP>
 __device__ __forceinline__ void gemm_tile(const GemmArgs &g, const __bf16 *planes, int w0, int b0, int tid,
                                           __bf16 (*sA)[GM * SA], __bf16 (*sX)[NP * 4 * GN * 8], f32x16 (&acc)[RT][2]) {
     const int lane = tid & 63, wv = tid >> 6, wr = wv >> 1, wc = wv & 1;
-    const int nkt = g.npad / GK, ntn = g.B / GN;
+    const int nkt = g.K / GK, ntn = g.B / GN;
     const uint32_t *flags = g.kflags + b0 / GN;
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
@@ -317,7 +340,7 @@ __global__ __launch_bounds__(GT, 2) void k_mfma_fwd(GemmArgs g, EpiArgs e) {
     const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int w0 = tl.row * GM + (wv >> 1) * WM, b0 = tl.col * GN;
     const int q = (b0 >> 6) + (wv & 1); // bitmap word of this wave's sources
-    const int L = limbs_of(*e.lvmax_cur);
+    const int L = limbs_feeding(e.lvmax_cur, e.level, e.classes);
     if (blockIdx.x == 0 && tid == 0) atomicAdd(e.planes_issued, (unsigned long long)L);
     f32x16 acc[RT][2];
 #pragma nounroll
@@ -383,34 +406,46 @@ __global__ __launch_bounds__(GT, 2) void k_mfma_bwd(GemmArgs g, EpiArgs e) {
 
 // ---- element-wise kernels -------------------------------------------------------
 
-__global__ __launch_bounds__(PB) void k_build_adj(int32_t n, int32_t npad, const int32_t *__restrict__ rp,
-                                                  const int32_t *__restrict__ col, __bf16 *__restrict__ adj) {
+// A[v][(c-1) npad + w] = 1 for every arc v -> w of weight c (c = 1 without
+// weights).
+__global__ __launch_bounds__(PB) void k_build_adj(int32_t n, int32_t npad, int32_t K, const int32_t *__restrict__ rp,
+                                                  const int32_t *__restrict__ col, const uint8_t *__restrict__ wt,
+                                                  __bf16 *__restrict__ adj) {
     const int32_t v = blockIdx.x;
     if (v >= n) return;
     const __bf16 one = (__bf16)1.0f;
-    for (int32_t e = rp[v] + threadIdx.x; e < rp[v + 1]; e += PB) adj[(size_t)v * npad + col[e]] = one;
+    for (int32_t e = rp[v] + threadIdx.x; e < rp[v + 1]; e += PB) {
+        const int32_t c = wt ? (int32_t)wt[e] - 1 : 0;
+        adj[(size_t)v * K + (size_t)c * npad + col[e]] = one;
+    }
 }
 
-// planes[k][v/8][b][v%8] = limb k of lambda(s_b, v) for v at level l, else 0,
-// for the limbs of level l's largest count; kflags[v / GK][b / GN] |= (some
-// limb non-zero).  Thread (vg, b) covers 8 rows.
+// Planes feeding level l+1: planes[k][c][v/8][b][v%8] = limb k of
+// lambda(s_b, v) for v at level l-c (class c+1, weight c+1), else 0, for the
+// limbs of the largest count among the feeding levels; kflags[(c npad + v) /
+// GK][b / GN] |= (some limb non-zero).  Thread (c, vg, b) covers 8 rows; levels
+// are `words` words apart, and levels below 0 contribute nothing.
 template <typename S>
-__global__ __launch_bounds__(PB) void k_limb_split(int32_t n, int32_t npad, int32_t B, int32_t NW,
-                                                   const unsigned long long *__restrict__ lvmax_cur,
-                                                   const uint64_t *__restrict__ fl, const S *__restrict__ sigma,
-                                                   __bf16 *__restrict__ planes, size_t plane_elems,
-                                                   uint32_t *__restrict__ kflags) {
+__global__ __launch_bounds__(PB) void k_limb_split(int32_t n, int32_t npad, int32_t B, int32_t NW, int32_t M,
+                                                   int32_t l, const unsigned long long *__restrict__ lvmax_l,
+                                                   const uint64_t *__restrict__ fl, size_t words,
+                                                   const S *__restrict__ sigma, __bf16 *__restrict__ planes,
+                                                   size_t plane_elems, uint32_t *__restrict__ kflags) {
     const size_t id = (size_t)blockIdx.x * PB + threadIdx.x;
-    if (id >= (size_t)(npad / 8) * B) return;
-    const int L = limbs_of(*lvmax_cur);
-    const int32_t vg = (int32_t)(id / B), b = (int32_t)(id - (size_t)vg * B);
+    const size_t per_class = (size_t)(npad / 8) * B;
+    if (id >= per_class * M) return;
+    const int32_t c = (int32_t)(id / per_class);
+    const size_t r = id - (size_t)c * per_class;
+    const int L = limbs_feeding(lvmax_l, l, M);
+    const int32_t vg = (int32_t)(r / B), b = (int32_t)(r - (size_t)vg * B);
+    const uint64_t *f = c <= l ? fl - (size_t)c * words : nullptr;
     uint64_t s[8];
     bool nz = false;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         const int32_t v = vg * 8 + j;
         s[j] = 0;
-        if (v < n && ((fl[(size_t)v * NW + (b >> 6)] >> (b & 63)) & 1)) s[j] = (uint64_t)sigma[(size_t)v * B + b];
+        if (f && v < n && ((f[(size_t)v * NW + (b >> 6)] >> (b & 63)) & 1)) s[j] = (uint64_t)sigma[(size_t)v * B + b];
         nz |= s[j] != 0;
     }
     for (int k = 0; k < L; ++k) {
@@ -419,24 +454,31 @@ __global__ __launch_bounds__(PB) void k_limb_split(int32_t n, int32_t npad, int3
         for (int j = 0; j < 8; ++j) o[j] = (__bf16)(float)((s[j] >> (8 * k)) & 0xFF);
         *reinterpret_cast<bf16x8 *>(planes + (size_t)k * plane_elems + id * 8) = o;
     }
-    if (__ballot(nz) && (threadIdx.x & 63) == 0) atomicOr(&kflags[(size_t)(vg * 8 / GK) * (B / GN) + b / GN], 1u);
+    if (__ballot(nz) && (threadIdx.x & 63) == 0)
+        atomicOr(&kflags[(size_t)(((size_t)c * npad + (size_t)vg * 8) / GK) * (B / GN) + b / GN], 1u);
 }
 
-// planes[0..2][v/8][b][v%8] = hi, mid, lo BF16 parts of c(v, b) for v at level l.
-__global__ __launch_bounds__(PB) void k_coef_split(int32_t n, int32_t npad, int32_t B, int32_t NW,
-                                                   const uint64_t *__restrict__ fl, const float *__restrict__ cval,
-                                                   __bf16 *__restrict__ planes, size_t plane_elems,
-                                                   uint32_t *__restrict__ kflags) {
+// Planes for backward level l: planes[0..2][c][v/8][b][v%8] = hi, mid, lo BF16
+// parts of c(v, b) for v at level l+1+c (class c+1), for the `deeper` levels
+// below l that exist (the others contribute nothing).
+__global__ __launch_bounds__(PB) void k_coef_split(int32_t n, int32_t npad, int32_t B, int32_t NW, int32_t M,
+                                                   int32_t deeper, const uint64_t *__restrict__ fl, size_t words,
+                                                   const float *__restrict__ cval, __bf16 *__restrict__ planes,
+                                                   size_t plane_elems, uint32_t *__restrict__ kflags) {
     const size_t id = (size_t)blockIdx.x * PB + threadIdx.x;
-    if (id >= (size_t)(npad / 8) * B) return;
-    const int32_t vg = (int32_t)(id / B), b = (int32_t)(id - (size_t)vg * B);
+    const size_t per_class = (size_t)(npad / 8) * B;
+    if (id >= per_class * M) return;
+    const int32_t cl = (int32_t)(id / per_class);
+    const size_t r = id - (size_t)cl * per_class;
+    const int32_t vg = (int32_t)(r / B), b = (int32_t)(r - (size_t)vg * B);
+    const uint64_t *f = cl < deeper ? fl + (size_t)cl * words : nullptr;
     bf16x8 hi, mid, lo;
     bool nz = false;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         const int32_t v = vg * 8 + j;
         float c = 0.f;
-        if (v < n && ((fl[(size_t)v * NW + (b >> 6)] >> (b & 63)) & 1)) c = cval[(size_t)v * B + b];
+        if (f && v < n && ((f[(size_t)v * NW + (b >> 6)] >> (b & 63)) & 1)) c = cval[(size_t)v * B + b];
         const __bf16 h = (__bf16)c;
         const float r1 = c - (float)h;
         const __bf16 m = (__bf16)r1;
@@ -449,10 +491,15 @@ __global__ __launch_bounds__(PB) void k_coef_split(int32_t n, int32_t npad, int3
     *reinterpret_cast<bf16x8 *>(planes + id * 8) = hi;
     *reinterpret_cast<bf16x8 *>(planes + plane_elems + id * 8) = mid;
     *reinterpret_cast<bf16x8 *>(planes + 2 * plane_elems + id * 8) = lo;
-    if (__ballot(nz) && (threadIdx.x & 63) == 0) atomicOr(&kflags[(size_t)(vg * 8 / GK) * (B / GN) + b / GN], 1u);
+    if (__ballot(nz) && (threadIdx.x & 63) == 0)
+        atomicOr(&kflags[(size_t)(((size_t)cl * npad + (size_t)vg * 8) / GK) * (B / GN) + b / GN], 1u);
 }
 
 inline unsigned blocks_for(size_t count, int per) { return (unsigned)((count + per - 1) / per); }
+
+inline size_t kflag_bytes(bc_ctx *ctx) {
+    return (size_t)ctx->al.classes * (ctx->al.npad / GK) * (ctx->sp.batch / GN) * sizeof(uint32_t);
+}
 
 GemmArgs gemm_args(bc_ctx *ctx, const __bf16 *planes) {
     AlgebraicState &a = ctx->al;
@@ -464,7 +511,8 @@ GemmArgs gemm_args(bc_ctx *ctx, const __bf16 *planes) {
     g.n = ctx->n;
     g.B = ctx->sp.batch;
     g.NW = ctx->sp.words;
-    g.plane_elems = (size_t)a.npad * ctx->sp.batch;
+    g.K = a.classes * a.npad;
+    g.plane_elems = (size_t)g.K * ctx->sp.batch;
     return g;
 }
 
@@ -473,28 +521,31 @@ GemmArgs gemm_args(bc_ctx *ctx, const __bf16 *planes) {
 bc_status algebraic_prepare(bc_ctx *ctx) {
     AlgebraicState &a = ctx->al;
     const int32_t B = ctx->sp.batch;
-    if (ctx->weighted) return bc_fail(ctx, BC_ERR_UNSUPPORTED, "algebraic form: unit weights only");
+    if (ctx->weighted && ctx->max_weight > BC_ALGEBRAIC_MAX_WEIGHT)
+        return bc_fail(ctx, BC_ERR_UNSUPPORTED, "algebraic form: weights above 8 (one product class per weight)");
     if (B % GN != 0) return bc_fail(ctx, BC_ERR_UNSUPPORTED, "algebraic form: batch must be 256 or 512");
     if (ctx->max_degree > 65792)
         return bc_fail(ctx, BC_ERR_UNSUPPORTED,
                        "algebraic form: a degree above 65792 breaks exact FP32 accumulation of 8-bit limbs");
     a.npad = std::max(GM, (ctx->n + GM - 1) / GM * GM);
-    const size_t adj_bytes = (size_t)a.npad * a.npad * sizeof(__bf16);
+    a.classes = ctx->weighted ? (int32_t)ctx->max_weight : 1;
+    const size_t K = (size_t)a.classes * a.npad;
+    const size_t adj_bytes = (size_t)a.npad * K * sizeof(__bf16);
     if (adj_bytes > (size_t(96) << 30))
         return bc_fail(ctx, BC_ERR_UNSUPPORTED, "algebraic form: the dense adjacency would exceed 96 GiB");
-    const size_t plane_elems = (size_t)a.npad * B;
+    const size_t plane_elems = K * B;
     a.adj = (__bf16 *)bc_dalloc(ctx, adj_bytes);
     a.planes = (__bf16 *)bc_dalloc(ctx, 8 * plane_elems * sizeof(__bf16)); // up to 8 limbs, or 3 coefficient planes
-    a.part = (uint64_t *)bc_dalloc(ctx, plane_elems * sizeof(uint64_t));
-    a.kflags = (uint32_t *)bc_dalloc(ctx, (size_t)(a.npad / GK) * (B / GN) * sizeof(uint32_t));
+    a.part = (uint64_t *)bc_dalloc(ctx, (size_t)a.npad * B * sizeof(uint64_t));
+    a.kflags = (uint32_t *)bc_dalloc(ctx, (K / GK) * (B / GN) * sizeof(uint32_t));
     a.planes_issued = (unsigned long long *)bc_dalloc(ctx, 256);
     if (!a.adj || !a.planes || !a.part || !a.kflags || !a.planes_issued)
         return bc_fail(ctx, BC_ERR_NOMEM, "algebraic form: allocation failed");
     BC_HIP(ctx, hipMemsetAsync(a.adj, 0, adj_bytes, ctx->stream));
     BC_HIP(ctx, hipMemsetAsync(a.planes_issued, 0, sizeof(unsigned long long), ctx->stream));
     if (ctx->n > 0)
-        hipLaunchKernelGGL(k_build_adj, dim3(ctx->n), dim3(PB), 0, ctx->stream, ctx->n, a.npad, ctx->row_ptr,
-                           ctx->col, a.adj);
+        hipLaunchKernelGGL(k_build_adj, dim3(ctx->n), dim3(PB), 0, ctx->stream, ctx->n, a.npad, (int32_t)K,
+                           ctx->row_ptr, ctx->col, ctx->weighted ? (const uint8_t *)ctx->weight : nullptr, a.adj);
     BC_HIP(ctx, hipGetLastError());
     return BC_OK;
 }
@@ -520,13 +571,13 @@ bc_status algebraic_forward_level_t(bc_ctx *ctx, int32_t l) {
     const size_t words = (size_t)ctx->n * s.words;
     const size_t aw = (size_t)(ctx->n + 31) / 32;
     const uint64_t *fcur = s.front + (size_t)l * words;
-    const size_t plane_elems = (size_t)a.npad * s.batch;
-    BC_HIP(ctx, hipMemsetAsync(a.kflags, 0, (size_t)(a.npad / GK) * (s.batch / GN) * sizeof(uint32_t), ctx->stream));
+    const size_t plane_elems = (size_t)a.classes * a.npad * s.batch;
+    BC_HIP(ctx, hipMemsetAsync(a.kflags, 0, kflag_bytes(ctx), ctx->stream));
     {
         LaunchTimer tm(ctx, "limb_split");
         hipLaunchKernelGGL(k_limb_split<S>, dim3(blocks_for(plane_elems / 8, PB)), dim3(PB), 0, ctx->stream, ctx->n,
-                           a.npad, s.batch, s.words, s.lvmax + l, fcur, (const S *)s.sigma, a.planes, plane_elems,
-                           a.kflags);
+                           a.npad, s.batch, s.words, a.classes, l, s.lvmax + l, fcur, words, (const S *)s.sigma,
+                           a.planes, plane_elems, a.kflags);
         tm.done();
     }
     EpiArgs e{};
@@ -538,6 +589,8 @@ bc_status algebraic_forward_level_t(bc_ctx *ctx, int32_t l) {
     e.status = ctx->status;
     e.lvmax_cur = s.lvmax + l;
     e.lvmax_next = s.lvmax + l + 1;
+    e.classes = a.classes;
+    e.level = l;
     e.planes_issued = a.planes_issued;
     const GemmArgs g = gemm_args(ctx, a.planes);
     LaunchTimer tm(ctx, "mfma_fwd");
@@ -547,18 +600,22 @@ bc_status algebraic_forward_level_t(bc_ctx *ctx, int32_t l) {
     return BC_OK;
 }
 
-// Backward level l as a product with A: acc = A . C_{l+1}, masked to level l.
+// Backward level l as a product with A: acc = sum_c A_c . C_{l+c}, masked to
+// level l; `deeper` of the levels l+1 .. l+M exist (front[l+1] at fnext, the
+// next ones `words` apart).
 template <typename S>
-bc_status algebraic_backward_level_t(bc_ctx *ctx, const uint64_t *fcur, const uint64_t *fnext, double *delta_dump,
-                                     bool accumulate) {
+bc_status algebraic_backward_level_t(bc_ctx *ctx, const uint64_t *fcur, const uint64_t *fnext, int32_t deeper,
+                                     double *delta_dump, bool accumulate) {
     AlgebraicState &a = ctx->al;
     SparseState &s = ctx->sp;
-    const size_t plane_elems = (size_t)a.npad * s.batch;
-    BC_HIP(ctx, hipMemsetAsync(a.kflags, 0, (size_t)(a.npad / GK) * (s.batch / GN) * sizeof(uint32_t), ctx->stream));
+    const size_t words = (size_t)ctx->n * s.words;
+    const size_t plane_elems = (size_t)a.classes * a.npad * s.batch;
+    BC_HIP(ctx, hipMemsetAsync(a.kflags, 0, kflag_bytes(ctx), ctx->stream));
     {
         LaunchTimer tm(ctx, "coef_split");
         hipLaunchKernelGGL(k_coef_split, dim3(blocks_for(plane_elems / 8, PB)), dim3(PB), 0, ctx->stream, ctx->n,
-                           a.npad, s.batch, s.words, fnext, s.cval, a.planes, plane_elems, a.kflags);
+                           a.npad, s.batch, s.words, a.classes, fnext ? deeper : 0, fnext, words, s.cval, a.planes,
+                           plane_elems, a.kflags);
         tm.done();
     }
     EpiArgs e{};
@@ -583,9 +640,9 @@ bc_status algebraic_forward_level(bc_ctx *ctx, bool wide, int32_t l) {
 }
 
 bc_status algebraic_backward_level(bc_ctx *ctx, bool wide, const uint64_t *fcur, const uint64_t *fnext,
-                                   double *delta_dump, bool accumulate) {
-    return wide ? algebraic_backward_level_t<uint64_t>(ctx, fcur, fnext, delta_dump, accumulate)
-                : algebraic_backward_level_t<uint32_t>(ctx, fcur, fnext, delta_dump, accumulate);
+                                   int32_t deeper, double *delta_dump, bool accumulate) {
+    return wide ? algebraic_backward_level_t<uint64_t>(ctx, fcur, fnext, deeper, delta_dump, accumulate)
+                : algebraic_backward_level_t<uint32_t>(ctx, fcur, fnext, deeper, delta_dump, accumulate);
 }
 
 int64_t algebraic_planes_issued(bc_ctx *ctx) {

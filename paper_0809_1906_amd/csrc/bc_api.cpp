@@ -306,9 +306,12 @@ bc_status bc_create(const bc_graph *g, const bc_options *opt_in, bc_ctx **out) {
     if (opt.edges && form == BC_FORM_ALGEBRAIC)
         return fail_create(BC_ERR_UNSUPPORTED,
                            "edge betweenness needs per-arc terms; the algebraic form's products give row sums only");
-    if (hw && (form == BC_FORM_SPARSE || form == BC_FORM_ALGEBRAIC || form == BC_FORM_HYBRID))
+    if (hw && (form == BC_FORM_SPARSE || form == BC_FORM_HYBRID))
         return fail_create(BC_ERR_UNSUPPORTED,
-                           "weighted graphs are served by the per-source form (BC_FORM_PLAIN_FP64) only");
+                           "weighted graphs are served by the per-source and algebraic forms only");
+    if (hw && form == BC_FORM_ALGEBRAIC && max_w > BC_ALGEBRAIC_MAX_WEIGHT)
+        return fail_create(BC_ERR_UNSUPPORTED,
+                           "the algebraic form takes weights up to BC_ALGEBRAIC_MAX_WEIGHT (one product class each)");
 
     // ---- device side ----
     bc_ctx *ctx = new (std::nothrow) bc_ctx();

@@ -53,10 +53,11 @@ struct SparseState {
 // State of the algebraic form (dense adjacency products on MFMA).
 struct AlgebraicState {
     int32_t npad = 0;                  // n rounded up to 256 (the product's row block)
-    __bf16 *adj = nullptr;             // [npad][npad] 0/1
-    __bf16 *planes = nullptr;          // up to 8 planes of [npad/8][batch][8]
+    int32_t classes = 1;               // M: one 0/1 matrix per integer weight 1..M
+    __bf16 *adj = nullptr;             // [npad][M npad] 0/1, class c in columns [(c-1) npad, c npad)
+    __bf16 *planes = nullptr;          // up to 8 planes of [M npad/8][batch][8]
     uint64_t *part = nullptr;          // [npad][batch] partial limb sums
-    uint32_t *kflags = nullptr;        // [npad/32][batch/256] non-empty k-tiles
+    uint32_t *kflags = nullptr;        // [M npad/32][batch/128] non-empty k-tiles
     unsigned long long *planes_issued = nullptr; // products issued (limb or coefficient planes)
     bool every_level = false;          // the algebraic form: every level l >= 1 by products
 };
@@ -249,8 +250,9 @@ bc_status sparse_prepare(bc_ctx *ctx, int32_t batch, int32_t split_degree);
 bc_status algebraic_prepare(bc_ctx *ctx);
 // Forward level l -> l+1 by products (front, counts, any and lvmax of level l+1).
 bc_status algebraic_forward_level(bc_ctx *ctx, bool wide, int32_t l);
+// Backward level l; `deeper` of the levels l+1 .. l+M exist, fnext = front[l+1].
 bc_status algebraic_backward_level(bc_ctx *ctx, bool wide, const uint64_t *fcur, const uint64_t *fnext,
-                                   double *delta_dump, bool accumulate);
+                                   int32_t deeper, double *delta_dump, bool accumulate);
 int64_t algebraic_planes_issued(bc_ctx *ctx); // synchronises; -1 on a device error
 void algebraic_reset_counters(bc_ctx *ctx);
 bc_status sparse_release(bc_ctx *ctx);

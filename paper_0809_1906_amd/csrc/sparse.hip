@@ -712,7 +712,8 @@ bc_status ensure_levels(bc_ctx *ctx, int32_t need) {
 // the number of non-empty levels.  Forward levels are launched ahead of the
 // host knowing whether they are needed (as many as the previous batch used);
 // the host then reads the per-level vertex filters back with one
-// synchronisation and finds the first empty level.  With S = uint32_t,
+// synchronisation and finds the first empty level (with weights 1..M, the
+// first of M consecutive empty levels: levels are then distances).  With S = uint32_t,
 // *need_wide reports a count of 2^32 or more, before anything was added to BC.
 template <int NW, typename S>
 bc_status run_batch_t(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool accumulate, int32_t *nlev_out,
@@ -741,13 +742,23 @@ bc_status run_batch_t(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool acc
     }
     int32_t launched = 0, nlev = -1;
     const bool wide_now = sizeof(S) == 8;
+    // Weighted graphs (the algebraic form, Sec. 3.2): levels are distances and
+    // level l+1 is formed from levels l+1-M .. l; the search ends at M
+    // consecutive empty levels.
+    const bool weighted = ctx->weighted;
+    const int32_t M = weighted ? ctx->al.classes : 1;
 
     const size_t rec0 = ctx->hy.probe ? ctx->hy.probe->recs.size() : 0;
     while (nlev < 0) {
-        const int32_t target = launched == 0 ? guess : launched + 2;
+        const int32_t target = launched == 0 ? std::max(guess + M - 1, M + 1) : launched + std::max(2, M);
         st = ensure_levels(ctx, target + 1);
         if (st != BC_OK) return st;
         for (int32_t l = launched; l < target; ++l) {
+            if (weighted) {
+                st = algebraic_forward_level(ctx, wide_now, l);
+                if (st != BC_OK) return st;
+                continue;
+            }
             if (l == 0) {
                 LaunchTimer tm(ctx, "fwd_push0");
                 hipLaunchKernelGGL(k_fwd_push0<S>, dim3(B), dim3(SB), 0, ctx->stream, t, NW, (const int32_t *)s.src,
@@ -783,11 +794,14 @@ bc_status run_batch_t(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool acc
             *need_wide = true;
             return BC_OK;
         }
+        // nlev = the first level l >= 1 that starts a run of M empty levels
+        int32_t run = 0;
         for (int32_t l = first; l <= target && nlev < 0; ++l) {
             const uint32_t *a = s.any_host + (size_t)l * aw;
             bool empty = true;
             for (int32_t i = 0; i < aw && empty; ++i) empty = a[i] == 0;
-            if (empty) nlev = l;
+            run = empty ? run + 1 : 0;
+            if (run == M) nlev = l - M + 1;
         }
         launched = target;
     }
@@ -802,9 +816,17 @@ bc_status run_batch_t(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool acc
         const bool deeper = lv + 1 < nlev;
         const uint64_t *fnext = deeper ? s.front + (size_t)(lv + 1) * words : nullptr;
         const uint32_t *anext = deeper ? s.any + (size_t)(lv + 1) * aw : nullptr;
+        if (weighted) {
+            // successors at levels lv+1 .. lv+M that exist; at the deepest
+            // level none, and the product only sets c = 1 / lambda
+            st = algebraic_backward_level(ctx, sizeof(S) == 8, fcur, fnext, std::min(M, nlev - 1 - lv), ddump,
+                                          accumulate);
+            if (st != BC_OK) return st;
+            continue;
+        }
         ProbeScope ps(ctx);
         if (deeper && by_products(ctx, lv, false)) {
-            st = algebraic_backward_level(ctx, sizeof(S) == 8, fcur, fnext, ddump, accumulate);
+            st = algebraic_backward_level(ctx, sizeof(S) == 8, fcur, fnext, 1, ddump, accumulate);
             if (st != BC_OK) return st;
             ps.done(false, lv);
             continue;

@@ -137,11 +137,22 @@ def test_invalid_arguments():
 
 def test_batched_forms_refuse_weights_before_device_work():
     g = gg.with_uniform_weights(gg.path(5), 1, 1, 9)
-    for form in (B.BC_FORM_SPARSE, B.BC_FORM_ALGEBRAIC, B.BC_FORM_HYBRID):
+    for form in (B.BC_FORM_SPARSE, B.BC_FORM_HYBRID):
         opt = bcgpu.bc_options_init()
         opt.form = form
         st, msg = _create_status(g.n, g.row_ptr, g.col, g.weight, opt)
         assert st == B.BC_ERR_UNSUPPORTED and "weighted" in msg
+
+
+def test_algebraic_form_refuses_weights_above_its_classes():
+    """The algebraic form takes one product class per weight, up to
+    BC_ALGEBRAIC_MAX_WEIGHT; a heavier edge is refused before device work."""
+    assert B.BC_ALGEBRAIC_MAX_WEIGHT == 8
+    g = gg.with_constant_weight(gg.path(5), B.BC_ALGEBRAIC_MAX_WEIGHT + 1)
+    opt = bcgpu.bc_options_init()
+    opt.form = B.BC_FORM_ALGEBRAIC
+    st, msg = _create_status(g.n, g.row_ptr, g.col, g.weight, opt)
+    assert st == B.BC_ERR_UNSUPPORTED and "BC_ALGEBRAIC_MAX_WEIGHT" in msg
 
 
 def test_edges_refused_where_not_computed():

@@ -103,3 +103,43 @@ def test_algebraic_method_grid():
     g = gg.grid(4, 4)
     _, _, _, bc = cross.algebraic(g)
     assert _rel_err(oracle.bc(g), [float(x) for x in bc]) <= 1e-14
+
+
+@pytest.mark.parametrize("seed,n,p,wmax", [(11, 7, 0.45, 3), (12, 8, 0.4, 5), (13, 6, 0.6, 8), (14, 8, 0.35, 2)])
+def test_algebraic_weighted_equals_brute_force(seed, n, p, wmax):
+    """The per-weight-class reading of Sec. 3.2 against the definitions
+    (every simple path enumerated, exact rationals)."""
+    g = gg.random_graph(n, p, seed, weights=wmax)
+    D, Lam, Delta, bc = cross.algebraic_weighted(g)
+    dist, count, bf = cross.brute_force(g)
+    assert bc == bf
+    for s_ in range(n):
+        for t in range(n):
+            want = -1 if dist[s_][t] is None else dist[s_][t]
+            assert D[s_, t] == want
+            assert int(Lam[s_, t]) == count[s_][t]
+
+
+@pytest.mark.parametrize("seed,n,p,wmax", [(21, 30, 0.15, 4), (22, 40, 0.1, 8), (23, 25, 0.2, 1)])
+def test_algebraic_weighted_matches_oracle(seed, n, p, wmax):
+    """Per source: distances and counts exactly, dependencies to rounding;
+    M = 1 reduces to the method of Sec. 3.1."""
+    g = gg.random_graph(n, p, seed, weights=wmax)
+    D, Lam, Delta, bc = cross.algebraic_weighted(g)
+    assert _rel_err(oracle.bc(g), [float(x) for x in bc]) <= 1e-13
+    for s_ in range(n):
+        d, sigma, delta = oracle.sssp(g, s_)
+        np.testing.assert_array_equal(d, D[s_])
+        assert [int(x) for x in sigma] == [int(x) for x in Lam[s_]]
+        np.testing.assert_allclose(delta, [float(x) for x in Delta[s_]], rtol=1e-13, atol=1e-13)
+    if wmax == 1:
+        assert bc == cross.algebraic(gg.random_graph(n, p, seed))[3]
+
+
+def test_algebraic_weighted_gap_levels():
+    """Weights leave empty distance levels between non-empty ones (a path of
+    weight-5 edges): the forward stops only after M empty levels."""
+    g = gg.with_constant_weight(gg.path(6), 5)
+    D, Lam, _, bc = cross.algebraic_weighted(g)
+    assert D[0, 5] == 25 and int(Lam[0, 5]) == 1
+    assert _rel_err(oracle.bc(g), [float(x) for x in bc]) <= 1e-14
