@@ -19,6 +19,10 @@ Other workloads (same JSON schema; used for profiles and design figures):
   ws4096   4096 Watts-Strogatz graphs, all sources: one persistent launch
   rmat20w  RMAT-20 with weights U{1..255}, 4096 sampled sources: bucketed
            shortest paths per source
+  er16384w4
+           the er16384 graph with weights U{1..4}, all sources: the algebraic
+           form with one product class per weight (Sec. 3.2), batch 512,
+           against the plain form's bucketed per-source sweep
   allpairs16384
            ER n=16384, degree 256: BC over every pair by Algorithm 2 (the
            algebraic form's forward fills all-pairs distances and counts, one
@@ -66,6 +70,9 @@ WORKLOADS = {
     "rmat20w": {"form": "plain", "batch": 0, "compare": [],
                 "desc": "rmat20w: RMAT scale 20, edgefactor 16, largest component, weights U{1..255}; BC "
                         "over 4096 sources sampled without replacement"},
+    "er16384w4": {"form": "algebraic", "batch": 512, "compare": [("plain", 0)],
+                  "desc": "er16384w4: Erdos-Renyi n=16384, average degree 256, largest component, weights "
+                          "U{1..4}; exact all-source BC"},
     "allpairs16384": {"form": "algebraic", "batch": 512, "compare": [],
                       "desc": "allpairs16384: Erdos-Renyi n=16384, average degree 256, largest component; BC "
                               "over every ordered pair by Algorithm 2 from all-pairs distances and counts"},
@@ -199,16 +206,21 @@ def roofline(name, wl, kern, info, steps):
     base = {"kernel": dom, "avg_launch_ms": ms / max(launches, 1), "launches": launches}
     if dom in ("mfma_fwd", "mfma_bwd"):
         npad = (n + 255) // 256 * 256
+        # with weights 1..M a product runs over K = M * npad (one class each)
+        wts = getattr(wl["graph"], "weight", None)
+        classes = int(wts.max()) if wts is not None and wts.size else 1
         # a backward launch is three coefficient planes; a forward launch loops
         # over its level's 8-bit limbs, counted by the library (mfma_planes)
         bwd_launches = kern.get("mfma_bwd", (0.0, 0))[1]
         planes = 3 * launches if dom == "mfma_bwd" else max(info.mfma_planes - 3 * bwd_launches, launches)
-        flops = 2.0 * info.batch * npad * npad * planes
+        flops = 2.0 * info.batch * npad * npad * classes * planes
+        base["weight_classes"] = classes
         ach = flops / (ms * 1e-3) / 1e12
         return dict(base, bound="mfma", achieved=ach, peak=MFMA_BF16_PEAK_TFS, unit="TFLOP/s",
                     frac=ach / MFMA_BF16_PEAK_TFS, traffic=None,
                     alg_flops_per_launch=flops / max(launches, 1),
-                    planes=planes, note="issued dense products: 2 * batch * npad^2 per limb or coefficient plane")
+                    planes=planes, note="issued dense products: 2 * batch * npad * (M * npad) per limb or "
+                                        "coefficient plane, M weight classes")
     if dom == "weighted_sweep":
         total = float(S) * steps * weighted_bytes(n, m)
     elif dom == "multigraph_sweep":

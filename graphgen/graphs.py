@@ -380,6 +380,7 @@ WORKLOADS = {
     "er16384": "ER n=16384, average degree 256, largest component; all sources",
     "ws4096": "4096 Watts-Strogatz graphs, n ~ U{64..4096}, k=6, p=0.1; all sources of every graph",
     "rmat20w": "RMAT scale 20, largest component, weights U{1..255}; 4096 sampled sources",
+    "er16384w4": "ER n=16384, average degree 256, largest component, weights U{1..4}; all sources",
 }
 
 
@@ -397,6 +398,13 @@ def rmat16() -> Graph:
 
 def er16384() -> Graph:
     return erdos_renyi(16384, 256.0, workload_seed(2), name="er16384")
+
+
+def er16384w4() -> Graph:
+    """The er16384 graph with weights U{1..4} per undirected edge."""
+    g = with_uniform_weights(er16384(), workload_seed(5), 1, 4)
+    g.name = "er16384w4"
+    return g
 
 
 def ws_batch(count: int = 4096, nmin: int = 64, nmax: int = 4096, seed: Optional[int] = None):
