@@ -13,7 +13,9 @@
 // level-synchronous forward sweep (distance, exact uint64 counts) and the
 // backward sweep (c(v) = (1 + delta(v)) / lambda(v) in FP32, sums in FP64)
 // entirely in LDS; each unit's dependencies are summed in an FP64 LDS vector
-// and added to BC once per unit.  The launch (a queue-counter reset kernel and
+// and added to BC once per unit.  The unit's columns are staged in LDS as
+// 16-bit local ids when they fit (n <= 4096), so that a level step waits on
+// LDS only; larger graphs read them from global memory.  The launch (a queue-counter reset kernel and
 // the persistent kernel) is captured once into a HIP graph and replayed.
 #include "bc_internal.h"
 
@@ -24,6 +26,7 @@ namespace {
 constexpr int MT = 512;          // threads per workgroup
 constexpr int32_t MG_INF = 0x7FFFFFFF;
 constexpr int ABURST = 8;        // column reads issued together per vertex
+constexpr int32_t COL_CAP = 16320; // 16-bit columns staged in LDS
 
 struct MultiArgs {
     const int32_t *voff;   // [ngraphs+1] first global vertex of each graph
@@ -44,38 +47,39 @@ struct MultiArgs {
 
 __global__ void k_mg_reset(unsigned int *next) { *next = 0; }
 
-__global__ __launch_bounds__(MT) void k_mg_sweep(MultiArgs a) {
-    __shared__ int32_t s_dist[MG_MAX_N];
-    __shared__ unsigned long long s_sig[MG_MAX_N];
-    __shared__ float s_c[MG_MAX_N];
-    __shared__ int32_t s_queue[MG_MAX_N];
-    __shared__ int32_t s_lev[MG_MAX_N + 2];
-    __shared__ double s_bc[MG_MAX_N];
-    __shared__ int32_t s_rp[MG_MAX_N + 1]; // the unit's graph: row offsets relative to its first arc
-    __shared__ int32_t s_unit, s_cnt[3];
-    __shared__ uint32_t s_ovf;
+struct MgShared {
+    int32_t dist[MG_MAX_N];
+    unsigned long long sig[MG_MAX_N];
+    float c[MG_MAX_N];
+    uint16_t queue[MG_MAX_N];
+    uint16_t lev[MG_MAX_N + 2];
+    double bc[MG_MAX_N];
+    int32_t rp[MG_MAX_N + 1]; // the unit's graph: row offsets relative to its first arc
+    uint16_t col[COL_CAP];    // the unit's columns, when they fit
+    int32_t unit, cnt[3];
+    uint32_t ovf;
+};
 
+// The sources [s0, s1) of unit u; columns from LDS (LC) or global memory.
+template <bool LC>
+__device__ __forceinline__ void mg_unit(const MultiArgs &a, MgShared &sh, int32_t u, int32_t n, int32_t vo,
+                                        const int32_t *gcol, int32_t s0, int32_t s1) {
+    int32_t *s_dist = sh.dist;
+    unsigned long long *s_sig = sh.sig;
+    float *s_c = sh.c;
+    uint16_t *s_queue = sh.queue, *s_lev = sh.lev;
+    double *s_bc = sh.bc;
+    const int32_t *s_rp = sh.rp;
+    int32_t *s_cnt = sh.cnt;
     const int tid = threadIdx.x;
-    for (;;) {
-        if (tid == 0) s_unit = (int32_t)atomicAdd(a.next, 1u);
-        __syncthreads();
-        const int32_t u = s_unit;
-        if (u >= a.nunits) break;
-        const int32_t g = a.units[3 * u], s0 = a.units[3 * u + 1], s1 = a.units[3 * u + 2];
-        const int32_t vo = a.voff[g], n = a.voff[g + 1] - vo;
-        const int32_t *grp = a.rp + a.rpoff[g];
-        const int32_t *col = a.col + grp[0];
-        for (int32_t v = tid; v <= n; v += MT) s_rp[v] = grp[v] - grp[0];
-        for (int32_t v = tid; v < n; v += MT) s_bc[v] = 0.0;
-        if (tid == 0) s_ovf = 0;
-        __syncthreads();
+    auto col = [&](int32_t e) -> int32_t { return LC ? (int32_t)sh.col[e] : gcol[e]; };
         for (int32_t s = s0; s < s1; ++s) {
             for (int32_t v = tid; v < n; v += MT) {
                 s_dist[v] = v == s ? 0 : MG_INF;
                 s_sig[v] = v == s ? 1ull : 0ull;
             }
             if (tid == 0) {
-                s_queue[0] = s;
+                s_queue[0] = (uint16_t)s;
                 s_lev[0] = 0;
                 s_lev[1] = 1;
                 s_cnt[0] = 0;
@@ -98,7 +102,7 @@ __global__ __launch_bounds__(MT) void k_mg_sweep(MultiArgs a) {
                     for (int32_t e0 = rb; e0 < re; e0 += ABURST) {
                         int32_t ws[ABURST]; // one burst of column reads in flight
 #pragma unroll
-                        for (int j = 0; j < ABURST; ++j) ws[j] = e0 + j < re ? col[e0 + j] : -1;
+                        for (int j = 0; j < ABURST; ++j) ws[j] = e0 + j < re ? col(e0 + j) : -1;
 #pragma unroll
                         for (int j = 0; j < ABURST; ++j) {
                             const int32_t w = ws[j];
@@ -107,7 +111,7 @@ __global__ __launch_bounds__(MT) void k_mg_sweep(MultiArgs a) {
                             if (dw == MG_INF) {
                                 const int32_t old = atomicCAS(&s_dist[w], MG_INF, L + 1);
                                 if (old == MG_INF) {
-                                    s_queue[qe + atomicAdd(&s_cnt[cur], 1)] = w;
+                                    s_queue[qe + atomicAdd(&s_cnt[cur], 1)] = (uint16_t)w;
                                     dw = L + 1;
                                 } else {
                                     dw = old;
@@ -115,7 +119,7 @@ __global__ __launch_bounds__(MT) void k_mg_sweep(MultiArgs a) {
                             }
                             if (dw == L + 1) { // v in P_s(w)
                                 const unsigned long long old = atomicAdd(&s_sig[w], sv);
-                                if (old + sv < old) s_ovf = 1;
+                                if (old + sv < old) sh.ovf = 1;
                             }
                         }
                     }
@@ -124,7 +128,7 @@ __global__ __launch_bounds__(MT) void k_mg_sweep(MultiArgs a) {
                 qb = qe;
                 qe += s_cnt[cur];
                 ++L;
-                if (tid == 0) s_lev[L + 1] = qe;
+                if (tid == 0) s_lev[L + 1] = (uint16_t)qe;
             }
             __syncthreads();
             const int32_t nlev = L;
@@ -139,7 +143,7 @@ __global__ __launch_bounds__(MT) void k_mg_sweep(MultiArgs a) {
                         for (int32_t e0 = rb; e0 < re; e0 += ABURST) {
                             int32_t ws[ABURST];
 #pragma unroll
-                            for (int j = 0; j < ABURST; ++j) ws[j] = e0 + j < re ? col[e0 + j] : -1;
+                            for (int j = 0; j < ABURST; ++j) ws[j] = e0 + j < re ? col(e0 + j) : -1;
 #pragma unroll
                             for (int j = 0; j < ABURST; ++j)
                                 if (ws[j] >= 0 && s_dist[ws[j]] == l + 1) acc += (double)s_c[ws[j]];
@@ -163,10 +167,34 @@ __global__ __launch_bounds__(MT) void k_mg_sweep(MultiArgs a) {
             }
             __syncthreads();
         }
+}
+
+__global__ __launch_bounds__(MT) void k_mg_sweep(MultiArgs a) {
+    __shared__ MgShared sh;
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) sh.unit = (int32_t)atomicAdd(a.next, 1u);
+        __syncthreads();
+        const int32_t u = sh.unit;
+        if (u >= a.nunits) break;
+        const int32_t g = a.units[3 * u], s0 = a.units[3 * u + 1], s1 = a.units[3 * u + 2];
+        const int32_t vo = a.voff[g], n = a.voff[g + 1] - vo;
+        const int32_t *grp = a.rp + a.rpoff[g];
+        const int32_t *col = a.col + grp[0];
+        const int32_t arcs = grp[n] - grp[0];
+        const bool lds_col = arcs <= COL_CAP;
+        for (int32_t v = tid; v <= n; v += MT) sh.rp[v] = grp[v] - grp[0];
+        for (int32_t v = tid; v < n; v += MT) sh.bc[v] = 0.0;
+        if (lds_col)
+            for (int32_t e = tid; e < arcs; e += MT) sh.col[e] = (uint16_t)col[e];
+        if (tid == 0) sh.ovf = 0;
+        __syncthreads();
+        if (lds_col) mg_unit<true>(a, sh, u, n, vo, col, s0, s1);
+        else mg_unit<false>(a, sh, u, n, vo, col, s0, s1);
         if (!a.dump_n)
             for (int32_t v = tid; v < n; v += MT)
-                if (s_bc[v] != 0.0) unsafeAtomicAdd(&a.bc[vo + v], s_bc[v]);
-        if (tid == 0 && s_ovf) atomicOr(a.status, (uint32_t)BC_DEV_SIGMA_OVERFLOW);
+                if (sh.bc[v] != 0.0) unsafeAtomicAdd(&a.bc[vo + v], sh.bc[v]);
+        if (tid == 0 && sh.ovf) atomicOr(a.status, (uint32_t)BC_DEV_SIGMA_OVERFLOW);
         __syncthreads();
     }
 }

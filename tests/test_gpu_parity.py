@@ -383,6 +383,19 @@ def test_many_graphs_one_launch(gpu_lib):
         assert rel_err(delta[i][lo:hi], dl) <= 1e-5
 
 
+def test_many_graphs_columns_from_memory(gpu_lib):
+    """Graphs whose arcs do not fit the workgroup's staged 16-bit columns
+    (K_300: 89 700 arcs; ER n=4096 degree 14: 57 400) read them from global
+    memory, in the same launch as graphs that fit."""
+    gs = [gg.complete(300), gg.er_plus_tree(4096, 12.0, 3), gg.path(600), gg.star(4096),
+          gg.watts_strogatz(3000, 6, 0.1, 5)]
+    say("many_graphs_wide", [g.col.size for g in gs])
+    want = np.concatenate([oracle.bc(g, threads=8) for g in gs])
+    with gpu_lib.BC(gs) as ctx:
+        ctx.run()
+        assert rel_err(ctx.read(), want) <= 1e-5
+
+
 def test_many_graphs_overflow(gpu_lib):
     gs = [gg.path(5), gg.grid(35, 35)]  # C(68,34) > 2^64 - 1 in the second graph
     say("many_overflow")
