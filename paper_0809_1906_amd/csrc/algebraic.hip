@@ -37,7 +37,7 @@
 // most deg(w) non-zero terms of at most 255.
 //
 // Data layout: A is a dense row-major BF16 [npad][M * npad] matrix (npad = n
-// rounded up to 256, the block's row count).  Planes are k-packed: plane[v / 8][b][v % 8], so each
+// rounded up to 256, a multiple of the block's row count).  Planes are k-packed: plane[v / 8][b][v % 8], so each
 // MFMA B-operand lane reads 16 contiguous bytes.  Every product is
 // C[w][b] = sum_v A[w][v] X[v][b] with rows = vertices and columns = sources;
 // in the 32x32 MFMA output the 32 lanes of each half-wave hold 32 consecutive
@@ -54,14 +54,15 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int GM = 256;  // rows (vertices) per block: 2 wave rows x 128
+constexpr int GM = 128;  // rows (vertices) per block: 2 wave rows x 64
 constexpr int GN = 128;  // columns (sources) per block: 2 wave columns x 64 (one bitmap word)
 constexpr int GK = 32;   // k (vertices) per pipeline stage
 constexpr int GT = 256;  // threads per block (4 waves, 2 x 2)
-constexpr int WM = 128;  // rows per wave: 4 MFMA row tiles of 32
+constexpr int WM = 64;   // rows per wave: 2 MFMA row tiles of 32
 constexpr int RT = WM / 32;
 constexpr int SA = GK + 8; // LDS row stride of the adjacency tile, in BF16 (padding against bank conflicts)
 constexpr int PB = 256;  // threads per block of the element-wise kernels
+constexpr int NPAD = 256; // n is padded to a multiple of this (of GM too)
 
 enum { EPI_ONLY = 0, EPI_FIRST = 1, EPI_MID = 2, EPI_LAST = 3 };
 
@@ -115,11 +116,11 @@ __device__ __forceinline__ int limbs_feeding(const unsigned long long *lvmax_l, 
 // ---- the product -------------------------------------------------------------------
 
 // One pipeline stage held in registers between its global loads and its LDS
-// stores: per thread 4 x 16 B of the adjacency tile (GM x GK) and 2 x 16 B of
+// stores: per thread GM/64 x 16 B of the adjacency tile (GM x GK) and 2 x 16 B of
 // each plane tile (GK x GN).
 template <int NP>
 struct Stage {
-    u32x4 a[4];
+    u32x4 a[GM / 64];
     u32x4 x[NP * 2];
 };
 
@@ -128,7 +129,7 @@ __device__ __forceinline__ void load_stage(const GemmArgs &g, const __bf16 *plan
                                            Stage<NP> &st) {
     const int row = tid >> 2, kq = tid & 3; // four threads read one row's 64 B
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < GM / 64; ++i)
         st.a[i] = *reinterpret_cast<const u32x4 *>(g.adj + (size_t)(w0 + row + 64 * i) * g.K + (size_t)kt * GK +
                                                    kq * 8);
     const int c = tid & (GN - 1), i0 = tid / GN; // k-group i0 and i0 + 2, column c
@@ -144,7 +145,7 @@ template <int NP>
 __device__ __forceinline__ void store_stage(__bf16 *sA, __bf16 *sX, int tid, const Stage<NP> &st) {
     const int row = tid >> 2, kq = tid & 3;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) *reinterpret_cast<u32x4 *>(sA + (row + 64 * i) * SA + kq * 8) = st.a[i];
+    for (int i = 0; i < GM / 64; ++i) *reinterpret_cast<u32x4 *>(sA + (row + 64 * i) * SA + kq * 8) = st.a[i];
     const int c = tid & (GN - 1), i0 = tid / GN;
 #pragma unroll
     for (int p = 0; p < NP; ++p)
@@ -153,7 +154,7 @@ __device__ __forceinline__ void store_stage(__bf16 *sA, __bf16 *sX, int tid, con
             *reinterpret_cast<u32x4 *>(sX + (((size_t)p * 4 + i0 + 2 * j) * GN + c) * 8) = st.x[p * 2 + j];
 }
 
-// Wave (wr, wc) multiplies rows [128 wr, 128 wr + 128) of the A tile by
+// Wave (wr, wc) multiplies rows [WM wr, WM wr + WM) of the A tile by
 // columns [64 wc, 64 wc + 64) of each plane tile.
 template <int NP>
 __device__ __forceinline__ void mma_stage(const __bf16 *sA, const __bf16 *sX, int lane, int wr, int wc,
@@ -208,8 +209,8 @@ template <int NP>
 constexpr int stages() { return NP == 1 ? 2 : 1; }
 
 // acc[w][b] = sum over k-tiles with a non-zero flag of A[w][k] X_p[k][b],
-// summed over the NP planes starting at `planes`, for the block's 256 rows and
-// 128 sources; wave (wr, wc) holds rows w0 + 128 wr + [0, 128) and sources
+// summed over the NP planes starting at `planes`, for the block's GM rows and
+// 128 sources; wave (wr, wc) holds rows w0 + WM wr + [0, WM) and sources
 // b0 + 64 wc + [0, 64).  The next stage's global loads are in flight (in
 // registers) during the current stage's products.  (Two register stages in
 // flight measured slower: the extra registers pushed the forward kernel into
@@ -527,7 +528,7 @@ bc_status algebraic_prepare(bc_ctx *ctx) {
     if (ctx->max_degree > 65792)
         return bc_fail(ctx, BC_ERR_UNSUPPORTED,
                        "algebraic form: a degree above 65792 breaks exact FP32 accumulation of 8-bit limbs");
-    a.npad = std::max(GM, (ctx->n + GM - 1) / GM * GM);
+    a.npad = std::max(NPAD, (ctx->n + NPAD - 1) / NPAD * NPAD);
     a.classes = ctx->weighted ? (int32_t)ctx->max_weight : 1;
     const size_t K = (size_t)a.classes * a.npad;
     const size_t adj_bytes = (size_t)a.npad * K * sizeof(__bf16);
