@@ -317,8 +317,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true", help="end with a 1 GiB device copy")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 (sources shard across "
-                                   "GPUs by design, but no multi-GPU path is built)"}))
+        print(json.dumps({"error": "one GPU only: --gpus must be 1 (sources shard across GPUs by design, "
+                                   "but no multi-GPU path is implemented)"}))
         sys.exit(2)
 
     import torch

@@ -14,7 +14,7 @@ def pytest_configure(config):
 
 @pytest.fixture(scope="session")
 def gpu_lib():
-    """The HIP library on a GPU machine; fails loudly when it is not built."""
+    """The HIP library on a machine with an MI355X; fails loudly when it is not built."""
     import torch
     if not torch.cuda.is_available():
         pytest.fail("GPU test run without a visible GPU")
