@@ -12,7 +12,11 @@ Contents
   cross.py   independent cross-oracles used to pin brandes.c:
              brute-force path enumeration from the definitions (Sec. 1.1),
              all-pairs counts + Algorithm 2 (Sec. 4.2.1), and the corrected
-             dense algebraic method (Sec. 3.1) in exact arithmetic.
+             dense algebraic method (Sec. 3.1, and Sec. 3.2 per weight class)
+             in exact arithmetic.
+  sampled.py Algorithm 1 (Sec. 4.1.1), the sampled forward, distances only:
+             limited searches from a distinguished set, all-pairs distances
+             on the auxiliary graph, and the final minimum.
 
 Every pin is a ``-m "not gpu"`` test under tests/.  No function here is
 "parity unpinned".
