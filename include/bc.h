@@ -274,6 +274,30 @@ bc_status bc_read_sssp(bc_ctx *ctx, const int32_t *sources, int32_t count,
 #define BC_ALL_PAIRS_MAX_N 32768
 bc_status bc_all_pairs(bc_ctx *ctx, double *bc_out, bc_mem mem);
 
+/*
+ * Distances by Algorithm 1 (Sec. 4.1.1), the sampled forward for unweighted
+ * graphs.  The distinguished set S is `sources` (each once) followed by
+ * `sample` (the caller's random sample; ids already in S are skipped).  From
+ * every x in S a `limit`-limited breadth-first search gives d'(x, v)
+ * (limit 0 = ceil(sqrt(n))); the weighted graph H on S takes the edge weights
+ * d'(x, y); all-pairs distances D_H of H follow; and for each source,
+ * dist_out[i][v] = min over x in S of D_H(s_i, x) + d'(x, v).  Every value is
+ * the length of a real walk, so it is never below d(s_i, v); it equals it when
+ * each shortest path meets S at least once in every `limit` consecutive hops,
+ * which a uniform sample of about sqrt(n) ln n vertices does with high
+ * probability at limit sqrt(n).  -1 where no walk was found.  The number of
+ * shortest paths (the paper's last step, a count of minimising vertices) is
+ * not a path count and is not computed.
+ *   sources, sample   host arrays of vertex ids in [0, n) (caller numbering)
+ *   dist_out          host, count * n int32, row i for sources[i]
+ * Synchronises.  Errors: BC_ERR_INVALID_ARG (bad id, count, limit above 65534),
+ * BC_ERR_UNSUPPORTED (weighted graph, context of many graphs, |S| above
+ * BC_SAMPLED_MAX_S), BC_ERR_NOMEM, BC_ERR_DEVICE, BC_ERR_STATE.
+ */
+#define BC_SAMPLED_MAX_S 4096
+bc_status bc_sampled_distances(bc_ctx *ctx, const int32_t *sources, int32_t count, const int32_t *sample,
+                               int32_t nsample, int32_t limit, int32_t *dist_out);
+
 typedef struct {
     int32_t n;           /* vertices */
     int64_t m;           /* undirected edges = nnz / 2 */

@@ -41,6 +41,7 @@ FORMS = {"auto": BC_FORM_AUTO, "plain": BC_FORM_PLAIN_FP64, "sparse": BC_FORM_SP
 
 BC_ALL_PAIRS_MAX_N = 32768
 BC_ALGEBRAIC_MAX_WEIGHT = 8
+BC_SAMPLED_MAX_S = 4096
 BC_TUNE_DEFAULT = 0
 BC_TUNE_MEASURED = 1
 BC_TUNE_CACHED = 2
@@ -88,6 +89,8 @@ SIGNATURES = {
     "bc_reset": (ctypes.c_int, [ctypes.c_void_p]),
     "bc_read_edges": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
     "bc_all_pairs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
+    "bc_sampled_distances": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                            ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]),
     "bc_read_sssp": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_void_p]),
     "bc_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(bc_info)]),
@@ -170,6 +173,10 @@ def bc_read_edges(ctx, out_ptr, mem: int) -> None:
 
 def bc_all_pairs(ctx, out_ptr, mem: int) -> None:
     _check(load().bc_all_pairs(ctx, out_ptr, mem), ctx)
+
+
+def bc_sampled_distances(ctx, sources_ptr, count: int, sample_ptr, nsample: int, limit: int, out_ptr) -> None:
+    _check(load().bc_sampled_distances(ctx, sources_ptr, count, sample_ptr, nsample, limit, out_ptr), ctx)
 
 
 def bc_read_sssp(ctx, sources_ptr, count: int, dist_ptr, sigma_ptr, delta_ptr) -> None:
@@ -336,6 +343,17 @@ class BC:
         out = np.zeros(max(self.n, 1), dtype=np.float64)
         bc_all_pairs(self._ctx, out.ctypes.data, BC_MEM_HOST)
         return out[: self.n]
+
+    def sampled_distances(self, sources, sample, limit: int = 0) -> np.ndarray:
+        """Distances from each source by Algorithm 1 (Sec. 4.1.1) with the
+        distinguished set sources + sample and the given search limit (0 =
+        ceil(sqrt(n))): int32 [len(sources), n], -1 where no walk was found."""
+        s = np.ascontiguousarray(sources, dtype=np.int32)
+        x = np.ascontiguousarray(sample, dtype=np.int32)
+        out = np.zeros((max(s.size, 1), max(self.n, 1)), np.int32)
+        bc_sampled_distances(self._ctx, s.ctypes.data if s.size else None, int(s.size),
+                             x.ctypes.data if x.size else None, int(x.size), int(limit), out.ctypes.data)
+        return out[: s.size, : self.n]
 
     def read_device(self):
         out = self.torch.empty(max(self.n, 1), dtype=self.torch.float64, device=f"cuda:{self.device}")
