@@ -28,6 +28,11 @@ Other workloads (same JSON schema; used for profiles and design figures):
            algebraic form's forward fills all-pairs distances and counts, one
            kernel sums the masked triple terms), against Brandes in the same
            context
+  sampled16
+           RMAT-16, 1024 sources: distances by Algorithm 1 (Sec. 4.1.1) with a
+           uniform sample of ceil(sqrt(n) ln n) vertices and search limit
+           ceil(sqrt(n)), output left in HBM, against the exact forward and
+           backward of the hybrid form for the same sources
 
 Prints one JSON line.  Profiling runs use --sources N (a bounded prefix of the
 sources) and --calibrate-copy (a 1 GiB device-to-device copy at the end, the
@@ -73,6 +78,10 @@ WORKLOADS = {
     "er16384w4": {"form": "algebraic", "batch": 512, "compare": [("plain", 0)],
                   "desc": "er16384w4: Erdos-Renyi n=16384, average degree 256, largest component, weights "
                           "U{1..4}; exact all-source BC"},
+    "sampled16": {"form": "hybrid", "batch": 256, "compare": [],
+                  "desc": "sampled16: RMAT scale 16 (as rmat16), 1024 sources and a uniform sample of "
+                          "ceil(sqrt(n) ln n) = 2325 vertices, search limit ceil(sqrt(n)) = 217; distances by "
+                          "Algorithm 1"},
     "allpairs16384": {"form": "algebraic", "batch": 512, "compare": [],
                       "desc": "allpairs16384: Erdos-Renyi n=16384, average degree 256, largest component; BC "
                               "over every ordered pair by Algorithm 2 from all-pairs distances and counts"},
@@ -85,6 +94,7 @@ DTYPES = {
     "algebraic": "bf16 MFMA products of 8-bit count limbs with f32 accumulate, u64 counts, f32 dependency "
                  "state, f64 sums",
     "many": "u64 counts, f32 dependency state, f64 sums",
+    "sampled": "int32 distances (u16 limited-search distances, u64 frontier bitmaps)",
     "allpairs": "u64 counts and int32 distances (forward by bf16 MFMA products of 8-bit limbs), u32 mask "
                 "arithmetic, f64 terms and sums",
 }
@@ -147,6 +157,11 @@ def load_workload(name, sources):
         g, src = gg.rmat20w()
     elif name == "allpairs16384":
         g, src = gg.er16384(), None
+    elif name == "sampled16":
+        g, src, smp = gg.rmat16_sampled()
+        log(f"graph {name} n={g.n} m={g.m} sources={src.size} sample={smp.size} gen {time.perf_counter() - t0:.1f}s")
+        return {"graph": g, "n": g.n, "m": g.m, "src": src, "sample": smp, "S": int(src.size),
+                "work": float(src.size) * g.m}
     else:
         g = getattr(gg, name)()
         src = None
@@ -299,6 +314,112 @@ def run_allpairs(args, spec, wl, bcgpu, torch):
     }
 
 
+def cpu_baseline_sampled(wl, k: int):
+    """The oracle's Algorithm 1 steps on a bounded sample, scaled to the whole
+    job: limited searches from 160 evenly spaced distinguished vertices
+    (scaled by |S| / 160), Floyd-Warshall on a 1024-vertex H (data-independent
+    cost, scaled by (|S| / 1024)^3), and the final minimum for 32 sources over
+    those 160 rows (scaled by |S| / 160 and sources / 32).  numpy, one
+    thread."""
+    from oracle import sampled
+    g, src, smp = wl["graph"], wl["src"], wl["sample"]
+    S = np.array(list(dict.fromkeys([int(x) for x in src] + [int(x) for x in smp])), np.int64)
+    ns, nb, nf, nm = S.size, 160, 1024, 32
+    pick = S[np.linspace(0, ns - 1, nb).astype(np.int64)]
+    t0 = time.perf_counter()
+    Dp = np.stack([sampled.limited_bfs(g, int(x), k) for x in pick])
+    t_bfs = (time.perf_counter() - t0) * ns / nb
+    H = np.random.default_rng(1).integers(1, 50, size=(nf, nf)).astype(np.int64)
+    np.fill_diagonal(H, 0)
+    t0 = time.perf_counter()
+    DH = sampled.floyd_warshall(H)
+    t_fw = (time.perf_counter() - t0) * (ns / nf) ** 3
+    t0 = time.perf_counter()
+    for r in range(nm):
+        np.min(DH[r, :nb][:, None] + Dp, axis=0)
+    t_min = (time.perf_counter() - t0) * (ns / nb) * (src.size / nm)
+    t = t_bfs + t_fw + t_min
+    return {"value": src.size * g.m / t, "unit": "TEPS", "cores": 1, "kind": "oracle",
+            "sample": f"limited searches from {nb} of {ns} distinguished vertices ({t_bfs:.1f} s scaled), "
+                      f"Floyd-Warshall on a {nf}-vertex H ({t_fw:.1f} s scaled by (|S|/{nf})^3), final minimum "
+                      f"for {nm} of {src.size} sources over {nb} rows ({t_min:.1f} s scaled); numpy, one thread; "
+                      f"estimated whole job {t:.1f} s"}
+
+
+def run_sampled(args, spec, wl, bcgpu, torch):
+    """One step = one bc_sampled_distances call with the output in HBM:
+    limited searches from S, H, Floyd-Warshall, the final minimum
+    (Algorithm 1, Sec. 4.1.1)."""
+    g, n, m, src, smp = wl["graph"], wl["n"], wl["m"], wl["src"], wl["sample"]
+    k = int(np.ceil(np.sqrt(n)))
+    ns = len(set(src.tolist()) | set(smp.tolist()))
+    sp = (ns + 63) // 64 * 64
+    ctx = bcgpu.BC(g, form=args.form or spec["form"], batch=spec["batch"], timing=True)
+    out = torch.empty((src.size, n), dtype=torch.int32, device="cuda:0")
+    for i in range(args.warmup):
+        ctx.sampled_distances(src, smp, k, out=out)
+        log(f"sampled warmup {i} done")
+    # spot check against exact distances (well inside the w.h.p. regime: k is past the diameter)
+    pick = src[:: max(1, src.size // 6)][:6]
+    dist, _, _ = ctx.sssp(pick)
+    got = out.cpu().numpy()
+    rows = [int(np.where(src == p)[0][0]) for p in pick]
+    exact_ok = bool(np.array_equal(got[rows], dist))
+    log(f"sampled vs exact distances on {len(pick)} sources: {'equal' if exact_ok else 'DIFFERENT'}")
+    names = ("limited_bfs", "floyd_warshall", "sampled_min")
+    before = {k_: ctx.timing(k_) for k_ in names}
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for i in range(args.steps):
+        ctx.sampled_distances(src, smp, k, out=out)
+        log(f"sampled step {i} done")
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / args.steps
+    phase = {k_: (ctx.timing(k_)[0] - before[k_][0]) / args.steps for k_ in names}
+    log("phase ms per step:", phase)
+    # the final minimum is a min-plus product: 2 int32 ops per (source, x, v)
+    ops = 2.0 * src.size * ns * n
+    ach = ops / (phase["sampled_min"] * 1e-3) / 1e12
+    roof = {"kernel": "sampled_min", "avg_launch_ms": phase["sampled_min"], "launches": args.steps,
+            "bound": "alu", "achieved": ach, "peak": VALU_INT32_PEAK_TOPS, "unit": "Top/s",
+            "frac": ach / VALU_INT32_PEAK_TOPS, "traffic": None, "alg_ops_per_launch": ops,
+            "note": "sources x |S| x n terms x 2 int32 ops (add, min) per launch; peak = 256 CUs x 64 lanes x "
+                    "2.4 GHz"}
+    compare = {}
+    if not args.no_compare:
+        ctx.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.run(src)
+        ctx.read()
+        bdt = time.perf_counter() - t0
+        compare["exact_brandes_same_sources"] = {"form": ctx.info().form, "value": src.size * m / bdt,
+                                                 "ms_per_step": bdt * 1e3}
+        log(f"exact forward+backward for the same sources {bdt * 1e3:.1f} ms")
+    ctx.close()
+    cpu = None if args.no_cpu_baseline else cpu_baseline_sampled(wl, k)
+    return {
+        "metric": "sampled-forward distances by Algorithm 1 on RMAT-16, sources·m/s",
+        "value": src.size * m / dt,
+        "unit": "TEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPES["sampled"],
+        "data": "synthetic",
+        "config": {"workload": spec["desc"], "n": n, "m": m, "sources": int(src.size), "distinguished": ns,
+                   "padded": sp, "limit": k, "exact_on_spot_check": exact_ok},
+        "compare": compare,
+        "phase_ms_per_step": phase,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -336,6 +457,9 @@ def main():
     wl = load_workload(args.workload, args.sources)
     if args.workload == "allpairs16384":
         print(json.dumps(run_allpairs(args, spec, wl, bcgpu, torch)), flush=True)
+        return
+    if args.workload == "sampled16":
+        print(json.dumps(run_sampled(args, spec, wl, bcgpu, torch)), flush=True)
         return
     src, work = wl["src"], wl["work"]
 

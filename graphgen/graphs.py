@@ -422,3 +422,13 @@ def rmat20w():
     g = rmat(20, 16, seed, name="rmat20")
     g = with_uniform_weights(g, seed, 1, 255)
     return g, sample_sources(g.n, 4096, seed)
+
+
+def rmat16_sampled(count: int = 1024):
+    """(graph, sources, sample) for the sampled forward of Sec. 4.1.1 on
+    RMAT-16: ``count`` sources and a uniform sample of ceil(sqrt(n) ln n)
+    vertices, both without replacement, drawn independently."""
+    g = rmat16()
+    seed = workload_seed(6)
+    size = int(np.ceil(np.sqrt(g.n) * np.log(g.n)))
+    return g, sample_sources(g.n, count, seed), sample_sources(g.n, size, seed + 1)

@@ -289,14 +289,16 @@ bc_status bc_all_pairs(bc_ctx *ctx, double *bc_out, bc_mem mem);
  * shortest paths (the paper's last step, a count of minimising vertices) is
  * not a path count and is not computed.
  *   sources, sample   host arrays of vertex ids in [0, n) (caller numbering)
- *   dist_out          host, count * n int32, row i for sources[i]
+ *   dist_out          count * n int32, row i for sources[i], in host or device
+ *                     memory as `mem` says (device: written on the context's
+ *                     stream, ordered before the call returns)
  * Synchronises.  Errors: BC_ERR_INVALID_ARG (bad id, count, limit above 65534),
  * BC_ERR_UNSUPPORTED (weighted graph, context of many graphs, |S| above
  * BC_SAMPLED_MAX_S), BC_ERR_NOMEM, BC_ERR_DEVICE, BC_ERR_STATE.
  */
 #define BC_SAMPLED_MAX_S 4096
 bc_status bc_sampled_distances(bc_ctx *ctx, const int32_t *sources, int32_t count, const int32_t *sample,
-                               int32_t nsample, int32_t limit, int32_t *dist_out);
+                               int32_t nsample, int32_t limit, int32_t *dist_out, bc_mem mem);
 
 typedef struct {
     int32_t n;           /* vertices */

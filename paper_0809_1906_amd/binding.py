@@ -90,7 +90,7 @@ SIGNATURES = {
     "bc_read_edges": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
     "bc_all_pairs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
     "bc_sampled_distances": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
-                                            ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]),
+                                            ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int]),
     "bc_read_sssp": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_void_p]),
     "bc_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(bc_info)]),
@@ -175,8 +175,9 @@ def bc_all_pairs(ctx, out_ptr, mem: int) -> None:
     _check(load().bc_all_pairs(ctx, out_ptr, mem), ctx)
 
 
-def bc_sampled_distances(ctx, sources_ptr, count: int, sample_ptr, nsample: int, limit: int, out_ptr) -> None:
-    _check(load().bc_sampled_distances(ctx, sources_ptr, count, sample_ptr, nsample, limit, out_ptr), ctx)
+def bc_sampled_distances(ctx, sources_ptr, count: int, sample_ptr, nsample: int, limit: int, out_ptr,
+                         mem: int) -> None:
+    _check(load().bc_sampled_distances(ctx, sources_ptr, count, sample_ptr, nsample, limit, out_ptr, mem), ctx)
 
 
 def bc_read_sssp(ctx, sources_ptr, count: int, dist_ptr, sigma_ptr, delta_ptr) -> None:
@@ -344,16 +345,26 @@ class BC:
         bc_all_pairs(self._ctx, out.ctypes.data, BC_MEM_HOST)
         return out[: self.n]
 
-    def sampled_distances(self, sources, sample, limit: int = 0) -> np.ndarray:
+    def sampled_distances(self, sources, sample, limit: int = 0, out=None):
         """Distances from each source by Algorithm 1 (Sec. 4.1.1) with the
         distinguished set sources + sample and the given search limit (0 =
-        ceil(sqrt(n))): int32 [len(sources), n], -1 where no walk was found."""
+        ceil(sqrt(n))): int32 [len(sources), n], -1 where no walk was found.
+        With `out` (an int32 device tensor of that shape) the rows are written
+        there and `out` is returned; otherwise a host array."""
         s = np.ascontiguousarray(sources, dtype=np.int32)
         x = np.ascontiguousarray(sample, dtype=np.int32)
-        out = np.zeros((max(s.size, 1), max(self.n, 1)), np.int32)
-        bc_sampled_distances(self._ctx, s.ctypes.data if s.size else None, int(s.size),
-                             x.ctypes.data if x.size else None, int(x.size), int(limit), out.ctypes.data)
-        return out[: s.size, : self.n]
+        sp = s.ctypes.data if s.size else None
+        xp = x.ctypes.data if x.size else None
+        if out is not None:
+            if (not out.is_cuda or out.dtype != self.torch.int32 or not out.is_contiguous()
+                    or tuple(out.shape) != (s.size, self.n)):
+                raise ValueError("out must be a contiguous int32 device tensor of shape (len(sources), n)")
+            bc_sampled_distances(self._ctx, sp, int(s.size), xp, int(x.size), int(limit), out.data_ptr(),
+                                 BC_MEM_DEVICE)
+            return out
+        res = np.zeros((max(s.size, 1), max(self.n, 1)), np.int32)
+        bc_sampled_distances(self._ctx, sp, int(s.size), xp, int(x.size), int(limit), res.ctypes.data, BC_MEM_HOST)
+        return res[: s.size, : self.n]
 
     def read_device(self):
         out = self.torch.empty(max(self.n, 1), dtype=self.torch.float64, device=f"cuda:{self.device}")

@@ -782,20 +782,21 @@ bc_status bc_all_pairs(bc_ctx *ctx, double *bc_out, bc_mem mem) {
 }
 
 bc_status bc_sampled_distances(bc_ctx *ctx, const int32_t *sources, int32_t count, const int32_t *sample,
-                               int32_t nsample, int32_t limit, int32_t *dist_out) {
+                               int32_t nsample, int32_t limit, int32_t *dist_out, bc_mem mem) {
     if (!ctx) return BC_ERR_INVALID_ARG;
     bc_status s = check_usable(ctx);
     if (s != BC_OK) return s;
     if (ctx->many) return bc_fail(ctx, BC_ERR_UNSUPPORTED, "sampled forward: not for a context of many graphs");
     if (ctx->weighted) return bc_fail(ctx, BC_ERR_UNSUPPORTED, "sampled forward: unweighted graphs only");
-    if (count < 0 || nsample < 0 || limit < 0 || (count > 0 && (!sources || !dist_out)) || (nsample > 0 && !sample))
+    if (count < 0 || nsample < 0 || limit < 0 || (count > 0 && (!sources || !dist_out)) || (nsample > 0 && !sample) ||
+        (mem != BC_MEM_HOST && mem != BC_MEM_DEVICE))
         return bc_fail(ctx, BC_ERR_INVALID_ARG, "sampled forward: bad arguments");
     for (int32_t i = 0; i < count; ++i)
         if (sources[i] < 0 || sources[i] >= ctx->n) return bc_fail(ctx, BC_ERR_INVALID_ARG, "source id out of range");
     for (int32_t i = 0; i < nsample; ++i)
         if (sample[i] < 0 || sample[i] >= ctx->n) return bc_fail(ctx, BC_ERR_INVALID_ARG, "sample id out of range");
     if (count == 0 || ctx->n == 0) return BC_OK;
-    return sampled_distances(ctx, sources, count, sample, nsample, limit, dist_out);
+    return sampled_distances(ctx, sources, count, sample, nsample, limit, dist_out, mem == BC_MEM_DEVICE);
 }
 
 bc_status bc_get_info(const bc_ctx *ctx, bc_info *out) {

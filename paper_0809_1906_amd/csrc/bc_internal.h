@@ -266,10 +266,10 @@ bc_status sparse_dump(bc_ctx *ctx, const int32_t *d_sources, int32_t count,
                       int32_t *dist_dump, uint64_t *sigma_dump, double *delta_dump);
 
 // ---- sampled forward (sampled.hip) -------------------------------------------------
-// Distances by Algorithm 1; host arrays, ids already validated; writes
-// count * n caller-order rows to h_out.
+// Distances by Algorithm 1; host id arrays, already validated; writes
+// count * n caller-order rows to out (host or device memory as out_on_device).
 bc_status sampled_distances(bc_ctx *ctx, const int32_t *h_sources, int32_t count, const int32_t *h_sample,
-                            int32_t nsample, int32_t limit, int32_t *h_out);
+                            int32_t nsample, int32_t limit, int32_t *out, bool out_on_device);
 
 // ---- all pairs (allpairs.hip) ---------------------------------------------------
 // BC of every vertex (internal order) by Algorithm 2 from all-pairs D and

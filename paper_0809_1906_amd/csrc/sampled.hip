@@ -9,12 +9,18 @@
 // Step 6 (counting minimising vertices) does not count shortest paths and is
 // not computed.
 //
-// Layout: d' is uint16 [Sp][n] (Sp = |S| rounded up to 64; DINF = no path
-// within k), H and D_H int32 [Sp][Sp] (HINF = no path; HINF + HINF fits
-// int32).  The limited searches run 64 sources at a time as one bitmap word per
-// vertex: level L pulls the frontier words of each vertex's neighbours.  The
-// final minimum gives each block four sources and 256 vertices; the four rows
-// of D_H sit in LDS and each d' row is read coalesced across the block.
+// Layout (sp = |S| rounded up to 64, W = sp / 64 bitmap words):
+//   d'    uint16 dT[v][sp], vertex-major: dT[v][x] = d'(S_x, v), DINF = none
+//   bits  frontier, next frontier and visited sets as uint64 [v][W]: bit x of
+//         vertex v's words is row x of S
+//   H     int32 [sp][sp], HINF = no path (HINF + HINF fits int32); D_H in place
+// The limited searches advance every row of S together, one launch per level:
+// a wave takes a chunk of at most CH arcs of one vertex, lane w pulls word w of
+// each neighbour's frontier; vertices with more than CH arcs leave one partial
+// OR per chunk, merged by a second launch.  Floyd-Warshall runs in 64 x 64
+// tiles: per pivot block, the diagonal tile, then the column strip and then
+// the whole (symmetric) matrix as min-plus products.  Step 5 is the min-plus
+// product of the sources' rows of D_H with d', in LDS-staged 128 x 128 tiles.
 #include "bc_internal.h"
 
 #include <algorithm>
@@ -26,7 +32,9 @@ namespace {
 constexpr int SB = 256;
 constexpr uint16_t DINF = 0xFFFF;
 constexpr int32_t HINF = 1 << 29;
-constexpr int IT = 4; // sources per block of the final minimum
+constexpr int CH = 128; // arcs per chunk of a search level
+constexpr int TB = 64;  // Floyd-Warshall tile
+constexpr int KC = 32;  // k step of the min-plus products
 
 inline unsigned blocks_for(size_t count) { return (unsigned)((count + SB - 1) / SB); }
 
@@ -35,111 +43,342 @@ __global__ __launch_bounds__(SB) void k_fill_u16(uint16_t *__restrict__ x, size_
     if (i < count) x[i] = value;
 }
 
-// Start of a 64-source word: clear the bitmaps (the sources follow).
-__global__ __launch_bounds__(SB) void k_lb_clear(int32_t n, uint64_t *__restrict__ front,
-                                                 uint64_t *__restrict__ visited) {
-    const int32_t v = blockIdx.x * SB + threadIdx.x;
-    if (v < n) {
-        front[v] = 0;
-        visited[v] = 0;
+// Bits of word w that are rows of S.
+__device__ inline uint64_t word_rows(int32_t w, int32_t ns) {
+    const int32_t r = ns - 64 * w;
+    return r >= 64 ? ~0ull : r <= 0 ? 0ull : ((1ull << r) - 1);
+}
+
+// Level 0: row i of S starts at its own vertex (S has no repeats, so each
+// vertex's words hold at most one bit here; the bitmaps were cleared).
+__global__ __launch_bounds__(SB) void k_ls_sources(int32_t ns, const int32_t *__restrict__ S, int32_t W, int32_t sp,
+                                                   uint64_t *__restrict__ F, uint64_t *__restrict__ V,
+                                                   uint16_t *__restrict__ dT) {
+    const int32_t i = blockIdx.x * SB + threadIdx.x;
+    if (i >= ns) return;
+    const int32_t v = S[i];
+    const uint64_t bit = 1ull << (i & 63);
+    F[(size_t)v * W + (i >> 6)] = bit;
+    V[(size_t)v * W + (i >> 6)] = bit;
+    dT[(size_t)v * sp + i] = 0;
+}
+
+// New bits of vertex v at level L: record them and set its next-frontier word.
+__device__ inline void ls_settle(int32_t v, int lane, int32_t W, int32_t sp, uint64_t acc, uint64_t vis,
+                                 uint64_t rows, int32_t L, uint64_t *__restrict__ N, uint64_t *__restrict__ V,
+                                 uint16_t *__restrict__ dT, uint32_t *__restrict__ found) {
+    const uint64_t nw = acc & ~vis & rows;
+    if (lane < W) {
+        N[(size_t)v * W + lane] = nw;
+        if (nw) {
+            V[(size_t)v * W + lane] = vis | nw;
+            uint16_t *row = dT + (size_t)v * sp + 64 * lane;
+            for (uint64_t m = nw; m; m &= m - 1) row[__builtin_ctzll(m)] = (uint16_t)L;
+        }
     }
+    if (__builtin_amdgcn_ballot_w64(nw != 0) != 0 && lane == 0) found[L] = 1;
 }
 
-// The word's sources at level 0.
-__global__ __launch_bounds__(64) void k_lb_sources(int32_t n, const int32_t *__restrict__ S, int32_t base,
-                                                   int32_t cnt, uint64_t *__restrict__ front,
-                                                   uint64_t *__restrict__ visited, uint16_t *__restrict__ dp) {
-    const int b = threadIdx.x;
-    if (b >= cnt) return;
-    const int32_t x = S[base + b];
-    atomicOr((unsigned long long *)&front[x], 1ull << b);
-    atomicOr((unsigned long long *)&visited[x], 1ull << b);
-    dp[(size_t)(base + b) * n + x] = 0;
-}
-
-// Level L of the limited searches of one word: every vertex not yet reached
-// by all of the word's sources pulls its neighbours' frontier bits.
-__global__ __launch_bounds__(SB) void k_lb_level(int32_t n, const int32_t *__restrict__ rp,
-                                                 const int32_t *__restrict__ col, uint64_t full, int32_t base,
-                                                 int32_t L, const uint64_t *__restrict__ front,
-                                                 uint64_t *__restrict__ next, uint64_t *__restrict__ visited,
-                                                 uint16_t *__restrict__ dp, uint32_t *__restrict__ found) {
-    const int32_t v = blockIdx.x * SB + threadIdx.x;
-    uint64_t nw = 0;
-    if (v < n) {
-        const uint64_t vis = visited[v];
-        if (vis != full) {
-            uint64_t acc = 0;
-            for (int32_t e = rp[v]; e < rp[v + 1]; ++e) acc |= front[col[e]];
-            nw = acc & ~vis & full;
-            if (nw) {
-                visited[v] = vis | nw;
-                for (uint64_t m = nw; m; m &= m - 1) dp[(size_t)(base + __builtin_ctzll(m)) * n + v] = (uint16_t)L;
+// Level L: one wave per chunk (v, first arc); chunks below nsplit belong to
+// vertices with more than CH arcs and leave their OR in P.
+__global__ __launch_bounds__(SB) void k_ls_level(int32_t nchunks, int32_t nsplit, const int2 *__restrict__ chunks,
+                                                 const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                                 int32_t W, int32_t ns, int32_t sp, int32_t L,
+                                                 const uint64_t *__restrict__ F, uint64_t *__restrict__ N,
+                                                 uint64_t *__restrict__ V, uint64_t *__restrict__ P,
+                                                 uint16_t *__restrict__ dT, uint32_t *__restrict__ found) {
+    const int lane = threadIdx.x & 63;
+    const int32_t c = __builtin_amdgcn_readfirstlane(blockIdx.x * (SB / 64) + (threadIdx.x >> 6));
+    if (c >= nchunks) return;
+    const int2 ch = chunks[c];
+    const int32_t v = ch.x;
+    const uint64_t rows = word_rows(lane, ns);
+    const uint64_t vis = lane < W ? V[(size_t)v * W + lane] : 0;
+    uint64_t acc = 0;
+    if (__builtin_amdgcn_ballot_w64(vis != rows) != 0) {
+        const int32_t e1 = min(ch.y + CH, rp[v + 1]);
+        const uint64_t *Fl = F + lane;
+        int32_t e = ch.y;
+        for (; e + 8 <= e1; e += 8) {
+            int32_t u[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) u[q] = col[e + q];
+            if (lane < W) {
+                uint64_t a = 0;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) a |= Fl[(size_t)u[q] * W];
+                acc |= a;
             }
         }
-        next[v] = nw;
+        for (; e < e1; ++e) {
+            const int32_t u = col[e];
+            if (lane < W) acc |= Fl[(size_t)u * W];
+        }
     }
-    if (__any(nw != 0) && (threadIdx.x & 63) == 0) found[L] = 1;
+    if (c < nsplit) {
+        if (lane < W) P[(size_t)c * W + lane] = acc;
+        return;
+    }
+    ls_settle(v, lane, W, sp, acc, vis, rows, L, N, V, dT, found);
 }
 
-// Step 3: H[i][j] = d'(S_i, S_j), 0 on the diagonal, HINF where no path was
-// found and in the padding.
-__global__ __launch_bounds__(SB) void k_build_h(int32_t n, int32_t ns, int32_t sp, const int32_t *__restrict__ S,
-                                                const uint16_t *__restrict__ dp, int32_t *__restrict__ H) {
+// Level L for the split vertices: OR of their chunks' partial results.
+__global__ __launch_bounds__(SB) void k_ls_finish(int32_t nsv, const int32_t *__restrict__ sv,
+                                                  const int32_t *__restrict__ sc, int32_t W, int32_t ns, int32_t sp,
+                                                  int32_t L, const uint64_t *__restrict__ P, uint64_t *__restrict__ N,
+                                                  uint64_t *__restrict__ V, uint16_t *__restrict__ dT,
+                                                  uint32_t *__restrict__ found) {
+    const int lane = threadIdx.x & 63;
+    const int32_t j = __builtin_amdgcn_readfirstlane(blockIdx.x * (SB / 64) + (threadIdx.x >> 6));
+    if (j >= nsv) return;
+    const int32_t v = sv[j];
+    uint64_t acc = 0;
+    if (lane < W)
+        for (int32_t c = sc[j]; c < sc[j + 1]; ++c) acc |= P[(size_t)c * W + lane];
+    const uint64_t vis = lane < W ? V[(size_t)v * W + lane] : 0;
+    ls_settle(v, lane, W, sp, acc, vis, word_rows(lane, ns), L, N, V, dT, found);
+}
+
+// Step 3: H[j][i] = d'(S_i, S_j) = dT[S_j][i] (symmetric: the graph is
+// undirected); 0 on the diagonal, HINF where no path was found and in the
+// padding.
+__global__ __launch_bounds__(SB) void k_build_h(int32_t ns, int32_t sp, const int32_t *__restrict__ S,
+                                                const uint16_t *__restrict__ dT, int32_t *__restrict__ H) {
     const size_t id = (size_t)blockIdx.x * SB + threadIdx.x;
     if (id >= (size_t)sp * sp) return;
-    const int32_t i = (int32_t)(id / sp), j = (int32_t)(id % sp);
+    const int32_t j = (int32_t)(id / sp), i = (int32_t)(id % sp);
     int32_t h = HINF;
     if (i == j) h = 0;
     else if (i < ns && j < ns) {
-        const uint16_t d = dp[(size_t)i * n + S[j]];
+        const uint16_t d = dT[(size_t)S[j] * sp + i];
         h = d == DINF ? HINF : (int32_t)d;
     }
     H[id] = h;
 }
 
-// Step 4, pivot k: H[i][j] = min(H[i][j], H[i][k] + H[k][j]).  Row and
-// column k do not change in this pass (H[k][k] = 0), so it runs in place.
-__global__ __launch_bounds__(SB) void k_fw(int32_t sp, int32_t k, int32_t *__restrict__ H) {
-    const size_t id = (size_t)blockIdx.x * SB + threadIdx.x;
-    if (id >= (size_t)sp * sp) return;
-    const int32_t i = (int32_t)(id / sp), j = (int32_t)(id % sp);
-    const int32_t via = H[(size_t)i * sp + k] + H[(size_t)k * sp + j];
-    if (via < H[id]) H[id] = via;
+// Step 4 in 64 x 64 tiles, rounds r = 0 .. sp/64 - 1 over the pivot blocks.
+// Every step only lowers an entry to the length of some walk, and every
+// entry ends at the shortest one, so each phase may see entries of a tile
+// before or after another phase's update of the same values.
+//
+// Phase 1: the diagonal tile (r, r) closed on its own: repeated min-plus
+// squaring of the tile (diagonal 0, so k squarings give the shortest walks of
+// at most 2^k edges; 6 cover every simple path of 64 vertices), stopping once
+// a squaring changes nothing.  The tile is in LDS s[64][TP] and in c (thread
+// t: rows 4 (t >> 4) .., columns 4 (t & 15) ..); both hold the result.
+constexpr int TP = TB + 4; // LDS pitch of a closed tile (16-byte aligned rows)
+__device__ void close_tile(int32_t *s, int32_t (&c)[4][4]) {
+    const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+    for (int it = 0; it < 6; ++it) {
+        int32_t nc[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) nc[i][j] = c[i][j];
+        for (int k = 0; k < TB; k += 2) {
+            int2 a[4];
+            int4 b0 = *(const int4 *)&s[k * TP + tx * 4], b1 = *(const int4 *)&s[(k + 1) * TP + tx * 4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) a[q] = *(const int2 *)&s[(ty * 4 + q) * TP + k];
+            const int32_t r0[4] = {b0.x, b0.y, b0.z, b0.w}, r1[4] = {b1.x, b1.y, b1.z, b1.w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) nc[i][j] = min(min(nc[i][j], a[i].x + r0[j]), a[i].y + r1[j]);
+        }
+        int changed = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) changed |= nc[i][j] != c[i][j];
+        __syncthreads(); // every read of this squaring is done
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                c[i][j] = nc[i][j];
+                s[(ty * 4 + i) * TP + tx * 4 + j] = nc[i][j];
+            }
+        if (!__syncthreads_or(changed)) break;
+    }
 }
 
-// Step 5: out[r][v] = min over x of D_H(r, x) + d'(x, v) for the requested
-// sources r (rows 0 .. count-1 of S); -1 where no walk was found.
-__global__ __launch_bounds__(SB) void k_final(int32_t n, int32_t ns, int32_t sp, int32_t count,
-                                              const int32_t *__restrict__ DH, const uint16_t *__restrict__ dp,
-                                              int32_t *__restrict__ out) {
-    extern __shared__ int32_t s_h[]; // [IT][sp]
-    const int32_t r0 = blockIdx.y * IT;
-    for (int32_t i = threadIdx.x; i < IT * sp; i += SB) {
-        const int32_t t = i / sp, x = i % sp;
-        s_h[i] = r0 + t < count ? DH[(size_t)(r0 + t) * sp + x] : HINF;
-    }
+// Phase 1 as its own launch (the first pivot block; later diagonal tiles are
+// closed inside the previous round's phase 3).
+__global__ __launch_bounds__(SB) void k_fw_diag(int32_t sp, int32_t r, int32_t *__restrict__ D) {
+    __shared__ __attribute__((aligned(16))) int32_t s[TB * TP];
+    const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+    int32_t *base = D + (size_t)r * TB * sp + (size_t)r * TB;
+    int32_t c[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            c[i][j] = base[(size_t)(ty * 4 + i) * sp + tx * 4 + j];
+            s[(ty * 4 + i) * TP + tx * 4 + j] = c[i][j];
+        }
     __syncthreads();
+    close_tile(s, c);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) base[(size_t)(ty * 4 + i) * sp + tx * 4 + j] = c[i][j];
+}
+
+inline __device__ int32_t as_dist(int32_t x) { return x; }
+inline __device__ int32_t as_dist(uint16_t x) { return x == DINF ? HINF : (int32_t)x; }
+
+enum MinPlusMode { MP_OUT = 0, MP_LOWER = 1, MP_LOWER_SYM = 2 };
+
+// Min-plus product over k of A[m][k] + B[n][k]: A int32 [M][lda], B [N][ldb]
+// (int32, or uint16 distances with DINF), both with k contiguous, K a
+// multiple of KC, rows 16-byte aligned.  Tiles of T = 16R rows and columns;
+// 256 threads, each an R x R block, through k-major LDS in KC steps, two k per
+// step so that the compiler fuses the two minima (v_min3).
+//   MP_OUT        C = the product, -1 where it stays HINF or above
+//   MP_LOWER      C = min(C, product), stored only where it decreases
+//   MP_LOWER_SYM  as MP_LOWER on a symmetric C (M = N): the blocks take the
+//                 tiles on and above the diagonal and store each decrease at
+//                 (m, n) and at (n, m); with R = 4, the block of diagonal tile
+//                 (closeb, closeb) then closes that tile (phase 1 of the next
+//                 round, which no other block of this launch reads)
+// In the lowering modes an entry that does not decrease is never written, so
+// other blocks may read it concurrently.
+template <int R, int MODE, typename BT>
+__global__ __launch_bounds__(SB) void k_minplus(int32_t M, int32_t N, int32_t K, const int32_t *A, int64_t lda,
+                                                const BT *B, int64_t ldb, int32_t *C, int64_t ldc,
+                                                int32_t closeb) {
+    constexpr int T = 16 * R, P = T + 4;
+    __shared__ __attribute__((aligned(16))) int32_t smem[2 * KC * P];
+    int32_t(*sA)[P] = (int32_t(*)[P])smem;
+    int32_t(*sB)[P] = (int32_t(*)[P])(smem + KC * P);
+    static_assert(R != 4 || 2 * KC * P >= TB * TP, "a closed tile fits the staging area");
+    const int t = threadIdx.x;
+    int32_t bm = blockIdx.y, bn = blockIdx.x;
+    if (MODE == MP_LOWER_SYM) {
+        // blockIdx.x enumerates the tiles (bm, bn) with bm <= bn
+        const int32_t id = blockIdx.x;
+        int32_t j = (int32_t)((sqrtf(8.0f * (float)id + 1.0f) - 1.0f) * 0.5f);
+        while (j * (j + 1) / 2 > id) --j;
+        while ((j + 1) * (j + 2) / 2 <= id) ++j;
+        bn = j;
+        bm = id - j * (j + 1) / 2;
+    }
+    const int32_t m0 = bm * T, n0 = bn * T;
+    const int ty = t >> 4, tx = t & 15;
+    int32_t c[R][R];
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            int32_t x = HINF;
+            if (MODE != MP_OUT) {
+                const int32_t m = m0 + ty * R + i, n = n0 + tx * R + j;
+                if (m < M && n < N) x = C[(size_t)m * ldc + n];
+            }
+            c[i][j] = x;
+        }
+    for (int32_t k0 = 0; k0 < K; k0 += KC) {
+        // A: rows (t >> 3) + 32p, four int32 at k (t & 7) * 4
+#pragma unroll
+        for (int p = 0; p < T / 32; ++p) {
+            const int row = (t >> 3) + 32 * p, k = (t & 7) * 4;
+            const int32_t m = m0 + row;
+            int4 a = make_int4(HINF, HINF, HINF, HINF);
+            if (m < M) a = *(const int4 *)(A + (size_t)m * lda + k0 + k);
+            sA[k][row] = a.x;
+            sA[k + 1][row] = a.y;
+            sA[k + 2][row] = a.z;
+            sA[k + 3][row] = a.w;
+        }
+        if constexpr (sizeof(BT) == 2) {
+            // B: rows (t >> 2) + 64p, eight uint16 at k (t & 3) * 8
+#pragma unroll
+            for (int p = 0; p < T / 64; ++p) {
+                const int row = (t >> 2) + 64 * p, k = (t & 3) * 8;
+                const int32_t n = n0 + row;
+                uint4 b = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
+                if (n < N) b = *(const uint4 *)(B + (size_t)n * ldb + k0 + k);
+                const uint32_t wv[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    sB[k + 2 * q][row] = as_dist((uint16_t)(wv[q] & 0xFFFF));
+                    sB[k + 2 * q + 1][row] = as_dist((uint16_t)(wv[q] >> 16));
+                }
+            }
+        } else {
+#pragma unroll
+            for (int p = 0; p < T / 32; ++p) {
+                const int row = (t >> 3) + 32 * p, k = (t & 7) * 4;
+                const int32_t n = n0 + row;
+                int4 b = make_int4(HINF, HINF, HINF, HINF);
+                if (n < N) b = *(const int4 *)(B + (size_t)n * ldb + k0 + k);
+                sB[k][row] = b.x;
+                sB[k + 1][row] = b.y;
+                sB[k + 2][row] = b.z;
+                sB[k + 3][row] = b.w;
+            }
+        }
+        __syncthreads();
+        constexpr int UNR = R == 8 ? 2 : 1;
+#pragma unroll UNR
+        for (int k = 0; k < KC; k += 2) {
+            int32_t a0[R], a1[R], b0[R], b1[R];
+#pragma unroll
+            for (int h = 0; h < R; h += 4) {
+                *(int4 *)&a0[h] = *(const int4 *)&sA[k][ty * R + h];
+                *(int4 *)&a1[h] = *(const int4 *)&sA[k + 1][ty * R + h];
+                *(int4 *)&b0[h] = *(const int4 *)&sB[k][tx * R + h];
+                *(int4 *)&b1[h] = *(const int4 *)&sB[k + 1][tx * R + h];
+            }
+#pragma unroll
+            for (int i = 0; i < R; ++i)
+#pragma unroll
+                for (int j = 0; j < R; ++j) c[i][j] = min(min(c[i][j], a0[i] + b0[j]), a1[i] + b1[j]);
+        }
+        __syncthreads();
+    }
+    if constexpr (MODE == MP_LOWER_SYM && R == 4) {
+        if (bm == closeb && bn == closeb) {
+#pragma unroll
+            for (int i = 0; i < R; ++i)
+#pragma unroll
+                for (int j = 0; j < R; ++j) smem[(ty * R + i) * TP + tx * R + j] = c[i][j];
+            __syncthreads();
+            close_tile(smem, c);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const int32_t m = m0 + ty * R + i;
+        if (m >= M) continue;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int32_t n = n0 + tx * R + j;
+            if (n >= N) continue;
+            if (MODE == MP_OUT) {
+                C[(size_t)m * ldc + n] = c[i][j] >= HINF ? -1 : c[i][j];
+            } else {
+                if (c[i][j] < C[(size_t)m * ldc + n]) C[(size_t)m * ldc + n] = c[i][j];
+                if (MODE == MP_LOWER_SYM && bm != bn && c[i][j] < C[(size_t)n * ldc + m])
+                    C[(size_t)n * ldc + m] = c[i][j];
+            }
+        }
+    }
+}
+
+// out[i] = in[row[i]]: rows in the requested order, repeats included.
+__global__ __launch_bounds__(SB) void k_pick_rows(int32_t n, int32_t count, const int32_t *__restrict__ row,
+                                                  const int32_t *__restrict__ in, int32_t *__restrict__ out) {
     const int32_t v = blockIdx.x * SB + threadIdx.x;
     if (v >= n) return;
-    int32_t best[IT];
-#pragma unroll
-    for (int t = 0; t < IT; ++t) best[t] = HINF;
-    for (int32_t x = 0; x < ns; ++x) {
-        const uint16_t d = dp[(size_t)x * n + v];
-        if (d == DINF) continue;
-#pragma unroll
-        for (int t = 0; t < IT; ++t) best[t] = min(best[t], s_h[t * sp + x] + (int32_t)d);
-    }
-#pragma unroll
-    for (int t = 0; t < IT; ++t)
-        if (r0 + t < count) out[(size_t)(r0 + t) * n + v] = best[t] >= HINF ? -1 : best[t];
+    for (int32_t i = blockIdx.y; i < count; i += gridDim.y) out[(size_t)i * n + v] = in[(size_t)row[i] * n + v];
 }
 
 } // namespace
 
 bc_status sampled_distances(bc_ctx *ctx, const int32_t *h_sources, int32_t count, const int32_t *h_sample,
-                            int32_t nsample, int32_t limit, int32_t *h_out) {
+                            int32_t nsample, int32_t limit, int32_t *out, bool out_on_device) {
     const int32_t n = ctx->n;
     // S: the distinct requested sources first (rows 0 .. nreq-1), then the
     // sample; row_of[i] is the row of the i-th requested source
@@ -156,84 +395,147 @@ bc_status sampled_distances(bc_ctx *ctx, const int32_t *h_sources, int32_t count
     }
     const int32_t ns = (int32_t)S.size();
     int32_t nreq = 0;
-    for (int32_t r : row_of) nreq = std::max(nreq, r + 1);
+    bool in_order = true; // row_of[i] == i: no repeats among the sources
+    for (int32_t i = 0; i < count; ++i) {
+        nreq = std::max(nreq, row_of[(size_t)i] + 1);
+        in_order = in_order && row_of[(size_t)i] == i;
+    }
     if (ns > BC_SAMPLED_MAX_S)
         return bc_fail(ctx, BC_ERR_UNSUPPORTED, "sampled forward: more than BC_SAMPLED_MAX_S distinguished vertices");
     const int32_t k = limit > 0 ? limit : std::max(1, (int32_t)std::ceil(std::sqrt((double)n)));
     if (k > 65534) return bc_fail(ctx, BC_ERR_INVALID_ARG, "sampled forward: limit above 65534");
-    const int32_t sp = (ns + 63) / 64 * 64;
-    int32_t *dS = (int32_t *)bc_dalloc(ctx, sizeof(int32_t) * (size_t)std::max(sp, 1));
-    uint16_t *dp = (uint16_t *)bc_dalloc(ctx, sizeof(uint16_t) * (size_t)sp * n);
+    const int32_t sp = (ns + 63) / 64 * 64, W = sp / 64;
+
+    // chunks of at most CH arcs: first those of vertices with more arcs (their
+    // partial ORs go to P), then one per remaining vertex (even with no arcs,
+    // so that every vertex's next-frontier words are written each level)
+    std::vector<int32_t> rp((size_t)n + 1);
+    hipError_t e = hipMemcpyAsync(rp.data(), ctx->row_ptr, sizeof(int32_t) * rp.size(), hipMemcpyDeviceToHost,
+                                  ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return bc_hip(ctx, e, "sampled forward: row offsets");
+    std::vector<int2> chunks;
+    std::vector<int32_t> sv, sc;
+    chunks.reserve((size_t)n + (size_t)(rp[(size_t)n] / CH));
+    for (int32_t v = 0; v < n; ++v)
+        if (rp[(size_t)v + 1] - rp[(size_t)v] > CH) {
+            sv.push_back(v);
+            sc.push_back((int32_t)chunks.size());
+            for (int32_t a = rp[(size_t)v]; a < rp[(size_t)v + 1]; a += CH) chunks.push_back(make_int2(v, a));
+        }
+    const int32_t nsplit = (int32_t)chunks.size(), nsv = (int32_t)sv.size();
+    sc.push_back(nsplit);
+    for (int32_t v = 0; v < n; ++v)
+        if (rp[(size_t)v + 1] - rp[(size_t)v] <= CH) chunks.push_back(make_int2(v, rp[(size_t)v]));
+    const int32_t nchunks = (int32_t)chunks.size();
+
+    const size_t bits = (size_t)n * W;
+    int32_t *dS = (int32_t *)bc_dalloc(ctx, sizeof(int32_t) * (size_t)sp);
+    uint16_t *dT = (uint16_t *)bc_dalloc(ctx, sizeof(uint16_t) * (size_t)sp * n);
     int32_t *H = (int32_t *)bc_dalloc(ctx, sizeof(int32_t) * (size_t)sp * sp);
-    uint64_t *front = (uint64_t *)bc_dalloc(ctx, sizeof(uint64_t) * (size_t)n);
-    uint64_t *next = (uint64_t *)bc_dalloc(ctx, sizeof(uint64_t) * (size_t)n);
-    uint64_t *visited = (uint64_t *)bc_dalloc(ctx, sizeof(uint64_t) * (size_t)n);
+    uint64_t *front = (uint64_t *)bc_dalloc(ctx, sizeof(uint64_t) * bits);
+    uint64_t *next = (uint64_t *)bc_dalloc(ctx, sizeof(uint64_t) * bits);
+    uint64_t *visited = (uint64_t *)bc_dalloc(ctx, sizeof(uint64_t) * bits);
+    uint64_t *part = (uint64_t *)bc_dalloc(ctx, sizeof(uint64_t) * (size_t)std::max(nsplit, 1) * W);
+    int2 *dchunks = (int2 *)bc_dalloc(ctx, sizeof(int2) * (size_t)nchunks);
+    int32_t *dsv = (int32_t *)bc_dalloc(ctx, sizeof(int32_t) * (size_t)(2 * nsv + 1));
     uint32_t *found = (uint32_t *)bc_dalloc(ctx, sizeof(uint32_t) * (size_t)(k + 1));
     int32_t *outi = (int32_t *)bc_dalloc(ctx, sizeof(int32_t) * (size_t)std::max(nreq, 1) * n);
-    int32_t *outc = (int32_t *)bc_dalloc(ctx, sizeof(int32_t) * (size_t)std::max(nreq, 1) * n);
+    // caller-numbered rows: straight into a device output when no source repeats
+    const bool direct = out_on_device && in_order;
+    int32_t *outc = direct ? out : (int32_t *)bc_dalloc(ctx, sizeof(int32_t) * (size_t)std::max(nreq, 1) * n);
+    int32_t *drow = out_on_device && !in_order ? (int32_t *)bc_dalloc(ctx, sizeof(int32_t) * (size_t)count)
+                                               : nullptr;
     std::vector<uint32_t> found_h((size_t)k + 1);
     auto cleanup = [&]() {
-        for (void *p : {(void *)dS, (void *)dp, (void *)H, (void *)front, (void *)next, (void *)visited,
-                        (void *)found, (void *)outi, (void *)outc})
-            bc_dfree(ctx, p);
+        for (void *q : {(void *)dS, (void *)dT, (void *)H, (void *)front, (void *)next, (void *)visited, (void *)part,
+                        (void *)dchunks, (void *)dsv, (void *)found, (void *)outi})
+            bc_dfree(ctx, q);
+        if (!direct) bc_dfree(ctx, outc);
+        bc_dfree(ctx, drow);
     };
-    if (!dS || !dp || !H || !front || !next || !visited || !found || !outi || !outc) {
+    if (!dS || !dT || !H || !front || !next || !visited || !part || !dchunks || !dsv || !found || !outi || !outc ||
+        (out_on_device && !in_order && !drow)) {
         cleanup();
         return bc_fail(ctx, BC_ERR_NOMEM, "sampled forward: allocation failed");
     }
-    auto fail_hip = [&](hipError_t e, const char *what) {
+    auto fail_hip = [&](hipError_t err, const char *what) {
         cleanup();
-        return bc_hip(ctx, e, what);
+        return bc_hip(ctx, err, what);
     };
-    hipError_t e = hipMemcpy(dS, S.data(), sizeof(int32_t) * (size_t)ns, hipMemcpyHostToDevice);
+    std::vector<int32_t> svsc(sv);
+    svsc.insert(svsc.end(), sc.begin(), sc.end());
+    e = hipMemcpyAsync(dS, S.data(), sizeof(int32_t) * (size_t)ns, hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(dchunks, chunks.data(), sizeof(int2) * chunks.size(), hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(dsv, svsc.data(), sizeof(int32_t) * svsc.size(), hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(front, 0, sizeof(uint64_t) * bits, ctx->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(visited, 0, sizeof(uint64_t) * bits, ctx->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(found, 0, sizeof(uint32_t) * (size_t)(k + 1), ctx->stream);
     if (e != hipSuccess) return fail_hip(e, "sampled forward: upload");
     bc_status st = map_ids_to_internal(ctx, dS, ns);
     if (st != BC_OK) {
         cleanup();
         return st;
     }
-    hipLaunchKernelGGL(k_fill_u16, dim3(blocks_for((size_t)sp * n)), dim3(SB), 0, ctx->stream, dp, (size_t)sp * n,
+    hipLaunchKernelGGL(k_fill_u16, dim3(blocks_for((size_t)sp * n)), dim3(SB), 0, ctx->stream, dT, (size_t)sp * n,
                        DINF);
-    // step 2: limited searches, one word of 64 sources at a time
+    hipLaunchKernelGGL(k_ls_sources, dim3(blocks_for((size_t)ns)), dim3(SB), 0, ctx->stream, ns, dS, W, sp, front,
+                       visited, dT);
+    // step 2: every row of S advances one level per launch
     {
         LaunchTimer tm(ctx, "limited_bfs");
-        for (int32_t base = 0; base < ns; base += 64) {
-            const int32_t cnt = std::min(64, ns - base);
-            const uint64_t full = cnt == 64 ? ~0ull : ((1ull << cnt) - 1);
-            hipLaunchKernelGGL(k_lb_clear, dim3(blocks_for((size_t)n)), dim3(SB), 0, ctx->stream, n, front, visited);
-            hipLaunchKernelGGL(k_lb_sources, dim3(1), dim3(64), 0, ctx->stream, n, dS, base, cnt, front, visited, dp);
-            e = hipMemsetAsync(found, 0, sizeof(uint32_t) * (size_t)(k + 1), ctx->stream);
-            if (e != hipSuccess) return fail_hip(e, "sampled forward: clear");
-            uint64_t *f = front, *g = next;
-            for (int32_t L = 1; L <= k; ++L) {
-                hipLaunchKernelGGL(k_lb_level, dim3(blocks_for((size_t)n)), dim3(SB), 0, ctx->stream, n, ctx->row_ptr,
-                                   ctx->col, full, base, L, f, g, visited, dp, found);
-                std::swap(f, g);
-                // every 8 levels: stop once a level found nothing new
-                if (L % 8 == 0 || L == k) {
-                    e = hipMemcpyAsync(found_h.data(), found, sizeof(uint32_t) * (size_t)(k + 1),
-                                       hipMemcpyDeviceToHost, ctx->stream);
-                    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-                    if (e != hipSuccess) return fail_hip(e, "sampled forward: level read-back");
-                    if (found_h[(size_t)L] == 0) break;
-                }
+        uint64_t *f = front, *g = next;
+        const unsigned level_blocks = (unsigned)((nchunks + SB / 64 - 1) / (SB / 64));
+        const unsigned finish_blocks = (unsigned)((nsv + SB / 64 - 1) / (SB / 64));
+        for (int32_t L = 1; L <= k; ++L) {
+            hipLaunchKernelGGL(k_ls_level, dim3(level_blocks), dim3(SB), 0, ctx->stream, nchunks, nsplit, dchunks,
+                               ctx->row_ptr, ctx->col, W, ns, sp, L, f, g, visited, part, dT, found);
+            if (nsv > 0)
+                hipLaunchKernelGGL(k_ls_finish, dim3(finish_blocks), dim3(SB), 0, ctx->stream, nsv, dsv,
+                                   dsv + nsv, W, ns, sp, L, part, g, visited, dT, found);
+            std::swap(f, g);
+            // every 8 levels: stop once a level found nothing new
+            if (L % 8 == 0 || L == k) {
+                e = hipMemcpyAsync(found_h.data(), found, sizeof(uint32_t) * (size_t)(k + 1), hipMemcpyDeviceToHost,
+                                   ctx->stream);
+                if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+                if (e != hipSuccess) return fail_hip(e, "sampled forward: level read-back");
+                if (found_h[(size_t)L] == 0) break;
             }
         }
         tm.done();
     }
     // steps 3 and 4
-    hipLaunchKernelGGL(k_build_h, dim3(blocks_for((size_t)sp * sp)), dim3(SB), 0, ctx->stream, n, ns, sp, dS, dp, H);
+    hipLaunchKernelGGL(k_build_h, dim3(blocks_for((size_t)sp * sp)), dim3(SB), 0, ctx->stream, ns, sp, dS, dT, H);
     {
         LaunchTimer tm(ctx, "floyd_warshall");
-        for (int32_t kk = 0; kk < ns; ++kk)
-            hipLaunchKernelGGL(k_fw, dim3(blocks_for((size_t)sp * sp)), dim3(SB), 0, ctx->stream, sp, kk, H);
+        const int32_t nb = sp / TB;
+        const unsigned tri = (unsigned)(nb * (nb + 1) / 2);
+        // phase 1 of the first round; each later diagonal tile is closed by the
+        // previous round's phase 3
+        hipLaunchKernelGGL(k_fw_diag, dim3(1), dim3(SB), 0, ctx->stream, sp, 0, H);
+        for (int32_t r = 0; r < nb; ++r) {
+            int32_t *strip = H + (size_t)r * TB;                  // column strip: rows 0..sp-1, columns of block r
+            const int32_t *diag = H + (size_t)r * TB * sp + (size_t)r * TB;
+            // phase 2: strip <- min(strip, strip (x) diagonal); the diagonal's own rows do not change
+            hipLaunchKernelGGL((k_minplus<4, MP_LOWER, int32_t>), dim3(1, nb), dim3(SB), 0, ctx->stream, sp, TB, TB,
+                               (const int32_t *)strip, (int64_t)sp, diag, (int64_t)sp, strip, (int64_t)sp, -1);
+            // phase 3: every entry <- min(entry, strip (x) strip), upper tiles mirrored; then the
+            // next diagonal tile is closed
+            hipLaunchKernelGGL((k_minplus<4, MP_LOWER_SYM, int32_t>), dim3(tri), dim3(SB), 0, ctx->stream, sp, sp, TB,
+                               (const int32_t *)strip, (int64_t)sp, (const int32_t *)strip, (int64_t)sp, H,
+                               (int64_t)sp, r + 1 < nb ? r + 1 : -1);
+        }
         tm.done();
     }
-    // step 5
-    if (nreq > 0 && n > 0) {
+    // step 5: the sources' rows of D_H (rows 0 .. nreq-1) min-plus d'
+    {
         LaunchTimer tm(ctx, "sampled_min");
-        hipLaunchKernelGGL(k_final, dim3(blocks_for((size_t)n), (nreq + IT - 1) / IT), dim3(SB),
-                           sizeof(int32_t) * IT * (size_t)sp, ctx->stream, n, ns, sp, nreq, H, dp, outi);
+        hipLaunchKernelGGL((k_minplus<8, MP_OUT, uint16_t>), dim3((n + 127) / 128, (nreq + 127) / 128), dim3(SB), 0,
+                           ctx->stream, nreq, n, sp, (const int32_t *)H, (int64_t)sp, (const uint16_t *)dT,
+                           (int64_t)sp, outi, (int64_t)n, -1);
         tm.done();
     }
     e = hipGetLastError();
@@ -244,15 +546,26 @@ bc_status sampled_distances(bc_ctx *ctx, const int32_t *h_sources, int32_t count
             cleanup();
             return st;
         }
+        if (out_on_device && !direct) {
+            e = hipMemcpyAsync(drow, row_of.data(), sizeof(int32_t) * (size_t)count, hipMemcpyHostToDevice,
+                               ctx->stream);
+            if (e != hipSuccess) return fail_hip(e, "sampled forward: row upload");
+            hipLaunchKernelGGL(k_pick_rows, dim3(blocks_for((size_t)n), std::min(count, 65535)), dim3(SB), 0, ctx->stream, n, count,
+                               drow, outc, out);
+            e = hipGetLastError();
+            if (e != hipSuccess) return fail_hip(e, "sampled forward: row order");
+        }
         e = hipStreamSynchronize(ctx->stream);
         if (e != hipSuccess) return fail_hip(e, "sampled forward");
-        // requested order, repeats included
-        std::vector<int32_t> rows((size_t)nreq * n);
-        e = hipMemcpy(rows.data(), outc, sizeof(int32_t) * rows.size(), hipMemcpyDeviceToHost);
-        if (e != hipSuccess) return fail_hip(e, "sampled forward: copy out");
-        for (int32_t i = 0; i < count; ++i)
-            std::copy(rows.begin() + (size_t)row_of[i] * n, rows.begin() + (size_t)(row_of[i] + 1) * n,
-                      h_out + (size_t)i * n);
+        if (!out_on_device) {
+            // requested order, repeats included
+            std::vector<int32_t> rows((size_t)nreq * n);
+            e = hipMemcpy(rows.data(), outc, sizeof(int32_t) * rows.size(), hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return fail_hip(e, "sampled forward: copy out");
+            for (int32_t i = 0; i < count; ++i)
+                std::copy(rows.begin() + (size_t)row_of[i] * n, rows.begin() + (size_t)(row_of[i] + 1) * n,
+                          out + (size_t)i * n);
+        }
     }
     cleanup();
     return BC_OK;

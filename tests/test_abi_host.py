@@ -132,7 +132,7 @@ def test_invalid_arguments():
     assert lib.bc_read(None, None, 0) == B.BC_ERR_INVALID_ARG
     assert lib.bc_reset(None) == B.BC_ERR_INVALID_ARG
     assert lib.bc_all_pairs(None, None, 0) == B.BC_ERR_INVALID_ARG
-    assert lib.bc_sampled_distances(None, None, 0, None, 0, 0, None) == B.BC_ERR_INVALID_ARG
+    assert lib.bc_sampled_distances(None, None, 0, None, 0, 0, None, 0) == B.BC_ERR_INVALID_ARG
     lib.bc_destroy(None)
 
 

@@ -39,6 +39,8 @@ def cases():
                         gg.sample_sources(700, 150, 7), 3),
         # n with a ragged last block; k past the diameter
         "ws1000_deep": (gg.watts_strogatz(1000, 4, 0.05, 9), np.array([1, 999]), gg.sample_sources(1000, 40, 5), 60),
+        # H is a chain of 600 vertices over ten pivot blocks: distances of up to 600 hops in H
+        "path1200_chain": (gg.path(1200), np.array([0, 1199, 601]), np.arange(0, 1200, 2), 2),
         "rmat10": (gg.rmat(10, 8, 3), gg.sample_sources(gg.rmat(10, 8, 3).n, 9, 2),
                    gg.sample_sources(gg.rmat(10, 8, 3).n, 70, 3), 2),
     }
@@ -121,3 +123,22 @@ def test_sampled_errors_and_empty(gpu_lib):
         with pytest.raises(gpu_lib.BCError) as e:
             ctx.sampled_distances([0], [], limit=2)
         assert e.value.status == gpu_lib.BC_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("repeats", [False, True])
+def test_sampled_device_output(gpu_lib, repeats):
+    """Rows written into a device tensor: straight from the final kernel when
+    no source repeats, through a row gather when some do."""
+    import torch
+    g = gg.er_plus_tree(900, 4.0, 21)
+    src = np.array([7, 300, 899, 7, 5] if repeats else [7, 300, 899, 5], np.int32)
+    smp = gg.sample_sources(g.n, 90, 22)
+    want = sampled.sampled_distances(g, src, smp, k=3)
+    say("sampled_device", repeats)
+    with gpu_lib.BC(g) as ctx:
+        out = torch.full((src.size, g.n), -7, dtype=torch.int32, device="cuda:0")
+        assert ctx.sampled_distances(src, smp, limit=3, out=out) is out
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), want)
+        with pytest.raises(ValueError):
+            ctx.sampled_distances(src, smp, limit=3, out=out[:, :10])
