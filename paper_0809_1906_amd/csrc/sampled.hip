@@ -38,9 +38,10 @@ constexpr int KC = 32;  // k step of the min-plus products
 
 inline unsigned blocks_for(size_t count) { return (unsigned)((count + SB - 1) / SB); }
 
-__global__ __launch_bounds__(SB) void k_fill_u16(uint16_t *__restrict__ x, size_t count, uint16_t value) {
+// x[0 .. 8 count) = DINF, sixteen bytes per thread.
+__global__ __launch_bounds__(SB) void k_fill_dinf(uint4 *__restrict__ x, size_t count) {
     const size_t i = (size_t)blockIdx.x * SB + threadIdx.x;
-    if (i < count) x[i] = value;
+    if (i < count) x[i] = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
 }
 
 // Bits of word w that are rows of S.
@@ -133,8 +134,14 @@ __global__ __launch_bounds__(SB) void k_ls_finish(int32_t nsv, const int32_t *__
     if (j >= nsv) return;
     const int32_t v = sv[j];
     uint64_t acc = 0;
-    if (lane < W)
-        for (int32_t c = sc[j]; c < sc[j + 1]; ++c) acc |= P[(size_t)c * W + lane];
+    if (lane < W) {
+        const int32_t ce = sc[j + 1];
+        int32_t c = sc[j];
+        for (; c + 4 <= ce; c += 4)
+            acc |= P[(size_t)c * W + lane] | P[(size_t)(c + 1) * W + lane] | P[(size_t)(c + 2) * W + lane] |
+                   P[(size_t)(c + 3) * W + lane];
+        for (; c < ce; ++c) acc |= P[(size_t)c * W + lane];
+    }
     const uint64_t vis = lane < W ? V[(size_t)v * W + lane] : 0;
     ls_settle(v, lane, W, sp, acc, vis, word_rows(lane, ns), L, N, V, dT, found);
 }
@@ -232,23 +239,30 @@ enum MinPlusMode { MP_OUT = 0, MP_LOWER = 1, MP_LOWER_SYM = 2 };
 
 // Min-plus product over k of A[m][k] + B[n][k]: A int32 [M][lda], B [N][ldb]
 // (int32, or uint16 distances with DINF), both with k contiguous, K a
-// multiple of KC, rows 16-byte aligned.  Tiles of T = 16R rows and columns;
+// multiple of KC, rows 16-byte aligned; with brow, column n takes B row
+// brow[n].  The next k step's operands are loaded while this one computes.  Tiles of T = 16R rows and columns;
 // 256 threads, each an R x R block, through k-major LDS in KC steps, two k per
 // step so that the compiler fuses the two minima (v_min3).
 //   MP_OUT        C = the product, -1 where it stays HINF or above
-//   MP_LOWER      C = min(C, product), stored only where it decreases
+//   MP_LOWER      C = min(C, product), stored only where it decreases; with
+//                 CT, also CT[n][m] where the result is below it
 //   MP_LOWER_SYM  as MP_LOWER on a symmetric C (M = N): the blocks take the
-//                 tiles on and above the diagonal and store each decrease at
-//                 (m, n) and at (n, m); with R = 4, the block of diagonal tile
-//                 (closeb, closeb) then closes that tile (phase 1 of the next
-//                 round, which no other block of this launch reads)
+//                 tiles (bm, bn) with bm <= bn except those in tile row or
+//                 column `blk`, and store each decrease at (m, n) and (n, m);
+//                 with R = 4, the block of diagonal tile (closeb, closeb) then
+//                 closes that tile (phase 1 of the next round, which no other
+//                 block of this launch reads)
 // In the lowering modes an entry that does not decrease is never written, so
-// other blocks may read it concurrently.
+// other blocks may read it concurrently.  With a gate, the launch does nothing
+// unless *gate is nonzero.
 template <int R, int MODE, typename BT>
 __global__ __launch_bounds__(SB) void k_minplus(int32_t M, int32_t N, int32_t K, const int32_t *A, int64_t lda,
-                                                const BT *B, int64_t ldb, int32_t *C, int64_t ldc,
-                                                int32_t closeb) {
+                                                const BT *B, int64_t ldb, const int32_t *brow, int32_t *C,
+                                                int64_t ldc, int32_t *CT, int32_t blk, int32_t closeb,
+                                                const uint32_t *gate) {
     constexpr int T = 16 * R, P = T + 4;
+    constexpr bool B16 = sizeof(BT) == 2;
+    if (gate && *gate == 0) return; // the 16-bit product below runs instead
     __shared__ __attribute__((aligned(16))) int32_t smem[2 * KC * P];
     int32_t(*sA)[P] = (int32_t(*)[P])smem;
     int32_t(*sB)[P] = (int32_t(*)[P])(smem + KC * P);
@@ -263,63 +277,84 @@ __global__ __launch_bounds__(SB) void k_minplus(int32_t M, int32_t N, int32_t K,
         while ((j + 1) * (j + 2) / 2 <= id) ++j;
         bn = j;
         bm = id - j * (j + 1) / 2;
+        if (bm == blk || bn == blk) return; // the strips are final after phase 2
     }
     const int32_t m0 = bm * T, n0 = bn * T;
     const int ty = t >> 4, tx = t & 15;
-    int32_t c[R][R];
+    // staging registers: A rows (t >> 3) + 32p, four int32 at k (t & 7) * 4;
+    // B likewise, or (16-bit) rows (t >> 2) + 64p, eight uint16 at k (t & 3) * 8
+    constexpr int NA = T / 32, NB = B16 ? T / 64 : T / 32;
+    int4 ra[NA];
+    uint4 rb[NB];
+    const BT *brows[NB];
 #pragma unroll
-    for (int i = 0; i < R; ++i)
+    for (int p = 0; p < NB; ++p) {
+        const int32_t n = n0 + (B16 ? (t >> 2) + 64 * p : (t >> 3) + 32 * p);
+        brows[p] = n < N ? B + (size_t)(brow ? brow[n] : n) * ldb : nullptr;
+    }
+    auto load = [&](int32_t k0) {
 #pragma unroll
-        for (int j = 0; j < R; ++j) {
-            int32_t x = HINF;
-            if (MODE != MP_OUT) {
-                const int32_t m = m0 + ty * R + i, n = n0 + tx * R + j;
-                if (m < M && n < N) x = C[(size_t)m * ldc + n];
-            }
-            c[i][j] = x;
+        for (int p = 0; p < NA; ++p) {
+            const int32_t m = m0 + (t >> 3) + 32 * p;
+            ra[p] = m < M ? *(const int4 *)(A + (size_t)m * lda + k0 + (t & 7) * 4)
+                          : make_int4(HINF, HINF, HINF, HINF);
         }
-    for (int32_t k0 = 0; k0 < K; k0 += KC) {
-        // A: rows (t >> 3) + 32p, four int32 at k (t & 7) * 4
 #pragma unroll
-        for (int p = 0; p < T / 32; ++p) {
+        for (int p = 0; p < NB; ++p) {
+            const int kk = B16 ? (t & 3) * 8 : (t & 7) * 4;
+            if (brows[p]) rb[p] = *(const uint4 *)(brows[p] + k0 + kk);
+            else rb[p] = B16 ? make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu)
+                             : make_uint4(HINF, HINF, HINF, HINF);
+        }
+    };
+    auto stage = [&]() {
+#pragma unroll
+        for (int p = 0; p < NA; ++p) {
             const int row = (t >> 3) + 32 * p, k = (t & 7) * 4;
-            const int32_t m = m0 + row;
-            int4 a = make_int4(HINF, HINF, HINF, HINF);
-            if (m < M) a = *(const int4 *)(A + (size_t)m * lda + k0 + k);
-            sA[k][row] = a.x;
-            sA[k + 1][row] = a.y;
-            sA[k + 2][row] = a.z;
-            sA[k + 3][row] = a.w;
+            sA[k][row] = ra[p].x;
+            sA[k + 1][row] = ra[p].y;
+            sA[k + 2][row] = ra[p].z;
+            sA[k + 3][row] = ra[p].w;
         }
-        if constexpr (sizeof(BT) == 2) {
-            // B: rows (t >> 2) + 64p, eight uint16 at k (t & 3) * 8
 #pragma unroll
-            for (int p = 0; p < T / 64; ++p) {
+        for (int p = 0; p < NB; ++p) {
+            const uint32_t wv[4] = {rb[p].x, rb[p].y, rb[p].z, rb[p].w};
+            if constexpr (B16) {
                 const int row = (t >> 2) + 64 * p, k = (t & 3) * 8;
-                const int32_t n = n0 + row;
-                uint4 b = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
-                if (n < N) b = *(const uint4 *)(B + (size_t)n * ldb + k0 + k);
-                const uint32_t wv[4] = {b.x, b.y, b.z, b.w};
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     sB[k + 2 * q][row] = as_dist((uint16_t)(wv[q] & 0xFFFF));
                     sB[k + 2 * q + 1][row] = as_dist((uint16_t)(wv[q] >> 16));
                 }
-            }
-        } else {
-#pragma unroll
-            for (int p = 0; p < T / 32; ++p) {
+            } else {
                 const int row = (t >> 3) + 32 * p, k = (t & 7) * 4;
-                const int32_t n = n0 + row;
-                int4 b = make_int4(HINF, HINF, HINF, HINF);
-                if (n < N) b = *(const int4 *)(B + (size_t)n * ldb + k0 + k);
-                sB[k][row] = b.x;
-                sB[k + 1][row] = b.y;
-                sB[k + 2][row] = b.z;
-                sB[k + 3][row] = b.w;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) sB[k + q][row] = (int32_t)wv[q];
             }
         }
+    };
+    load(0);
+    int32_t c[R][R], c0[MODE == MP_OUT ? 1 : R][MODE == MP_OUT ? 1 : R],
+        ct0[MODE == MP_LOWER ? R : 1][MODE == MP_LOWER ? R : 1];
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            int32_t x = HINF;
+            if constexpr (MODE != MP_OUT) {
+                const int32_t m = m0 + ty * R + i, n = n0 + tx * R + j;
+                const bool in = m < M && n < N;
+                if (in) x = C[(size_t)m * ldc + n];
+                c0[i][j] = x;
+                // the transposed entries: written only by this block, at the end
+                if constexpr (MODE == MP_LOWER) ct0[i][j] = in && CT ? CT[(size_t)n * ldc + m] : HINF;
+            }
+            c[i][j] = x;
+        }
+    for (int32_t k0 = 0; k0 < K; k0 += KC) {
+        stage();
         __syncthreads();
+        if (k0 + KC < K) load(k0 + KC);
         constexpr int UNR = R == 8 ? 2 : 1;
 #pragma unroll UNR
         for (int k = 0; k < KC; k += 2) {
@@ -356,13 +391,113 @@ __global__ __launch_bounds__(SB) void k_minplus(int32_t M, int32_t N, int32_t K,
         for (int j = 0; j < R; ++j) {
             const int32_t n = n0 + tx * R + j;
             if (n >= N) continue;
-            if (MODE == MP_OUT) {
+            if constexpr (MODE == MP_OUT) {
                 C[(size_t)m * ldc + n] = c[i][j] >= HINF ? -1 : c[i][j];
             } else {
-                if (c[i][j] < C[(size_t)m * ldc + n]) C[(size_t)m * ldc + n] = c[i][j];
-                if (MODE == MP_LOWER_SYM && bm != bn && c[i][j] < C[(size_t)n * ldc + m])
-                    C[(size_t)n * ldc + m] = c[i][j];
+                // (n, m) equals (m, n) before the update: the tiles read here
+                // hold no strip entry, and the matrix is symmetric elsewhere
+                if (c[i][j] < c0[i][j]) {
+                    C[(size_t)m * ldc + n] = c[i][j];
+                    if (MODE == MP_LOWER_SYM && bm != bn) C[(size_t)n * ldc + m] = c[i][j];
+                }
+                if constexpr (MODE == MP_LOWER)
+                    if (CT && c[i][j] < ct0[i][j]) CT[(size_t)n * ldc + m] = c[i][j];
             }
+        }
+    }
+}
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+// The sources' rows of D_H as uint16 (DINF where none) for the 16-bit final
+// product; *wide = 1 when some finite value exceeds cap = 65534 - k, so that a
+// sum could pass 65534 (the 32-bit product runs then).
+__global__ __launch_bounds__(SB) void k_dh16(int32_t M, int32_t sp, const int32_t *__restrict__ DH, int32_t cap,
+                                             uint16_t *__restrict__ A16, uint32_t *__restrict__ wide) {
+    const size_t id = (size_t)blockIdx.x * SB + threadIdx.x;
+    if (id >= (size_t)M * sp) return;
+    const int32_t d = DH[id];
+    const bool fin = d < HINF;
+    A16[id] = fin ? (uint16_t)min(d, (int32_t)DINF) : DINF;
+    if (fin && d > cap) *wide = 1;
+}
+
+// Step 5 in 16-bit arithmetic: C[m][n] = min over k of A[m][k] + B[n'][k], A
+// and B uint16 [rows][sp] with k contiguous, DINF = none, n' = brow[n] (or n); each sum saturates at
+// 65535 (v_pk_add_u16 with clamp) and two columns share one register
+// (v_pk_min_u16), one instruction per term for the add and the minimum.
+// Exact while every finite D_H entry plus every finite d' stays below 65535,
+// which the gate guarantees: the launch does nothing when *wide is set.  Tiles
+// of 128 x 128 through k-major LDS in steps of 64; each thread an 8 x 8 block;
+// result -1 where no walk was found.
+constexpr int KH = 64, PH = 128 + 8; // k step and LDS pitch (uint16) of the 16-bit product
+__global__ __launch_bounds__(SB) void k_minplus16(int32_t M, int32_t N, int32_t K, const uint16_t *__restrict__ A,
+                                                  const uint16_t *__restrict__ B, int64_t ld,
+                                                  const int32_t *__restrict__ brow, int32_t *__restrict__ C,
+                                                  int64_t ldc, const uint32_t *__restrict__ wide) {
+    if (*wide != 0) return;
+    __shared__ __attribute__((aligned(16))) uint16_t sA[KH][PH];
+    __shared__ __attribute__((aligned(16))) uint16_t sB[KH][PH];
+    const int t = threadIdx.x;
+    const int32_t m0 = blockIdx.y * 128, n0 = blockIdx.x * 128;
+    const int ty = t >> 4, tx = t & 15;
+    u16x2 c[8][4];
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) c[i][j] = (u16x2){DINF, DINF};
+    // staging: thread t loads rows 2 (t & 63) and 2 (t & 63) + 1 at k chunks
+    // ((t >> 6) + 4p) * 8 and writes each k as one 32-bit pair of rows
+    const int pr = 2 * (t & 63);
+    const uint16_t *bp0 = n0 + pr < N ? B + (size_t)(brow ? brow[n0 + pr] : n0 + pr) * ld : nullptr;
+    const uint16_t *bp1 = n0 + pr + 1 < N ? B + (size_t)(brow ? brow[n0 + pr + 1] : n0 + pr + 1) * ld : nullptr;
+    for (int32_t k0 = 0; k0 < K; k0 += KH) {
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const int kk = ((t >> 6) + 4 * p) * 8;
+            uint4 a0 = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu), a1 = a0, b0 = a0, b1 = a0;
+            if (m0 + pr < M) a0 = *(const uint4 *)(A + (size_t)(m0 + pr) * ld + k0 + kk);
+            if (m0 + pr + 1 < M) a1 = *(const uint4 *)(A + (size_t)(m0 + pr + 1) * ld + k0 + kk);
+            if (bp0) b0 = *(const uint4 *)(bp0 + k0 + kk);
+            if (bp1) b1 = *(const uint4 *)(bp1 + k0 + kk);
+            const uint32_t x0[4] = {a0.x, a0.y, a0.z, a0.w}, x1[4] = {a1.x, a1.y, a1.z, a1.w};
+            const uint32_t y0[4] = {b0.x, b0.y, b0.z, b0.w}, y1[4] = {b1.x, b1.y, b1.z, b1.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                *(uint32_t *)&sA[kk + 2 * q][pr] = (x0[q] & 0xFFFFu) | (x1[q] << 16);
+                *(uint32_t *)&sA[kk + 2 * q + 1][pr] = (x0[q] >> 16) | (x1[q] & 0xFFFF0000u);
+                *(uint32_t *)&sB[kk + 2 * q][pr] = (y0[q] & 0xFFFFu) | (y1[q] << 16);
+                *(uint32_t *)&sB[kk + 2 * q + 1][pr] = (y0[q] >> 16) | (y1[q] & 0xFFFF0000u);
+            }
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int k = 0; k < KH; ++k) {
+            const uint4 av = *(const uint4 *)&sA[k][ty * 8];
+            const uint4 bv = *(const uint4 *)&sB[k][tx * 8];
+            const uint32_t aw[4] = {av.x, av.y, av.z, av.w};
+            const u16x2 b[4] = {__builtin_bit_cast(u16x2, bv.x), __builtin_bit_cast(u16x2, bv.y),
+                                __builtin_bit_cast(u16x2, bv.z), __builtin_bit_cast(u16x2, bv.w)};
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const unsigned short ai = (unsigned short)((i & 1) ? (aw[i >> 1] >> 16) : (aw[i >> 1] & 0xFFFF));
+                const u16x2 a2 = (u16x2){ai, ai};
+#pragma unroll
+                for (int j = 0; j < 4; ++j) c[i][j] = __builtin_elementwise_min(c[i][j], __builtin_elementwise_add_sat(a2, b[j]));
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int32_t m = m0 + ty * 8 + i;
+        if (m >= M) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int32_t n = n0 + tx * 8 + 2 * j;
+            const int32_t lo = c[i][j].x, hi = c[i][j].y;
+            if (n < N) C[(size_t)m * ldc + n] = lo == DINF ? -1 : lo;
+            if (n + 1 < N) C[(size_t)m * ldc + n + 1] = hi == DINF ? -1 : hi;
         }
     }
 }
@@ -439,8 +574,9 @@ bc_status sampled_distances(bc_ctx *ctx, const int32_t *h_sources, int32_t count
     uint64_t *part = (uint64_t *)bc_dalloc(ctx, sizeof(uint64_t) * (size_t)std::max(nsplit, 1) * W);
     int2 *dchunks = (int2 *)bc_dalloc(ctx, sizeof(int2) * (size_t)nchunks);
     int32_t *dsv = (int32_t *)bc_dalloc(ctx, sizeof(int32_t) * (size_t)(2 * nsv + 1));
-    uint32_t *found = (uint32_t *)bc_dalloc(ctx, sizeof(uint32_t) * (size_t)(k + 1));
-    int32_t *outi = (int32_t *)bc_dalloc(ctx, sizeof(int32_t) * (size_t)std::max(nreq, 1) * n);
+    uint32_t *found = (uint32_t *)bc_dalloc(ctx, sizeof(uint32_t) * (size_t)(k + 2)); // [k + 1]: the wide flag
+    uint32_t *wide = found + (k + 1);
+    uint16_t *a16 = (uint16_t *)bc_dalloc(ctx, sizeof(uint16_t) * (size_t)std::max(nreq, 1) * sp);
     // caller-numbered rows: straight into a device output when no source repeats
     const bool direct = out_on_device && in_order;
     int32_t *outc = direct ? out : (int32_t *)bc_dalloc(ctx, sizeof(int32_t) * (size_t)std::max(nreq, 1) * n);
@@ -449,12 +585,12 @@ bc_status sampled_distances(bc_ctx *ctx, const int32_t *h_sources, int32_t count
     std::vector<uint32_t> found_h((size_t)k + 1);
     auto cleanup = [&]() {
         for (void *q : {(void *)dS, (void *)dT, (void *)H, (void *)front, (void *)next, (void *)visited, (void *)part,
-                        (void *)dchunks, (void *)dsv, (void *)found, (void *)outi})
+                        (void *)dchunks, (void *)dsv, (void *)found, (void *)a16})
             bc_dfree(ctx, q);
         if (!direct) bc_dfree(ctx, outc);
         bc_dfree(ctx, drow);
     };
-    if (!dS || !dT || !H || !front || !next || !visited || !part || !dchunks || !dsv || !found || !outi || !outc ||
+    if (!dS || !dT || !H || !front || !next || !visited || !part || !dchunks || !dsv || !found || !a16 || !outc ||
         (out_on_device && !in_order && !drow)) {
         cleanup();
         return bc_fail(ctx, BC_ERR_NOMEM, "sampled forward: allocation failed");
@@ -472,15 +608,16 @@ bc_status sampled_distances(bc_ctx *ctx, const int32_t *h_sources, int32_t count
         e = hipMemcpyAsync(dsv, svsc.data(), sizeof(int32_t) * svsc.size(), hipMemcpyHostToDevice, ctx->stream);
     if (e == hipSuccess) e = hipMemsetAsync(front, 0, sizeof(uint64_t) * bits, ctx->stream);
     if (e == hipSuccess) e = hipMemsetAsync(visited, 0, sizeof(uint64_t) * bits, ctx->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(found, 0, sizeof(uint32_t) * (size_t)(k + 1), ctx->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(found, 0, sizeof(uint32_t) * (size_t)(k + 2), ctx->stream);
     if (e != hipSuccess) return fail_hip(e, "sampled forward: upload");
     bc_status st = map_ids_to_internal(ctx, dS, ns);
     if (st != BC_OK) {
         cleanup();
         return st;
     }
-    hipLaunchKernelGGL(k_fill_u16, dim3(blocks_for((size_t)sp * n)), dim3(SB), 0, ctx->stream, dT, (size_t)sp * n,
-                       DINF);
+    static_assert(DINF == 0xFFFF, "the fill writes all-ones words");
+    hipLaunchKernelGGL(k_fill_dinf, dim3(blocks_for((size_t)sp * n / 8)), dim3(SB), 0, ctx->stream, (uint4 *)dT,
+                       (size_t)sp * n / 8);
     hipLaunchKernelGGL(k_ls_sources, dim3(blocks_for((size_t)ns)), dim3(SB), 0, ctx->stream, ns, dS, W, sp, front,
                        visited, dT);
     // step 2: every row of S advances one level per launch
@@ -520,32 +657,38 @@ bc_status sampled_distances(bc_ctx *ctx, const int32_t *h_sources, int32_t count
             int32_t *strip = H + (size_t)r * TB;                  // column strip: rows 0..sp-1, columns of block r
             const int32_t *diag = H + (size_t)r * TB * sp + (size_t)r * TB;
             // phase 2: strip <- min(strip, strip (x) diagonal); the diagonal's own rows do not change
+            // (and the row strip, its transpose)
             hipLaunchKernelGGL((k_minplus<4, MP_LOWER, int32_t>), dim3(1, nb), dim3(SB), 0, ctx->stream, sp, TB, TB,
-                               (const int32_t *)strip, (int64_t)sp, diag, (int64_t)sp, strip, (int64_t)sp, -1);
-            // phase 3: every entry <- min(entry, strip (x) strip), upper tiles mirrored; then the
-            // next diagonal tile is closed
+                               (const int32_t *)strip, (int64_t)sp, diag, (int64_t)sp, nullptr, strip, (int64_t)sp,
+                               H + (size_t)r * TB * sp, -1, -1, nullptr);
+            // phase 3: every entry outside the strips <- min(entry, strip (x) strip), upper
+            // tiles mirrored; then the next diagonal tile is closed
             hipLaunchKernelGGL((k_minplus<4, MP_LOWER_SYM, int32_t>), dim3(tri), dim3(SB), 0, ctx->stream, sp, sp, TB,
-                               (const int32_t *)strip, (int64_t)sp, (const int32_t *)strip, (int64_t)sp, H,
-                               (int64_t)sp, r + 1 < nb ? r + 1 : -1);
+                               (const int32_t *)strip, (int64_t)sp, (const int32_t *)strip, (int64_t)sp, nullptr,
+                               H, (int64_t)sp, nullptr, r, r + 1 < nb ? r + 1 : -1, nullptr);
         }
         tm.done();
     }
-    // step 5: the sources' rows of D_H (rows 0 .. nreq-1) min-plus d'
-    {
+    // step 5: the sources' rows of D_H (rows 0 .. nreq-1) min-plus d', in 16-bit
+    // arithmetic when every finite sum stays below 65535, else in 32-bit; column
+    // v of a row is the caller's vertex v (its d' row is that of new_of_old[v])
+    if (nreq > 0) {
         LaunchTimer tm(ctx, "sampled_min");
-        hipLaunchKernelGGL((k_minplus<8, MP_OUT, uint16_t>), dim3((n + 127) / 128, (nreq + 127) / 128), dim3(SB), 0,
-                           ctx->stream, nreq, n, sp, (const int32_t *)H, (int64_t)sp, (const uint16_t *)dT,
-                           (int64_t)sp, outi, (int64_t)n, -1);
+        const dim3 grid((n + 127) / 128, (nreq + 127) / 128);
+        hipLaunchKernelGGL(k_dh16, dim3(blocks_for((size_t)nreq * sp)), dim3(SB), 0, ctx->stream, nreq, sp,
+                           (const int32_t *)H, 65534 - k, a16, wide);
+        hipLaunchKernelGGL(k_minplus16, grid, dim3(SB), 0, ctx->stream, nreq, n, sp, (const uint16_t *)a16,
+                           (const uint16_t *)dT, (int64_t)sp, (const int32_t *)ctx->new_of_old, outc, (int64_t)n,
+                           (const uint32_t *)wide);
+        hipLaunchKernelGGL((k_minplus<8, MP_OUT, uint16_t>), grid, dim3(SB), 0, ctx->stream, nreq, n, sp,
+                           (const int32_t *)H, (int64_t)sp, (const uint16_t *)dT, (int64_t)sp,
+                           (const int32_t *)ctx->new_of_old, outc, (int64_t)n, nullptr, -1, -1,
+                           (const uint32_t *)wide);
         tm.done();
     }
     e = hipGetLastError();
     if (e != hipSuccess) return fail_hip(e, "sampled forward");
-    if (nreq > 0 && n > 0) {
-        st = rows_to_caller_order_i32(ctx, outc, outi, nreq);
-        if (st != BC_OK) {
-            cleanup();
-            return st;
-        }
+    if (nreq > 0) {
         if (out_on_device && !direct) {
             e = hipMemcpyAsync(drow, row_of.data(), sizeof(int32_t) * (size_t)count, hipMemcpyHostToDevice,
                                ctx->stream);

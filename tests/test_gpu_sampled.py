@@ -142,3 +142,20 @@ def test_sampled_device_output(gpu_lib, repeats):
         assert np.array_equal(out.cpu().numpy(), want)
         with pytest.raises(ValueError):
             ctx.sampled_distances(src, smp, limit=3, out=out[:, :10])
+
+
+def test_sampled_wide_values_take_32_bit_path(gpu_lib):
+    """The final minimum runs in 16-bit arithmetic only while every finite
+    D_H entry is at most 65534 - k.  With k = 65534 any positive entry is over
+    that bound, so the 32-bit product runs; both routes give the exact
+    distances here (k is past the diameter either way)."""
+    g = gg.er_plus_tree(600, 3.0, 41)
+    src = gg.sample_sources(g.n, 5, 42)
+    smp = gg.sample_sources(g.n, 40, 43)
+    want = exact(g, src)
+    say("sampled_wide", g.n)
+    with gpu_lib.BC(g) as ctx:
+        wide = ctx.sampled_distances(src, smp, limit=65534)
+        narrow = ctx.sampled_distances(src, smp, limit=64)
+    assert np.array_equal(wide, want) and np.array_equal(narrow, want)
+    assert np.array_equal(wide, sampled.sampled_distances(g, src, smp, k=65534))
