@@ -11,13 +11,15 @@
 //
 // Layout (sp = |S| rounded up to 64, W = sp / 64 bitmap words):
 //   d'    uint16 dT[v][sp], vertex-major: dT[v][x] = d'(S_x, v), DINF = none
-//   bits  frontier, next frontier and visited sets as uint64 [v][W]: bit x of
-//         vertex v's words is row x of S
+//   bits  visited sets and the new bits of each level (a ring of 8 levels,
+//         the last being the frontier) as uint64 [v][W]: bit x of vertex v's
+//         words is row x of S
 //   H     int32 [sp][sp], HINF = no path (HINF + HINF fits int32); D_H in place
 // The limited searches advance every row of S together, one launch per level:
 // a wave takes a chunk of at most CH arcs of one vertex, lane w pulls word w of
 // each neighbour's frontier; vertices with more than CH arcs leave one partial
-// OR per chunk, merged by a second launch.  Floyd-Warshall runs in 64 x 64
+// OR per chunk, merged by a second launch.  Every 8 levels the new bits become
+// d' entries, sixteen bytes per thread.  Floyd-Warshall runs in 64 x 64
 // tiles: per pivot block, the diagonal tile, then the column strip and then
 // the whole (symmetric) matrix as min-plus products.  Step 5 is the min-plus
 // product of the sources' rows of D_H with d', in LDS-staged 128 x 128 tiles.
@@ -38,12 +40,6 @@ constexpr int KC = 32;  // k step of the min-plus products
 
 inline unsigned blocks_for(size_t count) { return (unsigned)((count + SB - 1) / SB); }
 
-// x[0 .. 8 count) = DINF, sixteen bytes per thread.
-__global__ __launch_bounds__(SB) void k_fill_dinf(uint4 *__restrict__ x, size_t count) {
-    const size_t i = (size_t)blockIdx.x * SB + threadIdx.x;
-    if (i < count) x[i] = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
-}
-
 // Bits of word w that are rows of S.
 __device__ inline uint64_t word_rows(int32_t w, int32_t ns) {
     const int32_t r = ns - 64 * w;
@@ -52,42 +48,99 @@ __device__ inline uint64_t word_rows(int32_t w, int32_t ns) {
 
 // Level 0: row i of S starts at its own vertex (S has no repeats, so each
 // vertex's words hold at most one bit here; the bitmaps were cleared).
-__global__ __launch_bounds__(SB) void k_ls_sources(int32_t ns, const int32_t *__restrict__ S, int32_t W, int32_t sp,
-                                                   uint64_t *__restrict__ F, uint64_t *__restrict__ V,
-                                                   uint16_t *__restrict__ dT) {
+__global__ __launch_bounds__(SB) void k_ls_sources(int32_t ns, const int32_t *__restrict__ S, int32_t W,
+                                                   uint64_t *__restrict__ F, uint64_t *__restrict__ V) {
     const int32_t i = blockIdx.x * SB + threadIdx.x;
     if (i >= ns) return;
     const int32_t v = S[i];
     const uint64_t bit = 1ull << (i & 63);
     F[(size_t)v * W + (i >> 6)] = bit;
     V[(size_t)v * W + (i >> 6)] = bit;
-    dT[(size_t)v * sp + i] = 0;
 }
 
-// New bits of vertex v at level L: record them and set its next-frontier word.
-__device__ inline void ls_settle(int32_t v, int lane, int32_t W, int32_t sp, uint64_t acc, uint64_t vis,
-                                 uint64_t rows, int32_t L, uint64_t *__restrict__ N, uint64_t *__restrict__ V,
-                                 uint16_t *__restrict__ dT, uint32_t *__restrict__ found) {
+// New bits of vertex v at level L: they are its next-frontier word (kept for
+// the flush into d') and join its visited word.
+__device__ inline void ls_settle(int32_t v, int lane, int32_t W, uint64_t acc, uint64_t vis, uint64_t rows,
+                                 int32_t L, uint64_t *__restrict__ N, uint64_t *__restrict__ V,
+                                 uint32_t *__restrict__ found) {
     const uint64_t nw = acc & ~vis & rows;
     if (lane < W) {
         N[(size_t)v * W + lane] = nw;
-        if (nw) {
-            V[(size_t)v * W + lane] = vis | nw;
-            uint16_t *row = dT + (size_t)v * sp + 64 * lane;
-            for (uint64_t m = nw; m; m &= m - 1) row[__builtin_ctzll(m)] = (uint16_t)L;
-        }
+        if (nw) V[(size_t)v * W + lane] = vis | nw;
     }
     if (__builtin_amdgcn_ballot_w64(nw != 0) != 0 && lane == 0) found[L] = 1;
+}
+
+// d' from the new-bit words of levels L0 .. L0 + nl - 1 (ring slot L % RING,
+// nl <= RING).  A block takes 32 words: it stages their slot words in LDS (one
+// coalesced load per thread), then thread (word, g) owns the sixteen bytes of
+// entries 64w + 8g .. + 7 of row v of dT, so a wave stores one contiguous
+// kilobyte.  Levels that found nothing are skipped (their slots were not
+// rewritten).  The slots' bits are disjoint, so the slot index of an entry is
+// read off three OR-planes of the slot words (bit j of the index: the OR of
+// the slots whose index has bit j).  The first flush writes every entry (DINF
+// where no level set it); later ones read, merge and write back the groups
+// that gained entries.
+constexpr int RING = 8;
+constexpr int FW_WORDS = SB / 8; // words per block of the flush
+__global__ __launch_bounds__(SB) void k_ls_flush(int32_t n, int32_t W, int32_t sp, const uint64_t *__restrict__ ring,
+                                                 int32_t L0, int32_t nl, int32_t first,
+                                                 const uint32_t *__restrict__ found, uint16_t *__restrict__ dT) {
+    __shared__ uint64_t sw[RING][FW_WORDS];
+    uint32_t live = 0; // bit q: level L0 + q found something (level 0: the sources)
+    for (int32_t q = 0; q < nl; ++q)
+        if (L0 + q == 0 || found[L0 + q]) live |= 1u << q;
+    if (!first && !live) return;
+    const size_t words = (size_t)n * W;
+    const size_t base = (size_t)blockIdx.x * FW_WORDS;
+    {
+        const int q = threadIdx.x / FW_WORDS, i = threadIdx.x % FW_WORDS;
+        uint64_t x = 0;
+        if (((live >> q) & 1u) && base + i < words) x = ring[(size_t)((L0 + q) % RING) * words + base + i];
+        sw[q][i] = x;
+    }
+    __syncthreads();
+    const int i = threadIdx.x >> 3, g = threadIdx.x & 7;
+    const size_t vw = base + i;
+    if (vw >= words) return;
+    uint32_t ga = 0, g0 = 0, g1 = 0, g2 = 0;
+#pragma unroll
+    for (int q = 0; q < RING; ++q) {
+        const uint32_t x = (uint32_t)(sw[q][i] >> (8 * g)) & 0xFFu;
+        ga |= x;
+        if (q & 1) g0 |= x;
+        if (q & 2) g1 |= x;
+        if (q & 4) g2 |= x;
+    }
+    if (!first && !ga) return;
+    const int32_t v = (int32_t)(vw / W), w = (int32_t)(vw % W);
+    uint4 *dst = (uint4 *)(dT + (size_t)v * sp + 64 * w + 8 * g);
+    uint32_t out[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
+    if (!first) {
+        const uint4 o = *dst;
+        out[0] = o.x;
+        out[1] = o.y;
+        out[2] = o.z;
+        out[3] = o.w;
+    }
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+        if ((ga >> b) & 1u) {
+            const uint32_t lv = (uint32_t)L0 + (((g0 >> b) & 1u) | (((g1 >> b) & 1u) << 1) | (((g2 >> b) & 1u) << 2));
+            const int sh = 16 * (b & 1);
+            out[b >> 1] = (out[b >> 1] & ~(0xFFFFu << sh)) | (lv << sh);
+        }
+    *dst = make_uint4(out[0], out[1], out[2], out[3]);
 }
 
 // Level L: one wave per chunk (v, first arc); chunks below nsplit belong to
 // vertices with more than CH arcs and leave their OR in P.
 __global__ __launch_bounds__(SB) void k_ls_level(int32_t nchunks, int32_t nsplit, const int2 *__restrict__ chunks,
                                                  const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
-                                                 int32_t W, int32_t ns, int32_t sp, int32_t L,
-                                                 const uint64_t *__restrict__ F, uint64_t *__restrict__ N,
+                                                 int32_t W, int32_t ns, int32_t L, const uint64_t *__restrict__ F, uint64_t *__restrict__ N,
                                                  uint64_t *__restrict__ V, uint64_t *__restrict__ P,
-                                                 uint16_t *__restrict__ dT, uint32_t *__restrict__ found) {
+                                                 uint32_t *__restrict__ found) {
+    if (L > 1 && found[L - 1] == 0) return; // empty frontier: nothing to do, the flush skips this level
     const int lane = threadIdx.x & 63;
     const int32_t c = __builtin_amdgcn_readfirstlane(blockIdx.x * (SB / 64) + (threadIdx.x >> 6));
     if (c >= nchunks) return;
@@ -120,15 +173,14 @@ __global__ __launch_bounds__(SB) void k_ls_level(int32_t nchunks, int32_t nsplit
         if (lane < W) P[(size_t)c * W + lane] = acc;
         return;
     }
-    ls_settle(v, lane, W, sp, acc, vis, rows, L, N, V, dT, found);
+    ls_settle(v, lane, W, acc, vis, rows, L, N, V, found);
 }
 
 // Level L for the split vertices: OR of their chunks' partial results.
 __global__ __launch_bounds__(SB) void k_ls_finish(int32_t nsv, const int32_t *__restrict__ sv,
-                                                  const int32_t *__restrict__ sc, int32_t W, int32_t ns, int32_t sp,
-                                                  int32_t L, const uint64_t *__restrict__ P, uint64_t *__restrict__ N,
-                                                  uint64_t *__restrict__ V, uint16_t *__restrict__ dT,
-                                                  uint32_t *__restrict__ found) {
+                                                  const int32_t *__restrict__ sc, int32_t W, int32_t ns, int32_t L, const uint64_t *__restrict__ P, uint64_t *__restrict__ N,
+                                                  uint64_t *__restrict__ V, uint32_t *__restrict__ found) {
+    if (L > 1 && found[L - 1] == 0) return;
     const int lane = threadIdx.x & 63;
     const int32_t j = __builtin_amdgcn_readfirstlane(blockIdx.x * (SB / 64) + (threadIdx.x >> 6));
     if (j >= nsv) return;
@@ -143,7 +195,7 @@ __global__ __launch_bounds__(SB) void k_ls_finish(int32_t nsv, const int32_t *__
         for (; c < ce; ++c) acc |= P[(size_t)c * W + lane];
     }
     const uint64_t vis = lane < W ? V[(size_t)v * W + lane] : 0;
-    ls_settle(v, lane, W, sp, acc, vis, word_rows(lane, ns), L, N, V, dT, found);
+    ls_settle(v, lane, W, acc, vis, word_rows(lane, ns), L, N, V, found);
 }
 
 // Step 3: H[j][i] = d'(S_i, S_j) = dT[S_j][i] (symmetric: the graph is
@@ -240,9 +292,10 @@ enum MinPlusMode { MP_OUT = 0, MP_LOWER = 1, MP_LOWER_SYM = 2 };
 // Min-plus product over k of A[m][k] + B[n][k]: A int32 [M][lda], B [N][ldb]
 // (int32, or uint16 distances with DINF), both with k contiguous, K a
 // multiple of KC, rows 16-byte aligned; with brow, column n takes B row
-// brow[n].  The next k step's operands are loaded while this one computes.  Tiles of T = 16R rows and columns;
-// 256 threads, each an R x R block, through k-major LDS in KC steps, two k per
-// step so that the compiler fuses the two minima (v_min3).
+// brow[n].  Tiles of T = 16R rows and columns; 256 threads, each an R x R
+// block, through k-major LDS in KC steps (the next step's operands load while
+// this one computes), two k per step so that the compiler fuses the two
+// minima (v_min3).
 //   MP_OUT        C = the product, -1 where it stays HINF or above
 //   MP_LOWER      C = min(C, product), stored only where it decreases; with
 //                 CT, also CT[n][m] where the result is below it
@@ -568,8 +621,7 @@ bc_status sampled_distances(bc_ctx *ctx, const int32_t *h_sources, int32_t count
     int32_t *dS = (int32_t *)bc_dalloc(ctx, sizeof(int32_t) * (size_t)sp);
     uint16_t *dT = (uint16_t *)bc_dalloc(ctx, sizeof(uint16_t) * (size_t)sp * n);
     int32_t *H = (int32_t *)bc_dalloc(ctx, sizeof(int32_t) * (size_t)sp * sp);
-    uint64_t *front = (uint64_t *)bc_dalloc(ctx, sizeof(uint64_t) * bits);
-    uint64_t *next = (uint64_t *)bc_dalloc(ctx, sizeof(uint64_t) * bits);
+    uint64_t *ring = (uint64_t *)bc_dalloc(ctx, sizeof(uint64_t) * bits * RING);
     uint64_t *visited = (uint64_t *)bc_dalloc(ctx, sizeof(uint64_t) * bits);
     uint64_t *part = (uint64_t *)bc_dalloc(ctx, sizeof(uint64_t) * (size_t)std::max(nsplit, 1) * W);
     int2 *dchunks = (int2 *)bc_dalloc(ctx, sizeof(int2) * (size_t)nchunks);
@@ -584,13 +636,13 @@ bc_status sampled_distances(bc_ctx *ctx, const int32_t *h_sources, int32_t count
                                                : nullptr;
     std::vector<uint32_t> found_h((size_t)k + 1);
     auto cleanup = [&]() {
-        for (void *q : {(void *)dS, (void *)dT, (void *)H, (void *)front, (void *)next, (void *)visited, (void *)part,
+        for (void *q : {(void *)dS, (void *)dT, (void *)H, (void *)ring, (void *)visited, (void *)part,
                         (void *)dchunks, (void *)dsv, (void *)found, (void *)a16})
             bc_dfree(ctx, q);
         if (!direct) bc_dfree(ctx, outc);
         bc_dfree(ctx, drow);
     };
-    if (!dS || !dT || !H || !front || !next || !visited || !part || !dchunks || !dsv || !found || !a16 || !outc ||
+    if (!dS || !dT || !H || !ring || !visited || !part || !dchunks || !dsv || !found || !a16 || !outc ||
         (out_on_device && !in_order && !drow)) {
         cleanup();
         return bc_fail(ctx, BC_ERR_NOMEM, "sampled forward: allocation failed");
@@ -606,7 +658,7 @@ bc_status sampled_distances(bc_ctx *ctx, const int32_t *h_sources, int32_t count
         e = hipMemcpyAsync(dchunks, chunks.data(), sizeof(int2) * chunks.size(), hipMemcpyHostToDevice, ctx->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(dsv, svsc.data(), sizeof(int32_t) * svsc.size(), hipMemcpyHostToDevice, ctx->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(front, 0, sizeof(uint64_t) * bits, ctx->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(ring, 0, sizeof(uint64_t) * bits, ctx->stream); // level 0
     if (e == hipSuccess) e = hipMemsetAsync(visited, 0, sizeof(uint64_t) * bits, ctx->stream);
     if (e == hipSuccess) e = hipMemsetAsync(found, 0, sizeof(uint32_t) * (size_t)(k + 2), ctx->stream);
     if (e != hipSuccess) return fail_hip(e, "sampled forward: upload");
@@ -615,31 +667,38 @@ bc_status sampled_distances(bc_ctx *ctx, const int32_t *h_sources, int32_t count
         cleanup();
         return st;
     }
-    static_assert(DINF == 0xFFFF, "the fill writes all-ones words");
-    hipLaunchKernelGGL(k_fill_dinf, dim3(blocks_for((size_t)sp * n / 8)), dim3(SB), 0, ctx->stream, (uint4 *)dT,
-                       (size_t)sp * n / 8);
-    hipLaunchKernelGGL(k_ls_sources, dim3(blocks_for((size_t)ns)), dim3(SB), 0, ctx->stream, ns, dS, W, sp, front,
-                       visited, dT);
-    // step 2: every row of S advances one level per launch
+    hipLaunchKernelGGL(k_ls_sources, dim3(blocks_for((size_t)ns)), dim3(SB), 0, ctx->stream, ns, dS, W, ring,
+                       visited);
+    // step 2: every row of S advances one level per launch; level L's new bits
+    // go to ring slot L % RING (the next level's frontier), and every RING
+    // levels (and at the end) they are written into d'
     {
         LaunchTimer tm(ctx, "limited_bfs");
-        uint64_t *f = front, *g = next;
         const unsigned level_blocks = (unsigned)((nchunks + SB / 64 - 1) / (SB / 64));
         const unsigned finish_blocks = (unsigned)((nsv + SB / 64 - 1) / (SB / 64));
+        const unsigned flush_blocks = (unsigned)((bits + FW_WORDS - 1) / FW_WORDS);
+        int32_t flushed = 0; // levels below this one are in d'
         for (int32_t L = 1; L <= k; ++L) {
+            const uint64_t *f = ring + (size_t)((L - 1) % RING) * bits;
+            uint64_t *g = ring + (size_t)(L % RING) * bits;
             hipLaunchKernelGGL(k_ls_level, dim3(level_blocks), dim3(SB), 0, ctx->stream, nchunks, nsplit, dchunks,
-                               ctx->row_ptr, ctx->col, W, ns, sp, L, f, g, visited, part, dT, found);
+                               ctx->row_ptr, ctx->col, W, ns, L, f, g, visited, part, found);
             if (nsv > 0)
                 hipLaunchKernelGGL(k_ls_finish, dim3(finish_blocks), dim3(SB), 0, ctx->stream, nsv, dsv,
-                                   dsv + nsv, W, ns, sp, L, part, g, visited, dT, found);
-            std::swap(f, g);
-            // every 8 levels: stop once a level found nothing new
-            if (L % 8 == 0 || L == k) {
+                                   dsv + nsv, W, ns, L, part, g, visited, found);
+            if (L % RING == RING - 1 || L == k) {
                 e = hipMemcpyAsync(found_h.data(), found, sizeof(uint32_t) * (size_t)(k + 1), hipMemcpyDeviceToHost,
                                    ctx->stream);
                 if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
                 if (e != hipSuccess) return fail_hip(e, "sampled forward: level read-back");
-                if (found_h[(size_t)L] == 0) break;
+                bool news = flushed == 0; // the first flush also writes every unreached entry
+                for (int32_t q = flushed; q <= L; ++q) news = news || found_h[(size_t)q] != 0;
+                if (news)
+                    hipLaunchKernelGGL(k_ls_flush, dim3(flush_blocks), dim3(SB), 0, ctx->stream, n, W, sp,
+                                       (const uint64_t *)ring, flushed, L - flushed + 1, flushed == 0 ? 1 : 0,
+                                       (const uint32_t *)found, dT);
+                flushed = L + 1;
+                if (found_h[(size_t)L] == 0) break; // a level found nothing new: the searches are over
             }
         }
         tm.done();
