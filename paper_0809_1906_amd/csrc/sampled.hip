@@ -484,6 +484,17 @@ __global__ __launch_bounds__(SB) void k_dh16(int32_t M, int32_t sp, const int32_
 // of 128 x 128 through k-major LDS in steps of 64; each thread an 8 x 8 block;
 // result -1 where no walk was found.
 constexpr int KH = 64, PH = 128 + 8; // k step and LDS pitch (uint16) of the 16-bit product
+
+// Eight k values of rows r and r + 1 (x0, x1: one 16-byte load each) into the
+// k-major tile, each k as one 32-bit word holding both rows.
+__device__ inline void stage_pairs(uint16_t (*s)[PH], int kk, int r, uint4 x0, uint4 x1) {
+    const uint32_t u0[4] = {x0.x, x0.y, x0.z, x0.w}, u1[4] = {x1.x, x1.y, x1.z, x1.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        *(uint32_t *)&s[kk + 2 * q][r] = (u0[q] & 0xFFFFu) | (u1[q] << 16);
+        *(uint32_t *)&s[kk + 2 * q + 1][r] = (u0[q] >> 16) | (u1[q] & 0xFFFF0000u);
+    }
+}
 __global__ __launch_bounds__(SB) void k_minplus16(int32_t M, int32_t N, int32_t K, const uint16_t *__restrict__ A,
                                                   const uint16_t *__restrict__ B, int64_t ld,
                                                   const int32_t *__restrict__ brow, int32_t *__restrict__ C,
@@ -504,26 +515,32 @@ __global__ __launch_bounds__(SB) void k_minplus16(int32_t M, int32_t N, int32_t 
     const int pr = 2 * (t & 63);
     const uint16_t *bp0 = n0 + pr < N ? B + (size_t)(brow ? brow[n0 + pr] : n0 + pr) * ld : nullptr;
     const uint16_t *bp1 = n0 + pr + 1 < N ? B + (size_t)(brow ? brow[n0 + pr + 1] : n0 + pr + 1) * ld : nullptr;
+    // the next k step's staging words, loaded while this one computes:
+    // rows pr and pr + 1 of A and of B at k chunks kk0 and kk1
+    const int kk0 = (t >> 6) * 8, kk1 = kk0 + 32;
+    const uint4 none = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
+    const uint16_t *ap0 = m0 + pr < M ? A + (size_t)(m0 + pr) * ld : nullptr;
+    const uint16_t *ap1 = m0 + pr + 1 < M ? A + (size_t)(m0 + pr + 1) * ld : nullptr;
+    uint4 a00, a01, a10, a11, b00, b01, b10, b11; // [chunk][row of the pair]
+#define MP16_LOAD(k0)                                                                                          \
+    do {                                                                                                       \
+        a00 = ap0 ? *(const uint4 *)(ap0 + (k0) + kk0) : none;                                                 \
+        a01 = ap1 ? *(const uint4 *)(ap1 + (k0) + kk0) : none;                                                 \
+        a10 = ap0 ? *(const uint4 *)(ap0 + (k0) + kk1) : none;                                                 \
+        a11 = ap1 ? *(const uint4 *)(ap1 + (k0) + kk1) : none;                                                 \
+        b00 = bp0 ? *(const uint4 *)(bp0 + (k0) + kk0) : none;                                                 \
+        b01 = bp1 ? *(const uint4 *)(bp1 + (k0) + kk0) : none;                                                 \
+        b10 = bp0 ? *(const uint4 *)(bp0 + (k0) + kk1) : none;                                                 \
+        b11 = bp1 ? *(const uint4 *)(bp1 + (k0) + kk1) : none;                                                 \
+    } while (0)
+    MP16_LOAD(0);
     for (int32_t k0 = 0; k0 < K; k0 += KH) {
-#pragma unroll
-        for (int p = 0; p < 2; ++p) {
-            const int kk = ((t >> 6) + 4 * p) * 8;
-            uint4 a0 = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu), a1 = a0, b0 = a0, b1 = a0;
-            if (m0 + pr < M) a0 = *(const uint4 *)(A + (size_t)(m0 + pr) * ld + k0 + kk);
-            if (m0 + pr + 1 < M) a1 = *(const uint4 *)(A + (size_t)(m0 + pr + 1) * ld + k0 + kk);
-            if (bp0) b0 = *(const uint4 *)(bp0 + k0 + kk);
-            if (bp1) b1 = *(const uint4 *)(bp1 + k0 + kk);
-            const uint32_t x0[4] = {a0.x, a0.y, a0.z, a0.w}, x1[4] = {a1.x, a1.y, a1.z, a1.w};
-            const uint32_t y0[4] = {b0.x, b0.y, b0.z, b0.w}, y1[4] = {b1.x, b1.y, b1.z, b1.w};
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                *(uint32_t *)&sA[kk + 2 * q][pr] = (x0[q] & 0xFFFFu) | (x1[q] << 16);
-                *(uint32_t *)&sA[kk + 2 * q + 1][pr] = (x0[q] >> 16) | (x1[q] & 0xFFFF0000u);
-                *(uint32_t *)&sB[kk + 2 * q][pr] = (y0[q] & 0xFFFFu) | (y1[q] << 16);
-                *(uint32_t *)&sB[kk + 2 * q + 1][pr] = (y0[q] >> 16) | (y1[q] & 0xFFFF0000u);
-            }
-        }
+        stage_pairs(sA, kk0, pr, a00, a01);
+        stage_pairs(sA, kk1, pr, a10, a11);
+        stage_pairs(sB, kk0, pr, b00, b01);
+        stage_pairs(sB, kk1, pr, b10, b11);
         __syncthreads();
+        if (k0 + KH < K) MP16_LOAD(k0 + KH);
 #pragma unroll 4
         for (int k = 0; k < KH; ++k) {
             const uint4 av = *(const uint4 *)&sA[k][ty * 8];
@@ -541,6 +558,7 @@ __global__ __launch_bounds__(SB) void k_minplus16(int32_t M, int32_t N, int32_t 
         }
         __syncthreads();
     }
+#undef MP16_LOAD
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
         const int32_t m = m0 + ty * 8 + i;
