@@ -59,6 +59,11 @@ MFMA_BF16_PEAK_TFS = 2500.0
 # 32-bit integer vector operations: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz
 VALU_INT32_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
+# HIP event pairs on every launch of one source batch in TIMING_SAMPLE during
+# the timed steps (batches are alike, so the per-launch averages keep every
+# level's share; every launch is counted)
+TIMING_SAMPLE = 5
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sparse_rmat16_traffic.txt")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_0809_1906_amd", "csrc", "sparse.hip")
 
@@ -218,7 +223,8 @@ def roofline(name, wl, kern, info, steps):
     dom = max(kern, key=lambda k: kern[k][0])
     ms, launches = kern[dom]
     n, m, S = wl["n"], wl["m"], wl["S"]
-    base = {"kernel": dom, "avg_launch_ms": ms / max(launches, 1), "launches": launches}
+    base = {"kernel": dom, "avg_launch_ms": ms / max(launches, 1), "launches": launches,
+            "timed_one_batch_in": TIMING_SAMPLE}
     if dom in ("mfma_fwd", "mfma_bwd"):
         npad = (n + 255) // 256 * 256
         # with weights 1..M a product runs over K = M * npad (one class each)
@@ -467,7 +473,7 @@ def main():
         return
     src, work = wl["src"], wl["work"]
 
-    def timed_runs(form, steps, warmup, batch=0, timing=True, edges=False):
+    def timed_runs(form, steps, warmup, batch=0, timing=TIMING_SAMPLE, edges=False):
         t = time.perf_counter()
         ctx = bcgpu.BC(wl["graph"], form="auto" if form == "many" else form, batch=batch, timing=timing,
                        edges=edges)

@@ -136,7 +136,7 @@ typedef struct {
     int32_t device;       /* HIP device ordinal; -1 = the current device */
     void *stream;         /* hipStream_t to run on; NULL = the null stream */
     bc_allocator allocator;
-    int32_t timing;       /* nonzero: time every kernel launch with HIP events */
+    int32_t timing;       /* 0: off; k >= 1: HIP events on the launches of one source batch in k */
     int32_t split_degree; /* batched forms: rows longer than this are split into
                              segments of this many arcs; 0 = default (128) */
     int32_t vertex_order; /* internal vertex numbering (a device layout choice that
@@ -327,11 +327,15 @@ typedef struct {
 bc_status bc_get_info(const bc_ctx *ctx, bc_info *out);
 
 /*
- * Kernel timing (contexts created with timing != 0).  For the kernel named
- * `kernel` (e.g. "plain_sweep", "fwd_pull", "bwd_pull"), returns the summed
- * duration in milliseconds of its launches since create / reset, measured
- * with HIP events on the context's stream, and the number of launches.
- * Unknown names give zero.  Synchronises the stream.
+ * Kernel timing (contexts created with timing = k >= 1).  For the kernel
+ * named `kernel` (e.g. "plain_sweep", "fwd_pull", "bwd_pull"), returns the
+ * number of its launches since create / reset and their summed duration in
+ * milliseconds, measured with HIP events on the context's stream.  With k = 1
+ * every launch is timed; with k > 1 the batched forms time every launch of
+ * the first source batch and then of every k-th (so every level keeps its
+ * share), the total being scaled from the timed launches to all of them;
+ * forms without batches time every launch.  Unknown names give zero.
+ * Synchronises the stream.  bc_create refuses a negative k.
  */
 bc_status bc_get_timing(bc_ctx *ctx, const char *kernel, double *total_ms, int64_t *launches);
 

@@ -245,7 +245,7 @@ class BC:
     """
 
     def __init__(self, graph, form: str = "auto", batch: int = 0, device: int = 0, stream=None,
-                 allocator: str = "torch", timing: bool = False, split_degree: int = 0,
+                 allocator: str = "torch", timing=False, split_degree: int = 0,
                  vertex_order: str = "degree", arena_log2: int = 0, tune_cache: Optional[str] = None,
                  grid: int = 0, edges: bool = False):
         import torch
@@ -263,7 +263,7 @@ class BC:
         opt.batch = batch
         opt.device = device
         opt.stream = self._stream.cuda_stream
-        opt.timing = 1 if timing else 0
+        opt.timing = int(timing)  # False / True / k: events on one launch in k
         opt.split_degree = split_degree
         opt.vertex_order = {"degree": 0, "input": 1}[vertex_order]
         opt.arena_log2 = arena_log2

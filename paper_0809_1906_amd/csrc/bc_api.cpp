@@ -186,10 +186,16 @@ void bc_timers_clear(bc_ctx *ctx) {
             bc_event_put(ctx, pr.second);
         }
     ctx->timers.clear();
+    ctx->timing_batches = 0;
+    ctx->timing_sel = true;
+}
+
+void bc_timing_batch(bc_ctx *ctx) {
+    if (ctx->timing > 1) ctx->timing_sel = ctx->timing_batches++ % ctx->timing == 0;
 }
 
 LaunchTimer::LaunchTimer(bc_ctx *c, const char *nm) : ctx(c), name(nm) {
-    if (!ctx->timing) return;
+    if (!ctx->timing || !ctx->timing_sel) return;
     a = bc_event_get(ctx);
     b = bc_event_get(ctx);
     if (a && b) {
@@ -202,11 +208,13 @@ LaunchTimer::LaunchTimer(bc_ctx *c, const char *nm) : ctx(c), name(nm) {
 }
 
 void LaunchTimer::done() {
-    if (!ctx->timing || !a) return;
-    hipEventRecord(b, ctx->stream);
+    if (!ctx->timing) return;
     auto &t = ctx->timers[name];
-    t.pending.emplace_back(a, b);
     t.launches += 1;
+    if (!a) return;
+    hipEventRecord(b, ctx->stream);
+    t.pending.emplace_back(a, b);
+    t.timed += 1;
     a = b = nullptr;
 }
 
@@ -269,6 +277,7 @@ bc_status bc_create(const bc_graph *g, const bc_options *opt_in, bc_ctx **out) {
         return fail_create(BC_ERR_INVALID_ARG, "arena_log2 must be in [0, 30]");
     if (opt.grid < 0 || opt.grid > 65536)
         return fail_create(BC_ERR_INVALID_ARG, "grid must be in [0, 65536]");
+    if (opt.timing < 0) return fail_create(BC_ERR_INVALID_ARG, "timing must be 0 (off) or k >= 1 (one launch in k)");
     if (opt.split_degree != 0 && opt.split_degree < 64)
         return fail_create(BC_ERR_INVALID_ARG, "split_degree must be 0 (default) or at least 64");
     if ((opt.allocator.alloc == nullptr) != (opt.allocator.free == nullptr))
@@ -323,7 +332,7 @@ bc_status bc_create(const bc_graph *g, const bc_options *opt_in, bc_ctx **out) {
     ctx->weighted = hw != nullptr;
     ctx->stream = (hipStream_t)opt.stream;
     ctx->alloc = opt.allocator;
-    ctx->timing = opt.timing != 0;
+    ctx->timing = opt.timing;
     ctx->form = form;
 
     auto bail = [&](bc_status s, const std::string &m) {
@@ -466,6 +475,7 @@ bc_status bc_create_many(const bc_graph *gs, int32_t count, const bc_options *op
     }
     if (opt.batch < 0) return fail_create(BC_ERR_INVALID_ARG, "batch must be >= 0");
     if (opt.edges) return fail_create(BC_ERR_UNSUPPORTED, "bc_create_many computes vertex betweenness only");
+    if (opt.timing < 0) return fail_create(BC_ERR_INVALID_ARG, "timing must be 0 (off) or k >= 1 (one launch in k)");
     if ((opt.allocator.alloc == nullptr) != (opt.allocator.free == nullptr))
         return fail_create(BC_ERR_INVALID_ARG, "allocator needs both alloc and free, or neither");
     // host validation of every graph, then the concatenated layout
@@ -510,7 +520,7 @@ bc_status bc_create_many(const bc_graph *gs, int32_t count, const bc_options *op
     ctx->max_degree = max_deg;
     ctx->stream = (hipStream_t)opt.stream;
     ctx->alloc = opt.allocator;
-    ctx->timing = opt.timing != 0;
+    ctx->timing = opt.timing;
     ctx->form = BC_FORM_MANY;
     ctx->many = true;
     auto bail = [&](bc_status s, const std::string &m) {
@@ -835,8 +845,9 @@ bc_status bc_get_timing(bc_ctx *ctx, const char *kernel, double *total_ms, int64
         bc_event_put(ctx, pr.second);
     }
     it->second.pending.clear();
-    *total_ms = it->second.total_ms;
-    *launches = it->second.launches;
+    const KernelTimer &t = it->second;
+    *total_ms = t.timed ? t.total_ms * (double)t.launches / (double)t.timed : 0.0;
+    *launches = t.launches;
     return BC_OK;
 }
 

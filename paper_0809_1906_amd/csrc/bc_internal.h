@@ -19,8 +19,9 @@ enum : uint32_t {
 // Timing of one kernel name: HIP event pairs not yet folded into total_ms.
 struct KernelTimer {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
-    double total_ms = 0.0;
+    double total_ms = 0.0; // summed over the timed launches
     int64_t launches = 0;
+    int64_t timed = 0;     // launches that carried an event pair
 };
 
 // State of the batched sparse form (per-level frontier bitmaps).
@@ -191,7 +192,9 @@ struct bc_ctx {
     bool overflow_seen = false;
     std::string err;
 
-    bool timing = false;
+    int32_t timing = 0;         // 0 off; k >= 1: events on the launches of one source batch in k
+    int64_t timing_batches = 0; // batches begun since create / reset
+    bool timing_sel = true;     // the current batch's launches carry events
     std::map<std::string, KernelTimer> timers;
     std::vector<hipEvent_t> event_pool; // timing events ready for reuse
 };
@@ -207,7 +210,12 @@ hipEvent_t bc_event_get(bc_ctx *ctx);
 void bc_event_put(bc_ctx *ctx, hipEvent_t e);
 // Returns every pending kernel-timer event to the pool and zeroes the timers.
 void bc_timers_clear(bc_ctx *ctx);
-// Records an event pair around a launch when timing is on.
+// Records an event pair around a launch when timing is on and the current
+// source batch is timed; every launch is counted.  bc_timing_batch marks the
+// start of a batch: with timing = k > 1 every launch of one batch in k carries
+// events, so per-launch averages keep every level's share.  Work outside
+// batches is timed whenever timing is on.
+void bc_timing_batch(bc_ctx *ctx);
 struct LaunchTimer {
     bc_ctx *ctx;
     const char *name;

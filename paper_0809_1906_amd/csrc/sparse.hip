@@ -977,6 +977,7 @@ bc_status sparse_run(bc_ctx *ctx, const int32_t *d_src, int64_t count) {
     const int32_t B = ctx->sp.batch;
     for (int64_t b0 = 0; b0 < count; b0 += B) {
         int32_t nlev = 0;
+        bc_timing_batch(ctx); // with sampled timing, this batch's launches are timed or not as a whole
         bc_status st = run_batch(ctx, d_src + b0, (int32_t)std::min<int64_t>(B, count - b0), true, &nlev);
         if (st != BC_OK) return st;
     }

@@ -127,6 +127,9 @@ def test_invalid_arguments():
     opt = bcgpu.bc_options_init()
     opt.form = 42
     assert lib.bc_create(ctypes.byref(g), ctypes.byref(opt), ctypes.byref(ctx)) == B.BC_ERR_INVALID_ARG
+    opt = bcgpu.bc_options_init()
+    opt.timing = -1  # timing is 0 (off) or one launch in k >= 1
+    assert lib.bc_create(ctypes.byref(g), ctypes.byref(opt), ctypes.byref(ctx)) == B.BC_ERR_INVALID_ARG
     # calls on a NULL context
     assert lib.bc_run(None, None, -1, 0) == B.BC_ERR_INVALID_ARG
     assert lib.bc_read(None, None, 0) == B.BC_ERR_INVALID_ARG
