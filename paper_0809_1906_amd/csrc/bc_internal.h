@@ -121,8 +121,10 @@ struct WeightedState {
 constexpr int MG_MAX_N = 4096; // largest graph a many-graph context takes
 struct MultiState {
     int32_t ngraphs = 0, nunits = 0, chunk = 64, grid = 0;
+    int32_t ncompact = 0;             // units [0, ncompact) go to the compact sweep first
     int32_t *voff = nullptr, *rpoff = nullptr, *rp = nullptr, *units = nullptr;
-    unsigned int *next = nullptr;
+    int32_t *redo = nullptr;          // compact units handed back to the full sweep
+    unsigned int *next = nullptr;     // queue counters: compact, full, redo; [3] = redo count
     std::vector<int32_t> h_voff;
     hipStream_t stream = nullptr;     // private stream the launch is captured on
     hipEvent_t ev = nullptr;

@@ -15,8 +15,20 @@
 // entirely in LDS; each unit's dependencies are summed in an FP64 LDS vector
 // and added to BC once per unit.  The unit's columns are staged in LDS as
 // 16-bit local ids when they fit (n <= 4096), so that a level step waits on
-// LDS only; larger graphs read them from global memory.  The launch (a queue-counter reset kernel and
-// the persistent kernel) is captured once into a HIP graph and replayed.
+// LDS only; larger graphs read them from global memory.
+//
+// The level steps are latency-bound, so a compact sweep runs first with two
+// workgroups per compute unit.  Each takes under half of the LDS:
+// - 16-bit distances;
+// - 32-bit counts, each overwritten by c(v) in the backward once v's own
+//   dependency is known;
+// - at most LEVCAP levels;
+// - 16-bit row offsets and columns read through the caches.
+// It takes the graphs with at most 65535 arcs. A unit whose counts pass 2^32
+// - 1 or whose depth passes LEVCAP drops its partial sums and is handed to the
+// full sweep. The launches (counter reset, compact sweep, full sweep over the
+// remaining graphs, full sweep over the handed-back units) are captured once
+// into a HIP graph and replayed.
 #include "bc_internal.h"
 
 #include <algorithm>
@@ -27,6 +39,8 @@ constexpr int MT = 512;          // threads per workgroup
 constexpr int32_t MG_INF = 0x7FFFFFFF;
 constexpr int ABURST = 8;        // column reads issued together per vertex
 constexpr int32_t COL_CAP = 16320; // 16-bit columns staged in LDS
+constexpr int LEVCAP = 1024;       // levels per source in the compact sweep
+constexpr uint32_t D16_INF = 0xFFFF;
 
 struct MultiArgs {
     const int32_t *voff;   // [ngraphs+1] first global vertex of each graph
@@ -35,7 +49,10 @@ struct MultiArgs {
     const int32_t *col;    // concatenated arcs, local vertex ids
     const int32_t *units;  // [nunits][3] = (graph, s0, s1), local source ids
     int32_t nunits;
+    const unsigned int *nunits_dev; // if set, the unit count is read here instead
     unsigned int *next;    // queue counter
+    int32_t *redo;         // compact sweep: units handed to the full sweep
+    unsigned int *redo_count;
     double *bc;            // [sum n]
     uint32_t *status;
     // per-source readout (bc_read_sssp): unit u covers one source, row u
@@ -45,7 +62,9 @@ struct MultiArgs {
     double *delta_dump;
 };
 
-__global__ void k_mg_reset(unsigned int *next) { *next = 0; }
+__global__ void k_mg_reset(unsigned int *next) {
+    if (threadIdx.x < 4) next[threadIdx.x] = 0;
+}
 
 struct MgShared {
     int32_t dist[MG_MAX_N];
@@ -172,11 +191,12 @@ __device__ __forceinline__ void mg_unit(const MultiArgs &a, MgShared &sh, int32_
 __global__ __launch_bounds__(MT) void k_mg_sweep(MultiArgs a) {
     __shared__ MgShared sh;
     const int tid = threadIdx.x;
+    const int32_t nunits = a.nunits_dev ? (int32_t)*a.nunits_dev : a.nunits;
     for (;;) {
         if (tid == 0) sh.unit = (int32_t)atomicAdd(a.next, 1u);
         __syncthreads();
         const int32_t u = sh.unit;
-        if (u >= a.nunits) break;
+        if (u >= nunits) break;
         const int32_t g = a.units[3 * u], s0 = a.units[3 * u + 1], s1 = a.units[3 * u + 2];
         const int32_t vo = a.voff[g], n = a.voff[g + 1] - vo;
         const int32_t *grp = a.rp + a.rpoff[g];
@@ -195,6 +215,157 @@ __global__ __launch_bounds__(MT) void k_mg_sweep(MultiArgs a) {
             for (int32_t v = tid; v < n; v += MT)
                 if (sh.bc[v] != 0.0) unsafeAtomicAdd(&a.bc[vo + v], sh.bc[v]);
         if (tid == 0 && sh.ovf) atomicOr(a.status, (uint32_t)BC_DEV_SIGMA_OVERFLOW);
+        __syncthreads();
+    }
+}
+
+// ---- the compact sweep ------------------------------------------------------------
+
+struct MgCompact {
+    uint32_t dist2[MG_MAX_N / 2]; // two 16-bit distances per word, D16_INF = unreached
+    uint32_t sc[MG_MAX_N];        // the count (uint32) in the forward; c(v) (float bits) after v's backward step
+    uint16_t queue[MG_MAX_N];
+    uint16_t lev[LEVCAP + 2];
+    double bc[MG_MAX_N];
+    uint16_t rp[MG_MAX_N + 1];    // row offsets relative to the graph's first arc
+    int32_t unit, cnt[3];
+    uint32_t fail;                // counts or depth out of range: the full sweep redoes the unit
+};
+
+__device__ __forceinline__ uint32_t d16_get(const uint32_t *d2, int32_t v) {
+    return (d2[v >> 1] >> (16 * (v & 1))) & 0xFFFFu;
+}
+
+// Level of w, claiming it for level nl when it is unreached (*claimed says so).
+__device__ __forceinline__ uint32_t d16_claim(uint32_t *d2, int32_t w, uint32_t nl, bool &claimed) {
+    const int sh = 16 * (w & 1);
+    uint32_t word = d2[w >> 1];
+    for (;;) {
+        const uint32_t cur = (word >> sh) & 0xFFFFu;
+        if (cur != D16_INF) {
+            claimed = false;
+            return cur;
+        }
+        const uint32_t want = (word & ~(0xFFFFu << sh)) | (nl << sh);
+        const uint32_t old = atomicCAS(&d2[w >> 1], word, want);
+        if (old == word) {
+            claimed = true;
+            return nl;
+        }
+        word = old; // the other half changed, or another thread claimed w
+    }
+}
+
+// The sources [s0, s1) of the unit in sh (graph of n vertices, columns col).
+__device__ void mg_unit_compact(MgCompact &sh, int32_t n, const int32_t *__restrict__ col, int32_t s0, int32_t s1) {
+    const int tid = threadIdx.x;
+    for (int32_t s = s0; s < s1 && !sh.fail; ++s) {
+        for (int32_t v = tid; v < (n + 1) / 2; v += MT) sh.dist2[v] = 0xFFFFFFFFu;
+        for (int32_t v = tid; v < n; v += MT) sh.sc[v] = 0;
+        __syncthreads();
+        if (tid == 0) {
+            sh.dist2[s >> 1] &= ~(0xFFFFu << (16 * (s & 1))); // level 0
+            sh.sc[s] = 1;
+            sh.queue[0] = (uint16_t)s;
+            sh.lev[0] = 0;
+            sh.lev[1] = 1;
+            sh.cnt[0] = sh.cnt[1] = sh.cnt[2] = 0;
+        }
+        __syncthreads();
+        // forward: as in the full sweep (three counters, one barrier per level)
+        int32_t qb = 0, qe = 1, L = 0;
+        while (qb < qe) {
+            const int cur = L % 3;
+            if (tid == 0) sh.cnt[(L + 1) % 3] = 0;
+            for (int32_t i = qb + tid; i < qe; i += MT) {
+                const int32_t v = sh.queue[i];
+                const uint32_t sv = sh.sc[v];
+                const int32_t rb = sh.rp[v], re = sh.rp[v + 1];
+                for (int32_t e0 = rb; e0 < re; e0 += ABURST) {
+                    int32_t ws[ABURST];
+#pragma unroll
+                    for (int j = 0; j < ABURST; ++j) ws[j] = e0 + j < re ? col[e0 + j] : -1;
+#pragma unroll
+                    for (int j = 0; j < ABURST; ++j) {
+                        const int32_t w = ws[j];
+                        if (w < 0) continue;
+                        bool claimed = false;
+                        const uint32_t dw = d16_claim(sh.dist2, w, (uint32_t)(L + 1), claimed);
+                        if (claimed) sh.queue[qe + atomicAdd(&sh.cnt[cur], 1)] = (uint16_t)w;
+                        if (dw == (uint32_t)(L + 1)) { // v in P_s(w)
+                            const uint32_t old = atomicAdd(&sh.sc[w], sv);
+                            if (old + sv < old) sh.fail = 1;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            qb = qe;
+            qe += sh.cnt[cur];
+            ++L;
+            if (L + 1 > LEVCAP) {
+                if (tid == 0) sh.fail = 1;
+                break;
+            }
+            if (tid == 0) sh.lev[L + 1] = (uint16_t)qe;
+        }
+        __syncthreads();
+        if (sh.fail) break;
+        const int32_t nlev = L;
+        // backward: deepest level first; one thread per vertex; c(v) replaces
+        // the count of v (read only by v's own thread, just before)
+        for (int32_t l = nlev - 1; l >= 1; --l) {
+            for (int32_t i = sh.lev[l] + tid; i < sh.lev[l + 1]; i += MT) {
+                const int32_t v = sh.queue[i];
+                double acc = 0.0;
+                if (l + 1 < nlev) {
+                    const int32_t rb = sh.rp[v], re = sh.rp[v + 1];
+                    for (int32_t e0 = rb; e0 < re; e0 += ABURST) {
+                        int32_t ws[ABURST];
+#pragma unroll
+                        for (int j = 0; j < ABURST; ++j) ws[j] = e0 + j < re ? col[e0 + j] : -1;
+#pragma unroll
+                        for (int j = 0; j < ABURST; ++j)
+                            if (ws[j] >= 0 && d16_get(sh.dist2, ws[j]) == (uint32_t)(l + 1))
+                                acc += (double)__uint_as_float(sh.sc[ws[j]]);
+                    }
+                }
+                const double sv = (double)sh.sc[v];
+                const double dl = sv * acc;
+                sh.sc[v] = __float_as_uint((float)((1.0 + dl) / sv));
+                if (v != s) sh.bc[v] += dl;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__global__ __launch_bounds__(MT, 2) void k_mg_sweep_compact(MultiArgs a) {
+    __shared__ MgCompact sh;
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) sh.unit = (int32_t)atomicAdd(a.next, 1u);
+        __syncthreads();
+        const int32_t u = sh.unit;
+        if (u >= a.nunits) break;
+        const int32_t g = a.units[3 * u], s0 = a.units[3 * u + 1], s1 = a.units[3 * u + 2];
+        const int32_t vo = a.voff[g], n = a.voff[g + 1] - vo;
+        const int32_t *grp = a.rp + a.rpoff[g];
+        for (int32_t v = tid; v <= n; v += MT) sh.rp[v] = (uint16_t)(grp[v] - grp[0]);
+        for (int32_t v = tid; v < n; v += MT) sh.bc[v] = 0.0;
+        if (tid == 0) sh.fail = 0;
+        __syncthreads();
+        mg_unit_compact(sh, n, a.col + grp[0], s0, s1);
+        __syncthreads();
+        if (!sh.fail) {
+            for (int32_t v = tid; v < n; v += MT)
+                if (sh.bc[v] != 0.0) unsafeAtomicAdd(&a.bc[vo + v], sh.bc[v]);
+        } else if (tid == 0) {
+            const unsigned int k = atomicAdd(a.redo_count, 1u);
+            a.redo[3 * k] = g;
+            a.redo[3 * k + 1] = s0;
+            a.redo[3 * k + 2] = s1;
+        }
         __syncthreads();
     }
 }
@@ -240,22 +411,30 @@ bc_status multigraph_prepare(bc_ctx *ctx, const std::vector<int32_t> &voff, cons
     std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
         return voff[x + 1] - voff[x] > voff[y + 1] - voff[y];
     });
+    // the compact sweep's units first (graphs with at most 65535 arcs), then
+    // the others, each group longest first
     std::vector<int32_t> units;
-    for (int32_t g : order) {
-        const int32_t n = voff[g + 1] - voff[g];
-        for (int32_t s0 = 0; s0 < n; s0 += m.chunk) {
-            units.push_back(g);
-            units.push_back(s0);
-            units.push_back(std::min(n, s0 + m.chunk));
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int32_t g : order) {
+            const int32_t n = voff[g + 1] - voff[g];
+            const int32_t arcs = rp[(size_t)rpoff[(size_t)g] + n] - rp[(size_t)rpoff[(size_t)g]];
+            if ((arcs <= 65535) != (pass == 0)) continue;
+            for (int32_t s0 = 0; s0 < n; s0 += m.chunk) {
+                units.push_back(g);
+                units.push_back(s0);
+                units.push_back(std::min(n, s0 + m.chunk));
+            }
         }
+        if (pass == 0) m.ncompact = (int32_t)(units.size() / 3);
     }
     m.nunits = (int32_t)(units.size() / 3);
     m.voff = (int32_t *)bc_dalloc(ctx, voff.size() * sizeof(int32_t));
     m.rpoff = (int32_t *)bc_dalloc(ctx, std::max<size_t>(rpoff.size(), 1) * sizeof(int32_t));
     m.rp = (int32_t *)bc_dalloc(ctx, std::max<size_t>(rp.size(), 1) * sizeof(int32_t));
     m.units = (int32_t *)bc_dalloc(ctx, std::max<size_t>(units.size(), 3) * sizeof(int32_t));
+    m.redo = (int32_t *)bc_dalloc(ctx, (size_t)std::max(m.ncompact, 1) * 3 * sizeof(int32_t));
     m.next = (unsigned int *)bc_dalloc(ctx, 256);
-    if (!m.voff || !m.rpoff || !m.rp || !m.units || !m.next)
+    if (!m.voff || !m.rpoff || !m.rp || !m.units || !m.redo || !m.next)
         return bc_fail(ctx, BC_ERR_NOMEM, "many graphs: allocation failed");
     BC_HIP(ctx, hipMemcpy(m.voff, voff.data(), voff.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     if (!rpoff.empty())
@@ -274,12 +453,26 @@ bc_status multigraph_prepare(bc_ctx *ctx, const std::vector<int32_t> &voff, cons
 bc_status multigraph_run(bc_ctx *ctx) {
     MultiState &m = ctx->mg;
     if (m.nunits == 0) return BC_OK;
-    const MultiArgs a = args_of(ctx, m.units, m.nunits);
     if (!m.exec) {
+        // compact sweep, full sweep over the other graphs, full sweep over the
+        // units the compact sweep handed back (its count read on the device)
+        MultiArgs ac = args_of(ctx, m.units, m.ncompact);
+        ac.next = m.next;
+        ac.redo = m.redo;
+        ac.redo_count = m.next + 3;
+        MultiArgs af = args_of(ctx, m.units + (size_t)3 * m.ncompact, m.nunits - m.ncompact);
+        af.next = m.next + 1;
+        MultiArgs ar = args_of(ctx, m.redo, 0);
+        ar.nunits_dev = m.next + 3;
+        ar.next = m.next + 2;
         hipGraph_t graph = nullptr;
         BC_HIP(ctx, hipStreamBeginCapture(m.stream, hipStreamCaptureModeThreadLocal));
-        hipLaunchKernelGGL(k_mg_reset, dim3(1), dim3(1), 0, m.stream, m.next);
-        hipLaunchKernelGGL(k_mg_sweep, dim3(m.grid), dim3(MT), 0, m.stream, a);
+        hipLaunchKernelGGL(k_mg_reset, dim3(1), dim3(64), 0, m.stream, m.next);
+        if (m.ncompact > 0)
+            hipLaunchKernelGGL(k_mg_sweep_compact, dim3(std::min(m.ncompact, 2 * m.grid)), dim3(MT), 0, m.stream, ac);
+        if (m.nunits > m.ncompact)
+            hipLaunchKernelGGL(k_mg_sweep, dim3(std::min(m.nunits - m.ncompact, m.grid)), dim3(MT), 0, m.stream, af);
+        if (m.ncompact > 0) hipLaunchKernelGGL(k_mg_sweep, dim3(m.grid), dim3(MT), 0, m.stream, ar);
         BC_HIP(ctx, hipStreamEndCapture(m.stream, &graph));
         const hipError_t e = hipGraphInstantiate(&m.exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
@@ -319,7 +512,7 @@ bc_status multigraph_dump(bc_ctx *ctx, const int32_t *h_sources, int32_t count, 
     a.dist_dump = dist_dump;
     a.sigma_dump = sigma_dump;
     a.delta_dump = delta_dump;
-    hipLaunchKernelGGL(k_mg_reset, dim3(1), dim3(1), 0, ctx->stream, m.next);
+    hipLaunchKernelGGL(k_mg_reset, dim3(1), dim3(64), 0, ctx->stream, m.next);
     hipLaunchKernelGGL(k_mg_sweep, dim3(std::min(count, m.grid)), dim3(MT), 0, ctx->stream, a);
     BC_HIP(ctx, hipGetLastError());
     BC_HIP(ctx, hipStreamSynchronize(ctx->stream));

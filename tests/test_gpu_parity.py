@@ -404,3 +404,18 @@ def test_many_graphs_overflow(gpu_lib):
         with pytest.raises(gpu_lib.BCError) as ei:
             ctx.read()
         assert ei.value.status == gpu_lib.BC_ERR_OVERFLOW
+
+
+def test_many_graphs_handed_back_units(gpu_lib):
+    """Units that the compact sweep cannot finish go to the full sweep:
+    counts above 2^32 - 1 (grid 20 x 20: up to C(38,19) ~ 3.5e10) and
+    sources deeper than its level cap (a 1500-path, a 2500-cycle), in the
+    same launch as units it does finish.  Replays add again."""
+    gs = [gg.grid(20, 20), gg.path(1500), gg.watts_strogatz(1000, 6, 0.1, 3), gg.cycle(2500), gg.star(64)]
+    say("many_handback", [g.n for g in gs])
+    want = np.concatenate([oracle.bc(g, threads=8) for g in gs])
+    with gpu_lib.BC(gs) as ctx:
+        ctx.run()
+        assert rel_err(ctx.read(), want) <= 1e-5
+        ctx.run()
+        assert rel_err(ctx.read(), 2 * want) <= 1e-5
