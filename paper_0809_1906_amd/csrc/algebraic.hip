@@ -73,6 +73,10 @@ struct GemmArgs {
     int32_t npad, n, B, NW;
     int32_t K;             // M * npad: the class matrices side by side
     size_t plane_elems;    // K * B
+    int32_t ksplit;        // forward: 1, or 2 blocks per tile, each over half of K
+    int32_t ntiles;        // grid_blocks(npad, B): tiles of one product
+    float *ws;             // split tiles' partial sums, [8][ntiles][2][64][GT]
+    uint32_t *arrive;      // [8][ntiles]
 };
 
 struct EpiArgs {
@@ -198,6 +202,18 @@ __device__ __forceinline__ Tile tile_of(int npad, int B) {
 }
 inline unsigned grid_blocks(int npad, int B) { return (unsigned)(((npad / GM + 7) / 8) * 8 * (B / GN)); }
 
+// With K split in two: blocks L and L + 8 (the same XCD) take the two halves
+// of one tile; otherwise as tile_of.  *tile is the tile's index in
+// [0, grid_blocks).
+__device__ __forceinline__ Tile tile_of_split(int npad, int B, int &half, int &tile) {
+    const int C = B / GN;
+    const int L = blockIdx.x, x = L & 7, t = L >> 3, tt = t >> 1;
+    half = __builtin_amdgcn_readfirstlane(t & 1);
+    const int row = (tt / C) * 8 + x, col = tt % C;
+    tile = __builtin_amdgcn_readfirstlane(row * C + col);
+    return Tile{__builtin_amdgcn_readfirstlane(row), __builtin_amdgcn_readfirstlane(col)};
+}
+
 __device__ __forceinline__ int next_tile(const uint32_t *flags, int ntn, int kt, int nkt) {
     while (kt < nkt && flags[(size_t)kt * ntn] == 0) ++kt;
     return kt;
@@ -217,9 +233,10 @@ constexpr int stages() { return NP == 1 ? 2 : 1; }
 // AGPR spills.)
 template <int NP>
 __device__ __forceinline__ void gemm_tile(const GemmArgs &g, const __bf16 *planes, int w0, int b0, int tid,
-                                          __bf16 (*sA)[GM * SA], __bf16 (*sX)[NP * 4 * GN * 8], f32x16 (&acc)[RT][2]) {
+                                          __bf16 (*sA)[GM * SA], __bf16 (*sX)[NP * 4 * GN * 8], f32x16 (&acc)[RT][2],
+                                          int kt0 = 0, int kt1 = -1) {
     const int lane = tid & 63, wv = tid >> 6, wr = wv >> 1, wc = wv & 1;
-    const int nkt = g.K / GK, ntn = g.B / GN;
+    const int nkt = kt1 < 0 ? g.K / GK : kt1, ntn = g.B / GN;
     const uint32_t *flags = g.kflags + b0 / GN;
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
@@ -228,7 +245,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, const __bf16 *plane
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[rt][ct][r] = 0.f;
 
-    int kt = next_tile(flags, ntn, 0, nkt);
+    int kt = next_tile(flags, ntn, kt0, nkt);
     int buf = 0;
     Stage<NP> st;
     if (kt < nkt) {
@@ -251,6 +268,42 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, const __bf16 *plane
         }
         kt = kn;
     }
+}
+
+// The two halves of a split tile meet here after their products for limb k.
+// Each stores its partial sums (agent-scope stores, coherent across XCDs) to
+// its own slot for limb k; the second to arrive adds the other's and returns
+// true, the first returns false.  One slot per limb: a half never waits, so
+// it may be several limbs ahead of the other.
+__device__ __forceinline__ bool split_meet(const GemmArgs &g, int k, int tile, int half, int tid, int &s_last,
+                                           f32x16 (&acc)[RT][2]) {
+    float *slot = g.ws + (((size_t)k * g.ntiles + tile) * 2) * 64 * GT;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                __hip_atomic_store(&slot[((size_t)half * 64 + (rt * 2 + ct) * 16 + r) * GT + tid], acc[rt][ct][r],
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __asm__ __volatile__("s_waitcnt vmcnt(0)" ::: "memory"); // this thread's stores are done
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t *cnt = &g.arrive[(size_t)k * g.ntiles + tile];
+        s_last = atomicAdd(cnt, 1u) == 1u;
+        if (s_last) __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    if (!s_last) return false;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                acc[rt][ct][r] += __hip_atomic_load(&slot[((size_t)(1 - half) * 64 + (rt * 2 + ct) * 16 + r) * GT + tid],
+                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return true;
 }
 
 // Forward epilogue for limb `shift / 8`; `mode` (uniform over the launch) says
@@ -284,15 +337,19 @@ __device__ __forceinline__ void epi_fwd(const GemmArgs &g, const EpiArgs &e, int
                 // visited vertices' sums are discarded.
                 const bool open = valid && !((vis >> bit) & 1);
                 bool fresh = false;
+                // part is carried from limb to limb, possibly by the two
+                // blocks of a split tile: agent-scope accesses keep it coherent
+                unsigned long long *pp = reinterpret_cast<unsigned long long *>(&e.part[idx]);
                 if (first) {
-                    if (valid) e.part[idx] = P;
+                    if (valid) __hip_atomic_store(pp, (unsigned long long)P, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 } else {
                     const uint64_t add = P << shift;
                     uint64_t tot = add;
-                    if (valid && (mid || last)) tot += e.part[idx];
+                    if (valid && (mid || last)) tot += __hip_atomic_load(pp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     if (open && shift > 0 && ((P >> (64 - shift)) != 0 || tot < add)) ovf = true;
                     if (mid) {
-                        if (valid) e.part[idx] = tot;
+                        if (valid)
+                            __hip_atomic_store(pp, (unsigned long long)tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     } else {
                         fresh = open && tot != 0;
                         if (fresh) {
@@ -336,17 +393,21 @@ template <typename S>
 __global__ __launch_bounds__(GT, 2) void k_mfma_fwd(GemmArgs g, EpiArgs e) {
     __shared__ __align__(16) __bf16 sA[2][GM * SA];
     __shared__ __align__(16) __bf16 sX[2][4 * GN * 8];
-    const Tile tl = tile_of(g.npad, g.B);
+    __shared__ int s_last;
+    int half = 0, tile = 0;
+    const Tile tl = g.ksplit == 2 ? tile_of_split(g.npad, g.B, half, tile) : tile_of(g.npad, g.B);
     if (tl.row >= g.npad / GM) return;
     const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int w0 = tl.row * GM + (wv >> 1) * WM, b0 = tl.col * GN;
     const int q = (b0 >> 6) + (wv & 1); // bitmap word of this wave's sources
     const int L = limbs_feeding(e.lvmax_cur, e.level, e.classes);
     if (blockIdx.x == 0 && tid == 0) atomicAdd(e.planes_issued, (unsigned long long)L);
+    const int nkt = g.K / GK, kt0 = g.ksplit == 2 ? half * (nkt / 2) : 0, kt1 = g.ksplit == 2 ? kt0 + nkt / 2 : nkt;
     f32x16 acc[RT][2];
 #pragma nounroll
     for (int k = 0; k < L; ++k) {
-        gemm_tile<1>(g, g.planes + (size_t)k * g.plane_elems, tl.row * GM, b0, tid, sA, sX, acc);
+        gemm_tile<1>(g, g.planes + (size_t)k * g.plane_elems, tl.row * GM, b0, tid, sA, sX, acc, kt0, kt1);
+        if (g.ksplit == 2 && !split_meet(g, k, tile, half, tid, s_last, acc)) continue; // the other half finishes it
         const int mode = L == 1 ? EPI_ONLY : k == 0 ? EPI_FIRST : k + 1 < L ? EPI_MID : EPI_LAST;
         // The epilogue's row addresses do not depend on k; an opaque copy of
         // the block's first row keeps the compiler from computing all of them
@@ -365,6 +426,8 @@ template <typename S>
 __global__ __launch_bounds__(GT, 2) void k_mfma_bwd(GemmArgs g, EpiArgs e) {
     __shared__ __align__(16) __bf16 sA[stages<3>()][GM * SA];
     __shared__ __align__(16) __bf16 sX[stages<3>()][3 * 4 * GN * 8];
+    // one block per tile: its stages of three planes are long enough already
+    // (split in two halves of K it measured slower)
     const Tile tl = tile_of(g.npad, g.B);
     if (tl.row >= g.npad / GM) return;
     const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -514,6 +577,10 @@ GemmArgs gemm_args(bc_ctx *ctx, const __bf16 *planes) {
     g.NW = ctx->sp.words;
     g.K = a.classes * a.npad;
     g.plane_elems = (size_t)g.K * ctx->sp.batch;
+    g.ksplit = a.ksplit;
+    g.ntiles = (int32_t)grid_blocks(a.npad, ctx->sp.batch);
+    g.ws = a.ws;
+    g.arrive = a.arrive;
     return g;
 }
 
@@ -540,8 +607,18 @@ bc_status algebraic_prepare(bc_ctx *ctx) {
     a.part = (uint64_t *)bc_dalloc(ctx, (size_t)a.npad * B * sizeof(uint64_t));
     a.kflags = (uint32_t *)bc_dalloc(ctx, (K / GK) * (B / GN) * sizeof(uint32_t));
     a.planes_issued = (unsigned long long *)bc_dalloc(ctx, 256);
-    if (!a.adj || !a.planes || !a.part || !a.kflags || !a.planes_issued)
+    // forward products over a long K: two blocks per output tile, so that a
+    // compute unit holds four blocks while each reads its operands once
+    a.ksplit = K / GK >= 256 ? 2 : 1;
+    const size_t ntiles = grid_blocks(a.npad, B);
+    if (a.ksplit == 2) {
+        a.ws = (float *)bc_dalloc(ctx, (size_t)8 * ntiles * 2 * 64 * GT * sizeof(float));
+        a.arrive = (uint32_t *)bc_dalloc(ctx, (size_t)8 * ntiles * sizeof(uint32_t));
+    }
+    if (!a.adj || !a.planes || !a.part || !a.kflags || !a.planes_issued ||
+        (a.ksplit == 2 && (!a.ws || !a.arrive)))
         return bc_fail(ctx, BC_ERR_NOMEM, "algebraic form: allocation failed");
+    if (a.ksplit == 2) BC_HIP(ctx, hipMemsetAsync(a.arrive, 0, (size_t)8 * ntiles * sizeof(uint32_t), ctx->stream));
     BC_HIP(ctx, hipMemsetAsync(a.adj, 0, adj_bytes, ctx->stream));
     BC_HIP(ctx, hipMemsetAsync(a.planes_issued, 0, sizeof(unsigned long long), ctx->stream));
     if (ctx->n > 0)
@@ -554,7 +631,8 @@ bc_status algebraic_prepare(bc_ctx *ctx) {
 bc_status algebraic_release(bc_ctx *ctx) {
     AlgebraicState &a = ctx->al;
     BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    for (void *p : {(void *)a.adj, (void *)a.planes, (void *)a.part, (void *)a.kflags, (void *)a.planes_issued})
+    for (void *p : {(void *)a.adj, (void *)a.planes, (void *)a.part, (void *)a.kflags, (void *)a.planes_issued,
+                    (void *)a.ws, (void *)a.arrive})
         if (p) bc_dfree(ctx, p);
     const bool every = a.every_level;
     a = AlgebraicState{};
@@ -595,7 +673,7 @@ bc_status algebraic_forward_level_t(bc_ctx *ctx, int32_t l) {
     e.planes_issued = a.planes_issued;
     const GemmArgs g = gemm_args(ctx, a.planes);
     LaunchTimer tm(ctx, "mfma_fwd");
-    hipLaunchKernelGGL(k_mfma_fwd<S>, dim3(grid_blocks(a.npad, s.batch)), dim3(GT), 0, ctx->stream, g, e);
+    hipLaunchKernelGGL(k_mfma_fwd<S>, dim3(grid_blocks(a.npad, s.batch) * a.ksplit), dim3(GT), 0, ctx->stream, g, e);
     tm.done();
     BC_HIP(ctx, hipGetLastError());
     return BC_OK;

@@ -60,6 +60,9 @@ struct AlgebraicState {
     uint64_t *part = nullptr;          // [npad][batch] partial limb sums
     uint32_t *kflags = nullptr;        // [M npad/32][batch/128] non-empty k-tiles
     unsigned long long *planes_issued = nullptr; // products issued (limb or coefficient planes)
+    int32_t ksplit = 1;                // forward products: blocks per output tile, each over a share of K
+    float *ws = nullptr;               // [8 limbs][tiles][2 halves][64][256] partial sums of split tiles
+    uint32_t *arrive = nullptr;        // [8 limbs][tiles] halves arrived
     bool every_level = false;          // the algebraic form: every level l >= 1 by products
 };
 
