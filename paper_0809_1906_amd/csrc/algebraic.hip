@@ -607,9 +607,11 @@ bc_status algebraic_prepare(bc_ctx *ctx) {
     a.part = (uint64_t *)bc_dalloc(ctx, (size_t)a.npad * B * sizeof(uint64_t));
     a.kflags = (uint32_t *)bc_dalloc(ctx, (K / GK) * (B / GN) * sizeof(uint32_t));
     a.planes_issued = (unsigned long long *)bc_dalloc(ctx, 256);
-    // forward products over a long K: two blocks per output tile, so that a
-    // compute unit holds four blocks while each reads its operands once
-    a.ksplit = K / GK >= 256 ? 2 : 1;
+    // unweighted forward products over a long K (one npad per limb): two
+    // blocks per output tile, so that a compute unit holds four blocks while
+    // each reads its operands once.  With weight classes K is M npad and the
+    // split measured slower (ER-16384, weights 1..4: 0.43 of BF16 against 0.50).
+    a.ksplit = a.classes == 1 && K / GK >= 256 ? 2 : 1;
     const size_t ntiles = grid_blocks(a.npad, B);
     if (a.ksplit == 2) {
         a.ws = (float *)bc_dalloc(ctx, (size_t)8 * ntiles * 2 * 64 * GT * sizeof(float));
