@@ -177,7 +177,7 @@ def load_workload(name, sources):
     return {"graph": g, "n": g.n, "m": g.m, "src": src, "S": S, "work": float(S) * g.m}
 
 
-def cpu_baseline(name, wl, target_s: float = 12.0):
+def cpu_baseline(name, wl, target_s: float = 20.0):
     """The oracle as it stands, on a bounded sample of the workload, all host
     cores it may use (at most 16)."""
     import oracle
