@@ -237,6 +237,10 @@ def roofline(name, wl, kern, info, steps):
         planes = 3 * launches if dom == "mfma_bwd" else max(info.mfma_planes - 3 * bwd_launches, launches)
         flops = 2.0 * info.batch * npad * npad * classes * planes
         base["weight_classes"] = classes
+        if info.mfma_ktiles_dense > 0:
+            # k-tiles whose every plane was zero are skipped; the flops above
+            # are the dense products' (the metric's "issued dense products")
+            base["k_tiles_skipped_frac"] = 1.0 - info.mfma_ktiles_run / info.mfma_ktiles_dense
         ach = flops / (ms * 1e-3) / 1e12
         return dict(base, bound="mfma", achieved=ach, peak=MFMA_BF16_PEAK_TFS, unit="TFLOP/s",
                     frac=ach / MFMA_BF16_PEAK_TFS, traffic=None,
@@ -253,8 +257,15 @@ def roofline(name, wl, kern, info, steps):
     else:
         total = float(S) * steps * pass_bytes(n, m)
     ach = total / (ms * 1e-3) / 1e9
+    traffic = measured_traffic(dom, name)
+    extra = {}
+    if traffic:
+        # measured DRAM bytes per launch over the launch time, against the
+        # peak; and how many algorithmic bytes each DRAM byte served
+        extra["dram_frac"] = traffic / (ms / max(launches, 1) * 1e-3) / 1e9 / HBM_PEAK_GBS
+        extra["alg_bytes_per_dram_byte"] = total / max(launches, 1) / traffic
     return dict(base, bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
-                traffic=measured_traffic(dom, name), alg_bytes_per_launch=total / max(launches, 1))
+                traffic=traffic, alg_bytes_per_launch=total / max(launches, 1), **extra)
 
 
 def run_allpairs(args, spec, wl, bcgpu, torch):
@@ -474,6 +485,8 @@ def main():
         return
     src, work = wl["src"], wl["work"]
 
+    step_ms = {}
+
     def timed_runs(form, steps, warmup, batch=0, timing=TIMING_SAMPLE, edges=False):
         t = time.perf_counter()
         ctx = bcgpu.BC(wl["graph"], form="auto" if form == "many" else form, batch=batch, timing=timing,
@@ -489,16 +502,22 @@ def main():
         ctx.reset()
         torch.cuda.synchronize()
         t = time.perf_counter()
+        per_step = []
         for i in range(steps):
+            ts = time.perf_counter()
             ctx.run(src)
             torch.cuda.synchronize()
+            per_step.append(time.perf_counter() - ts)
             log(f"{form} step {i} done")
         dt = (time.perf_counter() - t) / steps
+        step_ms[form] = {"mean": dt * 1e3, "median": float(np.median(per_step)) * 1e3,
+                         "min": float(np.min(per_step)) * 1e3}
         bc = ctx.read()
         log(f"{form} {steps} steps: {dt * 1e3:.1f} ms/step, {work / dt:.3e} TEPS")
         return ctx, dt, bc
 
     ctx, dt, bc_main = timed_runs(form, args.steps, args.warmup, batch, edges=args.edges)
+    main_step_ms = dict(step_ms[form])
     info = ctx.info()
     kern = {}
     for k in KERNELS:
@@ -562,6 +581,7 @@ def main():
         "tuned_batch_width": free,
         "compare": compare,
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kern.items()},
+        "step_ms": main_step_ms,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -320,10 +320,14 @@ typedef struct {
                                 per backward level; each is batch * npad^2
                                 multiply-adds, 2 * batch * npad^2 flops (npad = n
                                 rounded up to 256) */
+    int64_t mfma_ktiles_run;   /* k-tiles (32 rows of the adjacency by 128 sources)
+                                  multiplied by those products */
+    int64_t mfma_ktiles_dense; /* k-tiles a dense product would multiply; the
+                                  difference was skipped, every plane's tile zero */
 } bc_info;
 
-/* Fills *out; synchronises the context's stream (mfma_planes is read from the
- * device). */
+/* Fills *out; synchronises the context's stream (mfma_planes and the k-tile
+ * counts are read from the device). */
 bc_status bc_get_info(const bc_ctx *ctx, bc_info *out);
 
 /*

@@ -77,6 +77,7 @@ struct GemmArgs {
     int32_t ntiles;        // grid_blocks(npad, B): tiles of one product
     float *ws;             // split tiles' partial sums, [8][ntiles][2][64][GT]
     uint32_t *arrive;      // [8][ntiles]
+    unsigned long long *ktiles; // [0] k-tiles multiplied, [1] k-tiles in the blocks' ranges
 };
 
 struct EpiArgs {
@@ -246,7 +247,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, const __bf16 *plane
             for (int r = 0; r < 16; ++r) acc[rt][ct][r] = 0.f;
 
     int kt = next_tile(flags, ntn, kt0, nkt);
-    int buf = 0;
+    int buf = 0, done = 0;
     Stage<NP> st;
     if (kt < nkt) {
         load_stage<NP>(g, planes, kt, w0, b0, tid, st);
@@ -267,6 +268,11 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, const __bf16 *plane
             __syncthreads();
         }
         kt = kn;
+        ++done;
+    }
+    if (tid == 0 && g.ktiles) {
+        atomicAdd(&g.ktiles[0], (unsigned long long)done);
+        atomicAdd(&g.ktiles[1], (unsigned long long)(nkt - kt0));
     }
 }
 
@@ -581,6 +587,7 @@ GemmArgs gemm_args(bc_ctx *ctx, const __bf16 *planes) {
     g.ntiles = (int32_t)grid_blocks(a.npad, ctx->sp.batch);
     g.ws = a.ws;
     g.arrive = a.arrive;
+    g.ktiles = a.planes_issued ? a.planes_issued + 1 : nullptr;
     return g;
 }
 
@@ -622,7 +629,7 @@ bc_status algebraic_prepare(bc_ctx *ctx) {
         return bc_fail(ctx, BC_ERR_NOMEM, "algebraic form: allocation failed");
     if (a.ksplit == 2) BC_HIP(ctx, hipMemsetAsync(a.arrive, 0, (size_t)8 * ntiles * sizeof(uint32_t), ctx->stream));
     BC_HIP(ctx, hipMemsetAsync(a.adj, 0, adj_bytes, ctx->stream));
-    BC_HIP(ctx, hipMemsetAsync(a.planes_issued, 0, sizeof(unsigned long long), ctx->stream));
+    BC_HIP(ctx, hipMemsetAsync(a.planes_issued, 0, 3 * sizeof(unsigned long long), ctx->stream));
     if (ctx->n > 0)
         hipLaunchKernelGGL(k_build_adj, dim3(ctx->n), dim3(PB), 0, ctx->stream, ctx->n, a.npad, (int32_t)K,
                            ctx->row_ptr, ctx->col, ctx->weighted ? (const uint8_t *)ctx->weight : nullptr, a.adj);
@@ -736,7 +743,20 @@ int64_t algebraic_planes_issued(bc_ctx *ctx) {
     return (int64_t)v;
 }
 
+bool algebraic_ktiles(bc_ctx *ctx, int64_t *run, int64_t *dense) {
+    AlgebraicState &a = ctx->al;
+    *run = *dense = 0;
+    if (!a.planes_issued) return true;
+    unsigned long long v[2] = {0, 0};
+    if (hipMemcpyAsync(v, a.planes_issued + 1, sizeof v, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess)
+        return false;
+    *run = (int64_t)v[0];
+    *dense = (int64_t)v[1];
+    return true;
+}
+
 void algebraic_reset_counters(bc_ctx *ctx) {
     if (ctx->al.planes_issued)
-        (void)hipMemsetAsync(ctx->al.planes_issued, 0, sizeof(unsigned long long), ctx->stream);
+        (void)hipMemsetAsync(ctx->al.planes_issued, 0, 3 * sizeof(unsigned long long), ctx->stream);
 }

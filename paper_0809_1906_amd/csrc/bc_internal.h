@@ -267,6 +267,9 @@ bc_status algebraic_forward_level(bc_ctx *ctx, bool wide, int32_t l);
 bc_status algebraic_backward_level(bc_ctx *ctx, bool wide, const uint64_t *fcur, const uint64_t *fnext,
                                    int32_t deeper, double *delta_dump, bool accumulate);
 int64_t algebraic_planes_issued(bc_ctx *ctx); // synchronises; -1 on a device error
+// k-tiles the products multiplied and those a dense product would have;
+// synchronises; false on a device error
+bool algebraic_ktiles(bc_ctx *ctx, int64_t *run, int64_t *dense);
 void algebraic_reset_counters(bc_ctx *ctx);
 bc_status sparse_release(bc_ctx *ctx);
 bc_status algebraic_release(bc_ctx *ctx);
