@@ -56,11 +56,10 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int GM = 128;  // rows (vertices) per block: 2 wave rows x 64
 constexpr int GN = 128;  // columns (sources) per block: 2 wave columns x 64 (one bitmap word)
-constexpr int GK = 32;   // k (vertices) per pipeline stage
+constexpr int GK = 32;   // k (vertices) per k-tile of the skip flags
 constexpr int GT = 256;  // threads per block (4 waves, 2 x 2)
 constexpr int WM = 64;   // rows per wave: 2 MFMA row tiles of 32
 constexpr int RT = WM / 32;
-constexpr int SA = GK + 8; // LDS row stride of the adjacency tile, in BF16 (padding against bank conflicts)
 constexpr int PB = 256;  // threads per block of the element-wise kernels
 constexpr int NPAD = 256; // n is padded to a multiple of this (of GM too)
 
@@ -120,52 +119,72 @@ __device__ __forceinline__ int limbs_feeding(const unsigned long long *lvmax_l, 
 
 // ---- the product -------------------------------------------------------------------
 
+// KS: k (vertices) per pipeline stage, 32 or 64.  A 64-deep stage holds
+// twice the products per barrier.  LDS row stride of the adjacency tile:
+// KS + 8 BF16 (padding against bank conflicts).
+template <int KS>
+constexpr int lds_a() { return GM * (KS + 8); }
+template <int NP, int KS>
+constexpr int lds_x() { return NP * (KS / 8) * GN * 8; }
+// The forward product (one plane) runs 64-deep stages: against 32-deep ones
+// they took ER-16384 from 636 to 549 us per launch, and the weight-class
+// products (K = M npad) from 1.31 to 1.02 ms.  The backward's three planes
+// keep 32-deep stages, already three times larger.
+constexpr int FWD_KS = 64;
+constexpr int BWD_KS = 64;
+
 // One pipeline stage held in registers between its global loads and its LDS
-// stores: per thread GM/64 x 16 B of the adjacency tile (GM x GK) and 2 x 16 B of
-// each plane tile (GK x GN).
-template <int NP>
+// stores: the adjacency tile (GM x KS) in 16 B pieces, KS / 8 threads per row,
+// and KS / 16 pieces of 16 B of each plane tile (KS x GN) per thread.
+template <int NP, int KS_>
 struct Stage {
-    u32x4 a[GM / 64];
-    u32x4 x[NP * 2];
+    static constexpr int KS = KS_, TPR = KS / 8, RPP = GT / TPR, AP = GM / RPP;
+    u32x4 a[AP];
+    u32x4 x[NP * (KS / 16)];
 };
 
-template <int NP>
-__device__ __forceinline__ void load_stage(const GemmArgs &g, const __bf16 *planes, int kt, int w0, int b0, int tid,
-                                           Stage<NP> &st) {
-    const int row = tid >> 2, kq = tid & 3; // four threads read one row's 64 B
+template <int NP, int KS>
+__device__ __forceinline__ void load_stage(const GemmArgs &g, const __bf16 *planes, int ks, int w0, int b0, int tid,
+                                           Stage<NP, KS> &st) {
+    using T = Stage<NP, KS>;
+    const int row = tid / T::TPR, kq = tid % T::TPR; // T::TPR threads read one row's 2 KS bytes
 #pragma unroll
-    for (int i = 0; i < GM / 64; ++i)
-        st.a[i] = *reinterpret_cast<const u32x4 *>(g.adj + (size_t)(w0 + row + 64 * i) * g.K + (size_t)kt * GK +
+    for (int i = 0; i < T::AP; ++i)
+        st.a[i] = *reinterpret_cast<const u32x4 *>(g.adj + (size_t)(w0 + row + T::RPP * i) * g.K + (size_t)ks * T::KS +
                                                    kq * 8);
-    const int c = tid & (GN - 1), i0 = tid / GN; // k-group i0 and i0 + 2, column c
+    const int c = tid & (GN - 1), i0 = tid / GN; // k-groups i0, i0 + 2, ..., column c
 #pragma unroll
     for (int p = 0; p < NP; ++p)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
-            st.x[p * 2 + j] = *reinterpret_cast<const u32x4 *>(
-                planes + (size_t)p * g.plane_elems + (((size_t)kt * (GK / 8) + i0 + 2 * j) * g.B + b0 + c) * 8);
+        for (int j = 0; j < T::KS / 16; ++j)
+            st.x[p * (T::KS / 16) + j] = *reinterpret_cast<const u32x4 *>(
+                planes + (size_t)p * g.plane_elems + (((size_t)ks * (T::KS / 8) + i0 + 2 * j) * g.B + b0 + c) * 8);
 }
 
-template <int NP>
-__device__ __forceinline__ void store_stage(__bf16 *sA, __bf16 *sX, int tid, const Stage<NP> &st) {
-    const int row = tid >> 2, kq = tid & 3;
+template <int NP, int KS>
+__device__ __forceinline__ void store_stage(__bf16 *sA, __bf16 *sX, int tid, const Stage<NP, KS> &st) {
+    using T = Stage<NP, KS>;
+    constexpr int SA = T::KS + 8;
+    const int row = tid / T::TPR, kq = tid % T::TPR;
 #pragma unroll
-    for (int i = 0; i < GM / 64; ++i) *reinterpret_cast<u32x4 *>(sA + (row + 64 * i) * SA + kq * 8) = st.a[i];
+    for (int i = 0; i < T::AP; ++i) *reinterpret_cast<u32x4 *>(sA + (row + T::RPP * i) * SA + kq * 8) = st.a[i];
     const int c = tid & (GN - 1), i0 = tid / GN;
 #pragma unroll
     for (int p = 0; p < NP; ++p)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
-            *reinterpret_cast<u32x4 *>(sX + (((size_t)p * 4 + i0 + 2 * j) * GN + c) * 8) = st.x[p * 2 + j];
+        for (int j = 0; j < T::KS / 16; ++j)
+            *reinterpret_cast<u32x4 *>(sX + (((size_t)p * (T::KS / 8) + i0 + 2 * j) * GN + c) * 8) =
+                st.x[p * (T::KS / 16) + j];
 }
 
 // Wave (wr, wc) multiplies rows [WM wr, WM wr + WM) of the A tile by
 // columns [64 wc, 64 wc + 64) of each plane tile.
-template <int NP>
+template <int NP, int KS>
 __device__ __forceinline__ void mma_stage(const __bf16 *sA, const __bf16 *sX, int lane, int wr, int wc,
                                           f32x16 (&acc)[RT][2]) {
+    constexpr int SA = KS + 8;
 #pragma unroll
-    for (int kh = 0; kh < 2; ++kh) {
+    for (int kh = 0; kh < KS / 16; ++kh) {
         bf16x8 a[RT];
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt)
@@ -176,7 +195,7 @@ __device__ __forceinline__ void mma_stage(const __bf16 *sA, const __bf16 *sX, in
 #pragma unroll
             for (int ct = 0; ct < 2; ++ct) {
                 const bf16x8 b = *reinterpret_cast<const bf16x8 *>(
-                    sX + (((size_t)p * 4 + kh * 2 + (lane >> 5)) * GN + wc * 64 + ct * 32 + (lane & 31)) * 8);
+                    sX + (((size_t)p * (KS / 8) + kh * 2 + (lane >> 5)) * GN + wc * 64 + ct * 32 + (lane & 31)) * 8);
 #pragma unroll
                 for (int rt = 0; rt < RT; ++rt)
                     acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[rt], b, acc[rt][ct], 0, 0, 0);
@@ -215,9 +234,16 @@ __device__ __forceinline__ Tile tile_of_split(int npad, int B, int &half, int &t
     return Tile{__builtin_amdgcn_readfirstlane(row), __builtin_amdgcn_readfirstlane(col)};
 }
 
-__device__ __forceinline__ int next_tile(const uint32_t *flags, int ntn, int kt, int nkt) {
-    while (kt < nkt && flags[(size_t)kt * ntn] == 0) ++kt;
-    return kt;
+// The next stage from ks on (of nks) with a non-zero flag among its TPS k-tiles.
+template <int TPS>
+__device__ __forceinline__ int next_stage(const uint32_t *flags, int ntn, int ks, int nks) {
+    for (; ks < nks; ++ks) {
+        uint32_t f = 0;
+#pragma unroll
+        for (int t = 0; t < TPS; ++t) f |= flags[((size_t)ks * TPS + t) * ntn];
+        if (f != 0) break;
+    }
+    return ks;
 }
 
 // LDS stages of the pipeline: two for one plane; one for three planes, whose
@@ -225,19 +251,20 @@ __device__ __forceinline__ int next_tile(const uint32_t *flags, int ntn, int kt,
 template <int NP>
 constexpr int stages() { return NP == 1 ? 2 : 1; }
 
-// acc[w][b] = sum over k-tiles with a non-zero flag of A[w][k] X_p[k][b],
+// acc[w][b] = sum over stages with a non-zero k-tile flag of A[w][k] X_p[k][b],
 // summed over the NP planes starting at `planes`, for the block's GM rows and
 // 128 sources; wave (wr, wc) holds rows w0 + WM wr + [0, WM) and sources
 // b0 + 64 wc + [0, 64).  The next stage's global loads are in flight (in
 // registers) during the current stage's products.  (Two register stages in
 // flight measured slower: the extra registers pushed the forward kernel into
-// AGPR spills.)
-template <int NP>
+// AGPR spills.)  kt0 and kt1 are k-tiles, multiples of the stage's k-tiles.
+template <int NP, int KS>
 __device__ __forceinline__ void gemm_tile(const GemmArgs &g, const __bf16 *planes, int w0, int b0, int tid,
-                                          __bf16 (*sA)[GM * SA], __bf16 (*sX)[NP * 4 * GN * 8], f32x16 (&acc)[RT][2],
+                                          __bf16 (*sA)[lds_a<KS>()], __bf16 (*sX)[lds_x<NP, KS>()], f32x16 (&acc)[RT][2],
                                           int kt0 = 0, int kt1 = -1) {
+    constexpr int TPS = KS / GK; // k-tiles per stage
     const int lane = tid & 63, wv = tid >> 6, wr = wv >> 1, wc = wv & 1;
-    const int nkt = kt1 < 0 ? g.K / GK : kt1, ntn = g.B / GN;
+    const int nks = (kt1 < 0 ? g.K / GK : kt1) / TPS, ks0 = kt0 / TPS, ntn = g.B / GN;
     const uint32_t *flags = g.kflags + b0 / GN;
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
@@ -246,33 +273,33 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, const __bf16 *plane
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[rt][ct][r] = 0.f;
 
-    int kt = next_tile(flags, ntn, kt0, nkt);
+    int ks = next_stage<TPS>(flags, ntn, ks0, nks);
     int buf = 0, done = 0;
-    Stage<NP> st;
-    if (kt < nkt) {
-        load_stage<NP>(g, planes, kt, w0, b0, tid, st);
-        store_stage<NP>(sA[0], sX[0], tid, st);
+    Stage<NP, KS> st;
+    if (ks < nks) {
+        load_stage<NP, KS>(g, planes, ks, w0, b0, tid, st);
+        store_stage<NP, KS>(sA[0], sX[0], tid, st);
     }
     __syncthreads();
-    while (kt < nkt) {
-        const int kn = next_tile(flags, ntn, kt + 1, nkt);
-        if (kn < nkt) load_stage<NP>(g, planes, kn, w0, b0, tid, st);
-        mma_stage<NP>(sA[buf], sX[buf], lane, wr, wc, acc);
+    while (ks < nks) {
+        const int kn = next_stage<TPS>(flags, ntn, ks + 1, nks);
+        if (kn < nks) load_stage<NP, KS>(g, planes, kn, w0, b0, tid, st);
+        mma_stage<NP, KS>(sA[buf], sX[buf], lane, wr, wc, acc);
         if constexpr (stages<NP>() == 2) {
-            if (kn < nkt) store_stage<NP>(sA[buf ^ 1], sX[buf ^ 1], tid, st);
+            if (kn < nks) store_stage<NP, KS>(sA[buf ^ 1], sX[buf ^ 1], tid, st);
             __syncthreads();
             buf ^= 1;
         } else {
             __syncthreads(); // every wave is done with the stage
-            if (kn < nkt) store_stage<NP>(sA[0], sX[0], tid, st);
+            if (kn < nks) store_stage<NP, KS>(sA[0], sX[0], tid, st);
             __syncthreads();
         }
-        kt = kn;
+        ks = kn;
         ++done;
     }
     if (tid == 0 && g.ktiles) {
-        atomicAdd(&g.ktiles[0], (unsigned long long)done);
-        atomicAdd(&g.ktiles[1], (unsigned long long)(nkt - kt0));
+        atomicAdd(&g.ktiles[0], (unsigned long long)done * TPS);
+        atomicAdd(&g.ktiles[1], (unsigned long long)(nks - ks0) * TPS);
     }
 }
 
@@ -395,10 +422,11 @@ __device__ __forceinline__ void epi_fwd(const GemmArgs &g, const EpiArgs &e, int
 
 // Forward level l -> l+1: one pass per 8-bit limb of level l's largest count,
 // each followed by its epilogue.  Grid: grid_blocks(npad, B), tiles by tile_of.
-template <typename S>
+// KS: k per pipeline stage.
+template <typename S, int KS>
 __global__ __launch_bounds__(GT, 2) void k_mfma_fwd(GemmArgs g, EpiArgs e) {
-    __shared__ __align__(16) __bf16 sA[2][GM * SA];
-    __shared__ __align__(16) __bf16 sX[2][4 * GN * 8];
+    __shared__ __align__(16) __bf16 sA[2][lds_a<KS>()];
+    __shared__ __align__(16) __bf16 sX[2][lds_x<1, KS>()];
     __shared__ int s_last;
     int half = 0, tile = 0;
     const Tile tl = g.ksplit == 2 ? tile_of_split(g.npad, g.B, half, tile) : tile_of(g.npad, g.B);
@@ -412,7 +440,7 @@ __global__ __launch_bounds__(GT, 2) void k_mfma_fwd(GemmArgs g, EpiArgs e) {
     f32x16 acc[RT][2];
 #pragma nounroll
     for (int k = 0; k < L; ++k) {
-        gemm_tile<1>(g, g.planes + (size_t)k * g.plane_elems, tl.row * GM, b0, tid, sA, sX, acc, kt0, kt1);
+        gemm_tile<1, KS>(g, g.planes + (size_t)k * g.plane_elems, tl.row * GM, b0, tid, sA, sX, acc, kt0, kt1);
         if (g.ksplit == 2 && !split_meet(g, k, tile, half, tid, s_last, acc)) continue; // the other half finishes it
         const int mode = L == 1 ? EPI_ONLY : k == 0 ? EPI_FIRST : k + 1 < L ? EPI_MID : EPI_LAST;
         // The epilogue's row addresses do not depend on k; an opaque copy of
@@ -430,8 +458,8 @@ __global__ __launch_bounds__(GT, 2) void k_mfma_fwd(GemmArgs g, EpiArgs e) {
 // and BC(v) += delta summed over the block's sources (v != s_b).
 template <typename S>
 __global__ __launch_bounds__(GT, 2) void k_mfma_bwd(GemmArgs g, EpiArgs e) {
-    __shared__ __align__(16) __bf16 sA[stages<3>()][GM * SA];
-    __shared__ __align__(16) __bf16 sX[stages<3>()][3 * 4 * GN * 8];
+    __shared__ __align__(16) __bf16 sA[stages<3>()][lds_a<BWD_KS>()];
+    __shared__ __align__(16) __bf16 sX[stages<3>()][lds_x<3, BWD_KS>()];
     // one block per tile: its stages of three planes are long enough already
     // (split in two halves of K it measured slower)
     const Tile tl = tile_of(g.npad, g.B);
@@ -440,7 +468,7 @@ __global__ __launch_bounds__(GT, 2) void k_mfma_bwd(GemmArgs g, EpiArgs e) {
     const int b0 = tl.col * GN;
     if (blockIdx.x == 0 && tid == 0) atomicAdd(e.planes_issued, 3ull);
     f32x16 acc[RT][2];
-    gemm_tile<3>(g, g.planes, tl.row * GM, b0, tid, sA, sX, acc);
+    gemm_tile<3, BWD_KS>(g, g.planes, tl.row * GM, b0, tid, sA, sX, acc);
 
     const int w0 = tl.row * GM + (wv >> 1) * WM;
     const int q = (b0 >> 6) + (wv & 1);
@@ -614,12 +642,13 @@ bc_status algebraic_prepare(bc_ctx *ctx) {
     a.part = (uint64_t *)bc_dalloc(ctx, (size_t)a.npad * B * sizeof(uint64_t));
     a.kflags = (uint32_t *)bc_dalloc(ctx, (K / GK) * (B / GN) * sizeof(uint32_t));
     a.planes_issued = (unsigned long long *)bc_dalloc(ctx, 256);
-    // unweighted forward products over a long K (one npad per limb): two
-    // blocks per output tile, so that a compute unit holds four blocks while
-    // each reads its operands once.  With weight classes K is M npad and the
-    // split measured slower (ER-16384, weights 1..4: 0.43 of BF16 against 0.50).
-    a.ksplit = a.classes == 1 && K / GK >= 256 ? 2 : 1;
+    // Unweighted forward products over a long K (one npad per limb) with
+    // fewer tiles than two per compute unit: two blocks per output tile, each
+    // over half of K, so that the grid fills the chip.  With 512 tiles or more
+    // the split measured slower (ER-16384, B = 512: 124 against 116 ms per
+    // step), and with weight classes too (K is M npad; 0.43 of BF16 against 0.50).
     const size_t ntiles = grid_blocks(a.npad, B);
+    a.ksplit = a.classes == 1 && K / GK >= 256 && ntiles < 512 ? 2 : 1;
     if (a.ksplit == 2) {
         a.ws = (float *)bc_dalloc(ctx, (size_t)8 * ntiles * 2 * 64 * GT * sizeof(float));
         a.arrive = (uint32_t *)bc_dalloc(ctx, (size_t)8 * ntiles * sizeof(uint32_t));
@@ -682,7 +711,8 @@ bc_status algebraic_forward_level_t(bc_ctx *ctx, int32_t l) {
     e.planes_issued = a.planes_issued;
     const GemmArgs g = gemm_args(ctx, a.planes);
     LaunchTimer tm(ctx, "mfma_fwd");
-    hipLaunchKernelGGL(k_mfma_fwd<S>, dim3(grid_blocks(a.npad, s.batch) * a.ksplit), dim3(GT), 0, ctx->stream, g, e);
+    hipLaunchKernelGGL((k_mfma_fwd<S, FWD_KS>), dim3(grid_blocks(a.npad, s.batch) * a.ksplit), dim3(GT), 0,
+                       ctx->stream, g, e);
     tm.done();
     BC_HIP(ctx, hipGetLastError());
     return BC_OK;

@@ -194,6 +194,28 @@ def test_rmat16_algebraic_form_sampled(gpu_lib):
     assert rel_err(got, want) <= 1e-5
 
 
+def test_algebraic_split_k(gpu_lib):
+    """Forward products over a long K with fewer output tiles than two per
+    compute unit run as two blocks per tile, each over half of K, meeting
+    through agent-scope partial sums (ER n = 12000, mean degree 48, batch
+    128: 96 tiles, K = 12032).  One batch of per-source results bit-exact, BC
+    over a ragged two-batch source list."""
+    g = gg.er_plus_tree(12000, 48.0, 77)
+    say("algebraic_split_k", g.n, g.m)
+    src = gg.sample_sources(g.n, 128, 78).astype(np.int32)
+    sub = gg.sample_sources(g.n, 200, 79).astype(np.int32)
+    with gpu_lib.BC(g, form="algebraic", batch=128) as ctx:
+        dist, sigma, delta = ctx.sssp(src)
+        ctx.run(sub)
+        got = ctx.read()
+    for i in range(0, 128, 9):
+        d, sg, dl = oracle.sssp_u64(g, int(src[i]))
+        assert np.array_equal(dist[i], d) and np.array_equal(sigma[i], sg), f"source {src[i]}"
+        assert rel_err(delta[i], dl) <= 1e-5
+    assert int(sigma.max()) > 255  # counts of more than one limb crossed the split
+    assert rel_err(got, oracle.bc(g, sub, threads=8)) <= 1e-5
+
+
 def test_algebraic_limbs_and_wide_counts(gpu_lib):
     """Counts of several 8-bit limbs (grid 20x20: up to C(38,19) > 2^32, so
     five limbs and uint64 storage) stay exact through the BF16 products."""
