@@ -126,11 +126,12 @@ template <int KS>
 constexpr int lds_a() { return GM * (KS + 8); }
 template <int NP, int KS>
 constexpr int lds_x() { return NP * (KS / 8) * GN * 8; }
-// The forward product (one plane) runs 64-deep stages: against 32-deep ones
-// they took ER-16384 from 636 to 549 us per launch, and the weight-class
-// products (K = M npad) from 1.31 to 1.02 ms.  The backward's three planes
-// keep 32-deep stages, already three times larger.
-constexpr int FWD_KS = 64;
+// Stage depths, measured on ER-16384 (B = 512) against 32-deep stages:
+// - forward (one plane): one 128-deep stage, 636 -> 490 us per launch, and
+//   1.31 -> 0.88 ms for the weight-class products (K = M npad); two 64-deep
+//   stages gave 549 us and 1.02 ms;
+// - backward (three planes): one 64-deep stage, 815 -> 714 us.
+constexpr int FWD_KS = 128;
 constexpr int BWD_KS = 64;
 
 // One pipeline stage held in registers between its global loads and its LDS
@@ -246,10 +247,10 @@ __device__ __forceinline__ int next_stage(const uint32_t *flags, int ntn, int ks
     return ks;
 }
 
-// LDS stages of the pipeline: two for one plane; one for three planes, whose
-// stage is three times larger, so that two blocks fit a compute unit.
-template <int NP>
-constexpr int stages() { return NP == 1 ? 2 : 1; }
+// LDS stages of the pipeline: two for one plane up to 64 deep, else one, so
+// that two blocks fit a compute unit.
+template <int NP, int KS>
+constexpr int stages() { return NP == 1 && KS <= 64 ? 2 : 1; }
 
 // acc[w][b] = sum over stages with a non-zero k-tile flag of A[w][k] X_p[k][b],
 // summed over the NP planes starting at `planes`, for the block's GM rows and
@@ -285,7 +286,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, const __bf16 *plane
         const int kn = next_stage<TPS>(flags, ntn, ks + 1, nks);
         if (kn < nks) load_stage<NP, KS>(g, planes, kn, w0, b0, tid, st);
         mma_stage<NP, KS>(sA[buf], sX[buf], lane, wr, wc, acc);
-        if constexpr (stages<NP>() == 2) {
+        if constexpr (stages<NP, KS>() == 2) {
             if (kn < nks) store_stage<NP, KS>(sA[buf ^ 1], sX[buf ^ 1], tid, st);
             __syncthreads();
             buf ^= 1;
@@ -425,8 +426,8 @@ __device__ __forceinline__ void epi_fwd(const GemmArgs &g, const EpiArgs &e, int
 // KS: k per pipeline stage.
 template <typename S, int KS>
 __global__ __launch_bounds__(GT, 2) void k_mfma_fwd(GemmArgs g, EpiArgs e) {
-    __shared__ __align__(16) __bf16 sA[2][lds_a<KS>()];
-    __shared__ __align__(16) __bf16 sX[2][lds_x<1, KS>()];
+    __shared__ __align__(16) __bf16 sA[stages<1, KS>()][lds_a<KS>()];
+    __shared__ __align__(16) __bf16 sX[stages<1, KS>()][lds_x<1, KS>()];
     __shared__ int s_last;
     int half = 0, tile = 0;
     const Tile tl = g.ksplit == 2 ? tile_of_split(g.npad, g.B, half, tile) : tile_of(g.npad, g.B);
@@ -458,8 +459,8 @@ __global__ __launch_bounds__(GT, 2) void k_mfma_fwd(GemmArgs g, EpiArgs e) {
 // and BC(v) += delta summed over the block's sources (v != s_b).
 template <typename S>
 __global__ __launch_bounds__(GT, 2) void k_mfma_bwd(GemmArgs g, EpiArgs e) {
-    __shared__ __align__(16) __bf16 sA[stages<3>()][lds_a<BWD_KS>()];
-    __shared__ __align__(16) __bf16 sX[stages<3>()][lds_x<3, BWD_KS>()];
+    __shared__ __align__(16) __bf16 sA[stages<3, BWD_KS>()][lds_a<BWD_KS>()];
+    __shared__ __align__(16) __bf16 sX[stages<3, BWD_KS>()][lds_x<3, BWD_KS>()];
     // one block per tile: its stages of three planes are long enough already
     // (split in two halves of K it measured slower)
     const Tile tl = tile_of(g.npad, g.B);
