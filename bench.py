@@ -237,11 +237,18 @@ def roofline(name, wl, kern, info, steps):
         planes = 3 * launches if dom == "mfma_bwd" else max(info.mfma_planes - 3 * bwd_launches, launches)
         flops = 2.0 * info.batch * npad * npad * classes * planes
         base["weight_classes"] = classes
-        if info.mfma_ktiles_dense > 0:
-            # k-tiles whose every plane was zero are skipped; the flops above
-            # are the dense products' (the metric's "issued dense products")
-            base["k_tiles_skipped_frac"] = 1.0 - info.mfma_ktiles_run / info.mfma_ktiles_dense
+        # k-tiles whose every plane was zero are skipped; the flops above are
+        # the dense products' (the metric's "issued dense products"), and
+        # frac_executed scales them by this kernel's share of k-tiles run
+        if dom == "mfma_fwd":
+            run, dense = info.mfma_ktiles_run_fwd, info.mfma_ktiles_dense_fwd
+        else:
+            run = info.mfma_ktiles_run - info.mfma_ktiles_run_fwd
+            dense = info.mfma_ktiles_dense - info.mfma_ktiles_dense_fwd
         ach = flops / (ms * 1e-3) / 1e12
+        if dense > 0:
+            base["k_tiles_skipped_frac"] = 1.0 - run / dense
+            base["frac_executed"] = ach / MFMA_BF16_PEAK_TFS * run / dense
         return dict(base, bound="mfma", achieved=ach, peak=MFMA_BF16_PEAK_TFS, unit="TFLOP/s",
                     frac=ach / MFMA_BF16_PEAK_TFS, traffic=None,
                     alg_flops_per_launch=flops / max(launches, 1),

@@ -324,6 +324,8 @@ typedef struct {
                                   multiplied by those products */
     int64_t mfma_ktiles_dense; /* k-tiles a dense product would multiply; the
                                   difference was skipped, every plane's tile zero */
+    int64_t mfma_ktiles_run_fwd;   /* the forward products' share of mfma_ktiles_run */
+    int64_t mfma_ktiles_dense_fwd; /* the forward products' share of mfma_ktiles_dense */
 } bc_info;
 
 /* Fills *out; synchronises the context's stream (mfma_planes and the k-tile

@@ -76,7 +76,8 @@ class bc_info(ctypes.Structure):
                 ("device_bytes", ctypes.c_int64), ("mfma_density_fwd", ctypes.c_double),
                 ("mfma_density_bwd", ctypes.c_double), ("tune_source", ctypes.c_int32),
                 ("mfma_planes", ctypes.c_int64), ("mfma_ktiles_run", ctypes.c_int64),
-                ("mfma_ktiles_dense", ctypes.c_int64)]
+                ("mfma_ktiles_dense", ctypes.c_int64), ("mfma_ktiles_run_fwd", ctypes.c_int64),
+                ("mfma_ktiles_dense_fwd", ctypes.c_int64)]
 
 
 # Every symbol include/bc.h declares, with its ctypes signature.

@@ -76,7 +76,7 @@ struct GemmArgs {
     int32_t ntiles;        // grid_blocks(npad, B): tiles of one product
     float *ws;             // split tiles' partial sums, [8][ntiles][2][64][GT]
     uint32_t *arrive;      // [8][ntiles]
-    unsigned long long *ktiles; // [0] k-tiles multiplied, [1] k-tiles in the blocks' ranges
+    unsigned long long *ktiles; // [0] k-tiles multiplied, [1] k-tiles in the blocks' ranges (per direction)
 };
 
 struct EpiArgs {
@@ -600,7 +600,7 @@ inline size_t kflag_bytes(bc_ctx *ctx) {
     return (size_t)ctx->al.classes * (ctx->al.npad / GK) * (ctx->sp.batch / GN) * sizeof(uint32_t);
 }
 
-GemmArgs gemm_args(bc_ctx *ctx, const __bf16 *planes) {
+GemmArgs gemm_args(bc_ctx *ctx, const __bf16 *planes, bool forward) {
     AlgebraicState &a = ctx->al;
     GemmArgs g;
     g.adj = a.adj;
@@ -616,7 +616,8 @@ GemmArgs gemm_args(bc_ctx *ctx, const __bf16 *planes) {
     g.ntiles = (int32_t)grid_blocks(a.npad, ctx->sp.batch);
     g.ws = a.ws;
     g.arrive = a.arrive;
-    g.ktiles = a.planes_issued ? a.planes_issued + 1 : nullptr;
+    // counters: [0] planes, [1..2] forward k-tiles, [3..4] backward k-tiles
+    g.ktiles = a.planes_issued ? a.planes_issued + (forward ? 1 : 3) : nullptr;
     return g;
 }
 
@@ -659,7 +660,7 @@ bc_status algebraic_prepare(bc_ctx *ctx) {
         return bc_fail(ctx, BC_ERR_NOMEM, "algebraic form: allocation failed");
     if (a.ksplit == 2) BC_HIP(ctx, hipMemsetAsync(a.arrive, 0, (size_t)8 * ntiles * sizeof(uint32_t), ctx->stream));
     BC_HIP(ctx, hipMemsetAsync(a.adj, 0, adj_bytes, ctx->stream));
-    BC_HIP(ctx, hipMemsetAsync(a.planes_issued, 0, 3 * sizeof(unsigned long long), ctx->stream));
+    BC_HIP(ctx, hipMemsetAsync(a.planes_issued, 0, 5 * sizeof(unsigned long long), ctx->stream));
     if (ctx->n > 0)
         hipLaunchKernelGGL(k_build_adj, dim3(ctx->n), dim3(PB), 0, ctx->stream, ctx->n, a.npad, (int32_t)K,
                            ctx->row_ptr, ctx->col, ctx->weighted ? (const uint8_t *)ctx->weight : nullptr, a.adj);
@@ -710,7 +711,7 @@ bc_status algebraic_forward_level_t(bc_ctx *ctx, int32_t l) {
     e.classes = a.classes;
     e.level = l;
     e.planes_issued = a.planes_issued;
-    const GemmArgs g = gemm_args(ctx, a.planes);
+    const GemmArgs g = gemm_args(ctx, a.planes, true);
     LaunchTimer tm(ctx, "mfma_fwd");
     hipLaunchKernelGGL((k_mfma_fwd<S, FWD_KS>), dim3(grid_blocks(a.npad, s.batch) * a.ksplit), dim3(GT), 0,
                        ctx->stream, g, e);
@@ -746,7 +747,7 @@ bc_status algebraic_backward_level_t(bc_ctx *ctx, const uint64_t *fcur, const ui
     e.delta_dump = delta_dump;
     e.accumulate = accumulate ? 1 : 0;
     e.planes_issued = a.planes_issued;
-    const GemmArgs g = gemm_args(ctx, a.planes);
+    const GemmArgs g = gemm_args(ctx, a.planes, false);
     LaunchTimer tm(ctx, "mfma_bwd");
     hipLaunchKernelGGL(k_mfma_bwd<S>, dim3(grid_blocks(a.npad, s.batch)), dim3(GT), 0, ctx->stream, g, e);
     tm.done();
@@ -774,20 +775,22 @@ int64_t algebraic_planes_issued(bc_ctx *ctx) {
     return (int64_t)v;
 }
 
-bool algebraic_ktiles(bc_ctx *ctx, int64_t *run, int64_t *dense) {
+bool algebraic_ktiles(bc_ctx *ctx, int64_t *run, int64_t *dense, int64_t *run_fwd, int64_t *dense_fwd) {
     AlgebraicState &a = ctx->al;
-    *run = *dense = 0;
+    *run = *dense = *run_fwd = *dense_fwd = 0;
     if (!a.planes_issued) return true;
-    unsigned long long v[2] = {0, 0};
+    unsigned long long v[4] = {0, 0, 0, 0};
     if (hipMemcpyAsync(v, a.planes_issued + 1, sizeof v, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
         hipStreamSynchronize(ctx->stream) != hipSuccess)
         return false;
-    *run = (int64_t)v[0];
-    *dense = (int64_t)v[1];
+    *run_fwd = (int64_t)v[0];
+    *dense_fwd = (int64_t)v[1];
+    *run = (int64_t)(v[0] + v[2]);
+    *dense = (int64_t)(v[1] + v[3]);
     return true;
 }
 
 void algebraic_reset_counters(bc_ctx *ctx) {
     if (ctx->al.planes_issued)
-        (void)hipMemsetAsync(ctx->al.planes_issued, 0, 3 * sizeof(unsigned long long), ctx->stream);
+        (void)hipMemsetAsync(ctx->al.planes_issued, 0, 5 * sizeof(unsigned long long), ctx->stream);
 }

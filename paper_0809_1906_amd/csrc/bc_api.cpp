@@ -827,9 +827,10 @@ bc_status bc_get_info(const bc_ctx *ctx, bc_info *out) {
     out->mfma_density_bwd = every ? 0.0 : hybrid ? ctx->hy.theta_bwd : 2.0;
     out->tune_source = ctx->hy.tune_source;
     out->mfma_planes = ctx->poisoned ? 0 : algebraic_planes_issued(const_cast<bc_ctx *>(ctx));
-    out->mfma_ktiles_run = out->mfma_ktiles_dense = 0;
-    if (!ctx->poisoned && !algebraic_ktiles(const_cast<bc_ctx *>(ctx), &out->mfma_ktiles_run, &out->mfma_ktiles_dense))
-        out->mfma_ktiles_run = out->mfma_ktiles_dense = -1;
+    out->mfma_ktiles_run = out->mfma_ktiles_dense = out->mfma_ktiles_run_fwd = out->mfma_ktiles_dense_fwd = 0;
+    if (!ctx->poisoned && !algebraic_ktiles(const_cast<bc_ctx *>(ctx), &out->mfma_ktiles_run, &out->mfma_ktiles_dense,
+                                            &out->mfma_ktiles_run_fwd, &out->mfma_ktiles_dense_fwd))
+        out->mfma_ktiles_run = out->mfma_ktiles_dense = out->mfma_ktiles_run_fwd = out->mfma_ktiles_dense_fwd = -1;
     return BC_OK;
 }
 

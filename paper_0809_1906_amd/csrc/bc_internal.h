@@ -269,7 +269,7 @@ bc_status algebraic_backward_level(bc_ctx *ctx, bool wide, const uint64_t *fcur,
 int64_t algebraic_planes_issued(bc_ctx *ctx); // synchronises; -1 on a device error
 // k-tiles the products multiplied and those a dense product would have;
 // synchronises; false on a device error
-bool algebraic_ktiles(bc_ctx *ctx, int64_t *run, int64_t *dense);
+bool algebraic_ktiles(bc_ctx *ctx, int64_t *run, int64_t *dense, int64_t *run_fwd, int64_t *dense_fwd);
 void algebraic_reset_counters(bc_ctx *ctx);
 bc_status sparse_release(bc_ctx *ctx);
 bc_status algebraic_release(bc_ctx *ctx);

@@ -208,6 +208,13 @@ def test_algebraic_split_k(gpu_lib):
         dist, sigma, delta = ctx.sssp(src)
         ctx.run(sub)
         got = ctx.read()
+        info = ctx.info()
+    # k-tile counts: the forward's share within the totals, run within dense,
+    # and each block counts its whole range of K = npad once per product pass
+    npad = (g.n + 255) // 256 * 256
+    assert 0 < info.mfma_ktiles_run_fwd <= info.mfma_ktiles_dense_fwd < info.mfma_ktiles_dense
+    assert 0 < info.mfma_ktiles_run <= info.mfma_ktiles_dense
+    assert info.mfma_ktiles_dense % (npad // 32) == 0
     for i in range(0, 128, 9):
         d, sg, dl = oracle.sssp_u64(g, int(src[i]))
         assert np.array_equal(dist[i], d) and np.array_equal(sigma[i], sg), f"source {src[i]}"
