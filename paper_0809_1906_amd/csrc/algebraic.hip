@@ -54,10 +54,10 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int GM = 128;  // rows (vertices) per block: 2 wave rows x 64
+constexpr int GM = 128;  // rows (vertices) per block of the backward: 2 wave rows x 64
 constexpr int GN = 128;  // columns (sources) per block: 2 wave columns x 64 (one bitmap word)
 constexpr int GK = 32;   // k (vertices) per k-tile of the skip flags
-constexpr int GT = 256;  // threads per block (4 waves, 2 x 2)
+constexpr int GT = 256;  // threads per block of the backward (4 waves, 2 x 2); BM rows take 2 BM
 constexpr int WM = 64;   // rows per wave: 2 MFMA row tiles of 32
 constexpr int RT = WM / 32;
 constexpr int PB = 256;  // threads per block of the element-wise kernels
@@ -73,8 +73,8 @@ struct GemmArgs {
     int32_t K;             // M * npad: the class matrices side by side
     size_t plane_elems;    // K * B
     int32_t ksplit;        // forward: 1, or 2 blocks per tile, each over half of K
-    int32_t ntiles;        // grid_blocks(npad, B): tiles of one product
-    float *ws;             // split tiles' partial sums, [8][ntiles][2][64][GT]
+    int32_t ntiles;        // grid_blocks<BM>(npad, B): tiles of one product
+    float *ws;             // split tiles' partial sums, [8][ntiles][2][64][forward block threads]
     uint32_t *arrive;      // [8][ntiles]
     unsigned long long *ktiles; // [0] k-tiles multiplied, [1] k-tiles in the blocks' ranges (per direction)
 };
@@ -122,8 +122,8 @@ __device__ __forceinline__ int limbs_feeding(const unsigned long long *lvmax_l, 
 // KS: k (vertices) per pipeline stage, 32 or 64.  A 64-deep stage holds
 // twice the products per barrier.  LDS row stride of the adjacency tile:
 // KS + 8 BF16 (padding against bank conflicts).
-template <int KS>
-constexpr int lds_a() { return GM * (KS + 8); }
+template <int KS, int BM>
+constexpr int lds_a() { return BM * (KS + 8); }
 template <int NP, int KS>
 constexpr int lds_x() { return NP * (KS / 8) * GN * 8; }
 // Stage depths, measured on ER-16384 (B = 512) against 32-deep stages:
@@ -133,39 +133,48 @@ constexpr int lds_x() { return NP * (KS / 8) * GN * 8; }
 // - backward (three planes): one 64-deep stage, 815 -> 714 us.
 constexpr int FWD_KS = 128;
 constexpr int BWD_KS = 64;
+// Block rows (BM, a multiple of 128; 2 BM threads, waves of 64 x 64 in BM / 64
+// rows by 2 columns).  A 256-row forward block (8 waves, 102 KB of LDS, one
+// per compute unit; 1.37 times the flops per operand byte) measured no faster:
+// 504 against 490 us per ER-16384 launch.
+constexpr int FWD_BM = 128;
+constexpr int BWD_BM = GM;
 
 // One pipeline stage held in registers between its global loads and its LDS
-// stores: the adjacency tile (GM x KS) in 16 B pieces, KS / 8 threads per row,
-// and KS / 16 pieces of 16 B of each plane tile (KS x GN) per thread.
-template <int NP, int KS_>
+// stores: the adjacency tile (BM x KS) in 16 B pieces, KS / 8 threads per row,
+// and KS / 16 pieces of 16 B of each plane tile (KS x GN) per pair of threads
+// (the block's 2 BM threads cover 2 BM / GN k-groups at a time).
+template <int NP, int KS_, int BM>
 struct Stage {
-    static constexpr int KS = KS_, TPR = KS / 8, RPP = GT / TPR, AP = GM / RPP;
+    static constexpr int KS = KS_, T = 2 * BM, TPR = KS / 8, RPP = T / TPR, AP = BM / RPP, XG = T / GN;
+    static_assert(AP >= 1 && (KS / 8) % XG == 0, "stage shape");
     u32x4 a[AP];
-    u32x4 x[NP * (KS / 16)];
+    u32x4 x[NP * (KS / 8) / XG];
 };
 
-template <int NP, int KS>
+template <int NP, int KS, int BM>
 __device__ __forceinline__ void load_stage(const GemmArgs &g, const __bf16 *planes, int ks, int w0, int b0, int tid,
-                                           Stage<NP, KS> &st) {
-    using T = Stage<NP, KS>;
+                                           Stage<NP, KS, BM> &st) {
+    using T = Stage<NP, KS, BM>;
     const int row = tid / T::TPR, kq = tid % T::TPR; // T::TPR threads read one row's 2 KS bytes
 #pragma unroll
     for (int i = 0; i < T::AP; ++i)
         st.a[i] = *reinterpret_cast<const u32x4 *>(g.adj + (size_t)(w0 + row + T::RPP * i) * g.K + (size_t)ks * T::KS +
                                                    kq * 8);
-    const int c = tid & (GN - 1), i0 = tid / GN; // k-groups i0, i0 + 2, ..., column c
+    constexpr int XJ = T::KS / 8 / T::XG;
+    const int c = tid & (GN - 1), i0 = tid / GN; // k-groups i0, i0 + XG, ..., column c
 #pragma unroll
     for (int p = 0; p < NP; ++p)
 #pragma unroll
-        for (int j = 0; j < T::KS / 16; ++j)
-            st.x[p * (T::KS / 16) + j] = *reinterpret_cast<const u32x4 *>(
-                planes + (size_t)p * g.plane_elems + (((size_t)ks * (T::KS / 8) + i0 + 2 * j) * g.B + b0 + c) * 8);
+        for (int j = 0; j < XJ; ++j)
+            st.x[p * XJ + j] = *reinterpret_cast<const u32x4 *>(
+                planes + (size_t)p * g.plane_elems + (((size_t)ks * (T::KS / 8) + i0 + T::XG * j) * g.B + b0 + c) * 8);
 }
 
-template <int NP, int KS>
-__device__ __forceinline__ void store_stage(__bf16 *sA, __bf16 *sX, int tid, const Stage<NP, KS> &st) {
-    using T = Stage<NP, KS>;
-    constexpr int SA = T::KS + 8;
+template <int NP, int KS, int BM>
+__device__ __forceinline__ void store_stage(__bf16 *sA, __bf16 *sX, int tid, const Stage<NP, KS, BM> &st) {
+    using T = Stage<NP, KS, BM>;
+    constexpr int SA = T::KS + 8, XJ = T::KS / 8 / T::XG;
     const int row = tid / T::TPR, kq = tid % T::TPR;
 #pragma unroll
     for (int i = 0; i < T::AP; ++i) *reinterpret_cast<u32x4 *>(sA + (row + T::RPP * i) * SA + kq * 8) = st.a[i];
@@ -173,9 +182,9 @@ __device__ __forceinline__ void store_stage(__bf16 *sA, __bf16 *sX, int tid, con
 #pragma unroll
     for (int p = 0; p < NP; ++p)
 #pragma unroll
-        for (int j = 0; j < T::KS / 16; ++j)
-            *reinterpret_cast<u32x4 *>(sX + (((size_t)p * (T::KS / 8) + i0 + 2 * j) * GN + c) * 8) =
-                st.x[p * (T::KS / 16) + j];
+        for (int j = 0; j < XJ; ++j)
+            *reinterpret_cast<u32x4 *>(sX + (((size_t)p * (T::KS / 8) + i0 + T::XG * j) * GN + c) * 8) =
+                st.x[p * XJ + j];
 }
 
 // Wave (wr, wc) multiplies rows [WM wr, WM wr + WM) of the A tile by
@@ -214,19 +223,19 @@ __device__ __forceinline__ void mma_stage(const __bf16 *sA, const __bf16 *sX, in
 struct Tile {
     int row, col;
 };
-__device__ __forceinline__ Tile tile_of(int npad, int B) {
-    const int R = npad / GM, C = B / GN;
+__device__ __forceinline__ Tile tile_of(int B) {
+    const int C = B / GN;
     const int L = blockIdx.x, x = L & 7, t = L >> 3;
-    (void)R;
     // uniform over the block: keep it in scalar registers
     return Tile{__builtin_amdgcn_readfirstlane((t / C) * 8 + x), __builtin_amdgcn_readfirstlane(t % C)};
 }
-inline unsigned grid_blocks(int npad, int B) { return (unsigned)(((npad / GM + 7) / 8) * 8 * (B / GN)); }
+template <int BM>
+inline unsigned grid_blocks(int npad, int B) { return (unsigned)(((npad / BM + 7) / 8) * 8 * (B / GN)); }
 
 // With K split in two: blocks L and L + 8 (the same XCD) take the two halves
 // of one tile; otherwise as tile_of.  *tile is the tile's index in
 // [0, grid_blocks).
-__device__ __forceinline__ Tile tile_of_split(int npad, int B, int &half, int &tile) {
+__device__ __forceinline__ Tile tile_of_split(int B, int &half, int &tile) {
     const int C = B / GN;
     const int L = blockIdx.x, x = L & 7, t = L >> 3, tt = t >> 1;
     half = __builtin_amdgcn_readfirstlane(t & 1);
@@ -259,9 +268,9 @@ constexpr int stages() { return NP == 1 && KS <= 64 ? 2 : 1; }
 // registers) during the current stage's products.  (Two register stages in
 // flight measured slower: the extra registers pushed the forward kernel into
 // AGPR spills.)  kt0 and kt1 are k-tiles, multiples of the stage's k-tiles.
-template <int NP, int KS>
+template <int NP, int KS, int BM>
 __device__ __forceinline__ void gemm_tile(const GemmArgs &g, const __bf16 *planes, int w0, int b0, int tid,
-                                          __bf16 (*sA)[lds_a<KS>()], __bf16 (*sX)[lds_x<NP, KS>()], f32x16 (&acc)[RT][2],
+                                          __bf16 (*sA)[lds_a<KS, BM>()], __bf16 (*sX)[lds_x<NP, KS>()], f32x16 (&acc)[RT][2],
                                           int kt0 = 0, int kt1 = -1) {
     constexpr int TPS = KS / GK; // k-tiles per stage
     const int lane = tid & 63, wv = tid >> 6, wr = wv >> 1, wc = wv & 1;
@@ -276,23 +285,23 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, const __bf16 *plane
 
     int ks = next_stage<TPS>(flags, ntn, ks0, nks);
     int buf = 0, done = 0;
-    Stage<NP, KS> st;
+    Stage<NP, KS, BM> st;
     if (ks < nks) {
-        load_stage<NP, KS>(g, planes, ks, w0, b0, tid, st);
-        store_stage<NP, KS>(sA[0], sX[0], tid, st);
+        load_stage<NP, KS, BM>(g, planes, ks, w0, b0, tid, st);
+        store_stage<NP, KS, BM>(sA[0], sX[0], tid, st);
     }
     __syncthreads();
     while (ks < nks) {
         const int kn = next_stage<TPS>(flags, ntn, ks + 1, nks);
-        if (kn < nks) load_stage<NP, KS>(g, planes, kn, w0, b0, tid, st);
+        if (kn < nks) load_stage<NP, KS, BM>(g, planes, kn, w0, b0, tid, st);
         mma_stage<NP, KS>(sA[buf], sX[buf], lane, wr, wc, acc);
         if constexpr (stages<NP, KS>() == 2) {
-            if (kn < nks) store_stage<NP, KS>(sA[buf ^ 1], sX[buf ^ 1], tid, st);
+            if (kn < nks) store_stage<NP, KS, BM>(sA[buf ^ 1], sX[buf ^ 1], tid, st);
             __syncthreads();
             buf ^= 1;
         } else {
             __syncthreads(); // every wave is done with the stage
-            if (kn < nks) store_stage<NP, KS>(sA[0], sX[0], tid, st);
+            if (kn < nks) store_stage<NP, KS, BM>(sA[0], sX[0], tid, st);
             __syncthreads();
         }
         ks = kn;
@@ -309,16 +318,17 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, const __bf16 *plane
 // its own slot for limb k; the second to arrive adds the other's and returns
 // true, the first returns false.  One slot per limb: a half never waits, so
 // it may be several limbs ahead of the other.
+template <int T>
 __device__ __forceinline__ bool split_meet(const GemmArgs &g, int k, int tile, int half, int tid, int &s_last,
                                            f32x16 (&acc)[RT][2]) {
-    float *slot = g.ws + (((size_t)k * g.ntiles + tile) * 2) * 64 * GT;
+    float *slot = g.ws + (((size_t)k * g.ntiles + tile) * 2) * 64 * T;
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
             for (int r = 0; r < 16; ++r)
-                __hip_atomic_store(&slot[((size_t)half * 64 + (rt * 2 + ct) * 16 + r) * GT + tid], acc[rt][ct][r],
+                __hip_atomic_store(&slot[((size_t)half * 64 + (rt * 2 + ct) * 16 + r) * T + tid], acc[rt][ct][r],
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __asm__ __volatile__("s_waitcnt vmcnt(0)" ::: "memory"); // this thread's stores are done
     __syncthreads();
@@ -335,7 +345,7 @@ __device__ __forceinline__ bool split_meet(const GemmArgs &g, int k, int tile, i
         for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
             for (int r = 0; r < 16; ++r)
-                acc[rt][ct][r] += __hip_atomic_load(&slot[((size_t)(1 - half) * 64 + (rt * 2 + ct) * 16 + r) * GT + tid],
+                acc[rt][ct][r] += __hip_atomic_load(&slot[((size_t)(1 - half) * 64 + (rt * 2 + ct) * 16 + r) * T + tid],
                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return true;
 }
@@ -422,18 +432,18 @@ __device__ __forceinline__ void epi_fwd(const GemmArgs &g, const EpiArgs &e, int
 }
 
 // Forward level l -> l+1: one pass per 8-bit limb of level l's largest count,
-// each followed by its epilogue.  Grid: grid_blocks(npad, B), tiles by tile_of.
+// each followed by its epilogue.  Grid: grid_blocks<BM>(npad, B), tiles by tile_of.
 // KS: k per pipeline stage.
-template <typename S, int KS>
-__global__ __launch_bounds__(GT, 2) void k_mfma_fwd(GemmArgs g, EpiArgs e) {
-    __shared__ __align__(16) __bf16 sA[stages<1, KS>()][lds_a<KS>()];
+template <typename S, int KS, int BM>
+__global__ __launch_bounds__(2 * BM, 2) void k_mfma_fwd(GemmArgs g, EpiArgs e) {
+    __shared__ __align__(16) __bf16 sA[stages<1, KS>()][lds_a<KS, BM>()];
     __shared__ __align__(16) __bf16 sX[stages<1, KS>()][lds_x<1, KS>()];
     __shared__ int s_last;
     int half = 0, tile = 0;
-    const Tile tl = g.ksplit == 2 ? tile_of_split(g.npad, g.B, half, tile) : tile_of(g.npad, g.B);
-    if (tl.row >= g.npad / GM) return;
+    const Tile tl = g.ksplit == 2 ? tile_of_split(g.B, half, tile) : tile_of(g.B);
+    if (tl.row >= g.npad / BM) return;
     const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int w0 = tl.row * GM + (wv >> 1) * WM, b0 = tl.col * GN;
+    const int w0 = tl.row * BM + (wv >> 1) * WM, b0 = tl.col * GN;
     const int q = (b0 >> 6) + (wv & 1); // bitmap word of this wave's sources
     const int L = limbs_feeding(e.lvmax_cur, e.level, e.classes);
     if (blockIdx.x == 0 && tid == 0) atomicAdd(e.planes_issued, (unsigned long long)L);
@@ -441,8 +451,9 @@ __global__ __launch_bounds__(GT, 2) void k_mfma_fwd(GemmArgs g, EpiArgs e) {
     f32x16 acc[RT][2];
 #pragma nounroll
     for (int k = 0; k < L; ++k) {
-        gemm_tile<1, KS>(g, g.planes + (size_t)k * g.plane_elems, tl.row * GM, b0, tid, sA, sX, acc, kt0, kt1);
-        if (g.ksplit == 2 && !split_meet(g, k, tile, half, tid, s_last, acc)) continue; // the other half finishes it
+        gemm_tile<1, KS, BM>(g, g.planes + (size_t)k * g.plane_elems, tl.row * BM, b0, tid, sA, sX, acc, kt0, kt1);
+        if (g.ksplit == 2 && !split_meet<2 * BM>(g, k, tile, half, tid, s_last, acc))
+            continue; // the other half finishes it
         const int mode = L == 1 ? EPI_ONLY : k == 0 ? EPI_FIRST : k + 1 < L ? EPI_MID : EPI_LAST;
         // The epilogue's row addresses do not depend on k; an opaque copy of
         // the block's first row keeps the compiler from computing all of them
@@ -459,19 +470,19 @@ __global__ __launch_bounds__(GT, 2) void k_mfma_fwd(GemmArgs g, EpiArgs e) {
 // and BC(v) += delta summed over the block's sources (v != s_b).
 template <typename S>
 __global__ __launch_bounds__(GT, 2) void k_mfma_bwd(GemmArgs g, EpiArgs e) {
-    __shared__ __align__(16) __bf16 sA[stages<3, BWD_KS>()][lds_a<BWD_KS>()];
+    __shared__ __align__(16) __bf16 sA[stages<3, BWD_KS>()][lds_a<BWD_KS, BWD_BM>()];
     __shared__ __align__(16) __bf16 sX[stages<3, BWD_KS>()][lds_x<3, BWD_KS>()];
     // one block per tile: its stages of three planes are long enough already
     // (split in two halves of K it measured slower)
-    const Tile tl = tile_of(g.npad, g.B);
-    if (tl.row >= g.npad / GM) return;
+    const Tile tl = tile_of(g.B);
+    if (tl.row >= g.npad / BWD_BM) return;
     const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int b0 = tl.col * GN;
     if (blockIdx.x == 0 && tid == 0) atomicAdd(e.planes_issued, 3ull);
     f32x16 acc[RT][2];
-    gemm_tile<3, BWD_KS>(g, g.planes, tl.row * GM, b0, tid, sA, sX, acc);
+    gemm_tile<3, BWD_KS, BWD_BM>(g, g.planes, tl.row * BWD_BM, b0, tid, sA, sX, acc);
 
-    const int w0 = tl.row * GM + (wv >> 1) * WM;
+    const int w0 = tl.row * BWD_BM + (wv >> 1) * WM;
     const int q = (b0 >> 6) + (wv & 1);
     const int half = lane >> 5, col = lane & 31;
     S *sigma = reinterpret_cast<S *>(e.sigma);
@@ -613,7 +624,8 @@ GemmArgs gemm_args(bc_ctx *ctx, const __bf16 *planes, bool forward) {
     g.K = a.classes * a.npad;
     g.plane_elems = (size_t)g.K * ctx->sp.batch;
     g.ksplit = a.ksplit;
-    g.ntiles = (int32_t)grid_blocks(a.npad, ctx->sp.batch);
+    g.ntiles = (int32_t)(forward ? grid_blocks<FWD_BM>(a.npad, ctx->sp.batch)
+                                 : grid_blocks<BWD_BM>(a.npad, ctx->sp.batch));
     g.ws = a.ws;
     g.arrive = a.arrive;
     // counters: [0] planes, [1..2] forward k-tiles, [3..4] backward k-tiles
@@ -645,14 +657,15 @@ bc_status algebraic_prepare(bc_ctx *ctx) {
     a.kflags = (uint32_t *)bc_dalloc(ctx, (K / GK) * (B / GN) * sizeof(uint32_t));
     a.planes_issued = (unsigned long long *)bc_dalloc(ctx, 256);
     // Unweighted forward products over a long K (one npad per limb) with
-    // fewer tiles than two per compute unit: two blocks per output tile, each
-    // over half of K, so that the grid fills the chip.  With 512 tiles or more
+    // fewer tiles than the compute units hold blocks at once (256 units, LDS
+    // for 256 / FWD_BM blocks each): two blocks per output tile, each over
+    // half of K, so that the grid fills the chip.  With a full chip of tiles
     // the split measured slower (ER-16384, B = 512: 124 against 116 ms per
     // step), and with weight classes too (K is M npad; 0.43 of BF16 against 0.50).
-    const size_t ntiles = grid_blocks(a.npad, B);
-    a.ksplit = a.classes == 1 && K / GK >= 256 && ntiles < 512 ? 2 : 1;
+    const size_t ntiles = grid_blocks<FWD_BM>(a.npad, B);
+    a.ksplit = a.classes == 1 && K / GK >= 256 && ntiles < (size_t)256 * (256 / FWD_BM) ? 2 : 1;
     if (a.ksplit == 2) {
-        a.ws = (float *)bc_dalloc(ctx, (size_t)8 * ntiles * 2 * 64 * GT * sizeof(float));
+        a.ws = (float *)bc_dalloc(ctx, (size_t)8 * ntiles * 2 * 64 * (2 * FWD_BM) * sizeof(float));
         a.arrive = (uint32_t *)bc_dalloc(ctx, (size_t)8 * ntiles * sizeof(uint32_t));
     }
     if (!a.adj || !a.planes || !a.part || !a.kflags || !a.planes_issued ||
@@ -713,8 +726,8 @@ bc_status algebraic_forward_level_t(bc_ctx *ctx, int32_t l) {
     e.planes_issued = a.planes_issued;
     const GemmArgs g = gemm_args(ctx, a.planes, true);
     LaunchTimer tm(ctx, "mfma_fwd");
-    hipLaunchKernelGGL((k_mfma_fwd<S, FWD_KS>), dim3(grid_blocks(a.npad, s.batch) * a.ksplit), dim3(GT), 0,
-                       ctx->stream, g, e);
+    hipLaunchKernelGGL((k_mfma_fwd<S, FWD_KS, FWD_BM>), dim3(grid_blocks<FWD_BM>(a.npad, s.batch) * a.ksplit),
+                       dim3(2 * FWD_BM), 0, ctx->stream, g, e);
     tm.done();
     BC_HIP(ctx, hipGetLastError());
     return BC_OK;
@@ -749,7 +762,7 @@ bc_status algebraic_backward_level_t(bc_ctx *ctx, const uint64_t *fcur, const ui
     e.planes_issued = a.planes_issued;
     const GemmArgs g = gemm_args(ctx, a.planes, false);
     LaunchTimer tm(ctx, "mfma_bwd");
-    hipLaunchKernelGGL(k_mfma_bwd<S>, dim3(grid_blocks(a.npad, s.batch)), dim3(GT), 0, ctx->stream, g, e);
+    hipLaunchKernelGGL(k_mfma_bwd<S>, dim3(grid_blocks<BWD_BM>(a.npad, s.batch)), dim3(GT), 0, ctx->stream, g, e);
     tm.done();
     BC_HIP(ctx, hipGetLastError());
     return BC_OK;
