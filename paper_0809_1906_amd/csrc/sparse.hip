@@ -149,8 +149,10 @@ __device__ __forceinline__ bool last_arriver(uint32_t *arrive, int32_t total, in
 }
 
 // acc[q] += sum over arcs [beg, end) of sigma(v, 64q+lane) for neighbours v
-// whose word q of the level-l frontier meets U[q] at this lane.
-template <int NW, typename S>
+// whose word q of the level-l frontier meets U[q] at this lane.  UNIT: every
+// count of level l is 1 (level 1: the source's neighbours, one path each in a
+// simple graph), so the sum counts frontier bits and gathers no count row.
+template <int NW, typename S, bool UNIT>
 __device__ __forceinline__ void fwd_scan(const Topo &t, int32_t beg, int32_t end, const uint64_t (&U)[NW],
                                          const uint32_t *__restrict__ any_cur, const uint64_t *__restrict__ fcur,
                                          const S *__restrict__ sigma, int lane, uint64_t (&acc)[NW], bool &ovf) {
@@ -173,6 +175,14 @@ __device__ __forceinline__ void fwd_scan(const Topo &t, int32_t beg, int32_t end
 #pragma unroll
         for (int q = 0; q < NW; ++q) nz |= f[q];
         uint64_t act = __ballot(nz != 0);
+        if constexpr (UNIT) {
+            while (act) {
+                const int j = pop_lowest(act);
+#pragma unroll
+                for (int q = 0; q < NW; ++q) acc[q] += (rl64(f[q], j) >> lane) & 1;
+            }
+            continue;
+        }
         while (act) {
             uint64_t x[ARCS][NW];
 #pragma unroll
@@ -370,7 +380,7 @@ __device__ __forceinline__ void fwd_commit(int32_t w, const uint64_t (&vis)[NW],
 // rows complete in the last segment wave to arrive.  After the last real level
 // every vertex is visited for every source it can reach, so speculative
 // launches past the depth exit after one load per wave.
-template <int NW, typename S>
+template <int NW, typename S, bool UNIT>
 __global__ __launch_bounds__(SB) void k_fwd_pull(Topo t, const uint32_t *__restrict__ any_cur,
                                                  const uint64_t *__restrict__ fcur, uint64_t *__restrict__ fnext,
                                                  uint64_t *__restrict__ visited, S *__restrict__ sigma,
@@ -398,7 +408,7 @@ __global__ __launch_bounds__(SB) void k_fwd_pull(Topo t, const uint32_t *__restr
 #pragma unroll
     for (int q = 0; q < NW; ++q) acc[q] = 0;
     bool ovf = false, wide = false;
-    fwd_scan<NW, S>(t, it.beg, it.end, U, any_cur, fcur, sigma, lane, acc, ovf);
+    fwd_scan<NW, S, UNIT>(t, it.beg, it.end, U, any_cur, fcur, sigma, lane, acc, ovf);
     uint64_t out[NW];
     if (it.h < 0) {
         uint64_t mx = 0;
@@ -774,7 +784,10 @@ bc_status run_batch_t(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool acc
                 continue;
             }
             LaunchTimer tm(ctx, "fwd_pull");
-            hipLaunchKernelGGL((k_fwd_pull<NW, S>), dim3(pull_blocks), dim3(SB), 0, ctx->stream, t,
+            // level 1 holds the sources' neighbours, each with one shortest
+            // path (the input graph is simple): its pull counts frontier bits
+            const auto kern = l == 1 ? k_fwd_pull<NW, S, true> : k_fwd_pull<NW, S, false>;
+            hipLaunchKernelGGL(kern, dim3(pull_blocks), dim3(SB), 0, ctx->stream, t,
                                s.any + (size_t)l * aw, s.front + (size_t)l * words, s.front + (size_t)(l + 1) * words,
                                s.visited, sigma, (unsigned long long *)s.hacc, s.arrive, s.any + (size_t)(l + 1) * aw,
                                ctx->status, by_products(ctx, l + 1, true) ? s.lvmax + l + 1 : nullptr);
