@@ -33,6 +33,7 @@
 #include "bc_internal.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace {
 
@@ -149,15 +150,16 @@ __device__ __forceinline__ bool last_arriver(uint32_t *arrive, int32_t total, in
 }
 
 // acc[q] += sum over arcs [beg, end) of sigma(v, 64q+lane) for neighbours v
-// whose word q of the level-l frontier meets U[q] at this lane.  UNIT: every
-// count of level l is 1 (level 1: the source's neighbours, one path each in a
-// simple graph), so the sum counts frontier bits and gathers no count row.
-template <int NW, typename S, bool UNIT>
+// whose word q of the level-l frontier meets U[q] at this lane; sigma holds
+// the counts as G.  UNIT: every count of level l is 1 (level 1: the source's
+// neighbours, one path each in a simple graph), so the sum counts frontier
+// bits and gathers no count row.
+template <int NW, typename G, bool UNIT>
 __device__ __forceinline__ void fwd_scan(const Topo &t, int32_t beg, int32_t end, const uint64_t (&U)[NW],
                                          const uint32_t *__restrict__ any_cur, const uint64_t *__restrict__ fcur,
-                                         const S *__restrict__ sigma, int lane, uint64_t (&acc)[NW], bool &ovf) {
+                                         const G *__restrict__ sigma, int lane, uint64_t (&acc)[NW], bool &ovf) {
     constexpr int ARCS = NW >= GDEPTH ? 1 : GDEPTH / NW; // arcs per round, ARCS * NW gathers in flight
-    const S *sig = sigma + lane;
+    const G *sig = sigma + lane;
     for (int32_t base = beg; base < end; base += 64) {
         const int32_t e = base + lane;
         int32_t v = 0;
@@ -183,29 +185,36 @@ __device__ __forceinline__ void fwd_scan(const Topo &t, int32_t beg, int32_t end
             }
             continue;
         }
+        // Straight-line loads, the lane's bit selecting after all are issued:
+        // a load under a per-lane branch was compiled with a wait for its own
+        // result, so the gathers of a round ran one after another.  An arc
+        // slot past the last active arc, or a word with no source of this
+        // lane's mask, reads row 0 instead: a valid, cached address whose
+        // value is then dropped.
+        using X = typename std::conditional<sizeof(G) == 8, uint64_t, uint32_t>::type;
         while (act) {
-            uint64_t x[ARCS][NW];
+            X x[ARCS][NW];
+            uint64_t m[ARCS][NW];
 #pragma unroll
             for (int a = 0; a < ARCS; ++a) {
+                const bool live = act != 0;
+                const int j = live ? pop_lowest(act) : 0;
+                const size_t row = live ? (size_t)rl32(v, j) * t.B : 0;
 #pragma unroll
-                for (int q = 0; q < NW; ++q) x[a][q] = 0;
-                if (act) {
-                    const int j = pop_lowest(act);
-                    const size_t row = (size_t)rl32(v, j) * t.B;
-#pragma unroll
-                    for (int q = 0; q < NW; ++q) {
-                        const uint64_t fj = rl64(f[q], j);
-                        if (fj != 0 && ((fj >> lane) & 1)) x[a][q] = (uint64_t)sig[row + (size_t)q * 64];
-                    }
+                for (int q = 0; q < NW; ++q) {
+                    m[a][q] = live ? rl64(f[q], j) : 0;
+                    x[a][q] = sig[m[a][q] != 0 ? row + (size_t)q * 64 : 0];
                 }
             }
 #pragma unroll
             for (int a = 0; a < ARCS; ++a) {
 #pragma unroll
                 for (int q = 0; q < NW; ++q) {
-                    const uint64_t s = acc[q] + x[a][q];
-                    ovf |= s < acc[q];
-                    acc[q] = s;
+                    if ((m[a][q] >> lane) & 1) {
+                        const uint64_t s = acc[q] + (uint64_t)x[a][q];
+                        ovf |= s < acc[q];
+                        acc[q] = s;
+                    }
                 }
             }
         }
@@ -380,10 +389,19 @@ __device__ __forceinline__ void fwd_commit(int32_t w, const uint64_t (&vis)[NW],
 // rows complete in the last segment wave to arrive.  After the last real level
 // every vertex is visited for every source it can reach, so speculative
 // launches past the depth exit after one load per wave.
-template <int NW, typename S, bool UNIT>
+// Variants of the forward pull (uniform over a launch):
+// - FWD_GENERAL gathers level l's counts from sigma;
+// - FWD_UNIT (level 1 -> 2) sums frontier bits, every level-1 count being 1,
+//   and when sig16 is set also stores the level-2 counts there as 16 bits
+//   (each is at most the vertex's degree, below 2^16: the host checks);
+// - FWD_HALF (level 2 -> 3, after FWD_UNIT) gathers the level-2 counts from
+//   sig16: half the bytes of a uint32 row.
+enum { FWD_GENERAL = 0, FWD_UNIT = 1, FWD_HALF = 2 };
+template <int NW, typename S, int MODE>
 __global__ __launch_bounds__(SB) void k_fwd_pull(Topo t, const uint32_t *__restrict__ any_cur,
                                                  const uint64_t *__restrict__ fcur, uint64_t *__restrict__ fnext,
                                                  uint64_t *__restrict__ visited, S *__restrict__ sigma,
+                                                 uint16_t *__restrict__ sig16,
                                                  unsigned long long *__restrict__ hacc, uint32_t *__restrict__ arrive,
                                                  uint32_t *__restrict__ any_next, uint32_t *__restrict__ status,
                                                  unsigned long long *__restrict__ lvmax_next) {
@@ -408,14 +426,21 @@ __global__ __launch_bounds__(SB) void k_fwd_pull(Topo t, const uint32_t *__restr
 #pragma unroll
     for (int q = 0; q < NW; ++q) acc[q] = 0;
     bool ovf = false, wide = false;
-    fwd_scan<NW, S, UNIT>(t, it.beg, it.end, U, any_cur, fcur, sigma, lane, acc, ovf);
+    if constexpr (MODE == FWD_HALF)
+        fwd_scan<NW, uint16_t, false>(t, it.beg, it.end, U, any_cur, fcur, sig16, lane, acc, ovf);
+    else
+        fwd_scan<NW, S, MODE == FWD_UNIT>(t, it.beg, it.end, U, any_cur, fcur, sigma, lane, acc, ovf);
     uint64_t out[NW];
     if (it.h < 0) {
         uint64_t mx = 0;
 #pragma unroll
         for (int q = 0; q < NW; ++q) {
             out[q] = __ballot(acc[q] != 0);
-            if (acc[q] != 0) store_count(&sigma[(size_t)w * t.B + (size_t)q * 64 + lane], acc[q], wide);
+            if (acc[q] != 0) {
+                const size_t idx = (size_t)w * t.B + (size_t)q * 64 + lane;
+                store_count(&sigma[idx], acc[q], wide);
+                if (MODE == FWD_UNIT && sig16) sig16[idx] = (uint16_t)acc[q];
+            }
             mx = acc[q] > mx ? acc[q] : mx;
         }
         fwd_commit<NW>(w, vis, out, lane, fnext, visited, any_next);
@@ -436,7 +461,9 @@ __global__ __launch_bounds__(SB) void k_fwd_pull(Topo t, const uint32_t *__restr
                 const uint64_t x = __hip_atomic_load(&hrow[q * 64], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if (x != 0) {
                     __hip_atomic_store(&hrow[q * 64], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    store_count(&sigma[(size_t)w * t.B + (size_t)q * 64 + lane], x, wide);
+                    const size_t idx = (size_t)w * t.B + (size_t)q * 64 + lane;
+                    store_count(&sigma[idx], x, wide);
+                    if (MODE == FWD_UNIT && sig16) sig16[idx] = (uint16_t)x;
                 }
                 out[q] = __ballot(x != 0);
                 mx = x > mx ? x : mx;
@@ -752,6 +779,12 @@ bc_status run_batch_t(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool acc
     }
     int32_t launched = 0, nlev = -1;
     const bool wide_now = sizeof(S) == 8;
+    // 16-bit copy of level 2's counts, in the unused upper half of the count
+    // array (uint32 counts fill the first half of its uint64 capacity)
+    uint16_t *sig16 = !wide_now && ctx->max_degree < 65536
+                          ? reinterpret_cast<uint16_t *>(reinterpret_cast<uint32_t *>(s.sigma) + (size_t)n * B)
+                          : nullptr;
+    bool l1_pulled = false; // level 1 -> 2 ran as the pull that fills sig16
     // Weighted graphs (the algebraic form, Sec. 3.2): levels are distances and
     // level l+1 is formed from levels l+1-M .. l; the search ends at M
     // consecutive empty levels.
@@ -785,12 +818,18 @@ bc_status run_batch_t(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool acc
             }
             LaunchTimer tm(ctx, "fwd_pull");
             // level 1 holds the sources' neighbours, each with one shortest
-            // path (the input graph is simple): its pull counts frontier bits
-            const auto kern = l == 1 ? k_fwd_pull<NW, S, true> : k_fwd_pull<NW, S, false>;
+            // path (the input graph is simple): its pull counts frontier bits,
+            // and level 2's counts (at most a degree) also go to sig16, from
+            // which level 2 -> 3 gathers them
+            const auto kern = l == 1                  ? k_fwd_pull<NW, S, FWD_UNIT>
+                              : l == 2 && l1_pulled ? k_fwd_pull<NW, S, FWD_HALF>
+                                                      : k_fwd_pull<NW, S, FWD_GENERAL>;
+            if (l == 1) l1_pulled = sig16 != nullptr;
             hipLaunchKernelGGL(kern, dim3(pull_blocks), dim3(SB), 0, ctx->stream, t,
                                s.any + (size_t)l * aw, s.front + (size_t)l * words, s.front + (size_t)(l + 1) * words,
-                               s.visited, sigma, (unsigned long long *)s.hacc, s.arrive, s.any + (size_t)(l + 1) * aw,
-                               ctx->status, by_products(ctx, l + 1, true) ? s.lvmax + l + 1 : nullptr);
+                               s.visited, sigma, sig16, (unsigned long long *)s.hacc, s.arrive,
+                               s.any + (size_t)(l + 1) * aw, ctx->status,
+                               by_products(ctx, l + 1, true) ? s.lvmax + l + 1 : nullptr);
             tm.done();
             ps.done(true, l);
         }
