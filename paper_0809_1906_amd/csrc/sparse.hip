@@ -525,7 +525,7 @@ __global__ __launch_bounds__(SB) void k_bwd_pull(Topo t, const uint64_t *__restr
 // Backward level l, one wave per (row or row segment, word q): at the fat
 // levels this keeps NW times more waves in flight than a wave per row, and a
 // word with no sources at this level costs its wave a single load.
-template <int NW, typename S>
+template <int NW, typename S, bool EB>
 __global__ __launch_bounds__(SB) void k_bwd_pull_w(Topo t, const uint64_t *__restrict__ fcur,
                                                    const uint32_t *__restrict__ any_next,
                                                    const uint64_t *__restrict__ fnext, const S *__restrict__ sigma,
@@ -558,11 +558,14 @@ __global__ __launch_bounds__(SB) void k_bwd_pull_w(Topo t, const uint64_t *__res
                 if ((any_next[w >> 5] >> (w & 31)) & 1) g = fnext[(size_t)w * NW + q] & F;
             }
             uint64_t act = __ballot(g != 0);
+            // gathers per round: without edge terms the wave has the
+            // registers for sixteen at full occupancy
+            constexpr int D = EB ? GDEPTH : 2 * GDEPTH;
             while (act) {
-                float x[GDEPTH];
-                int jj[GDEPTH];
+                float x[D];
+                int jj[D];
 #pragma unroll
-                for (int u = 0; u < GDEPTH; ++u) {
+                for (int u = 0; u < D; ++u) {
                     x[u] = 0.f;
                     jj[u] = -1;
                     if (act) {
@@ -572,8 +575,8 @@ __global__ __launch_bounds__(SB) void k_bwd_pull_w(Topo t, const uint64_t *__res
                     }
                 }
 #pragma unroll
-                for (int u = 0; u < GDEPTH; ++u) acc[0] += (double)x[u];
-                if (eb) {
+                for (int u = 0; u < D; ++u) acc[0] += (double)x[u];
+                if (EB && eb) {
                     static_assert(GDEPTH == 8, "wave_sum8 reduces eight arcs");
                     double p[8];
 #pragma unroll
@@ -884,11 +887,13 @@ bc_status run_batch_t(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool acc
             continue;
         }
         LaunchTimer tm(ctx, "bwd_pull");
-        if (s.bwd_per_word || ctx->edges) // edge terms come from the per-word pull
-            hipLaunchKernelGGL((k_bwd_pull_w<NW, S>), dim3(word_blocks), dim3(SB), 0, ctx->stream, t, fcur, anext,
-                               fnext, (const S *)sigma, s.cval, s.src, ctx->bc, s.hacc, s.arrive_w, ddump,
-                               accumulate ? 1 : 0, accumulate && ctx->edges ? ctx->eb : nullptr);
-        else
+        if (s.bwd_per_word || ctx->edges) { // edge terms come from the per-word pull
+            double *eb = accumulate && ctx->edges ? ctx->eb : nullptr;
+            const auto kern = eb ? k_bwd_pull_w<NW, S, true> : k_bwd_pull_w<NW, S, false>;
+            hipLaunchKernelGGL(kern, dim3(word_blocks), dim3(SB), 0, ctx->stream, t, fcur, anext, fnext,
+                               (const S *)sigma, s.cval, s.src, ctx->bc, s.hacc, s.arrive_w, ddump,
+                               accumulate ? 1 : 0, eb);
+        } else
             hipLaunchKernelGGL((k_bwd_pull<NW, S>), dim3(pull_blocks), dim3(SB), 0, ctx->stream, t, fcur, anext, fnext,
                                (const S *)sigma, s.cval, s.src, ctx->bc, s.hacc, s.arrive, ddump, accumulate ? 1 : 0);
         tm.done();
