@@ -14,6 +14,8 @@ the many-graph workload, the sum over graphs of n_g * m_g).
                     [--form F] [--batch B] [--no-cpu-baseline] [--no-compare]
 
 Other workloads (same JSON schema; used for profiles and design figures):
+  er1024   ER n=1024, degree 8, plus a spanning tree, all sources: the plain
+           FP64 form, against the sparse form
   er16384  ER n=16384, degree 256, all sources: algebraic form, batch 512,
            against the sparse and hybrid forms
   ws4096   4096 Watts-Strogatz graphs, all sources: one persistent launch
@@ -68,6 +70,9 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sparse_rmat16_traffic.txt")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_0809_1906_amd", "csrc", "sparse.hip")
 
 WORKLOADS = {
+    "er1024": {"form": "plain", "batch": 0, "compare": [("sparse", 256)],
+               "desc": "er1024: Erdos-Renyi n=1024, average degree 8, plus a seeded random spanning tree; exact "
+                       "all-source BC"},
     "rmat16": {"form": "hybrid", "batch": 256, "compare": [("plain", 0)],
                "desc": "rmat16: RMAT scale 16, edgefactor 16, (a,b,c,d)=(.57,.19,.19,.05), symmetrised, "
                        "deduplicated, largest component; exact all-source BC"},
@@ -177,44 +182,93 @@ def load_workload(name, sources):
     return {"graph": g, "n": g.n, "m": g.m, "src": src, "S": S, "work": float(S) * g.m}
 
 
-def cpu_baseline(name, wl, target_s: float = 20.0):
-    """The oracle as it stands, on a bounded sample of the workload, all host
-    cores it may use (at most 16)."""
+def host_cpus():
+    """(threads the oracle uses, nproc, CPU model).  The oracle uses the CPUs
+    this process may run on, at most 16: one GPU's share of a GPU host."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return max(1, min(16, avail)), os.cpu_count() or 1, model
+
+
+def err_report(got, want):
+    """max_v |x - y| / max(|y|, 1), its argmax, and the largest purely
+    relative error over vertices with BC >= 1."""
+    got, want = np.asarray(got, np.float64), np.asarray(want, np.float64)
+    if want.size == 0:
+        return {"max_rel_err_vs_oracle": 0.0}
+    e = np.abs(got - want) / np.maximum(np.abs(want), 1.0)
+    i = int(np.argmax(e))
+    big = np.abs(want) >= 1.0
+    pure = float(np.max(np.abs(got - want)[big] / np.abs(want)[big])) if np.any(big) else 0.0
+    return {"max_rel_err_vs_oracle": float(e[i]), "argmax_vertex": i, "bc_at_argmax": float(want[i]),
+            "max_pure_rel_err_bc_ge_1": pure}
+
+
+def cpu_baseline(name, wl, target_s: float = 20.0, whole: bool = True):
+    """The oracle as it stands, timed on the host: over every source of the
+    workload when that fits the budget (else an evenly spaced sample sized to
+    about target_s), on the host threads host_cpus() allows; also one thread
+    on the first 64 sources.  Returns (baseline dict, oracle BC of the sources
+    it ran or None, the sources it ran)."""
     import oracle
-    threads = max(1, min(16, os.cpu_count() or 1))
+    threads, nproc, model = host_cpus()
+    cores = {"cores": threads, "nproc": nproc, "cpu_model": model,
+             "threads_note": "threads = the CPUs this process may use, at most 16 (one GPU's share of the host)"}
     if name == "ws4096":
         gs = wl["graph"]
         order = list(range(0, len(gs), 3))  # every third graph, in generation order, until the time is up
         t0 = time.perf_counter()
-        done, work = 0, 0.0
+        done, work, per_graph = 0, 0.0, {}
         for i in order:
-            oracle.bc(gs[i], threads=threads)
+            per_graph[i] = oracle.bc(gs[i], threads=threads)
             done += 1
             work += gs[i].n * gs[i].m
             if time.perf_counter() - t0 > target_s:
                 break
         t = time.perf_counter() - t0
-        return {"value": work / t, "unit": "TEPS", "cores": threads, "kind": "oracle",
-                "sample": f"{done} of {len(gs)} graphs (every third, first ones), all sources each, {threads} threads "
-                          f"over sources, {t:.1f} s"}
+        return ({"value": work / t, "unit": "TEPS", "kind": "oracle", **cores,
+                 "sample": f"{done} of {len(gs)} graphs (every third, first ones), all sources each, {threads} "
+                           f"threads over sources, {t:.1f} s"}, per_graph, None)
     g = wl["graph"]
     pool = wl["src"] if wl["src"] is not None else np.arange(g.n, dtype=np.int32)
-    probe = pool[np.linspace(0, pool.size - 1, min(pool.size, threads)).astype(np.int64)]
+    # one thread, the first 64 sources
+    first = pool[:64]
     t0 = time.perf_counter()
-    oracle.bc(g, probe, threads=threads)
-    per_src = (time.perf_counter() - t0) / probe.size
-    count = int(min(pool.size, max(probe.size, target_s / max(per_src, 1e-9))))
-    sample = pool[np.linspace(0, pool.size - 1, count).astype(np.int64)]
+    oracle.bc(g, first, threads=1)
+    t1 = time.perf_counter() - t0
+    single = {"value": first.size * g.m / t1, "unit": "TEPS", "sources": int(first.size), "seconds": t1,
+              "sample": f"the first {first.size} sources, one thread"}
+    log(f"oracle, one thread, {first.size} sources: {t1:.2f} s")
+    est = t1 / max(first.size, 1) * pool.size / threads
+    if whole and est <= 3.0 * target_s:
+        sample = pool
+    else:
+        count = int(min(pool.size, max(64, target_s / max(t1 / max(first.size, 1) / threads, 1e-9))))
+        sample = pool[np.linspace(0, pool.size - 1, count).astype(np.int64)]
+    log(f"oracle on {sample.size} of {pool.size} sources, {threads} threads (estimate {est:.1f} s for all)")
     t0 = time.perf_counter()
-    oracle.bc(g, sample, threads=threads)
+    want = oracle.bc(g, sample, threads=threads)
     t = time.perf_counter() - t0
-    return {"value": count * g.m / t, "unit": "TEPS", "cores": threads, "kind": "oracle",
-            "sample": f"{count} of {pool.size} sources (evenly spaced), serial Brandes per source, "
-                      f"{threads} threads over sources, {t:.1f} s"}
+    what = ("every source" if sample.size == pool.size else
+            f"{sample.size} of {pool.size} sources (evenly spaced)")
+    return ({"value": sample.size * g.m / t, "unit": "TEPS", "kind": "oracle", **cores,
+             "sample": f"{what}, serial Brandes per source, {threads} threads over sources, {t:.1f} s",
+             "single_core": single}, want, sample)
 
 
-KERNELS = ("fwd_pull", "bwd_pull", "fwd_push0", "batch_init", "limb_split", "mfma_fwd", "coef_split", "mfma_bwd",
-           "plain_sweep", "weighted_sweep", "multigraph_sweep")
+KERNELS = ("fwd_pull", "bwd_pull", "fwd_push0", "batch_init", "batch_check", "kflag_clear", "limb_split", "mfma_fwd",
+           "coef_split", "mfma_bwd", "plain_sweep", "weighted_sweep", "multigraph_sweep")
 
 
 def roofline(name, wl, kern, info, steps):
@@ -271,6 +325,9 @@ def roofline(name, wl, kern, info, steps):
         # peak; and how many algorithmic bytes each DRAM byte served
         extra["dram_frac"] = traffic / (ms / max(launches, 1) * 1e-3) / 1e9 / HBM_PEAK_GBS
         extra["alg_bytes_per_dram_byte"] = total / max(launches, 1) / traffic
+        extra["note"] = ("frac = the per-source model's algorithmic bytes (a batch shares its CSR and bitmap "
+                         "reads, so one DRAM byte serves several model bytes) per launch time; dram_frac = "
+                         "bytes measured by rocprofv3 FETCH_SIZE/WRITE_SIZE per launch time, the HBM rate")
     return dict(base, bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
                 traffic=traffic, alg_bytes_per_launch=total / max(launches, 1), **extra)
 
@@ -298,12 +355,15 @@ def run_allpairs(args, spec, wl, bcgpu, torch):
     log("kernel times (ms, launches):", kern)
     ms, launches = kern["all_pairs"]
     avg = ms / launches
-    ops = 2.0 * float(n) ** 3  # one add and one compare per tested triple
+    # a tested triple is one three-operand add and half a three-operand
+    # minimum: 1.5 VALU lane-instructions, the unit of the peak
+    ops = 1.5 * float(n) ** 3
     ach = ops / (avg * 1e-3) / 1e12
     roof = {"kernel": "all_pairs", "avg_launch_ms": avg, "launches": launches, "bound": "alu", "achieved": ach,
-            "peak": VALU_INT32_PEAK_TOPS, "unit": "Top/s", "frac": ach / VALU_INT32_PEAK_TOPS, "traffic": None,
-            "alg_ops_per_launch": ops,
-            "note": "n^3 tested triples x 2 int32 ops (add, compare) per launch; peak = 256 CUs x 64 lanes x 2.4 GHz"}
+            "peak": VALU_INT32_PEAK_TOPS, "unit": "T lane-instructions/s", "frac": ach / VALU_INT32_PEAK_TOPS,
+            "traffic": None, "alg_ops_per_launch": ops,
+            "note": "n^3 tested triples x 1.5 VALU lane-instructions (v_add3, half a v_min3) per launch; peak = "
+                    "256 CUs x 64 lanes x 2.4 GHz lane-instructions/s"}
     compare = {}
     if not args.no_compare:
         ctx.reset()
@@ -317,7 +377,12 @@ def run_allpairs(args, spec, wl, bcgpu, torch):
                                            "max_rel_diff_vs_all_pairs": err}
         log(f"brandes {bdt * 1e3:.1f} ms, max rel diff {err:.2e}")
     ctx.close()
-    cpu = None if args.no_cpu_baseline else cpu_baseline("er16384", wl)
+    cpu, acc = None, {}
+    if not args.no_cpu_baseline:
+        cpu, want, _ = cpu_baseline("er16384", wl)
+        if want is not None and want.size == n:
+            acc = err_report(got, want)
+            log(f"all pairs vs oracle: {acc}")
     return {
         "metric": "all-pairs BC by Algorithm 2 on ER-16384, TEPS (n·m/s)",
         "value": n * m / dt,
@@ -334,6 +399,7 @@ def run_allpairs(args, spec, wl, bcgpu, torch):
         "config": {"workload": spec["desc"], "n": n, "m": m, "form_filling_D_Lambda": form, "batch": info.batch},
         "compare": compare,
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kern.items()},
+        "accuracy": acc,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
@@ -494,10 +560,12 @@ def main():
 
     step_ms = {}
 
-    def timed_runs(form, steps, warmup, batch=0, timing=TIMING_SAMPLE, edges=False):
+    def timed_runs(form, steps, warmup, batch=0, timing=TIMING_SAMPLE, edges=False, host_driven=False,
+                   label=None):
+        label = label or form
         t = time.perf_counter()
         ctx = bcgpu.BC(wl["graph"], form="auto" if form == "many" else form, batch=batch, timing=timing,
-                       edges=edges)
+                       edges=edges, host_driven=host_driven)
         info = ctx.info()
         log(f"{form} create (upload, dense adjacency, tuning) {time.perf_counter() - t:.2f}s: batch {info.batch}, "
             f"products when density >= ({info.mfma_density_fwd:.3f} fwd, {info.mfma_density_bwd:.3f} bwd), "
@@ -505,7 +573,7 @@ def main():
         for i in range(warmup):
             ctx.run(src)
             ctx.read()
-            log(f"{form} warmup {i} done")
+            log(f"{label} warmup {i} done")
         ctx.reset()
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -515,12 +583,12 @@ def main():
             ctx.run(src)
             torch.cuda.synchronize()
             per_step.append(time.perf_counter() - ts)
-            log(f"{form} step {i} done")
+            log(f"{label} step {i} done")
         dt = (time.perf_counter() - t) / steps
-        step_ms[form] = {"mean": dt * 1e3, "median": float(np.median(per_step)) * 1e3,
-                         "min": float(np.min(per_step)) * 1e3}
+        step_ms[label] = {"mean": dt * 1e3, "median": float(np.median(per_step)) * 1e3,
+                          "min": float(np.min(per_step)) * 1e3}
         bc = ctx.read()
-        log(f"{form} {steps} steps: {dt * 1e3:.1f} ms/step, {work / dt:.3e} TEPS")
+        log(f"{label} {steps} steps: {dt * 1e3:.1f} ms/step, {work / dt:.3e} TEPS")
         return ctx, dt, bc
 
     ctx, dt, bc_main = timed_runs(form, args.steps, args.warmup, batch, edges=args.edges)
@@ -544,6 +612,16 @@ def main():
                 "mfma_density": [finfo.mfma_density_fwd, finfo.mfma_density_bwd]}
 
     compare = {}
+    if not args.no_compare and form in ("hybrid", "sparse", "algebraic") and args.workload != "er16384w4":
+        # the same form with every batch driven level by level from the host
+        hctx, hdt, bc_h = timed_runs(form, args.compare_steps, 1, batch, host_driven=True, label="host-driven")
+        hctx.close()
+        err = float(np.max(np.abs(bc_main / args.steps - bc_h / args.compare_steps) /
+                           np.maximum(np.abs(bc_h / args.compare_steps), 1.0)))
+        compare["host_driven"] = {"value": work / hdt, "ms_per_step": hdt * 1e3,
+                                  "max_rel_diff_vs_measured": err,
+                                  "note": "every batch's levels launched from the host, one synchronisation per "
+                                          "batch, instead of replaying the recorded batch"}
     if not args.no_compare:
         for cform, cbatch in spec["compare"]:
             cctx, cdt, bc_c = timed_runs(cform, args.compare_steps, 0, cbatch)
@@ -556,7 +634,28 @@ def main():
             compare[cform] = {"value": work / cdt, "ms_per_step": cdt * 1e3, "batch": cinfo.batch,
                               "kernel_ms": ckern, "max_rel_diff_vs_measured": err}
 
-    cpu = None if args.no_cpu_baseline else cpu_baseline(args.workload, wl)
+    cpu, accuracy = None, {}
+    if not args.no_cpu_baseline:
+        cpu, want, osrc = cpu_baseline(args.workload, wl)
+        per_step = bc_main / args.steps  # the context accumulated every timed step
+        if args.workload == "ws4096":
+            offs = np.concatenate([[0], np.cumsum([x.n for x in wl["graph"]])])
+            worst = {"max_rel_err_vs_oracle": 0.0}
+            for i, wv in want.items():
+                r = err_report(per_step[offs[i]:offs[i + 1]], wv)
+                if r["max_rel_err_vs_oracle"] >= worst["max_rel_err_vs_oracle"]:
+                    worst = dict(r, graph=i)
+            accuracy = dict(worst, compared=f"{len(want)} graphs, the oracle's CPU-baseline sample")
+        elif osrc is not None and (wl["src"] is None and osrc.size == wl["n"]
+                                   or wl["src"] is not None and osrc.size == wl["src"].size):
+            accuracy = dict(err_report(per_step, want), compared="the measured output, every source")
+        elif osrc is not None:
+            # the oracle ran a sample: run the same sources on the GPU
+            with bcgpu.BC(wl["graph"], form="auto" if form == "many" else form, batch=batch) as sctx:
+                sctx.run(osrc)
+                accuracy = dict(err_report(sctx.read(), want),
+                                compared=f"{osrc.size} sources (the oracle's sample), same form and batch")
+        log(f"accuracy vs oracle: {accuracy}")
 
     if args.calibrate_copy:
         x = torch.empty(256 << 20, dtype=torch.float32, device=dev)  # 1 GiB
@@ -571,6 +670,10 @@ def main():
     if form in ("hybrid", "sparse", "algebraic"):
         config["mfma_density_thresholds"] = [info.mfma_density_fwd, info.mfma_density_bwd]
         config["tune_source"] = ["default", "measured", "cached"][info.tune_source]
+        config["mfma_planes_issued"] = int(info.mfma_planes)
+        if form == "hybrid" and info.mfma_planes == 0:
+            config["mfma_note"] = ("the tuner measured every level faster by CSR pulls on this graph, so no "
+                                   "level ran as an MFMA product in the timed steps")
     out = {
         "metric": METRIC if args.workload == "rmat16" else f"BC TEPS (sources·m/s) on {args.workload}",
         "value": work / dt,
@@ -588,7 +691,9 @@ def main():
         "tuned_batch_width": free,
         "compare": compare,
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kern.items()},
+        "time_outside_kernels_frac": max(0.0, 1.0 - sum(v[0] for v in kern.values()) / args.steps / (dt * 1e3)),
         "step_ms": main_step_ms,
+        "accuracy": accuracy,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

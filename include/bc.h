@@ -41,7 +41,9 @@ typedef enum {
     BC_ERR_NOMEM = 3,         /* a device or host allocation failed */
     BC_ERR_DEVICE = 4,        /* a HIP runtime call failed; the context is poisoned */
     BC_ERR_OVERFLOW = 5,      /* a shortest-path count exceeded 2^64 - 1 */
-    BC_ERR_STATE = 6,         /* call not allowed in the context's current state */
+    BC_ERR_STATE = 6,         /* call not allowed in the context's current state: the context
+                                 was poisoned by a device error, or its stream is being
+                                 captured into a HIP graph (no call may be recorded) */
     BC_ERR_UNSUPPORTED = 7    /* valid request this form cannot serve */
 } bc_status;
 
@@ -80,6 +82,12 @@ typedef enum { BC_MEM_HOST = 0, BC_MEM_DEVICE = 1 } bc_mem;
  */
 /* Largest integer weight the algebraic form takes (one product class each). */
 #define BC_ALGEBRAIC_MAX_WEIGHT 8
+/* Largest vertex degree the algebraic form takes: an output of a product sums
+ * at most deg 8-bit limb terms, and FP32 accumulation is exact while
+ * 255 * deg <= 2^24 + 256.  bc_create refuses a larger degree with
+ * BC_ERR_UNSUPPORTED for the algebraic form; the hybrid form then runs every
+ * level by pulls. */
+#define BC_ALGEBRAIC_MAX_DEGREE 65792
 
 typedef enum {
     BC_FORM_AUTO = 0,
@@ -162,7 +170,17 @@ typedef struct {
                              (the hybrid form then takes every backward level
                              by pulls); BC_ERR_UNSUPPORTED for the algebraic
                              form and bc_create_many. */
-    int32_t reserved[1];
+    int32_t host_driven;  /* batched forms, unit weights.  0 (default): bc_run
+                             records one source batch's launches (every level of
+                             the forward and backward sweeps, up to the deepest
+                             level seen so far plus one) into a HIP graph once
+                             and replays it for every batch, with no host
+                             synchronisation between batches; a batch that
+                             goes deeper, or whose counts need 64 bits, is
+                             handed back and re-run when the context is next
+                             used.  Nonzero: every batch is driven level by
+                             level from the host, one synchronisation per
+                             batch.  Results are the same. */
 } bc_options;
 
 /* Where the batch width and hybrid thresholds of a context came from. */
@@ -337,10 +355,12 @@ bc_status bc_get_info(const bc_ctx *ctx, bc_info *out);
  * named `kernel` (e.g. "plain_sweep", "fwd_pull", "bwd_pull"), returns the
  * number of its launches since create / reset and their summed duration in
  * milliseconds, measured with HIP events on the context's stream.  With k = 1
- * every launch is timed; with k > 1 the batched forms time every launch of
- * the first source batch and then of every k-th (so every level keeps its
- * share), the total being scaled from the timed launches to all of them;
- * forms without batches time every launch.  Unknown names give zero.
+ * every launch is timed (the batched forms then drive every batch from the
+ * host); with k > 1 the batched forms time every launch of the first source
+ * batch and then of every k-th (so every level keeps its share), running
+ * those batches host-driven and replaying the others, and scale the timed
+ * batches' totals and launch counts to all batches; forms without batches
+ * time every launch.  Unknown names give zero.
  * Synchronises the stream.  bc_create refuses a negative k.
  */
 bc_status bc_get_timing(bc_ctx *ctx, const char *kernel, double *total_ms, int64_t *launches);

@@ -11,4 +11,4 @@ from .binding import (BC_OK, BC_ERR_INVALID_ARG, BC_ERR_INVALID_GRAPH, BC_ERR_NO
                       BC_ERR_DEVICE, BC_ERR_OVERFLOW, BC_ERR_STATE, BC_ERR_UNSUPPORTED)
 from .binding import (BC_FORM_AUTO, BC_FORM_PLAIN_FP64, BC_FORM_SPARSE, BC_FORM_ALGEBRAIC,  # noqa: F401
                       BC_FORM_HYBRID, BC_FORM_MANY, BC_TUNE_DEFAULT, BC_TUNE_MEASURED, BC_TUNE_CACHED,
-                      BC_ALL_PAIRS_MAX_N, BC_ALGEBRAIC_MAX_WEIGHT, BC_SAMPLED_MAX_S)
+                      BC_ALL_PAIRS_MAX_N, BC_ALGEBRAIC_MAX_WEIGHT, BC_ALGEBRAIC_MAX_DEGREE, BC_SAMPLED_MAX_S)

@@ -41,6 +41,7 @@ FORMS = {"auto": BC_FORM_AUTO, "plain": BC_FORM_PLAIN_FP64, "sparse": BC_FORM_SP
 
 BC_ALL_PAIRS_MAX_N = 32768
 BC_ALGEBRAIC_MAX_WEIGHT = 8
+BC_ALGEBRAIC_MAX_DEGREE = 65792
 BC_SAMPLED_MAX_S = 4096
 BC_TUNE_DEFAULT = 0
 BC_TUNE_MEASURED = 1
@@ -66,7 +67,7 @@ class bc_options(ctypes.Structure):
                 ("timing", ctypes.c_int32), ("split_degree", ctypes.c_int32),
                 ("vertex_order", ctypes.c_int32), ("arena_log2", ctypes.c_int32),
                 ("tune_cache", ctypes.c_char_p), ("grid", ctypes.c_int32), ("edges", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 1)]
+                ("host_driven", ctypes.c_int32)]
 
 
 class bc_info(ctypes.Structure):
@@ -249,7 +250,7 @@ class BC:
     def __init__(self, graph, form: str = "auto", batch: int = 0, device: int = 0, stream=None,
                  allocator: str = "torch", timing=False, split_degree: int = 0,
                  vertex_order: str = "degree", arena_log2: int = 0, tune_cache: Optional[str] = None,
-                 grid: int = 0, edges: bool = False):
+                 grid: int = 0, edges: bool = False, host_driven: bool = False):
         import torch
         load()
         if not torch.cuda.is_available():
@@ -273,6 +274,7 @@ class BC:
         opt.tune_cache = self._tune_cache
         opt.grid = grid
         opt.edges = 1 if edges else 0
+        opt.host_driven = 1 if host_driven else 0
         self._alloc = None
         if allocator == "torch":
             self._alloc = _TorchAllocator(device)

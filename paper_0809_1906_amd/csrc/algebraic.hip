@@ -77,6 +77,8 @@ struct GemmArgs {
     float *ws;             // split tiles' partial sums, [8][ntiles][2][64][forward block threads]
     uint32_t *arrive;      // [8][ntiles]
     unsigned long long *ktiles; // [0] k-tiles multiplied, [1] k-tiles in the blocks' ranges (per direction)
+    const uint32_t *gate;  // unit weights: flag of the level the product reads (forward: level l;
+                           // backward: level l, whose vertices it writes); zero = every block exits
 };
 
 struct EpiArgs {
@@ -93,6 +95,7 @@ struct EpiArgs {
     unsigned long long *lvmax_next;      // forward: largest count of level l+1
     int32_t classes, level;              // forward: M, and l (levels l+1-M .. l feed level l+1)
     unsigned long long *planes_issued;   // products issued (limb or coefficient planes)
+    uint32_t *flag_next;                 // forward, unit weights: set when level l+1 gets a vertex
     int accumulate;
 };
 
@@ -361,7 +364,7 @@ __device__ __forceinline__ void epi_fwd(const GemmArgs &g, const EpiArgs &e, int
     const bool first = mode == EPI_FIRST, mid = mode == EPI_MID, last = mode == EPI_LAST;
     const bool final_limb = mode == EPI_ONLY || last;
     S *sigma = reinterpret_cast<S *>(e.sigma);
-    bool wide = false, ovf = false;
+    bool wide = false, ovf = false, reached = false;
     uint64_t mx = 0;
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
@@ -413,6 +416,7 @@ __device__ __forceinline__ void epi_fwd(const GemmArgs &g, const EpiArgs &e, int
                     if (word) {
                         e.visited[(size_t)w * g.NW + q] = vis | word;
                         atomicOr(&e.any_next[w >> 5], 1u << (w & 31));
+                        reached = true;
                     }
                 }
             }
@@ -427,6 +431,9 @@ __device__ __forceinline__ void epi_fwd(const GemmArgs &g, const EpiArgs &e, int
         if (lane == 0 && mx > __hip_atomic_load(e.lvmax_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
             atomicMax(e.lvmax_next, (unsigned long long)mx);
         if (__any(wide) && lane == 0) atomicOr(&e.status[1], 1u);
+        if (e.flag_next && __any(reached) && lane == 0 &&
+            __hip_atomic_load(e.flag_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+            __hip_atomic_store(e.flag_next, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (__any(ovf) && lane == 0) atomicOr(&e.status[0], (uint32_t)BC_DEV_SIGMA_OVERFLOW);
 }
@@ -439,6 +446,7 @@ __global__ __launch_bounds__(2 * BM, 2) void k_mfma_fwd(GemmArgs g, EpiArgs e) {
     __shared__ __align__(16) __bf16 sA[stages<1, KS>()][lds_a<KS, BM>()];
     __shared__ __align__(16) __bf16 sX[stages<1, KS>()][lds_x<1, KS>()];
     __shared__ int s_last;
+    if (g.gate && *g.gate == 0) return; // level l is empty: nothing to expand
     int half = 0, tile = 0;
     const Tile tl = g.ksplit == 2 ? tile_of_split(g.B, half, tile) : tile_of(g.B);
     if (tl.row >= g.npad / BM) return;
@@ -474,6 +482,7 @@ __global__ __launch_bounds__(GT, 2) void k_mfma_bwd(GemmArgs g, EpiArgs e) {
     __shared__ __align__(16) __bf16 sX[stages<3, BWD_KS>()][lds_x<3, BWD_KS>()];
     // one block per tile: its stages of three planes are long enough already
     // (split in two halves of K it measured slower)
+    if (g.gate && *g.gate == 0) return; // level l is empty (or the batch was handed back)
     const Tile tl = tile_of(g.B);
     if (tl.row >= g.npad / BWD_BM) return;
     const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -501,7 +510,7 @@ __global__ __launch_bounds__(GT, 2) void k_mfma_bwd(GemmArgs g, EpiArgs e) {
                     const double sv = (double)sigma[idx];
                     const double dl = sv * (double)acc[rt][ct][r];
                     e.cval[idx] = (float)((1.0 + dl) / sv);
-                    if (e.delta_dump) e.delta_dump[idx] = dl;
+                    if (e.delta_dump) e.delta_dump[(size_t)(q * 64 + bit) * g.n + v] = dl; // [b][v], as bc_read_sssp
                     if (e.src_lane[q * 64 + bit] != v) contrib += dl;
                 }
             }
@@ -515,6 +524,12 @@ __global__ __launch_bounds__(GT, 2) void k_mfma_bwd(GemmArgs g, EpiArgs e) {
 }
 
 // ---- element-wise kernels -------------------------------------------------------
+
+// Zeroes `count` words (a kernel rather than a memset, so that it can be
+// recorded into a replayed graph).
+__global__ __launch_bounds__(PB) void k_zero32(uint32_t *__restrict__ p, size_t count) {
+    for (size_t i = (size_t)blockIdx.x * PB + threadIdx.x; i < count; i += (size_t)gridDim.x * PB) p[i] = 0;
+}
 
 // A[v][(c-1) npad + w] = 1 for every arc v -> w of weight c (c = 1 without
 // weights).
@@ -540,10 +555,12 @@ __global__ __launch_bounds__(PB) void k_limb_split(int32_t n, int32_t npad, int3
                                                    int32_t l, const unsigned long long *__restrict__ lvmax_l,
                                                    const uint64_t *__restrict__ fl, size_t words,
                                                    const S *__restrict__ sigma, __bf16 *__restrict__ planes,
-                                                   size_t plane_elems, uint32_t *__restrict__ kflags) {
+                                                   size_t plane_elems, uint32_t *__restrict__ kflags,
+                                                   const uint32_t *__restrict__ gate) {
     const size_t id = (size_t)blockIdx.x * PB + threadIdx.x;
     const size_t per_class = (size_t)(npad / 8) * B;
     if (id >= per_class * M) return;
+    if (gate && *gate == 0) return; // level l is empty: the product exits too
     const int32_t c = (int32_t)(id / per_class);
     const size_t r = id - (size_t)c * per_class;
     const int L = limbs_feeding(lvmax_l, l, M);
@@ -574,10 +591,14 @@ __global__ __launch_bounds__(PB) void k_limb_split(int32_t n, int32_t npad, int3
 __global__ __launch_bounds__(PB) void k_coef_split(int32_t n, int32_t npad, int32_t B, int32_t NW, int32_t M,
                                                    int32_t deeper, const uint64_t *__restrict__ fl, size_t words,
                                                    const float *__restrict__ cval, __bf16 *__restrict__ planes,
-                                                   size_t plane_elems, uint32_t *__restrict__ kflags) {
+                                                   size_t plane_elems, uint32_t *__restrict__ kflags,
+                                                   const uint32_t *__restrict__ gate) {
     const size_t id = (size_t)blockIdx.x * PB + threadIdx.x;
     const size_t per_class = (size_t)(npad / 8) * B;
     if (id >= per_class * M) return;
+    // gate[0]: level l (empty: the product exits too); gate[1]: level l+1
+    if (gate && gate[0] == 0) return;
+    if (gate && gate[1] == 0) deeper = 0;
     const int32_t cl = (int32_t)(id / per_class);
     const size_t r = id - (size_t)cl * per_class;
     const int32_t vg = (int32_t)(r / B), b = (int32_t)(r - (size_t)vg * B);
@@ -607,8 +628,16 @@ __global__ __launch_bounds__(PB) void k_coef_split(int32_t n, int32_t npad, int3
 
 inline unsigned blocks_for(size_t count, int per) { return (unsigned)((count + per - 1) / per); }
 
-inline size_t kflag_bytes(bc_ctx *ctx) {
-    return (size_t)ctx->al.classes * (ctx->al.npad / GK) * (ctx->sp.batch / GN) * sizeof(uint32_t);
+inline size_t kflag_words(bc_ctx *ctx) {
+    return (size_t)ctx->al.classes * (ctx->al.npad / GK) * (ctx->sp.batch / GN);
+}
+
+void clear_kflags(bc_ctx *ctx) {
+    const size_t w = kflag_words(ctx);
+    LaunchTimer tm(ctx, "kflag_clear");
+    hipLaunchKernelGGL(k_zero32, dim3((unsigned)std::min<size_t>((w + PB - 1) / PB, 1024)), dim3(PB), 0, ctx->stream,
+                       ctx->al.kflags, w);
+    tm.done();
 }
 
 GemmArgs gemm_args(bc_ctx *ctx, const __bf16 *planes, bool forward) {
@@ -627,6 +656,7 @@ GemmArgs gemm_args(bc_ctx *ctx, const __bf16 *planes, bool forward) {
     g.ntiles = (int32_t)(forward ? grid_blocks<FWD_BM>(a.npad, ctx->sp.batch)
                                  : grid_blocks<BWD_BM>(a.npad, ctx->sp.batch));
     g.ws = a.ws;
+    g.gate = nullptr;
     g.arrive = a.arrive;
     // counters: [0] planes, [1..2] forward k-tiles, [3..4] backward k-tiles
     g.ktiles = a.planes_issued ? a.planes_issued + (forward ? 1 : 3) : nullptr;
@@ -641,7 +671,7 @@ bc_status algebraic_prepare(bc_ctx *ctx) {
     if (ctx->weighted && ctx->max_weight > BC_ALGEBRAIC_MAX_WEIGHT)
         return bc_fail(ctx, BC_ERR_UNSUPPORTED, "algebraic form: weights above 8 (one product class per weight)");
     if (B % GN != 0) return bc_fail(ctx, BC_ERR_UNSUPPORTED, "algebraic form: batch must be 256 or 512");
-    if (ctx->max_degree > 65792)
+    if (ctx->max_degree > BC_ALGEBRAIC_MAX_DEGREE)
         return bc_fail(ctx, BC_ERR_UNSUPPORTED,
                        "algebraic form: a degree above 65792 breaks exact FP32 accumulation of 8-bit limbs");
     a.npad = std::max(NPAD, (ctx->n + NPAD - 1) / NPAD * NPAD);
@@ -697,19 +727,19 @@ bc_status algebraic_release(bc_ctx *ctx) {
 // counts, any[l+1] and the largest count of level l+1 exactly as the pull
 // kernel does; reads the largest count of level l on the device.
 template <typename S>
-bc_status algebraic_forward_level_t(bc_ctx *ctx, int32_t l) {
+bc_status algebraic_forward_level_t(bc_ctx *ctx, int32_t l, uint32_t *gate) {
     AlgebraicState &a = ctx->al;
     SparseState &s = ctx->sp;
     const size_t words = (size_t)ctx->n * s.words;
     const size_t aw = (size_t)(ctx->n + 31) / 32;
     const uint64_t *fcur = s.front + (size_t)l * words;
     const size_t plane_elems = (size_t)a.classes * a.npad * s.batch;
-    BC_HIP(ctx, hipMemsetAsync(a.kflags, 0, kflag_bytes(ctx), ctx->stream));
+    clear_kflags(ctx);
     {
         LaunchTimer tm(ctx, "limb_split");
         hipLaunchKernelGGL(k_limb_split<S>, dim3(blocks_for(plane_elems / 8, PB)), dim3(PB), 0, ctx->stream, ctx->n,
                            a.npad, s.batch, s.words, a.classes, l, s.lvmax + l, fcur, words, (const S *)s.sigma,
-                           a.planes, plane_elems, a.kflags);
+                           a.planes, plane_elems, a.kflags, (const uint32_t *)gate);
         tm.done();
     }
     EpiArgs e{};
@@ -724,7 +754,9 @@ bc_status algebraic_forward_level_t(bc_ctx *ctx, int32_t l) {
     e.classes = a.classes;
     e.level = l;
     e.planes_issued = a.planes_issued;
-    const GemmArgs g = gemm_args(ctx, a.planes, true);
+    e.flag_next = gate ? gate + 1 : nullptr;
+    GemmArgs g = gemm_args(ctx, a.planes, true);
+    g.gate = gate;
     LaunchTimer tm(ctx, "mfma_fwd");
     hipLaunchKernelGGL((k_mfma_fwd<S, FWD_KS, FWD_BM>), dim3(grid_blocks<FWD_BM>(a.npad, s.batch) * a.ksplit),
                        dim3(2 * FWD_BM), 0, ctx->stream, g, e);
@@ -738,17 +770,17 @@ bc_status algebraic_forward_level_t(bc_ctx *ctx, int32_t l) {
 // next ones `words` apart).
 template <typename S>
 bc_status algebraic_backward_level_t(bc_ctx *ctx, const uint64_t *fcur, const uint64_t *fnext, int32_t deeper,
-                                     double *delta_dump, bool accumulate) {
+                                     double *delta_dump, bool accumulate, const uint32_t *gate) {
     AlgebraicState &a = ctx->al;
     SparseState &s = ctx->sp;
     const size_t words = (size_t)ctx->n * s.words;
     const size_t plane_elems = (size_t)a.classes * a.npad * s.batch;
-    BC_HIP(ctx, hipMemsetAsync(a.kflags, 0, kflag_bytes(ctx), ctx->stream));
+    clear_kflags(ctx);
     {
         LaunchTimer tm(ctx, "coef_split");
         hipLaunchKernelGGL(k_coef_split, dim3(blocks_for(plane_elems / 8, PB)), dim3(PB), 0, ctx->stream, ctx->n,
                            a.npad, s.batch, s.words, a.classes, fnext ? deeper : 0, fnext, words, s.cval, a.planes,
-                           plane_elems, a.kflags);
+                           plane_elems, a.kflags, gate);
         tm.done();
     }
     EpiArgs e{};
@@ -760,7 +792,8 @@ bc_status algebraic_backward_level_t(bc_ctx *ctx, const uint64_t *fcur, const ui
     e.delta_dump = delta_dump;
     e.accumulate = accumulate ? 1 : 0;
     e.planes_issued = a.planes_issued;
-    const GemmArgs g = gemm_args(ctx, a.planes, false);
+    GemmArgs g = gemm_args(ctx, a.planes, false);
+    g.gate = gate;
     LaunchTimer tm(ctx, "mfma_bwd");
     hipLaunchKernelGGL(k_mfma_bwd<S>, dim3(grid_blocks<BWD_BM>(a.npad, s.batch)), dim3(GT), 0, ctx->stream, g, e);
     tm.done();
@@ -768,14 +801,14 @@ bc_status algebraic_backward_level_t(bc_ctx *ctx, const uint64_t *fcur, const ui
     return BC_OK;
 }
 
-bc_status algebraic_forward_level(bc_ctx *ctx, bool wide, int32_t l) {
-    return wide ? algebraic_forward_level_t<uint64_t>(ctx, l) : algebraic_forward_level_t<uint32_t>(ctx, l);
+bc_status algebraic_forward_level(bc_ctx *ctx, bool wide, int32_t l, uint32_t *gate) {
+    return wide ? algebraic_forward_level_t<uint64_t>(ctx, l, gate) : algebraic_forward_level_t<uint32_t>(ctx, l, gate);
 }
 
 bc_status algebraic_backward_level(bc_ctx *ctx, bool wide, const uint64_t *fcur, const uint64_t *fnext,
-                                   int32_t deeper, double *delta_dump, bool accumulate) {
-    return wide ? algebraic_backward_level_t<uint64_t>(ctx, fcur, fnext, deeper, delta_dump, accumulate)
-                : algebraic_backward_level_t<uint32_t>(ctx, fcur, fnext, deeper, delta_dump, accumulate);
+                                   int32_t deeper, double *delta_dump, bool accumulate, const uint32_t *gate) {
+    return wide ? algebraic_backward_level_t<uint64_t>(ctx, fcur, fnext, deeper, delta_dump, accumulate, gate)
+                : algebraic_backward_level_t<uint32_t>(ctx, fcur, fnext, deeper, delta_dump, accumulate, gate);
 }
 
 int64_t algebraic_planes_issued(bc_ctx *ctx) {

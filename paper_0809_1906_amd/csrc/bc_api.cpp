@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -102,6 +103,7 @@ void release_all(bc_ctx *ctx) {
     ctx->mg.exec = nullptr;
     ctx->mg.ev = nullptr;
     ctx->mg.stream = nullptr;
+    sparse_graphs_release(ctx);
     bc_timers_clear(ctx);
     for (hipEvent_t e : ctx->event_pool) hipEventDestroy(e);
     ctx->event_pool.clear();
@@ -187,15 +189,19 @@ void bc_timers_clear(bc_ctx *ctx) {
         }
     ctx->timers.clear();
     ctx->timing_batches = 0;
+    ctx->eager_batches = 0;
     ctx->timing_sel = true;
 }
 
 void bc_timing_batch(bc_ctx *ctx) {
-    if (ctx->timing > 1) ctx->timing_sel = ctx->timing_batches++ % ctx->timing == 0;
+    if (ctx->timing > 1) ctx->timing_sel = ctx->timing_batches % ctx->timing == 0;
+    ++ctx->timing_batches;
 }
 
+void bc_timing_eager(bc_ctx *ctx) { ++ctx->eager_batches; }
+
 LaunchTimer::LaunchTimer(bc_ctx *c, const char *nm) : ctx(c), name(nm) {
-    if (!ctx->timing || !ctx->timing_sel) return;
+    if (ctx->recording || !ctx->timing || !ctx->timing_sel) return;
     a = bc_event_get(ctx);
     b = bc_event_get(ctx);
     if (a && b) {
@@ -208,7 +214,7 @@ LaunchTimer::LaunchTimer(bc_ctx *c, const char *nm) : ctx(c), name(nm) {
 }
 
 void LaunchTimer::done() {
-    if (!ctx->timing) return;
+    if (ctx->recording || !ctx->timing) return;
     auto &t = ctx->timers[name];
     t.launches += 1;
     if (!a) return;
@@ -321,6 +327,13 @@ bc_status bc_create(const bc_graph *g, const bc_options *opt_in, bc_ctx **out) {
     if (hw && form == BC_FORM_ALGEBRAIC && max_w > BC_ALGEBRAIC_MAX_WEIGHT)
         return fail_create(BC_ERR_UNSUPPORTED,
                            "the algebraic form takes weights up to BC_ALGEBRAIC_MAX_WEIGHT (one product class each)");
+    // An output of a product sums at most deg(w) limb terms of at most 255;
+    // FP32 holds every integer below 2^24 exactly, so 255 * deg must stay below
+    // 2^24 + 256 (deg <= 65792).  The hybrid form runs such graphs by pulls.
+    if (form == BC_FORM_ALGEBRAIC && max_deg > BC_ALGEBRAIC_MAX_DEGREE)
+        return fail_create(BC_ERR_UNSUPPORTED,
+                           "the algebraic form takes degrees up to BC_ALGEBRAIC_MAX_DEGREE (exact FP32 sums of "
+                           "8-bit limbs)");
 
     // ---- device side ----
     bc_ctx *ctx = new (std::nothrow) bc_ctx();
@@ -333,12 +346,14 @@ bc_status bc_create(const bc_graph *g, const bc_options *opt_in, bc_ctx **out) {
     ctx->stream = (hipStream_t)opt.stream;
     ctx->alloc = opt.allocator;
     ctx->timing = opt.timing;
+    ctx->host_driven = opt.host_driven != 0;
     ctx->form = form;
 
     auto bail = [&](bc_status s, const std::string &m) {
+        const std::string msg = m; // m may be ctx->err, which delete frees
         release_all(ctx);
         delete ctx;
-        return fail_create(s, m);
+        return fail_create(s, msg);
     };
     int dev = opt.device;
     if (dev < 0) {
@@ -524,9 +539,10 @@ bc_status bc_create_many(const bc_graph *gs, int32_t count, const bc_options *op
     ctx->form = BC_FORM_MANY;
     ctx->many = true;
     auto bail = [&](bc_status s, const std::string &m) {
+        const std::string msg = m; // m may be ctx->err, which delete frees
         release_all(ctx);
         delete ctx;
-        return fail_create(s, m);
+        return fail_create(s, msg);
     };
     int dev = opt.device;
     if (dev < 0 && hipGetDevice(&dev) != hipSuccess) return bail(BC_ERR_DEVICE, "hipGetDevice failed");
@@ -601,7 +617,16 @@ static bc_status stage_sources(bc_ctx *ctx, const int32_t *sources, int64_t coun
 static bc_status check_usable(bc_ctx *ctx) {
     if (ctx->poisoned) return bc_fail(ctx, BC_ERR_STATE, "context poisoned by an earlier device error");
     if (hipSetDevice(ctx->device) != hipSuccess) return bc_hip(ctx, hipErrorInvalidDevice, "hipSetDevice");
-    return BC_OK;
+    // Every call may synchronise the stream or read results back, which a
+    // stream under graph capture does not allow; nothing is recorded.
+    if (ctx->stream) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(ctx->stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+            return bc_fail(ctx, BC_ERR_STATE, "the context's stream is being captured into a HIP graph");
+    }
+    // batches replayed by an earlier bc_run: read their checks, re-run what
+    // they handed back
+    return sparse_settle(ctx);
 }
 
 static bc_status check_overflow(bc_ctx *ctx) {
@@ -811,6 +836,7 @@ bc_status bc_sampled_distances(bc_ctx *ctx, const int32_t *sources, int32_t coun
 
 bc_status bc_get_info(const bc_ctx *ctx, bc_info *out) {
     if (!ctx || !out) return BC_ERR_INVALID_ARG;
+    if (!ctx->poisoned) (void)sparse_settle(const_cast<bc_ctx *>(ctx)); // replays' depth and sources
     memset(out, 0, sizeof(*out));
     out->n = ctx->n;
     out->m = ctx->nnz / 2;
@@ -838,6 +864,7 @@ bc_status bc_get_timing(bc_ctx *ctx, const char *kernel, double *total_ms, int64
     if (!ctx || !kernel || !total_ms || !launches) return BC_ERR_INVALID_ARG;
     *total_ms = 0.0;
     *launches = 0;
+    if (!ctx->poisoned) (void)sparse_settle(ctx); // replays' handed-back batches are counted too
     auto it = ctx->timers.find(kernel);
     if (it == ctx->timers.end()) return BC_OK;
     BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -850,8 +877,13 @@ bc_status bc_get_timing(bc_ctx *ctx, const char *kernel, double *total_ms, int64
     }
     it->second.pending.clear();
     const KernelTimer &t = it->second;
-    *total_ms = t.timed ? t.total_ms * (double)t.launches / (double)t.timed : 0.0;
-    *launches = t.launches;
+    // host-driven batches count their launches; replayed ones are alike and
+    // carry no events: scale by batches
+    const double f = ctx->eager_batches > 0 && ctx->timing_batches > ctx->eager_batches
+                         ? (double)ctx->timing_batches / (double)ctx->eager_batches
+                         : 1.0;
+    *total_ms = t.timed ? t.total_ms * (double)t.launches / (double)t.timed * f : 0.0;
+    *launches = (int64_t)std::llround((double)t.launches * f);
     return BC_OK;
 }
 

@@ -24,6 +24,20 @@ struct KernelTimer {
     int64_t timed = 0;     // launches that carried an event pair
 };
 
+// Device control block of a replayed run of source batches (see sparse.hip):
+// the batch counter that tells each replay which sources it takes, and what
+// the per-batch checks found.
+struct BatchCtl {
+    int32_t batch;          // index of the batch the next replay runs
+    int32_t total;          // sources in the run
+    const int32_t *src;     // the run's internal source ids
+    int32_t *redo;          // [batches] first source of each batch handed back to the host
+    uint32_t redo_count;
+    uint32_t max_nlev;      // deepest level count among the batches that completed
+    uint32_t need_wide;     // a handed-back batch needs uint64 counts
+    uint32_t deep;          // a handed-back batch went past the captured depth
+};
+
 // State of the batched sparse form (per-level frontier bitmaps).
 struct SparseState {
     int32_t batch = 0;        // sources per batch: 64, 128, 256 or 512
@@ -36,7 +50,6 @@ struct SparseState {
     uint64_t *visited = nullptr; // [n][words]
     uint64_t *sigma = nullptr;   // [n][batch] as uint64, or uint32 in its first half
     float *cval = nullptr;       // [n][batch]  c(v) = (1 + delta(v)) / sigma(v)
-    double *delta_dump = nullptr;// [n][batch]  only for bc_read_sssp
     int32_t *src = nullptr;      // [batch] sources of the current batch (-1 = empty lane)
     uint32_t *any_host = nullptr; // pinned mirror of any, read once per batch
     int32_t *heavy_id = nullptr; // [n] index among heavy rows or -1
@@ -45,7 +58,21 @@ struct SparseState {
     uint32_t *arrive_w = nullptr;// [nheavy][words] segment arrival counters (per row and word)
     bool bwd_per_word = true;    // backward: one wave per (row, word) instead of per row
     int32_t depth_guess = 8;     // forward levels launched before the first check
+    int32_t depth_max = 0;       // most levels any batch of this state has had (0: none run yet)
     bool wide = false;           // counts need uint64 storage (else uint32)
+    uint32_t *lvflag = nullptr;  // [level_cap] non-zero iff the level holds a vertex for some source
+    // replayed batches (unit weights): graphs of one batch's launches, the
+    // control block, the handed-back list and what the graphs were made for
+    BatchCtl *ctl = nullptr;
+    int32_t *redo = nullptr;
+    int64_t redo_cap = 0;
+    hipStream_t cap_stream = nullptr;  // private stream the batch is captured on
+    hipGraphExec_t gexec = nullptr;    // the recorded batch
+    int32_t g_levels = 0;              // forward levels the graph holds
+    bool g_wide = false;
+    const void *g_front = nullptr;     // state pointers the graph was recorded with
+    std::vector<uint8_t> g_plan;       // per level: bit 0 forward by products, bit 1 backward
+    bool g_pending = false;            // replays whose checks the host has not read
     int32_t *seg_v = nullptr, *seg_beg = nullptr, *seg_end = nullptr; // [nseg]
     int32_t nheavy = 0, nseg = 0;
     double *hacc = nullptr;      // [nheavy][batch] partial sums of split rows (u64 or f64)
@@ -197,8 +224,12 @@ struct bc_ctx {
     bool overflow_seen = false;
     std::string err;
 
+    bool host_driven = false;   // batched forms: no replayed batches (bc_options.host_driven)
+    bool recording = false;     // launches are being recorded into a graph (no timing events)
+
     int32_t timing = 0;         // 0 off; k >= 1: events on the launches of one source batch in k
     int64_t timing_batches = 0; // batches begun since create / reset
+    int64_t eager_batches = 0;  // of those, batches driven from the host (their launches counted)
     bool timing_sel = true;     // the current batch's launches carry events
     std::map<std::string, KernelTimer> timers;
     std::vector<hipEvent_t> event_pool; // timing events ready for reuse
@@ -219,8 +250,11 @@ void bc_timers_clear(bc_ctx *ctx);
 // source batch is timed; every launch is counted.  bc_timing_batch marks the
 // start of a batch: with timing = k > 1 every launch of one batch in k carries
 // events, so per-launch averages keep every level's share.  Work outside
-// batches is timed whenever timing is on.
+// batches is timed whenever timing is on.  A replayed batch carries no
+// events; a timed batch is run host-driven (bc_timing_eager counts it), and
+// bc_get_timing scales the host-driven batches' totals to all batches.
 void bc_timing_batch(bc_ctx *ctx);
+void bc_timing_eager(bc_ctx *ctx);
 struct LaunchTimer {
     bc_ctx *ctx;
     const char *name;
@@ -262,10 +296,15 @@ bc_status multigraph_dump(bc_ctx *ctx, const int32_t *h_sources, int32_t count, 
 bc_status sparse_prepare(bc_ctx *ctx, int32_t batch, int32_t split_degree);
 bc_status algebraic_prepare(bc_ctx *ctx);
 // Forward level l -> l+1 by products (front, counts, any and lvmax of level l+1).
-bc_status algebraic_forward_level(bc_ctx *ctx, bool wide, int32_t l);
+// With gate = &lvflag[l] (unit weights), an empty level l makes every
+// launch exit at once, and a non-empty level l+1 sets gate[1].
+bc_status algebraic_forward_level(bc_ctx *ctx, bool wide, int32_t l, uint32_t *gate = nullptr);
 // Backward level l; `deeper` of the levels l+1 .. l+M exist, fnext = front[l+1].
+// With gate = &lvflag[l] (unit weights), an empty level l exits at once and
+// level l+1 counts as existing only if gate[1] is set.
 bc_status algebraic_backward_level(bc_ctx *ctx, bool wide, const uint64_t *fcur, const uint64_t *fnext,
-                                   int32_t deeper, double *delta_dump, bool accumulate);
+                                   int32_t deeper, double *delta_dump, bool accumulate,
+                                   const uint32_t *gate = nullptr);
 int64_t algebraic_planes_issued(bc_ctx *ctx); // synchronises; -1 on a device error
 // k-tiles the products multiplied and those a dense product would have;
 // synchronises; false on a device error
@@ -277,6 +316,12 @@ bc_status algebraic_release(bc_ctx *ctx);
 // the batched forms; accumulate = false leaves BC untouched.
 bc_status sparse_batch(bc_ctx *ctx, const int32_t *d_sources, int32_t count, bool accumulate);
 bc_status sparse_run(bc_ctx *ctx, const int32_t *d_sources, int64_t count);
+// Reads back what replayed batches found and re-runs the batches they handed
+// back (on the host-driven path); synchronises.  A no-op when nothing is
+// pending.  Every entry point calls it before touching the context's state.
+bc_status sparse_settle(bc_ctx *ctx);
+// Destroys the recorded batch graphs and their capture stream; synchronises.
+void sparse_graphs_release(bc_ctx *ctx);
 // delta_dump = nullptr runs the forward only (distances and counts).
 bc_status sparse_dump(bc_ctx *ctx, const int32_t *d_sources, int32_t count,
                       int32_t *dist_dump, uint64_t *sigma_dump, double *delta_dump);

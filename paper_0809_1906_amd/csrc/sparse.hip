@@ -139,6 +139,13 @@ __device__ __forceinline__ double wave_sum8(const double (&p)[8], int lane) {
 // cache write-back fence.
 __device__ __forceinline__ void wait_memory() { __asm__ __volatile__("s_waitcnt vmcnt(0)" ::: "memory"); }
 
+// Marks a level as holding a vertex (lvflag): the flag settles after the first
+// few waves, which later waves read and skip the store.
+__device__ __forceinline__ void mark_level(uint32_t *flag) {
+    if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+        __hip_atomic_store(flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ bool last_arriver(uint32_t *arrive, int32_t total, int lane) {
     wait_memory();
     uint32_t old = 0;
@@ -273,10 +280,11 @@ __device__ __forceinline__ void bwd_scan(const Topo &t, int32_t beg, int32_t end
 
 // For every word with sources at this level: delta(v,b) = sigma(v,b) * acc,
 // c(v,b) = (1 + delta) / sigma; BC(v) += sum of delta over lanes whose source
-// is not v (one atomic per vertex).
+// is not v (one atomic per vertex).  A dump of the dependencies is
+// source-major, delta_dump[b][v] (n per row), the layout bc_read_sssp returns.
 template <int NW, typename S>
 __device__ __forceinline__ void bwd_finalize(int32_t v, const uint64_t (&F)[NW], const double (&acc)[NW], int lane,
-                                             int B, const S *__restrict__ sigma, float *__restrict__ cval,
+                                             int B, int32_t n, const S *__restrict__ sigma, float *__restrict__ cval,
                                              const int32_t *__restrict__ src_lane, double *__restrict__ bc,
                                              double *__restrict__ delta_dump, int accumulate) {
     double contrib = 0.0;
@@ -287,7 +295,7 @@ __device__ __forceinline__ void bwd_finalize(int32_t v, const uint64_t (&F)[NW],
             const double sv = (double)sigma[idx];
             const double dl = sv * acc[q];
             cval[idx] = (float)((1.0 + dl) / sv);
-            if (delta_dump) delta_dump[idx] = dl;
+            if (delta_dump) delta_dump[(size_t)(q * 64 + lane) * n + v] = dl;
             if (src_lane[q * 64 + lane] != v) contrib += dl;
         }
     }
@@ -298,11 +306,12 @@ __device__ __forceinline__ void bwd_finalize(int32_t v, const uint64_t (&F)[NW],
     }
 }
 
-// Clears front levels 0 and 1 (a: 2 * words entries), visited (b) and every
-// level's vertex filter.
+// Clears front levels 0 and 1 (a: 2 * words entries), visited (b), every
+// level's vertex filter and every level's flag.
 __global__ __launch_bounds__(SB) void k_sp_clear(uint64_t *__restrict__ a, uint64_t *__restrict__ b, size_t words,
                                                  uint32_t *__restrict__ any_all, size_t any_total,
-                                                 unsigned long long *__restrict__ lvmax, int32_t levels) {
+                                                 unsigned long long *__restrict__ lvmax, uint32_t *__restrict__ lvflag,
+                                                 int32_t levels) {
     const size_t tid = (size_t)blockIdx.x * SB + threadIdx.x, stride = (size_t)gridDim.x * SB;
     for (size_t i = tid; i < words; i += stride) {
         a[i] = 0;
@@ -311,17 +320,42 @@ __global__ __launch_bounds__(SB) void k_sp_clear(uint64_t *__restrict__ a, uint6
     }
     for (size_t i = tid; i < any_total; i += stride) any_all[i] = 0;
     // every count of level 1 is 1 (the pushed first level)
-    for (size_t i = tid; i < (size_t)levels; i += stride) lvmax[i] = i <= 1 ? 1ull : 0ull;
+    for (size_t i = tid; i < (size_t)levels; i += stride) {
+        lvmax[i] = i <= 1 ? 1ull : 0ull;
+        lvflag[i] = 0;
+    }
 }
 
+// Start of a replayed run: the control block's batch counter, sources and
+// handed-back list.
+__global__ void k_run_init(BatchCtl *ctl, const int32_t *src, int32_t total, int32_t *redo) {
+    if (threadIdx.x != 0) return;
+    ctl->batch = 0;
+    ctl->total = total;
+    ctl->src = src;
+    ctl->redo = redo;
+    ctl->redo_count = 0;
+    ctl->max_nlev = 0;
+    ctl->need_wide = 0;
+    ctl->deep = 0;
+}
+
+// Seeds the batch: lane b takes source src[b] (b < count).  In a replayed
+// batch (ctl non-null) the sources are the run's batch ctl->batch instead.
 template <typename S>
 __global__ __launch_bounds__(SB) void k_sp_seed(const int32_t *__restrict__ src, int32_t count, int32_t B, int32_t NW,
                                                 uint64_t *front0, uint64_t *visited, S *sigma, int32_t *src_lane,
-                                                uint32_t *any0) {
+                                                uint32_t *any0, uint32_t *lvflag, const BatchCtl *__restrict__ ctl) {
     const int32_t b = blockIdx.x * SB + threadIdx.x;
     if (b >= B) return;
+    if (ctl) {
+        const int64_t b0 = (int64_t)ctl->batch * B;
+        src = ctl->src + b0;
+        count = (int32_t)min((int64_t)B, (int64_t)ctl->total - b0);
+    }
     const int32_t s = b < count ? src[b] : -1;
     src_lane[b] = s;
+    if (b == 0 && count > 0) lvflag[0] = 1u;
     if (s >= 0) {
         const unsigned long long bit = 1ull << (b & 63);
         atomicOr((unsigned long long *)&front0[(size_t)s * NW + (b >> 6)], bit);
@@ -337,10 +371,12 @@ __global__ __launch_bounds__(SB) void k_sp_seed(const int32_t *__restrict__ src,
 template <typename S>
 __global__ __launch_bounds__(SB) void k_fwd_push0(Topo t, int32_t NW, const int32_t *__restrict__ src_lane,
                                                   uint64_t *__restrict__ fnext, uint64_t *__restrict__ visited,
-                                                  S *__restrict__ sigma, uint32_t *__restrict__ any_next) {
+                                                  S *__restrict__ sigma, uint32_t *__restrict__ any_next,
+                                                  uint32_t *__restrict__ flag_next) {
     const int32_t b = blockIdx.x;
     const int32_t s = src_lane[b];
     if (s < 0) return;
+    if (threadIdx.x == 0 && t.rp[s + 1] > t.rp[s]) mark_level(flag_next);
     const unsigned long long bit = 1ull << (b & 63);
     const int q = b >> 6;
     for (int32_t e = t.rp[s] + threadIdx.x; e < t.rp[s + 1]; e += SB) {
@@ -368,7 +404,7 @@ __device__ __forceinline__ void wave_max_to(unsigned long long *dst, uint64_t x)
 template <int NW>
 __device__ __forceinline__ void fwd_commit(int32_t w, const uint64_t (&vis)[NW], const uint64_t (&out)[NW], int lane,
                                            uint64_t *__restrict__ fnext, uint64_t *__restrict__ visited,
-                                           uint32_t *__restrict__ any_next) {
+                                           uint32_t *__restrict__ any_next, uint32_t *__restrict__ flag_next) {
     uint64_t mine_out = 0, mine_vis = 0, all = 0;
 #pragma unroll
     for (int q = 0; q < NW; ++q) {
@@ -382,7 +418,10 @@ __device__ __forceinline__ void fwd_commit(int32_t w, const uint64_t (&vis)[NW],
         fnext[(size_t)w * NW + lane] = mine_out;
         if (mine_out) visited[(size_t)w * NW + lane] = mine_vis;
     }
-    if (lane == 0 && all) atomicOr(&any_next[w >> 5], 1u << (w & 31));
+    if (lane == 0 && all) {
+        atomicOr(&any_next[w >> 5], 1u << (w & 31));
+        mark_level(flag_next);
+    }
 }
 
 // Forward level l -> l+1 for l >= 1.  Light rows complete in their wave; split
@@ -404,7 +443,12 @@ __global__ __launch_bounds__(SB) void k_fwd_pull(Topo t, const uint32_t *__restr
                                                  uint16_t *__restrict__ sig16,
                                                  unsigned long long *__restrict__ hacc, uint32_t *__restrict__ arrive,
                                                  uint32_t *__restrict__ any_next, uint32_t *__restrict__ status,
-                                                 unsigned long long *__restrict__ lvmax_next) {
+                                                 unsigned long long *__restrict__ lvmax_next,
+                                                 uint32_t *__restrict__ lvf) {
+    // lvf[0]: level l holds a vertex; lvf[1]: set here when level l+1 does.
+    // An empty level l leaves level l+1 empty: every wave exits at once (its
+    // front words are then never read: readers check the flag first).
+    if (*lvf == 0) return;
     const int lane = threadIdx.x & 63;
     const int64_t wid = (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6);
     Item it;
@@ -443,7 +487,7 @@ __global__ __launch_bounds__(SB) void k_fwd_pull(Topo t, const uint32_t *__restr
             }
             mx = acc[q] > mx ? acc[q] : mx;
         }
-        fwd_commit<NW>(w, vis, out, lane, fnext, visited, any_next);
+        fwd_commit<NW>(w, vis, out, lane, fnext, visited, any_next, lvf + 1);
         if (lvmax_next) wave_max_to(lvmax_next, mx);
     } else {
         unsigned long long *hrow = hacc + (size_t)it.h * t.B + lane;
@@ -468,7 +512,7 @@ __global__ __launch_bounds__(SB) void k_fwd_pull(Topo t, const uint32_t *__restr
                 out[q] = __ballot(x != 0);
                 mx = x > mx ? x : mx;
             }
-            fwd_commit<NW>(w, vis, out, lane, fnext, visited, any_next);
+            fwd_commit<NW>(w, vis, out, lane, fnext, visited, any_next, lvf + 1);
             if (lvmax_next) wave_max_to(lvmax_next, mx);
         }
     }
@@ -485,7 +529,11 @@ __global__ __launch_bounds__(SB) void k_bwd_pull(Topo t, const uint64_t *__restr
                                                  float *__restrict__ cval, const int32_t *__restrict__ src_lane,
                                                  double *__restrict__ bc, double *__restrict__ hacc,
                                                  uint32_t *__restrict__ arrive, double *__restrict__ delta_dump,
-                                                 int accumulate) {
+                                                 int accumulate, const uint32_t *__restrict__ lvf) {
+    // lvf[0]: level l holds a vertex (cleared for a batch handed back);
+    // lvf[1]: level l+1 does (else fnext is not read)
+    if (lvf[0] == 0) return;
+    if (lvf[1] == 0) fnext = nullptr;
     const int lane = threadIdx.x & 63;
     const int64_t wid = (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6);
     Item it;
@@ -502,7 +550,7 @@ __global__ __launch_bounds__(SB) void k_bwd_pull(Topo t, const uint64_t *__restr
     for (int q = 0; q < NW; ++q) acc[q] = 0.0;
     if (fnext) bwd_scan<NW>(t, it.beg, it.end, F, any_next, fnext, cval, lane, acc);
     if (it.h < 0) {
-        bwd_finalize<NW, S>(v, F, acc, lane, t.B, sigma, cval, src_lane, bc, delta_dump, accumulate);
+        bwd_finalize<NW, S>(v, F, acc, lane, t.B, t.n, sigma, cval, src_lane, bc, delta_dump, accumulate);
         return;
     }
     double *hrow = hacc + (size_t)it.h * t.B + lane;
@@ -518,7 +566,7 @@ __global__ __launch_bounds__(SB) void k_bwd_pull(Topo t, const uint64_t *__restr
                 if (acc[q] != 0.0) __hip_atomic_store(&hrow[q * 64], 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
-        bwd_finalize<NW, S>(v, F, acc, lane, t.B, sigma, cval, src_lane, bc, delta_dump, accumulate);
+        bwd_finalize<NW, S>(v, F, acc, lane, t.B, t.n, sigma, cval, src_lane, bc, delta_dump, accumulate);
     }
 }
 
@@ -532,7 +580,11 @@ __global__ __launch_bounds__(SB) void k_bwd_pull_w(Topo t, const uint64_t *__res
                                                    float *__restrict__ cval, const int32_t *__restrict__ src_lane,
                                                    double *__restrict__ bc, double *__restrict__ hacc,
                                                    uint32_t *__restrict__ arrive, double *__restrict__ delta_dump,
-                                                   int accumulate, double *__restrict__ eb) {
+                                                   int accumulate, double *__restrict__ eb,
+                                                   const uint32_t *__restrict__ lvf) {
+    // lvf as in k_bwd_pull
+    if (lvf[0] == 0) return;
+    if (lvf[1] == 0) fnext = nullptr;
     const int lane = threadIdx.x & 63;
     const int64_t wid = (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6);
     const int q = (int)(wid % NW);
@@ -595,8 +647,8 @@ __global__ __launch_bounds__(SB) void k_bwd_pull_w(Topo t, const uint64_t *__res
     float *cval_q = cval + (size_t)q * 64;
     const int32_t *src_q = src_lane + q * 64;
     if (it.h < 0) {
-        bwd_finalize<1, S>(v, F1, acc, lane, t.B, sig_q, cval_q, src_q, bc,
-                           delta_dump ? delta_dump + (size_t)q * 64 : nullptr, accumulate);
+        bwd_finalize<1, S>(v, F1, acc, lane, t.B, t.n, sig_q, cval_q, src_q, bc,
+                           delta_dump ? delta_dump + (size_t)q * 64 * t.n : nullptr, accumulate);
         return;
     }
     double *hp = hacc + (size_t)it.h * t.B + (size_t)q * 64 + lane;
@@ -607,17 +659,19 @@ __global__ __launch_bounds__(SB) void k_bwd_pull_w(Topo t, const uint64_t *__res
             acc[0] = __hip_atomic_load(hp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (acc[0] != 0.0) __hip_atomic_store(hp, 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        bwd_finalize<1, S>(v, F1, acc, lane, t.B, sig_q, cval_q, src_q, bc,
-                           delta_dump ? delta_dump + (size_t)q * 64 : nullptr, accumulate);
+        bwd_finalize<1, S>(v, F1, acc, lane, t.B, t.n, sig_q, cval_q, src_q, bc,
+                           delta_dump ? delta_dump + (size_t)q * 64 * t.n : nullptr, accumulate);
     }
 }
 
-// Per-source readout for bc_read_sssp: out[b][v] in source-major layout.
+// Per-source readout for bc_read_sssp: out[b][v] in source-major layout.  The
+// dependencies are already there (the backward wrote them); unreached
+// vertices get 0.
 template <typename S>
 __global__ __launch_bounds__(SB) void k_sp_dump(int32_t n, int32_t NW, int32_t B, int32_t count, int32_t nlev,
                                                 const uint64_t *__restrict__ front, const S *__restrict__ sigma,
-                                                const double *__restrict__ dstate, int32_t *__restrict__ dist_out,
-                                                uint64_t *__restrict__ sigma_out, double *__restrict__ delta_out) {
+                                                int32_t *__restrict__ dist_out, uint64_t *__restrict__ sigma_out,
+                                                double *__restrict__ delta_out) {
     const int64_t i = (int64_t)blockIdx.x * SB + threadIdx.x;
     if (i >= (int64_t)n * count) return;
     const int32_t b = (int32_t)(i / n), v = (int32_t)(i - (int64_t)b * n);
@@ -625,10 +679,9 @@ __global__ __launch_bounds__(SB) void k_sp_dump(int32_t n, int32_t NW, int32_t B
     int32_t d = -1;
     for (int32_t l = 0; l < nlev && d < 0; ++l)
         if ((front[((size_t)l * n + v) * NW + q] >> bit) & 1) d = l;
-    const size_t idx = (size_t)v * B + b;
     dist_out[i] = d;
-    sigma_out[i] = d >= 0 ? (uint64_t)sigma[idx] : 0;
-    if (delta_out) delta_out[i] = d >= 0 ? dstate[idx] : 0.0;
+    sigma_out[i] = d >= 0 ? (uint64_t)sigma[(size_t)v * B + b] : 0;
+    if (delta_out && d < 0) delta_out[i] = 0.0;
 }
 
 Topo topo(bc_ctx *ctx) {
@@ -716,11 +769,13 @@ bc_status ensure_levels(bc_ctx *ctx, int32_t need) {
     uint64_t *nf = (uint64_t *)bc_dalloc(ctx, (size_t)cap * lvl_words * sizeof(uint64_t));
     uint32_t *na = (uint32_t *)bc_dalloc(ctx, (size_t)cap * aw * sizeof(uint32_t));
     unsigned long long *nm = (unsigned long long *)bc_dalloc(ctx, (size_t)cap * sizeof(unsigned long long));
+    uint32_t *nl = (uint32_t *)bc_dalloc(ctx, (size_t)cap * sizeof(uint32_t));
     uint32_t *nh = nullptr;
-    if (!nf || !na || !nm || hipHostMalloc((void **)&nh, (size_t)cap * aw * sizeof(uint32_t)) != hipSuccess) {
+    if (!nf || !na || !nm || !nl || hipHostMalloc((void **)&nh, (size_t)cap * aw * sizeof(uint32_t)) != hipSuccess) {
         bc_dfree(ctx, nf);
         bc_dfree(ctx, na);
         bc_dfree(ctx, nm);
+        bc_dfree(ctx, nl);
         return bc_fail(ctx, BC_ERR_NOMEM, "sparse form: frontier allocation failed");
     }
     const int32_t old = s.level_cap;
@@ -730,22 +785,135 @@ bc_status ensure_levels(bc_ctx *ctx, int32_t need) {
         BC_HIP(ctx, hipMemcpyAsync(na, s.any, (size_t)old * aw * sizeof(uint32_t), hipMemcpyDeviceToDevice, ctx->stream));
         BC_HIP(ctx, hipMemcpyAsync(nm, s.lvmax, (size_t)old * sizeof(unsigned long long), hipMemcpyDeviceToDevice,
                                    ctx->stream));
+        BC_HIP(ctx, hipMemcpyAsync(nl, s.lvflag, (size_t)old * sizeof(uint32_t), hipMemcpyDeviceToDevice, ctx->stream));
     }
     BC_HIP(ctx, hipMemsetAsync(na + (size_t)old * aw, 0, (size_t)(cap - old) * aw * sizeof(uint32_t), ctx->stream));
     BC_HIP(ctx, hipMemsetAsync(nm + old, 0, (size_t)(cap - old) * sizeof(unsigned long long), ctx->stream));
+    BC_HIP(ctx, hipMemsetAsync(nl + old, 0, (size_t)(cap - old) * sizeof(uint32_t), ctx->stream));
     BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
     if (s.front) {
         bc_dfree(ctx, s.front);
         bc_dfree(ctx, s.any);
         bc_dfree(ctx, s.lvmax);
+        bc_dfree(ctx, s.lvflag);
         hipHostFree(s.any_host);
     }
     s.front = nf;
     s.any = na;
     s.lvmax = nm;
+    s.lvflag = nl;
     s.any_host = nh;
     s.level_cap = cap;
     return BC_OK;
+}
+
+// ---- the launches of one batch, shared by the host-driven batch and the
+// recorded (replayed) batch ----------------------------------------------------
+
+struct BatchShape {
+    int32_t n, B, aw;
+    size_t words;
+    int pull_blocks, word_blocks;
+    Topo t;
+};
+
+template <int NW>
+BatchShape batch_shape(bc_ctx *ctx) {
+    SparseState &s = ctx->sp;
+    BatchShape b;
+    b.n = ctx->n;
+    b.B = s.batch;
+    b.aw = any_words(ctx);
+    b.words = (size_t)b.n * NW;
+    b.pull_blocks = (int)(((int64_t)b.n + s.nseg + WPB - 1) / WPB);
+    b.word_blocks = (int)((((int64_t)b.n + s.nseg) * NW + WPB - 1) / WPB);
+    b.t = topo(ctx);
+    return b;
+}
+
+// Clears the batch state and seeds the sources: d_src/count, or with ctl the
+// run's batch ctl->batch.
+template <int NW, typename S>
+bc_status launch_batch_init(bc_ctx *ctx, const BatchShape &b, const int32_t *d_src, int32_t count,
+                            const BatchCtl *ctl) {
+    SparseState &s = ctx->sp;
+    LaunchTimer tm(ctx, "batch_init");
+    const int blocks = (int)std::min<size_t>((b.words + SB - 1) / SB, 8192);
+    hipLaunchKernelGGL(k_sp_clear, dim3(std::max(blocks, 1)), dim3(SB), 0, ctx->stream, s.front, s.visited, b.words,
+                       s.any, (size_t)s.level_cap * b.aw, s.lvmax, s.lvflag, s.level_cap);
+    hipLaunchKernelGGL(k_sp_seed<S>, dim3((b.B + SB - 1) / SB), dim3(SB), 0, ctx->stream, d_src, count, b.B, NW,
+                       s.front, s.visited, reinterpret_cast<S *>(s.sigma), s.src, s.any, s.lvflag, ctl);
+    tm.done();
+    BC_HIP(ctx, hipGetLastError());
+    return BC_OK;
+}
+
+// Forward level l -> l+1 of an unweighted batch.  products: this level goes
+// by products; next_products: level l+1 will (so its largest count is
+// recorded).  *l1_pulled tracks whether level 1 -> 2 filled the 16-bit counts.
+template <int NW, typename S>
+bc_status launch_fwd_level(bc_ctx *ctx, const BatchShape &b, int32_t l, bool products, bool next_products,
+                           uint16_t *sig16, bool *l1_pulled) {
+    SparseState &s = ctx->sp;
+    if (l == 0) {
+        LaunchTimer tm(ctx, "fwd_push0");
+        hipLaunchKernelGGL(k_fwd_push0<S>, dim3(b.B), dim3(SB), 0, ctx->stream, b.t, NW, (const int32_t *)s.src,
+                           s.front + b.words, s.visited, reinterpret_cast<S *>(s.sigma), s.any + b.aw, s.lvflag + 1);
+        tm.done();
+        return BC_OK;
+    }
+    if (products) return algebraic_forward_level(ctx, sizeof(S) == 8, l, s.lvflag + l);
+    LaunchTimer tm(ctx, "fwd_pull");
+    // level 1 holds the sources' neighbours, each with one shortest path (the
+    // input graph is simple): its pull counts frontier bits, and level 2's
+    // counts (at most a degree) also go to sig16, from which level 2 -> 3
+    // gathers them
+    const auto kern = l == 1                 ? k_fwd_pull<NW, S, FWD_UNIT>
+                      : l == 2 && *l1_pulled ? k_fwd_pull<NW, S, FWD_HALF>
+                                             : k_fwd_pull<NW, S, FWD_GENERAL>;
+    if (l == 1) *l1_pulled = sig16 != nullptr;
+    hipLaunchKernelGGL(kern, dim3(b.pull_blocks), dim3(SB), 0, ctx->stream, b.t, s.any + (size_t)l * b.aw,
+                       s.front + (size_t)l * b.words, s.front + (size_t)(l + 1) * b.words, s.visited,
+                       reinterpret_cast<S *>(s.sigma), sig16, (unsigned long long *)s.hacc, s.arrive,
+                       s.any + (size_t)(l + 1) * b.aw, ctx->status, next_products ? s.lvmax + l + 1 : nullptr,
+                       s.lvflag + l);
+    tm.done();
+    return BC_OK;
+}
+
+// Backward level lv of an unweighted batch.  Level lv+1 is read only when its
+// flag says it holds a vertex (front[lv+1] must exist: lv+1 < level_cap).
+template <int NW, typename S>
+bc_status launch_bwd_level(bc_ctx *ctx, const BatchShape &b, int32_t lv, bool products, double *ddump,
+                           bool accumulate) {
+    SparseState &s = ctx->sp;
+    const uint64_t *fcur = s.front + (size_t)lv * b.words;
+    const uint64_t *fnext = s.front + (size_t)(lv + 1) * b.words;
+    const uint32_t *anext = s.any + (size_t)(lv + 1) * b.aw;
+    if (products) return algebraic_backward_level(ctx, sizeof(S) == 8, fcur, fnext, 1, ddump, accumulate, s.lvflag + lv);
+    LaunchTimer tm(ctx, "bwd_pull");
+    const S *sigma = reinterpret_cast<const S *>(s.sigma);
+    if (s.bwd_per_word || ctx->edges) { // edge terms come from the per-word pull
+        double *eb = accumulate && ctx->edges ? ctx->eb : nullptr;
+        const auto kern = eb ? k_bwd_pull_w<NW, S, true> : k_bwd_pull_w<NW, S, false>;
+        hipLaunchKernelGGL(kern, dim3(b.word_blocks), dim3(SB), 0, ctx->stream, b.t, fcur, anext, fnext, sigma, s.cval,
+                           s.src, ctx->bc, s.hacc, s.arrive_w, ddump, accumulate ? 1 : 0, eb,
+                           (const uint32_t *)s.lvflag + lv);
+    } else
+        hipLaunchKernelGGL((k_bwd_pull<NW, S>), dim3(b.pull_blocks), dim3(SB), 0, ctx->stream, b.t, fcur, anext, fnext,
+                           sigma, s.cval, s.src, ctx->bc, s.hacc, s.arrive, ddump, accumulate ? 1 : 0,
+                           (const uint32_t *)s.lvflag + lv);
+    tm.done();
+    return BC_OK;
+}
+
+// 16-bit copy of level 2's counts, in the unused upper half of the count
+// array (uint32 counts fill the first half of its uint64 capacity).
+template <typename S>
+uint16_t *sig16_of(bc_ctx *ctx) {
+    return sizeof(S) == 4 && ctx->max_degree < 65536
+               ? reinterpret_cast<uint16_t *>(reinterpret_cast<uint32_t *>(ctx->sp.sigma) + (size_t)ctx->n * ctx->sp.batch)
+               : nullptr;
 }
 
 // One batch of up to B sources with counts stored as S; *nlev_out receives
@@ -755,42 +923,29 @@ bc_status ensure_levels(bc_ctx *ctx, int32_t need) {
 // synchronisation and finds the first empty level (with weights 1..M, the
 // first of M consecutive empty levels: levels are then distances).  With S = uint32_t,
 // *need_wide reports a count of 2^32 or more, before anything was added to BC.
+// With accumulate = false, delta_dump (count rows of n, source-major) receives
+// the dependencies instead of BC.
 template <int NW, typename S>
 bc_status run_batch_t(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool accumulate, int32_t *nlev_out,
-                      bool *need_wide, bool backward) {
+                      bool *need_wide, bool backward, double *delta_dump) {
     SparseState &s = ctx->sp;
-    const int32_t n = ctx->n, B = s.batch;
-    const size_t words = (size_t)n * NW;
-    const int32_t aw = any_words(ctx);
-    const int pull_blocks = (int)(((int64_t)n + s.nseg + WPB - 1) / WPB);
-    const int word_blocks = (int)((((int64_t)n + s.nseg) * NW + WPB - 1) / WPB);
     const int32_t guess = std::max(s.depth_guess, 2);
-    S *sigma = reinterpret_cast<S *>(s.sigma);
     *need_wide = false;
     bc_status st = ensure_levels(ctx, guess + 1);
     if (st != BC_OK) return st;
-    const Topo t = topo(ctx);
-    {
-        LaunchTimer tm(ctx, "batch_init");
-        const int blocks = (int)std::min<size_t>((words + SB - 1) / SB, 8192);
-        hipLaunchKernelGGL(k_sp_clear, dim3(std::max(blocks, 1)), dim3(SB), 0, ctx->stream, s.front, s.visited, words,
-                           s.any, (size_t)s.level_cap * aw, s.lvmax, s.level_cap);
-        hipLaunchKernelGGL(k_sp_seed<S>, dim3((B + SB - 1) / SB), dim3(SB), 0, ctx->stream, d_src, count, B, NW,
-                           s.front, s.visited, sigma, s.src, s.any);
-        tm.done();
-        BC_HIP(ctx, hipGetLastError());
-    }
+    const BatchShape b = batch_shape<NW>(ctx);
+    const size_t words = b.words;
+    const int32_t aw = b.aw;
+    st = launch_batch_init<NW, S>(ctx, b, d_src, count, nullptr);
+    if (st != BC_OK) return st;
     int32_t launched = 0, nlev = -1;
     const bool wide_now = sizeof(S) == 8;
-    // 16-bit copy of level 2's counts, in the unused upper half of the count
-    // array (uint32 counts fill the first half of its uint64 capacity)
-    uint16_t *sig16 = !wide_now && ctx->max_degree < 65536
-                          ? reinterpret_cast<uint16_t *>(reinterpret_cast<uint32_t *>(s.sigma) + (size_t)n * B)
-                          : nullptr;
+    uint16_t *sig16 = sig16_of<S>(ctx);
     bool l1_pulled = false; // level 1 -> 2 ran as the pull that fills sig16
     // Weighted graphs (the algebraic form, Sec. 3.2): levels are distances and
     // level l+1 is formed from levels l+1-M .. l; the search ends at M
-    // consecutive empty levels.
+    // consecutive empty levels.  An empty level there does not end the
+    // search, so those products run without level flags.
     const bool weighted = ctx->weighted;
     const int32_t M = weighted ? ctx->al.classes : 1;
 
@@ -799,41 +954,22 @@ bc_status run_batch_t(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool acc
         const int32_t target = launched == 0 ? std::max(guess + M - 1, M + 1) : launched + std::max(2, M);
         st = ensure_levels(ctx, target + 1);
         if (st != BC_OK) return st;
+        const BatchShape bb = batch_shape<NW>(ctx); // same shape; front may have moved
         for (int32_t l = launched; l < target; ++l) {
             if (weighted) {
                 st = algebraic_forward_level(ctx, wide_now, l);
                 if (st != BC_OK) return st;
                 continue;
             }
-            if (l == 0) {
-                LaunchTimer tm(ctx, "fwd_push0");
-                hipLaunchKernelGGL(k_fwd_push0<S>, dim3(B), dim3(SB), 0, ctx->stream, t, NW, (const int32_t *)s.src,
-                                   s.front + words, s.visited, sigma, s.any + aw);
-                tm.done();
+            if (l == 0) { // pushed, not a level the hybrid choice covers
+                st = launch_fwd_level<NW, S>(ctx, bb, 0, false, by_products(ctx, 1, true), sig16, &l1_pulled);
+                if (st != BC_OK) return st;
                 continue;
             }
             ProbeScope ps(ctx);
-            if (by_products(ctx, l, true)) {
-                st = algebraic_forward_level(ctx, wide_now, l);
-                if (st != BC_OK) return st;
-                ps.done(true, l);
-                continue;
-            }
-            LaunchTimer tm(ctx, "fwd_pull");
-            // level 1 holds the sources' neighbours, each with one shortest
-            // path (the input graph is simple): its pull counts frontier bits,
-            // and level 2's counts (at most a degree) also go to sig16, from
-            // which level 2 -> 3 gathers them
-            const auto kern = l == 1                  ? k_fwd_pull<NW, S, FWD_UNIT>
-                              : l == 2 && l1_pulled ? k_fwd_pull<NW, S, FWD_HALF>
-                                                      : k_fwd_pull<NW, S, FWD_GENERAL>;
-            if (l == 1) l1_pulled = sig16 != nullptr;
-            hipLaunchKernelGGL(kern, dim3(pull_blocks), dim3(SB), 0, ctx->stream, t,
-                               s.any + (size_t)l * aw, s.front + (size_t)l * words, s.front + (size_t)(l + 1) * words,
-                               s.visited, sigma, sig16, (unsigned long long *)s.hacc, s.arrive,
-                               s.any + (size_t)(l + 1) * aw, ctx->status,
-                               by_products(ctx, l + 1, true) ? s.lvmax + l + 1 : nullptr);
-            tm.done();
+            st = launch_fwd_level<NW, S>(ctx, bb, l, by_products(ctx, l, true), by_products(ctx, l + 1, true), sig16,
+                                         &l1_pulled);
+            if (st != BC_OK) return st;
             ps.done(true, l);
         }
         BC_HIP(ctx, hipGetLastError());
@@ -861,42 +997,27 @@ bc_status run_batch_t(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool acc
         launched = target;
     }
     s.depth_guess = nlev;
+    s.depth_max = std::max(s.depth_max, nlev);
     // Level 0 adds nothing to BC (v is the source), but with edges on its
     // arcs out of the source carry edge terms.
     // A forward-only batch (all-pairs distances and counts) runs no level.
     const int32_t lowest = !backward ? nlev : accumulate && !ctx->edges ? 1 : 0;
-    double *ddump = accumulate ? nullptr : s.delta_dump;
+    double *ddump = accumulate ? nullptr : delta_dump;
+    const BatchShape bb = batch_shape<NW>(ctx);
     for (int32_t lv = nlev - 1; lv >= lowest; --lv) {
-        const uint64_t *fcur = s.front + (size_t)lv * words;
-        const bool deeper = lv + 1 < nlev;
-        const uint64_t *fnext = deeper ? s.front + (size_t)(lv + 1) * words : nullptr;
-        const uint32_t *anext = deeper ? s.any + (size_t)(lv + 1) * aw : nullptr;
         if (weighted) {
             // successors at levels lv+1 .. lv+M that exist; at the deepest
             // level none, and the product only sets c = 1 / lambda
+            const uint64_t *fcur = s.front + (size_t)lv * words;
+            const uint64_t *fnext = lv + 1 < nlev ? s.front + (size_t)(lv + 1) * words : nullptr;
             st = algebraic_backward_level(ctx, sizeof(S) == 8, fcur, fnext, std::min(M, nlev - 1 - lv), ddump,
                                           accumulate);
             if (st != BC_OK) return st;
             continue;
         }
         ProbeScope ps(ctx);
-        if (deeper && by_products(ctx, lv, false)) {
-            st = algebraic_backward_level(ctx, sizeof(S) == 8, fcur, fnext, 1, ddump, accumulate);
-            if (st != BC_OK) return st;
-            ps.done(false, lv);
-            continue;
-        }
-        LaunchTimer tm(ctx, "bwd_pull");
-        if (s.bwd_per_word || ctx->edges) { // edge terms come from the per-word pull
-            double *eb = accumulate && ctx->edges ? ctx->eb : nullptr;
-            const auto kern = eb ? k_bwd_pull_w<NW, S, true> : k_bwd_pull_w<NW, S, false>;
-            hipLaunchKernelGGL(kern, dim3(word_blocks), dim3(SB), 0, ctx->stream, t, fcur, anext, fnext,
-                               (const S *)sigma, s.cval, s.src, ctx->bc, s.hacc, s.arrive_w, ddump,
-                               accumulate ? 1 : 0, eb);
-        } else
-            hipLaunchKernelGGL((k_bwd_pull<NW, S>), dim3(pull_blocks), dim3(SB), 0, ctx->stream, t, fcur, anext, fnext,
-                               (const S *)sigma, s.cval, s.src, ctx->bc, s.hacc, s.arrive, ddump, accumulate ? 1 : 0);
-        tm.done();
+        st = launch_bwd_level<NW, S>(ctx, bb, lv, lv + 1 < nlev && by_products(ctx, lv, false), ddump, accumulate);
+        if (st != BC_OK) return st;
         ps.done(false, lv);
     }
     BC_HIP(ctx, hipGetLastError());
@@ -928,29 +1049,184 @@ bc_status run_batch_t(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool acc
 
 template <int NW>
 bc_status run_batch_nw(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool accumulate, int32_t *nlev_out,
-                       bool backward) {
+                       bool backward, double *delta_dump) {
     SparseState &s = ctx->sp;
     if (!s.wide) {
         bool need_wide = false;
-        bc_status st = run_batch_t<NW, uint32_t>(ctx, d_src, count, accumulate, nlev_out, &need_wide, backward);
+        bc_status st =
+            run_batch_t<NW, uint32_t>(ctx, d_src, count, accumulate, nlev_out, &need_wide, backward, delta_dump);
         if (st != BC_OK || !need_wide) return st;
         s.wide = true;
     }
     bool unused = false;
-    return run_batch_t<NW, uint64_t>(ctx, d_src, count, accumulate, nlev_out, &unused, backward);
+    return run_batch_t<NW, uint64_t>(ctx, d_src, count, accumulate, nlev_out, &unused, backward, delta_dump);
 }
 
 // Counts start as uint32; the first batch that needs more switches the context
 // to uint64 storage for good and is re-run.
 bc_status run_batch(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool accumulate, int32_t *nlev_out,
-                    bool backward = true) {
+                    bool backward = true, double *delta_dump = nullptr) {
     switch (ctx->sp.words) {
-    case 1: return run_batch_nw<1>(ctx, d_src, count, accumulate, nlev_out, backward);
-    case 2: return run_batch_nw<2>(ctx, d_src, count, accumulate, nlev_out, backward);
-    case 4: return run_batch_nw<4>(ctx, d_src, count, accumulate, nlev_out, backward);
-    case 8: return run_batch_nw<8>(ctx, d_src, count, accumulate, nlev_out, backward);
+    case 1: return run_batch_nw<1>(ctx, d_src, count, accumulate, nlev_out, backward, delta_dump);
+    case 2: return run_batch_nw<2>(ctx, d_src, count, accumulate, nlev_out, backward, delta_dump);
+    case 4: return run_batch_nw<4>(ctx, d_src, count, accumulate, nlev_out, backward, delta_dump);
+    case 8: return run_batch_nw<8>(ctx, d_src, count, accumulate, nlev_out, backward, delta_dump);
     }
     return bc_fail(ctx, BC_ERR_INVALID_ARG, "sparse form: batch must be 64, 128, 256 or 512");
+}
+
+// ---- replayed batches -----------------------------------------------------------
+//
+// A run of many batches on an unweighted graph is not driven level by level
+// from the host.  One batch's launch sequence -- clear, seed, forward levels
+// 0 .. L-1, a check, backward levels L-1 .. lowest -- is recorded once into a
+// HIP graph and replayed for every batch of the run; a device control block
+// tells each replay which sources it takes.  The level-synchronous order of
+// the search (Sec. 4) is kept: each level is one launch, and a level past
+// the batch's depth finds its flag clear and exits at once.  The check at
+// the end of the forward hands a batch back when its search had not ended
+// within the L levels (level L holds a vertex) or a count needs 64-bit
+// storage: it puts the batch on a list and clears every level flag, so the
+// batch's backward launches exit and add nothing.  The host reads the list
+// when the context is next used and re-runs those batches host-driven.  L is
+// the deepest batch seen so far plus one.  The hybrid form's per-level
+// choice is the one the last host-driven batch's densities give.
+
+// End of a replayed batch's forward (one thread).
+__global__ void k_batch_check(BatchCtl *ctl, uint32_t *lvflag, int32_t L, uint32_t *status, int32_t B) {
+    if (threadIdx.x != 0) return;
+    const bool deep = lvflag[L] != 0, wide = status[1] != 0;
+    if (deep || wide) {
+        ctl->redo[ctl->redo_count++] = ctl->batch * B;
+        if (wide) ctl->need_wide = 1u;
+        if (deep) ctl->deep = 1u;
+        for (int32_t l = 0; l <= L; ++l) lvflag[l] = 0u;
+        status[1] = 0u;
+    } else {
+        uint32_t nlev = (uint32_t)L;
+        for (int32_t l = 1; l <= L; ++l)
+            if (lvflag[l] == 0u) {
+                nlev = (uint32_t)l;
+                break;
+            }
+        if (nlev > ctl->max_nlev) ctl->max_nlev = nlev;
+    }
+    ctl->batch += 1;
+}
+
+// Which levels of a replayed batch go by products: bit 0 forward l -> l+1,
+// bit 1 backward l; as by_products, the backward also deciding from the last
+// host-driven batch's densities.
+std::vector<uint8_t> replay_plan(const bc_ctx *ctx, int32_t L) {
+    std::vector<uint8_t> plan((size_t)L + 1, 0);
+    const std::vector<double> &pd = ctx->hy.prev_density;
+    for (int32_t l = 1; l <= L; ++l) {
+        const bool f = by_products(ctx, l, true);
+        const bool b = ctx->al.every_level ||
+                       (ctx->hy.products && !ctx->edges && (size_t)l < pd.size() && pd[(size_t)l] >= ctx->hy.theta_bwd);
+        plan[(size_t)l] = (uint8_t)((f ? 1 : 0) | (b ? 2 : 0));
+    }
+    return plan;
+}
+
+template <int NW, typename S>
+bc_status record_batch_t(bc_ctx *ctx, int32_t L, const std::vector<uint8_t> &plan) {
+    SparseState &s = ctx->sp;
+    const BatchShape b = batch_shape<NW>(ctx);
+    bc_status st = launch_batch_init<NW, S>(ctx, b, nullptr, 0, s.ctl);
+    uint16_t *sig16 = sig16_of<S>(ctx);
+    bool l1_pulled = false;
+    for (int32_t l = 0; l < L && st == BC_OK; ++l)
+        st = launch_fwd_level<NW, S>(ctx, b, l, l > 0 && (plan[(size_t)l] & 1), (plan[(size_t)l + 1] & 1) != 0, sig16,
+                                     &l1_pulled);
+    if (st != BC_OK) return st;
+    {
+        LaunchTimer tm(ctx, "batch_check");
+        hipLaunchKernelGGL(k_batch_check, dim3(1), dim3(64), 0, ctx->stream, s.ctl, s.lvflag, L, ctx->status,
+                           s.batch);
+        tm.done();
+    }
+    // level 0 adds nothing to BC, but with edges on its arcs carry edge terms
+    const int32_t lowest = ctx->edges ? 0 : 1;
+    for (int32_t lv = L - 1; lv >= lowest && st == BC_OK; --lv)
+        st = launch_bwd_level<NW, S>(ctx, b, lv, lv >= 1 && (plan[(size_t)lv] & 2), nullptr, true);
+    if (st != BC_OK) return st;
+    BC_HIP(ctx, hipGetLastError());
+    return BC_OK;
+}
+
+template <int NW>
+bc_status record_batch_nw(bc_ctx *ctx, int32_t L, const std::vector<uint8_t> &plan) {
+    return ctx->sp.wide ? record_batch_t<NW, uint64_t>(ctx, L, plan) : record_batch_t<NW, uint32_t>(ctx, L, plan);
+}
+
+bc_status record_batch(bc_ctx *ctx, int32_t L, const std::vector<uint8_t> &plan) {
+    switch (ctx->sp.words) {
+    case 1: return record_batch_nw<1>(ctx, L, plan);
+    case 2: return record_batch_nw<2>(ctx, L, plan);
+    case 4: return record_batch_nw<4>(ctx, L, plan);
+    case 8: return record_batch_nw<8>(ctx, L, plan);
+    }
+    return bc_fail(ctx, BC_ERR_INVALID_ARG, "sparse form: batch must be 64, 128, 256 or 512");
+}
+
+void destroy_graphs(bc_ctx *ctx) {
+    SparseState &s = ctx->sp;
+    if (s.gexec) hipGraphExecDestroy(s.gexec);
+    s.gexec = nullptr;
+}
+
+// Records one batch on the private capture stream (nothing runs) and
+// instantiates it.
+bc_status capture_batch(bc_ctx *ctx, int32_t L, const std::vector<uint8_t> &plan) {
+    SparseState &s = ctx->sp;
+    destroy_graphs(ctx);
+    if (!s.cap_stream) BC_HIP(ctx, hipStreamCreateWithFlags(&s.cap_stream, hipStreamNonBlocking));
+    hipStream_t saved = ctx->stream;
+    hipGraph_t graph = nullptr;
+    bc_status st = BC_OK;
+    hipError_t e = hipStreamBeginCapture(s.cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        ctx->stream = s.cap_stream;
+        ctx->recording = true;
+        st = record_batch(ctx, L, plan);
+        ctx->stream = saved;
+        ctx->recording = false;
+        const hipError_t e2 = hipStreamEndCapture(s.cap_stream, &graph);
+        if (e2 != hipSuccess) e = e2;
+    }
+    if (st == BC_OK && e == hipSuccess) e = hipGraphInstantiate(&s.gexec, graph, nullptr, nullptr, 0);
+    if (graph) hipGraphDestroy(graph);
+    if (st != BC_OK || e != hipSuccess) {
+        s.gexec = nullptr;
+        return st != BC_OK ? st : bc_hip(ctx, e, "recording a batch into a HIP graph");
+    }
+    return BC_OK;
+}
+
+// The recorded batch for the current depth, count width, state and level plan.
+bc_status ensure_replay(bc_ctx *ctx) {
+    SparseState &s = ctx->sp;
+    const int32_t L = std::max(s.depth_max + 1, 2);
+    bc_status st = ensure_levels(ctx, L + 1);
+    if (st != BC_OK) return st;
+    const std::vector<uint8_t> plan = replay_plan(ctx, L);
+    if (s.gexec && s.g_levels == L && s.g_wide == s.wide && s.g_front == (const void *)s.front && s.g_plan == plan)
+        return BC_OK;
+    BC_HIP(ctx, hipStreamSynchronize(ctx->stream)); // no replay of the old graph is in flight
+    st = capture_batch(ctx, L, plan);
+    if (st != BC_OK) return st;
+    s.g_levels = L;
+    s.g_wide = s.wide;
+    s.g_front = s.front;
+    s.g_plan = plan;
+    return BC_OK;
+}
+
+// A batch of a replayed run that ran host-driven instead: its replay's slot
+// in the control block is passed over.
+__global__ void k_ctl_skip(BatchCtl *ctl) {
+    if (threadIdx.x == 0) ctl->batch += 1;
 }
 
 } // namespace
@@ -994,8 +1270,9 @@ bc_status sparse_prepare(bc_ctx *ctx, int32_t batch, int32_t split_degree) {
     s.sigma = (uint64_t *)bc_dalloc(ctx, nn * batch * sizeof(uint64_t));
     s.cval = (float *)bc_dalloc(ctx, nn * batch * sizeof(float));
     s.src = (int32_t *)bc_dalloc(ctx, batch * sizeof(int32_t));
+    s.ctl = (BatchCtl *)bc_dalloc(ctx, sizeof(BatchCtl));
     if (!s.heavy_id || !s.heavy_nseg || !s.arrive || !s.arrive_w || !s.seg_v || !s.seg_beg || !s.seg_end || !s.hacc || !s.visited ||
-        !s.sigma || !s.cval || !s.src)
+        !s.sigma || !s.cval || !s.src || !s.ctl)
         return bc_fail(ctx, BC_ERR_NOMEM, "sparse form: state allocation failed");
     if (n > 0)
         BC_HIP(ctx, hipMemcpyAsync(s.heavy_id, heavy_id.data(), nn * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
@@ -1021,9 +1298,11 @@ bc_status sparse_batch(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool ac
 bc_status sparse_release(bc_ctx *ctx) {
     SparseState &s = ctx->sp;
     BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    for (void *p : {(void *)s.front, (void *)s.any, (void *)s.lvmax, (void *)s.visited, (void *)s.sigma, (void *)s.cval,
-                    (void *)s.delta_dump, (void *)s.src, (void *)s.heavy_id, (void *)s.heavy_nseg, (void *)s.arrive,
-                    (void *)s.arrive_w, (void *)s.seg_v, (void *)s.seg_beg, (void *)s.seg_end, (void *)s.hacc})
+    sparse_graphs_release(ctx);
+    for (void *p : {(void *)s.front, (void *)s.any, (void *)s.lvmax, (void *)s.lvflag, (void *)s.visited,
+                    (void *)s.sigma, (void *)s.cval, (void *)s.src, (void *)s.heavy_id,
+                    (void *)s.heavy_nseg, (void *)s.arrive, (void *)s.arrive_w, (void *)s.seg_v, (void *)s.seg_beg,
+                    (void *)s.seg_end, (void *)s.hacc, (void *)s.ctl, (void *)s.redo})
         if (p) bc_dfree(ctx, p);
     if (s.any_host) hipHostFree(s.any_host);
     s = SparseState{};
@@ -1031,34 +1310,98 @@ bc_status sparse_release(bc_ctx *ctx) {
 }
 
 bc_status sparse_run(bc_ctx *ctx, const int32_t *d_src, int64_t count) {
-    const int32_t B = ctx->sp.batch;
-    for (int64_t b0 = 0; b0 < count; b0 += B) {
+    SparseState &s = ctx->sp;
+    const int32_t B = s.batch;
+    const bool replay = !ctx->weighted && !ctx->host_driven && count < (int64_t(1) << 31) - B;
+    int64_t b0 = 0;
+    // Host-driven batches: every batch without replay; with replay the first
+    // batch a state runs, which gives the depth and the level densities.
+    for (; b0 < count && (!replay || s.depth_max == 0); b0 += B) {
         int32_t nlev = 0;
         bc_timing_batch(ctx); // with sampled timing, this batch's launches are timed or not as a whole
+        bc_timing_eager(ctx);
         bc_status st = run_batch(ctx, d_src + b0, (int32_t)std::min<int64_t>(B, count - b0), true, &nlev);
+        if (st != BC_OK) return st;
+    }
+    if (b0 >= count) return BC_OK;
+    bc_status st = ensure_replay(ctx);
+    if (st != BC_OK) return st;
+    const int64_t rest = count - b0, nb = (rest + B - 1) / B;
+    if (nb > s.redo_cap) {
+        int32_t *r = (int32_t *)bc_dalloc(ctx, (size_t)nb * sizeof(int32_t));
+        if (!r) return bc_fail(ctx, BC_ERR_NOMEM, "sparse form: allocation of the handed-back list failed");
+        bc_dfree(ctx, s.redo);
+        s.redo = r;
+        s.redo_cap = nb;
+    }
+    hipLaunchKernelGGL(k_run_init, dim3(1), dim3(64), 0, ctx->stream, s.ctl, d_src + b0, (int32_t)rest, s.redo);
+    BC_HIP(ctx, hipGetLastError());
+    s.g_pending = true; // from here on the device holds checks the host must read
+    for (int64_t i = 0; i < nb; ++i) {
+        bc_timing_batch(ctx);
+        if (ctx->timing && ctx->timing_sel) {
+            // a timed batch runs host-driven, so that its launches carry events
+            bc_timing_eager(ctx);
+            const int64_t off = b0 + i * B;
+            int32_t nlev = 0;
+            st = run_batch(ctx, d_src + off, (int32_t)std::min<int64_t>(B, count - off), true, &nlev);
+            if (st != BC_OK) return st;
+            hipLaunchKernelGGL(k_ctl_skip, dim3(1), dim3(64), 0, ctx->stream, s.ctl);
+            BC_HIP(ctx, hipGetLastError());
+            // it may have grown the level storage or switched to 64-bit counts
+            if ((st = ensure_replay(ctx)) != BC_OK) return st;
+            continue;
+        }
+        BC_HIP(ctx, hipGraphLaunch(s.gexec, ctx->stream));
+    }
+    return BC_OK;
+}
+
+bc_status sparse_settle(bc_ctx *ctx) {
+    SparseState &s = ctx->sp;
+    if (!s.g_pending) return BC_OK;
+    s.g_pending = false;
+    BatchCtl c{};
+    BC_HIP(ctx, hipMemcpyAsync(&c, s.ctl, sizeof c, hipMemcpyDeviceToHost, ctx->stream));
+    BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    s.depth_max = std::max(s.depth_max, (int32_t)c.max_nlev);
+    s.depth_guess = std::max(s.depth_guess, (int32_t)c.max_nlev);
+    ctx->max_levels = std::max(ctx->max_levels, (int32_t)c.max_nlev);
+    if (c.redo_count == 0) return BC_OK;
+    std::vector<int32_t> redo(c.redo_count);
+    BC_HIP(ctx, hipMemcpy(redo.data(), s.redo, redo.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (c.need_wide) s.wide = true; // sticky, as on the host-driven path
+    for (const int32_t b0 : redo) {
+        int32_t nlev = 0;
+        bc_status st = run_batch(ctx, c.src + b0, std::min(s.batch, c.total - b0), true, &nlev);
         if (st != BC_OK) return st;
     }
     return BC_OK;
 }
 
+void sparse_graphs_release(bc_ctx *ctx) {
+    SparseState &s = ctx->sp;
+    hipStreamSynchronize(ctx->stream); // no replay is in flight
+    destroy_graphs(ctx);
+    if (s.cap_stream) hipStreamDestroy(s.cap_stream);
+    s.cap_stream = nullptr;
+    s.g_pending = false;
+}
+
 bc_status sparse_dump(bc_ctx *ctx, const int32_t *d_src, int32_t count,
                       int32_t *dist_dump, uint64_t *sigma_dump, double *delta_dump) {
     SparseState &s = ctx->sp;
-    if (delta_dump && !s.delta_dump) {
-        s.delta_dump = (double *)bc_dalloc(ctx, (size_t)std::max(ctx->n, 1) * s.batch * sizeof(double));
-        if (!s.delta_dump) return bc_fail(ctx, BC_ERR_NOMEM, "sparse form: dump allocation failed");
-    }
     int32_t nlev = 0;
-    bc_status st = run_batch(ctx, d_src, count, false, &nlev, delta_dump != nullptr);
+    bc_status st = run_batch(ctx, d_src, count, false, &nlev, delta_dump != nullptr, delta_dump);
     if (st != BC_OK) return st;
     const int64_t cells = (int64_t)ctx->n * count;
     const unsigned blocks = (unsigned)((cells + SB - 1) / SB);
     if (s.wide)
         hipLaunchKernelGGL(k_sp_dump<uint64_t>, dim3(blocks), dim3(SB), 0, ctx->stream, ctx->n, s.words, s.batch, count,
-                           nlev, s.front, (const uint64_t *)s.sigma, s.delta_dump, dist_dump, sigma_dump, delta_dump);
+                           nlev, s.front, (const uint64_t *)s.sigma, dist_dump, sigma_dump, delta_dump);
     else
         hipLaunchKernelGGL(k_sp_dump<uint32_t>, dim3(blocks), dim3(SB), 0, ctx->stream, ctx->n, s.words, s.batch, count,
-                           nlev, s.front, (const uint32_t *)s.sigma, s.delta_dump, dist_dump, sigma_dump, delta_dump);
+                           nlev, s.front, (const uint32_t *)s.sigma, dist_dump, sigma_dump, delta_dump);
     BC_HIP(ctx, hipGetLastError());
     return BC_OK;
 }

@@ -116,7 +116,7 @@ size_t state_bytes(int32_t n, int32_t batch) {
 }
 
 bool products_possible(const bc_ctx *ctx) {
-    if (ctx->weighted || ctx->max_degree > 65792) return false;
+    if (ctx->weighted || ctx->max_degree > BC_ALGEBRAIC_MAX_DEGREE) return false;
     const size_t npad = (size_t)std::max(256, (ctx->n + 255) / 256 * 256);
     return npad * npad * 2 <= kHybridAdjBudget;
 }
@@ -339,8 +339,10 @@ bc_status tune_prepare(bc_ctx *ctx, const bc_options &opt, bc_form form) {
         if (st == BC_OK) st = prepare_width(ctx, best_w, split, products);
     }
     if (st != BC_OK) return st;
-    // Calibration added to BC and may have flagged an overflow: start clean.
+    // Calibration added to BC (and, with edges on, to the per-arc terms) and
+    // may have flagged an overflow: start clean.
     BC_HIP(ctx, hipMemsetAsync(ctx->bc, 0, sizeof(double) * (size_t)std::max(ctx->n, 1), ctx->stream));
+    if (ctx->eb) BC_HIP(ctx, hipMemsetAsync(ctx->eb, 0, sizeof(double) * (size_t)std::max(ctx->nnz, 1), ctx->stream));
     BC_HIP(ctx, hipMemsetAsync(ctx->status, 0, 256, ctx->stream));
     BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
     clear_after_calibration(ctx);

@@ -145,7 +145,7 @@ def test_all_pairs_limits(gpu_lib):
         assert e.value.status == gpu_lib.BC_ERR_UNSUPPORTED
 
 
-def test_er16384_all_pairs_full_size(gpu_lib):
+def test_er16384_all_pairs_full_size(gpu_lib, oracle_all_sources):
     """The all-pairs workload at its full size (ER, n = 16384, mean degree
     256), with the algebraic form filling D and Lambda as the benchmark does,
     against the oracle's all-source BC."""
@@ -153,6 +153,5 @@ def test_er16384_all_pairs_full_size(gpu_lib):
     say("er16384_all_pairs", g.n, g.m)
     with gpu_lib.BC(g, form="algebraic", batch=512) as ctx:
         got = ctx.all_pairs()
-    say("oracle all sources")
-    want = oracle.bc(g, threads=16)
+    want = oracle_all_sources("er16384", g)
     assert rel_err(got, want) <= TOL

@@ -110,3 +110,21 @@ def test_read_edges_needs_edges(gpu_lib):
         with pytest.raises(gpu_lib.BCError) as e:
             ctx.read_edges()
         assert e.value.status == gpu_lib.BC_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("form", ["sparse", "hybrid"])
+def test_edges_after_tuning(gpu_lib, form):
+    """A context that tunes its batch width (batch 0, n >= 2048, no cache
+    entry) runs calibration batches before any caller work; their per-arc
+    terms must not stay in the edge sums, as their dependencies do not stay
+    in BC."""
+    g = gg.er_plus_tree(3000, 6.0, 2101)
+    say("edges after tuning", form, g.n, g.m)
+    want_bc, want_eb = oracle.edge_bc(g, threads=16)
+    with gpu_lib.BC(g, form=form, batch=0, edges=True) as ctx:
+        assert ctx.info().tune_source == 1, "the context should have measured its batch width"
+        assert not np.any(ctx.read_edges()), "edge sums after create must be zero"
+        ctx.run()
+        got_bc, got_eb = ctx.read(), ctx.read_edges()
+    assert rel_err(got_bc, want_bc) <= TOL[form]
+    assert rel_err(got_eb, want_eb) <= TOL[form]
