@@ -531,6 +531,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sources", type=int, default=0, help="run only the first N sources (profiling)")
     ap.add_argument("--calibrate-copy", action="store_true", help="end with a 1 GiB device copy")
+    ap.add_argument("--timing", type=int, default=TIMING_SAMPLE,
+                    help="HIP events on the launches of one batch in K during the timed steps (0: none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "one GPU only: --gpus must be 1 (sources shard across GPUs by design, "
@@ -591,7 +593,7 @@ def main():
         log(f"{label} {steps} steps: {dt * 1e3:.1f} ms/step, {work / dt:.3e} TEPS")
         return ctx, dt, bc
 
-    ctx, dt, bc_main = timed_runs(form, args.steps, args.warmup, batch, edges=args.edges)
+    ctx, dt, bc_main = timed_runs(form, args.steps, args.warmup, batch, edges=args.edges, timing=args.timing)
     main_step_ms = dict(step_ms[form])
     info = ctx.info()
     kern = {}
@@ -600,7 +602,7 @@ def main():
         if launches:
             kern[k] = (ms, launches)
     log("kernel times (ms, launches):", kern)
-    roof = roofline(args.workload, wl, kern, info, args.steps)
+    roof = roofline(args.workload, wl, kern, info, args.steps) if kern else None
     ctx.close()
 
     free = None
@@ -614,7 +616,8 @@ def main():
     compare = {}
     if not args.no_compare and form in ("hybrid", "sparse", "algebraic") and args.workload != "er16384w4":
         # the same form with every batch driven level by level from the host
-        hctx, hdt, bc_h = timed_runs(form, args.compare_steps, 1, batch, host_driven=True, label="host-driven")
+        hctx, hdt, bc_h = timed_runs(form, args.compare_steps, 1, batch, timing=args.timing, host_driven=True,
+                                     label="host-driven")
         hctx.close()
         err = float(np.max(np.abs(bc_main / args.steps - bc_h / args.compare_steps) /
                            np.maximum(np.abs(bc_h / args.compare_steps), 1.0)))
