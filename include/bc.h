@@ -318,6 +318,32 @@ bc_status bc_all_pairs(bc_ctx *ctx, double *bc_out, bc_mem mem);
 bc_status bc_sampled_distances(bc_ctx *ctx, const int32_t *sources, int32_t count, const int32_t *sample,
                                int32_t nsample, int32_t limit, int32_t *dist_out, bc_mem mem);
 
+/*
+ * For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid allocation): bc_read_sssp, every output in DEVICE
+ * memory, allocating nothing.
+ *   sources             host array of count vertex ids, 1 <= count <= the
+ *                       limit of bc_read_sssp
+ *   dist, sigma, delta  device arrays of count * n elements (any may be NULL),
+ *                       written exactly as bc_read_sssp writes its host arrays
+ * The call stages the internal source ids and count * n cells of distance,
+ * count and dependency -- about 20 * count * n bytes, plus 12 * count for a
+ * context of many graphs -- in one fixed device array of
+ * BC_NOALLOC_SCRATCH_BYTES, which the library holds on every GPU it runs on
+ * until the process ends; a larger request gives BC_ERR_UNSUPPORTED.  Any
+ * other allocation the context would need on the way (frontier levels for a
+ * graph deeper than any batch run so far, a weighted source's larger arena,
+ * the handed-back batches of an earlier replayed run) gives BC_ERR_NOMEM
+ * instead; an ordinary call with the same sources first makes that room.
+ * Every call on one GPU uses the same array, which keeps the last call's
+ * contents: calls that overlap on one GPU (from several threads, or
+ * contexts on other streams) race.  Synchronises.
+ * Errors: as bc_read_sssp, BC_ERR_UNSUPPORTED, BC_ERR_NOMEM.
+ */
+#define BC_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+bc_status bc_read_sssp_noalloc(bc_ctx *ctx, const int32_t *sources, int32_t count,
+                               int32_t *dist, uint64_t *sigma, double *delta);
+
 typedef struct {
     int32_t n;           /* vertices */
     int64_t m;           /* undirected edges = nnz / 2 */

@@ -43,6 +43,7 @@ BC_ALL_PAIRS_MAX_N = 32768
 BC_ALGEBRAIC_MAX_WEIGHT = 8
 BC_ALGEBRAIC_MAX_DEGREE = 65792
 BC_SAMPLED_MAX_S = 4096
+BC_NOALLOC_SCRATCH_BYTES = 64 << 20
 BC_TUNE_DEFAULT = 0
 BC_TUNE_MEASURED = 1
 BC_TUNE_CACHED = 2
@@ -96,6 +97,8 @@ SIGNATURES = {
                                             ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int]),
     "bc_read_sssp": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_void_p]),
+    "bc_read_sssp_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_void_p]),
     "bc_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(bc_info)]),
     "bc_get_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_int64)]),
@@ -185,6 +188,10 @@ def bc_sampled_distances(ctx, sources_ptr, count: int, sample_ptr, nsample: int,
 
 def bc_read_sssp(ctx, sources_ptr, count: int, dist_ptr, sigma_ptr, delta_ptr) -> None:
     _check(load().bc_read_sssp(ctx, sources_ptr, count, dist_ptr, sigma_ptr, delta_ptr), ctx)
+
+
+def bc_read_sssp_noalloc(ctx, sources_ptr, count: int, dist_ptr, sigma_ptr, delta_ptr) -> None:
+    _check(load().bc_read_sssp_noalloc(ctx, sources_ptr, count, dist_ptr, sigma_ptr, delta_ptr), ctx)
 
 
 def bc_get_info(ctx) -> bc_info:
@@ -387,6 +394,21 @@ class BC:
         delta = np.zeros((k, max(self.n, 1)), np.float64)
         bc_read_sssp(self._ctx, s.ctypes.data, k, dist.ctypes.data, sigma.ctypes.data, delta.ctypes.data)
         return dist[:, : self.n], sigma[:, : self.n], delta[:, : self.n]
+
+    def sssp_noalloc(self, sources, dist=None, sigma=None, delta=None):
+        """bc_read_sssp_noalloc into caller device tensors of shape (k, n):
+        dist int32, sigma int64 (the uint64 counts' bits), delta float64; any
+        may be None.  Allocates nothing."""
+        s = np.ascontiguousarray(sources, dtype=np.int32)
+        k = int(s.size)
+        want = {"dist": (dist, self.torch.int32), "sigma": (sigma, self.torch.int64),
+                "delta": (delta, self.torch.float64)}
+        for name, (t, dt) in want.items():
+            if t is not None and (not t.is_cuda or t.dtype != dt or not t.is_contiguous()
+                                  or tuple(t.shape) != (k, self.n)):
+                raise ValueError(f"{name} must be a contiguous {dt} device tensor of shape (len(sources), n)")
+        ptr = lambda t: t.data_ptr() if t is not None else None  # noqa: E731
+        bc_read_sssp_noalloc(self._ctx, s.ctypes.data if k else None, k, ptr(dist), ptr(sigma), ptr(delta))
 
     def info(self) -> bc_info:
         return bc_get_info(self._ctx)

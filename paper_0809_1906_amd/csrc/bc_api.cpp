@@ -138,6 +138,7 @@ bc_status bc_hip(bc_ctx *ctx, hipError_t e, const char *what) {
 }
 
 void *bc_dalloc(bc_ctx *ctx, size_t bytes) {
+    if (ctx->no_alloc) return nullptr; // bc_read_sssp_noalloc: BC_ERR_NOMEM, never an allocation
     if (bytes == 0) bytes = 256;
     bytes = (bytes + 255) & ~size_t(255);
     void *p = nullptr;
@@ -361,6 +362,7 @@ bc_status bc_create(const bc_graph *g, const bc_options *opt_in, bc_ctx **out) {
     }
     if (hipSetDevice(dev) != hipSuccess) return bail(BC_ERR_DEVICE, "hipSetDevice failed");
     ctx->device = dev;
+    noalloc_init_device(dev);
 
     // Internal numbering: vertices by nonincreasing degree (stable), or as given.
     const bool relabel = opt.vertex_order == BC_ORDER_DEGREE && n > 1;
@@ -548,6 +550,7 @@ bc_status bc_create_many(const bc_graph *gs, int32_t count, const bc_options *op
     if (dev < 0 && hipGetDevice(&dev) != hipSuccess) return bail(BC_ERR_DEVICE, "hipGetDevice failed");
     if (hipSetDevice(dev) != hipSuccess) return bail(BC_ERR_DEVICE, "hipSetDevice failed");
     ctx->device = dev;
+    noalloc_init_device(dev);
     if (hipStreamCreateWithFlags(&ctx->mg.stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&ctx->mg.ev, hipEventDisableTiming) != hipSuccess)
         return bail(BC_ERR_DEVICE, "stream creation failed");
@@ -614,7 +617,9 @@ static bc_status stage_sources(bc_ctx *ctx, const int32_t *sources, int64_t coun
     return BC_OK;
 }
 
-static bc_status check_usable(bc_ctx *ctx) {
+} // extern "C"
+
+bc_status bc_check_usable(bc_ctx *ctx) {
     if (ctx->poisoned) return bc_fail(ctx, BC_ERR_STATE, "context poisoned by an earlier device error");
     if (hipSetDevice(ctx->device) != hipSuccess) return bc_hip(ctx, hipErrorInvalidDevice, "hipSetDevice");
     // Every call may synchronise the stream or read results back, which a
@@ -629,6 +634,8 @@ static bc_status check_usable(bc_ctx *ctx) {
     return sparse_settle(ctx);
 }
 
+extern "C" {
+
 static bc_status check_overflow(bc_ctx *ctx) {
     BC_HIP(ctx, hipMemcpyAsync(ctx->status_host, ctx->status, sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->stream));
     BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -641,7 +648,7 @@ static bc_status check_overflow(bc_ctx *ctx) {
 
 bc_status bc_run(bc_ctx *ctx, const int32_t *sources, int64_t count, bc_mem mem) {
     if (!ctx) return BC_ERR_INVALID_ARG;
-    bc_status s = check_usable(ctx);
+    bc_status s = bc_check_usable(ctx);
     if (s != BC_OK) return s;
     if (ctx->overflow_seen) return bc_fail(ctx, BC_ERR_OVERFLOW, "an earlier run overflowed a path count; call bc_reset");
     if (ctx->many) {
@@ -667,7 +674,7 @@ bc_status bc_run(bc_ctx *ctx, const int32_t *sources, int64_t count, bc_mem mem)
 bc_status bc_read(bc_ctx *ctx, double *bc_out, bc_mem mem) {
     if (!ctx) return BC_ERR_INVALID_ARG;
     if (!bc_out && ctx->n > 0) return bc_fail(ctx, BC_ERR_INVALID_ARG, "bc_out is NULL");
-    bc_status s = check_usable(ctx);
+    bc_status s = bc_check_usable(ctx);
     if (s != BC_OK) return s;
     s = check_overflow(ctx);
     if (s != BC_OK) return s;
@@ -684,7 +691,7 @@ bc_status bc_read_edges(bc_ctx *ctx, double *eb_out, bc_mem mem) {
     if (!ctx) return BC_ERR_INVALID_ARG;
     if (!ctx->edges) return bc_fail(ctx, BC_ERR_UNSUPPORTED, "the context was created without edges");
     if (!eb_out && ctx->nnz > 0) return bc_fail(ctx, BC_ERR_INVALID_ARG, "eb_out is NULL");
-    bc_status s = check_usable(ctx);
+    bc_status s = bc_check_usable(ctx);
     if (s != BC_OK) return s;
     s = check_overflow(ctx);
     if (s != BC_OK) return s;
@@ -699,7 +706,7 @@ bc_status bc_read_edges(bc_ctx *ctx, double *eb_out, bc_mem mem) {
 
 bc_status bc_reset(bc_ctx *ctx) {
     if (!ctx) return BC_ERR_INVALID_ARG;
-    bc_status s = check_usable(ctx);
+    bc_status s = bc_check_usable(ctx);
     if (s != BC_OK) return s;
     BC_HIP(ctx, hipMemsetAsync(ctx->bc, 0, sizeof(double) * (size_t)std::max(ctx->n, 1), ctx->stream));
     if (ctx->eb) BC_HIP(ctx, hipMemsetAsync(ctx->eb, 0, sizeof(double) * (size_t)std::max(ctx->nnz, 1), ctx->stream));
@@ -715,7 +722,9 @@ bc_status bc_reset(bc_ctx *ctx) {
 // Calls that run sources without adding to BC (per-source dumps, all pairs)
 // share the device overflow flag with bc_run: they save it and clear it first,
 // then read what they raised and put the saved value back.
-static bc_status status_save(bc_ctx *ctx, uint32_t *before) {
+} // extern "C"
+
+bc_status bc_status_save(bc_ctx *ctx, uint32_t *before) {
     BC_HIP(ctx, hipMemcpyAsync(ctx->status_host, ctx->status, sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->stream));
     BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
     *before = *ctx->status_host;
@@ -723,7 +732,7 @@ static bc_status status_save(bc_ctx *ctx, uint32_t *before) {
     return BC_OK;
 }
 
-static bc_status status_restore(bc_ctx *ctx, uint32_t before, uint32_t *now) {
+bc_status bc_status_restore(bc_ctx *ctx, uint32_t before, uint32_t *now) {
     BC_HIP(ctx, hipMemcpyAsync(ctx->status_host, ctx->status, sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->stream));
     BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
     *now = *ctx->status_host;
@@ -733,10 +742,12 @@ static bc_status status_restore(bc_ctx *ctx, uint32_t before, uint32_t *now) {
     return BC_OK;
 }
 
+extern "C" {
+
 bc_status bc_read_sssp(bc_ctx *ctx, const int32_t *sources, int32_t count,
                        int32_t *dist, uint64_t *sigma, double *delta) {
     if (!ctx) return BC_ERR_INVALID_ARG;
-    bc_status s = check_usable(ctx);
+    bc_status s = bc_check_usable(ctx);
     if (s != BC_OK) return s;
     int32_t maxc = ctx->many ? 64 : ctx->form == BC_FORM_PLAIN_FP64 ? 4096 : ctx->sp.batch;
     if (!sources || count < 1 || count > maxc) return bc_fail(ctx, BC_ERR_INVALID_ARG, "count must be in [1, batch]");
@@ -757,12 +768,12 @@ bc_status bc_read_sssp(bc_ctx *ctx, const int32_t *sources, int32_t count,
     };
     if (!dd || !ds || !dl || !od || !os || !ol) { cleanup(); return bc_fail(ctx, BC_ERR_NOMEM, "dump allocation failed"); }
     uint32_t before = 0, now = 0;
-    if ((s = status_save(ctx, &before)) != BC_OK) { cleanup(); return s; }
+    if ((s = bc_status_save(ctx, &before)) != BC_OK) { cleanup(); return s; }
     bc_status run;
     if (ctx->many) run = multigraph_dump(ctx, sources, count, dd, ds, dl);
     else if (ctx->form == BC_FORM_PLAIN_FP64) run = plain_run(ctx, d_src, count, false, dl, dd, ds);
     else run = sparse_dump(ctx, d_src, count, dd, ds, dl);
-    if (run != BC_ERR_DEVICE) s = status_restore(ctx, before, &now);
+    if (run != BC_ERR_DEVICE) s = bc_status_restore(ctx, before, &now);
     if (run != BC_OK || s != BC_OK) { cleanup(); return run != BC_OK ? run : s; }
     if (now & BC_DEV_SIGMA_OVERFLOW) { cleanup(); return bc_fail(ctx, BC_ERR_OVERFLOW, "a shortest-path count exceeded 2^64 - 1"); }
     if (ctx->n > 0) {
@@ -781,7 +792,7 @@ bc_status bc_read_sssp(bc_ctx *ctx, const int32_t *sources, int32_t count,
 bc_status bc_all_pairs(bc_ctx *ctx, double *bc_out, bc_mem mem) {
     if (!ctx) return BC_ERR_INVALID_ARG;
     if (!bc_out && ctx->n > 0) return bc_fail(ctx, BC_ERR_INVALID_ARG, "bc_out is NULL");
-    bc_status s = check_usable(ctx);
+    bc_status s = bc_check_usable(ctx);
     if (s != BC_OK) return s;
     if (ctx->many) return bc_fail(ctx, BC_ERR_UNSUPPORTED, "all pairs: not for a context of many graphs");
     if (ctx->n > BC_ALL_PAIRS_MAX_N)
@@ -790,12 +801,12 @@ bc_status bc_all_pairs(bc_ctx *ctx, double *bc_out, bc_mem mem) {
     double *res = (double *)bc_dalloc(ctx, sizeof(double) * (size_t)ctx->n);
     if (!res) return bc_fail(ctx, BC_ERR_NOMEM, "all pairs: result allocation failed");
     uint32_t before = 0, now = 0;
-    if ((s = status_save(ctx, &before)) != BC_OK) {
+    if ((s = bc_status_save(ctx, &before)) != BC_OK) {
         bc_dfree(ctx, res);
         return s;
     }
     const bc_status run = allpairs_bc(ctx, res);
-    if (run != BC_ERR_DEVICE) s = status_restore(ctx, before, &now);
+    if (run != BC_ERR_DEVICE) s = bc_status_restore(ctx, before, &now);
     if (run != BC_OK || s != BC_OK) {
         bc_dfree(ctx, res);
         return run != BC_OK ? run : s;
@@ -819,7 +830,7 @@ bc_status bc_all_pairs(bc_ctx *ctx, double *bc_out, bc_mem mem) {
 bc_status bc_sampled_distances(bc_ctx *ctx, const int32_t *sources, int32_t count, const int32_t *sample,
                                int32_t nsample, int32_t limit, int32_t *dist_out, bc_mem mem) {
     if (!ctx) return BC_ERR_INVALID_ARG;
-    bc_status s = check_usable(ctx);
+    bc_status s = bc_check_usable(ctx);
     if (s != BC_OK) return s;
     if (ctx->many) return bc_fail(ctx, BC_ERR_UNSUPPORTED, "sampled forward: not for a context of many graphs");
     if (ctx->weighted) return bc_fail(ctx, BC_ERR_UNSUPPORTED, "sampled forward: unweighted graphs only");

@@ -225,6 +225,7 @@ struct bc_ctx {
     std::string err;
 
     bool host_driven = false;   // batched forms: no replayed batches (bc_options.host_driven)
+    bool no_alloc = false;      // inside bc_read_sssp_noalloc: bc_dalloc refuses every request
     bool recording = false;     // launches are being recorded into a graph (no timing events)
 
     int32_t timing = 0;         // 0 off; k >= 1: events on the launches of one source batch in k
@@ -237,6 +238,13 @@ struct bc_ctx {
 
 // ---- helpers implemented in bc_api.cpp --------------------------------------
 bc_status bc_fail(bc_ctx *ctx, bc_status s, const std::string &msg);
+// Entry checks of every call on a context (poisoned, stream under capture),
+// then sparse_settle.
+bc_status bc_check_usable(bc_ctx *ctx);
+// Calls that run sources without adding to BC save the device overflow flag
+// and clear it, then read what they raised and put the saved value back.
+bc_status bc_status_save(bc_ctx *ctx, uint32_t *before);
+bc_status bc_status_restore(bc_ctx *ctx, uint32_t before, uint32_t *now);
 bc_status bc_hip(bc_ctx *ctx, hipError_t e, const char *what);
 void *bc_dalloc(bc_ctx *ctx, size_t bytes);
 void bc_dfree(bc_ctx *ctx, void *p);
@@ -290,8 +298,16 @@ bc_status weighted_run(bc_ctx *ctx, const int32_t *d_sources, int64_t count, boo
 bc_status multigraph_prepare(bc_ctx *ctx, const std::vector<int32_t> &voff, const std::vector<int32_t> &rpoff,
                              const std::vector<int32_t> &rp, int32_t chunk);
 bc_status multigraph_run(bc_ctx *ctx);
+// units: 3 * count int32 of device staging, or nullptr to allocate it
 bc_status multigraph_dump(bc_ctx *ctx, const int32_t *h_sources, int32_t count, int32_t *dist_dump,
-                          uint64_t *sigma_dump, double *delta_dump);
+                          uint64_t *sigma_dump, double *delta_dump, int32_t *units = nullptr);
+
+// ---- allocation-free readout (noalloc.hip) ----------------------------------------
+// Looks up, once per device and with that device current, the address of the
+// fixed staging array there (called when a context is created).
+void noalloc_init_device(int device);
+// That address, or nullptr if the lookup failed.
+unsigned char *noalloc_scratch(int device);
 
 bc_status sparse_prepare(bc_ctx *ctx, int32_t batch, int32_t split_degree);
 bc_status algebraic_prepare(bc_ctx *ctx);

@@ -491,7 +491,7 @@ bc_status multigraph_run(bc_ctx *ctx) {
 
 // Per-source readout: global vertex ids of the concatenated numbering.
 bc_status multigraph_dump(bc_ctx *ctx, const int32_t *h_sources, int32_t count, int32_t *dist_dump,
-                          uint64_t *sigma_dump, double *delta_dump) {
+                          uint64_t *sigma_dump, double *delta_dump, int32_t *units_buf) {
     MultiState &m = ctx->mg;
     std::vector<int32_t> units((size_t)3 * count);
     for (int32_t i = 0; i < count; ++i) {
@@ -501,7 +501,7 @@ bc_status multigraph_dump(bc_ctx *ctx, const int32_t *h_sources, int32_t count, 
         units[(size_t)3 * i + 1] = s - m.h_voff[(size_t)g];
         units[(size_t)3 * i + 2] = s - m.h_voff[(size_t)g] + 1;
     }
-    int32_t *du = (int32_t *)bc_dalloc(ctx, units.size() * sizeof(int32_t));
+    int32_t *du = units_buf ? units_buf : (int32_t *)bc_dalloc(ctx, units.size() * sizeof(int32_t));
     if (!du) return bc_fail(ctx, BC_ERR_NOMEM, "many graphs: readout allocation failed");
     BC_HIP(ctx, hipMemcpy(du, units.data(), units.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     const int64_t cells = (int64_t)count * ctx->n;
@@ -516,6 +516,6 @@ bc_status multigraph_dump(bc_ctx *ctx, const int32_t *h_sources, int32_t count, 
     hipLaunchKernelGGL(k_mg_sweep, dim3(std::min(count, m.grid)), dim3(MT), 0, ctx->stream, a);
     BC_HIP(ctx, hipGetLastError());
     BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    bc_dfree(ctx, du);
+    if (!units_buf) bc_dfree(ctx, du);
     return BC_OK;
 }
