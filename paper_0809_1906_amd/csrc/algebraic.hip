@@ -77,8 +77,8 @@ struct GemmArgs {
     float *ws;             // split tiles' partial sums, [8][ntiles][2][64][forward block threads]
     uint32_t *arrive;      // [8][ntiles]
     unsigned long long *ktiles; // [0] k-tiles multiplied, [1] k-tiles in the blocks' ranges (per direction)
-    const uint32_t *gate;  // unit weights: flag of the level the product reads (forward: level l;
-                           // backward: level l, whose vertices it writes); zero = every block exits
+    const uint32_t *gate;  // backward of a replayed batch: flag of level l, whose vertices it
+                           // writes; zero = every block exits
 };
 
 struct EpiArgs {
@@ -95,7 +95,6 @@ struct EpiArgs {
     unsigned long long *lvmax_next;      // forward: largest count of level l+1
     int32_t classes, level;              // forward: M, and l (levels l+1-M .. l feed level l+1)
     unsigned long long *planes_issued;   // products issued (limb or coefficient planes)
-    uint32_t *flag_next;                 // forward, unit weights: set when level l+1 gets a vertex
     int accumulate;
 };
 
@@ -364,7 +363,7 @@ __device__ __forceinline__ void epi_fwd(const GemmArgs &g, const EpiArgs &e, int
     const bool first = mode == EPI_FIRST, mid = mode == EPI_MID, last = mode == EPI_LAST;
     const bool final_limb = mode == EPI_ONLY || last;
     S *sigma = reinterpret_cast<S *>(e.sigma);
-    bool wide = false, ovf = false, reached = false;
+    bool wide = false, ovf = false;
     uint64_t mx = 0;
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
@@ -416,7 +415,6 @@ __device__ __forceinline__ void epi_fwd(const GemmArgs &g, const EpiArgs &e, int
                     if (word) {
                         e.visited[(size_t)w * g.NW + q] = vis | word;
                         atomicOr(&e.any_next[w >> 5], 1u << (w & 31));
-                        reached = true;
                     }
                 }
             }
@@ -431,9 +429,6 @@ __device__ __forceinline__ void epi_fwd(const GemmArgs &g, const EpiArgs &e, int
         if (lane == 0 && mx > __hip_atomic_load(e.lvmax_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
             atomicMax(e.lvmax_next, (unsigned long long)mx);
         if (__any(wide) && lane == 0) atomicOr(&e.status[1], 1u);
-        if (e.flag_next && __any(reached) && lane == 0 &&
-            __hip_atomic_load(e.flag_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
-            __hip_atomic_store(e.flag_next, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (__any(ovf) && lane == 0) atomicOr(&e.status[0], (uint32_t)BC_DEV_SIGMA_OVERFLOW);
 }
@@ -446,7 +441,6 @@ __global__ __launch_bounds__(2 * BM, 2) void k_mfma_fwd(GemmArgs g, EpiArgs e) {
     __shared__ __align__(16) __bf16 sA[stages<1, KS>()][lds_a<KS, BM>()];
     __shared__ __align__(16) __bf16 sX[stages<1, KS>()][lds_x<1, KS>()];
     __shared__ int s_last;
-    if (g.gate && *g.gate == 0) return; // level l is empty: nothing to expand
     int half = 0, tile = 0;
     const Tile tl = g.ksplit == 2 ? tile_of_split(g.B, half, tile) : tile_of(g.B);
     if (tl.row >= g.npad / BM) return;
@@ -555,12 +549,10 @@ __global__ __launch_bounds__(PB) void k_limb_split(int32_t n, int32_t npad, int3
                                                    int32_t l, const unsigned long long *__restrict__ lvmax_l,
                                                    const uint64_t *__restrict__ fl, size_t words,
                                                    const S *__restrict__ sigma, __bf16 *__restrict__ planes,
-                                                   size_t plane_elems, uint32_t *__restrict__ kflags,
-                                                   const uint32_t *__restrict__ gate) {
+                                                   size_t plane_elems, uint32_t *__restrict__ kflags) {
     const size_t id = (size_t)blockIdx.x * PB + threadIdx.x;
     const size_t per_class = (size_t)(npad / 8) * B;
     if (id >= per_class * M) return;
-    if (gate && *gate == 0) return; // level l is empty: the product exits too
     const int32_t c = (int32_t)(id / per_class);
     const size_t r = id - (size_t)c * per_class;
     const int L = limbs_feeding(lvmax_l, l, M);
@@ -727,7 +719,7 @@ bc_status algebraic_release(bc_ctx *ctx) {
 // counts, any[l+1] and the largest count of level l+1 exactly as the pull
 // kernel does; reads the largest count of level l on the device.
 template <typename S>
-bc_status algebraic_forward_level_t(bc_ctx *ctx, int32_t l, uint32_t *gate) {
+bc_status algebraic_forward_level_t(bc_ctx *ctx, int32_t l) {
     AlgebraicState &a = ctx->al;
     SparseState &s = ctx->sp;
     const size_t words = (size_t)ctx->n * s.words;
@@ -739,7 +731,7 @@ bc_status algebraic_forward_level_t(bc_ctx *ctx, int32_t l, uint32_t *gate) {
         LaunchTimer tm(ctx, "limb_split");
         hipLaunchKernelGGL(k_limb_split<S>, dim3(blocks_for(plane_elems / 8, PB)), dim3(PB), 0, ctx->stream, ctx->n,
                            a.npad, s.batch, s.words, a.classes, l, s.lvmax + l, fcur, words, (const S *)s.sigma,
-                           a.planes, plane_elems, a.kflags, (const uint32_t *)gate);
+                           a.planes, plane_elems, a.kflags);
         tm.done();
     }
     EpiArgs e{};
@@ -754,9 +746,7 @@ bc_status algebraic_forward_level_t(bc_ctx *ctx, int32_t l, uint32_t *gate) {
     e.classes = a.classes;
     e.level = l;
     e.planes_issued = a.planes_issued;
-    e.flag_next = gate ? gate + 1 : nullptr;
-    GemmArgs g = gemm_args(ctx, a.planes, true);
-    g.gate = gate;
+    const GemmArgs g = gemm_args(ctx, a.planes, true);
     LaunchTimer tm(ctx, "mfma_fwd");
     hipLaunchKernelGGL((k_mfma_fwd<S, FWD_KS, FWD_BM>), dim3(grid_blocks<FWD_BM>(a.npad, s.batch) * a.ksplit),
                        dim3(2 * FWD_BM), 0, ctx->stream, g, e);
@@ -801,8 +791,8 @@ bc_status algebraic_backward_level_t(bc_ctx *ctx, const uint64_t *fcur, const ui
     return BC_OK;
 }
 
-bc_status algebraic_forward_level(bc_ctx *ctx, bool wide, int32_t l, uint32_t *gate) {
-    return wide ? algebraic_forward_level_t<uint64_t>(ctx, l, gate) : algebraic_forward_level_t<uint32_t>(ctx, l, gate);
+bc_status algebraic_forward_level(bc_ctx *ctx, bool wide, int32_t l) {
+    return wide ? algebraic_forward_level_t<uint64_t>(ctx, l) : algebraic_forward_level_t<uint32_t>(ctx, l);
 }
 
 bc_status algebraic_backward_level(bc_ctx *ctx, bool wide, const uint64_t *fcur, const uint64_t *fnext,

@@ -36,6 +36,7 @@ struct BatchCtl {
     uint32_t max_nlev;      // deepest level count among the batches that completed
     uint32_t need_wide;     // a handed-back batch needs uint64 counts
     uint32_t deep;          // a handed-back batch went past the captured depth
+    uint32_t arrived;       // blocks of the current batch check that have finished
 };
 
 // State of the batched sparse form (per-level frontier bitmaps).
@@ -57,6 +58,8 @@ struct SparseState {
     uint32_t *arrive = nullptr;  // [nheavy] segment arrival counters (per row)
     uint32_t *arrive_w = nullptr;// [nheavy][words] segment arrival counters (per row and word)
     bool bwd_per_word = true;    // backward: one wave per (row, word) instead of per row
+    int32_t bwd_grid = 0;        // per-word backward: blocks per launch (0 = one wave per item)
+    int32_t fwd_grid = 0;        // forward pull: blocks per launch (0 = one wave per row or segment)
     int32_t depth_guess = 8;     // forward levels launched before the first check
     int32_t depth_max = 0;       // most levels any batch of this state has had (0: none run yet)
     bool wide = false;           // counts need uint64 storage (else uint32)
@@ -312,12 +315,10 @@ unsigned char *noalloc_scratch(int device);
 bc_status sparse_prepare(bc_ctx *ctx, int32_t batch, int32_t split_degree);
 bc_status algebraic_prepare(bc_ctx *ctx);
 // Forward level l -> l+1 by products (front, counts, any and lvmax of level l+1).
-// With gate = &lvflag[l] (unit weights), an empty level l makes every
-// launch exit at once, and a non-empty level l+1 sets gate[1].
-bc_status algebraic_forward_level(bc_ctx *ctx, bool wide, int32_t l, uint32_t *gate = nullptr);
+bc_status algebraic_forward_level(bc_ctx *ctx, bool wide, int32_t l);
 // Backward level l; `deeper` of the levels l+1 .. l+M exist, fnext = front[l+1].
-// With gate = &lvflag[l] (unit weights), an empty level l exits at once and
-// level l+1 counts as existing only if gate[1] is set.
+// With gate = &lvflag[l] (replayed batches), an empty level l exits at once
+// and level l+1 counts as existing only if gate[1] is set.
 bc_status algebraic_backward_level(bc_ctx *ctx, bool wide, const uint64_t *fcur, const uint64_t *fnext,
                                    int32_t deeper, double *delta_dump, bool accumulate,
                                    const uint32_t *gate = nullptr);

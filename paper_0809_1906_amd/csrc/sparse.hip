@@ -139,13 +139,6 @@ __device__ __forceinline__ double wave_sum8(const double (&p)[8], int lane) {
 // cache write-back fence.
 __device__ __forceinline__ void wait_memory() { __asm__ __volatile__("s_waitcnt vmcnt(0)" ::: "memory"); }
 
-// Marks a level as holding a vertex (lvflag): the flag settles after the first
-// few waves, which later waves read and skip the store.
-__device__ __forceinline__ void mark_level(uint32_t *flag) {
-    if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
-        __hip_atomic_store(flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 __device__ __forceinline__ bool last_arriver(uint32_t *arrive, int32_t total, int lane) {
     wait_memory();
     uint32_t old = 0;
@@ -338,6 +331,7 @@ __global__ void k_run_init(BatchCtl *ctl, const int32_t *src, int32_t total, int
     ctl->max_nlev = 0;
     ctl->need_wide = 0;
     ctl->deep = 0;
+    ctl->arrived = 0;
 }
 
 // Seeds the batch: lane b takes source src[b] (b < count).  In a replayed
@@ -345,7 +339,7 @@ __global__ void k_run_init(BatchCtl *ctl, const int32_t *src, int32_t total, int
 template <typename S>
 __global__ __launch_bounds__(SB) void k_sp_seed(const int32_t *__restrict__ src, int32_t count, int32_t B, int32_t NW,
                                                 uint64_t *front0, uint64_t *visited, S *sigma, int32_t *src_lane,
-                                                uint32_t *any0, uint32_t *lvflag, const BatchCtl *__restrict__ ctl) {
+                                                uint32_t *any0, const BatchCtl *__restrict__ ctl) {
     const int32_t b = blockIdx.x * SB + threadIdx.x;
     if (b >= B) return;
     if (ctl) {
@@ -355,7 +349,6 @@ __global__ __launch_bounds__(SB) void k_sp_seed(const int32_t *__restrict__ src,
     }
     const int32_t s = b < count ? src[b] : -1;
     src_lane[b] = s;
-    if (b == 0 && count > 0) lvflag[0] = 1u;
     if (s >= 0) {
         const unsigned long long bit = 1ull << (b & 63);
         atomicOr((unsigned long long *)&front0[(size_t)s * NW + (b >> 6)], bit);
@@ -371,12 +364,10 @@ __global__ __launch_bounds__(SB) void k_sp_seed(const int32_t *__restrict__ src,
 template <typename S>
 __global__ __launch_bounds__(SB) void k_fwd_push0(Topo t, int32_t NW, const int32_t *__restrict__ src_lane,
                                                   uint64_t *__restrict__ fnext, uint64_t *__restrict__ visited,
-                                                  S *__restrict__ sigma, uint32_t *__restrict__ any_next,
-                                                  uint32_t *__restrict__ flag_next) {
+                                                  S *__restrict__ sigma, uint32_t *__restrict__ any_next) {
     const int32_t b = blockIdx.x;
     const int32_t s = src_lane[b];
     if (s < 0) return;
-    if (threadIdx.x == 0 && t.rp[s + 1] > t.rp[s]) mark_level(flag_next);
     const unsigned long long bit = 1ull << (b & 63);
     const int q = b >> 6;
     for (int32_t e = t.rp[s] + threadIdx.x; e < t.rp[s + 1]; e += SB) {
@@ -404,7 +395,7 @@ __device__ __forceinline__ void wave_max_to(unsigned long long *dst, uint64_t x)
 template <int NW>
 __device__ __forceinline__ void fwd_commit(int32_t w, const uint64_t (&vis)[NW], const uint64_t (&out)[NW], int lane,
                                            uint64_t *__restrict__ fnext, uint64_t *__restrict__ visited,
-                                           uint32_t *__restrict__ any_next, uint32_t *__restrict__ flag_next) {
+                                           uint32_t *__restrict__ any_next) {
     uint64_t mine_out = 0, mine_vis = 0, all = 0;
 #pragma unroll
     for (int q = 0; q < NW; ++q) {
@@ -418,10 +409,7 @@ __device__ __forceinline__ void fwd_commit(int32_t w, const uint64_t (&vis)[NW],
         fnext[(size_t)w * NW + lane] = mine_out;
         if (mine_out) visited[(size_t)w * NW + lane] = mine_vis;
     }
-    if (lane == 0 && all) {
-        atomicOr(&any_next[w >> 5], 1u << (w & 31));
-        mark_level(flag_next);
-    }
+    if (lane == 0 && all) atomicOr(&any_next[w >> 5], 1u << (w & 31));
 }
 
 // Forward level l -> l+1 for l >= 1.  Light rows complete in their wave; split
@@ -437,20 +425,13 @@ __device__ __forceinline__ void fwd_commit(int32_t w, const uint64_t (&vis)[NW],
 //   sig16: half the bytes of a uint32 row.
 enum { FWD_GENERAL = 0, FWD_UNIT = 1, FWD_HALF = 2 };
 template <int NW, typename S, int MODE>
-__global__ __launch_bounds__(SB) void k_fwd_pull(Topo t, const uint32_t *__restrict__ any_cur,
-                                                 const uint64_t *__restrict__ fcur, uint64_t *__restrict__ fnext,
-                                                 uint64_t *__restrict__ visited, S *__restrict__ sigma,
-                                                 uint16_t *__restrict__ sig16,
-                                                 unsigned long long *__restrict__ hacc, uint32_t *__restrict__ arrive,
-                                                 uint32_t *__restrict__ any_next, uint32_t *__restrict__ status,
-                                                 unsigned long long *__restrict__ lvmax_next,
-                                                 uint32_t *__restrict__ lvf) {
-    // lvf[0]: level l holds a vertex; lvf[1]: set here when level l+1 does.
-    // An empty level l leaves level l+1 empty: every wave exits at once (its
-    // front words are then never read: readers check the flag first).
-    if (*lvf == 0) return;
-    const int lane = threadIdx.x & 63;
-    const int64_t wid = (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6);
+__device__ __forceinline__ void fwd_item(const Topo &t, int64_t wid, const uint32_t *__restrict__ any_cur,
+                                         const uint64_t *__restrict__ fcur, uint64_t *__restrict__ fnext,
+                                         uint64_t *__restrict__ visited, S *__restrict__ sigma,
+                                         uint16_t *__restrict__ sig16, unsigned long long *__restrict__ hacc,
+                                         uint32_t *__restrict__ arrive, uint32_t *__restrict__ any_next,
+                                         uint32_t *__restrict__ status, unsigned long long *__restrict__ lvmax_next,
+                                         int lane) {
     Item it;
     if (!item_of(t, wid, it)) return;
     const int32_t w = it.v;
@@ -487,7 +468,7 @@ __global__ __launch_bounds__(SB) void k_fwd_pull(Topo t, const uint32_t *__restr
             }
             mx = acc[q] > mx ? acc[q] : mx;
         }
-        fwd_commit<NW>(w, vis, out, lane, fnext, visited, any_next, lvf + 1);
+        fwd_commit<NW>(w, vis, out, lane, fnext, visited, any_next);
         if (lvmax_next) wave_max_to(lvmax_next, mx);
     } else {
         unsigned long long *hrow = hacc + (size_t)it.h * t.B + lane;
@@ -512,12 +493,41 @@ __global__ __launch_bounds__(SB) void k_fwd_pull(Topo t, const uint32_t *__restr
                 out[q] = __ballot(x != 0);
                 mx = x > mx ? x : mx;
             }
-            fwd_commit<NW>(w, vis, out, lane, fnext, visited, any_next, lvf + 1);
+            fwd_commit<NW>(w, vis, out, lane, fnext, visited, any_next);
             if (lvmax_next) wave_max_to(lvmax_next, mx);
         }
     }
     if (__any(ovf) && lane == 0) atomicOr(&status[0], (uint32_t)BC_DEV_SIGMA_OVERFLOW);
     if (__any(wide) && lane == 0) atomicOr(&status[1], 1u);
+}
+
+// The launches.  k_fwd_pull: each wave takes rows (or segments) wave, wave +
+// waves, ... of the n + nseg, eight waves per SIMD (the loop's extra live
+// values fit 64 registers for up to four words).  k_fwd_pull_row: one wave
+// per row or segment, for eight words per row, whose registers leave no room
+// for the loop.
+template <int NW, typename S, int MODE>
+__global__ __launch_bounds__(SB) __attribute__((amdgpu_waves_per_eu(8))) void k_fwd_pull(
+    Topo t, const uint32_t *__restrict__ any_cur, const uint64_t *__restrict__ fcur, uint64_t *__restrict__ fnext,
+    uint64_t *__restrict__ visited, S *__restrict__ sigma, uint16_t *__restrict__ sig16,
+    unsigned long long *__restrict__ hacc, uint32_t *__restrict__ arrive, uint32_t *__restrict__ any_next,
+    uint32_t *__restrict__ status, unsigned long long *__restrict__ lvmax_next) {
+    const int lane = threadIdx.x & 63;
+    const int64_t items = (int64_t)t.n + t.nseg, waves = (int64_t)gridDim.x * WPB;
+    for (int64_t wid = (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6); wid < items; wid += waves)
+        fwd_item<NW, S, MODE>(t, wid, any_cur, fcur, fnext, visited, sigma, sig16, hacc, arrive, any_next, status,
+                              lvmax_next, lane);
+}
+template <int NW, typename S, int MODE>
+__global__ __launch_bounds__(SB) void k_fwd_pull_row(
+    Topo t, const uint32_t *__restrict__ any_cur, const uint64_t *__restrict__ fcur, uint64_t *__restrict__ fnext,
+    uint64_t *__restrict__ visited, S *__restrict__ sigma, uint16_t *__restrict__ sig16,
+    unsigned long long *__restrict__ hacc, uint32_t *__restrict__ arrive, uint32_t *__restrict__ any_next,
+    uint32_t *__restrict__ status, unsigned long long *__restrict__ lvmax_next) {
+    const int64_t wid = (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6);
+    if (wid < (int64_t)t.n + t.nseg)
+        fwd_item<NW, S, MODE>(t, wid, any_cur, fcur, fnext, visited, sigma, sig16, hacc, arrive, any_next, status,
+                              lvmax_next, threadIdx.x & 63);
 }
 
 // Backward level l.  Light rows complete in their wave; split rows in the last
@@ -530,10 +540,12 @@ __global__ __launch_bounds__(SB) void k_bwd_pull(Topo t, const uint64_t *__restr
                                                  double *__restrict__ bc, double *__restrict__ hacc,
                                                  uint32_t *__restrict__ arrive, double *__restrict__ delta_dump,
                                                  int accumulate, const uint32_t *__restrict__ lvf) {
-    // lvf[0]: level l holds a vertex (cleared for a batch handed back);
-    // lvf[1]: level l+1 does (else fnext is not read)
-    if (lvf[0] == 0) return;
-    if (lvf[1] == 0) fnext = nullptr;
+    // replayed batches: lvf[0] says level l holds a vertex (cleared for a
+    // batch handed back), lvf[1] level l+1 (else fnext is not read)
+    if (lvf) {
+        if (lvf[0] == 0) return;
+        if (lvf[1] == 0) fnext = nullptr;
+    }
     const int lane = threadIdx.x & 63;
     const int64_t wid = (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6);
     Item it;
@@ -570,23 +582,17 @@ __global__ __launch_bounds__(SB) void k_bwd_pull(Topo t, const uint64_t *__restr
     }
 }
 
-// Backward level l, one wave per (row or row segment, word q): at the fat
+// Backward level l, one item per (row or row segment, word q): at the fat
 // levels this keeps NW times more waves in flight than a wave per row, and a
 // word with no sources at this level costs its wave a single load.
 template <int NW, typename S, bool EB>
-__global__ __launch_bounds__(SB) void k_bwd_pull_w(Topo t, const uint64_t *__restrict__ fcur,
-                                                   const uint32_t *__restrict__ any_next,
-                                                   const uint64_t *__restrict__ fnext, const S *__restrict__ sigma,
-                                                   float *__restrict__ cval, const int32_t *__restrict__ src_lane,
-                                                   double *__restrict__ bc, double *__restrict__ hacc,
-                                                   uint32_t *__restrict__ arrive, double *__restrict__ delta_dump,
-                                                   int accumulate, double *__restrict__ eb,
-                                                   const uint32_t *__restrict__ lvf) {
-    // lvf as in k_bwd_pull
-    if (lvf[0] == 0) return;
-    if (lvf[1] == 0) fnext = nullptr;
-    const int lane = threadIdx.x & 63;
-    const int64_t wid = (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6);
+__device__ __forceinline__ void bwd_item_w(const Topo &t, int64_t wid, const uint64_t *__restrict__ fcur,
+                                           const uint32_t *__restrict__ any_next, const uint64_t *__restrict__ fnext,
+                                           const S *__restrict__ sigma, float *__restrict__ cval,
+                                           const int32_t *__restrict__ src_lane, double *__restrict__ bc,
+                                           double *__restrict__ hacc, uint32_t *__restrict__ arrive,
+                                           double *__restrict__ delta_dump, int accumulate, double *__restrict__ eb,
+                                           int lane) {
     const int q = (int)(wid % NW);
     Item it;
     if (!item_of(t, wid / NW, it)) return;
@@ -662,6 +668,47 @@ __global__ __launch_bounds__(SB) void k_bwd_pull_w(Topo t, const uint64_t *__res
         bwd_finalize<1, S>(v, F1, acc, lane, t.B, t.n, sig_q, cval_q, src_q, bc,
                            delta_dump ? delta_dump + (size_t)q * 64 * t.n : nullptr, accumulate);
     }
+}
+
+// The launches.  k_bwd_pull_w: each wave takes items wave, wave + waves, ...
+// of the (n + nseg) * NW, eight waves per SIMD; a grid smaller than one wave
+// per item makes a launch whose level turns out empty (replayed batches) cost
+// a few thousand waves' flag reads instead of one wave per item.  With edge
+// terms the loop's extra live values would spill: one item per wave.
+template <int NW, typename S>
+__global__ __launch_bounds__(SB) __attribute__((amdgpu_waves_per_eu(8))) void k_bwd_pull_w(
+    Topo t, const uint64_t *__restrict__ fcur, const uint32_t *__restrict__ any_next,
+    const uint64_t *__restrict__ fnext, const S *__restrict__ sigma, float *__restrict__ cval,
+    const int32_t *__restrict__ src_lane, double *__restrict__ bc, double *__restrict__ hacc,
+    uint32_t *__restrict__ arrive, double *__restrict__ delta_dump, int accumulate, const uint32_t *__restrict__ lvf) {
+    // lvf as in k_bwd_pull
+    if (lvf) {
+        if (lvf[0] == 0) return;
+        if (lvf[1] == 0) fnext = nullptr;
+    }
+    const int lane = threadIdx.x & 63;
+    const int64_t items = ((int64_t)t.n + t.nseg) * NW, waves = (int64_t)gridDim.x * WPB;
+    for (int64_t wid = (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6); wid < items; wid += waves)
+        bwd_item_w<NW, S, false>(t, wid, fcur, any_next, fnext, sigma, cval, src_lane, bc, hacc, arrive, delta_dump,
+                                 accumulate, nullptr, lane);
+}
+template <int NW, typename S>
+__global__ __launch_bounds__(SB) void k_bwd_pull_we(Topo t, const uint64_t *__restrict__ fcur,
+                                                    const uint32_t *__restrict__ any_next,
+                                                    const uint64_t *__restrict__ fnext, const S *__restrict__ sigma,
+                                                    float *__restrict__ cval, const int32_t *__restrict__ src_lane,
+                                                    double *__restrict__ bc, double *__restrict__ hacc,
+                                                    uint32_t *__restrict__ arrive, double *__restrict__ delta_dump,
+                                                    int accumulate, double *__restrict__ eb,
+                                                    const uint32_t *__restrict__ lvf) {
+    if (lvf) {
+        if (lvf[0] == 0) return;
+        if (lvf[1] == 0) fnext = nullptr;
+    }
+    const int64_t wid = (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6);
+    if (wid < ((int64_t)t.n + t.nseg) * NW)
+        bwd_item_w<NW, S, true>(t, wid, fcur, any_next, fnext, sigma, cval, src_lane, bc, hacc, arrive, delta_dump,
+                                accumulate, eb, threadIdx.x & 63);
 }
 
 // Per-source readout for bc_read_sssp: out[b][v] in source-major layout.  The
@@ -842,7 +889,7 @@ bc_status launch_batch_init(bc_ctx *ctx, const BatchShape &b, const int32_t *d_s
     hipLaunchKernelGGL(k_sp_clear, dim3(std::max(blocks, 1)), dim3(SB), 0, ctx->stream, s.front, s.visited, b.words,
                        s.any, (size_t)s.level_cap * b.aw, s.lvmax, s.lvflag, s.level_cap);
     hipLaunchKernelGGL(k_sp_seed<S>, dim3((b.B + SB - 1) / SB), dim3(SB), 0, ctx->stream, d_src, count, b.B, NW,
-                       s.front, s.visited, reinterpret_cast<S *>(s.sigma), s.src, s.any, s.lvflag, ctl);
+                       s.front, s.visited, reinterpret_cast<S *>(s.sigma), s.src, s.any, ctl);
     tm.done();
     BC_HIP(ctx, hipGetLastError());
     return BC_OK;
@@ -858,51 +905,57 @@ bc_status launch_fwd_level(bc_ctx *ctx, const BatchShape &b, int32_t l, bool pro
     if (l == 0) {
         LaunchTimer tm(ctx, "fwd_push0");
         hipLaunchKernelGGL(k_fwd_push0<S>, dim3(b.B), dim3(SB), 0, ctx->stream, b.t, NW, (const int32_t *)s.src,
-                           s.front + b.words, s.visited, reinterpret_cast<S *>(s.sigma), s.any + b.aw, s.lvflag + 1);
+                           s.front + b.words, s.visited, reinterpret_cast<S *>(s.sigma), s.any + b.aw);
         tm.done();
         return BC_OK;
     }
-    if (products) return algebraic_forward_level(ctx, sizeof(S) == 8, l, s.lvflag + l);
+    if (products) return algebraic_forward_level(ctx, sizeof(S) == 8, l);
     LaunchTimer tm(ctx, "fwd_pull");
     // level 1 holds the sources' neighbours, each with one shortest path (the
     // input graph is simple): its pull counts frontier bits, and level 2's
     // counts (at most a degree) also go to sig16, from which level 2 -> 3
     // gathers them
-    const auto kern = l == 1                 ? k_fwd_pull<NW, S, FWD_UNIT>
-                      : l == 2 && *l1_pulled ? k_fwd_pull<NW, S, FWD_HALF>
-                                             : k_fwd_pull<NW, S, FWD_GENERAL>;
+    const bool strided = NW < 8 && s.fwd_grid > 0;
+    const auto kern = l == 1                 ? (strided ? k_fwd_pull<NW, S, FWD_UNIT> : k_fwd_pull_row<NW, S, FWD_UNIT>)
+                      : l == 2 && *l1_pulled ? (strided ? k_fwd_pull<NW, S, FWD_HALF> : k_fwd_pull_row<NW, S, FWD_HALF>)
+                                             : (strided ? k_fwd_pull<NW, S, FWD_GENERAL>
+                                                        : k_fwd_pull_row<NW, S, FWD_GENERAL>);
     if (l == 1) *l1_pulled = sig16 != nullptr;
-    hipLaunchKernelGGL(kern, dim3(b.pull_blocks), dim3(SB), 0, ctx->stream, b.t, s.any + (size_t)l * b.aw,
+    const int grid = strided ? std::min(b.pull_blocks, s.fwd_grid) : b.pull_blocks;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(SB), 0, ctx->stream, b.t, s.any + (size_t)l * b.aw,
                        s.front + (size_t)l * b.words, s.front + (size_t)(l + 1) * b.words, s.visited,
                        reinterpret_cast<S *>(s.sigma), sig16, (unsigned long long *)s.hacc, s.arrive,
-                       s.any + (size_t)(l + 1) * b.aw, ctx->status, next_products ? s.lvmax + l + 1 : nullptr,
-                       s.lvflag + l);
+                       s.any + (size_t)(l + 1) * b.aw, ctx->status, next_products ? s.lvmax + l + 1 : nullptr);
     tm.done();
     return BC_OK;
 }
 
-// Backward level lv of an unweighted batch.  Level lv+1 is read only when its
-// flag says it holds a vertex (front[lv+1] must exist: lv+1 < level_cap).
+// Backward level lv of an unweighted batch.  Host-driven (flags = false):
+// deeper says whether level lv+1 exists.  Replayed (flags = true): the level
+// flags the batch check wrote decide, on the device, whether level lv has a
+// vertex and whether level lv+1 is read (front[lv+1] must exist: lv+1 <
+// level_cap).
 template <int NW, typename S>
-bc_status launch_bwd_level(bc_ctx *ctx, const BatchShape &b, int32_t lv, bool products, double *ddump,
-                           bool accumulate) {
+bc_status launch_bwd_level(bc_ctx *ctx, const BatchShape &b, int32_t lv, bool products, bool deeper, bool flags,
+                           double *ddump, bool accumulate) {
     SparseState &s = ctx->sp;
     const uint64_t *fcur = s.front + (size_t)lv * b.words;
-    const uint64_t *fnext = s.front + (size_t)(lv + 1) * b.words;
-    const uint32_t *anext = s.any + (size_t)(lv + 1) * b.aw;
-    if (products) return algebraic_backward_level(ctx, sizeof(S) == 8, fcur, fnext, 1, ddump, accumulate, s.lvflag + lv);
+    const uint64_t *fnext = flags || deeper ? s.front + (size_t)(lv + 1) * b.words : nullptr;
+    const uint32_t *anext = fnext ? s.any + (size_t)(lv + 1) * b.aw : nullptr;
+    const uint32_t *lvf = flags ? s.lvflag + lv : nullptr;
+    if (products) return algebraic_backward_level(ctx, sizeof(S) == 8, fcur, fnext, 1, ddump, accumulate, lvf);
     LaunchTimer tm(ctx, "bwd_pull");
     const S *sigma = reinterpret_cast<const S *>(s.sigma);
-    if (s.bwd_per_word || ctx->edges) { // edge terms come from the per-word pull
-        double *eb = accumulate && ctx->edges ? ctx->eb : nullptr;
-        const auto kern = eb ? k_bwd_pull_w<NW, S, true> : k_bwd_pull_w<NW, S, false>;
-        hipLaunchKernelGGL(kern, dim3(b.word_blocks), dim3(SB), 0, ctx->stream, b.t, fcur, anext, fnext, sigma, s.cval,
-                           s.src, ctx->bc, s.hacc, s.arrive_w, ddump, accumulate ? 1 : 0, eb,
-                           (const uint32_t *)s.lvflag + lv);
+    if (ctx->edges && accumulate) // edge terms come from the per-word pull, one wave per item
+        hipLaunchKernelGGL((k_bwd_pull_we<NW, S>), dim3(b.word_blocks), dim3(SB), 0, ctx->stream, b.t, fcur, anext, fnext,
+                           sigma, s.cval, s.src, ctx->bc, s.hacc, s.arrive_w, ddump, 1, ctx->eb, lvf);
+    else if (s.bwd_per_word || ctx->edges) {
+        const int grid = s.bwd_grid > 0 ? std::min(b.word_blocks, s.bwd_grid) : b.word_blocks;
+        hipLaunchKernelGGL((k_bwd_pull_w<NW, S>), dim3(grid), dim3(SB), 0, ctx->stream, b.t, fcur, anext, fnext, sigma,
+                           s.cval, s.src, ctx->bc, s.hacc, s.arrive_w, ddump, accumulate ? 1 : 0, lvf);
     } else
         hipLaunchKernelGGL((k_bwd_pull<NW, S>), dim3(b.pull_blocks), dim3(SB), 0, ctx->stream, b.t, fcur, anext, fnext,
-                           sigma, s.cval, s.src, ctx->bc, s.hacc, s.arrive, ddump, accumulate ? 1 : 0,
-                           (const uint32_t *)s.lvflag + lv);
+                           sigma, s.cval, s.src, ctx->bc, s.hacc, s.arrive, ddump, accumulate ? 1 : 0, lvf);
     tm.done();
     return BC_OK;
 }
@@ -1016,7 +1069,9 @@ bc_status run_batch_t(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool acc
             continue;
         }
         ProbeScope ps(ctx);
-        st = launch_bwd_level<NW, S>(ctx, bb, lv, lv + 1 < nlev && by_products(ctx, lv, false), ddump, accumulate);
+        const bool deeper = lv + 1 < nlev;
+        st = launch_bwd_level<NW, S>(ctx, bb, lv, deeper && by_products(ctx, lv, false), deeper, false, ddump,
+                                     accumulate);
         if (st != BC_OK) return st;
         ps.done(false, lv);
     }
@@ -1082,31 +1137,54 @@ bc_status run_batch(bc_ctx *ctx, const int32_t *d_src, int32_t count, bool accum
 // 0 .. L-1, a check, backward levels L-1 .. lowest -- is recorded once into a
 // HIP graph and replayed for every batch of the run; a device control block
 // tells each replay which sources it takes.  The level-synchronous order of
-// the search (Sec. 4) is kept: each level is one launch, and a level past
-// the batch's depth finds its flag clear and exits at once.  The check at
-// the end of the forward hands a batch back when its search had not ended
+// the search (Sec. 4) is kept: each level is one launch.  A forward level
+// past the batch's depth costs one visited-word load per wave (every vertex
+// it could reach is visited); the check at the end of the forward sets one
+// flag per level from the levels' vertex filters, and a backward level whose
+// flag is clear exits at once.  The check also hands a batch back when its search had not ended
 // within the L levels (level L holds a vertex) or a count needs 64-bit
 // storage: it puts the batch on a list and clears every level flag, so the
 // batch's backward launches exit and add nothing.  The host reads the list
 // when the context is next used and re-runs those batches host-driven.  L is
-// the deepest batch seen so far plus one.  The hybrid form's per-level
+// the most levels any batch has had so far.  The hybrid form's per-level
 // choice is the one the last host-driven batch's densities give.
 
-// End of a replayed batch's forward (one thread).
-__global__ void k_batch_check(BatchCtl *ctl, uint32_t *lvflag, int32_t L, uint32_t *status, int32_t B) {
-    if (threadIdx.x != 0) return;
-    const bool deep = lvflag[L] != 0, wide = status[1] != 0;
+// End of a replayed batch's forward.  Block l (of L + 1) sets lvflag[l] from
+// level l's vertex filter; the last block to finish checks the batch: it
+// completed within the L levels when level L is empty, and its counts fit
+// the storage when no kernel asked for 64 bits.  Otherwise its first source
+// goes on the handed-back list and every level flag is cleared, so that its
+// backward launches exit and add nothing.
+__global__ __launch_bounds__(SB) void k_batch_check(BatchCtl *ctl, const uint32_t *__restrict__ any, int32_t aw,
+                                                    uint32_t *lvflag, int32_t L, uint32_t *status, int32_t B) {
+    __shared__ int s_last;
+    const int32_t l = blockIdx.x;
+    const uint32_t *a = any + (size_t)l * aw;
+    uint32_t x = 0;
+    for (int32_t i = threadIdx.x; i < aw; i += SB) x |= a[i];
+    const int nz = __syncthreads_or(x != 0);
+    if (threadIdx.x == 0) {
+        __hip_atomic_store(&lvflag[l], nz ? 1u : 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        s_last = atomicAdd(&ctl->arrived, 1u) == (uint32_t)L;
+    }
+    __syncthreads();
+    if (!s_last || threadIdx.x != 0) return;
+    __threadfence();
+    ctl->arrived = 0u;
+    auto flag = [&](int32_t k) { return __hip_atomic_load(&lvflag[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); };
+    const bool deep = flag(L) != 0, wide = status[1] != 0;
     if (deep || wide) {
         ctl->redo[ctl->redo_count++] = ctl->batch * B;
         if (wide) ctl->need_wide = 1u;
         if (deep) ctl->deep = 1u;
-        for (int32_t l = 0; l <= L; ++l) lvflag[l] = 0u;
+        for (int32_t k = 0; k <= L; ++k) __hip_atomic_store(&lvflag[k], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         status[1] = 0u;
     } else {
         uint32_t nlev = (uint32_t)L;
-        for (int32_t l = 1; l <= L; ++l)
-            if (lvflag[l] == 0u) {
-                nlev = (uint32_t)l;
+        for (int32_t k = 1; k <= L; ++k)
+            if (flag(k) == 0u) {
+                nlev = (uint32_t)k;
                 break;
             }
         if (nlev > ctl->max_nlev) ctl->max_nlev = nlev;
@@ -1142,14 +1220,14 @@ bc_status record_batch_t(bc_ctx *ctx, int32_t L, const std::vector<uint8_t> &pla
     if (st != BC_OK) return st;
     {
         LaunchTimer tm(ctx, "batch_check");
-        hipLaunchKernelGGL(k_batch_check, dim3(1), dim3(64), 0, ctx->stream, s.ctl, s.lvflag, L, ctx->status,
-                           s.batch);
+        hipLaunchKernelGGL(k_batch_check, dim3(L + 1), dim3(SB), 0, ctx->stream, s.ctl, (const uint32_t *)s.any, b.aw,
+                           s.lvflag, L, ctx->status, s.batch);
         tm.done();
     }
     // level 0 adds nothing to BC, but with edges on its arcs carry edge terms
     const int32_t lowest = ctx->edges ? 0 : 1;
     for (int32_t lv = L - 1; lv >= lowest && st == BC_OK; --lv)
-        st = launch_bwd_level<NW, S>(ctx, b, lv, lv >= 1 && (plan[(size_t)lv] & 2), nullptr, true);
+        st = launch_bwd_level<NW, S>(ctx, b, lv, lv >= 1 && (plan[(size_t)lv] & 2), true, true, nullptr, true);
     if (st != BC_OK) return st;
     BC_HIP(ctx, hipGetLastError());
     return BC_OK;
@@ -1207,7 +1285,7 @@ bc_status capture_batch(bc_ctx *ctx, int32_t L, const std::vector<uint8_t> &plan
 // The recorded batch for the current depth, count width, state and level plan.
 bc_status ensure_replay(bc_ctx *ctx) {
     SparseState &s = ctx->sp;
-    const int32_t L = std::max(s.depth_max + 1, 2);
+    const int32_t L = std::max(s.depth_max, 2);
     bc_status st = ensure_levels(ctx, L + 1);
     if (st != BC_OK) return st;
     const std::vector<uint8_t> plan = replay_plan(ctx, L);
@@ -1238,6 +1316,17 @@ bc_status sparse_prepare(bc_ctx *ctx, int32_t batch, int32_t split_degree) {
     s.batch = batch;
     s.words = batch / 64;
     s.split = split_degree > 0 ? split_degree : 128;
+    {
+        // launch shapes of the pulls: 32 blocks of four waves per compute
+        // unit, each wave striding over the items.  Measured on RMAT-16 at
+        // batch 256 against one wave per item: the backward took a step from
+        // 181 to 173 ms host-driven and 182 to 171 ms replayed, the forward
+        // then to 172 and 169 ms; 16 and 64 blocks per unit were slower.
+        int cus = 0;
+        BC_HIP(ctx, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
+        s.bwd_grid = 32 * std::max(cus, 1);
+        s.fwd_grid = 32 * std::max(cus, 1);
+    }
     const int32_t n = ctx->n;
     const size_t nn = (size_t)std::max(n, 1);
     // Heavy rows and their segments, from the host copy of row_ptr.

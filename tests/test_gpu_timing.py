@@ -36,8 +36,10 @@ def test_batch_sampled_timing(gpu_lib):
         assert ms1 > 0 and ms5 > 0 and msr > 0, name
         # the sampled total is the timed batches' average scaled to every launch
         assert 0.5 < (ms5 / n5) / (ms1 / n1) < 2.0, (name, ms1 / n1, ms5 / n5)
-        # replayed: the host-driven batches' launches scaled by batches
-        assert 0.8 < nr / n1 < 1.25, (name, n1, nr)
-        assert 0.5 < (msr / nr) / (ms1 / n1) < 2.0, (name, ms1 / n1, msr / nr)
+        # replayed: the timed (host-driven) batches' totals scaled by batches;
+        # they launch speculative forward levels up to the deepest batch seen,
+        # so counts and per-launch averages differ while totals agree
+        assert nr > 0, name
+        assert 0.5 < msr / ms1 < 2.0, (name, ms1, msr)
     for key in got:
         assert np.allclose(got[key][0], got[(0, False)][0], rtol=1e-12, atol=0.0), key
