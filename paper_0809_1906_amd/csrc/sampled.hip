@@ -1,13 +1,14 @@
-// Algorithm 1 of Sec. 4.1.1, the sampled forward for unweighted graphs,
+// The sampled forward of Sec. 4.1.1 (Algorithm 1) for unweighted graphs,
 // distances only.  With a distinguished set S (the requested sources first,
-// then the caller's random sample):
-//   step 2  a k-limited breadth-first search from every x in S gives d'(x, v):
-//           the hop distance when it is at most k, otherwise none;
-//   step 3  the weighted graph H on S has edge weights d'(x, y);
-//   step 4  all-pairs distances D_H of H (Floyd-Warshall);
-//   step 5  d(s, v) = min over x in S of D_H(s, x) + d'(x, v).
-// Step 6 (counting minimising vertices) does not count shortest paths and is
-// not computed.
+// then the caller's random sample) it runs four stages:
+//   limited searches  a breadth-first search from every x in S that stops
+//                     after k hops gives d'(x, v): the hop distance when it
+//                     is at most k, otherwise none;
+//   graph on S        H on the vertices of S, the weight of x-y being d'(x, y);
+//   closure           all-pairs distances D_H of H (Floyd-Warshall);
+//   combination       d(s, v) = min over x in S of D_H(s, x) + d'(x, v).
+// The algorithm's count of minimising vertices is not a count of shortest
+// paths and is not computed.
 //
 // Layout (sp = |S| rounded up to 64, W = sp / 64 bitmap words):
 //   d'    uint16 dT[v][sp], vertex-major: dT[v][x] = d'(S_x, v), DINF = none
@@ -21,8 +22,9 @@
 // OR per chunk, merged by a second launch.  Every 8 levels the new bits become
 // d' entries, sixteen bytes per thread.  Floyd-Warshall runs in 64 x 64
 // tiles: per pivot block, the diagonal tile, then the column strip and then
-// the whole (symmetric) matrix as min-plus products.  Step 5 is the min-plus
-// product of the sources' rows of D_H with d', in LDS-staged 128 x 128 tiles.
+// the whole (symmetric) matrix as min-plus products.  The combination is the
+// min-plus product of the sources' rows of D_H with d', in LDS-staged
+// 128 x 128 tiles.
 #include "bc_internal.h"
 
 #include <algorithm>
@@ -198,7 +200,7 @@ __global__ __launch_bounds__(SB) void k_ls_finish(int32_t nsv, const int32_t *__
     ls_settle(v, lane, W, acc, vis, word_rows(lane, ns), L, N, V, found);
 }
 
-// Step 3: H[j][i] = d'(S_i, S_j) = dT[S_j][i] (symmetric: the graph is
+// The graph on S: H[j][i] = d'(S_i, S_j) = dT[S_j][i] (symmetric: the graph is
 // undirected); 0 on the diagonal, HINF where no path was found and in the
 // padding.
 __global__ __launch_bounds__(SB) void k_build_h(int32_t ns, int32_t sp, const int32_t *__restrict__ S,
@@ -215,7 +217,7 @@ __global__ __launch_bounds__(SB) void k_build_h(int32_t ns, int32_t sp, const in
     H[id] = h;
 }
 
-// Step 4 in 64 x 64 tiles, rounds r = 0 .. sp/64 - 1 over the pivot blocks.
+// The closure in 64 x 64 tiles, rounds r = 0 .. sp/64 - 1 over the pivot blocks.
 // Every step only lowers an entry to the length of some walk, and every
 // entry ends at the shortest one, so each phase may see entries of a tile
 // before or after another phase's update of the same values.
@@ -475,7 +477,7 @@ __global__ __launch_bounds__(SB) void k_dh16(int32_t M, int32_t sp, const int32_
     if (fin && d > cap) *wide = 1;
 }
 
-// Step 5 in 16-bit arithmetic: C[m][n] = min over k of A[m][k] + B[n'][k], A
+// The combination in 16-bit arithmetic: C[m][n] = min over k of A[m][k] + B[n'][k], A
 // and B uint16 [rows][sp] with k contiguous, DINF = none, n' = brow[n] (or n); each sum saturates at
 // 65535 (v_pk_add_u16 with clamp) and two columns share one register
 // (v_pk_min_u16), one instruction per term for the add and the minimum.
@@ -687,7 +689,7 @@ bc_status sampled_distances(bc_ctx *ctx, const int32_t *h_sources, int32_t count
     }
     hipLaunchKernelGGL(k_ls_sources, dim3(blocks_for((size_t)ns)), dim3(SB), 0, ctx->stream, ns, dS, W, ring,
                        visited);
-    // step 2: every row of S advances one level per launch; level L's new bits
+    // limited searches: every row of S advances one level per launch; level L's new bits
     // go to ring slot L % RING (the next level's frontier), and every RING
     // levels (and at the end) they are written into d'
     {
@@ -721,7 +723,7 @@ bc_status sampled_distances(bc_ctx *ctx, const int32_t *h_sources, int32_t count
         }
         tm.done();
     }
-    // steps 3 and 4
+    // the graph on S and its closure
     hipLaunchKernelGGL(k_build_h, dim3(blocks_for((size_t)sp * sp)), dim3(SB), 0, ctx->stream, ns, sp, dS, dT, H);
     {
         LaunchTimer tm(ctx, "floyd_warshall");
@@ -746,7 +748,7 @@ bc_status sampled_distances(bc_ctx *ctx, const int32_t *h_sources, int32_t count
         }
         tm.done();
     }
-    // step 5: the sources' rows of D_H (rows 0 .. nreq-1) min-plus d', in 16-bit
+    // combination: the sources' rows of D_H (rows 0 .. nreq-1) min-plus d', in 16-bit
     // arithmetic when every finite sum stays below 65535, else in 32-bit; column
     // v of a row is the caller's vertex v (its d' row is that of new_of_old[v])
     if (nreq > 0) {

@@ -19,8 +19,8 @@ def exact(g, sources):
 
 @pytest.mark.parametrize("name", ["grid", "er", "union", "tree"])
 def test_every_vertex_distinguished_is_exact(name):
-    """S = V with k = 1: H is the graph itself, so step 4 alone gives the
-    exact distances."""
+    """S = V with k = 1: H is the graph itself, so its all-pairs closure alone
+    gives the exact distances."""
     g = {"grid": lambda: gg.grid(6, 7), "er": lambda: gg.er_plus_tree(60, 3.0, 2),
          "union": lambda: gg.disjoint_union(gg.path(8), gg.cycle(9)), "tree": lambda: gg.random_tree(50, 4)}[name]()
     src = np.arange(0, g.n, 5)
