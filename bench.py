@@ -285,29 +285,26 @@ def roofline(name, wl, kern, info, steps):
         # with weights 1..M a product runs over K = M * npad (one class each)
         wts = getattr(wl["graph"], "weight", None)
         classes = int(wts.max()) if wts is not None and wts.size else 1
-        # a backward launch is three coefficient planes; a forward launch loops
-        # over its level's 8-bit limbs, counted by the library (mfma_planes)
-        bwd_launches = kern.get("mfma_bwd", (0.0, 0))[1]
-        planes = 3 * launches if dom == "mfma_bwd" else max(info.mfma_planes - 3 * bwd_launches, launches)
-        flops = 2.0 * info.batch * npad * npad * classes * planes
-        base["weight_classes"] = classes
-        # k-tiles whose every plane was zero are skipped; the flops above are
-        # the dense products' (the metric's "issued dense products"), and
-        # frac_executed scales them by this kernel's share of k-tiles run
+        # the library counts k-tiles of 2^20 flops (one plane's 32 k by 128
+        # rows by 128 sources): those multiplied, and those the issued
+        # products cover (the rest skipped, every plane's k-tile zero); both
+        # count every batch of the timed steps, replayed or host-driven
         if dom == "mfma_fwd":
             run, dense = info.mfma_ktiles_run_fwd, info.mfma_ktiles_dense_fwd
         else:
             run = info.mfma_ktiles_run - info.mfma_ktiles_run_fwd
             dense = info.mfma_ktiles_dense - info.mfma_ktiles_dense_fwd
-        ach = flops / (ms * 1e-3) / 1e12
-        if dense > 0:
-            base["k_tiles_skipped_frac"] = 1.0 - run / dense
-            base["frac_executed"] = ach / MFMA_BF16_PEAK_TFS * run / dense
+        executed, issued = float(run) * 2.0 ** 20, float(dense) * 2.0 ** 20
+        ach = executed / (ms * 1e-3) / 1e12
+        base["weight_classes"] = classes
+        base["k_tiles_skipped_frac"] = 1.0 - run / dense if dense else 0.0
+        base["issued_dense_tflops"] = issued / (ms * 1e-3) / 1e12
         return dict(base, bound="mfma", achieved=ach, peak=MFMA_BF16_PEAK_TFS, unit="TFLOP/s",
                     frac=ach / MFMA_BF16_PEAK_TFS, traffic=None,
-                    alg_flops_per_launch=flops / max(launches, 1),
-                    planes=planes, note="issued dense products: 2 * batch * npad * (M * npad) per limb or "
-                                        "coefficient plane, M weight classes")
+                    alg_flops_per_launch=executed / max(launches, 1),
+                    planes_equivalent=issued / (2.0 * info.batch * npad * npad * classes),
+                    note="executed products: 2^20 flops per k-tile multiplied (one plane's 32 k x 128 rows x "
+                         "128 sources); issued_dense_tflops counts the skipped all-zero k-tiles too")
     if dom == "weighted_sweep":
         total = float(S) * steps * weighted_bytes(n, m)
     elif dom == "multigraph_sweep":
@@ -639,7 +636,7 @@ def main():
             err = float(np.max(np.abs(per_main - per_c) / np.maximum(np.abs(per_c), 1.0)))
             compare[cform] = {"value": work / cdt, "ms_per_step": cdt * 1e3, "batch": cinfo.batch,
                               "kernel_ms": ckern, "max_rel_diff_vs_measured": err}
-            if cform == "plain" and not getattr(wl["graph"], "weight", None) is not None:
+            if cform == "plain" and getattr(wl["graph"], "weight", None) is None:
                 # the per-source byte model of both passes over the step time
                 model = float(wl["S"]) * 2 * pass_bytes(wl["n"], wl["m"])
                 compare[cform]["roofline_model_frac"] = model / cdt / 1e9 / HBM_PEAK_GBS
@@ -687,6 +684,18 @@ def main():
         if form == "hybrid" and info.mfma_planes == 0:
             config["mfma_note"] = ("the tuner measured every level faster by CSR pulls on this graph, so no "
                                    "level ran as an MFMA product in the timed steps")
+        if info.mfma_fwd_rows:
+            config["mfma_fwd_rows"] = int(info.mfma_fwd_rows)
+    if form == "many":
+        config["unit_sources"] = int(info.batch)
+        config["tune_source"] = ["default", "measured", "cached"][info.tune_source]
+    if getattr(wl["graph"], "weight", None) is not None and form == "plain":
+        config["bucket_width"] = 1
+        config["bucket_note"] = (
+            "Delta = 1 (one bucket per distance value, Dial order) is a reading, not a tuned value: counts "
+            "sum over predecessors at exactly d(v) - w(u,v), so a wider bucket still needs one phase per "
+            "distinct distance and only adds re-relaxations, and the sweep is bound by random sector "
+            "reads of the distance arrays that every re-relaxation adds to")
     out = {
         "metric": METRIC if args.workload == "rmat16" else f"BC TEPS (sources·m/s) on {args.workload}",
         "value": work / dt,

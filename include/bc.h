@@ -154,11 +154,14 @@ typedef struct {
                              a ring of 2^arena_log2 entries (0 = default, max(4n, 2^16)
                              rounded up); a source that outgrows it is re-run with a
                              ring of nnz entries, so results never depend on it */
-    const char *tune_cache; /* sparse and hybrid forms: path of a text file of
-                             tuning results keyed by the graph's shape (n, m,
-                             degree histogram), the form, the requested batch and
-                             the device; a hit skips calibration, a miss appends
-                             the measured result.  NULL = this process only. */
+    const char *tune_cache; /* sparse, hybrid and algebraic forms and
+                             bc_create_many: path of a text file of tuning
+                             results keyed by the graph's shape (n, m, degree
+                             histogram; for many graphs, the histograms of their
+                             sizes), the form, the requested batch and the
+                             device; a hit skips calibration, a miss appends the
+                             result (measured, or measured earlier in this
+                             process).  NULL = this process only. */
     int32_t grid;         /* plain form (unit and integer weights): persistent
                              workgroups, each running one source at a time;
                              0 = default (the most that fit a workspace budget,
@@ -212,7 +215,9 @@ bc_status bc_create(const bc_graph *g, const bc_options *opt, bc_ctx **out);
  * The graphs are concatenated: vertex v of graph g has id
  * (n_0 + ... + n_{g-1}) + v, and bc_read returns BC in that numbering
  * (sum of n_g doubles).  opt->batch, when nonzero, is the number of sources
- * one work unit takes (default 64).  bc_run accepts only "every vertex"
+ * one work unit takes; 0 = tuned (timed launches over a sample of the graphs
+ * choose among 16, 32, 64, 128 and 256; 64 when the graphs hold under 2048
+ * vertices in all).  bc_run accepts only "every vertex"
  * (NULL, -1): it runs one persistent launch over a work queue of
  * (graph, source range) units, largest graphs first, recorded once into a HIP
  * graph and replayed.  bc_read_sssp takes ids in the concatenated numbering.
@@ -350,7 +355,8 @@ typedef struct {
     int32_t max_degree;
     int32_t weighted;    /* 1 when the graph carries weights */
     bc_form form;        /* the form in use (never BC_FORM_AUTO) */
-    int32_t batch;       /* sources per batch (1 for the plain form) */
+    int32_t batch;       /* sources per batch (1 for the plain form; sources
+                            per work unit for bc_create_many) */
     int32_t max_levels;  /* deepest level (or distinct distance count) seen + 1 */
     int64_t sources_run; /* sources accumulated since create / reset */
     int64_t device_bytes;/* device memory the context holds */
@@ -358,18 +364,30 @@ typedef struct {
                                 density(l) >= this (above 1: never) */
     double mfma_density_bwd; /* hybrid form: backward level l by products when
                                 density(l) >= this (above 1: never) */
-    int32_t tune_source;     /* BC_TUNE_* for the batch width and thresholds */
+    int32_t tune_source;     /* BC_TUNE_* for the tuned choices: batch width and
+                                thresholds (sparse, hybrid), forward block rows
+                                (algebraic, hybrid), sources per work unit
+                                (bc_create_many) */
     int64_t mfma_planes;     /* products with the adjacency issued since create /
                                 reset: one per 8-bit limb of a forward level, three
-                                per backward level; each is batch * npad^2
-                                multiply-adds, 2 * batch * npad^2 flops (npad = n
-                                rounded up to 256) */
-    int64_t mfma_ktiles_run;   /* k-tiles (32 rows of the adjacency by 128 sources)
-                                  multiplied by those products */
-    int64_t mfma_ktiles_dense; /* k-tiles a dense product would multiply; the
-                                  difference was skipped, every plane's tile zero */
+                                per backward level; each is batch * npad * K
+                                multiply-adds, 2 * batch * npad * K flops (npad = n
+                                rounded up to 256; K = npad, or M * npad with
+                                weights 1..M) */
+    int64_t mfma_ktiles_run;   /* k-tiles multiplied by those products; a k-tile is
+                                  one plane's 32 adjacency columns (k) by 128
+                                  adjacency rows by 128 sources, 2^20 flops, so
+                                  executed flops = 2^20 * mfma_ktiles_run */
+    int64_t mfma_ktiles_dense; /* k-tiles the issued products cover (2^20 *
+                                  mfma_ktiles_dense = mfma_planes * 2 * batch *
+                                  npad * K); the difference was skipped, every
+                                  plane's k-tile zero */
     int64_t mfma_ktiles_run_fwd;   /* the forward products' share of mfma_ktiles_run */
     int64_t mfma_ktiles_dense_fwd; /* the forward products' share of mfma_ktiles_dense */
+    int32_t mfma_fwd_rows;   /* algebraic and hybrid forms: adjacency rows per
+                                workgroup of the forward products (128 or 256;
+                                timed at create, see tune_source); 0 when the
+                                context has no products */
 } bc_info;
 
 /* Fills *out; synchronises the context's stream (mfma_planes and the k-tile

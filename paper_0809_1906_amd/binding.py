@@ -79,7 +79,7 @@ class bc_info(ctypes.Structure):
                 ("mfma_density_bwd", ctypes.c_double), ("tune_source", ctypes.c_int32),
                 ("mfma_planes", ctypes.c_int64), ("mfma_ktiles_run", ctypes.c_int64),
                 ("mfma_ktiles_dense", ctypes.c_int64), ("mfma_ktiles_run_fwd", ctypes.c_int64),
-                ("mfma_ktiles_dense_fwd", ctypes.c_int64)]
+                ("mfma_ktiles_dense_fwd", ctypes.c_int64), ("mfma_fwd_rows", ctypes.c_int32)]
 
 
 # Every symbol include/bc.h declares, with its ctypes signature.

@@ -136,10 +136,11 @@ constexpr int lds_x() { return NP * (KS / 8) * GN * 8; }
 constexpr int FWD_KS = 128;
 constexpr int BWD_KS = 64;
 // Block rows (BM, a multiple of 128; 2 BM threads, waves of 64 x 64 in BM / 64
-// rows by 2 columns).  A 256-row forward block (8 waves, 102 KB of LDS, one
-// per compute unit; 1.37 times the flops per operand byte) measured no faster:
-// 504 against 490 us per ER-16384 launch.
-constexpr int FWD_BM = 128;
+// rows by 2 columns).  The forward product runs 128-row blocks (67.6 KB of
+// LDS, two per compute unit) or 256-row blocks (8 waves, 102 KB, one per
+// unit, 1.37 times the flops per operand byte), whichever the tuner measured
+// faster on the graph (AlgebraicState::fwd_rows); on ER-16384 the two were
+// within 3% (490 against 504 us per launch).
 constexpr int BWD_BM = GM;
 
 // One pipeline stage held in registers between its global loads and its LDS
@@ -310,8 +311,10 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, const __bf16 *plane
         ++done;
     }
     if (tid == 0 && g.ktiles) {
-        atomicAdd(&g.ktiles[0], (unsigned long long)done * TPS);
-        atomicAdd(&g.ktiles[1], (unsigned long long)(nks - ks0) * TPS);
+        // in units of one plane's 32 x 128 x 128 (k, rows, sources): 2^20 flops
+        constexpr unsigned long long U = (unsigned long long)NP * (BM / 128);
+        atomicAdd(&g.ktiles[0], (unsigned long long)done * TPS * U);
+        atomicAdd(&g.ktiles[1], (unsigned long long)(nks - ks0) * TPS * U);
     }
 }
 
@@ -645,8 +648,9 @@ GemmArgs gemm_args(bc_ctx *ctx, const __bf16 *planes, bool forward) {
     g.K = a.classes * a.npad;
     g.plane_elems = (size_t)g.K * ctx->sp.batch;
     g.ksplit = a.ksplit;
-    g.ntiles = (int32_t)(forward ? grid_blocks<FWD_BM>(a.npad, ctx->sp.batch)
-                                 : grid_blocks<BWD_BM>(a.npad, ctx->sp.batch));
+    g.ntiles = (int32_t)(!forward           ? grid_blocks<BWD_BM>(a.npad, ctx->sp.batch)
+                         : a.fwd_rows == 256 ? grid_blocks<256>(a.npad, ctx->sp.batch)
+                                             : grid_blocks<128>(a.npad, ctx->sp.batch));
     g.ws = a.ws;
     g.gate = nullptr;
     g.arrive = a.arrive;
@@ -680,20 +684,26 @@ bc_status algebraic_prepare(bc_ctx *ctx) {
     a.planes_issued = (unsigned long long *)bc_dalloc(ctx, 256);
     // Unweighted forward products over a long K (one npad per limb) with
     // fewer tiles than the compute units hold blocks at once (256 units, LDS
-    // for 256 / FWD_BM blocks each): two blocks per output tile, each over
-    // half of K, so that the grid fills the chip.  With a full chip of tiles
-    // the split measured slower (ER-16384, B = 512: 124 against 116 ms per
-    // step), and with weight classes too (K is M npad; 0.43 of BF16 against 0.50).
-    const size_t ntiles = grid_blocks<FWD_BM>(a.npad, B);
-    a.ksplit = a.classes == 1 && K / GK >= 256 && ntiles < (size_t)256 * (256 / FWD_BM) ? 2 : 1;
+    // for 256 / BM blocks each): two blocks per output tile, each over half
+    // of K, so that the grid fills the chip.  With a full chip of tiles the
+    // split measured slower (ER-16384, B = 512: 124 against 116 ms per step),
+    // and with weight classes too (K is M npad; 0.43 of BF16 against 0.50).
+    // The decision is the same for 128- and 256-row blocks (tiles halve as
+    // the blocks per unit do); the workspace takes the larger of the two
+    // (grids are rounded up to whole rounds of the eight XCDs).
+    a.fwd_rows = 128;
+    const size_t ntiles = grid_blocks<128>(a.npad, B), ntiles256 = grid_blocks<256>(a.npad, B);
+    const size_t ws_elems = std::max(ntiles * 2 * 64 * (2 * 128), ntiles256 * 2 * 64 * (2 * 256));
+    const size_t ntiles_max = std::max(ntiles, ntiles256);
+    a.ksplit = a.classes == 1 && K / GK >= 256 && ntiles < (size_t)256 * (256 / 128) ? 2 : 1;
     if (a.ksplit == 2) {
-        a.ws = (float *)bc_dalloc(ctx, (size_t)8 * ntiles * 2 * 64 * (2 * FWD_BM) * sizeof(float));
-        a.arrive = (uint32_t *)bc_dalloc(ctx, (size_t)8 * ntiles * sizeof(uint32_t));
+        a.ws = (float *)bc_dalloc(ctx, (size_t)8 * ws_elems * sizeof(float));
+        a.arrive = (uint32_t *)bc_dalloc(ctx, (size_t)8 * ntiles_max * sizeof(uint32_t));
     }
     if (!a.adj || !a.planes || !a.part || !a.kflags || !a.planes_issued ||
         (a.ksplit == 2 && (!a.ws || !a.arrive)))
         return bc_fail(ctx, BC_ERR_NOMEM, "algebraic form: allocation failed");
-    if (a.ksplit == 2) BC_HIP(ctx, hipMemsetAsync(a.arrive, 0, (size_t)8 * ntiles * sizeof(uint32_t), ctx->stream));
+    if (a.ksplit == 2) BC_HIP(ctx, hipMemsetAsync(a.arrive, 0, (size_t)8 * ntiles_max * sizeof(uint32_t), ctx->stream));
     BC_HIP(ctx, hipMemsetAsync(a.adj, 0, adj_bytes, ctx->stream));
     BC_HIP(ctx, hipMemsetAsync(a.planes_issued, 0, 5 * sizeof(unsigned long long), ctx->stream));
     if (ctx->n > 0)
@@ -748,8 +758,12 @@ bc_status algebraic_forward_level_t(bc_ctx *ctx, int32_t l) {
     e.planes_issued = a.planes_issued;
     const GemmArgs g = gemm_args(ctx, a.planes, true);
     LaunchTimer tm(ctx, "mfma_fwd");
-    hipLaunchKernelGGL((k_mfma_fwd<S, FWD_KS, FWD_BM>), dim3(grid_blocks<FWD_BM>(a.npad, s.batch) * a.ksplit),
-                       dim3(2 * FWD_BM), 0, ctx->stream, g, e);
+    if (a.fwd_rows == 256)
+        hipLaunchKernelGGL((k_mfma_fwd<S, FWD_KS, 256>), dim3(grid_blocks<256>(a.npad, s.batch) * a.ksplit),
+                           dim3(2 * 256), 0, ctx->stream, g, e);
+    else
+        hipLaunchKernelGGL((k_mfma_fwd<S, FWD_KS, 128>), dim3(grid_blocks<128>(a.npad, s.batch) * a.ksplit),
+                           dim3(2 * 128), 0, ctx->stream, g, e);
     tm.done();
     BC_HIP(ctx, hipGetLastError());
     return BC_OK;

@@ -466,12 +466,8 @@ bc_status bc_create(const bc_graph *g, const bc_options *opt_in, bc_ctx **out) {
 
     bc_status ps = BC_OK;
     if (form == BC_FORM_PLAIN_FP64) ps = plain_prepare(ctx);
-    else if (form == BC_FORM_SPARSE || form == BC_FORM_HYBRID) ps = tune_prepare(ctx, opt, form);
-    else if (form == BC_FORM_ALGEBRAIC) {
-        ps = sparse_prepare(ctx, opt.batch ? opt.batch : 256, opt.split_degree);
-        if (ps == BC_OK) ps = algebraic_prepare(ctx);
-        ctx->al.every_level = true;
-    }
+    else if (form == BC_FORM_SPARSE || form == BC_FORM_HYBRID || form == BC_FORM_ALGEBRAIC)
+        ps = tune_prepare(ctx, opt, form);
     if (ps != BC_OK) return bail(ps, ctx->err);
     if (hipStreamSynchronize(ctx->stream) != hipSuccess) return bail(BC_ERR_DEVICE, "stream synchronisation failed");
     *out = ctx;
@@ -567,7 +563,7 @@ bc_status bc_create_many(const bc_graph *gs, int32_t count, const bc_options *op
         hipMemsetAsync(ctx->bc, 0, sizeof(double) * nn, ctx->stream) != hipSuccess ||
         hipMemsetAsync(ctx->status, 0, 256, ctx->stream) != hipSuccess)
         return bail(BC_ERR_DEVICE, "uploading the graphs failed");
-    bc_status ps = multigraph_prepare(ctx, voff, rpoff, rp, opt.batch);
+    bc_status ps = tune_many(ctx, opt, voff, rpoff, rp);
     if (ps != BC_OK) return bail(ps, ctx->err);
     if (hipStreamSynchronize(ctx->stream) != hipSuccess) return bail(BC_ERR_DEVICE, "stream synchronisation failed");
     *out = ctx;
@@ -863,6 +859,7 @@ bc_status bc_get_info(const bc_ctx *ctx, bc_info *out) {
     out->mfma_density_fwd = every ? 0.0 : hybrid ? ctx->hy.theta_fwd : 2.0;
     out->mfma_density_bwd = every ? 0.0 : hybrid ? ctx->hy.theta_bwd : 2.0;
     out->tune_source = ctx->hy.tune_source;
+    out->mfma_fwd_rows = every || hybrid ? ctx->al.fwd_rows : 0;
     out->mfma_planes = ctx->poisoned ? 0 : algebraic_planes_issued(const_cast<bc_ctx *>(ctx));
     out->mfma_ktiles_run = out->mfma_ktiles_dense = out->mfma_ktiles_run_fwd = out->mfma_ktiles_dense_fwd = 0;
     if (!ctx->poisoned && !algebraic_ktiles(const_cast<bc_ctx *>(ctx), &out->mfma_ktiles_run, &out->mfma_ktiles_dense,

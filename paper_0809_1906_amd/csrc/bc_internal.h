@@ -91,6 +91,7 @@ struct AlgebraicState {
     uint32_t *kflags = nullptr;        // [M npad/32][batch/128] non-empty k-tiles
     unsigned long long *planes_issued = nullptr; // products issued (limb or coefficient planes)
     int32_t ksplit = 1;                // forward products: blocks per output tile, each over a share of K
+    int32_t fwd_rows = 128;            // forward products: rows per block, 128 or 256 (tuned)
     float *ws = nullptr;               // [8 limbs][tiles][2 halves][64][256] partial sums of split tiles
     uint32_t *arrive = nullptr;        // [8 limbs][tiles] halves arrived
     bool every_level = false;          // the algebraic form: every level l >= 1 by products
@@ -159,6 +160,8 @@ struct MultiState {
     int32_t *redo = nullptr;          // compact units handed back to the full sweep
     unsigned int *next = nullptr;     // queue counters: compact, full, redo; [3] = redo count
     std::vector<int32_t> h_voff;
+    std::vector<int32_t> h_arcs;      // arcs of each graph
+    std::vector<int32_t> h_order;     // graphs by n_g descending (stable)
     hipStream_t stream = nullptr;     // private stream the launch is captured on
     hipEvent_t ev = nullptr;
     hipGraphExec_t exec = nullptr;    // captured reset + persistent sweep
@@ -301,6 +304,9 @@ bc_status weighted_run(bc_ctx *ctx, const int32_t *d_sources, int64_t count, boo
 bc_status multigraph_prepare(bc_ctx *ctx, const std::vector<int32_t> &voff, const std::vector<int32_t> &rpoff,
                              const std::vector<int32_t> &rp, int32_t chunk);
 bc_status multigraph_run(bc_ctx *ctx);
+// Rebuilds the work queue over `graphs` (ids in h_order's order; null = every
+// graph) at `chunk` sources per unit; the next run records its launches anew.
+bc_status multigraph_set_queue(bc_ctx *ctx, const std::vector<int32_t> *graphs, int32_t chunk);
 // units: 3 * count int32 of device staging, or nullptr to allocate it
 bc_status multigraph_dump(bc_ctx *ctx, const int32_t *h_sources, int32_t count, int32_t *dist_dump,
                           uint64_t *sigma_dump, double *delta_dump, int32_t *units = nullptr);
@@ -355,6 +361,11 @@ bc_status sampled_distances(bc_ctx *ctx, const int32_t *h_sources, int32_t count
 bc_status allpairs_bc(bc_ctx *ctx, double *bc_internal);
 
 // ---- tuning (tune.cpp) ----------------------------------------------------------
-// Prepares the sparse or hybrid form: batch width and hybrid thresholds come
-// from opt, from the tuning cache, or from timed calibration batches.
+// Prepares the sparse, hybrid or algebraic form: batch width, hybrid
+// thresholds and forward block rows come from opt, from the tuning cache, or
+// from timed calibration batches.
 bc_status tune_prepare(bc_ctx *ctx, const bc_options &opt, bc_form form);
+// Prepares bc_create_many's work queue; the sources per unit come from opt,
+// from the tuning cache, or from timed launches over a sample of the graphs.
+bc_status tune_many(bc_ctx *ctx, const bc_options &opt, const std::vector<int32_t> &voff,
+                    const std::vector<int32_t> &rpoff, const std::vector<int32_t> &rp);

@@ -403,45 +403,65 @@ bc_status multigraph_prepare(bc_ctx *ctx, const std::vector<int32_t> &voff, cons
     MultiState &m = ctx->mg;
     const int32_t ng = (int32_t)voff.size() - 1;
     m.ngraphs = ng;
-    m.chunk = chunk > 0 ? chunk : 64;
     m.h_voff = voff;
-    // units sorted by n_g^2 descending (stable: ties keep graph order)
-    std::vector<int32_t> order((size_t)ng);
-    for (int32_t g = 0; g < ng; ++g) order[(size_t)g] = g;
-    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+    m.h_arcs.assign((size_t)ng, 0);
+    for (int32_t g = 0; g < ng; ++g) {
+        const int32_t n = voff[g + 1] - voff[g];
+        m.h_arcs[(size_t)g] = rp[(size_t)rpoff[(size_t)g] + n] - rp[(size_t)rpoff[(size_t)g]];
+    }
+    // graphs by n_g descending (stable: ties keep graph order)
+    m.h_order.resize((size_t)ng);
+    for (int32_t g = 0; g < ng; ++g) m.h_order[(size_t)g] = g;
+    std::stable_sort(m.h_order.begin(), m.h_order.end(), [&](int32_t x, int32_t y) {
         return voff[x + 1] - voff[x] > voff[y + 1] - voff[y];
     });
-    // the compact sweep's units first (graphs with at most 65535 arcs), then
-    // the others, each group longest first
-    std::vector<int32_t> units;
-    for (int pass = 0; pass < 2; ++pass) {
-        for (int32_t g : order) {
-            const int32_t n = voff[g + 1] - voff[g];
-            const int32_t arcs = rp[(size_t)rpoff[(size_t)g] + n] - rp[(size_t)rpoff[(size_t)g]];
-            if ((arcs <= 65535) != (pass == 0)) continue;
-            for (int32_t s0 = 0; s0 < n; s0 += m.chunk) {
-                units.push_back(g);
-                units.push_back(s0);
-                units.push_back(std::min(n, s0 + m.chunk));
-            }
-        }
-        if (pass == 0) m.ncompact = (int32_t)(units.size() / 3);
-    }
-    m.nunits = (int32_t)(units.size() / 3);
     m.voff = (int32_t *)bc_dalloc(ctx, voff.size() * sizeof(int32_t));
     m.rpoff = (int32_t *)bc_dalloc(ctx, std::max<size_t>(rpoff.size(), 1) * sizeof(int32_t));
     m.rp = (int32_t *)bc_dalloc(ctx, std::max<size_t>(rp.size(), 1) * sizeof(int32_t));
-    m.units = (int32_t *)bc_dalloc(ctx, std::max<size_t>(units.size(), 3) * sizeof(int32_t));
-    m.redo = (int32_t *)bc_dalloc(ctx, (size_t)std::max(m.ncompact, 1) * 3 * sizeof(int32_t));
     m.next = (unsigned int *)bc_dalloc(ctx, 256);
-    if (!m.voff || !m.rpoff || !m.rp || !m.units || !m.redo || !m.next)
-        return bc_fail(ctx, BC_ERR_NOMEM, "many graphs: allocation failed");
+    if (!m.voff || !m.rpoff || !m.rp || !m.next) return bc_fail(ctx, BC_ERR_NOMEM, "many graphs: allocation failed");
     BC_HIP(ctx, hipMemcpy(m.voff, voff.data(), voff.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     if (!rpoff.empty())
         BC_HIP(ctx, hipMemcpy(m.rpoff, rpoff.data(), rpoff.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     if (!rp.empty()) BC_HIP(ctx, hipMemcpy(m.rp, rp.data(), rp.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    return multigraph_set_queue(ctx, nullptr, chunk > 0 ? chunk : 64);
+}
+
+// Units (graph, s0, s1) of `chunk` sources: the compact sweep's graphs (at
+// most 65535 arcs) first, then the others, each group largest first.
+bc_status multigraph_set_queue(bc_ctx *ctx, const std::vector<int32_t> *graphs, int32_t chunk) {
+    MultiState &m = ctx->mg;
+    const std::vector<int32_t> &order = graphs ? *graphs : m.h_order;
+    std::vector<int32_t> units;
+    int32_t ncompact = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int32_t g : order) {
+            const int32_t n = m.h_voff[(size_t)g + 1] - m.h_voff[(size_t)g];
+            if ((m.h_arcs[(size_t)g] <= 65535) != (pass == 0)) continue;
+            for (int32_t s0 = 0; s0 < n; s0 += chunk) {
+                units.push_back(g);
+                units.push_back(s0);
+                units.push_back(std::min(n, s0 + chunk));
+            }
+        }
+        if (pass == 0) ncompact = (int32_t)(units.size() / 3);
+    }
+    if (m.exec) { // recorded with the old queue's addresses and sizes
+        BC_HIP(ctx, hipStreamSynchronize(m.stream));
+        BC_HIP(ctx, hipGraphExecDestroy(m.exec));
+        m.exec = nullptr;
+    }
+    BC_HIP(ctx, hipStreamSynchronize(ctx->stream)); // no launch still reads the old queue
+    if (m.units) bc_dfree(ctx, m.units);
+    if (m.redo) bc_dfree(ctx, m.redo);
+    m.units = (int32_t *)bc_dalloc(ctx, std::max<size_t>(units.size(), 3) * sizeof(int32_t));
+    m.redo = (int32_t *)bc_dalloc(ctx, (size_t)std::max(ncompact, 1) * 3 * sizeof(int32_t));
+    if (!m.units || !m.redo) return bc_fail(ctx, BC_ERR_NOMEM, "many graphs: allocation failed");
     if (!units.empty())
         BC_HIP(ctx, hipMemcpy(m.units, units.data(), units.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    m.chunk = chunk;
+    m.ncompact = ncompact;
+    m.nunits = (int32_t)(units.size() / 3);
     int cus = 0;
     BC_HIP(ctx, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
     m.grid = std::max(1, std::min(m.nunits, cus > 0 ? cus : 256));

@@ -1,17 +1,22 @@
-// Autotuning of the batched forms.
+// Autotuning of the batched forms and of the many-graph queue.
 //
 // The paper analyses one method at a time; choosing between them per level is
 // this library's own addition.  Before any timed work, the tuner fixes
-//   * the batch width B of the sparse and hybrid forms, and
+//   * the batch width B of the sparse and hybrid forms;
 //   * the hybrid form's two density thresholds: forward level l -> l+1 (and
 //     backward level l) is computed by products with the dense adjacency
 //     (Sec. 3.1) when the level's union-frontier density reaches the
-//     threshold, and by CSR pulls (the level sweep of Sec. 4) otherwise.
+//     threshold, and by CSR pulls (the level sweep of Sec. 4) otherwise;
+//   * the rows of the adjacency one workgroup of the forward products takes
+//     (128 or 256), for the algebraic form and a hybrid form with forward
+//     products;
+//   * the sources per work unit of bc_create_many's queue.
 // It measures calibration batches of sources drawn from the graph itself,
 // each width once with every level by pulls and once with every level >= 1 by
 // products, records every level's GPU time and density, and picks for each
 // direction the threshold that minimises the summed time of the recorded
-// levels.  Results are cached per process and, optionally, in a text file.
+// levels; block rows and unit sizes are timed over whole batches or
+// launches.  Results are cached per process and, optionally, in a text file.
 #include "bc_internal.h"
 
 #include <algorithm>
@@ -35,10 +40,13 @@ constexpr double kSyncMs = 0.02;                    // host round trip per level
 constexpr double kNever = 2.0;                      // a threshold no density reaches
 constexpr double kAccept = 0.97;                    // a mix must beat pulls by 3% to be kept
 constexpr int kConfirm = 3;                         // alternating whole-batch comparisons of a mix
+constexpr double kManySampleWork = 3e9;             // many graphs: sum of n_g (n_g + arcs_g) one timed launch takes
+const int32_t kUnitSizes[] = {16, 32, 64, 128, 256}; // many graphs: sources per work unit tried
 
 struct TuneResult {
-    int32_t batch;
+    int32_t batch; // sources per batch, or per work unit for many graphs
     double theta_fwd, theta_bwd;
+    int32_t fwd_rows; // forward product block rows; 0 = not recorded (128)
 };
 
 std::mutex g_mu;
@@ -50,31 +58,62 @@ uint64_t fnv1a(const void *p, size_t n, uint64_t h = 1469598103934665603ull) {
     return h;
 }
 
-// Graph shape key: n, m, the degree histogram in log2 buckets quantised to
-// 1/64 of the vertices, the form, the requested width, the row split and the
-// device.
-std::string make_key(const bc_ctx *ctx, bc_form form, int32_t req_batch, int32_t split) {
+// Values in log2 buckets, each bucket's share quantised to 1/64, hashed.
+uint64_t log2_histogram_hash(const std::vector<uint32_t> &vals) {
     int64_t hist[33] = {0};
-    const std::vector<int32_t> &rp = ctx->h_row_ptr;
-    for (int32_t v = 0; v < ctx->n; ++v) {
-        const uint32_t d = (uint32_t)(rp[(size_t)v + 1] - rp[(size_t)v]) + 1u;
-        ++hist[31 - __builtin_clz(d)];
-    }
+    for (uint32_t x : vals) ++hist[31 - __builtin_clz(x + 1u)];
     uint8_t q[33];
-    for (int k = 0; k < 33; ++k) q[k] = (uint8_t)std::lround(64.0 * (double)hist[k] / std::max(ctx->n, 1));
+    for (int k = 0; k < 33; ++k)
+        q[k] = (uint8_t)std::lround(64.0 * (double)hist[k] / (double)std::max<size_t>(vals.size(), 1));
+    return fnv1a(q, sizeof q);
+}
+
+std::string device_key(int device) {
     hipDeviceProp_t prop{};
-    if (hipGetDeviceProperties(&prop, ctx->device) != hipSuccess) std::strcpy(prop.gcnArchName, "unknown");
-    char buf[256];
-    std::snprintf(buf, sizeof buf, "n=%d m=%lld dh=%016llx form=%d batch=%d split=%d arch=%s cu=%d", ctx->n,
-                  (long long)ctx->nnz / 2, (unsigned long long)fnv1a(q, sizeof q), (int)form, req_batch, split,
-                  prop.gcnArchName, prop.multiProcessorCount);
-    for (char *c = buf; *c; ++c)
-        if (*c == '\t' || *c == '\n') *c = ' ';
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) std::strcpy(prop.gcnArchName, "unknown");
+    char buf[160];
+    std::snprintf(buf, sizeof buf, " arch=%s cu=%d", prop.gcnArchName, prop.multiProcessorCount);
     return buf;
 }
 
-// File format: one entry per line, "<key>\t<batch> <theta_fwd> <theta_bwd>";
-// the last entry for a key wins; lines starting with '#' are ignored.
+std::string clean_key(std::string k) {
+    for (char &c : k)
+        if (c == '\t' || c == '\n') c = ' ';
+    return k;
+}
+
+// Graph shape key: n, m, the largest weight (0 unweighted), the degree
+// histogram, the form, the requested width, the row split and the device.
+std::string make_key(const bc_ctx *ctx, bc_form form, int32_t req_batch, int32_t split) {
+    std::vector<uint32_t> deg((size_t)ctx->n);
+    const std::vector<int32_t> &rp = ctx->h_row_ptr;
+    for (int32_t v = 0; v < ctx->n; ++v) deg[(size_t)v] = (uint32_t)(rp[(size_t)v + 1] - rp[(size_t)v]);
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "n=%d m=%lld w=%u dh=%016llx form=%d batch=%d split=%d", ctx->n,
+                  (long long)ctx->nnz / 2, ctx->weighted ? ctx->max_weight : 0u,
+                  (unsigned long long)log2_histogram_hash(deg), (int)form, req_batch, split);
+    return clean_key(buf + device_key(ctx->device));
+}
+
+// Many graphs: their number, total vertices and arcs, and the histograms of
+// their vertex and arc counts.
+std::string make_many_key(const bc_ctx *ctx) {
+    const MultiState &m = ctx->mg;
+    std::vector<uint32_t> ns((size_t)m.ngraphs), arcs((size_t)m.ngraphs);
+    for (int32_t g = 0; g < m.ngraphs; ++g) {
+        ns[(size_t)g] = (uint32_t)(m.h_voff[(size_t)g + 1] - m.h_voff[(size_t)g]);
+        arcs[(size_t)g] = (uint32_t)m.h_arcs[(size_t)g];
+    }
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "many graphs=%d n=%d arcs=%lld nh=%016llx ah=%016llx form=%d batch=0", m.ngraphs,
+                  ctx->n, (long long)ctx->nnz, (unsigned long long)log2_histogram_hash(ns),
+                  (unsigned long long)log2_histogram_hash(arcs), (int)BC_FORM_MANY);
+    return clean_key(buf + device_key(ctx->device));
+}
+
+// File format: one entry per line,
+// "<key>\t<batch> <theta_fwd> <theta_bwd> [<fwd_rows>]"; the last entry for a
+// key wins; lines starting with '#' are ignored.
 bool file_lookup(const char *path, const std::string &key, TuneResult &out) {
     std::ifstream f(path);
     if (!f) return false;
@@ -87,6 +126,7 @@ bool file_lookup(const char *path, const std::string &key, TuneResult &out) {
         std::istringstream v(line.substr(tab + 1));
         TuneResult r{};
         if (v >> r.batch >> r.theta_fwd >> r.theta_bwd) {
+            if (!(v >> r.fwd_rows)) r.fwd_rows = 0;
             out = r;
             found = true;
         }
@@ -97,8 +137,30 @@ bool file_lookup(const char *path, const std::string &key, TuneResult &out) {
 void file_store(const char *path, const std::string &key, const TuneResult &r) {
     FILE *f = std::fopen(path, "a");
     if (!f) return; // an unwritable cache only costs a later calibration
-    std::fprintf(f, "%s\t%d %.17g %.17g\n", key.c_str(), r.batch, r.theta_fwd, r.theta_bwd);
+    std::fprintf(f, "%s\t%d %.17g %.17g %d\n", key.c_str(), r.batch, r.theta_fwd, r.theta_bwd, r.fwd_rows);
     std::fclose(f);
+}
+
+// The caller's file comes first, then what this process measured before (a
+// result measured here and missing from the file is appended to it).
+bool cache_lookup(const bc_options &opt, const std::string &key, TuneResult &out) {
+    if (opt.tune_cache && file_lookup(opt.tune_cache, key, out)) return true;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_cache.find(key);
+        if (it == g_cache.end()) return false;
+        out = it->second;
+    }
+    if (opt.tune_cache) file_store(opt.tune_cache, key, out);
+    return true;
+}
+
+void cache_store(const bc_options &opt, const std::string &key, const TuneResult &r, bool measured) {
+    if (measured) {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_cache[key] = r;
+    }
+    if (opt.tune_cache) file_store(opt.tune_cache, key, r);
 }
 
 uint64_t fmix64(uint64_t x) {
@@ -223,43 +285,118 @@ double fit_threshold(const Calibration &cal, bool forward, double *saved_ms) {
     return best_theta;
 }
 
-void clear_after_calibration(bc_ctx *ctx) {
+// Forward product block rows: whole batches, every level as the form runs it
+// (the algebraic form: all by products; the hybrid form: by its thresholds),
+// with 128- and 256-row blocks, timed alternately so that both see the same
+// cache and clock state.  256 rows are kept only if they beat 128 by kAccept.
+bc_status pick_fwd_rows(bc_ctx *ctx, const int32_t *d_src, int32_t B, int32_t *rows) {
+    Calibration cal;
+    double t128 = 0.0, t256 = 0.0;
+    bc_status st = BC_OK;
+    for (int rep = 0; rep < kConfirm && st == BC_OK; ++rep) {
+        double a = 0.0, b = 0.0;
+        ctx->al.fwd_rows = 128;
+        st = run_mode(ctx, d_src, B, kPlainMixed, cal, &a);
+        ctx->al.fwd_rows = 256;
+        if (st == BC_OK) st = run_mode(ctx, d_src, B, kPlainMixed, cal, &b);
+        t128 += a;
+        t256 += b;
+    }
+    *rows = st == BC_OK && t256 < kAccept * t128 ? 256 : 128;
+    ctx->al.fwd_rows = *rows;
+    return st;
+}
+
+// Calibration sources: (kReps + 1) batches of `width`, drawn from the graph
+// by a fixed hash so that every context of one shape times the same ones.
+bc_status calibration_sources(bc_ctx *ctx, int32_t width, int32_t **out) {
+    const size_t nsrc = (size_t)(kReps + 1) * width;
+    std::vector<int32_t> h_src(nsrc);
+    for (size_t i = 0; i < nsrc; ++i) h_src[i] = (int32_t)(fmix64(0x0809190600ull + i) % (uint64_t)ctx->n);
+    int32_t *d_src = (int32_t *)bc_dalloc(ctx, nsrc * sizeof(int32_t));
+    if (!d_src) return bc_fail(ctx, BC_ERR_NOMEM, "tuning: source buffer allocation failed");
+    if (hipMemcpy(d_src, h_src.data(), nsrc * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
+        bc_dfree(ctx, d_src);
+        return bc_fail(ctx, BC_ERR_DEVICE, "tuning: source upload failed");
+    }
+    *out = d_src;
+    return BC_OK;
+}
+
+// Calibration added to BC (and, with edges on, to the per-arc terms) and may
+// have flagged an overflow: start clean.
+bc_status clear_after_calibration(bc_ctx *ctx) {
+    BC_HIP(ctx, hipMemsetAsync(ctx->bc, 0, sizeof(double) * (size_t)std::max(ctx->n, 1), ctx->stream));
+    if (ctx->eb) BC_HIP(ctx, hipMemsetAsync(ctx->eb, 0, sizeof(double) * (size_t)std::max(ctx->nnz, 1), ctx->stream));
+    BC_HIP(ctx, hipMemsetAsync(ctx->status, 0, 256, ctx->stream));
+    BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
     bc_timers_clear(ctx);
+    algebraic_reset_counters(ctx); // products and k-tiles count from create
     ctx->max_levels = 0;
+    return BC_OK;
+}
+
+// The algebraic form: batch width from opt (default 256); the forward block
+// rows from the cache or timed batches.
+bc_status tune_algebraic(bc_ctx *ctx, const bc_options &opt) {
+    const int32_t w = opt.batch ? opt.batch : 256;
+    bc_status st = sparse_prepare(ctx, w, opt.split_degree);
+    if (st == BC_OK) st = algebraic_prepare(ctx);
+    ctx->al.every_level = true;
+    if (st != BC_OK) return st;
+    const std::string key = make_key(ctx, BC_FORM_ALGEBRAIC, opt.batch, opt.split_degree);
+    TuneResult r{};
+    if (cache_lookup(opt, key, r)) {
+        if (r.batch != w || (r.fwd_rows != 0 && r.fwd_rows != 128 && r.fwd_rows != 256))
+            return bc_fail(ctx, BC_ERR_INVALID_ARG, "tuning cache: entry for this graph names an unusable batch width or block rows");
+        ctx->al.fwd_rows = r.fwd_rows ? r.fwd_rows : 128;
+        ctx->hy.tune_source = BC_TUNE_CACHED;
+        return BC_OK;
+    }
+    r = TuneResult{w, kNever, kNever, 128};
+    if (ctx->n < kTinyN) { // calibration would time launch latency only
+        ctx->hy.tune_source = BC_TUNE_DEFAULT;
+        cache_store(opt, key, r, false);
+        return BC_OK;
+    }
+    int32_t *d_src = nullptr;
+    st = calibration_sources(ctx, w, &d_src);
+    if (st != BC_OK) return st;
+    st = pick_fwd_rows(ctx, d_src, w, &r.fwd_rows);
+    bc_dfree(ctx, d_src);
+    if (st == BC_OK) st = clear_after_calibration(ctx);
+    if (st != BC_OK) return st;
+    ctx->hy.tune_source = BC_TUNE_MEASURED;
+    cache_store(opt, key, r, true);
+    return BC_OK;
 }
 
 } // namespace
 
 bc_status tune_prepare(bc_ctx *ctx, const bc_options &opt, bc_form form) {
+    ctx->hy = HybridState{};
+    if (form == BC_FORM_ALGEBRAIC) return tune_algebraic(ctx, opt);
     const bool hybrid = form == BC_FORM_HYBRID;
     const int32_t split = opt.split_degree;
     if (hybrid && opt.batch != 0 && opt.batch != 256 && opt.batch != 512)
         return bc_fail(ctx, BC_ERR_INVALID_ARG, "hybrid form: batch must be 0 (tuned), 256 or 512");
     const bool products = hybrid && products_possible(ctx);
-    ctx->hy = HybridState{};
     ctx->hy.products = products;
     if (!hybrid && opt.batch != 0) return sparse_prepare(ctx, opt.batch, split); // nothing to tune
 
     const std::string key = make_key(ctx, form, opt.batch, split);
-    // The caller's file comes first, then what this process measured before.
     TuneResult r{};
-    bool hit = opt.tune_cache && file_lookup(opt.tune_cache, key, r);
-    if (!hit) {
-        std::lock_guard<std::mutex> lk(g_mu);
-        auto it = g_cache.find(key);
-        if (it != g_cache.end()) {
-            r = it->second;
-            hit = true;
-        }
-    }
-    if (hit) {
+    if (cache_lookup(opt, key, r)) {
         const bool ok_width = r.batch == 128 || r.batch == 256 || r.batch == 512 || (!hybrid && r.batch == 64);
-        if (!ok_width || (hybrid && r.batch % 256 != 0) || (opt.batch != 0 && r.batch != opt.batch))
-            return bc_fail(ctx, BC_ERR_INVALID_ARG, "tuning cache: entry for this graph names an unusable batch width");
+        if (!ok_width || (hybrid && r.batch % 256 != 0) || (opt.batch != 0 && r.batch != opt.batch) ||
+            (r.fwd_rows != 0 && r.fwd_rows != 128 && r.fwd_rows != 256))
+            return bc_fail(ctx, BC_ERR_INVALID_ARG,
+                           "tuning cache: entry for this graph names an unusable batch width or block rows");
         bc_status st = prepare_width(ctx, r.batch, split, products);
         if (st != BC_OK) return st;
         ctx->hy.theta_fwd = products ? r.theta_fwd : kNever;
         ctx->hy.theta_bwd = products ? r.theta_bwd : kNever;
+        if (products) ctx->al.fwd_rows = r.fwd_rows ? r.fwd_rows : 128;
         ctx->hy.tune_source = BC_TUNE_CACHED;
         return BC_OK;
     }
@@ -267,7 +404,7 @@ bc_status tune_prepare(bc_ctx *ctx, const bc_options &opt, bc_form form) {
         const int32_t w = opt.batch ? opt.batch : 256;
         bc_status st = prepare_width(ctx, w, split, products);
         ctx->hy.tune_source = BC_TUNE_DEFAULT;
-        if (st == BC_OK && opt.tune_cache) file_store(opt.tune_cache, key, TuneResult{w, kNever, kNever});
+        if (st == BC_OK) cache_store(opt, key, TuneResult{w, kNever, kNever, 128}, false);
         return st;
     }
 
@@ -277,18 +414,13 @@ bc_status tune_prepare(bc_ctx *ctx, const bc_options &opt, bc_form form) {
     else widths = {128, 256, 512};
     while (widths.size() > 1 && state_bytes(ctx->n, widths.back()) > kStateBudget) widths.pop_back();
 
-    const int32_t maxw = widths.back();
-    const size_t nsrc = (size_t)(kReps + 1) * maxw;
-    std::vector<int32_t> h_src(nsrc);
-    for (size_t i = 0; i < nsrc; ++i) h_src[i] = (int32_t)(fmix64(0x0809190600ull + i) % (uint64_t)ctx->n);
-    int32_t *d_src = (int32_t *)bc_dalloc(ctx, nsrc * sizeof(int32_t));
-    if (!d_src) return bc_fail(ctx, BC_ERR_NOMEM, "tuning: source buffer allocation failed");
-    BC_HIP(ctx, hipMemcpy(d_src, h_src.data(), nsrc * sizeof(int32_t), hipMemcpyHostToDevice));
+    int32_t *d_src = nullptr;
+    bc_status st = calibration_sources(ctx, widths.back(), &d_src);
+    if (st != BC_OK) return st;
 
     double best_ms = 0.0;
-    int32_t best_w = 0, prepared = 0;
+    int32_t best_w = 0, prepared = 0, rows = 128;
     double best_tf = kNever, best_tb = kNever;
-    bc_status st = BC_OK;
     for (int32_t w : widths) {
         if (prepared) st = release_width(ctx, products);
         if (st == BC_OK) st = prepare_width(ctx, w, split, products);
@@ -333,27 +465,81 @@ bc_status tune_prepare(bc_ctx *ctx, const bc_options &opt, bc_form form) {
             best_tb = tb;
         }
     }
-    bc_dfree(ctx, d_src);
     if (st == BC_OK && prepared != best_w) {
         st = release_width(ctx, products);
         if (st == BC_OK) st = prepare_width(ctx, best_w, split, products);
     }
-    if (st != BC_OK) return st;
-    // Calibration added to BC (and, with edges on, to the per-arc terms) and
-    // may have flagged an overflow: start clean.
-    BC_HIP(ctx, hipMemsetAsync(ctx->bc, 0, sizeof(double) * (size_t)std::max(ctx->n, 1), ctx->stream));
-    if (ctx->eb) BC_HIP(ctx, hipMemsetAsync(ctx->eb, 0, sizeof(double) * (size_t)std::max(ctx->nnz, 1), ctx->stream));
-    BC_HIP(ctx, hipMemsetAsync(ctx->status, 0, 256, ctx->stream));
-    BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    clear_after_calibration(ctx);
     ctx->hy.theta_fwd = best_tf;
     ctx->hy.theta_bwd = best_tb;
+    // forward products in use: their block rows too
+    if (st == BC_OK && products && best_tf <= 1.0) st = pick_fwd_rows(ctx, d_src, best_w, &rows);
+    bc_dfree(ctx, d_src);
+    if (st == BC_OK) st = clear_after_calibration(ctx);
+    if (st != BC_OK) return st;
     ctx->hy.tune_source = BC_TUNE_MEASURED;
-    r = TuneResult{best_w, best_tf, best_tb};
-    {
-        std::lock_guard<std::mutex> lk(g_mu);
-        g_cache[key] = r;
+    cache_store(opt, key, TuneResult{best_w, best_tf, best_tb, rows}, true);
+    return BC_OK;
+}
+
+// bc_create_many's queue: sources per work unit from opt, the cache, or timed
+// launches.  The calibration runs a sample of the graphs (every k-th by size,
+// k chosen so that one launch takes about kManySampleWork of n_g (n_g +
+// arcs_g)) once per unit size to warm up and record the launch, then kReps
+// times timed; the fastest mean wins.  The compact sweep's workgroups per
+// compute unit are fixed at two by its LDS (each takes just under half).
+bc_status tune_many(bc_ctx *ctx, const bc_options &opt, const std::vector<int32_t> &voff,
+                    const std::vector<int32_t> &rpoff, const std::vector<int32_t> &rp) {
+    ctx->hy = HybridState{};
+    bc_status st = multigraph_prepare(ctx, voff, rpoff, rp, opt.batch > 0 ? opt.batch : 64);
+    if (st != BC_OK || opt.batch > 0) return st;
+    MultiState &m = ctx->mg;
+    const std::string key = make_many_key(ctx);
+    TuneResult r{};
+    if (cache_lookup(opt, key, r)) {
+        if (r.batch < 1 || r.batch > 4096)
+            return bc_fail(ctx, BC_ERR_INVALID_ARG, "tuning cache: entry for these graphs names an unusable unit size");
+        ctx->hy.tune_source = BC_TUNE_CACHED;
+        return r.batch == m.chunk ? BC_OK : multigraph_set_queue(ctx, nullptr, r.batch);
     }
-    if (opt.tune_cache) file_store(opt.tune_cache, key, r);
+    if (ctx->n < kTinyN) {
+        ctx->hy.tune_source = BC_TUNE_DEFAULT;
+        cache_store(opt, key, TuneResult{m.chunk, kNever, kNever, 0}, false);
+        return BC_OK;
+    }
+    double total = 0.0;
+    for (int32_t g = 0; g < m.ngraphs; ++g) {
+        const double n = (double)(m.h_voff[(size_t)g + 1] - m.h_voff[(size_t)g]);
+        total += n * (n + (double)m.h_arcs[(size_t)g]);
+    }
+    const size_t stride = (size_t)std::max(1.0, std::ceil(total / kManySampleWork));
+    std::vector<int32_t> sample;
+    for (size_t i = 0; i < m.h_order.size(); i += stride) sample.push_back(m.h_order[i]);
+
+    hipEvent_t t0 = bc_event_get(ctx), t1 = bc_event_get(ctx);
+    if (!t0 || !t1) st = bc_fail(ctx, BC_ERR_DEVICE, "hipEventCreate failed");
+    int32_t best = m.chunk;
+    double best_ms = 0.0;
+    for (int32_t c : kUnitSizes) {
+        if (st == BC_OK) st = multigraph_set_queue(ctx, &sample, c);
+        if (st == BC_OK) st = multigraph_run(ctx); // records the launch
+        if (st == BC_OK && hipEventRecord(t0, ctx->stream) != hipSuccess) st = bc_fail(ctx, BC_ERR_DEVICE, "hipEventRecord failed");
+        for (int j = 0; j < kReps && st == BC_OK; ++j) st = multigraph_run(ctx);
+        if (st == BC_OK && hipEventRecord(t1, ctx->stream) != hipSuccess) st = bc_fail(ctx, BC_ERR_DEVICE, "hipEventRecord failed");
+        if (st == BC_OK && hipEventSynchronize(t1) != hipSuccess) st = bc_fail(ctx, BC_ERR_DEVICE, "calibration failed");
+        if (st != BC_OK) break;
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, t0, t1);
+        if (best_ms == 0.0 || ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+    }
+    bc_event_put(ctx, t0);
+    bc_event_put(ctx, t1);
+    if (st == BC_OK) st = multigraph_set_queue(ctx, nullptr, best);
+    if (st == BC_OK) st = clear_after_calibration(ctx);
+    if (st != BC_OK) return st;
+    ctx->hy.tune_source = BC_TUNE_MEASURED;
+    cache_store(opt, key, TuneResult{best, kNever, kNever, 0}, true);
     return BC_OK;
 }
