@@ -95,8 +95,21 @@ struct EpiArgs {
     unsigned long long *lvmax_next;      // forward: largest count of level l+1
     int32_t classes, level;              // forward: M, and l (levels l+1-M .. l feed level l+1)
     unsigned long long *planes_issued;   // products issued (limb or coefficient planes)
+    unsigned long long *reach;           // forward, every level by products: [0] pairs the batch's
+                                         // sources can reach, [1] pairs reached, [2] set when the
+                                         // two were equal before this level's products
     int accumulate;
 };
+
+// Every (vertex, source) pair the batch can reach has been reached: the next
+// level is empty, and the products that would find that out are skipped.
+// Read only while no kernel adds to reach[1] (the planes kernel before a
+// level's products, which records the answer in reach[2] for them: the
+// products' own epilogues add to reach[1] while later blocks start).
+__device__ __forceinline__ bool search_over(const unsigned long long *reach) {
+    return reach && __hip_atomic_load(&reach[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+                        __hip_atomic_load(&reach[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 __device__ __forceinline__ void store_count(uint64_t *p, uint64_t x, bool &) { *p = x; }
 __device__ __forceinline__ void store_count(uint32_t *p, uint64_t x, bool &wide) {
@@ -368,6 +381,7 @@ __device__ __forceinline__ void epi_fwd(const GemmArgs &g, const EpiArgs &e, int
     S *sigma = reinterpret_cast<S *>(e.sigma);
     bool wide = false, ovf = false;
     uint64_t mx = 0;
+    uint32_t fresh_pairs = 0;
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
 #pragma unroll
@@ -418,6 +432,7 @@ __device__ __forceinline__ void epi_fwd(const GemmArgs &g, const EpiArgs &e, int
                     if (word) {
                         e.visited[(size_t)w * g.NW + q] = vis | word;
                         atomicOr(&e.any_next[w >> 5], 1u << (w & 31));
+                        fresh_pairs += (uint32_t)__popcll(word);
                     }
                 }
             }
@@ -432,6 +447,10 @@ __device__ __forceinline__ void epi_fwd(const GemmArgs &g, const EpiArgs &e, int
         if (lane == 0 && mx > __hip_atomic_load(e.lvmax_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
             atomicMax(e.lvmax_next, (unsigned long long)mx);
         if (__any(wide) && lane == 0) atomicOr(&e.status[1], 1u);
+        if (e.reach) { // lanes 0 and 32 hold the counts
+            fresh_pairs += __shfl_xor(fresh_pairs, 32, 64);
+            if (lane == 0 && fresh_pairs) atomicAdd(&e.reach[1], (unsigned long long)fresh_pairs);
+        }
     }
     if (__any(ovf) && lane == 0) atomicOr(&e.status[0], (uint32_t)BC_DEV_SIGMA_OVERFLOW);
 }
@@ -446,7 +465,7 @@ __global__ __launch_bounds__(2 * BM, 2) void k_mfma_fwd(GemmArgs g, EpiArgs e) {
     __shared__ int s_last;
     int half = 0, tile = 0;
     const Tile tl = g.ksplit == 2 ? tile_of_split(g.B, half, tile) : tile_of(g.B);
-    if (tl.row >= g.npad / BM) return;
+    if (tl.row >= g.npad / BM || (e.reach && e.reach[2] != 0)) return;
     const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int w0 = tl.row * BM + (wv >> 1) * WM, b0 = tl.col * GN;
     const int q = (b0 >> 6) + (wv & 1); // bitmap word of this wave's sources
@@ -552,10 +571,13 @@ __global__ __launch_bounds__(PB) void k_limb_split(int32_t n, int32_t npad, int3
                                                    int32_t l, const unsigned long long *__restrict__ lvmax_l,
                                                    const uint64_t *__restrict__ fl, size_t words,
                                                    const S *__restrict__ sigma, __bf16 *__restrict__ planes,
-                                                   size_t plane_elems, uint32_t *__restrict__ kflags) {
+                                                   size_t plane_elems, uint32_t *__restrict__ kflags,
+                                                   unsigned long long *__restrict__ reach) {
     const size_t id = (size_t)blockIdx.x * PB + threadIdx.x;
     const size_t per_class = (size_t)(npad / 8) * B;
-    if (id >= per_class * M) return;
+    const bool over = search_over(reach);
+    if (reach && id == 0) reach[2] = over ? 1ull : 0ull; // for this level's products
+    if (id >= per_class * M || over) return;
     const int32_t c = (int32_t)(id / per_class);
     const size_t r = id - (size_t)c * per_class;
     const int L = limbs_feeding(lvmax_l, l, M);
@@ -736,15 +758,20 @@ bc_status algebraic_forward_level_t(bc_ctx *ctx, int32_t l) {
     const size_t aw = (size_t)(ctx->n + 31) / 32;
     const uint64_t *fcur = s.front + (size_t)l * words;
     const size_t plane_elems = (size_t)a.classes * a.npad * s.batch;
+    // With every level by products the reached pairs are counted (the first
+    // level by the push, the rest by the epilogue), so a level after the last
+    // one skips its planes and products.
+    unsigned long long *reach = a.every_level ? s.reach : nullptr;
     clear_kflags(ctx);
     {
         LaunchTimer tm(ctx, "limb_split");
         hipLaunchKernelGGL(k_limb_split<S>, dim3(blocks_for(plane_elems / 8, PB)), dim3(PB), 0, ctx->stream, ctx->n,
                            a.npad, s.batch, s.words, a.classes, l, s.lvmax + l, fcur, words, (const S *)s.sigma,
-                           a.planes, plane_elems, a.kflags);
+                           a.planes, plane_elems, a.kflags, reach);
         tm.done();
     }
     EpiArgs e{};
+    e.reach = reach;
     e.part = a.part;
     e.fnext = s.front + (size_t)(l + 1) * words;
     e.visited = s.visited;

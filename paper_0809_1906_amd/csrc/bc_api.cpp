@@ -425,6 +425,31 @@ bc_status bc_create(const bc_graph *g, const bc_options *opt_in, bc_ctx **out) {
         if (!ctx->new_of_old) return bail(BC_ERR_NOMEM, "device allocation failed");
     }
     if (hipHostMalloc((void **)&ctx->status_host, 256) != hipSuccess) return bail(BC_ERR_NOMEM, "pinned allocation failed");
+    // Connected components (internal numbering): a source reaches exactly the
+    // vertices of its own, which lets a batch know when its search is over.
+    std::vector<int32_t> csize((size_t)std::max(n, 1), 0);
+    {
+        std::vector<int32_t> comp((size_t)n, -1), queue((size_t)n), sizes;
+        for (int32_t r = 0; r < n; ++r) {
+            if (comp[(size_t)r] >= 0) continue;
+            const int32_t id = (int32_t)sizes.size();
+            size_t head = 0, tail = 0;
+            queue[tail++] = r;
+            comp[(size_t)r] = id;
+            while (head < tail) {
+                const int32_t v = queue[head++];
+                for (int32_t e = urp[v]; e < urp[v + 1]; ++e)
+                    if (comp[(size_t)ucol[e]] < 0) {
+                        comp[(size_t)ucol[e]] = id;
+                        queue[tail++] = ucol[e];
+                    }
+            }
+            sizes.push_back((int32_t)tail);
+        }
+        for (int32_t v = 0; v < n; ++v) csize[(size_t)v] = sizes[(size_t)comp[(size_t)v]];
+    }
+    ctx->comp_size = (int32_t *)bc_dalloc(ctx, sizeof(int32_t) * (size_t)std::max(n, 1));
+    if (!ctx->comp_size) return bail(BC_ERR_NOMEM, "device allocation failed");
     // Host arrays (the caller's or the relabelled copies) go up synchronously.
     const bool direct_device = !relabel && g->mem == BC_MEM_DEVICE;
     hipMemcpyKind kind = direct_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
@@ -432,6 +457,7 @@ bc_status bc_create(const bc_graph *g, const bc_options *opt_in, bc_ctx **out) {
         (nnz > 0 && hipMemcpy(ctx->col, direct_device ? g->col : ucol, sizeof(int32_t) * (size_t)nnz, kind) != hipSuccess) ||
         (ctx->weight && nnz > 0 && hipMemcpy(ctx->weight, w8.data(), (size_t)nnz, hipMemcpyHostToDevice) != hipSuccess) ||
         (relabel && hipMemcpy(ctx->new_of_old, new_of_old.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice) != hipSuccess) ||
+        hipMemcpy(ctx->comp_size, csize.data(), sizeof(int32_t) * (size_t)std::max(n, 1), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemsetAsync(ctx->bc, 0, sizeof(double) * (size_t)std::max(n, 1), ctx->stream) != hipSuccess ||
         hipMemsetAsync(ctx->status, 0, 256, ctx->stream) != hipSuccess)
         return bail(BC_ERR_DEVICE, "uploading the graph failed");

@@ -52,6 +52,8 @@ struct SparseState {
     uint64_t *sigma = nullptr;   // [n][batch] as uint64, or uint32 in its first half
     float *cval = nullptr;       // [n][batch]  c(v) = (1 + delta(v)) / sigma(v)
     int32_t *src = nullptr;      // [batch] sources of the current batch (-1 = empty lane)
+    unsigned long long *reach = nullptr; // [0] the batch's sources' component sizes summed,
+                                         // [1] (vertex, source) pairs reached so far
     uint32_t *any_host = nullptr; // pinned mirror of any, read once per batch
     int32_t *heavy_id = nullptr; // [n] index among heavy rows or -1
     int32_t *heavy_nseg = nullptr; // [nheavy] segments per heavy row
@@ -201,6 +203,7 @@ struct bc_ctx {
     // device copies (internal numbering)
     int32_t *row_ptr = nullptr;
     int32_t *col = nullptr;
+    int32_t *comp_size = nullptr;   // [n] vertices in each vertex's connected component
     uint8_t *weight = nullptr;       // weights as bytes (weighted graphs with max weight <= 255)
     double *bc = nullptr;
     double *eb = nullptr;            // [nnz] edge betweenness terms per internal arc (edges on)

@@ -304,8 +304,9 @@ __device__ __forceinline__ void bwd_finalize(int32_t v, const uint64_t (&F)[NW],
 __global__ __launch_bounds__(SB) void k_sp_clear(uint64_t *__restrict__ a, uint64_t *__restrict__ b, size_t words,
                                                  uint32_t *__restrict__ any_all, size_t any_total,
                                                  unsigned long long *__restrict__ lvmax, uint32_t *__restrict__ lvflag,
-                                                 int32_t levels) {
+                                                 int32_t levels, unsigned long long *__restrict__ reach) {
     const size_t tid = (size_t)blockIdx.x * SB + threadIdx.x, stride = (size_t)gridDim.x * SB;
+    if (tid < 2) reach[tid] = 0;
     for (size_t i = tid; i < words; i += stride) {
         a[i] = 0;
         a[words + i] = 0;
@@ -339,7 +340,8 @@ __global__ void k_run_init(BatchCtl *ctl, const int32_t *src, int32_t total, int
 template <typename S>
 __global__ __launch_bounds__(SB) void k_sp_seed(const int32_t *__restrict__ src, int32_t count, int32_t B, int32_t NW,
                                                 uint64_t *front0, uint64_t *visited, S *sigma, int32_t *src_lane,
-                                                uint32_t *any0, const BatchCtl *__restrict__ ctl) {
+                                                uint32_t *any0, const BatchCtl *__restrict__ ctl,
+                                                const int32_t *__restrict__ comp_size, unsigned long long *reach) {
     const int32_t b = blockIdx.x * SB + threadIdx.x;
     if (b >= B) return;
     if (ctl) {
@@ -355,6 +357,8 @@ __global__ __launch_bounds__(SB) void k_sp_seed(const int32_t *__restrict__ src,
         atomicOr((unsigned long long *)&visited[(size_t)s * NW + (b >> 6)], bit);
         atomicOr(&any0[s >> 5], 1u << (s & 31));
         sigma[(size_t)s * B + b] = 1;
+        atomicAdd(&reach[0], (unsigned long long)comp_size[s]);
+        atomicAdd(&reach[1], 1ull);
     }
 }
 
@@ -364,10 +368,13 @@ __global__ __launch_bounds__(SB) void k_sp_seed(const int32_t *__restrict__ src,
 template <typename S>
 __global__ __launch_bounds__(SB) void k_fwd_push0(Topo t, int32_t NW, const int32_t *__restrict__ src_lane,
                                                   uint64_t *__restrict__ fnext, uint64_t *__restrict__ visited,
-                                                  S *__restrict__ sigma, uint32_t *__restrict__ any_next) {
+                                                  S *__restrict__ sigma, uint32_t *__restrict__ any_next,
+                                                  unsigned long long *__restrict__ reach) {
     const int32_t b = blockIdx.x;
     const int32_t s = src_lane[b];
     if (s < 0) return;
+    // the neighbours are distinct (a simple graph): each is a new pair
+    if (threadIdx.x == 0) atomicAdd(&reach[1], (unsigned long long)(t.rp[s + 1] - t.rp[s]));
     const unsigned long long bit = 1ull << (b & 63);
     const int q = b >> 6;
     for (int32_t e = t.rp[s] + threadIdx.x; e < t.rp[s + 1]; e += SB) {
@@ -887,9 +894,10 @@ bc_status launch_batch_init(bc_ctx *ctx, const BatchShape &b, const int32_t *d_s
     LaunchTimer tm(ctx, "batch_init");
     const int blocks = (int)std::min<size_t>((b.words + SB - 1) / SB, 8192);
     hipLaunchKernelGGL(k_sp_clear, dim3(std::max(blocks, 1)), dim3(SB), 0, ctx->stream, s.front, s.visited, b.words,
-                       s.any, (size_t)s.level_cap * b.aw, s.lvmax, s.lvflag, s.level_cap);
+                       s.any, (size_t)s.level_cap * b.aw, s.lvmax, s.lvflag, s.level_cap, s.reach);
     hipLaunchKernelGGL(k_sp_seed<S>, dim3((b.B + SB - 1) / SB), dim3(SB), 0, ctx->stream, d_src, count, b.B, NW,
-                       s.front, s.visited, reinterpret_cast<S *>(s.sigma), s.src, s.any, ctl);
+                       s.front, s.visited, reinterpret_cast<S *>(s.sigma), s.src, s.any, ctl,
+                       (const int32_t *)ctx->comp_size, s.reach);
     tm.done();
     BC_HIP(ctx, hipGetLastError());
     return BC_OK;
@@ -905,7 +913,7 @@ bc_status launch_fwd_level(bc_ctx *ctx, const BatchShape &b, int32_t l, bool pro
     if (l == 0) {
         LaunchTimer tm(ctx, "fwd_push0");
         hipLaunchKernelGGL(k_fwd_push0<S>, dim3(b.B), dim3(SB), 0, ctx->stream, b.t, NW, (const int32_t *)s.src,
-                           s.front + b.words, s.visited, reinterpret_cast<S *>(s.sigma), s.any + b.aw);
+                           s.front + b.words, s.visited, reinterpret_cast<S *>(s.sigma), s.any + b.aw, s.reach);
         tm.done();
         return BC_OK;
     }
@@ -1360,8 +1368,9 @@ bc_status sparse_prepare(bc_ctx *ctx, int32_t batch, int32_t split_degree) {
     s.cval = (float *)bc_dalloc(ctx, nn * batch * sizeof(float));
     s.src = (int32_t *)bc_dalloc(ctx, batch * sizeof(int32_t));
     s.ctl = (BatchCtl *)bc_dalloc(ctx, sizeof(BatchCtl));
+    s.reach = (unsigned long long *)bc_dalloc(ctx, 256);
     if (!s.heavy_id || !s.heavy_nseg || !s.arrive || !s.arrive_w || !s.seg_v || !s.seg_beg || !s.seg_end || !s.hacc || !s.visited ||
-        !s.sigma || !s.cval || !s.src || !s.ctl)
+        !s.sigma || !s.cval || !s.src || !s.ctl || !s.reach)
         return bc_fail(ctx, BC_ERR_NOMEM, "sparse form: state allocation failed");
     if (n > 0)
         BC_HIP(ctx, hipMemcpyAsync(s.heavy_id, heavy_id.data(), nn * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
@@ -1391,7 +1400,7 @@ bc_status sparse_release(bc_ctx *ctx) {
     for (void *p : {(void *)s.front, (void *)s.any, (void *)s.lvmax, (void *)s.lvflag, (void *)s.visited,
                     (void *)s.sigma, (void *)s.cval, (void *)s.src, (void *)s.heavy_id,
                     (void *)s.heavy_nseg, (void *)s.arrive, (void *)s.arrive_w, (void *)s.seg_v, (void *)s.seg_beg,
-                    (void *)s.seg_end, (void *)s.hacc, (void *)s.ctl, (void *)s.redo})
+                    (void *)s.seg_end, (void *)s.hacc, (void *)s.ctl, (void *)s.redo, (void *)s.reach})
         if (p) bc_dfree(ctx, p);
     if (s.any_host) hipHostFree(s.any_host);
     s = SparseState{};

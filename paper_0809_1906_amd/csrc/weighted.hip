@@ -67,6 +67,7 @@ struct WeightedWork {
     int64_t dcap;    // DAG-arc entries per workgroup
     int32_t *retry;  // sources (positions in the source list) whose live bins outgrew the arena
     uint32_t *retry_count;
+    const int32_t *comp_size; // [n] vertices in each vertex's connected component
 };
 
 __global__ __launch_bounds__(PB) void k_weighted_sweep(
@@ -236,6 +237,11 @@ __global__ __launch_bounds__(PB) void k_weighted_sweep(
             }
             wg::bar();
             if (s_abort) break;
+            // Every vertex of the source's component is settled: the bins hold
+            // only stale candidates, so no later phase settles anything (each
+            // phase writes its ring slot before any phase reads it, so the
+            // next source does not see what is left).
+            if (nsettled == W.comp_size[s]) break;
             // (3) allocate this phase's bins in the arena ring; the live window
             // (phases d-255 .. d) must fit, else the source is retried later
             {
@@ -382,7 +388,7 @@ WeightedWork work_of(bc_ctx *ctx, const WeightedBuffers &b) {
     WeightedState &w = ctx->wt;
     return WeightedWork{b.dist, b.sigma, b.acc, b.order, b.gstart, b.gdist, b.arena, b.bstart, b.bcount,
                         b.pstart, b.imp_x, b.imp_c, b.dag_p, b.dag_s, b.dag_a, b.gdag, b.cap, b.icap, b.dcap, w.retry,
-                        w.retry_count};
+                        w.retry_count, ctx->comp_size};
 }
 
 } // namespace
