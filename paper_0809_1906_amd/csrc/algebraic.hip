@@ -503,9 +503,21 @@ __global__ __launch_bounds__(GT, 2) void k_mfma_bwd(GemmArgs g, EpiArgs e) {
     if (tl.row >= g.npad / BWD_BM) return;
     const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int b0 = tl.col * GN;
-    if (blockIdx.x == 0 && tid == 0) atomicAdd(e.planes_issued, 3ull);
     f32x16 acc[RT][2];
-    gemm_tile<3, BWD_KS, BWD_BM>(g, g.planes, tl.row * BWD_BM, b0, tid, sA, sX, acc);
+    if (g.gate && g.gate[1] == 0) {
+        // the deepest level of a replayed batch: no successor, so delta = 0
+        // and c = 1 / lambda, without products (their flag scan alone would
+        // cost a dependent load per stage)
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[rt][ct][r] = 0.f;
+    } else {
+        if (blockIdx.x == 0 && tid == 0) atomicAdd(e.planes_issued, 3ull);
+        gemm_tile<3, BWD_KS, BWD_BM>(g, g.planes, tl.row * BWD_BM, b0, tid, sA, sX, acc);
+    }
 
     const int w0 = tl.row * BWD_BM + (wv >> 1) * WM;
     const int q = (b0 >> 6) + (wv & 1);
@@ -614,8 +626,8 @@ __global__ __launch_bounds__(PB) void k_coef_split(int32_t n, int32_t npad, int3
     const size_t per_class = (size_t)(npad / 8) * B;
     if (id >= per_class * M) return;
     // gate[0]: level l (empty: the product exits too); gate[1]: level l+1
-    if (gate && gate[0] == 0) return;
-    if (gate && gate[1] == 0) deeper = 0;
+    // (empty: the product multiplies nothing and reads no plane)
+    if (gate && (gate[0] == 0 || gate[1] == 0)) return;
     const int32_t cl = (int32_t)(id / per_class);
     const size_t r = id - (size_t)cl * per_class;
     const int32_t vg = (int32_t)(r / B), b = (int32_t)(r - (size_t)vg * B);

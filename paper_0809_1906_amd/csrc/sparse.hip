@@ -567,7 +567,13 @@ __global__ __launch_bounds__(SB) void k_bwd_pull(Topo t, const uint64_t *__restr
     double acc[NW];
 #pragma unroll
     for (int q = 0; q < NW; ++q) acc[q] = 0.0;
-    if (fnext) bwd_scan<NW>(t, it.beg, it.end, F, any_next, fnext, cval, lane, acc);
+    if (!fnext) {
+        // the deepest level: no successor, so delta = 0 and c = 1 / lambda;
+        // the row's first segment finalizes it, no partial sums are needed
+        if (it.first) bwd_finalize<NW, S>(v, F, acc, lane, t.B, t.n, sigma, cval, src_lane, bc, delta_dump, accumulate);
+        return;
+    }
+    bwd_scan<NW>(t, it.beg, it.end, F, any_next, fnext, cval, lane, acc);
     if (it.h < 0) {
         bwd_finalize<NW, S>(v, F, acc, lane, t.B, t.n, sigma, cval, src_lane, bc, delta_dump, accumulate);
         return;
@@ -608,7 +614,16 @@ __device__ __forceinline__ void bwd_item_w(const Topo &t, int64_t wid, const uin
     if (F == 0) return;
     const uint64_t F1[1] = {F};
     double acc[1] = {0.0};
-    if (fnext) {
+    if (!fnext) {
+        // the deepest level: no successor, so delta = 0 and c = 1 / lambda;
+        // the row's first segment finalizes it, no partial sums are needed
+        if (it.first)
+            bwd_finalize<1, S>(v, F1, acc, lane, t.B, t.n, sigma + (size_t)q * 64, cval + (size_t)q * 64,
+                               src_lane + q * 64, bc, delta_dump ? delta_dump + (size_t)q * 64 * t.n : nullptr,
+                               accumulate);
+        return;
+    }
+    {
         // the single-word scan over word q: shift the row base by q words
         const float *c = cval + (size_t)q * 64 + lane;
         // edge betweenness: arc v -> w carries sum over this word's sources of
