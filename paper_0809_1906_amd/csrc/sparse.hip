@@ -606,12 +606,29 @@ __device__ __forceinline__ void bwd_item_w(const Topo &t, int64_t wid, const uin
                                            double *__restrict__ hacc, uint32_t *__restrict__ arrive,
                                            double *__restrict__ delta_dump, int accumulate, double *__restrict__ eb,
                                            int lane) {
+    (void)any_next; // the per-word pull reads successors' words directly
     const int q = (int)(wid % NW);
     Item it;
-    if (!item_of(t, wid / NW, it)) return;
+    const int64_t r = wid / NW;
+    uint64_t F;
+    if (r < t.n) {
+        // a light row: its bounds, its heavy mark and its frontier word are
+        // independent loads, issued together
+        const int32_t v0 = (int32_t)r;
+        const int32_t hv = t.heavy_id[v0], b0 = t.rp[v0], e0 = t.rp[v0 + 1];
+        F = fcur[(size_t)v0 * NW + q];
+        if (hv >= 0 || F == 0) return;
+        it.v = v0;
+        it.beg = b0;
+        it.end = e0;
+        it.h = -1;
+        it.first = true;
+    } else {
+        if (!item_of(t, r, it)) return;
+        F = fcur[(size_t)it.v * NW + q];
+        if (F == 0) return;
+    }
     const int32_t v = it.v;
-    const uint64_t F = fcur[(size_t)v * NW + q];
-    if (F == 0) return;
     const uint64_t F1[1] = {F};
     double acc[1] = {0.0};
     if (!fnext) {
@@ -635,7 +652,13 @@ __device__ __forceinline__ void bwd_item_w(const Topo &t, int64_t wid, const uin
             uint64_t g = 0;
             if (e < it.end) {
                 w = t.col[e];
-                if ((any_next[w >> 5] >> (w & 31)) & 1) g = fnext[(size_t)w * NW + q] & F;
+                // the successor's word straight away, not after the level's
+                // vertex filter: every vertex's word of the level is written
+                // (zero off the level), the level's words are small enough to
+                // stay in the caches, and the filter was one more dependent
+                // load in front of the gathers (80.1 against 85.9 us per
+                // launch on RMAT-16)
+                g = fnext[(size_t)w * NW + q] & F;
             }
             uint64_t act = __ballot(g != 0);
             // gathers per round: without edge terms the wave has the
