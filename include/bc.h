@@ -75,9 +75,9 @@ typedef enum { BC_MEM_HOST = 0, BC_MEM_DEVICE = 1 } bc_mem;
  *                      (the fraction of vertices at level l for at least one
  *                      source of the batch) against two thresholds (forward,
  *                      backward) fixed at create time by timed calibration
- *                      batches or a tuning cache.  Unit weights.  Graphs whose
- *                      dense adjacency would exceed 16 GiB, or with a degree
- *                      above 65792, run every level by pulls.
+ *                      batches or a tuning cache.  Unit weights.  Graphs of
+ *                      more than 92672 vertices (padded to a multiple of 256),
+ *                      or with a degree above 65792, run every level by pulls.
  *  BC_FORM_AUTO        chosen by the library from the graph's shape.
  */
 /* Largest integer weight the algebraic form takes (one product class each). */

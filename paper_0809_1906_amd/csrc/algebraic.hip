@@ -36,8 +36,17 @@
 // unit weights are M = 1.  The exactness bound is unchanged: an output sums at
 // most deg(w) non-zero terms of at most 255.
 //
-// Data layout: A is a dense row-major BF16 [npad][M * npad] matrix (npad = n
-// rounded up to 256, a multiple of the block's row count).  Planes are k-packed: plane[v / 8][b][v % 8], so each
+// Data layout: A is a bit matrix in panels of 128 columns, [M * npad / 128]
+// [npad][4] words (npad = n rounded up to 256, a multiple of the block's row
+// count): a row's 16 B of one panel lie beside the next row's, so the bits of
+// 32 consecutive rows for one pipeline stage share four cache lines.  Word i
+// of a row's panel holds the panel's columns 32i .. 32i + 31, column 32i + 2p
+// at bit p and 32i + 2p + 1 at bit 16 + p (p < 16): masked with 0x10001 << p
+// and multiplied by 0x3F80 >> p, a word gives the BF16 pair (0 or 1, 0 or 1)
+// of columns 2p, 2p + 1 in one 24-bit multiply.  Each wave loads the bits of its own
+// rows into registers and expands them into MFMA A operands there: the
+// adjacency costs 1/16 of a BF16 matrix's bytes and no LDS traffic, and LDS
+// holds only the planes, which the block's waves share.  Planes are k-packed: plane[v / 8][b][v % 8], so each
 // MFMA B-operand lane reads 16 contiguous bytes.  Every product is
 // C[w][b] = sum_v A[w][v] X[v][b] with rows = vertices and columns = sources;
 // in the 32x32 MFMA output the 32 lanes of each half-wave hold 32 consecutive
@@ -54,19 +63,17 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int GM = 128;  // rows (vertices) per block of the backward: 2 wave rows x 64
-constexpr int GN = 128;  // columns (sources) per block: 2 wave columns x 64 (one bitmap word)
+constexpr int GN = 128;  // columns (sources) per block (two bitmap words)
 constexpr int GK = 32;   // k (vertices) per k-tile of the skip flags
-constexpr int GT = 256;  // threads per block of the backward (4 waves, 2 x 2); BM rows take 2 BM
 constexpr int WM = 64;   // rows per wave: 2 MFMA row tiles of 32
 constexpr int RT = WM / 32;
 constexpr int PB = 256;  // threads per block of the element-wise kernels
-constexpr int NPAD = 256; // n is padded to a multiple of this (of GM too)
+constexpr int NPAD = 256; // n is padded to a multiple of this (of every block's rows too)
 
 enum { EPI_ONLY = 0, EPI_FIRST = 1, EPI_MID = 2, EPI_LAST = 3 };
 
 struct GemmArgs {
-    const __bf16 *adj;     // [npad][K]
+    const uint32_t *abits; // [K / 128][npad][4] adjacency bit words (layout above)
     const __bf16 *planes;  // planes of [K/8][B][8]
     const uint32_t *kflags;// [K/GK][B/GN]: some plane entry of this k-tile is non-zero
     int32_t npad, n, B, NW;
@@ -134,99 +141,146 @@ __device__ __forceinline__ int limbs_feeding(const unsigned long long *lvmax_l, 
 
 // ---- the product -------------------------------------------------------------------
 
-// KS: k (vertices) per pipeline stage, 32 or 64.  A 64-deep stage holds
-// twice the products per barrier.  LDS row stride of the adjacency tile:
-// KS + 8 BF16 (padding against bank conflicts).
-template <int KS, int BM>
-constexpr int lds_a() { return BM * (KS + 8); }
+// Block shapes: BM rows by GN sources in 2 BM threads, waves of 64 x 64 in
+// BM / 64 rows by 2 columns (BM = 128: 4 waves, BM = 256: 8 waves).
+
+// Plane tile of one stage in LDS: [NP][KS / 8][GN][8] BF16 (16 B per lane of
+// an MFMA B operand, 32 consecutive sources of one k-group contiguous).
 template <int NP, int KS>
 constexpr int lds_x() { return NP * (KS / 8) * GN * 8; }
-// Stage depths, measured on ER-16384 (B = 512) against 32-deep stages:
-// - forward (one plane): one 128-deep stage, 636 -> 490 us per launch, and
-//   1.31 -> 0.88 ms for the weight-class products (K = M npad); two 64-deep
-//   stages gave 549 us and 1.02 ms;
-// - backward (three planes): one 64-deep stage, 815 -> 714 us.
+// Two LDS buffers (one barrier per stage, the next stage stored while the
+// current one is multiplied) when they fit: 2 x 32 KB for 128-row blocks (two
+// per compute unit), 2 x 48 KB for 256-row blocks (one per unit); else one.
+template <int NP, int KS, int BM>
+constexpr int stages() { return lds_x<NP, KS>() * 2 * 2 <= (BM == 256 ? 196608 : 65536) ? 2 : 1; }
+// Stage depths (k per stage): forward one plane 128 deep (32 KB), backward
+// three planes 64 deep (48 KB, one buffer).  Measured on ER-16384 (B = 512):
+// backward 32-deep stages with two buffers, and 256-row backward blocks with
+// two 48 KB buffers, were both slower (by 8% and 3%).
 constexpr int FWD_KS = 128;
 constexpr int BWD_KS = 64;
-// Block rows (BM, a multiple of 128; 2 BM threads, waves of 64 x 64 in BM / 64
-// rows by 2 columns).  The forward product runs 128-row blocks (67.6 KB of
-// LDS, two per compute unit) or 256-row blocks (8 waves, 102 KB, one per
-// unit, 1.37 times the flops per operand byte), whichever the tuner measured
-// faster on the graph (AlgebraicState::fwd_rows); on ER-16384 the two were
-// within 3% (490 against 504 us per launch).
-constexpr int BWD_BM = GM;
+// Forward block rows: 128 or 256, whichever the tuner measured faster on the
+// graph (AlgebraicState::fwd_rows); the backward takes 128.
+constexpr int BWD_BM = 128;
 
-// One pipeline stage held in registers between its global loads and its LDS
-// stores: the adjacency tile (BM x KS) in 16 B pieces, KS / 8 threads per row,
-// and KS / 16 pieces of 16 B of each plane tile (KS x GN) per pair of threads
-// (the block's 2 BM threads cover 2 BM / GN k-groups at a time).
-template <int NP, int KS_, int BM>
+// A stage's plane tile held in registers between its global loads and its LDS
+// stores: the block's T threads cover T / GN k-groups of GN sources at a time,
+// 16 B per thread and k-group.
+template <int NP, int KS_, int T_>
 struct Stage {
-    static constexpr int KS = KS_, T = 2 * BM, TPR = KS / 8, RPP = T / TPR, AP = BM / RPP, XG = T / GN;
-    static_assert(AP >= 1 && (KS / 8) % XG == 0, "stage shape");
-    u32x4 a[AP];
-    u32x4 x[NP * (KS / 8) / XG];
+    static constexpr int KS = KS_, XG = T_ / GN, XJ = KS / 8 / XG;
+    static_assert(XJ >= 1, "stage shape");
+    u32x4 x[NP * XJ];
 };
 
-template <int NP, int KS, int BM>
-__device__ __forceinline__ void load_stage(const GemmArgs &g, const __bf16 *planes, int ks, int w0, int b0, int tid,
-                                           Stage<NP, KS, BM> &st) {
-    using T = Stage<NP, KS, BM>;
-    const int row = tid / T::TPR, kq = tid % T::TPR; // T::TPR threads read one row's 2 KS bytes
-#pragma unroll
-    for (int i = 0; i < T::AP; ++i)
-        st.a[i] = *reinterpret_cast<const u32x4 *>(g.adj + (size_t)(w0 + row + T::RPP * i) * g.K + (size_t)ks * T::KS +
-                                                   kq * 8);
-    constexpr int XJ = T::KS / 8 / T::XG;
+// A wave's adjacency bits of one stage: for each 32-row MFMA tile rt, the
+// KS / 32 words of row (lane % 32) of that tile.
+template <int KS>
+struct ABits {
+    static constexpr int W = KS / 32;
+    static_assert(W == 2 || W == 4, "stage depth");
+    uint32_t w[RT][W];
+};
+
+template <int NP, int KS, int TT>
+__device__ __forceinline__ void load_stage(const GemmArgs &g, const __bf16 *planes, int ks, int b0, int tid,
+                                           Stage<NP, KS, TT> &st) {
+    using T = Stage<NP, KS, TT>;
     const int c = tid & (GN - 1), i0 = tid / GN; // k-groups i0, i0 + XG, ..., column c
 #pragma unroll
     for (int p = 0; p < NP; ++p)
 #pragma unroll
-        for (int j = 0; j < XJ; ++j)
-            st.x[p * XJ + j] = *reinterpret_cast<const u32x4 *>(
-                planes + (size_t)p * g.plane_elems + (((size_t)ks * (T::KS / 8) + i0 + T::XG * j) * g.B + b0 + c) * 8);
+        for (int j = 0; j < T::XJ; ++j)
+            st.x[p * T::XJ + j] = *reinterpret_cast<const u32x4 *>(
+                planes + (size_t)p * g.plane_elems + (((size_t)ks * (KS / 8) + i0 + T::XG * j) * g.B + b0 + c) * 8);
 }
 
-template <int NP, int KS, int BM>
-__device__ __forceinline__ void store_stage(__bf16 *sA, __bf16 *sX, int tid, const Stage<NP, KS, BM> &st) {
-    using T = Stage<NP, KS, BM>;
-    constexpr int SA = T::KS + 8, XJ = T::KS / 8 / T::XG;
-    const int row = tid / T::TPR, kq = tid % T::TPR;
+// rows0: the wave's first row.  Stage ks covers words (ks KS / 32) % 4 .. of
+// panel ks KS / 128: 16 B (one panel) or 8 B (half of one), aligned.
+template <int KS>
+__device__ __forceinline__ void load_abits(const GemmArgs &g, int ks, int rows0, int lane, ABits<KS> &ab) {
+    constexpr int SPP = 128 / KS; // stages per panel
 #pragma unroll
-    for (int i = 0; i < T::AP; ++i) *reinterpret_cast<u32x4 *>(sA + (row + T::RPP * i) * SA + kq * 8) = st.a[i];
+    for (int rt = 0; rt < RT; ++rt) {
+        const uint32_t *p = g.abits + ((size_t)(ks / SPP) * g.npad + rows0 + rt * 32 + (lane & 31)) * 4 +
+                            (ks % SPP) * ABits<KS>::W;
+        if constexpr (ABits<KS>::W == 4) {
+            const u32x4 v = *reinterpret_cast<const u32x4 *>(p);
+            ab.w[rt][0] = v[0];
+            ab.w[rt][1] = v[1];
+            ab.w[rt][2] = v[2];
+            ab.w[rt][3] = v[3];
+        } else {
+            const uint2 v = *reinterpret_cast<const uint2 *>(p);
+            ab.w[rt][0] = v.x;
+            ab.w[rt][1] = v.y;
+        }
+    }
+}
+
+template <int NP, int KS, int TT>
+__device__ __forceinline__ void store_stage(__bf16 *sX, int tid, const Stage<NP, KS, TT> &st) {
+    using T = Stage<NP, KS, TT>;
     const int c = tid & (GN - 1), i0 = tid / GN;
 #pragma unroll
     for (int p = 0; p < NP; ++p)
 #pragma unroll
-        for (int j = 0; j < XJ; ++j)
-            *reinterpret_cast<u32x4 *>(sX + (((size_t)p * (T::KS / 8) + i0 + T::XG * j) * GN + c) * 8) =
-                st.x[p * XJ + j];
+        for (int j = 0; j < T::XJ; ++j)
+            *reinterpret_cast<u32x4 *>(sX + (((size_t)p * (KS / 8) + i0 + T::XG * j) * GN + c) * 8) =
+                st.x[p * T::XJ + j];
 }
 
-// Wave (wr, wc) multiplies rows [WM wr, WM wr + WM) of the A tile by
-// columns [64 wc, 64 wc + 64) of each plane tile.
+// MFMA A operand (32 x 16 BF16, lane l: row l % 32, columns 8 (l / 32) .. +7)
+// from a word of bits: columns 16 h + 8 (l / 32) + j, j < 8, of the word's
+// half h are its pairs 8 h + 4 (l / 32) + j / 2, which the shift brings to
+// pairs 0 .. 3 (bits 0 .. 3 and 16 .. 19).
+__device__ __forceinline__ bf16x8 expand_bits(uint32_t w, int shift) {
+    const uint32_t y = w >> shift;
+    u32x4 o;
+    o[0] = __umul24(y & 0x10001u, 0x3F80u);
+    o[1] = __umul24(y & 0x20002u, 0x1FC0u);
+    o[2] = __umul24(y & 0x40004u, 0xFE0u);
+    o[3] = __umul24(y & 0x80008u, 0x7F0u);
+    return __builtin_bit_cast(bf16x8, o);
+}
+
+// The wave's rows (RT tiles of 32) by its two column tiles of 32 sources
+// starting at source wn of the block: A from the wave's bits, X from LDS.
 template <int NP, int KS>
-__device__ __forceinline__ void mma_stage(const __bf16 *sA, const __bf16 *sX, int lane, int wr, int wc,
+__device__ __forceinline__ void mma_stage(const __bf16 *sX, const ABits<KS> &ab, int lane, int wn,
                                           f32x16 (&acc)[RT][2]) {
-    constexpr int SA = KS + 8;
+    constexpr int CT = 2;
+    const int hs = (lane >> 5) * 4;
+    const __bf16 *x = sX + ((size_t)(lane >> 5) * GN + wn + (lane & 31)) * 8;
+    // B operands of k-step kh + 1 are read while step kh multiplies
+    bf16x8 b[2][NP][CT];
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+            b[0][p][ct] = *reinterpret_cast<const bf16x8 *>(x + ((size_t)p * (KS / 8) * GN + ct * 32) * 8);
 #pragma unroll
     for (int kh = 0; kh < KS / 16; ++kh) {
+        const int cur = kh & 1;
+        if (kh + 1 < KS / 16) {
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+#pragma unroll
+                for (int ct = 0; ct < CT; ++ct)
+                    b[cur ^ 1][p][ct] = *reinterpret_cast<const bf16x8 *>(
+                        x + (((size_t)p * (KS / 8) + (kh + 1) * 2) * GN + ct * 32) * 8);
+        }
+        __builtin_amdgcn_sched_barrier(0); // the reads stay ahead of this step's products
         bf16x8 a[RT];
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt)
-            a[rt] = *reinterpret_cast<const bf16x8 *>(sA + (wr * WM + rt * 32 + (lane & 31)) * SA + kh * 16 +
-                                                      (lane >> 5) * 8);
+        for (int rt = 0; rt < RT; ++rt) a[rt] = expand_bits(ab.w[rt][kh >> 1], hs + 8 * (kh & 1));
 #pragma unroll
-        for (int p = 0; p < NP; ++p) {
+        for (int p = 0; p < NP; ++p)
 #pragma unroll
-            for (int ct = 0; ct < 2; ++ct) {
-                const bf16x8 b = *reinterpret_cast<const bf16x8 *>(
-                    sX + (((size_t)p * (KS / 8) + kh * 2 + (lane >> 5)) * GN + wc * 64 + ct * 32 + (lane & 31)) * 8);
+            for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
                 for (int rt = 0; rt < RT; ++rt)
-                    acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[rt], b, acc[rt][ct], 0, 0, 0);
-            }
-        }
+                    acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[rt], b[cur][p][ct], acc[rt][ct], 0, 0, 0);
     }
 }
 
@@ -260,67 +314,94 @@ __device__ __forceinline__ Tile tile_of_split(int B, int &half, int &tile) {
     return Tile{__builtin_amdgcn_readfirstlane(row), __builtin_amdgcn_readfirstlane(col)};
 }
 
-// The next stage from ks on (of nks) with a non-zero flag among its TPS k-tiles.
+// Stages with a non-zero flag among their TPS k-tiles, 64 at a time: lane i
+// of each wave reads the flags of stage base + i, and the ballot is the
+// wave's window (one round trip per 64 stages, not one per stage).
 template <int TPS>
-__device__ __forceinline__ int next_stage(const uint32_t *flags, int ntn, int ks, int nks) {
-    for (; ks < nks; ++ks) {
-        uint32_t f = 0;
+__device__ __forceinline__ uint64_t stage_window(const uint32_t *flags, int ntn, int base, int nks, int lane) {
+    const int st = base + lane;
+    uint32_t f = 0;
+    if (st < nks) {
 #pragma unroll
-        for (int t = 0; t < TPS; ++t) f |= flags[((size_t)ks * TPS + t) * ntn];
-        if (f != 0) break;
+        for (int t = 0; t < TPS; ++t) f |= flags[((size_t)st * TPS + t) * ntn];
     }
-    return ks;
+    return __ballot(f != 0);
 }
 
-// LDS stages of the pipeline: two for one plane up to 64 deep, else one, so
-// that two blocks fit a compute unit.
-template <int NP, int KS>
-constexpr int stages() { return NP == 1 && KS <= 64 ? 2 : 1; }
+// The next stage from ks on (of nks) with a non-zero flag; [base, base + 64)
+// is the window in `bits`, refilled once ks passes it.
+template <int TPS>
+__device__ __forceinline__ int next_stage(const uint32_t *flags, int ntn, int ks, int nks, int lane, int &base,
+                                          uint64_t &bits) {
+    while (ks < nks) {
+        if (ks >= base + 64) {
+            base = ks;
+            bits = stage_window<TPS>(flags, ntn, base, nks, lane);
+        }
+        const uint64_t m = bits >> (ks - base);
+        if (m) return ks + __builtin_ctzll(m);
+        ks = base + 64;
+    }
+    return nks;
+}
 
 // acc[w][b] = sum over stages with a non-zero k-tile flag of A[w][k] X_p[k][b],
-// summed over the NP planes starting at `planes`, for the block's GM rows and
-// 128 sources; wave (wr, wc) holds rows w0 + WM wr + [0, WM) and sources
-// b0 + 64 wc + [0, 64).  The next stage's global loads are in flight (in
-// registers) during the current stage's products.  (Two register stages in
-// flight measured slower: the extra registers pushed the forward kernel into
-// AGPR spills.)  kt0 and kt1 are k-tiles, multiples of the stage's k-tiles.
+// summed over the NP planes starting at `planes`, for the block's BM rows
+// (from w0) and GN sources (from b0); wave wv holds rows w0 + WM (wv / WC) +
+// [0, WM) and sources b0 + WN (wv % WC) + [0, WN).  The next stage's planes
+// and bits are loaded (into registers) during the current stage's products.
+// kt0 and kt1 are k-tiles, multiples of the stage's k-tiles.
 template <int NP, int KS, int BM>
 __device__ __forceinline__ void gemm_tile(const GemmArgs &g, const __bf16 *planes, int w0, int b0, int tid,
-                                          __bf16 (*sA)[lds_a<KS, BM>()], __bf16 (*sX)[lds_x<NP, KS>()], f32x16 (&acc)[RT][2],
-                                          int kt0 = 0, int kt1 = -1) {
+                                          __bf16 (*sX)[lds_x<NP, KS>()], f32x16 (&acc)[RT][2], int kt0 = 0,
+                                          int kt1 = -1) {
     constexpr int TPS = KS / GK; // k-tiles per stage
-    const int lane = tid & 63, wv = tid >> 6, wr = wv >> 1, wc = wv & 1;
+    const int lane = tid & 63, wv = tid >> 6;
+    const int rows0 = w0 + (wv >> 1) * WM, wn = (wv & 1) * 64;
     const int nks = (kt1 < 0 ? g.K / GK : kt1) / TPS, ks0 = kt0 / TPS, ntn = g.B / GN;
     const uint32_t *flags = g.kflags + b0 / GN;
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct)
+        for (int c = 0; c < 2; ++c)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) acc[rt][ct][r] = 0.f;
+            for (int r = 0; r < 16; ++r) acc[rt][c][r] = 0.f;
 
-    int ks = next_stage<TPS>(flags, ntn, ks0, nks);
+    int wbase = ks0 - 64; // empty window
+    uint64_t wbits = 0;
+    int ks = next_stage<TPS>(flags, ntn, ks0, nks, lane, wbase, wbits);
+    int kn = ks < nks ? next_stage<TPS>(flags, ntn, ks + 1, nks, lane, wbase, wbits) : nks;
     int buf = 0, done = 0;
-    Stage<NP, KS, BM> st;
+    Stage<NP, KS, 2 * BM> st;
+    ABits<KS> ab, abn;
     if (ks < nks) {
-        load_stage<NP, KS, BM>(g, planes, ks, w0, b0, tid, st);
-        store_stage<NP, KS, BM>(sA[0], sX[0], tid, st);
+        // bits first: the planes' stores then wait for them too
+        load_abits<KS>(g, ks, rows0, lane, ab);
+        load_stage<NP, KS, 2 * BM>(g, planes, ks, b0, tid, st);
+        store_stage<NP, KS, 2 * BM>(sX[0], tid, st);
     }
     __syncthreads();
     while (ks < nks) {
-        const int kn = next_stage<TPS>(flags, ntn, ks + 1, nks);
-        if (kn < nks) load_stage<NP, KS, BM>(g, planes, kn, w0, b0, tid, st);
-        mma_stage<NP, KS>(sA[buf], sX[buf], lane, wr, wc, acc);
-        if constexpr (stages<NP, KS>() == 2) {
-            if (kn < nks) store_stage<NP, KS, BM>(sA[buf ^ 1], sX[buf ^ 1], tid, st);
+        // After the last stage the loads repeat the current one (in bounds,
+        // never multiplied): unconditional loads keep the waits for them
+        // after this stage's products.
+        const int kl = kn < nks ? kn : ks;
+        load_stage<NP, KS, 2 * BM>(g, planes, kl, b0, tid, st);
+        load_abits<KS>(g, kl, rows0, lane, abn);
+        __builtin_amdgcn_sched_barrier(0); // issued before the products, not sunk below them
+        mma_stage<NP, KS>(sX[buf], ab, lane, wn, acc);
+        if constexpr (stages<NP, KS, BM>() == 2) {
+            if (kn < nks) store_stage<NP, KS, 2 * BM>(sX[buf ^ 1], tid, st);
             __syncthreads();
             buf ^= 1;
         } else {
             __syncthreads(); // every wave is done with the stage
-            if (kn < nks) store_stage<NP, KS, BM>(sA[0], sX[0], tid, st);
+            if (kn < nks) store_stage<NP, KS, 2 * BM>(sX[0], tid, st);
             __syncthreads();
         }
+        ab = abn;
         ks = kn;
+        kn = kn < nks ? next_stage<TPS>(flags, ntn, kn + 1, nks, lane, wbase, wbits) : nks;
         ++done;
     }
     if (tid == 0 && g.ktiles) {
@@ -339,15 +420,14 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, const __bf16 *plane
 template <int T>
 __device__ __forceinline__ bool split_meet(const GemmArgs &g, int k, int tile, int half, int tid, int &s_last,
                                            f32x16 (&acc)[RT][2]) {
-    float *slot = g.ws + (((size_t)k * g.ntiles + tile) * 2) * 64 * T;
+    constexpr int V = RT * 2 * 16; // sums per thread
+    float *slot = g.ws + (((size_t)k * g.ntiles + tile) * 2) * V * T;
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
+    for (int i = 0; i < RT * 2; ++i)
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct)
-#pragma unroll
-            for (int r = 0; r < 16; ++r)
-                __hip_atomic_store(&slot[((size_t)half * 64 + (rt * 2 + ct) * 16 + r) * T + tid], acc[rt][ct][r],
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int r = 0; r < 16; ++r)
+            __hip_atomic_store(&slot[((size_t)half * V + i * 16 + r) * T + tid], acc[i / 2][i % 2][r],
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __asm__ __volatile__("s_waitcnt vmcnt(0)" ::: "memory"); // this thread's stores are done
     __syncthreads();
     if (tid == 0) {
@@ -358,20 +438,18 @@ __device__ __forceinline__ bool split_meet(const GemmArgs &g, int k, int tile, i
     __syncthreads();
     if (!s_last) return false;
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
+    for (int i = 0; i < RT * 2; ++i)
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct)
-#pragma unroll
-            for (int r = 0; r < 16; ++r)
-                acc[rt][ct][r] += __hip_atomic_load(&slot[((size_t)(1 - half) * 64 + (rt * 2 + ct) * 16 + r) * T + tid],
-                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int r = 0; r < 16; ++r)
+            acc[i / 2][i % 2][r] += __hip_atomic_load(&slot[((size_t)(1 - half) * V + i * 16 + r) * T + tid],
+                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return true;
 }
 
 // Forward epilogue for limb `shift / 8`; `mode` (uniform over the launch) says
 // whether it is the only limb, the first, a middle one or the last.  Lane
 // layout of the 32x32 output: lane l, register r holds row 8(r/4) + 4(l/32) +
-// r%4 and column l%32.
+// r%4 and column l%32; the two column tiles are bitmap word q.
 template <typename S>
 __device__ __forceinline__ void epi_fwd(const GemmArgs &g, const EpiArgs &e, int mode, int shift,
                                         const f32x16 (&acc)[RT][2], int w0, int q, int lane) {
@@ -459,9 +537,8 @@ __device__ __forceinline__ void epi_fwd(const GemmArgs &g, const EpiArgs &e, int
 // each followed by its epilogue.  Grid: grid_blocks<BM>(npad, B), tiles by tile_of.
 // KS: k per pipeline stage.
 template <typename S, int KS, int BM>
-__global__ __launch_bounds__(2 * BM, 2) void k_mfma_fwd(GemmArgs g, EpiArgs e) {
-    __shared__ __align__(16) __bf16 sA[stages<1, KS>()][lds_a<KS, BM>()];
-    __shared__ __align__(16) __bf16 sX[stages<1, KS>()][lds_x<1, KS>()];
+__global__ __launch_bounds__(2 * BM, BM == 128 ? 2 : 1) void k_mfma_fwd(GemmArgs g, EpiArgs e) {
+    __shared__ __align__(16) __bf16 sX[stages<1, KS, BM>()][lds_x<1, KS>()];
     __shared__ int s_last;
     int half = 0, tile = 0;
     const Tile tl = g.ksplit == 2 ? tile_of_split(g.B, half, tile) : tile_of(g.B);
@@ -475,7 +552,7 @@ __global__ __launch_bounds__(2 * BM, 2) void k_mfma_fwd(GemmArgs g, EpiArgs e) {
     f32x16 acc[RT][2];
 #pragma nounroll
     for (int k = 0; k < L; ++k) {
-        gemm_tile<1, KS, BM>(g, g.planes + (size_t)k * g.plane_elems, tl.row * BM, b0, tid, sA, sX, acc, kt0, kt1);
+        gemm_tile<1, KS, BM>(g, g.planes + (size_t)k * g.plane_elems, tl.row * BM, b0, tid, sX, acc, kt0, kt1);
         if (g.ksplit == 2 && !split_meet<2 * BM>(g, k, tile, half, tid, s_last, acc))
             continue; // the other half finishes it
         const int mode = L == 1 ? EPI_ONLY : k == 0 ? EPI_FIRST : k + 1 < L ? EPI_MID : EPI_LAST;
@@ -493,9 +570,8 @@ __global__ __launch_bounds__(2 * BM, 2) void k_mfma_fwd(GemmArgs g, EpiArgs e) {
 // delta(v,b) = lambda(v,b) * acc for v at level l, c(v,b) = (1 + delta) / lambda,
 // and BC(v) += delta summed over the block's sources (v != s_b).
 template <typename S>
-__global__ __launch_bounds__(GT, 2) void k_mfma_bwd(GemmArgs g, EpiArgs e) {
-    __shared__ __align__(16) __bf16 sA[stages<3, BWD_KS>()][lds_a<BWD_KS, BWD_BM>()];
-    __shared__ __align__(16) __bf16 sX[stages<3, BWD_KS>()][lds_x<3, BWD_KS>()];
+__global__ __launch_bounds__(2 * BWD_BM, BWD_BM == 128 ? 2 : 1) void k_mfma_bwd(GemmArgs g, EpiArgs e) {
+    __shared__ __align__(16) __bf16 sX[stages<3, BWD_KS, BWD_BM>()][lds_x<3, BWD_KS>()];
     // one block per tile: its stages of three planes are long enough already
     // (split in two halves of K it measured slower)
     if (g.gate && *g.gate == 0) return; // level l is empty (or the batch was handed back)
@@ -516,7 +592,7 @@ __global__ __launch_bounds__(GT, 2) void k_mfma_bwd(GemmArgs g, EpiArgs e) {
                 for (int r = 0; r < 16; ++r) acc[rt][ct][r] = 0.f;
     } else {
         if (blockIdx.x == 0 && tid == 0) atomicAdd(e.planes_issued, 3ull);
-        gemm_tile<3, BWD_KS, BWD_BM>(g, g.planes, tl.row * BWD_BM, b0, tid, sA, sX, acc);
+        gemm_tile<3, BWD_KS, BWD_BM>(g, g.planes, tl.row * BWD_BM, b0, tid, sX, acc);
     }
 
     const int w0 = tl.row * BWD_BM + (wv >> 1) * WM;
@@ -560,16 +636,18 @@ __global__ __launch_bounds__(PB) void k_zero32(uint32_t *__restrict__ p, size_t 
 }
 
 // A[v][(c-1) npad + w] = 1 for every arc v -> w of weight c (c = 1 without
-// weights).
-__global__ __launch_bounds__(PB) void k_build_adj(int32_t n, int32_t npad, int32_t K, const int32_t *__restrict__ rp,
+// weights), as bits of the panel layout: column k at bit (k % 2) 16 +
+// (k % 32) / 2 of word (k % 128) / 32 of row v in panel k / 128.
+__global__ __launch_bounds__(PB) void k_build_adj(int32_t n, int32_t npad, const int32_t *__restrict__ rp,
                                                   const int32_t *__restrict__ col, const uint8_t *__restrict__ wt,
-                                                  __bf16 *__restrict__ adj) {
+                                                  uint32_t *__restrict__ abits) {
     const int32_t v = blockIdx.x;
     if (v >= n) return;
-    const __bf16 one = (__bf16)1.0f;
     for (int32_t e = rp[v] + threadIdx.x; e < rp[v + 1]; e += PB) {
         const int32_t c = wt ? (int32_t)wt[e] - 1 : 0;
-        adj[(size_t)v * K + (size_t)c * npad + col[e]] = one;
+        const size_t k = (size_t)c * npad + col[e];
+        const uint32_t j = (uint32_t)(k & 31);
+        atomicOr(&abits[((k / 128) * npad + v) * 4 + (k % 128) / 32], 1u << ((j & 1) * 16 + (j >> 1)));
     }
 }
 
@@ -672,7 +750,7 @@ void clear_kflags(bc_ctx *ctx) {
 GemmArgs gemm_args(bc_ctx *ctx, const __bf16 *planes, bool forward) {
     AlgebraicState &a = ctx->al;
     GemmArgs g;
-    g.adj = a.adj;
+    g.abits = a.abits;
     g.planes = planes;
     g.kflags = a.kflags;
     g.npad = a.npad;
@@ -707,11 +785,11 @@ bc_status algebraic_prepare(bc_ctx *ctx) {
     a.npad = std::max(NPAD, (ctx->n + NPAD - 1) / NPAD * NPAD);
     a.classes = ctx->weighted ? (int32_t)ctx->max_weight : 1;
     const size_t K = (size_t)a.classes * a.npad;
-    const size_t adj_bytes = (size_t)a.npad * K * sizeof(__bf16);
-    if (adj_bytes > (size_t(96) << 30))
-        return bc_fail(ctx, BC_ERR_UNSUPPORTED, "algebraic form: the dense adjacency would exceed 96 GiB");
+    const size_t adj_bytes = (size_t)a.npad * K / 8;
     const size_t plane_elems = K * B;
-    a.adj = (__bf16 *)bc_dalloc(ctx, adj_bytes);
+    if (adj_bytes + 8 * plane_elems * sizeof(__bf16) > (size_t(96) << 30))
+        return bc_fail(ctx, BC_ERR_UNSUPPORTED, "algebraic form: the adjacency bits and planes would exceed 96 GiB");
+    a.abits = (uint32_t *)bc_dalloc(ctx, adj_bytes);
     a.planes = (__bf16 *)bc_dalloc(ctx, 8 * plane_elems * sizeof(__bf16)); // up to 8 limbs, or 3 coefficient planes
     a.part = (uint64_t *)bc_dalloc(ctx, (size_t)a.npad * B * sizeof(uint64_t));
     a.kflags = (uint32_t *)bc_dalloc(ctx, (K / GK) * (B / GN) * sizeof(uint32_t));
@@ -727,22 +805,22 @@ bc_status algebraic_prepare(bc_ctx *ctx) {
     // (grids are rounded up to whole rounds of the eight XCDs).
     a.fwd_rows = 128;
     const size_t ntiles = grid_blocks<128>(a.npad, B), ntiles256 = grid_blocks<256>(a.npad, B);
-    const size_t ws_elems = std::max(ntiles * 2 * 64 * (2 * 128), ntiles256 * 2 * 64 * (2 * 256));
+    const size_t ws_elems = std::max(ntiles * 2 * (RT * 2 * 16) * (2 * 128), ntiles256 * 2 * (RT * 2 * 16) * (2 * 256));
     const size_t ntiles_max = std::max(ntiles, ntiles256);
     a.ksplit = a.classes == 1 && K / GK >= 256 && ntiles < (size_t)256 * (256 / 128) ? 2 : 1;
     if (a.ksplit == 2) {
         a.ws = (float *)bc_dalloc(ctx, (size_t)8 * ws_elems * sizeof(float));
         a.arrive = (uint32_t *)bc_dalloc(ctx, (size_t)8 * ntiles_max * sizeof(uint32_t));
     }
-    if (!a.adj || !a.planes || !a.part || !a.kflags || !a.planes_issued ||
+    if (!a.abits || !a.planes || !a.part || !a.kflags || !a.planes_issued ||
         (a.ksplit == 2 && (!a.ws || !a.arrive)))
         return bc_fail(ctx, BC_ERR_NOMEM, "algebraic form: allocation failed");
     if (a.ksplit == 2) BC_HIP(ctx, hipMemsetAsync(a.arrive, 0, (size_t)8 * ntiles_max * sizeof(uint32_t), ctx->stream));
-    BC_HIP(ctx, hipMemsetAsync(a.adj, 0, adj_bytes, ctx->stream));
+    BC_HIP(ctx, hipMemsetAsync(a.abits, 0, adj_bytes, ctx->stream));
     BC_HIP(ctx, hipMemsetAsync(a.planes_issued, 0, 5 * sizeof(unsigned long long), ctx->stream));
     if (ctx->n > 0)
-        hipLaunchKernelGGL(k_build_adj, dim3(ctx->n), dim3(PB), 0, ctx->stream, ctx->n, a.npad, (int32_t)K,
-                           ctx->row_ptr, ctx->col, ctx->weighted ? (const uint8_t *)ctx->weight : nullptr, a.adj);
+        hipLaunchKernelGGL(k_build_adj, dim3(ctx->n), dim3(PB), 0, ctx->stream, ctx->n, a.npad,
+                           ctx->row_ptr, ctx->col, ctx->weighted ? (const uint8_t *)ctx->weight : nullptr, a.abits);
     BC_HIP(ctx, hipGetLastError());
     return BC_OK;
 }
@@ -750,7 +828,7 @@ bc_status algebraic_prepare(bc_ctx *ctx) {
 bc_status algebraic_release(bc_ctx *ctx) {
     AlgebraicState &a = ctx->al;
     BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    for (void *p : {(void *)a.adj, (void *)a.planes, (void *)a.part, (void *)a.kflags, (void *)a.planes_issued,
+    for (void *p : {(void *)a.abits, (void *)a.planes, (void *)a.part, (void *)a.kflags, (void *)a.planes_issued,
                     (void *)a.ws, (void *)a.arrive})
         if (p) bc_dfree(ctx, p);
     const bool every = a.every_level;
@@ -838,7 +916,8 @@ bc_status algebraic_backward_level_t(bc_ctx *ctx, const uint64_t *fcur, const ui
     GemmArgs g = gemm_args(ctx, a.planes, false);
     g.gate = gate;
     LaunchTimer tm(ctx, "mfma_bwd");
-    hipLaunchKernelGGL(k_mfma_bwd<S>, dim3(grid_blocks<BWD_BM>(a.npad, s.batch)), dim3(GT), 0, ctx->stream, g, e);
+    hipLaunchKernelGGL(k_mfma_bwd<S>, dim3(grid_blocks<BWD_BM>(a.npad, s.batch)), dim3(2 * BWD_BM), 0, ctx->stream,
+                       g, e);
     tm.done();
     BC_HIP(ctx, hipGetLastError());
     return BC_OK;

@@ -87,7 +87,7 @@ struct SparseState {
 struct AlgebraicState {
     int32_t npad = 0;                  // n rounded up to 256 (the product's row block)
     int32_t classes = 1;               // M: one 0/1 matrix per integer weight 1..M
-    __bf16 *adj = nullptr;             // [npad][M npad] 0/1, class c in columns [(c-1) npad, c npad)
+    uint32_t *abits = nullptr;         // [M npad / 128][npad][4] 0/1 bits in panels of 128 columns, class c in columns [(c-1) npad, c npad)
     __bf16 *planes = nullptr;          // up to 8 planes of [M npad/8][batch][8]
     uint64_t *part = nullptr;          // [npad][batch] partial limb sums
     uint32_t *kflags = nullptr;        // [M npad/32][batch/128] non-empty k-tiles
@@ -118,7 +118,7 @@ struct LevelProbe {
 // level (the fraction of vertices at level l for at least one source of the
 // batch) against thresholds fixed at create time.
 struct HybridState {
-    bool products = false;   // the dense adjacency exists and levels may use it
+    bool products = false;   // the adjacency bits exist and levels may use products
     double theta_fwd = 2.0;  // forward l -> l+1 by products when density(l) >= theta_fwd
     double theta_bwd = 2.0;  // backward l by products when density(l) >= theta_bwd
     std::vector<double> prev_density; // level densities of the last batch: the forward

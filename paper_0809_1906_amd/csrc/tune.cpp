@@ -4,7 +4,7 @@
 // this library's own addition.  Before any timed work, the tuner fixes
 //   * the batch width B of the sparse and hybrid forms;
 //   * the hybrid form's two density thresholds: forward level l -> l+1 (and
-//     backward level l) is computed by products with the dense adjacency
+//     backward level l) is computed by products with the adjacency matrix
 //     (Sec. 3.1) when the level's union-frontier density reaches the
 //     threshold, and by CSR pulls (the level sweep of Sec. 4) otherwise;
 //   * the rows of the adjacency one workgroup of the forward products takes
@@ -34,7 +34,9 @@ namespace {
 
 constexpr int32_t kTinyN = 2048;                    // smaller graphs take the defaults
 constexpr size_t kStateBudget = size_t(24) << 30;   // batch state allowed for a candidate width
-constexpr size_t kHybridAdjBudget = size_t(16) << 30; // dense adjacency allowed for the hybrid form
+// padded vertex count up to which the hybrid form considers products: one
+// product costs 2 B npad^2 flops whatever the level's size
+constexpr size_t kHybridMaxNpad = 92672;
 constexpr int kReps = 2;                            // timed calibration batches per width and mode
 constexpr double kSyncMs = 0.02;                    // host round trip per level of a stepwise forward
 constexpr double kNever = 2.0;                      // a threshold no density reaches
@@ -180,7 +182,7 @@ size_t state_bytes(int32_t n, int32_t batch) {
 bool products_possible(const bc_ctx *ctx) {
     if (ctx->weighted || ctx->max_degree > BC_ALGEBRAIC_MAX_DEGREE) return false;
     const size_t npad = (size_t)std::max(256, (ctx->n + 255) / 256 * 256);
-    return npad * npad * 2 <= kHybridAdjBudget;
+    return npad <= kHybridMaxNpad;
 }
 
 bc_status prepare_width(bc_ctx *ctx, int32_t batch, int32_t split, bool products) {
