@@ -458,15 +458,22 @@ __device__ __forceinline__ void epi_fwd(const GemmArgs &g, const EpiArgs &e, int
     const bool final_limb = mode == EPI_ONLY || last;
     S *sigma = reinterpret_cast<S *>(e.sigma);
     bool wide = false, ovf = false;
-    uint64_t mx = 0;
+    uint64_t mx = 0, any_rows = 0;
     uint32_t fresh_pairs = 0;
+    // The wave owns word q of its 64 rows: lane l loads row w0 + l's visited
+    // word once, and each row's lanes take it by a shuffle (no global round
+    // trip per row; the loop's stores to visited would otherwise keep the
+    // compiler from issuing these loads ahead of them).
+    const uint64_t vis_lane =
+        (!first && w0 + lane < g.n) ? e.visited[(size_t)(w0 + lane) * g.NW + q] : ~0ull;
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            const int w = w0 + rt * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+            const int lr = rt * 32 + 8 * (r >> 2) + 4 * half + (r & 3); // row in the wave
+            const int w = w0 + lr;
             const bool valid = w < g.n;
-            const uint64_t vis = (!first && valid) ? e.visited[(size_t)w * g.NW + q] : ~0ull;
+            const uint64_t vis = __shfl(vis_lane, lr, 64);
             uint64_t m[2];
 #pragma unroll
             for (int ct = 0; ct < 2; ++ct) {
@@ -509,7 +516,7 @@ __device__ __forceinline__ void epi_fwd(const GemmArgs &g, const EpiArgs &e, int
                     e.fnext[(size_t)w * g.NW + q] = word;
                     if (word) {
                         e.visited[(size_t)w * g.NW + q] = vis | word;
-                        atomicOr(&e.any_next[w >> 5], 1u << (w & 31));
+                        any_rows |= 1ull << lr;
                         fresh_pairs += (uint32_t)__popcll(word);
                     }
                 }
@@ -525,6 +532,13 @@ __device__ __forceinline__ void epi_fwd(const GemmArgs &g, const EpiArgs &e, int
         if (lane == 0 && mx > __hip_atomic_load(e.lvmax_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
             atomicMax(e.lvmax_next, (unsigned long long)mx);
         if (__any(wide) && lane == 0) atomicOr(&e.status[1], 1u);
+        // rows with new pairs, two words of the level's vertex filter per wave
+        // (w0 is a multiple of 64)
+        any_rows |= __shfl_xor(any_rows, 32, 64);
+        if (lane == 0 && any_rows) {
+            if ((uint32_t)any_rows) atomicOr(&e.any_next[w0 >> 5], (uint32_t)any_rows);
+            if (any_rows >> 32) atomicOr(&e.any_next[(w0 >> 5) + 1], (uint32_t)(any_rows >> 32));
+        }
         if (e.reach) { // lanes 0 and 32 hold the counts
             fresh_pairs += __shfl_xor(fresh_pairs, 32, 64);
             if (lane == 0 && fresh_pairs) atomicAdd(&e.reach[1], (unsigned long long)fresh_pairs);
@@ -599,12 +613,15 @@ __global__ __launch_bounds__(2 * BWD_BM, BWD_BM == 128 ? 2 : 1) void k_mfma_bwd(
     const int q = (b0 >> 6) + (wv & 1);
     const int half = lane >> 5, col = lane & 31;
     S *sigma = reinterpret_cast<S *>(e.sigma);
+    // level-l words of the wave's 64 rows, one load per lane (as in the forward)
+    const uint64_t f_lane = w0 + lane < g.n ? e.fcur[(size_t)(w0 + lane) * g.NW + q] : 0;
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            const int v = w0 + rt * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
-            const uint64_t F = v < g.n ? e.fcur[(size_t)v * g.NW + q] : 0;
+            const int lr = rt * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+            const int v = w0 + lr;
+            const uint64_t F = __shfl(f_lane, lr, 64);
             double contrib = 0.0;
 #pragma unroll
             for (int ct = 0; ct < 2; ++ct) {
