@@ -568,7 +568,7 @@ def main():
         ctx = bcgpu.BC(wl["graph"], form="auto" if form == "many" else form, batch=batch, timing=timing,
                        edges=edges, host_driven=host_driven)
         info = ctx.info()
-        log(f"{form} create (upload, dense adjacency, tuning) {time.perf_counter() - t:.2f}s: batch {info.batch}, "
+        log(f"{form} create (upload, adjacency bits, tuning) {time.perf_counter() - t:.2f}s: batch {info.batch}, "
             f"products when density >= ({info.mfma_density_fwd:.3f} fwd, {info.mfma_density_bwd:.3f} bwd), "
             f"tuning source {info.tune_source}")
         for i in range(warmup):

@@ -83,7 +83,7 @@ struct SparseState {
     double *hacc = nullptr;      // [nheavy][batch] partial sums of split rows (u64 or f64)
 };
 
-// State of the algebraic form (dense adjacency products on MFMA).
+// State of the algebraic form (products with the adjacency matrix on MFMA).
 struct AlgebraicState {
     int32_t npad = 0;                  // n rounded up to 256 (the product's row block)
     int32_t classes = 1;               // M: one 0/1 matrix per integer weight 1..M
@@ -114,7 +114,7 @@ struct LevelProbe {
 };
 
 // Hybrid form: each level l >= 1 goes by CSR pulls or by products with the
-// dense adjacency, chosen per batch from the union-frontier density of the
+// adjacency matrix, chosen per batch from the union-frontier density of the
 // level (the fraction of vertices at level l for at least one source of the
 // batch) against thresholds fixed at create time.
 struct HybridState {

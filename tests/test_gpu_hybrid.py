@@ -1,7 +1,7 @@
 """GPU parity of the hybrid form and of the tuner that configures it.
 
 The hybrid form takes each level l >= 1 either by CSR pulls (the level sweep
-of Sec. 4) or by products with the dense adjacency (Sec. 3.1), from the
+of Sec. 4) or by products with the adjacency matrix (Sec. 3.1), from the
 level's union-frontier density against two thresholds.  Whatever the mix,
 distances and path counts must equal the oracle's bit for bit and BC must stay
 within the FP32-state tolerance.  Thresholds are forced through the tuning

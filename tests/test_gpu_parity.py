@@ -175,7 +175,7 @@ def test_rmat16_full_size_sampled(gpu_lib):
 
 
 def test_rmat16_algebraic_form_sampled(gpu_lib):
-    """The algebraic form (products with the dense adjacency on MFMA) at the
+    """The algebraic form (products with the adjacency matrix on MFMA) at the
     benchmark's full size: one batch of per-source results, and BC over a
     ragged two-batch source list."""
     g = gg.rmat16()
