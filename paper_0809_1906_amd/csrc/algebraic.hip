@@ -43,11 +43,12 @@
 // of a row's panel holds the panel's columns 32i .. 32i + 31, column 32i + 2p
 // at bit p and 32i + 2p + 1 at bit 16 + p (p < 16): masked with 0x10001 << p
 // and multiplied by 0x3F80 >> p, a word gives the BF16 pair (0 or 1, 0 or 1)
-// of columns 2p, 2p + 1 in one 24-bit multiply.  Each wave loads the bits of its own
-// rows into registers and expands them into MFMA A operands there: the
-// adjacency costs 1/16 of a BF16 matrix's bytes and no LDS traffic, and LDS
-// holds only the planes, which the block's waves share.  Planes are k-packed: plane[v / 8][b][v % 8], so each
-// MFMA B-operand lane reads 16 contiguous bytes.  Every product is
+// of columns 2p, 2p + 1 in one 24-bit multiply.  Each wave loads the bits of
+// its own rows into registers and expands them into MFMA A operands there:
+// the adjacency costs 1/16 of a BF16 matrix's bytes and no LDS traffic, and
+// LDS holds only the planes, which the block's waves share.  Planes are
+// k-packed, plane[v / 8][b][v % 8], so each MFMA B-operand lane reads 16
+// contiguous bytes.  Every product is
 // C[w][b] = sum_v A[w][v] X[v][b] with rows = vertices and columns = sources;
 // in the 32x32 MFMA output the 32 lanes of each half-wave hold 32 consecutive
 // sources of one vertex, so two ballots give a 64-bit frontier word.
@@ -576,7 +577,7 @@ __global__ __launch_bounds__(2 * BM, BM == 128 ? 2 : 1) void k_mfma_fwd(GemmArgs
         int w0k = w0;
         __asm__ volatile("" : "+s"(w0k));
         epi_fwd<S>(g, e, mode, 8 * k, acc, w0k, q, lane);
-        __syncthreads(); // the next limb's pipeline reuses the LDS tiles
+        __syncthreads(); // the next limb's pipeline reuses the LDS buffers
     }
 }
 
