@@ -92,8 +92,12 @@ def check_ktiles(info, g, batch):
 
 
 CASES = {
-    # K split in two halves per output tile (few tiles: npad 4096, batch 256)
-    "er4096_split": (lambda: gg.er_plus_tree(4096, 16.0, 12, name="er4096"), 256),
+    # npad 4096, batch 256: 128 tiles of 128 rows, K whole in each block
+    "er4096": (lambda: gg.er_plus_tree(4096, 16.0, 12, name="er4096"), 256),
+    # K split in two halves per output tile (K = npad = 12032 >= 8192 with
+    # fewer than 512 tiles): both block shapes meet through the split
+    # workspace, 256-row blocks with half as many tiles
+    "er12000_split": (lambda: gg.er_plus_tree(12000, 48.0, 77), 128),
     # weight classes 1..4: K = 4 npad, no split
     "er2100w4": (lambda: gg.with_uniform_weights(gg.er_plus_tree(2100, 12.0, 13), 14, 1, 4), 256),
     # a small graph (one tile row of 256) at batch 512
