@@ -175,10 +175,12 @@ struct Stage {
 };
 
 // A wave's adjacency bits of one stage: for each 32-row MFMA tile rt, the
-// KS / 32 words of row (lane % 32) of that tile.
-template <int KS>
+// words of row (lane % 32) of that tile that the wave multiplies: the stage's
+// KS / 32, or with the stage's k range split between the two waves of a row
+// pair (KH), the KS / 64 of the wave's half.
+template <int KS, bool KH>
 struct ABits {
-    static constexpr int W = KS / 32;
+    static constexpr int W = KH ? KS / 64 : KS / 32;
     static_assert(W == 2 || W == 4, "stage depth");
     uint32_t w[RT][W];
 };
@@ -197,15 +199,17 @@ __device__ __forceinline__ void load_stage(const GemmArgs &g, const __bf16 *plan
 }
 
 // rows0: the wave's first row.  Stage ks covers words (ks KS / 32) % 4 .. of
-// panel ks KS / 128: 16 B (one panel) or 8 B (half of one), aligned.
-template <int KS>
-__device__ __forceinline__ void load_abits(const GemmArgs &g, int ks, int rows0, int lane, ABits<KS> &ab) {
+// panel ks KS / 128 (half of them per wave with KH): 16 B or 8 B, aligned.
+template <int KS, bool KH>
+__device__ __forceinline__ void load_abits(const GemmArgs &g, int ks, int rows0, int lane, int half,
+                                           ABits<KS, KH> &ab) {
     constexpr int SPP = 128 / KS; // stages per panel
+    constexpr int W = ABits<KS, KH>::W;
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
         const uint32_t *p = g.abits + ((size_t)(ks / SPP) * g.npad + rows0 + rt * 32 + (lane & 31)) * 4 +
-                            (ks % SPP) * ABits<KS>::W;
-        if constexpr (ABits<KS>::W == 4) {
+                            (ks % SPP) * (KS / 32) + (KH ? half * W : 0);
+        if constexpr (W == 4) {
             const u32x4 v = *reinterpret_cast<const u32x4 *>(p);
             ab.w[rt][0] = v[0];
             ab.w[rt][1] = v[1];
@@ -245,14 +249,17 @@ __device__ __forceinline__ bf16x8 expand_bits(uint32_t w, int shift) {
     return __builtin_bit_cast(bf16x8, o);
 }
 
-// The wave's rows (RT tiles of 32) by its two column tiles of 32 sources
+// The wave's rows (RT tiles of 32) by its CT column tiles of 32 sources
 // starting at source wn of the block: A from the wave's bits, X from LDS.
-template <int NP, int KS>
-__device__ __forceinline__ void mma_stage(const __bf16 *sX, const ABits<KS> &ab, int lane, int wn,
-                                          f32x16 (&acc)[RT][2]) {
-    constexpr int CT = 2;
+// Without KH the wave multiplies the stage's KS / 16 k-steps for 64 sources
+// (CT = 2); with KH, its half of them (from k-step half KS / 32) for all 128
+// sources (CT = 4).
+template <int NP, int KS, bool KH>
+__device__ __forceinline__ void mma_stage(const __bf16 *sX, const ABits<KS, KH> &ab, int lane, int wn, int half,
+                                          f32x16 (&acc)[RT][KH ? 4 : 2]) {
+    constexpr int CT = KH ? 4 : 2, STEPS = KH ? KS / 32 : KS / 16;
     const int hs = (lane >> 5) * 4;
-    const __bf16 *x = sX + ((size_t)(lane >> 5) * GN + wn + (lane & 31)) * 8;
+    const __bf16 *x = sX + (((size_t)(KH ? half * STEPS * 2 : 0) + (lane >> 5)) * GN + wn + (lane & 31)) * 8;
     // B operands of k-step kh + 1 are read while step kh multiplies
     bf16x8 b[2][NP][CT];
 #pragma unroll
@@ -261,9 +268,9 @@ __device__ __forceinline__ void mma_stage(const __bf16 *sX, const ABits<KS> &ab,
         for (int ct = 0; ct < CT; ++ct)
             b[0][p][ct] = *reinterpret_cast<const bf16x8 *>(x + ((size_t)p * (KS / 8) * GN + ct * 32) * 8);
 #pragma unroll
-    for (int kh = 0; kh < KS / 16; ++kh) {
+    for (int kh = 0; kh < STEPS; ++kh) {
         const int cur = kh & 1;
-        if (kh + 1 < KS / 16) {
+        if (kh + 1 < STEPS) {
 #pragma unroll
             for (int p = 0; p < NP; ++p)
 #pragma unroll
@@ -352,19 +359,19 @@ __device__ __forceinline__ int next_stage(const uint32_t *flags, int ntn, int ks
 // [0, WM) and sources b0 + WN (wv % WC) + [0, WN).  The next stage's planes
 // and bits are loaded (into registers) during the current stage's products.
 // kt0 and kt1 are k-tiles, multiples of the stage's k-tiles.
-template <int NP, int KS, int BM>
+template <int NP, int KS, int BM, bool KH = false>
 __device__ __forceinline__ void gemm_tile(const GemmArgs &g, const __bf16 *planes, int w0, int b0, int tid,
-                                          __bf16 (*sX)[lds_x<NP, KS>()], f32x16 (&acc)[RT][2], int kt0 = 0,
+                                          __bf16 (*sX)[lds_x<NP, KS>()], f32x16 (&acc)[RT][KH ? 4 : 2], int kt0 = 0,
                                           int kt1 = -1) {
     constexpr int TPS = KS / GK; // k-tiles per stage
-    const int lane = tid & 63, wv = tid >> 6;
-    const int rows0 = w0 + (wv >> 1) * WM, wn = (wv & 1) * 64;
+    const int lane = tid & 63, wv = tid >> 6, half = wv & 1;
+    const int rows0 = w0 + (wv >> 1) * WM, wn = KH ? 0 : half * 64;
     const int nks = (kt1 < 0 ? g.K / GK : kt1) / TPS, ks0 = kt0 / TPS, ntn = g.B / GN;
     const uint32_t *flags = g.kflags + b0 / GN;
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-        for (int c = 0; c < 2; ++c)
+        for (int c = 0; c < (KH ? 4 : 2); ++c)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[rt][c][r] = 0.f;
 
@@ -374,10 +381,10 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, const __bf16 *plane
     int kn = ks < nks ? next_stage<TPS>(flags, ntn, ks + 1, nks, lane, wbase, wbits) : nks;
     int buf = 0, done = 0;
     Stage<NP, KS, 2 * BM> st;
-    ABits<KS> ab, abn;
+    ABits<KS, KH> ab, abn;
     if (ks < nks) {
         // bits first: the planes' stores then wait for them too
-        load_abits<KS>(g, ks, rows0, lane, ab);
+        load_abits<KS, KH>(g, ks, rows0, lane, half, ab);
         load_stage<NP, KS, 2 * BM>(g, planes, ks, b0, tid, st);
         store_stage<NP, KS, 2 * BM>(sX[0], tid, st);
     }
@@ -388,9 +395,9 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, const __bf16 *plane
         // after this stage's products.
         const int kl = kn < nks ? kn : ks;
         load_stage<NP, KS, 2 * BM>(g, planes, kl, b0, tid, st);
-        load_abits<KS>(g, kl, rows0, lane, abn);
+        load_abits<KS, KH>(g, kl, rows0, lane, half, abn);
         __builtin_amdgcn_sched_barrier(0); // issued before the products, not sunk below them
-        mma_stage<NP, KS>(sX[buf], ab, lane, wn, acc);
+        mma_stage<NP, KS, KH>(sX[buf], ab, lane, wn, half, acc);
         if constexpr (stages<NP, KS, BM>() == 2) {
             if (kn < nks) store_stage<NP, KS, 2 * BM>(sX[buf ^ 1], tid, st);
             __syncthreads();
@@ -550,10 +557,20 @@ __device__ __forceinline__ void epi_fwd(const GemmArgs &g, const EpiArgs &e, int
 
 // Forward level l -> l+1: one pass per 8-bit limb of level l's largest count,
 // each followed by its epilogue.  Grid: grid_blocks<BM>(npad, B), tiles by tile_of.
-// KS: k per pipeline stage.
+// KS: k per pipeline stage.  The two waves of a row pair split each stage's
+// k range (each expands only its half of the adjacency bits, for all 128
+// sources) and sum the halves through LDS before the epilogue: half the bit
+// expansion of waves that each take 64 sources (ER-16384: 247 -> 233 us per
+// launch with 128-row blocks).
 template <typename S, int KS, int BM>
 __global__ __launch_bounds__(2 * BM, BM == 128 ? 2 : 1) void k_mfma_fwd(GemmArgs g, EpiArgs e) {
-    __shared__ __align__(16) __bf16 sX[stages<1, KS, BM>()][lds_x<1, KS>()];
+    constexpr bool KH = true; // the waves' k-split (the backward keeps the column split)
+    // one LDS area: the plane buffers during the products, then the halves'
+    // exchange (64 sums per lane per wave)
+    constexpr size_t PLANE_BYTES = (size_t)stages<1, KS, BM>() * lds_x<1, KS>() * sizeof(__bf16);
+    constexpr size_t XCHG_BYTES = KH ? (size_t)2 * BM / 64 * 64 * RT * 2 * 16 * sizeof(float) : 0;
+    __shared__ __align__(16) unsigned char smem[PLANE_BYTES > XCHG_BYTES ? PLANE_BYTES : XCHG_BYTES];
+    auto sX = reinterpret_cast<__bf16 (*)[lds_x<1, KS>()]>(smem);
     __shared__ int s_last;
     int half = 0, tile = 0;
     const Tile tl = g.ksplit == 2 ? tile_of_split(g.B, half, tile) : tile_of(g.B);
@@ -567,7 +584,54 @@ __global__ __launch_bounds__(2 * BM, BM == 128 ? 2 : 1) void k_mfma_fwd(GemmArgs
     f32x16 acc[RT][2];
 #pragma nounroll
     for (int k = 0; k < L; ++k) {
-        gemm_tile<1, KS, BM>(g, g.planes + (size_t)k * g.plane_elems, tl.row * BM, b0, tid, sX, acc, kt0, kt1);
+        if constexpr (KH) {
+            f32x16 acc4[RT][4];
+            gemm_tile<1, KS, BM, true>(g, g.planes + (size_t)k * g.plane_elems, tl.row * BM, b0, tid, sX, acc4, kt0,
+                                       kt1);
+            // wave wv keeps sources 64 h .. 64 h + 63 (h = wv & 1, its bitmap
+            // word) and hands the other 64 to its partner wv ^ 1; the tile
+            // loop ended at a barrier, so the plane buffers are free
+            // (h is uniform over the wave: constant tile indices in each
+            // branch keep acc4 in registers)
+            float *xb = reinterpret_cast<float *>(smem);
+            float *mine = xb + (size_t)wv * RT * 2 * 16 * 64 + lane;
+            const float *theirs = xb + (size_t)(wv ^ 1) * RT * 2 * 16 * 64 + lane;
+            if (wv & 1) {
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) mine[((rt * 2 + c) * 16 + r) * 64] = acc4[rt][c][r];
+            } else {
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) mine[((rt * 2 + c) * 16 + r) * 64] = acc4[rt][2 + c][r];
+            }
+            __syncthreads();
+            if (wv & 1) {
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r)
+                            acc[rt][c][r] = acc4[rt][2 + c][r] + theirs[((rt * 2 + c) * 16 + r) * 64];
+            } else {
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r)
+                            acc[rt][c][r] = acc4[rt][c][r] + theirs[((rt * 2 + c) * 16 + r) * 64];
+            }
+        } else {
+            gemm_tile<1, KS, BM>(g, g.planes + (size_t)k * g.plane_elems, tl.row * BM, b0, tid, sX, acc, kt0, kt1);
+        }
         if (g.ksplit == 2 && !split_meet<2 * BM>(g, k, tile, half, tid, s_last, acc))
             continue; // the other half finishes it
         const int mode = L == 1 ? EPI_ONLY : k == 0 ? EPI_FIRST : k + 1 < L ? EPI_MID : EPI_LAST;
