@@ -627,7 +627,9 @@ def main():
                                           "batch, instead of replaying the recorded batch"}
     if not args.no_compare:
         for cform, cbatch in spec["compare"]:
-            cctx, cdt, bc_c = timed_runs(cform, args.compare_steps, 0, cbatch)
+            # a batched form records its replayed batch in its first step:
+            # one untimed step first (the plain form has nothing to record)
+            cctx, cdt, bc_c = timed_runs(cform, args.compare_steps, 0 if cform == "plain" else 1, cbatch)
             cinfo = cctx.info()
             ckern = {k: cctx.timing(k)[0] for k in KERNELS if cctx.timing(k)[1]}
             cctx.close()

@@ -361,7 +361,11 @@ typedef struct {
     int64_t sources_run; /* sources accumulated since create / reset */
     int64_t device_bytes;/* device memory the context holds */
     double mfma_density_fwd; /* hybrid form: forward level l -> l+1 by products when
-                                density(l) >= this (above 1: never) */
+                                density(l) >= this (above 1: never); 0 for both
+                                directions in the every-level mode (every level
+                                by products and the algebraic form's end of
+                                search), which the tuner keeps when whole
+                                batches with it are faster */
     double mfma_density_bwd; /* hybrid form: backward level l by products when
                                 density(l) >= this (above 1: never) */
     int32_t tune_source;     /* BC_TUNE_* for the tuned choices: batch width and

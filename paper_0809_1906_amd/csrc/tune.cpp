@@ -7,6 +7,9 @@
 //     backward level l) is computed by products with the adjacency matrix
 //     (Sec. 3.1) when the level's union-frontier density reaches the
 //     threshold, and by CSR pulls (the level sweep of Sec. 4) otherwise;
+//   * for the hybrid form, also whole batches with every level by products
+//     (the algebraic form's mode, whose products count the pairs they reach
+//     and so skip the empty level that ends a search), kept when faster;
 //   * the rows of the adjacency one workgroup of the forward products takes
 //     (128 or 256), for the algebraic form and a hybrid form with forward
 //     products;
@@ -40,6 +43,9 @@ constexpr size_t kHybridMaxNpad = 92672;
 constexpr int kReps = 2;                            // timed calibration batches per width and mode
 constexpr double kSyncMs = 0.02;                    // host round trip per level of a stepwise forward
 constexpr double kNever = 2.0;                      // a threshold no density reaches
+// thresholds of the hybrid form's every-level mode in the cache file: every
+// level l >= 1 by products, with the end of search the algebraic form has
+constexpr double kEvery = -1.0;
 constexpr double kAccept = 0.97;                    // a mix must beat pulls by 3% to be kept
 constexpr int kConfirm = 3;                         // alternating whole-batch comparisons of a mix
 constexpr double kManySampleWork = 3e9;             // many graphs: sum of n_g (n_g + arcs_g) one timed launch takes
@@ -183,6 +189,19 @@ bool products_possible(const bc_ctx *ctx) {
     if (ctx->weighted || ctx->max_degree > BC_ALGEBRAIC_MAX_DEGREE) return false;
     const size_t npad = (size_t)std::max(256, (ctx->n + 255) / 256 * 256);
     return npad <= kHybridMaxNpad;
+}
+
+// The hybrid form in its every-level mode: every level l >= 1 by products and
+// the end of search (thresholds read 0: every density reaches them).  Edge
+// betweenness needs the per-arc pulls in the backward, so a context with
+// edges keeps pulls at every level instead.
+void set_every_level(bc_ctx *ctx) {
+    if (ctx->edges) {
+        ctx->hy.theta_fwd = ctx->hy.theta_bwd = kNever;
+        return;
+    }
+    ctx->hy.theta_fwd = ctx->hy.theta_bwd = 0.0;
+    ctx->al.every_level = true;
 }
 
 bc_status prepare_width(bc_ctx *ctx, int32_t batch, int32_t split, bool products) {
@@ -398,6 +417,7 @@ bc_status tune_prepare(bc_ctx *ctx, const bc_options &opt, bc_form form) {
         if (st != BC_OK) return st;
         ctx->hy.theta_fwd = products ? r.theta_fwd : kNever;
         ctx->hy.theta_bwd = products ? r.theta_bwd : kNever;
+        if (products && r.theta_fwd < 0.0) set_every_level(ctx);
         if (products) ctx->al.fwd_rows = r.fwd_rows ? r.fwd_rows : 128;
         ctx->hy.tune_source = BC_TUNE_CACHED;
         return BC_OK;
@@ -460,6 +480,26 @@ bc_status tune_prepare(bc_ctx *ctx, const bc_options &opt, bc_form form) {
                 ms = pulls / kConfirm;
             }
         }
+        if (products && !ctx->edges) {
+            // every level by products against the choice above, alternately
+            double every = 0.0, chosen = 0.0;
+            for (int rep = 0; rep < kConfirm && st == BC_OK; ++rep) {
+                double a = 0.0, b = 0.0;
+                ctx->al.every_level = true;
+                st = run_mode(ctx, d_src, w, kPlainMixed, cal, &a);
+                ctx->al.every_level = false;
+                ctx->hy.theta_fwd = tf;
+                ctx->hy.theta_bwd = tb;
+                if (st == BC_OK) st = run_mode(ctx, d_src, w, tf <= 1.0 || tb <= 1.0 ? kPlainMixed : kPlainPulls, cal, &b);
+                every += a;
+                chosen += b;
+            }
+            if (st != BC_OK) break;
+            if (every < kAccept * chosen) {
+                tf = tb = kEvery;
+                ms = every / kConfirm;
+            }
+        }
         if (best_w == 0 || ms < best_ms) {
             best_ms = ms;
             best_w = w;
@@ -473,6 +513,7 @@ bc_status tune_prepare(bc_ctx *ctx, const bc_options &opt, bc_form form) {
     }
     ctx->hy.theta_fwd = best_tf;
     ctx->hy.theta_bwd = best_tb;
+    if (best_tf < 0.0) set_every_level(ctx);
     // forward products in use: their block rows too
     if (st == BC_OK && products && best_tf <= 1.0) st = pick_fwd_rows(ctx, d_src, best_w, &rows);
     bc_dfree(ctx, d_src);

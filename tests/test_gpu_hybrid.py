@@ -180,3 +180,53 @@ def test_rmat16_hybrid_sampled(gpu_lib):
         ctx.run(sub)
         got = ctx.read()
     assert rel_err(got, oracle.bc(g, sub, threads=8)) <= TOL
+
+
+# The every-level mode: thresholds -1 in the cache (what the tuner writes when
+# whole batches with every level by products beat its per-level choice) give
+# the algebraic form's run inside the hybrid form, end of search included.
+@pytest.mark.parametrize("name", ["er1024", "grid20", "union", "path33"])
+def test_hybrid_every_level_mode(gpu_lib, tmp_path, name):
+    """Forced every-level mode: reported thresholds 0 / 0, BC and per-source
+    results as the oracle's, and the forward's k-tiles the same as the
+    algebraic form's on the same sources (the empty last level is skipped)."""
+    g = graphs()[name]
+    say("hybrid_every", name)
+    path = str(tmp_path / "tune.txt")
+    force_thresholds(gpu_lib, g, path, -1.0, -1.0)
+    rng = gg.Stream(91)
+    src = np.concatenate([np.arange(3), rng.bounded(np.full(120, g.n))]).astype(np.int32)
+    with gpu_lib.BC(g, form="hybrid", batch=256, tune_cache=path) as ctx:
+        info = ctx.info()
+        assert info.tune_source == gpu_lib.BC_TUNE_CACHED
+        assert info.mfma_density_fwd == 0.0 and info.mfma_density_bwd == 0.0
+        ctx.run(src)
+        got = ctx.read()
+        hy = ctx.info()
+        dist, sigma, delta = ctx.sssp(src[:64])
+    with gpu_lib.BC(g, form="algebraic", batch=256) as ctx:
+        ctx.run(src)
+        al = ctx.info()
+    assert hy.mfma_ktiles_dense_fwd == al.mfma_ktiles_dense_fwd
+    assert rel_err(got, oracle.bc(g, src)) <= TOL
+    for i in range(0, 64, 5):
+        d, sg, dl = oracle.sssp_u64(g, int(src[i]))
+        assert np.array_equal(dist[i], d) and np.array_equal(sigma[i], sg), f"source {src[i]}"
+        assert rel_err(delta[i], dl) <= TOL
+
+
+def test_hybrid_every_level_mode_not_with_edges(gpu_lib, tmp_path):
+    """Edge betweenness needs the per-arc pulls: a context with edges reads the
+    every-level entry as pulls at every level, and its edge BC is the
+    oracle's."""
+    g = graphs()["er1024"]
+    path = str(tmp_path / "tune.txt")
+    force_thresholds(gpu_lib, g, path, -1.0, -1.0)
+    want_bc, want_eb = oracle.edge_bc(g)
+    with gpu_lib.BC(g, form="hybrid", batch=256, tune_cache=path, edges=True) as ctx:
+        info = ctx.info()
+        assert info.mfma_density_fwd == 2.0 and info.mfma_density_bwd == 2.0
+        ctx.run()
+        got_bc, got_eb = ctx.read(), ctx.read_edges()
+        assert ctx.info().mfma_planes == 0
+    assert rel_err(got_bc, want_bc) <= TOL and rel_err(got_eb, want_eb) <= TOL
