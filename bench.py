@@ -58,6 +58,7 @@ import numpy as np  # noqa: E402
 METRIC = "BC TEPS (sources·m/s) on RMAT-16; batched-MFMA vs plain BFS form, same GPU"
 HBM_PEAK_GBS = 8000.0
 MFMA_BF16_PEAK_TFS = 2500.0
+MFMA_I8_PEAK_TOPS = 5000.0
 # 32-bit integer vector operations: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz
 VALU_INT32_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
@@ -100,12 +101,13 @@ WORKLOADS = {
 DTYPES = {
     "plain": "u64 counts, f64 dependency state and sums",
     "sparse": "u64 counts, f32 dependency state, f64 sums",
-    "hybrid": "u64 counts, f32 dependency state, f64 sums; bf16 MFMA products (8-bit limbs) where chosen",
-    "algebraic": "bf16 MFMA products of 8-bit count limbs with f32 accumulate, u64 counts, f32 dependency "
-                 "state, f64 sums",
+    "hybrid": "u64 counts, f32 dependency state, f64 sums; where chosen, int8 MFMA forward products (7-bit "
+              "limbs, i32 sums) and bf16 backward products (f32 sums)",
+    "algebraic": "int8 MFMA forward products of 7-bit count limbs with i32 accumulate, bf16 MFMA backward "
+                 "products with f32 accumulate, u64 counts, f32 dependency state, f64 sums",
     "many": "u64 counts, f32 dependency state, f64 sums",
     "sampled": "int32 distances (u16 limited-search distances, u64 frontier bitmaps)",
-    "allpairs": "u64 counts and int32 distances (forward by bf16 MFMA products of 8-bit limbs), u32 mask "
+    "allpairs": "u64 counts and int32 distances (forward by int8 MFMA products of 7-bit limbs), u32 mask "
                 "arithmetic, f64 terms and sums",
 }
 
@@ -299,8 +301,11 @@ def roofline(name, wl, kern, info, steps):
         base["weight_classes"] = classes
         base["k_tiles_skipped_frac"] = 1.0 - run / dense if dense else 0.0
         base["issued_dense_tflops"] = issued / (ms * 1e-3) / 1e12
-        return dict(base, bound="mfma", achieved=ach, peak=MFMA_BF16_PEAK_TFS, unit="TFLOP/s",
-                    frac=ach / MFMA_BF16_PEAK_TFS, traffic=None,
+        # the forward's products are int8 (dense peak 5.0 POP/s), the
+        # backward's BF16 (2.5 PFLOP/s)
+        peak, unit = (MFMA_I8_PEAK_TOPS, "TOP/s") if dom == "mfma_fwd" else (MFMA_BF16_PEAK_TFS, "TFLOP/s")
+        return dict(base, bound="mfma", achieved=ach, peak=peak, unit=unit,
+                    frac=ach / peak, traffic=None,
                     alg_flops_per_launch=executed / max(launches, 1),
                     planes_equivalent=issued / (2.0 * info.batch * npad * npad * classes),
                     note="executed products: 2^20 flops per k-tile multiplied (one plane's 32 k x 128 rows x "

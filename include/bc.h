@@ -63,8 +63,10 @@ typedef enum { BC_MEM_HOST = 0, BC_MEM_DEVICE = 1 } bc_mem;
  *                      dependency state stored as FP32 with FP64 accumulation.
  *                      Unit weights.
  *  BC_FORM_ALGEBRAIC   the algebraic method of Sec. 3.1 on a batch of sources:
- *                      frontier-matrix x adjacency products on BF16 MFMA with
- *                      path counts carried exactly in 8-bit limbs.  Unit
+ *                      frontier-matrix x adjacency products on MFMA, path
+ *                      counts carried exactly in 7-bit limbs by int8 products
+ *                      with int32 sums (forward), dependencies by BF16
+ *                      products with FP32 sums (backward).  Unit
  *                      weights, or integer weights up to
  *                      BC_ALGEBRAIC_MAX_WEIGHT (Sec. 3.2): one 0/1 matrix per
  *                      weight c, levels are distances, and level L is the
@@ -82,11 +84,11 @@ typedef enum { BC_MEM_HOST = 0, BC_MEM_DEVICE = 1 } bc_mem;
  */
 /* Largest integer weight the algebraic form takes (one product class each). */
 #define BC_ALGEBRAIC_MAX_WEIGHT 8
-/* Largest vertex degree the algebraic form takes: an output of a product sums
- * at most deg 8-bit limb terms, and FP32 accumulation is exact while
- * 255 * deg <= 2^24 + 256.  bc_create refuses a larger degree with
- * BC_ERR_UNSUPPORTED for the algebraic form; the hybrid form then runs every
- * level by pulls. */
+/* Largest vertex degree the algebraic form takes: an output of a forward
+ * product sums at most deg 7-bit limb terms in int32 and is copied to FP32
+ * for the epilogue, exact while 127 * deg < 2^24 (this limit leaves a factor
+ * of two).  bc_create refuses a larger degree with BC_ERR_UNSUPPORTED for the
+ * algebraic form; the hybrid form then runs every level by pulls. */
 #define BC_ALGEBRAIC_MAX_DEGREE 65792
 
 typedef enum {
@@ -373,7 +375,7 @@ typedef struct {
                                 (algebraic, hybrid), sources per work unit
                                 (bc_create_many) */
     int64_t mfma_planes;     /* products with the adjacency issued since create /
-                                reset: one per 8-bit limb of a forward level, three
+                                reset: one per 7-bit limb of a forward level, three
                                 per backward level; each is batch * npad * K
                                 multiply-adds, 2 * batch * npad * K flops (npad = n
                                 rounded up to 256; K = npad, or M * npad with

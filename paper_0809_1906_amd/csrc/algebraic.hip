@@ -1,16 +1,18 @@
 // Algebraic form (Sec. 3.1): a batch of B sources is a frontier matrix and each
-// level is a product with the 0/1 adjacency matrix A on BF16 MFMA.
+// level is a product with the 0/1 adjacency matrix A on MFMA (int8 forward,
+// BF16 backward).
 //
 // Forward (Compute Path Count, first-hit reading): with F_l[v][b] = lambda(s_b, v)
 // where d(s_b, v) = l and 0 elsewhere,
 //     F_{l+1} = Mask_unvisited(A . F_l),
 // i.e. for every w not yet reached from s_b, lambda(s_b, w) = sum over
 // neighbours v at level l of lambda(s_b, v).  Counts are carried exactly:
-// F_l is split into 8-bit limbs F^(k) (each exact in BF16), every product
-// A . F^(k) is accumulated in FP32 -- exact, because each output is an integer
-// of at most 255 * deg(w) < 2^24 (deg <= 65792 is checked at create) -- and the
-// limbs are recombined as sum_k 2^(8k) P^(k) in 64-bit integers, with a carry
-// out of 64 bits reported as an overflowing count.  The number of limbs comes
+// F_l is split into 7-bit limbs F^(k) (non-negative int8), every product
+// A . F^(k) is an int8 MFMA with int32 accumulation -- exact; each output is an
+// integer of at most 127 * deg(w) < 2^24 (deg <= 65792 is checked at create),
+// so its FP32 copy for the epilogue is exact too -- and the limbs are
+// recombined as sum_k 2^(7k) P^(k) in 64-bit integers, with a carry out of 64
+// bits reported as an overflowing count.  The number of limbs comes
 // from the largest count of level l, which the kernel that wrote level l
 // recorded on the device, so no host round trip precedes the products.
 //
@@ -34,7 +36,7 @@
 // the class matrices side by side, [A_1 | ... | A_M] (rows = vertices, K =
 // M * npad), against the stacked planes [X_1; ...; X_M] of the levels involved;
 // unit weights are M = 1.  The exactness bound is unchanged: an output sums at
-// most deg(w) non-zero terms of at most 255.
+// most deg(w) non-zero terms of at most 127.
 //
 // Data layout: A is a bit matrix in panels of 128 columns, [M * npad / 128]
 // [npad][4] words (npad = n rounded up to 256, a multiple of the block's row
@@ -46,9 +48,14 @@
 // of columns 2p, 2p + 1 in one 24-bit multiply.  Each wave loads the bits of
 // its own rows into registers and expands them into MFMA A operands there:
 // the adjacency costs 1/16 of a BF16 matrix's bytes and no LDS traffic, and
-// LDS holds only the planes, which the block's waves share.  Planes are
-// k-packed, plane[v / 8][b][v % 8], so each MFMA B-operand lane reads 16
-// contiguous bytes.  Every product is
+// LDS holds only the planes, which the block's waves share.  The forward's
+// int8 operands take a second copy of the bits in another order: column
+// 32i + 16h + 4d + j (h < 2, d < 4, j < 4) at bit 8j + 2d + h of word i, so
+// a shift by 2d + h and a mask with 0x01010101 give the four bytes (0 or 1)
+// of columns 16h + 4d .. +3, one dword of an int8 A operand.  Planes are
+// k-packed in 16-byte cells, plane[v / 8][b][v % 8] in BF16 and
+// plane[v / 16][b][v % 16] in int8, so each MFMA B-operand lane reads one
+// cell.  Every product is
 // C[w][b] = sum_v A[w][v] X[v][b] with rows = vertices and columns = sources;
 // in the 32x32 MFMA output the 32 lanes of each half-wave hold 32 consecutive
 // sources of one vertex, so two ballots give a 64-bit frontier word.
@@ -63,6 +70,8 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int GN = 128;  // columns (sources) per block (two bitmap words)
 constexpr int GK = 32;   // k (vertices) per k-tile of the skip flags
@@ -75,7 +84,8 @@ enum { EPI_ONLY = 0, EPI_FIRST = 1, EPI_MID = 2, EPI_LAST = 3 };
 
 struct GemmArgs {
     const uint32_t *abits; // [K / 128][npad][4] adjacency bit words (layout above)
-    const __bf16 *planes;  // planes of [K/8][B][8]
+    const uint32_t *abits8;// the same bits in the int8 operand order (forward)
+    const __bf16 *planes;  // planes of 16-byte cells: [K/8][B][8] BF16 or [K/16][B][16] int8
     const uint32_t *kflags;// [K/GK][B/GN]: some plane entry of this k-tile is non-zero
     int32_t npad, n, B, NW;
     int32_t K;             // M * npad: the class matrices side by side
@@ -125,10 +135,11 @@ __device__ __forceinline__ void store_count(uint32_t *p, uint64_t x, bool &wide)
     *p = (uint32_t)x;
 }
 
-// 8-bit limbs needed for a count (at least one).
+// 7-bit limbs needed for a count (at least one; ten cover 64 bits).
+constexpr int LIMB_BITS = 7;
 __device__ __forceinline__ int limbs_of(uint64_t mx) {
     int L = 1;
-    while (L < 8 && (mx >> (8 * L)) != 0) ++L;
+    while (L < 10 && (mx >> (LIMB_BITS * L)) != 0) ++L;
     return L;
 }
 
@@ -145,20 +156,22 @@ __device__ __forceinline__ int limbs_feeding(const unsigned long long *lvmax_l, 
 // Block shapes: BM rows by GN sources in 2 BM threads, waves of 64 x 64 in
 // BM / 64 rows by 2 columns (BM = 128: 4 waves, BM = 256: 8 waves).
 
-// Plane tile of one stage in LDS: [NP][KS / 8][GN][8] BF16 (16 B per lane of
-// an MFMA B operand, 32 consecutive sources of one k-group contiguous).
-template <int NP, int KS>
-constexpr int lds_x() { return NP * (KS / 8) * GN * 8; }
+// Plane tile of one stage in LDS: [NP][KS / KC][GN] cells of 16 B (KC = 8
+// BF16 or 16 int8 k per cell, one MFMA B-operand lane each; 32 consecutive
+// sources of one k-group contiguous), counted in BF16 units.
+template <int NP, int KS, int KC = 8>
+constexpr int lds_x() { return NP * (KS / KC) * GN * 8; }
 // Two LDS buffers (one barrier per stage, the next stage stored while the
 // current one is multiplied) when they fit: 2 x 32 KB for 128-row blocks (two
 // per compute unit), 2 x 48 KB for 256-row blocks (one per unit); else one.
-template <int NP, int KS, int BM>
-constexpr int stages() { return lds_x<NP, KS>() * 2 * 2 <= (BM == 256 ? 196608 : 65536) ? 2 : 1; }
-// Stage depths (k per stage): forward one plane 128 deep (32 KB), backward
-// three planes 64 deep (48 KB, one buffer).  Measured on ER-16384 (B = 512):
-// backward 32-deep stages with two buffers, and 256-row backward blocks with
-// two 48 KB buffers, were both slower (by 8% and 3%).
-constexpr int FWD_KS = 128;
+template <int NP, int KS, int BM, int KC = 8>
+constexpr int stages() { return lds_x<NP, KS, KC>() * 2 * 2 <= (BM == 256 ? 196608 : 65536) ? 2 : 1; }
+// Stage depths (k per stage): forward one int8 plane 256 deep (32 KB),
+// backward three BF16 planes 64 deep (48 KB, one buffer).  Measured on
+// ER-16384 (B = 512): backward 32-deep stages with two buffers, and 256-row
+// backward blocks with two 48 KB buffers, were both slower (by 8% and 3%).
+constexpr int FWD_KS = 256;
+constexpr int FWD_KC = 16;
 constexpr int BWD_KS = 64;
 // Forward block rows: 128 or 256, whichever the tuner measured faster on the
 // graph (AlgebraicState::fwd_rows); the backward takes 128.
@@ -167,9 +180,9 @@ constexpr int BWD_BM = 128;
 // A stage's plane tile held in registers between its global loads and its LDS
 // stores: the block's T threads cover T / GN k-groups of GN sources at a time,
 // 16 B per thread and k-group.
-template <int NP, int KS_, int T_>
+template <int NP, int KS_, int T_, int KC = 8>
 struct Stage {
-    static constexpr int KS = KS_, XG = T_ / GN, XJ = KS / 8 / XG;
+    static constexpr int KS = KS_, XG = T_ / GN, XJ = KS / KC / XG;
     static_assert(XJ >= 1, "stage shape");
     u32x4 x[NP * XJ];
 };
@@ -185,30 +198,31 @@ struct ABits {
     uint32_t w[RT][W];
 };
 
-template <int NP, int KS, int TT>
+template <int NP, int KS, int TT, int KC>
 __device__ __forceinline__ void load_stage(const GemmArgs &g, const __bf16 *planes, int ks, int b0, int tid,
-                                           Stage<NP, KS, TT> &st) {
-    using T = Stage<NP, KS, TT>;
+                                           Stage<NP, KS, TT, KC> &st) {
+    using T = Stage<NP, KS, TT, KC>;
     const int c = tid & (GN - 1), i0 = tid / GN; // k-groups i0, i0 + XG, ..., column c
 #pragma unroll
     for (int p = 0; p < NP; ++p)
 #pragma unroll
         for (int j = 0; j < T::XJ; ++j)
             st.x[p * T::XJ + j] = *reinterpret_cast<const u32x4 *>(
-                planes + (size_t)p * g.plane_elems + (((size_t)ks * (KS / 8) + i0 + T::XG * j) * g.B + b0 + c) * 8);
+                planes + (size_t)p * g.plane_elems + (((size_t)ks * (KS / KC) + i0 + T::XG * j) * g.B + b0 + c) * 8);
 }
 
-// rows0: the wave's first row.  Stage ks covers words (ks KS / 32) % 4 .. of
-// panel ks KS / 128 (half of them per wave with KH): 16 B or 8 B, aligned.
-template <int KS, bool KH>
+// rows0: the wave's first row.  The wave's columns of stage ks start at k0 =
+// ks KS (+ KS / 2 for the second half with KH), word (k0 % 128) / 32 of panel
+// k0 / 128: 16 B or 8 B, aligned.  I8: the bits in the int8 operand order.
+template <int KS, bool KH, bool I8 = false>
 __device__ __forceinline__ void load_abits(const GemmArgs &g, int ks, int rows0, int lane, int half,
                                            ABits<KS, KH> &ab) {
-    constexpr int SPP = 128 / KS; // stages per panel
     constexpr int W = ABits<KS, KH>::W;
+    const int k0 = ks * KS + (KH ? half * (KS / 2) : 0);
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
-        const uint32_t *p = g.abits + ((size_t)(ks / SPP) * g.npad + rows0 + rt * 32 + (lane & 31)) * 4 +
-                            (ks % SPP) * (KS / 32) + (KH ? half * W : 0);
+        const uint32_t *p = (I8 ? g.abits8 : g.abits) +
+                            ((size_t)(k0 / 128) * g.npad + rows0 + rt * 32 + (lane & 31)) * 4 + (k0 % 128) / 32;
         if constexpr (W == 4) {
             const u32x4 v = *reinterpret_cast<const u32x4 *>(p);
             ab.w[rt][0] = v[0];
@@ -223,15 +237,15 @@ __device__ __forceinline__ void load_abits(const GemmArgs &g, int ks, int rows0,
     }
 }
 
-template <int NP, int KS, int TT>
-__device__ __forceinline__ void store_stage(__bf16 *sX, int tid, const Stage<NP, KS, TT> &st) {
-    using T = Stage<NP, KS, TT>;
+template <int NP, int KS, int TT, int KC>
+__device__ __forceinline__ void store_stage(__bf16 *sX, int tid, const Stage<NP, KS, TT, KC> &st) {
+    using T = Stage<NP, KS, TT, KC>;
     const int c = tid & (GN - 1), i0 = tid / GN;
 #pragma unroll
     for (int p = 0; p < NP; ++p)
 #pragma unroll
         for (int j = 0; j < T::XJ; ++j)
-            *reinterpret_cast<u32x4 *>(sX + (((size_t)p * (KS / 8) + i0 + T::XG * j) * GN + c) * 8) =
+            *reinterpret_cast<u32x4 *>(sX + (((size_t)p * (KS / KC) + i0 + T::XG * j) * GN + c) * 8) =
                 st.x[p * T::XJ + j];
 }
 
@@ -249,24 +263,37 @@ __device__ __forceinline__ bf16x8 expand_bits(uint32_t w, int shift) {
     return __builtin_bit_cast(bf16x8, o);
 }
 
+// int8 MFMA A operand (32 x 32, lane l: row l % 32, columns 16 (l / 32) ..
+// +15, one byte each) from a word in the int8 order: dword d holds columns
+// 16 h + 4d .. +3 (h = l / 32), at bits 8j + 2d + h of the word.
+__device__ __forceinline__ i32x4 expand_i8(uint32_t w, int h) {
+    i32x4 o;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) o[d] = (int)((w >> (2 * d + h)) & 0x01010101u);
+    return o;
+}
+
 // The wave's rows (RT tiles of 32) by its CT column tiles of 32 sources
 // starting at source wn of the block: A from the wave's bits, X from LDS.
 // Without KH the wave multiplies the stage's KS / 16 k-steps for 64 sources
 // (CT = 2); with KH, its half of them (from k-step half KS / 32) for all 128
 // sources (CT = 4).
-template <int NP, int KS, bool KH>
+template <int NP, int KS, bool KH, bool I8 = false>
 __device__ __forceinline__ void mma_stage(const __bf16 *sX, const ABits<KS, KH> &ab, int lane, int wn, int half,
                                           f32x16 (&acc)[RT][KH ? 4 : 2]) {
-    constexpr int CT = KH ? 4 : 2, STEPS = KH ? KS / 32 : KS / 16;
+    // k-steps of 16 (BF16) or 32 (int8) k: two cell rows of 16 B each
+    constexpr int KC = I8 ? 16 : 8, KSTEP = 2 * KC;
+    constexpr int CT = KH ? 4 : 2, STEPS = KH ? KS / KSTEP / 2 : KS / KSTEP;
+    static_assert(!I8 || NP == 1, "int8 products take one plane");
     const int hs = (lane >> 5) * 4;
     const __bf16 *x = sX + (((size_t)(KH ? half * STEPS * 2 : 0) + (lane >> 5)) * GN + wn + (lane & 31)) * 8;
     // B operands of k-step kh + 1 are read while step kh multiplies
-    bf16x8 b[2][NP][CT];
+    u32x4 b[2][NP][CT];
 #pragma unroll
     for (int p = 0; p < NP; ++p)
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct)
-            b[0][p][ct] = *reinterpret_cast<const bf16x8 *>(x + ((size_t)p * (KS / 8) * GN + ct * 32) * 8);
+            b[0][p][ct] = *reinterpret_cast<const u32x4 *>(x + ((size_t)p * (KS / KC) * GN + ct * 32) * 8);
 #pragma unroll
     for (int kh = 0; kh < STEPS; ++kh) {
         const int cur = kh & 1;
@@ -275,20 +302,36 @@ __device__ __forceinline__ void mma_stage(const __bf16 *sX, const ABits<KS, KH> 
             for (int p = 0; p < NP; ++p)
 #pragma unroll
                 for (int ct = 0; ct < CT; ++ct)
-                    b[cur ^ 1][p][ct] = *reinterpret_cast<const bf16x8 *>(
-                        x + (((size_t)p * (KS / 8) + (kh + 1) * 2) * GN + ct * 32) * 8);
+                    b[cur ^ 1][p][ct] = *reinterpret_cast<const u32x4 *>(
+                        x + (((size_t)p * (KS / KC) + (kh + 1) * 2) * GN + ct * 32) * 8);
         }
         __builtin_amdgcn_sched_barrier(0); // the reads stay ahead of this step's products
-        bf16x8 a[RT];
+        if constexpr (I8) {
+            // int32 sums kept in the FP32-typed accumulators' bits
+            i32x4 a[RT];
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt) a[rt] = expand_bits(ab.w[rt][kh >> 1], hs + 8 * (kh & 1));
-#pragma unroll
-        for (int p = 0; p < NP; ++p)
+            for (int rt = 0; rt < RT; ++rt) a[rt] = expand_i8(ab.w[rt][kh], lane >> 5);
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
                 for (int rt = 0; rt < RT; ++rt)
-                    acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[rt], b[cur][p][ct], acc[rt][ct], 0, 0, 0);
+                    acc[rt][ct] = __builtin_bit_cast(
+                        f32x16, __builtin_amdgcn_mfma_i32_32x32x32_i8(a[rt], __builtin_bit_cast(i32x4, b[cur][0][ct]),
+                                                                      __builtin_bit_cast(i32x16, acc[rt][ct]), 0, 0,
+                                                                      0));
+        } else {
+            bf16x8 a[RT];
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) a[rt] = expand_bits(ab.w[rt][kh >> 1], hs + 8 * (kh & 1));
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+#pragma unroll
+                for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+                    for (int rt = 0; rt < RT; ++rt)
+                        acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            a[rt], __builtin_bit_cast(bf16x8, b[cur][p][ct]), acc[rt][ct], 0, 0, 0);
+        }
     }
 }
 
@@ -358,11 +401,13 @@ __device__ __forceinline__ int next_stage(const uint32_t *flags, int ntn, int ks
 // (from w0) and GN sources (from b0); wave wv holds rows w0 + WM (wv / WC) +
 // [0, WM) and sources b0 + WN (wv % WC) + [0, WN).  The next stage's planes
 // and bits are loaded (into registers) during the current stage's products.
-// kt0 and kt1 are k-tiles, multiples of the stage's k-tiles.
-template <int NP, int KS, int BM, bool KH = false>
+// kt0 and kt1 are k-tiles, multiples of the stage's k-tiles.  I8: int8
+// planes and products (exact int32 sums, returned converted to FP32).
+template <int NP, int KS, int BM, bool KH = false, bool I8 = false>
 __device__ __forceinline__ void gemm_tile(const GemmArgs &g, const __bf16 *planes, int w0, int b0, int tid,
-                                          __bf16 (*sX)[lds_x<NP, KS>()], f32x16 (&acc)[RT][KH ? 4 : 2], int kt0 = 0,
-                                          int kt1 = -1) {
+                                          __bf16 (*sX)[lds_x<NP, KS, I8 ? 16 : 8>()], f32x16 (&acc)[RT][KH ? 4 : 2],
+                                          int kt0 = 0, int kt1 = -1) {
+    constexpr int KC = I8 ? 16 : 8;
     constexpr int TPS = KS / GK; // k-tiles per stage
     const int lane = tid & 63, wv = tid >> 6, half = wv & 1;
     const int rows0 = w0 + (wv >> 1) * WM, wn = KH ? 0 : half * 64;
@@ -380,13 +425,13 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, const __bf16 *plane
     int ks = next_stage<TPS>(flags, ntn, ks0, nks, lane, wbase, wbits);
     int kn = ks < nks ? next_stage<TPS>(flags, ntn, ks + 1, nks, lane, wbase, wbits) : nks;
     int buf = 0, done = 0;
-    Stage<NP, KS, 2 * BM> st;
+    Stage<NP, KS, 2 * BM, KC> st;
     ABits<KS, KH> ab, abn;
     if (ks < nks) {
         // bits first: the planes' stores then wait for them too
-        load_abits<KS, KH>(g, ks, rows0, lane, half, ab);
-        load_stage<NP, KS, 2 * BM>(g, planes, ks, b0, tid, st);
-        store_stage<NP, KS, 2 * BM>(sX[0], tid, st);
+        load_abits<KS, KH, I8>(g, ks, rows0, lane, half, ab);
+        load_stage(g, planes, ks, b0, tid, st);
+        store_stage(sX[0], tid, st);
     }
     __syncthreads();
     while (ks < nks) {
@@ -394,17 +439,17 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, const __bf16 *plane
         // never multiplied): unconditional loads keep the waits for them
         // after this stage's products.
         const int kl = kn < nks ? kn : ks;
-        load_stage<NP, KS, 2 * BM>(g, planes, kl, b0, tid, st);
-        load_abits<KS, KH>(g, kl, rows0, lane, half, abn);
+        load_stage(g, planes, kl, b0, tid, st);
+        load_abits<KS, KH, I8>(g, kl, rows0, lane, half, abn);
         __builtin_amdgcn_sched_barrier(0); // issued before the products, not sunk below them
-        mma_stage<NP, KS, KH>(sX[buf], ab, lane, wn, half, acc);
-        if constexpr (stages<NP, KS, BM>() == 2) {
-            if (kn < nks) store_stage<NP, KS, 2 * BM>(sX[buf ^ 1], tid, st);
+        mma_stage<NP, KS, KH, I8>(sX[buf], ab, lane, wn, half, acc);
+        if constexpr (stages<NP, KS, BM, KC>() == 2) {
+            if (kn < nks) store_stage(sX[buf ^ 1], tid, st);
             __syncthreads();
             buf ^= 1;
         } else {
             __syncthreads(); // every wave is done with the stage
-            if (kn < nks) store_stage<NP, KS, 2 * BM>(sX[0], tid, st);
+            if (kn < nks) store_stage(sX[0], tid, st);
             __syncthreads();
         }
         ab = abn;
@@ -417,6 +462,14 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, const __bf16 *plane
         constexpr unsigned long long U = (unsigned long long)NP * (BM / 128);
         atomicAdd(&g.ktiles[0], (unsigned long long)done * TPS * U);
         atomicAdd(&g.ktiles[1], (unsigned long long)(nks - ks0) * TPS * U);
+    }
+    if constexpr (I8) {
+        // whole vectors: a bit cast of one vector element reads element 0
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int c = 0; c < (KH ? 4 : 2); ++c)
+                acc[rt][c] = __builtin_convertvector(__builtin_bit_cast(i32x16, acc[rt][c]), f32x16);
     }
 }
 
@@ -454,7 +507,7 @@ __device__ __forceinline__ bool split_meet(const GemmArgs &g, int k, int tile, i
     return true;
 }
 
-// Forward epilogue for limb `shift / 8`; `mode` (uniform over the launch) says
+// Forward epilogue for limb `shift / 7`; `mode` (uniform over the launch) says
 // whether it is the only limb, the first, a middle one or the last.  Lane
 // layout of the 32x32 output: lane l, register r holds row 8(r/4) + 4(l/32) +
 // r%4 and column l%32; the two column tiles are bitmap word q.
@@ -555,9 +608,9 @@ __device__ __forceinline__ void epi_fwd(const GemmArgs &g, const EpiArgs &e, int
     if (__any(ovf) && lane == 0) atomicOr(&e.status[0], (uint32_t)BC_DEV_SIGMA_OVERFLOW);
 }
 
-// Forward level l -> l+1: one pass per 8-bit limb of level l's largest count,
-// each followed by its epilogue.  Grid: grid_blocks<BM>(npad, B), tiles by tile_of.
-// KS: k per pipeline stage.  The two waves of a row pair split each stage's
+// Forward level l -> l+1: one pass per 7-bit limb of level l's largest count,
+// each an int8 product followed by its epilogue.  Grid: grid_blocks<BM>(npad,
+// B), tiles by tile_of.  KS: k per pipeline stage.  The two waves of a row pair split each stage's
 // k range (each expands only its half of the adjacency bits, for all 128
 // sources) and sum the halves through LDS before the epilogue: half the bit
 // expansion of waves that each take 64 sources (ER-16384: 247 -> 233 us per
@@ -565,12 +618,13 @@ __device__ __forceinline__ void epi_fwd(const GemmArgs &g, const EpiArgs &e, int
 template <typename S, int KS, int BM>
 __global__ __launch_bounds__(2 * BM, BM == 128 ? 2 : 1) void k_mfma_fwd(GemmArgs g, EpiArgs e) {
     constexpr bool KH = true; // the waves' k-split (the backward keeps the column split)
+    constexpr int KC = FWD_KC;
     // one LDS area: the plane buffers during the products, then the halves'
     // exchange (64 sums per lane per wave)
-    constexpr size_t PLANE_BYTES = (size_t)stages<1, KS, BM>() * lds_x<1, KS>() * sizeof(__bf16);
+    constexpr size_t PLANE_BYTES = (size_t)stages<1, KS, BM, KC>() * lds_x<1, KS, KC>() * sizeof(__bf16);
     constexpr size_t XCHG_BYTES = KH ? (size_t)2 * BM / 64 * 64 * RT * 2 * 16 * sizeof(float) : 0;
     __shared__ __align__(16) unsigned char smem[PLANE_BYTES > XCHG_BYTES ? PLANE_BYTES : XCHG_BYTES];
-    auto sX = reinterpret_cast<__bf16 (*)[lds_x<1, KS>()]>(smem);
+    auto sX = reinterpret_cast<__bf16 (*)[lds_x<1, KS, KC>()]>(smem);
     __shared__ int s_last;
     int half = 0, tile = 0;
     const Tile tl = g.ksplit == 2 ? tile_of_split(g.B, half, tile) : tile_of(g.B);
@@ -580,14 +634,18 @@ __global__ __launch_bounds__(2 * BM, BM == 128 ? 2 : 1) void k_mfma_fwd(GemmArgs
     const int q = (b0 >> 6) + (wv & 1); // bitmap word of this wave's sources
     const int L = limbs_feeding(e.lvmax_cur, e.level, e.classes);
     if (blockIdx.x == 0 && tid == 0) atomicAdd(e.planes_issued, (unsigned long long)L);
-    const int nkt = g.K / GK, kt0 = g.ksplit == 2 ? half * (nkt / 2) : 0, kt1 = g.ksplit == 2 ? kt0 + nkt / 2 : nkt;
+    // split K at a stage boundary (K is a multiple of 256, the stages' depth)
+    constexpr int TPS = KS / GK;
+    const int nst = g.K / KS, hst = nst / 2;
+    const int kt0 = g.ksplit == 2 && half ? hst * TPS : 0, kt1 = g.ksplit == 2 && !half ? hst * TPS : nst * TPS;
     f32x16 acc[RT][2];
 #pragma nounroll
     for (int k = 0; k < L; ++k) {
+        // int8 plane k: plane_elems bytes from the planes' start
+        const __bf16 *planes_k = g.planes + (size_t)k * (g.plane_elems / 2);
         if constexpr (KH) {
             f32x16 acc4[RT][4];
-            gemm_tile<1, KS, BM, true>(g, g.planes + (size_t)k * g.plane_elems, tl.row * BM, b0, tid, sX, acc4, kt0,
-                                       kt1);
+            gemm_tile<1, KS, BM, true, true>(g, planes_k, tl.row * BM, b0, tid, sX, acc4, kt0, kt1);
             // wave wv keeps sources 64 h .. 64 h + 63 (h = wv & 1, its bitmap
             // word) and hands the other 64 to its partner wv ^ 1; the tile
             // loop ended at a barrier, so the plane buffers are free
@@ -630,7 +688,7 @@ __global__ __launch_bounds__(2 * BM, BM == 128 ? 2 : 1) void k_mfma_fwd(GemmArgs
                             acc[rt][c][r] = acc4[rt][c][r] + theirs[((rt * 2 + c) * 16 + r) * 64];
             }
         } else {
-            gemm_tile<1, KS, BM>(g, g.planes + (size_t)k * g.plane_elems, tl.row * BM, b0, tid, sX, acc, kt0, kt1);
+            gemm_tile<1, KS, BM, false, true>(g, planes_k, tl.row * BM, b0, tid, sX, acc, kt0, kt1);
         }
         if (g.ksplit == 2 && !split_meet<2 * BM>(g, k, tile, half, tid, s_last, acc))
             continue; // the other half finishes it
@@ -640,7 +698,7 @@ __global__ __launch_bounds__(2 * BM, BM == 128 ? 2 : 1) void k_mfma_fwd(GemmArgs
         // once before the loop and holding them through the products.
         int w0k = w0;
         __asm__ volatile("" : "+s"(w0k));
-        epi_fwd<S>(g, e, mode, 8 * k, acc, w0k, q, lane);
+        epi_fwd<S>(g, e, mode, LIMB_BITS * k, acc, w0k, q, lane);
         __syncthreads(); // the next limb's pipeline reuses the LDS buffers
     }
 }
@@ -718,26 +776,31 @@ __global__ __launch_bounds__(PB) void k_zero32(uint32_t *__restrict__ p, size_t 
 }
 
 // A[v][(c-1) npad + w] = 1 for every arc v -> w of weight c (c = 1 without
-// weights), as bits of the panel layout: column k at bit (k % 2) 16 +
-// (k % 32) / 2 of word (k % 128) / 32 of row v in panel k / 128.
+// weights), as bits of the panel layout, word (k % 128) / 32 of row v in
+// panel k / 128 for column k: in abits at bit (k % 2) 16 + (k % 32) / 2 (the
+// BF16 pair order), in abits8 at bit 8 (k % 4) + 2 ((k % 16) / 4) + (k % 32)
+// / 16 (the int8 order).
 __global__ __launch_bounds__(PB) void k_build_adj(int32_t n, int32_t npad, const int32_t *__restrict__ rp,
                                                   const int32_t *__restrict__ col, const uint8_t *__restrict__ wt,
-                                                  uint32_t *__restrict__ abits) {
+                                                  uint32_t *__restrict__ abits, uint32_t *__restrict__ abits8) {
     const int32_t v = blockIdx.x;
     if (v >= n) return;
     for (int32_t e = rp[v] + threadIdx.x; e < rp[v + 1]; e += PB) {
         const int32_t c = wt ? (int32_t)wt[e] - 1 : 0;
         const size_t k = (size_t)c * npad + col[e];
         const uint32_t j = (uint32_t)(k & 31);
-        atomicOr(&abits[((k / 128) * npad + v) * 4 + (k % 128) / 32], 1u << ((j & 1) * 16 + (j >> 1)));
+        const size_t word = ((k / 128) * npad + v) * 4 + (k % 128) / 32;
+        atomicOr(&abits[word], 1u << ((j & 1) * 16 + (j >> 1)));
+        atomicOr(&abits8[word], 1u << (8 * (j & 3) + 2 * ((j >> 2) & 3) + (j >> 4)));
     }
 }
 
-// Planes feeding level l+1: planes[k][c][v/8][b][v%8] = limb k of
-// lambda(s_b, v) for v at level l-c (class c+1, weight c+1), else 0, for the
-// limbs of the largest count among the feeding levels; kflags[(c npad + v) /
-// GK][b / GN] |= (some limb non-zero).  Thread (c, vg, b) covers 8 rows; levels
-// are `words` words apart, and levels below 0 contribute nothing.
+// Planes feeding level l+1: int8 planes[k][c][v/16][b][v%16] = 7-bit limb k
+// of lambda(s_b, v) for v at level l-c (class c+1, weight c+1), else 0, for
+// the limbs of the largest count among the feeding levels (plane k starts
+// k plane_elems bytes in); kflags[(c npad + v) / GK][b / GN] |= (some limb
+// non-zero).  Thread (c, vg, b) covers 16 rows; levels are `words` words
+// apart, and levels below 0 contribute nothing.
 template <typename S>
 __global__ __launch_bounds__(PB) void k_limb_split(int32_t n, int32_t npad, int32_t B, int32_t NW, int32_t M,
                                                    int32_t l, const unsigned long long *__restrict__ lvmax_l,
@@ -746,7 +809,7 @@ __global__ __launch_bounds__(PB) void k_limb_split(int32_t n, int32_t npad, int3
                                                    size_t plane_elems, uint32_t *__restrict__ kflags,
                                                    unsigned long long *__restrict__ reach) {
     const size_t id = (size_t)blockIdx.x * PB + threadIdx.x;
-    const size_t per_class = (size_t)(npad / 8) * B;
+    const size_t per_class = (size_t)(npad / 16) * B;
     const bool over = search_over(reach);
     if (reach && id == 0) reach[2] = over ? 1ull : 0ull; // for this level's products
     if (id >= per_class * M || over) return;
@@ -755,23 +818,29 @@ __global__ __launch_bounds__(PB) void k_limb_split(int32_t n, int32_t npad, int3
     const int L = limbs_feeding(lvmax_l, l, M);
     const int32_t vg = (int32_t)(r / B), b = (int32_t)(r - (size_t)vg * B);
     const uint64_t *f = c <= l ? fl - (size_t)c * words : nullptr;
-    uint64_t s[8];
+    uint64_t s[16];
     bool nz = false;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const int32_t v = vg * 8 + j;
+    for (int j = 0; j < 16; ++j) {
+        const int32_t v = vg * 16 + j;
         s[j] = 0;
         if (f && v < n && ((f[(size_t)v * NW + (b >> 6)] >> (b & 63)) & 1)) s[j] = (uint64_t)sigma[(size_t)v * B + b];
         nz |= s[j] != 0;
     }
+    unsigned char *pb = reinterpret_cast<unsigned char *>(planes);
     for (int k = 0; k < L; ++k) {
-        bf16x8 o;
+        u32x4 o;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) o[j] = (__bf16)(float)((s[j] >> (8 * k)) & 0xFF);
-        *reinterpret_cast<bf16x8 *>(planes + (size_t)k * plane_elems + id * 8) = o;
+        for (int d = 0; d < 4; ++d) {
+            uint32_t x = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) x |= (uint32_t)((s[4 * d + j] >> (LIMB_BITS * k)) & 0x7F) << (8 * j);
+            o[d] = x;
+        }
+        *reinterpret_cast<u32x4 *>(pb + (size_t)k * plane_elems + id * 16) = o;
     }
     if (__ballot(nz) && (threadIdx.x & 63) == 0)
-        atomicOr(&kflags[(size_t)(((size_t)c * npad + (size_t)vg * 8) / GK) * (B / GN) + b / GN], 1u);
+        atomicOr(&kflags[(size_t)(((size_t)c * npad + (size_t)vg * 16) / GK) * (B / GN) + b / GN], 1u);
 }
 
 // Planes for backward level l: planes[0..2][c][v/8][b][v%8] = hi, mid, lo BF16
@@ -833,6 +902,7 @@ GemmArgs gemm_args(bc_ctx *ctx, const __bf16 *planes, bool forward) {
     AlgebraicState &a = ctx->al;
     GemmArgs g;
     g.abits = a.abits;
+    g.abits8 = a.abits8;
     g.planes = planes;
     g.kflags = a.kflags;
     g.npad = a.npad;
@@ -863,16 +933,18 @@ bc_status algebraic_prepare(bc_ctx *ctx) {
     if (B % GN != 0) return bc_fail(ctx, BC_ERR_UNSUPPORTED, "algebraic form: batch must be 256 or 512");
     if (ctx->max_degree > BC_ALGEBRAIC_MAX_DEGREE)
         return bc_fail(ctx, BC_ERR_UNSUPPORTED,
-                       "algebraic form: a degree above 65792 breaks exact FP32 accumulation of 8-bit limbs");
+                       "algebraic form: degrees above 65792 are not taken (exact FP32 copies of the products' sums)");
     a.npad = std::max(NPAD, (ctx->n + NPAD - 1) / NPAD * NPAD);
     a.classes = ctx->weighted ? (int32_t)ctx->max_weight : 1;
     const size_t K = (size_t)a.classes * a.npad;
     const size_t adj_bytes = (size_t)a.npad * K / 8;
     const size_t plane_elems = K * B;
-    if (adj_bytes + 8 * plane_elems * sizeof(__bf16) > (size_t(96) << 30))
+    if (2 * adj_bytes + 8 * plane_elems * sizeof(__bf16) > (size_t(96) << 30))
         return bc_fail(ctx, BC_ERR_UNSUPPORTED, "algebraic form: the adjacency bits and planes would exceed 96 GiB");
     a.abits = (uint32_t *)bc_dalloc(ctx, adj_bytes);
-    a.planes = (__bf16 *)bc_dalloc(ctx, 8 * plane_elems * sizeof(__bf16)); // up to 8 limbs, or 3 coefficient planes
+    a.abits8 = (uint32_t *)bc_dalloc(ctx, adj_bytes);
+    // up to ten int8 limb planes (10 plane_elems bytes), or 3 BF16 coefficient planes
+    a.planes = (__bf16 *)bc_dalloc(ctx, 8 * plane_elems * sizeof(__bf16));
     a.part = (uint64_t *)bc_dalloc(ctx, (size_t)a.npad * B * sizeof(uint64_t));
     a.kflags = (uint32_t *)bc_dalloc(ctx, (K / GK) * (B / GN) * sizeof(uint32_t));
     a.planes_issued = (unsigned long long *)bc_dalloc(ctx, 256);
@@ -894,15 +966,17 @@ bc_status algebraic_prepare(bc_ctx *ctx) {
         a.ws = (float *)bc_dalloc(ctx, (size_t)8 * ws_elems * sizeof(float));
         a.arrive = (uint32_t *)bc_dalloc(ctx, (size_t)8 * ntiles_max * sizeof(uint32_t));
     }
-    if (!a.abits || !a.planes || !a.part || !a.kflags || !a.planes_issued ||
+    if (!a.abits || !a.abits8 || !a.planes || !a.part || !a.kflags || !a.planes_issued ||
         (a.ksplit == 2 && (!a.ws || !a.arrive)))
         return bc_fail(ctx, BC_ERR_NOMEM, "algebraic form: allocation failed");
     if (a.ksplit == 2) BC_HIP(ctx, hipMemsetAsync(a.arrive, 0, (size_t)8 * ntiles_max * sizeof(uint32_t), ctx->stream));
     BC_HIP(ctx, hipMemsetAsync(a.abits, 0, adj_bytes, ctx->stream));
+    BC_HIP(ctx, hipMemsetAsync(a.abits8, 0, adj_bytes, ctx->stream));
     BC_HIP(ctx, hipMemsetAsync(a.planes_issued, 0, 5 * sizeof(unsigned long long), ctx->stream));
     if (ctx->n > 0)
         hipLaunchKernelGGL(k_build_adj, dim3(ctx->n), dim3(PB), 0, ctx->stream, ctx->n, a.npad,
-                           ctx->row_ptr, ctx->col, ctx->weighted ? (const uint8_t *)ctx->weight : nullptr, a.abits);
+                           ctx->row_ptr, ctx->col, ctx->weighted ? (const uint8_t *)ctx->weight : nullptr, a.abits,
+                           a.abits8);
     BC_HIP(ctx, hipGetLastError());
     return BC_OK;
 }
@@ -910,7 +984,7 @@ bc_status algebraic_prepare(bc_ctx *ctx) {
 bc_status algebraic_release(bc_ctx *ctx) {
     AlgebraicState &a = ctx->al;
     BC_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    for (void *p : {(void *)a.abits, (void *)a.planes, (void *)a.part, (void *)a.kflags, (void *)a.planes_issued,
+    for (void *p : {(void *)a.abits, (void *)a.abits8, (void *)a.planes, (void *)a.part, (void *)a.kflags, (void *)a.planes_issued,
                     (void *)a.ws, (void *)a.arrive})
         if (p) bc_dfree(ctx, p);
     const bool every = a.every_level;
@@ -937,7 +1011,7 @@ bc_status algebraic_forward_level_t(bc_ctx *ctx, int32_t l) {
     clear_kflags(ctx);
     {
         LaunchTimer tm(ctx, "limb_split");
-        hipLaunchKernelGGL(k_limb_split<S>, dim3(blocks_for(plane_elems / 8, PB)), dim3(PB), 0, ctx->stream, ctx->n,
+        hipLaunchKernelGGL(k_limb_split<S>, dim3(blocks_for(plane_elems / 16, PB)), dim3(PB), 0, ctx->stream, ctx->n,
                            a.npad, s.batch, s.words, a.classes, l, s.lvmax + l, fcur, words, (const S *)s.sigma,
                            a.planes, plane_elems, a.kflags, reach);
         tm.done();

@@ -328,13 +328,14 @@ bc_status bc_create(const bc_graph *g, const bc_options *opt_in, bc_ctx **out) {
     if (hw && form == BC_FORM_ALGEBRAIC && max_w > BC_ALGEBRAIC_MAX_WEIGHT)
         return fail_create(BC_ERR_UNSUPPORTED,
                            "the algebraic form takes weights up to BC_ALGEBRAIC_MAX_WEIGHT (one product class each)");
-    // An output of a product sums at most deg(w) limb terms of at most 255;
-    // FP32 holds every integer below 2^24 exactly, so 255 * deg must stay below
-    // 2^24 + 256 (deg <= 65792).  The hybrid form runs such graphs by pulls.
+    // An output of a forward product sums at most deg(w) limb terms of at
+    // most 127 in int32; its FP32 copy for the epilogue is exact below 2^24,
+    // which deg <= 65792 keeps with a factor of two to spare.  The hybrid form
+    // runs such graphs by pulls.
     if (form == BC_FORM_ALGEBRAIC && max_deg > BC_ALGEBRAIC_MAX_DEGREE)
         return fail_create(BC_ERR_UNSUPPORTED,
-                           "the algebraic form takes degrees up to BC_ALGEBRAIC_MAX_DEGREE (exact FP32 sums of "
-                           "8-bit limbs)");
+                           "the algebraic form takes degrees up to BC_ALGEBRAIC_MAX_DEGREE (exact FP32 copies of "
+                           "the products' sums)");
 
     // ---- device side ----
     bc_ctx *ctx = new (std::nothrow) bc_ctx();

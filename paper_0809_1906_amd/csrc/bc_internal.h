@@ -88,6 +88,7 @@ struct AlgebraicState {
     int32_t npad = 0;                  // n rounded up to 256 (the product's row block)
     int32_t classes = 1;               // M: one 0/1 matrix per integer weight 1..M
     uint32_t *abits = nullptr;         // [M npad / 128][npad][4] 0/1 bits in panels of 128 columns, class c in columns [(c-1) npad, c npad)
+    uint32_t *abits8 = nullptr;        // the same bits in the int8 operand order (forward products)
     __bf16 *planes = nullptr;          // up to 8 planes of [M npad/8][batch][8]
     uint64_t *part = nullptr;          // [npad][batch] partial limb sums
     uint32_t *kflags = nullptr;        // [M npad/32][batch/128] non-empty k-tiles

@@ -2,9 +2,10 @@
 allocation failure at every allocation a context makes, and calls refused
 while the context's stream is being captured into a HIP graph.
 
-- Degree: an output of a product sums at most deg 8-bit limb terms of at most
-  255, exact in FP32 while 255 * deg <= 2^24 + 256 (exact path counts, Sec. 1.1,
-  carried through the products of Sec. 3.1).  The star K_{1,65793} has one
+- Degree: an output of a forward product sums at most deg 7-bit limb terms
+  of at most 127 in int32, and its FP32 copy is exact while 127 * deg < 2^24;
+  the limit is 65792 (exact path counts, Sec. 1.1, carried through the
+  products of Sec. 3.1).  The star K_{1,65793} has one
   degree above that: the algebraic form refuses it, the hybrid form runs it by
   pulls, and BC equals the star's closed form ((n-1)(n-2) at the centre over
   ordered pairs, 0 at the leaves).

@@ -98,7 +98,7 @@ def test_hybrid_forced_mix_sssp_bit_exact(gpu_lib, tmp_path, name, mix):
 
 def test_hybrid_wide_counts_through_products(gpu_lib, tmp_path):
     """Grid 20x20 counts reach C(38,19) > 2^32: uint64 storage and several
-    8-bit limbs, with every level by products."""
+    7-bit limbs, with every level by products."""
     g = gg.grid(20, 20)
     path = str(tmp_path / "tune.txt")
     force_thresholds(gpu_lib, g, path, 0.0, 0.0)

@@ -224,8 +224,8 @@ def test_algebraic_split_k(gpu_lib):
 
 
 def test_algebraic_limbs_and_wide_counts(gpu_lib):
-    """Counts of several 8-bit limbs (grid 20x20: up to C(38,19) > 2^32, so
-    five limbs and uint64 storage) stay exact through the BF16 products."""
+    """Counts of several 7-bit limbs (grid 20x20: up to C(38,19) > 2^32, so
+    six limbs and uint64 storage) stay exact through the int8 products."""
     g = gg.grid(20, 20)
     say("algebraic_limbs")
     src = np.array([0, 19, 210, 399], np.int32)

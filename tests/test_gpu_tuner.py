@@ -3,7 +3,7 @@ workgroup (algebraic and hybrid forms) and the sources per work unit of
 bc_create_many's queue.
 
 Neither choice may change a result.  The forward products sum exact integer
-counts (8-bit limbs, degrees within BC_ALGEBRAIC_MAX_DEGREE), so distances and
+counts (7-bit limbs, degrees within BC_ALGEBRAIC_MAX_DEGREE), so distances and
 path counts are the same bit for bit with 128- and 256-row workgroups, and the
 backward, which the choice does not touch, then writes the same dependencies.
 A work unit's size only regroups the FP64 sums of the many-graph sweep.
