@@ -286,15 +286,32 @@ bc_status run_mode(bc_ctx *ctx, const int32_t *d_src, int32_t B, int mode, Calib
 
 // Threshold for one direction minimising the summed level time of the
 // samples; *saved_ms is the time it saves over all-pulls.  Ties keep pulls.
+// A threshold strictly inside the range of one level's densities over the
+// calibration batches is not a candidate: some batches would take that level
+// by products and others by pulls, and a replayed batch, which keeps the plan
+// of the batch it was recorded from, would run whichever that one took.
 double fit_threshold(const Calibration &cal, bool forward, double *saved_ms) {
     std::vector<const Sample *> v;
+    std::map<int, std::pair<double, double>> range; // level -> lowest, highest density
     for (const auto &kv : cal.samples)
-        if ((kv.first.second.first == 1) == forward && kv.second.has_pull && kv.second.has_prod) v.push_back(&kv.second);
+        if ((kv.first.second.first == 1) == forward && kv.second.has_pull && kv.second.has_prod) {
+            v.push_back(&kv.second);
+            const double d = kv.second.density;
+            auto it = range.find(kv.first.second.second);
+            if (it == range.end()) range[kv.first.second.second] = {d, d};
+            else it->second = {std::min(it->second.first, d), std::max(it->second.second, d)};
+        }
+    auto splits_a_level = [&](double theta) {
+        for (const auto &kv : range)
+            if (kv.second.first < theta && theta <= kv.second.second) return true;
+        return false;
+    };
     double all_pull = 0.0;
     for (const Sample *s : v) all_pull += s->t_pull;
     double best_theta = kNever, best = all_pull;
     for (const Sample *c : v) {
         const double theta = c->density;
+        if (splits_a_level(theta)) continue;
         double cost = forward ? kSyncMs * (double)v.size() : 0.0;
         for (const Sample *s : v) cost += s->density >= theta ? s->t_prod : s->t_pull;
         if (cost < best || (cost == best && theta > best_theta && best_theta <= 1.0)) {
