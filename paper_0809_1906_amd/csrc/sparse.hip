@@ -337,13 +337,19 @@ __global__ void k_run_init(BatchCtl *ctl, const int32_t *src, int32_t total, int
 
 // Seeds the batch: lane b takes source src[b] (b < count).  In a replayed
 // batch (ctl non-null) the sources are the run's batch ctl->batch instead.
+// The end-of-search counts get, one atomic per wave, the pairs the sources
+// can reach (their components' sizes) and those of level 0, and with rp
+// non-null (unit weights: level 1 is pushed, all of it) those of level 1,
+// each source's neighbours (distinct in a simple graph).  With weights a
+// neighbour's level is its arc's weight, and the products count level 1.
 template <typename S>
 __global__ __launch_bounds__(SB) void k_sp_seed(const int32_t *__restrict__ src, int32_t count, int32_t B, int32_t NW,
                                                 uint64_t *front0, uint64_t *visited, S *sigma, int32_t *src_lane,
                                                 uint32_t *any0, const BatchCtl *__restrict__ ctl,
-                                                const int32_t *__restrict__ comp_size, unsigned long long *reach) {
+                                                const int32_t *__restrict__ comp_size, const int32_t *__restrict__ rp,
+                                                unsigned long long *reach) {
     const int32_t b = blockIdx.x * SB + threadIdx.x;
-    if (b >= B) return;
+    if (b >= B) return; // B is a multiple of 64: whole waves return here (the shuffles below)
     if (ctl) {
         const int64_t b0 = (int64_t)ctl->batch * B;
         src = ctl->src + b0;
@@ -351,38 +357,69 @@ __global__ __launch_bounds__(SB) void k_sp_seed(const int32_t *__restrict__ src,
     }
     const int32_t s = b < count ? src[b] : -1;
     src_lane[b] = s;
+    unsigned long long comp = 0, lanes = 0;
     if (s >= 0) {
         const unsigned long long bit = 1ull << (b & 63);
         atomicOr((unsigned long long *)&front0[(size_t)s * NW + (b >> 6)], bit);
         atomicOr((unsigned long long *)&visited[(size_t)s * NW + (b >> 6)], bit);
         atomicOr(&any0[s >> 5], 1u << (s & 31));
         sigma[(size_t)s * B + b] = 1;
-        atomicAdd(&reach[0], (unsigned long long)comp_size[s]);
-        atomicAdd(&reach[1], 1ull);
+        comp = (unsigned long long)comp_size[s];
+        // s, and with rp its neighbours (level 1 of an unweighted batch)
+        lanes = 1 + (rp ? (unsigned long long)(rp[s + 1] - rp[s]) : 0ull);
+    }
+    // the pair counts of the end-of-search test: one atomic per wave
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        comp += __shfl_xor(comp, off, 64);
+        lanes += __shfl_xor(lanes, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0 && lanes) {
+        atomicAdd(&reach[0], comp);
+        atomicAdd(&reach[1], lanes);
     }
 }
 
 // Forward level 0 -> 1, pushed from the sources: every neighbour w of s_b
 // is at distance 1 with exactly one shortest path (lambda = 1).  One block per
-// batch lane; the block's threads take the source's arcs.
+// batch lane; the block's threads take the source's arcs.  The level's pairs
+// were counted by the seed kernel, and its vertex filter is written by
+// k_any_from_front after this kernel: the filter words are shared by the
+// sources adjacent to any of their 32 vertices, so an atomic per arc on them
+// serialised (ER n = 16384, 512 sources: about 256 atomics per word; 55 ->
+// 16 us per launch with the separate pass).
 template <typename S>
 __global__ __launch_bounds__(SB) void k_fwd_push0(Topo t, int32_t NW, const int32_t *__restrict__ src_lane,
                                                   uint64_t *__restrict__ fnext, uint64_t *__restrict__ visited,
-                                                  S *__restrict__ sigma, uint32_t *__restrict__ any_next,
-                                                  unsigned long long *__restrict__ reach) {
+                                                  S *__restrict__ sigma) {
     const int32_t b = blockIdx.x;
     const int32_t s = src_lane[b];
     if (s < 0) return;
-    // the neighbours are distinct (a simple graph): each is a new pair
-    if (threadIdx.x == 0) atomicAdd(&reach[1], (unsigned long long)(t.rp[s + 1] - t.rp[s]));
     const unsigned long long bit = 1ull << (b & 63);
     const int q = b >> 6;
     for (int32_t e = t.rp[s] + threadIdx.x; e < t.rp[s + 1]; e += SB) {
         const int32_t w = t.col[e];
         atomicOr((unsigned long long *)&fnext[(size_t)w * NW + q], bit);
         atomicOr((unsigned long long *)&visited[(size_t)w * NW + q], bit);
-        atomicOr(&any_next[w >> 5], 1u << (w & 31));
         sigma[(size_t)w * t.B + b] = 1;
+    }
+}
+
+// Level 1's vertex filter from its frontier words, after the push: thread v
+// tests vertex v's NW words, and each wave's ballot is two whole filter
+// words (aw = ceil(n / 32) words; plain stores, one writer per word).
+__global__ __launch_bounds__(SB) void k_any_from_front(int32_t n, int32_t NW, size_t aw,
+                                                       const uint64_t *__restrict__ front,
+                                                       uint32_t *__restrict__ any) {
+    const int32_t v = blockIdx.x * SB + threadIdx.x;
+    bool nz = false;
+    if (v < n)
+        for (int q = 0; q < NW; ++q) nz |= front[(size_t)v * NW + q] != 0;
+    const uint64_t m = __ballot(nz);
+    const size_t w0 = (size_t)(v >> 6) * 2; // v - lane is a multiple of 64
+    if ((threadIdx.x & 63) == 0) {
+        if (w0 < aw) any[w0] = (uint32_t)m;
+        if (w0 + 1 < aw) any[w0 + 1] = (uint32_t)(m >> 32);
     }
 }
 
@@ -935,7 +972,7 @@ bc_status launch_batch_init(bc_ctx *ctx, const BatchShape &b, const int32_t *d_s
                        s.any, (size_t)s.level_cap * b.aw, s.lvmax, s.lvflag, s.level_cap, s.reach);
     hipLaunchKernelGGL(k_sp_seed<S>, dim3((b.B + SB - 1) / SB), dim3(SB), 0, ctx->stream, d_src, count, b.B, NW,
                        s.front, s.visited, reinterpret_cast<S *>(s.sigma), s.src, s.any, ctl,
-                       (const int32_t *)ctx->comp_size, s.reach);
+                       (const int32_t *)ctx->comp_size, ctx->weighted ? nullptr : b.t.rp, s.reach);
     tm.done();
     BC_HIP(ctx, hipGetLastError());
     return BC_OK;
@@ -951,7 +988,9 @@ bc_status launch_fwd_level(bc_ctx *ctx, const BatchShape &b, int32_t l, bool pro
     if (l == 0) {
         LaunchTimer tm(ctx, "fwd_push0");
         hipLaunchKernelGGL(k_fwd_push0<S>, dim3(b.B), dim3(SB), 0, ctx->stream, b.t, NW, (const int32_t *)s.src,
-                           s.front + b.words, s.visited, reinterpret_cast<S *>(s.sigma), s.any + b.aw, s.reach);
+                           s.front + b.words, s.visited, reinterpret_cast<S *>(s.sigma));
+        hipLaunchKernelGGL(k_any_from_front, dim3((ctx->n + SB - 1) / SB), dim3(SB), 0, ctx->stream, ctx->n, NW,
+                           (size_t)b.aw, (const uint64_t *)(s.front + b.words), s.any + b.aw);
         tm.done();
         return BC_OK;
     }
