@@ -269,7 +269,7 @@ def cpu_baseline(name, wl, target_s: float = 20.0, whole: bool = True):
              "single_core": single}, want, sample)
 
 
-KERNELS = ("fwd_pull", "bwd_pull", "fwd_push0", "batch_init", "batch_check", "kflag_clear", "limb_split", "mfma_fwd",
+KERNELS = ("fwd_pull", "bwd_pull", "fwd_push0", "batch_init", "batch_check", "limb_split", "mfma_fwd",
            "coef_split", "mfma_bwd", "plain_sweep", "weighted_sweep", "multigraph_sweep")
 
 

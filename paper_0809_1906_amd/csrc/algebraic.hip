@@ -769,12 +769,6 @@ __global__ __launch_bounds__(2 * BWD_BM, BWD_BM == 128 ? 2 : 1) void k_mfma_bwd(
 
 // ---- element-wise kernels -------------------------------------------------------
 
-// Zeroes `count` words (a kernel rather than a memset, so that it can be
-// recorded into a replayed graph).
-__global__ __launch_bounds__(PB) void k_zero32(uint32_t *__restrict__ p, size_t count) {
-    for (size_t i = (size_t)blockIdx.x * PB + threadIdx.x; i < count; i += (size_t)gridDim.x * PB) p[i] = 0;
-}
-
 // A[v][(c-1) npad + w] = 1 for every arc v -> w of weight c (c = 1 without
 // weights), as bits of the panel layout, word (k % 128) / 32 of row v in
 // panel k / 128 for column k: in abits at bit (k % 2) 16 + (k % 32) / 2 (the
@@ -798,8 +792,10 @@ __global__ __launch_bounds__(PB) void k_build_adj(int32_t n, int32_t npad, const
 // Planes feeding level l+1: int8 planes[k][c][v/16][b][v%16] = 7-bit limb k
 // of lambda(s_b, v) for v at level l-c (class c+1, weight c+1), else 0, for
 // the limbs of the largest count among the feeding levels (plane k starts
-// k plane_elems bytes in); kflags[(c npad + v) / GK][b / GN] |= (some limb
-// non-zero).  Thread (c, vg, b) covers 16 rows; levels are `words` words
+// k plane_elems bytes in); kflags[(c npad + v) / GK][b / GN] = (some limb
+// non-zero).  Block (c, t, sb) covers k-tile t of class c (GK = 32 rows) for
+// source block sb (GN sources) and writes its flag; thread (h, j) takes the
+// 16 rows from 32 t + 16 h for source GN sb + j.  Levels are `words` words
 // apart, and levels below 0 contribute nothing.
 template <typename S>
 __global__ __launch_bounds__(PB) void k_limb_split(int32_t n, int32_t npad, int32_t B, int32_t NW, int32_t M,
@@ -808,15 +804,16 @@ __global__ __launch_bounds__(PB) void k_limb_split(int32_t n, int32_t npad, int3
                                                    const S *__restrict__ sigma, __bf16 *__restrict__ planes,
                                                    size_t plane_elems, uint32_t *__restrict__ kflags,
                                                    unsigned long long *__restrict__ reach) {
-    const size_t id = (size_t)blockIdx.x * PB + threadIdx.x;
-    const size_t per_class = (size_t)(npad / 16) * B;
+    static_assert(PB == 2 * GN && GK == 32, "one block per k-tile and source block");
     const bool over = search_over(reach);
-    if (reach && id == 0) reach[2] = over ? 1ull : 0ull; // for this level's products
-    if (id >= per_class * M || over) return;
-    const int32_t c = (int32_t)(id / per_class);
-    const size_t r = id - (size_t)c * per_class;
+    if (reach && blockIdx.x == 0 && threadIdx.x == 0) reach[2] = over ? 1ull : 0ull; // for this level's products
+    if (over) return; // the whole grid: the level's products are skipped and read no flag
+    const int32_t nsb = B / GN, tiles = npad / GK;
+    const int32_t c = (int32_t)(blockIdx.x / ((size_t)tiles * nsb));
+    const int32_t rem = (int32_t)(blockIdx.x - (size_t)c * tiles * nsb), t = rem / nsb, sb = rem - t * nsb;
+    const int32_t vg = t * 2 + (int32_t)(threadIdx.x / GN), b = sb * GN + (int32_t)(threadIdx.x % GN);
+    const size_t id = ((size_t)c * (npad / 16) + vg) * B + b; // the thread's 16-byte cell
     const int L = limbs_feeding(lvmax_l, l, M);
-    const int32_t vg = (int32_t)(r / B), b = (int32_t)(r - (size_t)vg * B);
     const uint64_t *f = c <= l ? fl - (size_t)c * words : nullptr;
     uint64_t s[16];
     bool nz = false;
@@ -839,63 +836,60 @@ __global__ __launch_bounds__(PB) void k_limb_split(int32_t n, int32_t npad, int3
         }
         *reinterpret_cast<u32x4 *>(pb + (size_t)k * plane_elems + id * 16) = o;
     }
-    if (__ballot(nz) && (threadIdx.x & 63) == 0)
-        atomicOr(&kflags[(size_t)(((size_t)c * npad + (size_t)vg * 16) / GK) * (B / GN) + b / GN], 1u);
+    const int any = __syncthreads_or(nz);
+    if (threadIdx.x == 0) kflags[((size_t)c * tiles + t) * nsb + sb] = any ? 1u : 0u;
 }
 
 // Planes for backward level l: planes[0..2][c][v/8][b][v%8] = hi, mid, lo BF16
 // parts of c(v, b) for v at level l+1+c (class c+1), for the `deeper` levels
-// below l that exist (the others contribute nothing).
+// below l that exist (the others contribute nothing), and kflags[(c npad +
+// v) / GK][b / GN] = (some part non-zero).  Blocks as in k_limb_split; a
+// thread's 16 rows are two 8-row cells.
 __global__ __launch_bounds__(PB) void k_coef_split(int32_t n, int32_t npad, int32_t B, int32_t NW, int32_t M,
                                                    int32_t deeper, const uint64_t *__restrict__ fl, size_t words,
                                                    const float *__restrict__ cval, __bf16 *__restrict__ planes,
                                                    size_t plane_elems, uint32_t *__restrict__ kflags,
                                                    const uint32_t *__restrict__ gate) {
-    const size_t id = (size_t)blockIdx.x * PB + threadIdx.x;
-    const size_t per_class = (size_t)(npad / 8) * B;
-    if (id >= per_class * M) return;
+    static_assert(PB == 2 * GN && GK == 32, "one block per k-tile and source block");
     // gate[0]: level l (empty: the product exits too); gate[1]: level l+1
-    // (empty: the product multiplies nothing and reads no plane)
+    // (empty: the product multiplies nothing and reads no plane or flag)
     if (gate && (gate[0] == 0 || gate[1] == 0)) return;
-    const int32_t cl = (int32_t)(id / per_class);
-    const size_t r = id - (size_t)cl * per_class;
-    const int32_t vg = (int32_t)(r / B), b = (int32_t)(r - (size_t)vg * B);
+    const int32_t nsb = B / GN, tiles = npad / GK;
+    const int32_t cl = (int32_t)(blockIdx.x / ((size_t)tiles * nsb));
+    const int32_t rem = (int32_t)(blockIdx.x - (size_t)cl * tiles * nsb), t = rem / nsb, sb = rem - t * nsb;
+    const int32_t b = sb * GN + (int32_t)(threadIdx.x % GN);
     const uint64_t *f = cl < deeper ? fl + (size_t)cl * words : nullptr;
-    bf16x8 hi, mid, lo;
     bool nz = false;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const int32_t v = vg * 8 + j;
-        float c = 0.f;
-        if (f && v < n && ((f[(size_t)v * NW + (b >> 6)] >> (b & 63)) & 1)) c = cval[(size_t)v * B + b];
-        const __bf16 h = (__bf16)c;
-        const float r1 = c - (float)h;
-        const __bf16 m = (__bf16)r1;
-        const float r2 = r1 - (float)m;
-        hi[j] = h;
-        mid[j] = m;
-        lo[j] = (__bf16)r2;
-        nz |= c != 0.f;
+    for (int h = 0; h < 2; ++h) {
+        const int32_t vg = t * 4 + (int32_t)(threadIdx.x / GN) * 2 + h; // 8-row cell
+        const size_t id = ((size_t)cl * (npad / 8) + vg) * B + b;
+        bf16x8 hi, mid, lo;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int32_t v = vg * 8 + j;
+            float c = 0.f;
+            if (f && v < n && ((f[(size_t)v * NW + (b >> 6)] >> (b & 63)) & 1)) c = cval[(size_t)v * B + b];
+            const __bf16 hb = (__bf16)c;
+            const float r1 = c - (float)hb;
+            const __bf16 m = (__bf16)r1;
+            const float r2 = r1 - (float)m;
+            hi[j] = hb;
+            mid[j] = m;
+            lo[j] = (__bf16)r2;
+            nz |= c != 0.f;
+        }
+        *reinterpret_cast<bf16x8 *>(planes + id * 8) = hi;
+        *reinterpret_cast<bf16x8 *>(planes + plane_elems + id * 8) = mid;
+        *reinterpret_cast<bf16x8 *>(planes + 2 * plane_elems + id * 8) = lo;
     }
-    *reinterpret_cast<bf16x8 *>(planes + id * 8) = hi;
-    *reinterpret_cast<bf16x8 *>(planes + plane_elems + id * 8) = mid;
-    *reinterpret_cast<bf16x8 *>(planes + 2 * plane_elems + id * 8) = lo;
-    if (__ballot(nz) && (threadIdx.x & 63) == 0)
-        atomicOr(&kflags[(size_t)(((size_t)cl * npad + (size_t)vg * 8) / GK) * (B / GN) + b / GN], 1u);
+    const int any = __syncthreads_or(nz);
+    if (threadIdx.x == 0) kflags[((size_t)cl * tiles + t) * nsb + sb] = any ? 1u : 0u;
 }
 
-inline unsigned blocks_for(size_t count, int per) { return (unsigned)((count + per - 1) / per); }
-
+// One block of the plane kernels per k-flag word: (class, k-tile, source block).
 inline size_t kflag_words(bc_ctx *ctx) {
     return (size_t)ctx->al.classes * (ctx->al.npad / GK) * (ctx->sp.batch / GN);
-}
-
-void clear_kflags(bc_ctx *ctx) {
-    const size_t w = kflag_words(ctx);
-    LaunchTimer tm(ctx, "kflag_clear");
-    hipLaunchKernelGGL(k_zero32, dim3((unsigned)std::min<size_t>((w + PB - 1) / PB, 1024)), dim3(PB), 0, ctx->stream,
-                       ctx->al.kflags, w);
-    tm.done();
 }
 
 GemmArgs gemm_args(bc_ctx *ctx, const __bf16 *planes, bool forward) {
@@ -1008,10 +1002,10 @@ bc_status algebraic_forward_level_t(bc_ctx *ctx, int32_t l) {
     // level by the push, the rest by the epilogue), so a level after the last
     // one skips its planes and products.
     unsigned long long *reach = a.every_level ? s.reach : nullptr;
-    clear_kflags(ctx);
     {
+        // writes every k-flag word (no clearing pass)
         LaunchTimer tm(ctx, "limb_split");
-        hipLaunchKernelGGL(k_limb_split<S>, dim3(blocks_for(plane_elems / 16, PB)), dim3(PB), 0, ctx->stream, ctx->n,
+        hipLaunchKernelGGL(k_limb_split<S>, dim3((unsigned)kflag_words(ctx)), dim3(PB), 0, ctx->stream, ctx->n,
                            a.npad, s.batch, s.words, a.classes, l, s.lvmax + l, fcur, words, (const S *)s.sigma,
                            a.planes, plane_elems, a.kflags, reach);
         tm.done();
@@ -1052,10 +1046,10 @@ bc_status algebraic_backward_level_t(bc_ctx *ctx, const uint64_t *fcur, const ui
     SparseState &s = ctx->sp;
     const size_t words = (size_t)ctx->n * s.words;
     const size_t plane_elems = (size_t)a.classes * a.npad * s.batch;
-    clear_kflags(ctx);
     {
+        // writes every k-flag word (no clearing pass)
         LaunchTimer tm(ctx, "coef_split");
-        hipLaunchKernelGGL(k_coef_split, dim3(blocks_for(plane_elems / 8, PB)), dim3(PB), 0, ctx->stream, ctx->n,
+        hipLaunchKernelGGL(k_coef_split, dim3((unsigned)kflag_words(ctx)), dim3(PB), 0, ctx->stream, ctx->n,
                            a.npad, s.batch, s.words, a.classes, fnext ? deeper : 0, fnext, words, s.cval, a.planes,
                            plane_elems, a.kflags, gate);
         tm.done();
