@@ -320,6 +320,18 @@ double fit_threshold(const Calibration &cal, bool forward, double *saved_ms) {
         }
     }
     *saved_ms = all_pull - best;
+    // The best candidate is the lowest density of some level's range; any
+    // threshold between it and the next lower sampled density splits the
+    // samples alike.  Take the middle of that gap (or half the density when
+    // nothing lies below): batches outside the calibration sample spread
+    // around the sampled densities, and one just below the candidate would
+    // send the level to pulls, in a replayed run for every batch.
+    if (best_theta <= 1.0) {
+        double below = -1.0;
+        for (const Sample *s : v)
+            if (s->density < best_theta) below = std::max(below, s->density);
+        best_theta = below >= 0.0 ? 0.5 * (below + best_theta) : 0.5 * best_theta;
+    }
     return best_theta;
 }
 
