@@ -5,6 +5,8 @@ dependencies within the form's tolerance (max |x-y| / max(|y|, 1)):
 1e-12 for the plain FP64 form, 1e-5 for the batched forms whose c(v) state is
 stored in FP32.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -101,6 +103,31 @@ def test_largest_square_grid_within_u64(gpu_lib, form):
     with gpu_lib.BC(g, form=form) as ctx:
         _, sigma, _ = ctx.sssp(np.array([0], np.int32))
     assert int(sigma[0, g.n - 1]) == 7219428434016265740  # C(66,33)
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_counts_past_2_63_through_every_limb(gpu_lib, form):
+    """A 34 x 35 grid reaches C(67,33), between 2^63 and 2^64 - 1, at its far
+    corner, and two vertices hanging off that corner keep the count: the step
+    out of the corner's level reads a largest count with bit 63 set, which
+    takes every one of the ten 7-bit limbs in the algebraic form's products.
+    Counts are C(x + y, x) on the grid and must come back exactly."""
+    base = gg.grid(34, 35)
+    rows = np.repeat(np.arange(base.n), np.diff(base.row_ptr))
+    keep = rows < base.col
+    far = base.n - 1
+    u = np.concatenate([rows[keep], [far, base.n]])
+    v = np.concatenate([base.col[keep], [base.n, base.n + 1]])
+    g = gg.from_edges(base.n + 2, u, v, name="grid34x35tail")
+    say("grid34x35tail", form)
+    with gpu_lib.BC(g, form=form) as ctx:
+        d, sigma, delta = ctx.sssp(np.array([0], np.int32))
+    x, y = np.divmod(np.arange(base.n), 35)
+    want = [math.comb(int(a + b), int(a)) for a, b in zip(x, y)] + [math.comb(67, 33)] * 2
+    assert math.comb(67, 33) > 2 ** 63
+    assert [int(c) for c in sigma[0]] == want
+    assert [int(t) for t in d[0]] == [int(a + b) for a, b in zip(x, y)] + [68, 69]
+    assert rel_err(delta[0], oracle.sssp(g, 0)[2]) <= TOL[form]
 
 
 @pytest.mark.parametrize("form", FORMS)
